@@ -1,0 +1,402 @@
+"""Pins for the CPU oracle: closed forms, invariants, textbook values and
+independent solvers that a plausible mistake in the oracle would break.
+
+Each test names the passage of arXiv 2604.02755 it checks.  None of the
+expected values comes from the HIP path.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2604_02755_amd import inputs as I
+
+
+def _iso(lam, mu):
+    D = np.zeros((6, 6))
+    D[:3, :3] = lam
+    D[np.arange(3), np.arange(3)] = lam + 2 * mu
+    D[3, 3] = D[4, 4] = D[5, 5] = mu
+    return D
+
+
+def _rand_tet(rng):
+    while True:
+        X = rng.normal(size=(4, 3))
+        if np.linalg.det(np.array([X[1] - X[0], X[2] - X[0], X[3] - X[0]])) > 0.05:
+            return X
+
+
+# ---------------------------------------------------------------- geometry
+
+def test_volumes_sum_to_box(oracle_lib):
+    """Second-order tets (Section 2.1): element volumes tile the box exactly."""
+    for mesh, vol in ((I.box_mesh(4, 3, 2, 1.0), 24.0),
+                      (I.perturbed_three_layer_mesh(8, 8, 8, seed=3), 512.0)):
+        tot = sum(oracle_lib.tet_geometry(mesh.xyz[t[:4]])[1] for t in mesh.tet10)
+        assert abs(tot - vol) < 1e-11 * vol
+
+
+def test_barycentric_gradients_reproduce_linear_fields(oracle_lib):
+    rng = np.random.default_rng(1)
+    X = _rand_tet(rng)
+    gL, V, rc = oracle_lib.tet_geometry(X)
+    assert rc == 0
+    # sum_i x_i (grad L_i)^T = I  (linear precision) and sum grad L_i = 0
+    assert np.allclose(X.T @ gL, np.eye(3), atol=1e-12)
+    assert np.allclose(gL.sum(0), 0, atol=1e-12)
+    assert abs(V - np.linalg.det(np.array([X[1] - X[0], X[2] - X[0], X[3] - X[0]])) / 6) < 1e-14
+
+
+def test_consistent_mass_matches_textbook_p2_tet(oracle_lib):
+    """Consistent mass of the 10-node tet: the textbook V/420 pattern
+    (corner diag 6, corner-corner 1, corner-adjacent edge -4, corner-opposite
+    edge -6, edge diag 32, edges sharing a vertex 16, opposite edges 8)."""
+    X = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1.0]])
+    _, Me = oracle_lib.element_matrices(X, np.zeros((6, 6)), 1.0)
+    V = 1 / 6
+    Mref = Me[0::3, 0::3] / V  # one component
+    edges = I.EDGES
+    T = np.zeros((10, 10))
+    for a in range(10):
+        for b in range(10):
+            if a < 4 and b < 4:
+                T[a, b] = 6 if a == b else 1
+            elif a < 4 or b < 4:
+                c, e = (a, b - 4) if a < 4 else (b, a - 4)
+                T[a, b] = -4 if c in edges[e] else -6
+            else:
+                ea, eb = set(edges[a - 4]), set(edges[b - 4])
+                T[a, b] = 32 if a == b else (16 if ea & eb else 8)
+    assert np.allclose(Mref, T / 420, atol=1e-15)
+    # components decouple, total mass rho V per component
+    assert abs(Me[0::3, 0::3].sum() - V) < 1e-15
+    assert np.allclose(Me[0::3, 1::3], 0)
+
+
+def test_face_mass_p2_triangle(oracle_lib):
+    """6-node triangle int N_a N_b dA: textbook A/180 pattern (corner diag 6,
+    corner-corner -1, corner-opposite edge -4, corner-adjacent edge 0, edge
+    diag 32, edge-edge 16)."""
+    X = np.array([[0, 0, 0], [2, 0, 0], [0, 1, 0.0]])
+    M, n, A = oracle_lib.face_matrix(X)
+    assert abs(A - 1.0) < 1e-15 and np.allclose(np.abs(n), [0, 0, 1])
+    fe = ((0, 1), (1, 2), (2, 0))
+    T = np.zeros((6, 6))
+    for a in range(6):
+        for b in range(6):
+            if a < 3 and b < 3:
+                T[a, b] = 6 if a == b else -1
+            elif a < 3 or b < 3:
+                c, e = (a, b - 3) if a < 3 else (b, a - 3)
+                T[a, b] = 0 if c in fe[e] else -4
+            else:
+                T[a, b] = 32 if a == b else 16
+    assert np.allclose(M, T * A / 180, atol=1e-15)
+
+
+# ---------------------------------------------------------------- stiffness
+
+def test_stiffness_symmetric_and_rigid_modes_in_null_space(oracle_lib):
+    """Eq. 2 with symmetric D: K_e symmetric, rigid translations and
+    rotations produce no force."""
+    rng = np.random.default_rng(2)
+    X = _rand_tet(rng)
+    L = rng.normal(size=(4, 6, 6))
+    D = np.einsum("jab,jcb->jac", L, L) + 3 * np.eye(6)
+    Ke, _ = oracle_lib.element_matrices(X, D, 1.0)
+    assert np.allclose(Ke, Ke.T, rtol=0, atol=1e-12 * np.abs(Ke).max())
+    Xn = np.vstack([X, [(X[a] + X[b]) / 2 for a, b in I.EDGES]])
+    modes = []
+    for c in range(3):
+        u = np.zeros((10, 3)); u[:, c] = 1; modes.append(u.ravel())
+    for ax in np.eye(3):
+        modes.append(np.cross(ax, Xn).ravel())
+    for u in modes:
+        assert np.abs(Ke @ u).max() <= 1e-13 * np.abs(Ke).max() * np.abs(u).max()
+    # positive definite on the complement of the 6 rigid modes
+    w = np.linalg.eigvalsh(Ke)
+    assert np.sum(w > 1e-10 * w.max()) == 24
+
+
+def test_element_energy_of_linear_field_is_exact(oracle_lib):
+    """Constant strain eps: u^T K_e u = V eps^T D eps (the 4-point rule is exact
+    for this; a wrong weight, sign or B entry breaks it)."""
+    rng = np.random.default_rng(3)
+    X = _rand_tet(rng)
+    Xn = np.vstack([X, [(X[a] + X[b]) / 2 for a, b in I.EDGES]])
+    F = rng.normal(size=(3, 3))
+    u = (Xn @ F.T).ravel()  # u_c = F[c, d] x_d
+    eps = np.array([F[0, 0], F[1, 1], F[2, 2], F[0, 1] + F[1, 0], F[1, 2] + F[2, 1], F[2, 0] + F[0, 2]])
+    D = _iso(2.0, 1.3)
+    Ke, _ = oracle_lib.element_matrices(X, D, 1.0)
+    V = oracle_lib.tet_geometry(X)[1]
+    assert abs(u @ Ke @ u - V * eps @ D @ eps) < 1e-12 * abs(V * eps @ D @ eps)
+
+
+def test_patch_test_on_distorted_mesh(oracle_lib):
+    """A linear displacement field on an assembled (distorted) mesh gives zero
+    residual at interior nodes."""
+    mesh = I.perturbed_three_layer_mesh(4, 4, 4, seed=7, amp=0.3, corr=2.0)
+    nn = mesh.n_nodes
+    K = np.zeros((3 * nn, 3 * nn))
+    D = _iso(5.0, 2.0)
+    for t in mesh.tet10:
+        Ke, _ = oracle_lib.element_matrices(mesh.xyz[t[:4]], D, 1.0)
+        d = (3 * t[:, None] + np.arange(3)).ravel()
+        K[np.ix_(d, d)] += Ke
+    F = np.array([[1e-3, 2e-3, -1e-3], [0.5e-3, -2e-3, 1e-3], [3e-3, 1e-3, 2e-3]])
+    u = (mesh.xyz @ F.T).ravel()
+    f = (K @ u).reshape(nn, 3)
+    x = mesh.xyz
+    interior = ((x[:, 0] > 1e-9) & (x[:, 0] < 4 - 1e-9) & (x[:, 1] > 1e-9) & (x[:, 1] < 4 - 1e-9)
+                & (x[:, 2] > -4 + 1e-9) & (x[:, 2] < -1e-9))
+    assert interior.sum() > 100
+    assert np.abs(f[interior]).max() < 1e-12 * np.abs(f).max()
+
+
+# ---------------------------------------------------------------- springs
+
+@pytest.mark.parametrize("ns", [12, 150])
+def test_spring_table_isotropic(oracle_lib, ns):
+    """Multi-spring model (Section 2.1): in the small-strain limit the spring
+    sum plus the elastic volumetric part is isotropic elasticity with the
+    layer's G0 and bulk modulus; 150 springs per point as in the paper."""
+    dirs, w = I.spring_table(ns)
+    assert dirs.shape == (ns, 6)
+    G0, nu = 1700 * 150.0 ** 2, 0.45
+    lam = 2 * G0 * nu / (1 - 2 * nu)
+    Kb = lam + 2 * G0 / 3
+    D, h = oracle_lib.ip_law(None, None, dirs, w, G0, Kb, 1e-3, 0.2)
+    assert np.abs(D - _iso(lam, G0)).max() < 1e-14 * (lam + 2 * G0)
+    assert h == 0.0
+
+
+def test_state_bytes_per_element_match_paper():
+    """Section 2.1: four doubles and two flags per spring (40 B), 150 springs
+    per point, four points per tet -> 24 kB per element."""
+    per_spring = 4 * 8 + 2 * 4
+    assert per_spring == 40
+    assert per_spring * 150 * 4 == 24000
+
+
+def test_skeleton_closed_forms(oracle_lib):
+    """Modified Ramberg-Osgood skeleton: beta from h_max, secant G/G0 = 1/2 at
+    gamma_ref, inverse residual at machine precision, odd symmetry."""
+    b = oracle_lib.ro_beta(0.2)
+    assert abs(b - 2 * math.pi * 0.2 / (2 - math.pi * 0.2)) < 1e-15
+    assert abs(b - 0.9161289188) < 1e-10
+    assert abs(oracle_lib.ro_inverse(1.0, b) - 0.5) < 1e-15
+    for e in (1e-9, 1e-4, 0.3, 1.0, 7.0, 1e3, 1e6):
+        s = oracle_lib.ro_inverse(e, b)
+        assert abs(s * (1 + abs(2 * s) ** b) - e) <= 4e-16 * e
+        assert oracle_lib.ro_inverse(-e, b) == -s
+
+
+def _cycle(oracle_lib, amp, n_per_quarter, n_cycles, G0, gref, hmax):
+    st = oracle_lib.new_spring()
+    g_hist, t_hist = [0.0], [0.0]
+    g = 0.0
+    path = np.concatenate([np.linspace(0, amp, n_per_quarter + 1)[1:]] +
+                          [np.linspace(amp, -amp, 2 * n_per_quarter + 1)[1:],
+                           np.linspace(-amp, amp, 2 * n_per_quarter + 1)[1:]] * n_cycles)
+    out = []
+    for gn in path:
+        tau, Gt, hk = oracle_lib.spring_step(st, gn - g, G0, gref, hmax)
+        g = gn
+        g_hist.append(g)
+        t_hist.append(tau)
+        out.append((Gt, hk))
+    return np.array(g_hist), np.array(t_hist), st, out
+
+
+@pytest.mark.parametrize("amp_ratio", [0.3, 1.0, 4.0])
+def test_masing_loop_closed_form_damping(oracle_lib, amp_ratio):
+    """Masing rule on the RO skeleton: the steady loop has tips at +-S(gamma_a)
+    and its area gives h = h_max (1 - G_sec/G0), which is also the spring's
+    reported equivalent damping."""
+    G0, gref, hmax = 4.0e7, 1e-3, 0.2
+    amp = amp_ratio * gref
+    nq = 4000
+    g, t, st, out = _cycle(oracle_lib, amp, nq, 2, G0, gref, hmax)
+    b = oracle_lib.ro_beta(hmax)
+    S = G0 * gref * oracle_lib.ro_inverse(amp / gref, b)
+    # tips
+    assert abs(t[nq] - S) < 1e-12 * S
+    assert abs(t[3 * nq] + S) < 1e-11 * S
+    assert abs(t[-1] - S) < 1e-11 * S
+    # area of the last full cycle (trapezoid)
+    gl, tl = g[-4 * nq - 1:], t[-4 * nq - 1:]
+    area = abs(np.sum(0.5 * (tl[1:] + tl[:-1]) * np.diff(gl)))
+    W = 0.5 * S * amp
+    h_loop = area / (4 * math.pi * W)
+    Gsec = S / amp
+    h_closed = hmax * (1 - Gsec / G0)
+    assert abs(h_loop - h_closed) < 2e-6 * max(h_closed, 1e-3)
+    assert abs(out[-1][1] - h_closed) < 1e-13
+    # rejoin at the tip: back on the skeleton with gm = amp
+    assert st[5] == 1.0 and abs(st[3] - amp) < 1e-18
+
+
+def test_masing_branch_residual_and_tangent(oracle_lib):
+    """On an unloading branch: gamma - gamma_r = 2 F((tau - tau_r)/2) with F
+    the skeleton's strain function, and G_t equals the branch slope."""
+    G0, gref, hmax = 3.0e7, 1e-3, 0.2
+    b = oracle_lib.ro_beta(hmax)
+    st = oracle_lib.new_spring()
+    oracle_lib.spring_step(st, 2.5e-3, G0, gref, hmax)
+    gr = st[0]
+    taus = []
+    for _ in range(10):
+        tau, Gt, _ = oracle_lib.spring_step(st, -3e-4, G0, gref, hmax)
+        taus.append((st[0], tau, Gt))
+    tr = st[2]
+    assert abs(st[1] - gr) == 0 and st[5] == 0.0
+    for gam, tau, Gt in taus:
+        x = (tau - tr) / 2 / (G0 * gref)
+        F = gref * x * (1 + abs(2 * x) ** b)
+        assert abs((gam - gr) - 2 * F) < 1e-13 * gref
+    # the secant slope between two branch points lies between their tangents
+    slope = (taus[-1][1] - taus[-2][1]) / (taus[-1][0] - taus[-2][0])
+    assert taus[-1][2] < slope < taus[-2][2] or taus[-2][2] < slope < taus[-1][2]
+
+
+def test_single_spring_ip_equals_spring(oracle_lib):
+    """N_s = 1 reduces the point law to the textbook single-spring loop: the
+    xy-shear entry of D is the spring tangent."""
+    G0, Kb, gref, hmax = 2.0e7, 5.0e7, 1e-3, 0.2
+    dirs = np.array([[0, 0, 0, 1.0, 0, 0]])
+    w = np.array([1.0])
+    st_ip = np.array([[0, 0, 0, 0, 0, 1.0]])
+    st_sp = oracle_lib.new_spring()
+    for dgam in (4e-4, 8e-4, -5e-4, -1e-3, 2e-4, 1.5e-3):
+        D, h = oracle_lib.ip_law(np.array([0, 0, 0, dgam, 0, 0]), st_ip, dirs, w, G0, Kb, gref, hmax)
+        _, Gt, hk = oracle_lib.spring_step(st_sp, dgam, G0, gref, hmax)
+        assert D[3, 3] == Gt and h == hk
+        assert np.allclose(D[:3, :3], Kb)
+
+
+# ---------------------------------------------------------------- damping
+
+def test_rayleigh_least_squares_fit(oracle_lib):
+    """Rayleigh damping (Section 2.1): the coefficients are the least-squares
+    fit of a/(4 pi f) + pi b f to a unit damping ratio over [f_lo, f_hi]:
+    the residual is orthogonal to both basis functions (checked by quadrature)."""
+    from scipy.integrate import quad
+    a, b = oracle_lib.rayleigh(0.1, 10.0)
+    r = lambda f: a / (4 * math.pi * f) + math.pi * b * f - 1
+    g1 = quad(lambda f: r(f) / (4 * math.pi * f), 0.1, 10, limit=200)[0]
+    g2 = quad(lambda f: r(f) * math.pi * f, 0.1, 10, limit=200)[0]
+    assert abs(g1) < 1e-9 and abs(g2) < 1e-7
+    assert abs(a - 4.0819) < 1e-4 and abs(b - 0.044671) < 1e-6
+
+
+# ---------------------------------------------------------------- driver
+
+def test_cg_matches_dense_direct_solve(oracle_lib):
+    """The CRS-PCG driver (Alg. 1) against a dense LU stepper on tiny meshes
+    (1x1x1 and 2x2x1 cubes) with the nonlinear law active."""
+    for dims in ((1, 1, 1), (2, 2, 1)):
+        mesh, prob = I.config(0, n_steps=12, mesh_dims=dims, cg_tol=1e-13)
+        prob.input_acc *= 50.0  # drive the springs well into the nonlinear range
+        r = oracle_lib.run(mesh, prob, want_du=True)
+        vel, du = oracle_lib.dense_stepper(mesh, prob)
+        assert oracle_lib.rel_l2(r["du"], du) < 1e-10
+        assert oracle_lib.rel_l2(r["vel"], vel) < 1e-10
+
+
+def test_newmark_conserves_energy_undamped(oracle_lib):
+    """Section 2.1 state updates are the trapezoidal rule: for a free, undamped
+    linear body the energy v^T M v / 2 + u^T K u / 2 is conserved."""
+    mesh = I.box_mesh(2, 2, 2, 1.0)
+    mesh.bface6 = mesh.bface6[:0]
+    mesh.bface_kind = mesh.bface_kind[:0]
+    prob = I.make_problem(1, (200.0,), (1800.0,), n_springs=12, n_steps=60, dt=1e-3,
+                          damping_mode=I.DAMPING_NONE, cg_tol=1e-14)
+    prob.nonlinear[:] = 0
+    rng = np.random.default_rng(5)
+    v0 = rng.normal(size=3 * mesh.n_nodes) * 1e-3
+    r = oracle_lib.run(mesh, prob, want_state=True, v0=v0)
+    nn = mesh.n_nodes
+    K = np.zeros((3 * nn, 3 * nn)); M = np.zeros((3 * nn, 3 * nn))
+    G0 = 1800 * 200.0 ** 2
+    lam = 2 * G0 * 0.45 / 0.1
+    for t in mesh.tet10:
+        Ke, Me = oracle_lib.element_matrices(mesh.xyz[t[:4]], _iso(lam, G0), 1800.0)
+        d = (3 * t[:, None] + np.arange(3)).ravel()
+        K[np.ix_(d, d)] += Ke
+        M[np.ix_(d, d)] += Me
+    E0 = 0.5 * v0 @ M @ v0
+    E1 = 0.5 * r["v"] @ M @ r["v"] + 0.5 * r["u"] @ K @ r["u"]
+    assert abs(E1 - E0) < 1e-10 * E0
+    assert 0.5 * r["u"] @ K @ r["u"] > 1e-3 * E0  # energy really moved into strain
+
+
+def _periodic_column(nz=8):
+    """1x1xnz column with x and y periodic ties (alias map) and only the base
+    dashpot: a laterally uniform layered half-space model."""
+    mesh = I.box_mesh(1, 1, nz, 1.0, I.two_layer(4.0))
+    NX = NY = 3
+    ids = np.arange(mesh.n_nodes)
+    Ii, Jj, Kk = ids % NX, (ids // NX) % NY, ids // (NX * NY)
+    alias = (np.where(Ii == 2, 0, Ii) + NX * (np.where(Jj == 2, 0, Jj) + NY * Kk)).astype(np.int32)
+    keep = mesh.bface_kind == 0
+    mesh.bface6 = np.ascontiguousarray(mesh.bface6[keep])
+    mesh.bface_kind = np.ascontiguousarray(mesh.bface_kind[keep])
+    top = ids[(Ii == 0) & (Jj == 0) & (Kk == 2 * nz)]
+    mesh.recv = top.astype(np.int32)
+    return mesh, alias
+
+
+def test_layer_over_halfspace_resonance(oracle_lib):
+    """Linear limit, 1D soil column (top 4 m Vs 150 rho 1700 on Vs 400 rho 1900):
+    the transfer function surface / outcrop (= 2 x incident) peaks at
+    f = Vs/4H = 9.375 Hz with height rho2 Vs2 / (rho1 Vs1) = 2.98."""
+    mesh, alias = _periodic_column(8)
+    n = 4096
+    acc = np.zeros((1, n, 3))
+    # Hann-windowed band-limited noise with zero net velocity change, so the
+    # response decays to rest inside the record and the FFT ratio is exact
+    win = np.hanning(n // 2)
+    w = I.band_limited_wave(77, n // 2, 1e-3, 0.1, 25.0, peak=1e-6) * win
+    w -= win * (w.sum() / win.sum())
+    acc[0, : n // 2, 0] = w
+    prob = I.make_problem(1, (150.0, 400.0), (1700.0, 1900.0), n_springs=12, n_steps=n,
+                          input_acc=acc, cg_tol=1e-12)
+    r = oracle_lib.run(mesh, prob, alias=alias)
+    vs_ = r["vel"][:, 0, 0]
+    vI = np.concatenate([[0.0], np.cumsum(0.5 * 1e-3 * (acc[0, 1:, 0] + acc[0, :-1, 0]))])
+    vI = vI + 0.5e-3 * acc[0, 0, 0]
+    nfft = 1 << 17
+    f = np.fft.rfftfreq(nfft, 1e-3)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        H = np.abs(np.fft.rfft(vs_, nfft)) / np.abs(np.fft.rfft(2 * vI, nfft))
+    band = (f > 4) & (f < 15)
+    fpk = f[band][np.argmax(H[band])]
+    hpk = H[band].max()
+    assert abs(fpk - 9.375) < 0.02 * 9.375, fpk
+    assert abs(hpk - 1900 * 400 / (1700 * 150)) < 0.05 * 2.98, hpk
+    # and the exact 1D transfer function elsewhere in the band (within 5 %)
+    k = 2 * np.pi * f / 150.0
+    alpha = 1700 * 150 / (1900 * 400)
+    H1d = 1 / np.sqrt(np.cos(k * 4) ** 2 + alpha ** 2 * np.sin(k * 4) ** 2)
+    sel = (f > 1) & (f < 14)
+    assert np.max(np.abs(H[sel] - H1d[sel]) / H1d[sel]) < 0.05
+
+
+def test_cg_nonconvergence_is_reported(oracle_lib):
+    mesh, prob = I.config(0, n_steps=5, mesh_dims=(2, 2, 1))
+    prob.cg_maxit = 2
+    with pytest.raises(oracle_lib.OracleError) as ei:
+        oracle_lib.run(mesh, prob)
+    assert ei.value.code == -5
+
+
+def test_invalid_mesh_rejected(oracle_lib):
+    mesh, prob = I.config(0, n_steps=2, mesh_dims=(1, 1, 1))
+    t = mesh.tet10.copy()
+    t[0, [1, 2]] = t[0, [2, 1]]  # negative Jacobian (and mid-nodes no longer match)
+    mesh.tet10 = t
+    with pytest.raises(oracle_lib.OracleError) as ei:
+        oracle_lib.run(mesh, prob)
+    assert ei.value.code == -1
