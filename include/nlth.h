@@ -1,0 +1,234 @@
+/*
+ * nlth -- MI355X-native ensemble solver for nonlinear time-history analysis of
+ * 3D seismic ground response with a multi-spring hysteretic law.
+ *
+ * Method: Ichimura, Fujita, Ito, Hori, Lalith, "Accelerating Nonlinear
+ * Time-History Analysis with Complex Constitutive Laws via Heterogeneous
+ * Memory Management" (arXiv 2604.02755).  Each time step solves the
+ * Newmark-beta incremental system of Section 2.1, Eq. 1 by preconditioned CG
+ * with an element-by-element (matrix-free) operator (Section 2.2, Algorithm 4),
+ * then updates the multi-spring law at the four integration points of every
+ * quadratic tetrahedron (Section 2.1, Eq. 2), paging the per-spring history
+ * between pinned host memory and HBM when it does not fit (Section 2.2,
+ * Algorithm 3).
+ *
+ * Conventions for every call:
+ *  - SI units, z up; the free surface is the top, absorbing faces are given
+ *    explicitly (base faces also carry the incident wave).
+ *  - Return value: NLTH_OK (0) or a negative NLTH_E* code; nlth_last_error()
+ *    then holds a message.
+ *  - Input arrays are owned by the caller and copied (host pointers) during
+ *    the call unless stated otherwise.
+ *  - Output buffers are owned by the caller (host pointers).
+ *  - Handles are owned by the library and released by their *_destroy call.
+ *  - One context per device; calls on one context are serialised internally.
+ */
+#ifndef NLTH_H
+#define NLTH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NLTH_VERSION 10000 /* 1.0.0 */
+
+/* status codes */
+#define NLTH_OK 0
+#define NLTH_EINVAL -1          /* invalid argument, mesh or problem */
+#define NLTH_EDEVICE -2         /* HIP runtime failure, or a host-only context */
+#define NLTH_ENOMEM_DEVICE -3   /* does not fit the HBM budget even with paging */
+#define NLTH_ENOMEM_HOST -4     /* pinned host budget exceeded */
+#define NLTH_ENOCONV -5         /* a member's CG hit cg_maxit */
+#define NLTH_EBUSY -6           /* request can never fit the budgets / handle in use */
+#define NLTH_ECANCELED -7       /* request was cancelled */
+#define NLTH_ETIMEDOUT -8       /* nlth_wait timed out */
+#define NLTH_ENOTFOUND -9       /* unknown ticket */
+
+/* damping modes: Rayleigh damping from the law's h (Section 2.1), constant h0, none */
+#define NLTH_DAMPING_LAW 0
+#define NLTH_DAMPING_CONST 1
+#define NLTH_DAMPING_NONE 2
+
+/* precision: all-FP64 block-Jacobi PCG, or FP64 flexible CG whose
+ * preconditioner is an FP32 block-Jacobi PCG (Section 2.3: only the
+ * preconditioner runs in single precision) */
+#define NLTH_FP64 0
+#define NLTH_MIXED 1
+
+/* operator selector for nlth_apply_operator */
+#define NLTH_OP_A 0 /* 4/dt^2 M + 2/dt C + K (Eq. 1 left-hand side) */
+#define NLTH_OP_K 1 /* K */
+#define NLTH_OP_M 2 /* M */
+
+#define NLTH_DEVICE_NONE (-1) /* host-only context: validation and mesh analysis */
+
+typedef struct nlth_ctx nlth_ctx;
+typedef struct nlth_mesh nlth_mesh;
+typedef struct nlth_ens nlth_ens;
+
+typedef struct {
+    int64_t hbm_budget;   /* device bytes the library may allocate; 0 = 90 % of free */
+    int64_t host_budget;  /* pinned host bytes for paged law state; 0 = 64 GiB */
+    void* stream;         /* optional hipStream_t for compute (e.g. torch's); NULL = own */
+    int32_t log_level;    /* 0 silent, 1 per solve, 2 per step */
+    int32_t max_batch;    /* serving: members per batch (0 = 64) */
+} nlth_ctx_opts;
+
+/* Create a context on HIP device `device` (or NLTH_DEVICE_NONE).  `opts` may
+ * be NULL.  Errors: NLTH_EDEVICE if the device cannot be used. */
+int nlth_ctx_create(int device, const nlth_ctx_opts* opts, nlth_ctx** out);
+/* Destroy; fails with NLTH_EBUSY while requests or meshes are alive. */
+int nlth_ctx_destroy(nlth_ctx* ctx);
+/* Message of the last error on this context (context-owned, NUL-terminated,
+ * valid until the next call on the context).  ctx may be NULL (global). */
+const char* nlth_last_error(const nlth_ctx* ctx);
+int nlth_version(void);
+
+/*
+ * Mesh: quadratic (10-node) tetrahedra, Section 2.1.  Node order per tet is
+ * VTK's: vertices v0..v3 then the midpoints of edges 01, 12, 20, 03, 13, 23.
+ * Tets must be straight-sided (mid-nodes at edge midpoints) with a positive
+ * Jacobian.  Boundary faces are 6-node triangles (3 vertices, then midpoints
+ * of ab, bc, ca); kind 0 = base (absorbing dashpot + incident wave input),
+ * kind 1 = side (absorbing dashpot).  Receivers are node ids whose velocity is
+ * recorded every step.  All arrays are copied.
+ * Errors: NLTH_EINVAL naming the first offending element/face/node.
+ */
+typedef struct {
+    int32_t n_nodes;
+    const double* xyz;         /* [n_nodes*3] */
+    int32_t n_tets;
+    const int32_t* tet10;      /* [n_tets*10] */
+    const int32_t* layer;      /* [n_tets] layer id, 0 <= id < n_layers of the problem */
+    int32_t n_bfaces;
+    const int32_t* bface6;     /* [n_bfaces*6] */
+    const uint8_t* bface_kind; /* [n_bfaces] */
+    int32_t n_recv;
+    const int32_t* recv;       /* [n_recv] */
+} nlth_mesh_desc;
+
+int nlth_mesh_create(nlth_ctx* ctx, const nlth_mesh_desc* d, nlth_mesh** out);
+int nlth_mesh_destroy(nlth_mesh* mesh);
+
+/* Mesh analysis results (host logic, available on a host-only context).
+ * elem_order (optional, [n_tets]) receives the processing order: position ->
+ * input tet id; color_offsets (optional, [n_colors+1]) the start of each
+ * colour in that order.  Tets of one colour share no node. */
+typedef struct {
+    int32_t n_nodes, n_tets, n_colors, n_bnodes;
+    double volume;
+} nlth_mesh_info;
+int nlth_mesh_query(const nlth_mesh* mesh, nlth_mesh_info* info, int32_t* elem_order,
+                    int32_t* color_offsets);
+
+/*
+ * Problem: an ensemble of members sharing one mesh (Section 3: ensembles of
+ * input waves and ground properties).  Per member and layer: density, S-wave
+ * velocity, Poisson ratio and the springs' reference strain (gamma_ref, where
+ * the secant modulus is G0/2).  Per layer: h_max (maximum damping of the
+ * Ramberg-Osgood/Masing loop) and whether the layer's springs are nonlinear.
+ * Spring table: unit-direction rows n_k (Voigt xx,yy,zz,xy,yz,zx with
+ * engineering shear; gamma_k = n_k . eps) and weights c_k; the point tangent
+ * is D = K_b m m^T + sum_k c_k G_t,k n_k n_k^T.
+ * input_acc[(m*n_steps + n)*3 + c] is the incident base acceleration of
+ * member m at t = (n+1) dt (zero at t = 0).
+ * Rayleigh damping (Section 2.1): alpha = a*h, beta = b*h per element with
+ * (a, b) the least-squares fit of alpha/(4 pi f) + pi beta f to 1 over
+ * [f_lo, f_hi]; h = the law's element damping (LAW), h0 (CONST) or 0 (NONE).
+ * CG stops when ||r||_2 <= cg_tol ||b||_2 per member; the inner FP32 solve of
+ * NLTH_MIXED stops at inner_tol relative or inner_maxit iterations.
+ */
+typedef struct {
+    int32_t n_members;
+    int32_t n_layers;
+    const double* rho;         /* [n_members*n_layers] */
+    const double* vs;
+    const double* nu;
+    const double* gamma_ref;
+    const double* h_max;       /* [n_layers] */
+    const int32_t* nonlinear;  /* [n_layers] */
+    int32_t n_springs;
+    const double* dirs;        /* [n_springs*6] */
+    const double* weights;     /* [n_springs] */
+    int32_t damping_mode;
+    double h0, f_lo, f_hi;
+    double dt;
+    int32_t n_steps;
+    const double* input_acc;   /* [n_members*n_steps*3] */
+    double cg_tol;
+    int32_t cg_maxit;
+    int32_t precision;         /* NLTH_FP64 or NLTH_MIXED */
+    double inner_tol;
+    int32_t inner_maxit;
+} nlth_problem;
+
+/* Result buffers (caller-owned host memory; NULL fields are skipped).
+ * vel[((m*n_steps + n)*n_recv + r)*3 + c]: receiver velocity after step n+1.
+ * iters[(m*n_steps + n)*2 + {0,1}]: outer and total inner CG iterations.
+ * member_status[m]: NLTH_OK or NLTH_ENOCONV (results valid up to the failing step).
+ * vmax[m*n_recv + r]: maximum velocity norm over the run at each receiver. */
+typedef struct {
+    double* vel;
+    int32_t* iters;
+    int32_t* member_status;
+    double* vmax;
+} nlth_result;
+
+/* Synchronous whole-run solve.  Returns NLTH_ENOCONV if any member failed,
+ * NLTH_ENOMEM_DEVICE / NLTH_ENOMEM_HOST if it cannot fit even with paging. */
+int nlth_solve(nlth_ctx* ctx, const nlth_mesh* mesh, const nlth_problem* prob, nlth_result* res);
+
+/* Staged form of nlth_solve: create uploads the problem and allocates all
+ * device state (and pinned host state when paging); step advances every
+ * member by n_steps (synchronous); read copies the results recorded so far;
+ * stats reports phase timers.  The problem's arrays are copied by create. */
+int nlth_ens_create(nlth_ctx* ctx, const nlth_mesh* mesh, const nlth_problem* prob, nlth_ens** out);
+int nlth_ens_step(nlth_ens* ens, int32_t n_steps);
+int nlth_ens_read(nlth_ens* ens, nlth_result* res);
+int nlth_ens_destroy(nlth_ens* ens);
+
+/* Phase timers (HIP events, milliseconds, accumulated since create or the
+ * last reset) and counters.  Event timing of individual kernels is on only
+ * when `profile` was set with nlth_ens_set_profile (it adds host overhead). */
+typedef struct {
+    int32_t steps_done;
+    int32_t paged;             /* law state streamed from pinned host memory */
+    int64_t outer_iters, inner_iters;
+    double ms_total;           /* wall time inside nlth_ens_step */
+    double ms_ebe64, ms_ebe32, ms_vec, ms_law, ms_other;
+    int64_t n_ebe64, n_ebe32, n_law;     /* timed launches */
+    int64_t elems_ebe64, elems_ebe32;    /* element-member pairs processed by those launches */
+    int64_t h2d_bytes, d2h_bytes;
+    double ms_copy;            /* copy-stream busy time while paging */
+    int32_t n_members, members_padded, n_colors;
+    int64_t device_bytes, host_bytes;
+} nlth_stats;
+int nlth_ens_stats(const nlth_ens* ens, nlth_stats* st);
+int nlth_ens_set_profile(nlth_ens* ens, int32_t profile);
+int nlth_ens_reset_stats(nlth_ens* ens);
+
+/* Continuous-batching request loop.  submit admits the request (queued until
+ * slots and HBM free up); the result buffers must stay valid until poll/wait
+ * reports completion.  NLTH_EBUSY if the request can never fit the budgets. */
+int nlth_submit(nlth_ctx* ctx, const nlth_mesh* mesh, const nlth_problem* prob, nlth_result* res,
+                uint64_t* ticket);
+int nlth_poll(nlth_ctx* ctx, uint64_t ticket, int32_t* done);
+/* returns the request's final status, or NLTH_ETIMEDOUT */
+int nlth_wait(nlth_ctx* ctx, uint64_t ticket, double timeout_s);
+int nlth_cancel(nlth_ctx* ctx, uint64_t ticket);
+
+/* Diagnostic: one element-by-element operator application y = Op x for
+ * member 0 of `prob` (Eq. 1 left-hand side with K from the given D and C from
+ * the given h), on the device, in FP64 or FP32 (precision).  D_ip:
+ * [n_tets*4*21] upper triangle of D row by row per integration point (input
+ * tet order); h: [n_tets] element damping (NULL = 0); x, y: [3*n_nodes]. */
+int nlth_apply_operator(nlth_ctx* ctx, const nlth_mesh* mesh, const nlth_problem* prob, int32_t which,
+                        int32_t precision, const double* D_ip, const double* h, const double* x,
+                        double* y);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -53,7 +53,8 @@ class _Problem(C.Structure):
                 ("dirs", _dp), ("weights", _dp), ("damping_mode", C.c_int), ("h0", C.c_double),
                 ("f_lo", C.c_double), ("f_hi", C.c_double), ("dt", C.c_double),
                 ("n_steps", C.c_int), ("input_acc", _dp), ("cg_tol", C.c_double),
-                ("cg_maxit", C.c_int), ("v0", _dp)]
+                ("cg_maxit", C.c_int), ("v0", _dp), ("apply_which", C.c_int), ("apply_D", _dp),
+                ("apply_h", _dp), ("apply_x", _dp), ("apply_y", _dp)]
 
 
 class _Result(C.Structure):
@@ -138,7 +139,7 @@ def run(mesh, prob, member: int = 0, alias=None, want_du: bool = False, want_sta
                  prob.n_springs, _p(dirs), _p(w), int(prob.damping_mode), float(prob.h0),
                  float(prob.f_lo), float(prob.f_hi), float(prob.dt), ns, _p(acc),
                  float(cg_tol if cg_tol is not None else prob.cg_tol), int(prob.cg_maxit),
-                 _p(k(_f64(v0))) if v0 is not None else None)
+                 _p(k(_f64(v0))) if v0 is not None else None, -1, None, None, None, None)
     out = dict(vel=np.zeros((ns, rc.size, 3)), iters=np.zeros(ns, np.int32))
     if want_du:
         out["du"] = np.zeros((ns, 3 * mesh.n_nodes))
@@ -157,6 +158,36 @@ def run(mesh, prob, member: int = 0, alias=None, want_du: bool = False, want_sta
     if code != 0:
         raise OracleError(code, L.or_last_error().decode(), out)
     return out
+
+
+def apply_operator(mesh, prob, which, D_ip, h, x, member: int = 0):
+    """y = Op x with the oracle's assembled CRS matrices (Op: 0 A, 1 K, 2 M)."""
+    L = lib()
+    keep = []
+
+    def k(a):
+        keep.append(a)
+        return a
+
+    xyz, tet, lay = k(_f64(mesh.xyz)), k(_i32(mesh.tet10)), k(_i32(mesh.layer))
+    bf, rc = k(_i32(mesh.bface6)), k(_i32(mesh.recv))
+    bk = k(np.ascontiguousarray(mesh.bface_kind, dtype=np.uint8))
+    m = _Mesh(mesh.n_nodes, _p(xyz), mesh.n_tets, _p(tet, _ip), _p(lay, _ip), int(bf.shape[0]),
+              _p(bf, _ip), bk.ctypes.data_as(C.POINTER(C.c_ubyte)), int(rc.size), _p(rc, _ip), None)
+    rho, vs, nu, gr = (k(_f64(np.asarray(getattr(prob, f))[member])) for f in ("rho", "vs", "nu", "gamma_ref"))
+    hm, nl, dirs, w = k(_f64(prob.h_max)), k(_i32(prob.nonlinear)), k(_f64(prob.dirs)), k(_f64(prob.weights))
+    D = k(_f64(D_ip).reshape(-1))
+    hh = k(_f64(h)) if h is not None else None
+    xx = k(_f64(x))
+    y = np.zeros_like(xx)
+    p = _Problem(prob.n_layers, _p(rho), _p(vs), _p(nu), _p(gr), _p(hm), _p(nl, _ip), prob.n_springs,
+                 _p(dirs), _p(w), int(prob.damping_mode), float(prob.h0), float(prob.f_lo), float(prob.f_hi),
+                 float(prob.dt), 0, None, 1e-8, 1, None, int(which), _p(D), _p(hh), _p(xx), _p(y))
+    out = _Result(_p(np.zeros(1)), None, None, None, None, None, None, None, 0)
+    code = L.or_run(C.byref(m), C.byref(p), C.byref(out))
+    if code != 0:
+        raise OracleError(code, L.or_last_error().decode())
+    return y
 
 
 # ---------------------------------------------------------------------------

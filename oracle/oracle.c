@@ -713,7 +713,41 @@ int or_run(const or_mesh* m, const or_problem* pr, or_result* res)
         }
     }
     double ahat = 0.0, bhat = 0.0;
-    or_rayleigh(pr->f_lo, pr->f_hi, &ahat, &bhat);
+    if (pr->damping_mode != 2) or_rayleigh(pr->f_lo, pr->f_hi, &ahat, &bhat);
+
+    if (pr->apply_which >= 0) { /* operator application with the given D and h */
+        for (long i = 0; i < 4L * ne; ++i) {
+            int k = 0;
+            for (int r = 0; r < 6; ++r)
+                for (int c = r; c < 6; ++c) {
+                    D[36 * i + 6 * r + c] = pr->apply_D[21 * i + k];
+                    D[36 * i + 6 * c + r] = pr->apply_D[21 * i + k];
+                    ++k;
+                }
+        }
+        double Ke[900], Me[900];
+        memcpy(Cg, Cabs, nb * sizeof(double));
+        for (long e = 0; e < ne; ++e) {
+            double h = pr->damping_mode == 0 ? (pr->apply_h ? pr->apply_h[e] : 0.0)
+                                             : (pr->damping_mode == 1 ? pr->h0 : 0.0);
+            or_element_matrices(Xall + 12 * e, D + 144 * e, pr->rho[m->layer[e]], Ke, Me);
+            scatter(&P, Kg, conn + 10 * e, 10, Ke, 1.0);
+            if (h != 0.0) {
+                scatter(&P, Cg, conn + 10 * e, 10, Me, ahat * h);
+                scatter(&P, Cg, conn + 10 * e, 10, Ke, bhat * h);
+            }
+        }
+        for (size_t k = 0; k < nb; ++k)
+            Ag[k] = pr->apply_which == 0 ? 4.0 / (dt * dt) * Mg[k] + 2.0 / dt * Cg[k] + Kg[k]
+                  : (pr->apply_which == 1 ? Kg[k] : Mg[k]);
+        spmv(&P, Ag, pr->apply_x, pr->apply_y);
+        free(D); free(th); free(he); free(Wbase);
+        free(Mg); free(Kg); free(Cg); free(Cabs); free(Ag);
+        free(P.rowptr); free(P.col);
+        free(G0); free(Kb); free(vp);
+        free(conn); free(gLall); free(vol); free(Xall);
+        return OR_OK;
+    }
 
     double *u = calloc(ndof, sizeof(double)), *v = calloc(ndof, sizeof(double)),
            *acc = calloc(ndof, sizeof(double)), *q = calloc(ndof, sizeof(double)),

@@ -55,6 +55,14 @@ typedef struct {
     double cg_tol;
     int cg_maxit;
     const double* v0;        /* optional [3*n_nodes] initial velocity (NULL = at rest) */
+    /* operator-application mode (kernel parity): when apply_which >= 0 the
+     * run stops after assembly and writes y = Op x, Op = 0: 4/dt^2 M + 2/dt C + K
+     * (with C from apply_h and the dashpots), 1: K, 2: M; K from apply_D */
+    int apply_which;
+    const double* apply_D;   /* [n_tets*4*21] upper triangle of D per point */
+    const double* apply_h;   /* [n_tets] element damping (NULL = 0) */
+    const double* apply_x;   /* [3*n_nodes] */
+    double* apply_y;         /* [3*n_nodes] */
 } or_problem;
 
 typedef struct {

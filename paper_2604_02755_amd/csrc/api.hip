@@ -1,0 +1,1335 @@
+// C-ABI of libnlth and the host runtime: contexts, mesh analysis (validation,
+// colouring, face and receiver tables), ensembles and the per-step driver.
+//
+// Per time step (Section 2.1, Eq. 1; Section 2.2, Algorithm 4):
+//   right-hand side of Eq. 1 (one element-by-element pass + boundary dashpots)
+//   3x3 block-Jacobi diagonal blocks of A (one pass) and their inverses
+//   CG on A du = b: FP64 block-Jacobi PCG, or FP64 flexible CG preconditioned
+//     by an FP32 block-Jacobi PCG (mixed precision)
+//   q += K du, Newmark updates of u, v, a
+//   multi-spring law at every integration point (D, theta, h), with the state
+//     streamed from pinned host memory in chunks when it does not fit in HBM
+//   receiver velocities
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <unordered_map>
+
+#include "runtime.hpp"
+
+namespace nlth {
+
+void launch_record_iters(hipStream_t s, int MB, int nm, int ns, const int* member_step, const int* stepping,
+                         const int* iters, const int* inner_total, int* iters_dev);
+
+static std::mutex g_err_mu;
+static std::string g_err;
+
+void set_error(Ctx* c, const Error& e)
+{
+    if (c) c->last_error = e.msg;
+    std::lock_guard<std::mutex> g(g_err_mu);
+    g_err = e.msg;
+}
+
+// ---------------------------------------------------------------------------
+// memory
+// ---------------------------------------------------------------------------
+
+void DevBuf::alloc(Budget* b, size_t n, bool pinned_host)
+{
+    release();
+    if (n == 0) return;
+    budget = b;
+    host = pinned_host;
+    if (b) {
+        std::lock_guard<std::mutex> g(b->mu);
+        if (pinned_host) {
+            if (b->host_limit > 0 && b->host_used + (int64_t)n > b->host_limit)
+                throw Error{NLTH_ENOMEM_HOST, "pinned host budget exceeded"};
+            b->host_used += n;
+        } else {
+            if (b->limit > 0 && b->used + (int64_t)n > b->limit)
+                throw Error{NLTH_ENOMEM_DEVICE, "device memory budget exceeded"};
+            b->used += n;
+        }
+    }
+    hipError_t e = pinned_host ? hipHostMalloc(&p, n, hipHostMallocDefault) : hipMalloc(&p, n);
+    if (e != hipSuccess) {
+        p = nullptr;
+        if (b) {
+            std::lock_guard<std::mutex> g(b->mu);
+            if (pinned_host) b->host_used -= n; else b->used -= n;
+        }
+        throw Error{pinned_host ? NLTH_ENOMEM_HOST : NLTH_ENOMEM_DEVICE,
+                    std::string(pinned_host ? "hipHostMalloc" : "hipMalloc") + " failed: " + hipGetErrorString(e)};
+    }
+    bytes = n;
+}
+
+void DevBuf::release()
+{
+    if (p) {
+        if (host) (void)hipHostFree(p); else (void)hipFree(p);
+        if (budget) {
+            std::lock_guard<std::mutex> g(budget->mu);
+            if (host) budget->host_used -= bytes; else budget->used -= bytes;
+        }
+    }
+    p = nullptr;
+    bytes = 0;
+}
+
+template <typename T>
+static void upload(Budget* b, DevBuf& d, const std::vector<T>& h)
+{
+    d.alloc(b, h.size() * sizeof(T));
+    if (!h.empty()) NLTH_HIP(hipMemcpy(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+}
+
+int pad_members(int nm)
+{
+    if (nm <= 1) return 1;
+    if (nm <= 256) {
+        int p = 1;
+        while (p < nm) p <<= 1;
+        return p;
+    }
+    return (nm + 255) / 256 * 256;
+}
+
+// ---------------------------------------------------------------------------
+// mesh analysis
+// ---------------------------------------------------------------------------
+
+static const int kEdge[6][2] = {{0, 1}, {1, 2}, {2, 0}, {0, 3}, {1, 3}, {2, 3}};
+
+// barycentric gradients and volume of a straight-sided tet
+static bool tet_geometry(const double X[4][3], double gL[4][3], double* vol)
+{
+    double J[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) J[a][b] = X[b + 1][a] - X[0][a];
+    const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+    *vol = det / 6.0;
+    if (!(det > 0.0)) return false;
+    // rows of J^-1 are the gradients of xi_1..xi_3
+    double inv[3][3];
+    inv[0][0] = c00 / det;
+    inv[1][0] = c01 / det;
+    inv[2][0] = c02 / det;
+    inv[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+    inv[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+    inv[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+    inv[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+    inv[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+    inv[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+    for (int i = 0; i < 3; ++i)
+        for (int a = 0; a < 3; ++a) gL[i + 1][a] = inv[i][a];
+    for (int a = 0; a < 3; ++a) gL[0][a] = -(gL[1][a] + gL[2][a] + gL[3][a]);
+    return true;
+}
+
+// 6-node triangle mass int N_a N_b dA: the classical pattern A/180 (corner
+// diagonal 6, corner-corner -1, corner and opposite edge -4, corner and an
+// edge through it 0, edge diagonal 32, edge-edge 16).
+static void p2_triangle_mass(double A, double M[36])
+{
+    static const int FE[3][2] = {{0, 1}, {1, 2}, {2, 0}};
+    for (int a = 0; a < 6; ++a)
+        for (int b = 0; b < 6; ++b) {
+            double v;
+            if (a < 3 && b < 3) v = (a == b) ? 6 : -1;
+            else if (a < 3 || b < 3) {
+                int c = a < 3 ? a : b, e = (a < 3 ? b : a) - 3;
+                v = (FE[e][0] == c || FE[e][1] == c) ? 0 : -4;
+            } else v = (a == b) ? 32 : 16;
+            M[6 * a + b] = v * A / 180.0;
+        }
+}
+
+struct Key3 {
+    int a, b, c;
+    bool operator==(const Key3& o) const { return a == o.a && b == o.b && c == o.c; }
+};
+struct Key3Hash {
+    size_t operator()(const Key3& k) const
+    {
+        return ((size_t)k.a * 73856093u) ^ ((size_t)k.b * 19349663u) ^ ((size_t)k.c * 83492791u);
+    }
+};
+static Key3 key3(int x, int y, int z)
+{
+    int v[3] = {x, y, z};
+    std::sort(v, v + 3);
+    return Key3{v[0], v[1], v[2]};
+}
+
+static void build_mesh(Ctx* ctx, const nlth_mesh_desc* d, Mesh& M)
+{
+    if (!d || d->n_nodes <= 0 || d->n_tets <= 0 || !d->xyz || !d->tet10 || !d->layer)
+        throw Error{NLTH_EINVAL, "mesh: n_nodes, n_tets, xyz, tet10 and layer are required"};
+    if (d->n_bfaces < 0 || (d->n_bfaces > 0 && (!d->bface6 || !d->bface_kind)))
+        throw Error{NLTH_EINVAL, "mesh: bface6/bface_kind missing"};
+    if (d->n_recv < 0 || (d->n_recv > 0 && !d->recv)) throw Error{NLTH_EINVAL, "mesh: recv missing"};
+    const int nn = d->n_nodes, ne = d->n_tets;
+    M.ctx = ctx;
+    M.nn = nn;
+    M.ne = ne;
+    M.xyz.assign(d->xyz, d->xyz + 3L * nn);
+    char buf[256];
+    for (long i = 0; i < 10L * ne; ++i)
+        if (d->tet10[i] < 0 || d->tet10[i] >= nn) {
+            snprintf(buf, sizeof buf, "mesh: tet %ld references node %d outside [0, %d)", i / 10, d->tet10[i], nn);
+            throw Error{NLTH_EINVAL, buf};
+        }
+    M.max_layer = 0;
+    for (int e = 0; e < ne; ++e) {
+        if (d->layer[e] < 0) {
+            snprintf(buf, sizeof buf, "mesh: tet %d has negative layer id", e);
+            throw Error{NLTH_EINVAL, buf};
+        }
+        M.max_layer = std::max(M.max_layer, d->layer[e]);
+    }
+    // geometry per input tet
+    std::vector<double> gl(12L * ne), vol(ne);
+    double vtot = 0;
+    for (int e = 0; e < ne; ++e) {
+        const int* t = d->tet10 + 10L * e;
+        double X[4][3], G[4][3], V;
+        for (int a = 0; a < 4; ++a)
+            for (int c = 0; c < 3; ++c) X[a][c] = d->xyz[3L * t[a] + c];
+        if (!tet_geometry(X, G, &V)) {
+            snprintf(buf, sizeof buf, "mesh: tet %d has a non-positive Jacobian", e);
+            throw Error{NLTH_EINVAL, buf};
+        }
+        for (int k = 0; k < 6; ++k) {
+            const double* pa = d->xyz + 3L * t[kEdge[k][0]];
+            const double* pb = d->xyz + 3L * t[kEdge[k][1]];
+            const double* pm = d->xyz + 3L * t[4 + k];
+            double el = 0, dv = 0;
+            for (int c = 0; c < 3; ++c) {
+                el += (pb[c] - pa[c]) * (pb[c] - pa[c]);
+                double q = pm[c] - 0.5 * (pa[c] + pb[c]);
+                dv += q * q;
+            }
+            if (dv > 1e-18 * el) {
+                snprintf(buf, sizeof buf, "mesh: tet %d is not straight-sided (mid-node of edge %d off the midpoint)", e, k);
+                throw Error{NLTH_EINVAL, buf};
+            }
+        }
+        for (int k = 0; k < 12; ++k) gl[12L * e + k] = G[k / 3][k % 3];
+        vol[e] = V;
+        vtot += V;
+    }
+    M.volume = vtot;
+
+    // greedy colouring: a tet takes the lowest colour no tet sharing a node has
+    const int W = 4;  // up to 256 colours
+    std::vector<uint64_t> used((size_t)nn * W, 0);
+    std::vector<int> color(ne);
+    int ncol = 0;
+    for (int e = 0; e < ne; ++e) {
+        const int* t = d->tet10 + 10L * e;
+        uint64_t u[W] = {0, 0, 0, 0};
+        for (int a = 0; a < 10; ++a)
+            for (int w = 0; w < W; ++w) u[w] |= used[(size_t)t[a] * W + w];
+        int c = -1;
+        for (int w = 0; w < W && c < 0; ++w)
+            if (~u[w]) c = 64 * w + __builtin_ctzll(~u[w]);
+        if (c < 0) throw Error{NLTH_EINVAL, "mesh: more than 256 colours needed"};
+        color[e] = c;
+        ncol = std::max(ncol, c + 1);
+        for (int a = 0; a < 10; ++a) used[(size_t)t[a] * W + c / 64] |= 1ull << (c % 64);
+    }
+    M.ncolor = ncol;
+    M.color_off.assign(ncol + 1, 0);
+    for (int e = 0; e < ne; ++e) M.color_off[color[e] + 1]++;
+    for (int c = 0; c < ncol; ++c) M.color_off[c + 1] += M.color_off[c];
+    M.order.resize(ne);
+    M.inv_order.resize(ne);
+    {
+        std::vector<int> fill(M.color_off.begin(), M.color_off.end() - 1);
+        for (int e = 0; e < ne; ++e) {
+            int pos = fill[color[e]]++;
+            M.order[pos] = e;
+            M.inv_order[e] = pos;
+        }
+    }
+    // sorted SoA arrays
+    std::vector<int> conn(10L * ne), lay(ne);
+    std::vector<double> g64(13L * ne);
+    std::vector<float> g32(13L * ne);
+    for (int p = 0; p < ne; ++p) {
+        int e = M.order[p];
+        for (int k = 0; k < 10; ++k) conn[(long)k * ne + p] = d->tet10[10L * e + k];
+        for (int k = 0; k < 12; ++k) g64[(long)k * ne + p] = gl[12L * e + k];
+        g64[12L * ne + p] = vol[e];
+        lay[p] = d->layer[e];
+    }
+    for (long i = 0; i < 13L * ne; ++i) g32[i] = (float)g64[i];
+
+    // boundary faces: owning tet (for the material), normal, P2 face mass
+    std::unordered_map<Key3, int, Key3Hash> owner;
+    owner.reserve(4L * ne);
+    static const int TF[4][3] = {{0, 1, 2}, {1, 2, 3}, {0, 2, 3}, {0, 1, 3}};
+    if (d->n_bfaces > 0)
+        for (int e = 0; e < ne; ++e)
+            for (int f = 0; f < 4; ++f) {
+                const int* t = d->tet10 + 10L * e;
+                owner[key3(t[TF[f][0]], t[TF[f][1]], t[TF[f][2]])] = e;
+            }
+    const int nf = d->n_bfaces;
+    M.nf = nf;
+    std::vector<int> fnode(6L * nf), flayer(nf);
+    std::vector<double> fM(36L * nf), fn(3L * nf);
+    std::vector<uint8_t> fkind(nf);
+    std::vector<std::vector<std::pair<int, int>>> node_faces;
+    std::vector<int> bnodes;
+    std::unordered_map<int, int> bn_index;
+    for (int f = 0; f < nf; ++f) {
+        const int* q = d->bface6 + 6L * f;
+        for (int a = 0; a < 6; ++a)
+            if (q[a] < 0 || q[a] >= nn) {
+                snprintf(buf, sizeof buf, "mesh: boundary face %d references node %d outside [0, %d)", f, q[a], nn);
+                throw Error{NLTH_EINVAL, buf};
+            }
+        if (d->bface_kind[f] > 1) {
+            snprintf(buf, sizeof buf, "mesh: boundary face %d has kind %d (0 base, 1 side)", f, d->bface_kind[f]);
+            throw Error{NLTH_EINVAL, buf};
+        }
+        auto it = owner.find(key3(q[0], q[1], q[2]));
+        if (it == owner.end()) {
+            snprintf(buf, sizeof buf, "mesh: boundary face %d is not a face of any tet", f);
+            throw Error{NLTH_EINVAL, buf};
+        }
+        flayer[f] = d->layer[it->second];
+        fkind[f] = d->bface_kind[f];
+        double e1[3], e2[3], c[3];
+        for (int k = 0; k < 3; ++k) {
+            e1[k] = d->xyz[3L * q[1] + k] - d->xyz[3L * q[0] + k];
+            e2[k] = d->xyz[3L * q[2] + k] - d->xyz[3L * q[0] + k];
+        }
+        c[0] = e1[1] * e2[2] - e1[2] * e2[1];
+        c[1] = e1[2] * e2[0] - e1[0] * e2[2];
+        c[2] = e1[0] * e2[1] - e1[1] * e2[0];
+        double nc = sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+        if (!(nc > 0)) {
+            snprintf(buf, sizeof buf, "mesh: boundary face %d is degenerate", f);
+            throw Error{NLTH_EINVAL, buf};
+        }
+        for (int k = 0; k < 3; ++k) fn[3L * f + k] = c[k] / nc;
+        p2_triangle_mass(0.5 * nc, &fM[36L * f]);
+        for (int a = 0; a < 6; ++a) {
+            fnode[6L * f + a] = q[a];
+            auto bi = bn_index.find(q[a]);
+            int idx;
+            if (bi == bn_index.end()) {
+                idx = (int)bnodes.size();
+                bn_index[q[a]] = idx;
+                bnodes.push_back(q[a]);
+                node_faces.emplace_back();
+            } else idx = bi->second;
+            node_faces[idx].push_back({f, a});
+        }
+    }
+    // boundary nodes in ascending node order, their (face, local) lists
+    std::vector<int> perm(bnodes.size());
+    for (size_t i = 0; i < perm.size(); ++i) perm[i] = (int)i;
+    std::sort(perm.begin(), perm.end(), [&](int x, int y) { return bnodes[x] < bnodes[y]; });
+    std::vector<int> bn_node, bn_ptr(1, 0), bn_face, bn_loc;
+    for (int pi : perm) {
+        bn_node.push_back(bnodes[pi]);
+        for (auto& fl : node_faces[pi]) {
+            bn_face.push_back(fl.first);
+            bn_loc.push_back(fl.second);
+        }
+        bn_ptr.push_back((int)bn_face.size());
+    }
+    M.nbn = (int)bn_node.size();
+    M.nrecv = d->n_recv;
+    M.recv.assign(d->recv, d->recv + d->n_recv);
+    for (int r = 0; r < d->n_recv; ++r)
+        if (M.recv[r] < 0 || M.recv[r] >= nn) {
+            snprintf(buf, sizeof buf, "mesh: receiver %d is node %d outside [0, %d)", r, M.recv[r], nn);
+            throw Error{NLTH_EINVAL, buf};
+        }
+    if (ctx->host_only) return;
+    Budget* b = &ctx->budget;
+    upload(b, M.conn, conn);
+    upload(b, M.geo64, g64);
+    upload(b, M.geo32, g32);
+    upload(b, M.layer, lay);
+    upload(b, M.bn_node, bn_node);
+    upload(b, M.bn_ptr, bn_ptr);
+    upload(b, M.bn_face, bn_face);
+    upload(b, M.bn_loc, bn_loc);
+    upload(b, M.f_node, fnode);
+    upload(b, M.f_M, fM);
+    upload(b, M.f_n, fn);
+    upload(b, M.f_layer, flayer);
+    upload(b, M.f_kind, fkind);
+    upload(b, M.recv_d, M.recv);
+}
+
+DevMesh Mesh::dev() const
+{
+    DevMesh d{};
+    d.ne = ne;
+    d.nn = nn;
+    d.conn = conn.as<int>();
+    d.geo64 = geo64.as<double>();
+    d.geo32 = geo32.as<float>();
+    d.layer = layer.as<int>();
+    d.nbn = nbn;
+    d.bn_node = bn_node.as<int>();
+    d.bn_ptr = bn_ptr.as<int>();
+    d.bn_face = bn_face.as<int>();
+    d.bn_loc = bn_loc.as<int>();
+    d.f_node = f_node.as<int>();
+    d.f_M = f_M.as<double>();
+    d.f_n = f_n.as<double>();
+    d.f_layer = f_layer.as<int>();
+    d.f_kind = f_kind.as<uint8_t>();
+    return d;
+}
+
+// ---------------------------------------------------------------------------
+// problem
+// ---------------------------------------------------------------------------
+
+void copy_problem(const nlth_problem* in, Problem& P)
+{
+    if (!in) throw Error{NLTH_EINVAL, "problem is NULL"};
+    if (in->n_members <= 0 || in->n_layers <= 0 || in->n_springs <= 0 || in->n_steps < 0)
+        throw Error{NLTH_EINVAL, "problem: n_members, n_layers, n_springs must be positive, n_steps >= 0"};
+    if (!in->rho || !in->vs || !in->nu || !in->gamma_ref || !in->h_max || !in->nonlinear || !in->dirs ||
+        !in->weights || (in->n_steps > 0 && !in->input_acc))
+        throw Error{NLTH_EINVAL, "problem: a required array is NULL"};
+    if (!(in->dt > 0) || !(in->cg_tol > 0) || in->cg_maxit <= 0)
+        throw Error{NLTH_EINVAL, "problem: dt, cg_tol and cg_maxit must be positive"};
+    if (in->precision != NLTH_FP64 && in->precision != NLTH_MIXED)
+        throw Error{NLTH_EINVAL, "problem: precision must be NLTH_FP64 or NLTH_MIXED"};
+    if (in->precision == NLTH_MIXED && (!(in->inner_tol > 0) || in->inner_maxit <= 0))
+        throw Error{NLTH_EINVAL, "problem: inner_tol and inner_maxit must be positive for NLTH_MIXED"};
+    if (in->damping_mode < 0 || in->damping_mode > 2) throw Error{NLTH_EINVAL, "problem: bad damping_mode"};
+    if (in->damping_mode == NLTH_DAMPING_LAW || in->damping_mode == NLTH_DAMPING_CONST)
+        if (!(in->f_lo > 0) || !(in->f_hi > in->f_lo)) throw Error{NLTH_EINVAL, "problem: need 0 < f_lo < f_hi"};
+    P.nm = in->n_members;
+    P.nl = in->n_layers;
+    P.ns = in->n_springs;
+    P.n_steps = in->n_steps;
+    const long ml = (long)P.nm * P.nl;
+    P.rho.assign(in->rho, in->rho + ml);
+    P.vs.assign(in->vs, in->vs + ml);
+    P.nu.assign(in->nu, in->nu + ml);
+    P.gref.assign(in->gamma_ref, in->gamma_ref + ml);
+    P.hmax.assign(in->h_max, in->h_max + P.nl);
+    P.nonlinear.assign(in->nonlinear, in->nonlinear + P.nl);
+    P.dirs.assign(in->dirs, in->dirs + 6L * P.ns);
+    P.w.assign(in->weights, in->weights + P.ns);
+    if (P.n_steps > 0) P.acc.assign(in->input_acc, in->input_acc + (long)P.nm * P.n_steps * 3);
+    for (long i = 0; i < ml; ++i) {
+        if (!(P.rho[i] > 0) || !(P.vs[i] > 0) || !(P.nu[i] >= 0 && P.nu[i] < 0.5) || !(P.gref[i] > 0))
+            throw Error{NLTH_EINVAL, "problem: need rho > 0, vs > 0, 0 <= nu < 0.5, gamma_ref > 0"};
+    }
+    for (int l = 0; l < P.nl; ++l)
+        if (!(P.hmax[l] >= 0 && P.hmax[l] < 2.0 / M_PI)) throw Error{NLTH_EINVAL, "problem: need 0 <= h_max < 2/pi"};
+    for (double x : P.acc)
+        if (!std::isfinite(x)) throw Error{NLTH_EINVAL, "problem: input_acc has a non-finite value"};
+    P.damping_mode = in->damping_mode;
+    P.h0 = in->h0;
+    P.f_lo = in->f_lo;
+    P.f_hi = in->f_hi;
+    P.dt = in->dt;
+    P.cg_tol = in->cg_tol;
+    P.cg_maxit = in->cg_maxit;
+    P.precision = in->precision;
+    P.inner_tol = in->inner_tol;
+    P.inner_maxit = in->inner_maxit;
+}
+
+// least-squares Rayleigh fit: minimise int (a/(4 pi f) + pi b f - 1)^2 df over [f_lo, f_hi]
+static void rayleigh_fit(double fl, double fh, double* a, double* b)
+{
+    const double pi = M_PI;
+    const double s11 = (1.0 / fl - 1.0 / fh) / (16.0 * pi * pi);
+    const double s12 = 0.25 * (fh - fl);
+    const double s22 = pi * pi * (fh * fh * fh - fl * fl * fl) / 3.0;
+    const double t1 = log(fh / fl) / (4.0 * pi);
+    const double t2 = 0.5 * pi * (fh * fh - fl * fl);
+    const double det = s11 * s22 - s12 * s12;
+    *a = (t1 * s22 - s12 * t2) / det;
+    *b = (s11 * t2 - s12 * t1) / det;
+}
+
+int64_t ensemble_bytes(const Mesh& m, const Problem& p, int MB, bool paged)
+{
+    const int64_t ndof = 3L * m.nn;
+    int64_t v = ndof * MB * 8;
+    int64_t bytes = 10 * v;                                  // u v a q du b r z p Ap
+    bytes += 2 * (int64_t)m.nn * 6 * MB * 8 + (int64_t)m.nn * 6 * MB * 4;  // diag, pinv, pinv32
+    if (p.precision == NLTH_MIXED) bytes += 5 * ndof * MB * 4;
+    bytes += (int64_t)m.ne * 4 * 21 * MB * 12;              // D64 + D32
+    bytes += (int64_t)m.ne * MB * 8;                        // h
+    bytes += (int64_t)p.n_steps * std::max(1, m.nrecv) * 3 * MB * 8;  // receiver history
+    bytes += (int64_t)p.n_steps * 3 * MB * 8 * 2;           // acc, vI
+    if (!paged) bytes += (int64_t)m.ne * 4 * p.ns * MB * 40;
+    return bytes;
+}
+
+// ---------------------------------------------------------------------------
+// ensemble
+// ---------------------------------------------------------------------------
+
+hipEvent_t Ens::ev()
+{
+    if (!ev_pool.empty()) {
+        hipEvent_t e = ev_pool.back();
+        ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    NLTH_HIP(hipEventCreate(&e));
+    return e;
+}
+
+void Ens::tstart(hipEvent_t& e0)
+{
+    e0 = nullptr;
+    if (!profile) return;
+    e0 = ev();
+    NLTH_HIP(hipEventRecord(e0, s));
+}
+
+void Ens::tstop(hipEvent_t e0, ProfCat* cat, int64_t elems)
+{
+    if (!profile || !e0) return;
+    hipEvent_t e1 = ev();
+    NLTH_HIP(hipEventRecord(e1, s));
+    pending.push_back({{e0, e1}, cat});
+    cat->elems += elems;
+}
+
+void Ens::collect_prof()
+{
+    for (auto& pe : pending) {
+        float ms = 0;
+        NLTH_HIP(hipEventElapsedTime(&ms, pe.first.first, pe.first.second));
+        pe.second->ms += ms;
+        pe.second->n += 1;
+        ev_pool.push_back(pe.first.first);
+        ev_pool.push_back(pe.first.second);
+    }
+    pending.clear();
+}
+
+void Ens::sync()
+{
+    NLTH_HIP(hipStreamSynchronize(s));
+    collect_prof();
+}
+
+void Ens::create(Ctx* c, const Mesh* m, const Problem& prob, int member_pad)
+{
+    ctx = c;
+    mesh = m;
+    P = prob;
+    if (P.nl <= m->max_layer) throw Error{NLTH_EINVAL, "problem: mesh uses a layer id >= n_layers"};
+    nm = P.nm;
+    MB = member_pad > 0 ? member_pad : pad_members(nm);
+    ndof = 3L * m->nn;
+    s = c->stream;
+    Budget* bg = &c->budget;
+    sc.dt = P.dt;
+    sc.damping_mode = P.damping_mode;
+    sc.h0 = P.h0;
+    if (P.damping_mode == NLTH_DAMPING_NONE) sc.ahat = sc.bhat = 0.0;
+    else rayleigh_fit(P.f_lo, P.f_hi, &sc.ahat, &sc.bhat);
+
+    // per-member material table (padded members copy member 0)
+    std::vector<double> mt((size_t)P.nl * MAT_N * MB, 0.0);
+    for (int l = 0; l < P.nl; ++l)
+        for (int mm = 0; mm < MB; ++mm) {
+            const int src = mm < nm ? mm : 0;
+            const double rho = P.rho[(long)src * P.nl + l], vs = P.vs[(long)src * P.nl + l];
+            const double nu = P.nu[(long)src * P.nl + l];
+            const double G0 = rho * vs * vs, lam = 2.0 * G0 * nu / (1.0 - 2.0 * nu);
+            const double hm = P.hmax[l];
+            double* col = &mt[(size_t)l * MAT_N * MB];
+            col[MAT_RHO * MB + mm] = rho;
+            col[MAT_G0 * MB + mm] = G0;
+            col[MAT_KB * MB + mm] = lam + 2.0 * G0 / 3.0;
+            col[MAT_VS * MB + mm] = vs;
+            col[MAT_VP * MB + mm] = sqrt((lam + 2.0 * G0) / rho);
+            col[MAT_GREF * MB + mm] = P.gref[(long)src * P.nl + l];
+            col[MAT_HMAX * MB + mm] = hm;
+            col[MAT_BETA * MB + mm] = 2.0 * M_PI * hm / (2.0 - M_PI * hm);
+        }
+    upload(bg, mat, mt);
+    upload(bg, dirs, P.dirs);
+    upload(bg, w, P.w);
+    upload(bg, nonlinear, P.nonlinear);
+
+    const int ns_steps = std::max(1, P.n_steps);
+    // inputs: acceleration as given, incident velocity by the trapezoid rule (device)
+    std::vector<double> acc_pad((size_t)MB * ns_steps * 3, 0.0);
+    if (P.n_steps > 0) std::copy(P.acc.begin(), P.acc.end(), acc_pad.begin());
+    upload(bg, acc, acc_pad);
+    vI_all.alloc(bg, acc_pad.size() * 8);
+    launch_incident_velocity(s, MB, MB, ns_steps, acc.as<double>(), vI_all.as<double>(), P.dt);
+    vI_cur.alloc(bg, 3L * MB * 8);
+
+    const size_t vb = (size_t)ndof * MB * 8;
+    for (DevBuf* bb : {&u, &v, &a, &q, &du, &b, &r, &z, &p, &Ap}) {
+        bb->alloc(bg, vb);
+        launch_fill(s, bb->as<double>(), 0.0, (long)ndof * MB);
+    }
+    diag.alloc(bg, (size_t)m->nn * 6 * MB * 8);
+    pinv.alloc(bg, (size_t)m->nn * 6 * MB * 8);
+    pinv32.alloc(bg, (size_t)m->nn * 6 * MB * 4);
+    if (P.precision == NLTH_MIXED)
+        for (DevBuf* bb : {&ir, &iz, &ip, &iw, &iAp}) {
+            bb->alloc(bg, (size_t)ndof * MB * 4);
+            launch_fill32(s, bb->as<float>(), 0.0f, (long)ndof * MB);
+        }
+    const size_t nD = (size_t)m->ne * 4 * 21 * MB;
+    D64.alloc(bg, nD * 8);
+    D32.alloc(bg, nD * 4);
+    h.alloc(bg, (size_t)m->ne * MB * 8);
+    const DevMesh dm = m->dev();
+    launch_law_init(s, dm, MB, MB, mat.as<double>(), P.nl, P.ns, dirs.as<double>(), w.as<double>(),
+                    D64.as<double>(), D32.as<float>(), h.as<double>());
+
+    // law state: resident if it fits the remaining budget, else paged
+    const size_t per_elem = (size_t)4 * P.ns * MB * 40;
+    const size_t theta_bytes = per_elem * m->ne;
+    int64_t avail;
+    {
+        std::lock_guard<std::mutex> g(bg->mu);
+        avail = bg->limit > 0 ? bg->limit - bg->used : INT64_MAX;
+    }
+    const int64_t reserve = (int64_t)P.n_steps * std::max(1, m->nrecv) * 3 * MB * 8 * 2 + (64 << 20);
+    paged = (int64_t)theta_bytes + reserve > avail;
+    if (!paged) {
+        theta.alloc(bg, theta_bytes);
+        launch_theta_init(s, theta.p, m->ne, P.ns, MB);
+    } else {
+        // chunk ring: the largest chunk with 3 slots fitting a quarter of what is left
+        int64_t slot_bytes = std::max<int64_t>((avail - reserve) / 4 / ring, (int64_t)per_elem);
+        slot_bytes = std::min<int64_t>(slot_bytes, (int64_t)1 << 31);
+        chunk_elems = (int)std::max<int64_t>(1, std::min<int64_t>(slot_bytes / (int64_t)per_elem, m->ne));
+        nchunks = (m->ne + chunk_elems - 1) / chunk_elems;
+        if (nchunks < ring) ring = std::max(1, nchunks);
+        theta_host.alloc(bg, theta_bytes, true);
+        theta.alloc(bg, (size_t)chunk_elems * per_elem * ring);
+        long off = 0;
+        for (int cix = 0; cix < nchunks; ++cix) {
+            int e0 = cix * chunk_elems, ec = std::min(chunk_elems, m->ne - e0);
+            chunk_e0.push_back(e0);
+            chunk_ec.push_back(ec);
+            chunk_off.push_back(off);
+            off += (long)ec * per_elem;
+        }
+        // initialise each chunk on the device and write it to the host copy
+        for (int cix = 0; cix < nchunks; ++cix) {
+            launch_theta_init(s, theta.p, chunk_ec[cix], P.ns, MB);
+            NLTH_HIP(hipMemcpyAsync((char*)theta_host.p + chunk_off[cix], theta.p, (size_t)chunk_ec[cix] * per_elem,
+                                    hipMemcpyDeviceToHost, s));
+        }
+        NLTH_HIP(hipStreamCreateWithFlags(&s_h2d, hipStreamNonBlocking));
+        NLTH_HIP(hipStreamCreateWithFlags(&s_d2h, hipStreamNonBlocking));
+        for (int k = 0; k < ring; ++k) {
+            hipEvent_t e1, e2, e3;
+            NLTH_HIP(hipEventCreateWithFlags(&e1, hipEventDisableTiming));
+            NLTH_HIP(hipEventCreateWithFlags(&e2, hipEventDisableTiming));
+            NLTH_HIP(hipEventCreateWithFlags(&e3, hipEventDisableTiming));
+            ev_h2d.push_back(e1);
+            ev_law.push_back(e2);
+            ev_d2h.push_back(e3);
+        }
+        slot_chunk.assign(ring, -1);
+        prefetched.assign(nchunks, false);
+        NLTH_HIP(hipEventCreate(&ev_copy0));
+        NLTH_HIP(hipEventCreate(&ev_copy1));
+    }
+
+    hist.alloc(bg, (size_t)MB * ns_steps * std::max(1, m->nrecv) * 3 * 8);
+    launch_fill(s, hist.as<double>(), 0.0, (long)MB * ns_steps * std::max(1, m->nrecv) * 3);
+    vmax.alloc(bg, (size_t)MB * std::max(1, m->nrecv) * 8);
+    launch_fill(s, vmax.as<double>(), 0.0, (long)MB * std::max(1, m->nrecv));
+    iters_dev.alloc(bg, (size_t)MB * ns_steps * 2 * 4);
+    NLTH_HIP(hipMemsetAsync(iters_dev.p, 0, iters_dev.bytes, s));
+    partial.alloc(bg, (size_t)3 * kMaxPartialBlocks * MB * 8);
+    // CG scalars: 12 double arrays and 9 int arrays of MB, plus any_active
+    scal.alloc(bg, (size_t)MB * (12 * 8 + 9 * 4) + 64);
+    NLTH_HIP(hipMemsetAsync(scal.p, 0, scal.bytes, s));
+    double* dptr = scal.as<double>();
+    cs.bb = dptr; cs.rr = dptr + MB; cs.rz = dptr + 2 * MB; cs.alpha = dptr + 3 * MB; cs.beta = dptr + 4 * MB;
+    cs.pAp = dptr + 5 * MB; cs.r0 = dptr + 6 * MB; cs.irr = dptr + 7 * MB; cs.irz = dptr + 8 * MB;
+    cs.ialpha = dptr + 9 * MB; cs.ibeta = dptr + 10 * MB; cs.ir0 = dptr + 11 * MB;
+    int* iptr = (int*)(dptr + 12 * MB);
+    cs.active = iptr; cs.iters = iptr + MB; cs.status = iptr + 2 * MB; cs.inner_active = iptr + 3 * MB;
+    cs.inner_iters = iptr + 4 * MB; cs.inner_total = iptr + 5 * MB;
+    cs.any_active = iptr + 8 * MB;
+    member_step.alloc(bg, (size_t)MB * 4);
+    stepping.alloc(bg, (size_t)MB * 4);
+    cs.stepping = stepping.as<int>();
+    h_member_step.assign(MB, 0);
+    h_stepping.assign(MB, 0);
+    h_status.assign(MB, 0);
+    {
+        std::lock_guard<std::mutex> g(bg->mu);
+        dev_bytes = bg->used;
+        host_bytes = bg->host_used;
+    }
+    NLTH_HIP(hipStreamSynchronize(s));
+}
+
+void Ens::destroy()
+{
+    if (!ctx) return;
+    if (s) (void)hipStreamSynchronize(s);
+    if (s_h2d) { (void)hipStreamSynchronize(s_h2d); (void)hipStreamDestroy(s_h2d); s_h2d = nullptr; }
+    if (s_d2h) { (void)hipStreamSynchronize(s_d2h); (void)hipStreamDestroy(s_d2h); s_d2h = nullptr; }
+    for (auto e : ev_h2d) (void)hipEventDestroy(e);
+    for (auto e : ev_law) (void)hipEventDestroy(e);
+    for (auto e : ev_d2h) (void)hipEventDestroy(e);
+    ev_h2d.clear(); ev_law.clear(); ev_d2h.clear();
+    for (auto& pe : pending) { (void)hipEventDestroy(pe.first.first); (void)hipEventDestroy(pe.first.second); }
+    pending.clear();
+    for (auto e : ev_pool) (void)hipEventDestroy(e);
+    ev_pool.clear();
+    if (ev_copy0) (void)hipEventDestroy(ev_copy0);
+    if (ev_copy1) (void)hipEventDestroy(ev_copy1);
+    ev_copy0 = ev_copy1 = nullptr;
+    ctx = nullptr;
+}
+
+void Ens::dots(int nd, const double* a0, const double* b0, const double* a1, const double* b1, const double* a2,
+               const double* b2, int& nblk)
+{
+    launch_dots(s, nd, a0, b0, a1, b1, a2, b2, ndof, MB, partial.as<double>(), &nblk);
+}
+
+int Ens::read_any_active()
+{
+    int h = 0;
+    NLTH_HIP(hipMemcpyAsync(&h, cs.any_active, sizeof(int), hipMemcpyDeviceToHost, s));
+    NLTH_HIP(hipStreamSynchronize(s));
+    return h;
+}
+
+void Ens::ebe(OpMode mode, const double* x1, const double* x2, double* y, const int* act)
+{
+    const DevMesh dm = mesh->dev();
+    for (int c = 0; c < mesh->ncolor; ++c) {
+        const int e0 = mesh->color_off[c], e1 = mesh->color_off[c + 1];
+        hipEvent_t t0;
+        tstart(t0);
+        launch_ebe<double>(s, mode, dm, MB, nm, e0, e1, D64.as<double>(), h.as<double>(), mat.as<double>(), P.nl, sc,
+                           x1, x2, y, act);
+        tstop(t0, &pc_ebe64, (int64_t)(e1 - e0) * nm);
+    }
+}
+
+void Ens::ebe32(const float* x, float* y, const int* act)
+{
+    const DevMesh dm = mesh->dev();
+    for (int c = 0; c < mesh->ncolor; ++c) {
+        const int e0 = mesh->color_off[c], e1 = mesh->color_off[c + 1];
+        hipEvent_t t0;
+        tstart(t0);
+        launch_ebe<float>(s, OP_A, dm, MB, nm, e0, e1, D32.as<float>(), h.as<double>(), mat.as<double>(), P.nl, sc,
+                          x, nullptr, y, act);
+        tstop(t0, &pc_ebe32, (int64_t)(e1 - e0) * nm);
+    }
+    launch_dashpot<float>(s, dm, MB, nm, mat.as<double>(), P.nl, (float)(2.0 / P.dt), x, y, nullptr, act);
+}
+
+void Ens::build_rhs()
+{
+    // b = f - q + C v + M (a + 4/dt v), f = 2 C_base v_I
+    launch_neg_copy(s, q.as<double>(), b.as<double>(), (long)ndof * MB);
+    ebe(OP_RHS, v.as<double>(), a.as<double>(), b.as<double>(), stepping.as<int>());
+    launch_dashpot<double>(s, mesh->dev(), MB, nm, mat.as<double>(), P.nl, 1.0, v.as<double>(), b.as<double>(),
+                           vI_cur.as<double>(), stepping.as<int>());
+}
+
+void Ens::build_diag()
+{
+    const DevMesh dm = mesh->dev();
+    launch_fill(s, diag.as<double>(), 0.0, (long)mesh->nn * 6 * MB);
+    for (int c = 0; c < mesh->ncolor; ++c)
+        launch_diag(s, dm, MB, nm, mesh->color_off[c], mesh->color_off[c + 1], D64.as<double>(), h.as<double>(),
+                    mat.as<double>(), P.nl, sc, diag.as<double>());
+    launch_diag_dashpot(s, dm, MB, nm, mat.as<double>(), P.nl, 2.0 / P.dt, diag.as<double>());
+    launch_invert_diag(s, mesh->nn, MB, nm, diag.as<double>(), pinv.as<double>(),
+                       P.precision == NLTH_MIXED ? pinv32.as<float>() : nullptr);
+}
+
+void Ens::solve_pcg()
+{
+    const long n = ndof;
+    int nblk;
+    double* x = du.as<double>();
+    const int* st = stepping.as<int>();
+    const double tol2 = P.cg_tol * P.cg_tol;
+    launch_fill(s, Ap.as<double>(), 0.0, n * MB);
+    ebe(OP_A, x, nullptr, Ap.as<double>(), st);
+    launch_dashpot<double>(s, mesh->dev(), MB, nm, mat.as<double>(), P.nl, 2.0 / P.dt, x, Ap.as<double>(), nullptr, st);
+    launch_pcg_start(s, mesh->nn, MB, nm, b.as<double>(), Ap.as<double>(), pinv.as<double>(), r.as<double>(),
+                     z.as<double>(), p.as<double>(), st);
+    dots(3, b.as<double>(), b.as<double>(), r.as<double>(), r.as<double>(), r.as<double>(), z.as<double>(), nblk);
+    launch_finalize(s, FIN_START, MB, nm, partial.as<double>(), nblk, cs, tol2, P.cg_maxit);
+    launch_zero_inactive_start(s, n, MB, nm, x, cs.bb, st);
+    if (!read_any_active()) return;
+    const int* act = cs.active;
+    for (;;) {
+        for (int k = 0; k < check_every; ++k) {
+            launch_fill(s, Ap.as<double>(), 0.0, n * MB);
+            ebe(OP_A, p.as<double>(), nullptr, Ap.as<double>(), act);
+            launch_dashpot<double>(s, mesh->dev(), MB, nm, mat.as<double>(), P.nl, 2.0 / P.dt, p.as<double>(),
+                                   Ap.as<double>(), nullptr, act);
+            dots(1, p.as<double>(), Ap.as<double>(), nullptr, nullptr, nullptr, nullptr, nblk);
+            launch_finalize(s, FIN_ALPHA, MB, nm, partial.as<double>(), nblk, cs, tol2, P.cg_maxit);
+            launch_pcg_update(s, mesh->nn, MB, nm, x, r.as<double>(), z.as<double>(), p.as<double>(),
+                              Ap.as<double>(), pinv.as<double>(), cs.alpha, act);
+            dots(2, r.as<double>(), r.as<double>(), r.as<double>(), z.as<double>(), nullptr, nullptr, nblk);
+            launch_finalize(s, FIN_BETA, MB, nm, partial.as<double>(), nblk, cs, tol2, P.cg_maxit);
+            launch_axpby_p(s, n, MB, nm, z.as<double>(), p.as<double>(), cs.beta, act);
+        }
+        if (!read_any_active()) break;
+    }
+}
+
+void Ens::inner_solve()
+{
+    const long n = ndof;
+    int nblk;
+    const int* act = cs.active;
+    const int* iact = cs.inner_active;
+    const double tol2 = P.inner_tol * P.inner_tol;
+    launch_inner_start(s, mesh->nn, MB, nm, r.as<double>(), pinv32.as<float>(), ir.as<float>(), iz.as<float>(),
+                       ip.as<float>(), iw.as<float>(), act);
+    launch_dots32(s, 2, ir.as<float>(), ir.as<float>(), ir.as<float>(), iw.as<float>(), n, MB, partial.as<double>(),
+                  &nblk);
+    launch_finalize(s, FIN_IN_START, MB, nm, partial.as<double>(), nblk, cs, tol2, P.inner_maxit);
+    int done_iters = 0;
+    while (done_iters < P.inner_maxit) {
+        const int chunk = std::min(check_every, P.inner_maxit - done_iters);
+        for (int k = 0; k < chunk; ++k) {
+            launch_fill32(s, iAp.as<float>(), 0.0f, n * MB);
+            ebe32(ip.as<float>(), iAp.as<float>(), iact);
+            launch_dots32(s, 1, ip.as<float>(), iAp.as<float>(), nullptr, nullptr, n, MB, partial.as<double>(), &nblk);
+            launch_finalize(s, FIN_IN_ALPHA, MB, nm, partial.as<double>(), nblk, cs, tol2, P.inner_maxit);
+            launch_inner_update(s, mesh->nn, MB, nm, iz.as<float>(), ir.as<float>(), iw.as<float>(), ip.as<float>(),
+                                iAp.as<float>(), pinv32.as<float>(), cs.ialpha, iact);
+            launch_dots32(s, 2, ir.as<float>(), ir.as<float>(), ir.as<float>(), iw.as<float>(), n, MB,
+                          partial.as<double>(), &nblk);
+            launch_finalize(s, FIN_IN_BETA, MB, nm, partial.as<double>(), nblk, cs, tol2, P.inner_maxit);
+            launch_inner_p(s, n, MB, nm, iw.as<float>(), ip.as<float>(), cs.ibeta, iact);
+        }
+        done_iters += chunk;
+        if (!read_any_active()) break;
+    }
+    launch_inner_out(s, n, MB, nm, iz.as<float>(), z.as<double>(), act);
+}
+
+void Ens::solve_fcg()
+{
+    const long n = ndof;
+    int nblk;
+    double* x = du.as<double>();
+    const int* st = stepping.as<int>();
+    const int* act = cs.active;
+    const double tol2 = P.cg_tol * P.cg_tol;
+    launch_fill(s, Ap.as<double>(), 0.0, n * MB);
+    ebe(OP_A, x, nullptr, Ap.as<double>(), st);
+    launch_dashpot<double>(s, mesh->dev(), MB, nm, mat.as<double>(), P.nl, 2.0 / P.dt, x, Ap.as<double>(), nullptr, st);
+    launch_pcg_start(s, mesh->nn, MB, nm, b.as<double>(), Ap.as<double>(), pinv.as<double>(), r.as<double>(),
+                     z.as<double>(), p.as<double>(), st);
+    dots(2, b.as<double>(), b.as<double>(), r.as<double>(), r.as<double>(), nullptr, nullptr, nblk);
+    launch_finalize(s, FIN_FCG_START, MB, nm, partial.as<double>(), nblk, cs, tol2, P.cg_maxit);
+    launch_zero_inactive_start(s, n, MB, nm, x, cs.bb, st);
+    if (!read_any_active()) return;
+    inner_solve();
+    launch_copy_p(s, n, MB, nm, z.as<double>(), p.as<double>(), act);
+    dots(1, r.as<double>(), z.as<double>(), nullptr, nullptr, nullptr, nullptr, nblk);
+    launch_finalize(s, FIN_FCG_RZ, MB, nm, partial.as<double>(), nblk, cs, tol2, P.cg_maxit);
+    for (;;) {
+        launch_fill(s, Ap.as<double>(), 0.0, n * MB);
+        ebe(OP_A, p.as<double>(), nullptr, Ap.as<double>(), act);
+        launch_dashpot<double>(s, mesh->dev(), MB, nm, mat.as<double>(), P.nl, 2.0 / P.dt, p.as<double>(),
+                               Ap.as<double>(), nullptr, act);
+        dots(1, p.as<double>(), Ap.as<double>(), nullptr, nullptr, nullptr, nullptr, nblk);
+        launch_finalize(s, FIN_ALPHA, MB, nm, partial.as<double>(), nblk, cs, tol2, P.cg_maxit);
+        launch_xr_update(s, n, MB, nm, x, r.as<double>(), p.as<double>(), Ap.as<double>(), cs.alpha, act);
+        dots(1, r.as<double>(), r.as<double>(), nullptr, nullptr, nullptr, nullptr, nblk);
+        launch_finalize(s, FIN_FCG_RR, MB, nm, partial.as<double>(), nblk, cs, tol2, P.cg_maxit);
+        if (!read_any_active()) break;
+        inner_solve();
+        dots(2, z.as<double>(), Ap.as<double>(), z.as<double>(), r.as<double>(), nullptr, nullptr, nblk);
+        launch_finalize(s, FIN_FCG_BETA, MB, nm, partial.as<double>(), nblk, cs, tol2, P.cg_maxit);
+        launch_axpby_p(s, n, MB, nm, z.as<double>(), p.as<double>(), cs.beta, act);
+    }
+}
+
+void Ens::law_phase()
+{
+    const DevMesh dm = mesh->dev();
+    const size_t per_elem = (size_t)4 * P.ns * MB * 40;
+    if (!paged) {
+        hipEvent_t t0;
+        tstart(t0);
+        launch_law(s, dm, MB, nm, 0, mesh->ne, mat.as<double>(), P.nl, nonlinear.as<int>(), P.ns, dirs.as<double>(),
+                   w.as<double>(), du.as<double>(), theta.p, D64.as<double>(), D32.as<float>(), h.as<double>(),
+                   stepping.as<int>());
+        tstop(t0, &pc_law, (int64_t)mesh->ne * nm);
+        return;
+    }
+    // Algorithm 3 pipeline: chunk c computes while c-1 goes to the host and
+    // c+1 comes to the device, on two copy streams and a ring of slots
+    for (int cix = 0; cix < nchunks; ++cix) {
+        const int slot = cix % ring;
+        char* dslot = (char*)theta.p + (size_t)slot * chunk_elems * per_elem;
+        const size_t bytes = (size_t)chunk_ec[cix] * per_elem;
+        if (!prefetched[cix]) {
+            if (slot_chunk[slot] >= 0) NLTH_HIP(hipStreamWaitEvent(s_h2d, ev_d2h[slot], 0));
+            NLTH_HIP(hipMemcpyAsync(dslot, (char*)theta_host.p + chunk_off[cix], bytes, hipMemcpyHostToDevice, s_h2d));
+            NLTH_HIP(hipEventRecord(ev_h2d[slot], s_h2d));
+            h2d_bytes += bytes;
+        }
+        prefetched[cix] = false;
+        slot_chunk[slot] = cix;
+        NLTH_HIP(hipStreamWaitEvent(s, ev_h2d[slot], 0));
+        hipEvent_t t0;
+        tstart(t0);
+        launch_law(s, dm, MB, nm, chunk_e0[cix], chunk_ec[cix], mat.as<double>(), P.nl, nonlinear.as<int>(), P.ns,
+                   dirs.as<double>(), w.as<double>(), du.as<double>(), dslot, D64.as<double>(), D32.as<float>(),
+                   h.as<double>(), stepping.as<int>());
+        tstop(t0, &pc_law, (int64_t)chunk_ec[cix] * nm);
+        NLTH_HIP(hipEventRecord(ev_law[slot], s));
+        NLTH_HIP(hipStreamWaitEvent(s_d2h, ev_law[slot], 0));
+        NLTH_HIP(hipMemcpyAsync((char*)theta_host.p + chunk_off[cix], dslot, bytes, hipMemcpyDeviceToHost, s_d2h));
+        NLTH_HIP(hipEventRecord(ev_d2h[slot], s_d2h));
+        d2h_bytes += bytes;
+    }
+    // the next step's first chunks are prefetched now so their transfer
+    // overlaps the next solve (each waits for its slot's write-back)
+    prefetch_next();
+}
+
+void Ens::prefetch_next()
+{
+    const size_t per_elem = (size_t)4 * P.ns * MB * 40;
+    for (int cix = 0; cix < std::min(ring - 1, nchunks); ++cix) {
+        const int slot = cix % ring;
+        char* dslot = (char*)theta.p + (size_t)slot * chunk_elems * per_elem;
+        const size_t bytes = (size_t)chunk_ec[cix] * per_elem;
+        // the slot's previous chunk must be back on the host; chunk cix's own
+        // write-back precedes that one on the D2H stream
+        NLTH_HIP(hipStreamWaitEvent(s_h2d, ev_d2h[slot], 0));
+        NLTH_HIP(hipMemcpyAsync(dslot, (char*)theta_host.p + chunk_off[cix], bytes, hipMemcpyHostToDevice, s_h2d));
+        NLTH_HIP(hipEventRecord(ev_h2d[slot], s_h2d));
+        h2d_bytes += bytes;
+        prefetched[cix] = true;
+    }
+}
+
+void Ens::one_step()
+{
+    const DevMesh dm = mesh->dev();
+    NLTH_HIP(hipMemcpyAsync(member_step.p, h_member_step.data(), MB * 4, hipMemcpyHostToDevice, s));
+    NLTH_HIP(hipMemcpyAsync(stepping.p, h_stepping.data(), MB * 4, hipMemcpyHostToDevice, s));
+    const int ns_steps = std::max(1, P.n_steps);
+    launch_pick_vI(s, MB, nm, ns_steps, vI_all.as<double>(), member_step.as<int>(), vI_cur.as<double>());
+    hipEvent_t t0;
+    tstart(t0);
+    build_rhs();
+    build_diag();
+    tstop(t0, &pc_other, 0);
+    if (P.precision == NLTH_FP64) solve_pcg();
+    else solve_fcg();
+    tstart(t0);
+    ebe(OP_K, du.as<double>(), nullptr, q.as<double>(), stepping.as<int>());
+    launch_newmark(s, ndof, MB, nm, du.as<double>(), u.as<double>(), v.as<double>(), a.as<double>(), P.dt,
+                   stepping.as<int>());
+    tstop(t0, &pc_other, 0);
+    law_phase();
+    launch_receivers(s, mesh->nrecv, mesh->recv_d.as<int>(), MB, nm, v.as<double>(), hist.as<double>(),
+                     member_step.as<int>(), ns_steps, vmax.as<double>(), stepping.as<int>());
+    launch_record_iters(s, MB, nm, ns_steps, member_step.as<int>(), stepping.as<int>(), cs.iters, cs.inner_total,
+                        iters_dev.as<int>());
+    NLTH_HIP(hipMemcpyAsync(h_status.data(), cs.status, MB * 4, hipMemcpyDeviceToHost, s));
+    sync();
+}
+
+void Ens::step_all(int n_steps)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    for (int k = 0; k < n_steps && steps_done < P.n_steps; ++k) {
+        for (int m = 0; m < MB; ++m) {
+            h_member_step[m] = steps_done;
+            h_stepping[m] = (m < nm && h_status[m] == 0) ? 1 : 0;
+        }
+        one_step();
+        ++steps_done;
+    }
+    if (paged) {
+        NLTH_HIP(hipStreamSynchronize(s_h2d));
+        NLTH_HIP(hipStreamSynchronize(s_d2h));
+    }
+    ms_total += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+void Ens::read(nlth_result* res) const
+{
+    if (!res) return;
+    const int ns_steps = std::max(1, P.n_steps);
+    const int nr = std::max(1, mesh->nrecv);
+    if (res->vel && P.n_steps > 0 && mesh->nrecv > 0)
+        NLTH_HIP(hipMemcpy(res->vel, hist.p, (size_t)nm * ns_steps * nr * 3 * 8, hipMemcpyDeviceToHost));
+    if (res->iters && P.n_steps > 0)
+        NLTH_HIP(hipMemcpy(res->iters, iters_dev.p, (size_t)nm * ns_steps * 2 * 4, hipMemcpyDeviceToHost));
+    if (res->vmax && mesh->nrecv > 0)
+        NLTH_HIP(hipMemcpy(res->vmax, vmax.p, (size_t)nm * nr * 8, hipMemcpyDeviceToHost));
+    if (res->member_status)
+        for (int m = 0; m < nm; ++m) res->member_status[m] = h_status[m];
+}
+
+Ctx::~Ctx()
+{
+    {
+        std::lock_guard<std::mutex> g(smu);
+        stop = true;
+    }
+    scv.notify_all();
+    if (worker.joinable()) worker.join();
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+}
+
+}  // namespace nlth
+
+using namespace nlth;
+
+// ---------------------------------------------------------------------------
+// C-ABI
+// ---------------------------------------------------------------------------
+
+#define API_BEGIN(ctxp) \
+    Ctx* ctx_ = (ctxp);  \
+    try {
+#define API_END                                 \
+    }                                           \
+    catch (const Error& e) {                    \
+        set_error(ctx_, e);                     \
+        return e.code;                          \
+    }                                           \
+    catch (const std::bad_alloc&) {             \
+        set_error(ctx_, Error{NLTH_ENOMEM_HOST, "host allocation failed"}); \
+        return NLTH_ENOMEM_HOST;                \
+    }                                           \
+    return NLTH_OK;
+
+struct nlth_ctx : Ctx {};
+struct nlth_mesh : Mesh {};
+struct nlth_ens : Ens {};
+
+extern "C" {
+
+int nlth_version(void) { return NLTH_VERSION; }
+
+const char* nlth_last_error(const nlth_ctx* ctx)
+{
+    if (ctx) return ctx->last_error.c_str();
+    std::lock_guard<std::mutex> g(g_err_mu);
+    static thread_local std::string copy;
+    copy = g_err;
+    return copy.c_str();
+}
+
+int nlth_ctx_create(int device, const nlth_ctx_opts* opts, nlth_ctx** out)
+{
+    API_BEGIN(nullptr)
+    if (!out) throw Error{NLTH_EINVAL, "out is NULL"};
+    *out = nullptr;
+    std::unique_ptr<nlth_ctx> c(new nlth_ctx());
+    c->device = device;
+    c->host_only = device == NLTH_DEVICE_NONE;
+    if (opts) {
+        c->log_level = opts->log_level;
+        if (opts->max_batch > 0) c->max_batch = opts->max_batch;
+    }
+    c->budget.host_limit = (opts && opts->host_budget > 0) ? opts->host_budget : (int64_t)64 << 30;
+    if (!c->host_only) {
+        int n = 0;
+        if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n)
+            throw Error{NLTH_EDEVICE, "no such HIP device"};
+        NLTH_HIP(hipSetDevice(device));
+        size_t fr = 0, tot = 0;
+        NLTH_HIP(hipMemGetInfo(&fr, &tot));
+        c->budget.limit = (opts && opts->hbm_budget > 0) ? opts->hbm_budget : (int64_t)(0.9 * fr);
+        if (opts && opts->stream) {
+            c->stream = (hipStream_t)opts->stream;
+        } else {
+            NLTH_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+            c->own_stream = true;
+        }
+    }
+    *out = c.release();
+    API_END
+}
+
+int nlth_ctx_destroy(nlth_ctx* ctx)
+{
+    if (!ctx) return NLTH_OK;
+    {
+        std::lock_guard<std::mutex> g(ctx->smu);
+        for (auto& kv : ctx->requests)
+            if (kv.second->state.load() < 2) {
+                set_error(ctx, Error{NLTH_EBUSY, "context has unfinished requests"});
+                return NLTH_EBUSY;
+            }
+    }
+    if (ctx->live_meshes.load() > 0) {
+        set_error(ctx, Error{NLTH_EBUSY, "context still has meshes"});
+        return NLTH_EBUSY;
+    }
+    delete ctx;
+    return NLTH_OK;
+}
+
+int nlth_mesh_create(nlth_ctx* ctx, const nlth_mesh_desc* d, nlth_mesh** out)
+{
+    API_BEGIN(ctx)
+    if (!ctx || !out) throw Error{NLTH_EINVAL, "ctx/out is NULL"};
+    *out = nullptr;
+    std::lock_guard<std::mutex> g(ctx->mu);
+    if (!ctx->host_only) NLTH_HIP(hipSetDevice(ctx->device));
+    std::unique_ptr<nlth_mesh> m(new nlth_mesh());
+    build_mesh(ctx, d, *m);
+    ctx->live_meshes++;
+    *out = m.release();
+    API_END
+}
+
+int nlth_mesh_destroy(nlth_mesh* mesh)
+{
+    if (!mesh) return NLTH_OK;
+    Ctx* c = mesh->ctx;
+    if (mesh->refs.load() > 0) {
+        set_error(c, Error{NLTH_EBUSY, "mesh is referenced by a pending request"});
+        return NLTH_EBUSY;
+    }
+    {
+        std::lock_guard<std::mutex> g(c->mu);
+        delete mesh;
+    }
+    c->live_meshes--;
+    return NLTH_OK;
+}
+
+int nlth_mesh_query(const nlth_mesh* mesh, nlth_mesh_info* info, int32_t* elem_order, int32_t* color_offsets)
+{
+    API_BEGIN(mesh ? mesh->ctx : nullptr)
+    if (!mesh) throw Error{NLTH_EINVAL, "mesh is NULL"};
+    if (info) {
+        info->n_nodes = mesh->nn;
+        info->n_tets = mesh->ne;
+        info->n_colors = mesh->ncolor;
+        info->n_bnodes = mesh->nbn;
+        info->volume = mesh->volume;
+    }
+    if (elem_order) std::copy(mesh->order.begin(), mesh->order.end(), elem_order);
+    if (color_offsets) std::copy(mesh->color_off.begin(), mesh->color_off.end(), color_offsets);
+    API_END
+}
+
+int nlth_ens_create(nlth_ctx* ctx, const nlth_mesh* mesh, const nlth_problem* prob, nlth_ens** out)
+{
+    API_BEGIN(ctx)
+    if (!ctx || !mesh || !out) throw Error{NLTH_EINVAL, "ctx/mesh/out is NULL"};
+    if (mesh->ctx != ctx) throw Error{NLTH_EINVAL, "mesh belongs to another context"};
+    *out = nullptr;
+    Problem P;
+    copy_problem(prob, P);
+    if (P.nl <= mesh->max_layer) throw Error{NLTH_EINVAL, "problem: mesh uses a layer id >= n_layers"};
+    if (ctx->host_only) throw Error{NLTH_EDEVICE, "host-only context cannot run solves"};
+    std::lock_guard<std::mutex> g(ctx->mu);
+    NLTH_HIP(hipSetDevice(ctx->device));
+    std::unique_ptr<nlth_ens> e(new nlth_ens());
+    e->create(ctx, mesh, P);
+    *out = e.release();
+    API_END
+}
+
+int nlth_ens_step(nlth_ens* ens, int32_t n_steps)
+{
+    API_BEGIN(ens ? ens->ctx : nullptr)
+    if (!ens || n_steps < 0) throw Error{NLTH_EINVAL, "ens is NULL or n_steps < 0"};
+    std::lock_guard<std::mutex> g(ens->ctx->mu);
+    NLTH_HIP(hipSetDevice(ens->ctx->device));
+    ens->step_all(n_steps);
+    for (int m = 0; m < ens->nm; ++m)
+        if (ens->h_status[m] != 0) {
+            char buf[128];
+            snprintf(buf, sizeof buf, "member %d: CG did not converge within cg_maxit", m);
+            throw Error{NLTH_ENOCONV, buf};
+        }
+    API_END
+}
+
+int nlth_ens_read(nlth_ens* ens, nlth_result* res)
+{
+    API_BEGIN(ens ? ens->ctx : nullptr)
+    if (!ens) throw Error{NLTH_EINVAL, "ens is NULL"};
+    std::lock_guard<std::mutex> g(ens->ctx->mu);
+    NLTH_HIP(hipSetDevice(ens->ctx->device));
+    ens->read(res);
+    API_END
+}
+
+int nlth_ens_destroy(nlth_ens* ens)
+{
+    if (!ens) return NLTH_OK;
+    Ctx* c = ens->ctx;
+    std::lock_guard<std::mutex> g(c->mu);
+    (void)hipSetDevice(c->device);
+    delete ens;
+    return NLTH_OK;
+}
+
+int nlth_ens_set_profile(nlth_ens* ens, int32_t profile)
+{
+    if (!ens) return NLTH_EINVAL;
+    ens->profile = profile != 0;
+    return NLTH_OK;
+}
+
+int nlth_ens_reset_stats(nlth_ens* ens)
+{
+    if (!ens) return NLTH_EINVAL;
+    ens->pc_ebe64 = ens->pc_ebe32 = ens->pc_vec = ens->pc_law = ens->pc_other = ProfCat{};
+    ens->ms_total = ens->ms_copy = 0;
+    ens->h2d_bytes = ens->d2h_bytes = 0;
+    return NLTH_OK;
+}
+
+int nlth_ens_stats(const nlth_ens* ens, nlth_stats* st)
+{
+    API_BEGIN(ens ? ens->ctx : nullptr)
+    if (!ens || !st) throw Error{NLTH_EINVAL, "ens/st is NULL"};
+    memset(st, 0, sizeof *st);
+    st->steps_done = ens->steps_done;
+    st->paged = ens->paged;
+    const int ns_steps = std::max(1, ens->P.n_steps);
+    std::vector<int> it((size_t)ens->nm * ns_steps * 2);
+    NLTH_HIP(hipMemcpy(it.data(), ens->iters_dev.p, it.size() * 4, hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < it.size(); i += 2) {
+        st->outer_iters += it[i];
+        st->inner_iters += it[i + 1];
+    }
+    st->ms_total = ens->ms_total;
+    st->ms_ebe64 = ens->pc_ebe64.ms;
+    st->ms_ebe32 = ens->pc_ebe32.ms;
+    st->ms_vec = ens->pc_vec.ms;
+    st->ms_law = ens->pc_law.ms;
+    st->ms_other = ens->pc_other.ms;
+    st->n_ebe64 = ens->pc_ebe64.n;
+    st->n_ebe32 = ens->pc_ebe32.n;
+    st->n_law = ens->pc_law.n;
+    st->elems_ebe64 = ens->pc_ebe64.elems;
+    st->elems_ebe32 = ens->pc_ebe32.elems;
+    st->h2d_bytes = ens->h2d_bytes;
+    st->d2h_bytes = ens->d2h_bytes;
+    st->ms_copy = ens->ms_copy;
+    st->n_members = ens->nm;
+    st->members_padded = ens->MB;
+    st->n_colors = ens->mesh->ncolor;
+    st->device_bytes = ens->dev_bytes;
+    st->host_bytes = ens->host_bytes;
+    API_END
+}
+
+int nlth_solve(nlth_ctx* ctx, const nlth_mesh* mesh, const nlth_problem* prob, nlth_result* res)
+{
+    nlth_ens* e = nullptr;
+    int rc = nlth_ens_create(ctx, mesh, prob, &e);
+    if (rc != NLTH_OK) return rc;
+    int rs = nlth_ens_step(e, prob->n_steps);
+    std::string msg = rs != NLTH_OK ? ctx->last_error : std::string();
+    int rr = nlth_ens_read(e, res);
+    nlth_ens_destroy(e);
+    if (rs != NLTH_OK) {
+        set_error(ctx, Error{rs, msg});
+        return rs;
+    }
+    return rr;
+}
+
+int nlth_apply_operator(nlth_ctx* ctx, const nlth_mesh* mesh, const nlth_problem* prob, int32_t which,
+                        int32_t precision, const double* D_ip, const double* hh, const double* x, double* y)
+{
+    API_BEGIN(ctx)
+    if (!ctx || !mesh || !prob || !D_ip || !x || !y) throw Error{NLTH_EINVAL, "NULL argument"};
+    if (ctx->host_only) throw Error{NLTH_EDEVICE, "host-only context"};
+    if (which < NLTH_OP_A || which > NLTH_OP_M) throw Error{NLTH_EINVAL, "which must be NLTH_OP_A/K/M"};
+    if (precision == NLTH_MIXED && which != NLTH_OP_A) throw Error{NLTH_EINVAL, "FP32 apply supports NLTH_OP_A"};
+    std::lock_guard<std::mutex> g(ctx->mu);
+    NLTH_HIP(hipSetDevice(ctx->device));
+    Problem P;
+    nlth_problem p1 = *prob;
+    p1.n_members = 1;
+    p1.n_steps = 0;
+    copy_problem(&p1, P);
+    std::unique_ptr<nlth_ens> e(new nlth_ens());
+    e->create(ctx, mesh, P);
+    const int ne = mesh->ne, nn = mesh->nn;
+    // D and h into the sorted, member-innermost layout (MB = 1)
+    std::vector<double> Dd((size_t)ne * 84), hd(ne, 0.0);
+    for (int pos = 0; pos < ne; ++pos) {
+        int e0 = mesh->order[pos];
+        for (int j = 0; j < 4; ++j)
+            for (int k = 0; k < 21; ++k) Dd[((size_t)(j * 21 + k)) * ne + pos] = D_ip[(size_t)e0 * 84 + j * 21 + k];
+        if (hh) hd[pos] = hh[e0];
+    }
+    std::vector<float> Df(Dd.begin(), Dd.end());
+    NLTH_HIP(hipMemcpy(e->D64.p, Dd.data(), Dd.size() * 8, hipMemcpyHostToDevice));
+    NLTH_HIP(hipMemcpy(e->D32.p, Df.data(), Df.size() * 4, hipMemcpyHostToDevice));
+    NLTH_HIP(hipMemcpy(e->h.p, hd.data(), hd.size() * 8, hipMemcpyHostToDevice));
+    const long n = 3L * nn;
+    int one = 1;
+    NLTH_HIP(hipMemcpy(e->stepping.p, &one, 4, hipMemcpyHostToDevice));
+    hipStream_t s = e->s;
+    if (precision == NLTH_FP64) {
+        NLTH_HIP(hipMemcpy(e->p.p, x, n * 8, hipMemcpyHostToDevice));
+        launch_fill(s, e->Ap.as<double>(), 0.0, n);
+        e->ebe((OpMode)which, e->p.as<double>(), nullptr, e->Ap.as<double>(), e->stepping.as<int>());
+        if (which == NLTH_OP_A)
+            launch_dashpot<double>(s, mesh->dev(), 1, 1, e->mat.as<double>(), P.nl, 2.0 / P.dt, e->p.as<double>(),
+                                   e->Ap.as<double>(), nullptr, e->stepping.as<int>());
+        NLTH_HIP(hipStreamSynchronize(s));
+        NLTH_HIP(hipMemcpy(y, e->Ap.p, n * 8, hipMemcpyDeviceToHost));
+    } else {
+        std::vector<float> xf(x, x + n), yf(n);
+        DevBuf xd, yd;
+        xd.alloc(&ctx->budget, n * 4);
+        yd.alloc(&ctx->budget, n * 4);
+        NLTH_HIP(hipMemcpy(xd.p, xf.data(), n * 4, hipMemcpyHostToDevice));
+        launch_fill32(s, yd.as<float>(), 0.0f, n);
+        e->ebe32(xd.as<float>(), yd.as<float>(), e->stepping.as<int>());
+        NLTH_HIP(hipStreamSynchronize(s));
+        NLTH_HIP(hipMemcpy(yf.data(), yd.p, n * 4, hipMemcpyDeviceToHost));
+        for (long i = 0; i < n; ++i) y[i] = yf[i];
+    }
+    API_END
+}
+
+}  // extern "C"

@@ -1,0 +1,1183 @@
+// HIP kernels (gfx950) for the nonlinear time-history ensemble solver.
+//
+// Method: Ichimura et al., arXiv 2604.02755.  Section 2.1, Eq. 1 (Newmark
+// incremental step), Eq. 2 (K_e from D at the integration points), the
+// multi-spring Ramberg-Osgood/Masing law; Section 2.2, Algorithm 4 (EBE
+// operator inside CG, law update per step).
+//
+// All per-member data is member-innermost (index * MB + m): one lane handles
+// one (element, member) or (node, member) pair; when MB >= 64 a wavefront
+// covers 64 members of one element, so element data is wave-uniform and
+// member data is read in contiguous 256/512-byte rows.
+//
+// Element-by-element scatter is atomic-free: a launch covers one colour of
+// the element colouring (no two elements of a colour share a node), and the
+// host issues the colours in sequence on one stream.
+#include <math.h>
+
+#include "nlth_impl.hpp"
+
+namespace nlth {
+
+// ---------------------------------------------------------------------------
+// constants
+// ---------------------------------------------------------------------------
+
+// 4-point degree-2 rule: barycentric (a, b, b, b) and permutations, weight V/4.
+#define QA_ 0.5854101966249685
+#define QB_ 0.1381966011250105
+
+// Consistent mass of the 10-node tet divided by its volume: the classical
+// pattern /420 (corner diagonal 6, corner-corner 1, corner and an edge through
+// it -4, corner and the opposite-side edge -6, edge diagonal 32, edges sharing
+// a vertex 16, opposite edges 8).
+__host__ __device__ constexpr double mass_ref(int a, int b)
+{
+    // edges as vertex pairs
+    constexpr int E[6][2] = {{0, 1}, {1, 2}, {2, 0}, {0, 3}, {1, 3}, {2, 3}};
+    if (a < 4 && b < 4) return (a == b ? 6.0 : 1.0) / 420.0;
+    if (a < 4 || b < 4) {
+        int c = a < 4 ? a : b;
+        int e = (a < 4 ? b : a) - 4;
+        return (E[e][0] == c || E[e][1] == c ? -4.0 : -6.0) / 420.0;
+    }
+    if (a == b) return 32.0 / 420.0;
+    int ea = a - 4, eb = b - 4;
+    bool share = E[ea][0] == E[eb][0] || E[ea][0] == E[eb][1] || E[ea][1] == E[eb][0] ||
+                 E[ea][1] == E[eb][1];
+    return (share ? 16.0 : 8.0) / 420.0;
+}
+
+// index of (r, c) in the row-by-row upper triangle of a symmetric 6x6
+__host__ __device__ constexpr int sym6(int r, int c)
+{
+    return r <= c ? r * 6 - r * (r - 1) / 2 + (c - r) : c * 6 - c * (c - 1) / 2 + (r - c);
+}
+
+template <typename T> __device__ __forceinline__ const T* geo_of(const DevMesh& M);
+template <> __device__ __forceinline__ const double* geo_of<double>(const DevMesh& M) { return M.geo64; }
+template <> __device__ __forceinline__ const float* geo_of<float>(const DevMesh& M) { return M.geo32; }
+
+__device__ __forceinline__ double matv(const double* mat, int l, int f, int MB, int m)
+{
+    return mat[((long)l * MAT_N + f) * MB + m];
+}
+
+// Shape-function gradients of the quadratic tet at integration point j.
+template <typename T>
+__device__ __forceinline__ void shape_grads(int j, const T gL[4][3], T G[10][3])
+{
+    T L[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) L[i] = (i == j) ? (T)QA_ : (T)QB_;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) G[i][a] = ((T)4 * L[i] - (T)1) * gL[i][a];
+    constexpr int E[6][2] = {{0, 1}, {1, 2}, {2, 0}, {0, 3}, {1, 3}, {2, 3}};
+#pragma unroll
+    for (int e = 0; e < 6; ++e)
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            G[4 + e][a] = (T)4 * (L[E[e][0]] * gL[E[e][1]][a] + L[E[e][1]] * gL[E[e][0]][a]);
+}
+
+// engineering strain (Voigt xx, yy, zz, xy, yz, zx) of nodal field u at one point
+template <typename T>
+__device__ __forceinline__ void strain(const T G[10][3], const T u[10][3], T eps[6])
+{
+#pragma unroll
+    for (int k = 0; k < 6; ++k) eps[k] = 0;
+#pragma unroll
+    for (int n = 0; n < 10; ++n) {
+        eps[0] += G[n][0] * u[n][0];
+        eps[1] += G[n][1] * u[n][1];
+        eps[2] += G[n][2] * u[n][2];
+        eps[3] += G[n][1] * u[n][0] + G[n][0] * u[n][1];
+        eps[4] += G[n][2] * u[n][1] + G[n][1] * u[n][2];
+        eps[5] += G[n][0] * u[n][2] + G[n][2] * u[n][0];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// simple vector kernels
+// ---------------------------------------------------------------------------
+
+__global__ void k_fill(double* p, double v, long n)
+{
+    long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+__global__ void k_fill32(float* p, float v, long n)
+{
+    long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+__global__ void k_neg_copy(const double* a, double* b, long n)
+{
+    long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i < n) b[i] = -a[i];
+}
+__global__ void k_cast32(const double* a, float* b, long n)
+{
+    long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (float)a[i];
+}
+
+static inline unsigned nblocks(long n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
+
+void launch_fill(hipStream_t s, double* p, double v, long n)
+{
+    if (n > 0) hipLaunchKernelGGL(k_fill, dim3(nblocks(n)), dim3(256), 0, s, p, v, n);
+}
+void launch_fill32(hipStream_t s, float* p, float v, long n)
+{
+    if (n > 0) hipLaunchKernelGGL(k_fill32, dim3(nblocks(n)), dim3(256), 0, s, p, v, n);
+}
+void launch_neg_copy(hipStream_t s, const double* a, double* b, long n)
+{
+    if (n > 0) hipLaunchKernelGGL(k_neg_copy, dim3(nblocks(n)), dim3(256), 0, s, a, b, n);
+}
+void launch_cast32(hipStream_t s, const double* a, float* b, long n)
+{
+    if (n > 0) hipLaunchKernelGGL(k_cast32, dim3(nblocks(n)), dim3(256), 0, s, a, b, n);
+}
+
+// ---------------------------------------------------------------------------
+// element-by-element operator (Eq. 1 left-hand side, Eq. 2 stiffness)
+// ---------------------------------------------------------------------------
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void k_ebe(DevMesh M, int MB, int nm, int e0, int e1,
+                                            const T* __restrict__ D, const double* __restrict__ h,
+                                            const double* __restrict__ mat, StepConst sc,
+                                            const T* __restrict__ x1, const T* __restrict__ x2,
+                                            T* __restrict__ y, const int* __restrict__ active)
+{
+    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const int m = (int)(t % MB);
+    const long e = e0 + t / MB;
+    if (e >= e1 || m >= nm) return;
+    if (active && !active[m]) return;
+    const long ne = M.ne;
+    const T* geo = geo_of<T>(M);
+    T gL[4][3];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) gL[k / 3][k % 3] = geo[k * ne + e];
+    const T vol = geo[12 * ne + e];
+    int nodes[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) nodes[k] = M.conn[k * ne + e];
+    const int l = M.layer[e];
+    const double rho = matv(mat, l, MAT_RHO, MB, m);
+    double he = 0.0;
+    if (sc.damping_mode == 0 && h) he = h[e * MB + m];
+    else if (sc.damping_mode == 1) he = sc.h0;
+    const double dt = sc.dt;
+    T sm, sk, cv = 0;
+    if (MODE == OP_A) {
+        sm = (T)(rho * (double)vol * (4.0 / (dt * dt) + 2.0 * sc.ahat * he / dt));
+        sk = (T)(1.0 + 2.0 * sc.bhat * he / dt);
+    } else if (MODE == OP_K) {
+        sm = 0; sk = 1;
+    } else if (MODE == OP_M) {
+        sm = (T)(rho * (double)vol); sk = 0;
+    } else {  // RHS: M (a + (4/dt + alpha) v) + beta K v
+        sm = (T)(rho * (double)vol);
+        sk = (T)(sc.bhat * he);
+        cv = (T)(4.0 / dt + sc.ahat * he);
+    }
+    T xk[10][3], xm[10][3];
+#pragma unroll
+    for (int n = 0; n < 10; ++n)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const long idx = ((long)nodes[n] * 3 + c) * MB + m;
+            T v1 = x1[idx];
+            xk[n][c] = v1;
+            if (MODE == OP_RHS) xm[n][c] = x2[idx] + cv * v1;
+            else xm[n][c] = v1;
+        }
+    T f[10][3];
+#pragma unroll
+    for (int n = 0; n < 10; ++n)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) f[n][c] = 0;
+
+    if (MODE != OP_M && sk != (T)0) {
+        const T w = sk * vol * (T)0.25;
+        const T* Dp = D + e * MB + m;
+        const long ds = ne * MB;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            T G[10][3], eps[6], d[21], s[6];
+            shape_grads<T>(j, gL, G);
+            strain<T>(G, xk, eps);
+#pragma unroll
+            for (int k = 0; k < 21; ++k) d[k] = Dp[(long)(j * 21 + k) * ds];
+#pragma unroll
+            for (int r = 0; r < 6; ++r) {
+                T a = 0;
+#pragma unroll
+                for (int c = 0; c < 6; ++c) a += d[sym6(r, c)] * eps[c];
+                s[r] = a * w;
+            }
+#pragma unroll
+            for (int n = 0; n < 10; ++n) {
+                f[n][0] += G[n][0] * s[0] + G[n][1] * s[3] + G[n][2] * s[5];
+                f[n][1] += G[n][1] * s[1] + G[n][0] * s[3] + G[n][2] * s[4];
+                f[n][2] += G[n][2] * s[2] + G[n][1] * s[4] + G[n][0] * s[5];
+            }
+        }
+    }
+    if (MODE != OP_K) {
+#pragma unroll
+        for (int a = 0; a < 10; ++a)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                T acc = 0;
+#pragma unroll
+                for (int b = 0; b < 10; ++b) acc += (T)mass_ref(a, b) * xm[b][c];
+                f[a][c] += sm * acc;
+            }
+    }
+#pragma unroll
+    for (int n = 0; n < 10; ++n)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const long idx = ((long)nodes[n] * 3 + c) * MB + m;
+            y[idx] += f[n][c];
+        }
+}
+
+template <typename T>
+void launch_ebe(hipStream_t s, OpMode mode, const DevMesh& M, int MB, int nm, int e0, int e1, const T* D,
+                const double* h, const double* mat, int, StepConst sc, const T* x1, const T* x2, T* y,
+                const int* active)
+{
+    long n = (long)(e1 - e0) * MB;
+    if (n <= 0) return;
+    dim3 g(nblocks(n)), b(256);
+    switch (mode) {
+    case OP_A: hipLaunchKernelGGL((k_ebe<T, OP_A>), g, b, 0, s, M, MB, nm, e0, e1, D, h, mat, sc, x1, x2, y, active); break;
+    case OP_K: hipLaunchKernelGGL((k_ebe<T, OP_K>), g, b, 0, s, M, MB, nm, e0, e1, D, h, mat, sc, x1, x2, y, active); break;
+    case OP_M: hipLaunchKernelGGL((k_ebe<T, OP_M>), g, b, 0, s, M, MB, nm, e0, e1, D, h, mat, sc, x1, x2, y, active); break;
+    case OP_RHS: hipLaunchKernelGGL((k_ebe<T, OP_RHS>), g, b, 0, s, M, MB, nm, e0, e1, D, h, mat, sc, x1, x2, y, active); break;
+    }
+}
+template void launch_ebe<double>(hipStream_t, OpMode, const DevMesh&, int, int, int, int, const double*,
+                                 const double*, const double*, int, StepConst, const double*,
+                                 const double*, double*, const int*);
+template void launch_ebe<float>(hipStream_t, OpMode, const DevMesh&, int, int, int, int, const float*,
+                                const double*, const double*, int, StepConst, const float*,
+                                const float*, float*, const int*);
+
+// ---------------------------------------------------------------------------
+// absorbing boundary: node-centric gather over boundary faces (deterministic)
+// dashpot on a face: rho (Vp n n^T + Vs (I - n n^T)) times int N_a N_b dA
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ void k_dashpot(DevMesh M, int MB, int nm, const double* __restrict__ mat, T coef,
+                          const T* __restrict__ x, T* __restrict__ y, const double* __restrict__ vI,
+                          const int* __restrict__ active)
+{
+    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const int m = (int)(t % MB);
+    const long i = t / MB;
+    if (i >= M.nbn || m >= nm) return;
+    if (active && !active[m]) return;
+    const int node = M.bn_node[i];
+    double acc[3] = {0, 0, 0};
+    for (int q = M.bn_ptr[i]; q < M.bn_ptr[i + 1]; ++q) {
+        const int f = M.bn_face[q], a = M.bn_loc[q];
+        const int l = M.f_layer[f];
+        const double rho = matv(mat, l, MAT_RHO, MB, m);
+        const double vs = matv(mat, l, MAT_VS, MB, m);
+        const double vp = matv(mat, l, MAT_VP, MB, m);
+        const double* nv = M.f_n + 3 * (long)f;
+        double X[3] = {0, 0, 0}, rs = 0;
+        for (int b = 0; b < 6; ++b) {
+            const double Mab = M.f_M[36 * (long)f + 6 * a + b];
+            const long nb = M.f_node[6 * (long)f + b];
+            rs += Mab;
+            for (int c = 0; c < 3; ++c) X[c] += Mab * (double)x[(nb * 3 + c) * MB + m];
+        }
+        double nx = nv[0] * X[0] + nv[1] * X[1] + nv[2] * X[2];
+        for (int c = 0; c < 3; ++c) acc[c] += (double)coef * rho * (vs * X[c] + (vp - vs) * nx * nv[c]);
+        if (vI && M.f_kind[f] == 0) {  // incident wave: 2 C_base v_I
+            double V[3] = {vI[0 * MB + m], vI[1 * MB + m], vI[2 * MB + m]};
+            double nV = nv[0] * V[0] + nv[1] * V[1] + nv[2] * V[2];
+            for (int c = 0; c < 3; ++c) acc[c] += 2.0 * rs * rho * (vs * V[c] + (vp - vs) * nV * nv[c]);
+        }
+    }
+    for (int c = 0; c < 3; ++c) y[((long)node * 3 + c) * MB + m] += (T)acc[c];
+}
+
+template <typename T>
+void launch_dashpot(hipStream_t s, const DevMesh& M, int MB, int nm, const double* mat, int, T coef, const T* x,
+                    T* y, const double* vI, const int* active)
+{
+    long n = (long)M.nbn * MB;
+    if (n > 0) hipLaunchKernelGGL((k_dashpot<T>), dim3(nblocks(n)), dim3(256), 0, s, M, MB, nm, mat, coef, x, y, vI, active);
+}
+template void launch_dashpot<double>(hipStream_t, const DevMesh&, int, int, const double*, int, double,
+                                     const double*, double*, const double*, const int*);
+template void launch_dashpot<float>(hipStream_t, const DevMesh&, int, int, const double*, int, float,
+                                    const float*, float*, const double*, const int*);
+
+// ---------------------------------------------------------------------------
+// 3x3 block-Jacobi preconditioner (Section 2.2): diagonal blocks of A
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_diag(DevMesh M, int MB, int nm, int e0, int e1,
+                                             const double* __restrict__ D, const double* __restrict__ h,
+                                             const double* __restrict__ mat, StepConst sc,
+                                             double* __restrict__ diag)
+{
+    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const int m = (int)(t % MB);
+    const long e = e0 + t / MB;
+    if (e >= e1 || m >= nm) return;
+    const long ne = M.ne;
+    double gL[4][3];
+    for (int k = 0; k < 12; ++k) gL[k / 3][k % 3] = M.geo64[k * ne + e];
+    const double vol = M.geo64[12 * ne + e];
+    const int l = M.layer[e];
+    const double rho = matv(mat, l, MAT_RHO, MB, m);
+    double he = 0.0;
+    if (sc.damping_mode == 0 && h) he = h[e * MB + m];
+    else if (sc.damping_mode == 1) he = sc.h0;
+    const double dt = sc.dt;
+    const double sm = rho * vol * (4.0 / (dt * dt) + 2.0 * sc.ahat * he / dt);
+    const double w = (1.0 + 2.0 * sc.bhat * he / dt) * vol * 0.25;
+    double blk[10][6];
+    for (int n = 0; n < 10; ++n) {
+        double md = sm * mass_ref(n, n);
+        blk[n][0] = md; blk[n][1] = 0; blk[n][2] = 0; blk[n][3] = md; blk[n][4] = 0; blk[n][5] = md;
+    }
+    const double* Dp = D + e * MB + m;
+    const long ds = ne * MB;
+    for (int j = 0; j < 4; ++j) {
+        double G[10][3], d[21];
+        shape_grads<double>(j, gL, G);
+        for (int k = 0; k < 21; ++k) d[k] = Dp[(long)(j * 21 + k) * ds];
+        for (int n = 0; n < 10; ++n) {
+            const double gx = G[n][0], gy = G[n][1], gz = G[n][2];
+            // columns of B for this node (6 strains x 3 displacement components)
+            const double b[3][6] = {{gx, 0, 0, gy, 0, gz}, {0, gy, 0, gx, gz, 0}, {0, 0, gz, 0, gy, gx}};
+            double Db[3][6];
+            for (int c = 0; c < 3; ++c)
+                for (int r = 0; r < 6; ++r) {
+                    double a = 0;
+                    for (int k = 0; k < 6; ++k) a += d[sym6(r, k)] * b[c][k];
+                    Db[c][r] = a;
+                }
+            double K[3][3];
+            for (int c = 0; c < 3; ++c)
+                for (int dd = 0; dd < 3; ++dd) {
+                    double a = 0;
+                    for (int r = 0; r < 6; ++r) a += b[c][r] * Db[dd][r];
+                    K[c][dd] = a;
+                }
+            blk[n][0] += w * K[0][0]; blk[n][1] += w * K[0][1]; blk[n][2] += w * K[0][2];
+            blk[n][3] += w * K[1][1]; blk[n][4] += w * K[1][2]; blk[n][5] += w * K[2][2];
+        }
+    }
+    for (int n = 0; n < 10; ++n) {
+        const long node = M.conn[n * ne + e];
+        for (int k = 0; k < 6; ++k) diag[(node * 6 + k) * MB + m] += blk[n][k];
+    }
+}
+
+void launch_diag(hipStream_t s, const DevMesh& M, int MB, int nm, int e0, int e1, const double* D, const double* h,
+                 const double* mat, int, StepConst sc, double* diag)
+{
+    long n = (long)(e1 - e0) * MB;
+    if (n > 0) hipLaunchKernelGGL(k_diag, dim3(nblocks(n)), dim3(256), 0, s, M, MB, nm, e0, e1, D, h, mat, sc, diag);
+}
+
+__global__ void k_diag_dashpot(DevMesh M, int MB, int nm, const double* __restrict__ mat, double coef,
+                               double* __restrict__ diag)
+{
+    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const int m = (int)(t % MB);
+    const long i = t / MB;
+    if (i >= M.nbn || m >= nm) return;
+    const long node = M.bn_node[i];
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int q = M.bn_ptr[i]; q < M.bn_ptr[i + 1]; ++q) {
+        const int f = M.bn_face[q], a = M.bn_loc[q];
+        const int l = M.f_layer[f];
+        const double rho = matv(mat, l, MAT_RHO, MB, m);
+        const double vs = matv(mat, l, MAT_VS, MB, m);
+        const double vp = matv(mat, l, MAT_VP, MB, m);
+        const double* n = M.f_n + 3 * (long)f;
+        const double Maa = M.f_M[36 * (long)f + 7 * a] * coef * rho;
+        acc[0] += Maa * (vs + (vp - vs) * n[0] * n[0]);
+        acc[1] += Maa * ((vp - vs) * n[0] * n[1]);
+        acc[2] += Maa * ((vp - vs) * n[0] * n[2]);
+        acc[3] += Maa * (vs + (vp - vs) * n[1] * n[1]);
+        acc[4] += Maa * ((vp - vs) * n[1] * n[2]);
+        acc[5] += Maa * (vs + (vp - vs) * n[2] * n[2]);
+    }
+    for (int k = 0; k < 6; ++k) diag[(node * 6 + k) * MB + m] += acc[k];
+}
+
+void launch_diag_dashpot(hipStream_t s, const DevMesh& M, int MB, int nm, const double* mat, int, double coef,
+                         double* diag)
+{
+    long n = (long)M.nbn * MB;
+    if (n > 0) hipLaunchKernelGGL(k_diag_dashpot, dim3(nblocks(n)), dim3(256), 0, s, M, MB, nm, mat, coef, diag);
+}
+
+__global__ void k_invert_diag(int nn, int MB, int nm, const double* __restrict__ diag,
+                              double* __restrict__ pinv, float* __restrict__ pinv32)
+{
+    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const int m = (int)(t % MB);
+    const long i = t / MB;
+    if (i >= nn || m >= nm) return;
+    double a[6];
+    for (int k = 0; k < 6; ++k) a[k] = diag[(i * 6 + k) * MB + m];
+    // a = [a0 a1 a2; a1 a3 a4; a2 a4 a5]
+    const double c00 = a[3] * a[5] - a[4] * a[4];
+    const double c01 = a[2] * a[4] - a[1] * a[5];
+    const double c02 = a[1] * a[4] - a[2] * a[3];
+    const double c11 = a[0] * a[5] - a[2] * a[2];
+    const double c12 = a[1] * a[2] - a[0] * a[4];
+    const double c22 = a[0] * a[3] - a[1] * a[1];
+    const double det = a[0] * c00 + a[1] * c01 + a[2] * c02;
+    double inv[6] = {0, 0, 0, 0, 0, 0};
+    if (det != 0.0) {
+        const double r = 1.0 / det;
+        inv[0] = c00 * r; inv[1] = c01 * r; inv[2] = c02 * r;
+        inv[3] = c11 * r; inv[4] = c12 * r; inv[5] = c22 * r;
+    }
+    for (int k = 0; k < 6; ++k) {
+        pinv[(i * 6 + k) * MB + m] = inv[k];
+        if (pinv32) pinv32[(i * 6 + k) * MB + m] = (float)inv[k];
+    }
+}
+
+void launch_invert_diag(hipStream_t s, int nn, int MB, int nm, const double* diag, double* pinv, float* pinv32)
+{
+    long n = (long)nn * MB;
+    if (n > 0) hipLaunchKernelGGL(k_invert_diag, dim3(nblocks(n)), dim3(256), 0, s, nn, MB, nm, diag, pinv, pinv32);
+}
+
+// ---------------------------------------------------------------------------
+// multi-spring law (Section 2.1): modified Ramberg-Osgood skeleton + Masing
+// ---------------------------------------------------------------------------
+
+// normalised skeleton inverse: s with s (1 + |2s|^beta) = e; Newton from the
+// upper bound min(|e|, (|e| / 2^beta)^(1/(1+beta))) decreases monotonically.
+__device__ __forceinline__ double ro_inverse(double e, double beta)
+{
+    const double a = fabs(e);
+    if (a == 0.0) return 0.0;
+    double s = fmin(a, pow(a / exp2(beta), 1.0 / (1.0 + beta)));
+    for (int it = 0; it < 60; ++it) {
+        const double p = pow(2.0 * s, beta);
+        const double f = s * (1.0 + p) - a;
+        if (f <= 0.0) break;
+        const double ds = f / (1.0 + (1.0 + beta) * p);
+        s -= ds;
+        if (ds <= 0x1p-52 * s) break;
+    }
+    return e < 0 ? -s : s;
+}
+
+struct SpringPar { double G0, gref, hmax, beta; };
+
+__device__ __forceinline__ double skeleton_tau(double g, const SpringPar& p)
+{
+    return p.G0 * p.gref * ro_inverse(g / p.gref, p.beta);
+}
+
+struct ThetaPtrs {
+    double *gp, *gr, *tr, *gm;
+    int *dir, *skel;
+};
+
+__device__ __forceinline__ ThetaPtrs theta_fields(void* base, long ec, int ns, int MB)
+{
+    const long n = ec * 4 * (long)ns * MB;
+    ThetaPtrs t;
+    double* d = (double*)base;
+    t.gp = d; t.gr = d + n; t.tr = d + 2 * n; t.gm = d + 3 * n;
+    int* iflag = (int*)(d + 4 * n);
+    t.dir = iflag; t.skel = iflag + n;
+    return t;
+}
+
+__global__ void k_theta_init(void* base, long ec, int ns, int MB)
+{
+    const long n = ec * 4 * (long)ns * MB;
+    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    ThetaPtrs t = theta_fields(base, ec, ns, MB);
+    t.gp[i] = 0; t.gr[i] = 0; t.tr[i] = 0; t.gm[i] = 0; t.dir[i] = 0; t.skel[i] = 1;
+}
+
+void launch_theta_init(hipStream_t s, void* base, long ec, int ns, int MB)
+{
+    long n = ec * 4 * (long)ns * MB;
+    if (n > 0) hipLaunchKernelGGL(k_theta_init, dim3(nblocks(n)), dim3(256), 0, s, base, ec, ns, MB);
+}
+
+// D of a point from the spring tangents: Kb m m^T + sum c_k G_k n_k n_k^T
+__global__ void k_law_init(DevMesh M, int MB, int nm, const double* __restrict__ mat, int ns,
+                           const double* __restrict__ dirs, const double* __restrict__ w,
+                           double* __restrict__ D, float* __restrict__ D32, double* __restrict__ h)
+{
+    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const int m = (int)(t % MB);
+    const long e = t / MB;
+    if (e >= M.ne || m >= nm) return;
+    const long ne = M.ne;
+    const int l = M.layer[e];
+    const double G0 = matv(mat, l, MAT_G0, MB, m), Kb = matv(mat, l, MAT_KB, MB, m);
+    double d[21];
+    for (int k = 0; k < 21; ++k) d[k] = 0;
+    for (int s = 0; s < ns; ++s) {
+        const double* n = dirs + 6 * s;
+        const double c = w[s] * G0;
+        for (int r = 0; r < 6; ++r)
+            for (int q = r; q < 6; ++q) d[sym6(r, q)] += c * n[r] * n[q];
+    }
+    for (int r = 0; r < 3; ++r)
+        for (int q = r; q < 3; ++q) d[sym6(r, q)] += Kb;
+    for (int j = 0; j < 4; ++j)
+        for (int k = 0; k < 21; ++k) {
+            const long idx = (((long)j * 21 + k) * ne + e) * MB + m;
+            D[idx] = d[k];
+            D32[idx] = (float)d[k];
+        }
+    h[e * MB + m] = 0.0;
+}
+
+void launch_law_init(hipStream_t s, const DevMesh& M, int MB, int nm, const double* mat, int, int ns,
+                     const double* dirs, const double* w, double* D, float* D32, double* h)
+{
+    long n = (long)M.ne * MB;
+    if (n > 0) hipLaunchKernelGGL(k_law_init, dim3(nblocks(n)), dim3(256), 0, s, M, MB, nm, mat, ns, dirs, w, D, D32, h);
+}
+
+__global__ __launch_bounds__(256) void k_law(DevMesh M, int MB, int nm, int e0, int ec,
+                                            const double* __restrict__ mat, const int* __restrict__ nonlinear,
+                                            int ns, const double* __restrict__ dirs,
+                                            const double* __restrict__ w, const double* __restrict__ du,
+                                            void* theta, double* __restrict__ D, float* __restrict__ D32,
+                                            double* __restrict__ h, const int* __restrict__ stepping)
+{
+    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const int m = (int)(t % MB);
+    const long el = t / MB;
+    if (el >= ec || m >= nm) return;
+    if (stepping && !stepping[m]) return;
+    const long e = e0 + el;
+    const long ne = M.ne;
+    const int l = M.layer[e];
+    if (!nonlinear[l]) return;
+    SpringPar P;
+    P.G0 = matv(mat, l, MAT_G0, MB, m);
+    P.gref = matv(mat, l, MAT_GREF, MB, m);
+    P.hmax = matv(mat, l, MAT_HMAX, MB, m);
+    P.beta = matv(mat, l, MAT_BETA, MB, m);
+    const double Kb = matv(mat, l, MAT_KB, MB, m);
+    double gL[4][3];
+    for (int k = 0; k < 12; ++k) gL[k / 3][k % 3] = M.geo64[k * ne + e];
+    double u[10][3];
+    for (int n = 0; n < 10; ++n) {
+        const long node = M.conn[n * ne + e];
+        for (int c = 0; c < 3; ++c) u[n][c] = du[(node * 3 + c) * MB + m];
+    }
+    ThetaPtrs th = theta_fields(theta, ec, ns, MB);
+    double hsum = 0.0;
+    for (int j = 0; j < 4; ++j) {
+        double G[10][3], eps[6];
+        shape_grads<double>(j, gL, G);
+        strain<double>(G, u, eps);
+        double d[21];
+        for (int k = 0; k < 21; ++k) d[k] = 0;
+        double hs = 0.0;
+        for (int s = 0; s < ns; ++s) {
+            const double* n = dirs + 6 * s;
+            const double dg = n[0] * eps[0] + n[1] * eps[1] + n[2] * eps[2] + n[3] * eps[3] +
+                              n[4] * eps[4] + n[5] * eps[5];
+            const long idx = (((long)s * 4 + j) * ec + el) * MB + m;
+            double gp = th.gp[idx], gr = th.gr[idx], tr = th.tr[idx], gm = th.gm[idx];
+            int dir = th.dir[idx], skel = th.skel[idx];
+            if (dg != 0.0) {
+                const int dsg = dg > 0.0 ? 1 : -1;
+                if (dir != 0 && dsg != dir) {  // reversal: a Masing branch starts here
+                    tr = skel ? skeleton_tau(gp, P) : tr + 2.0 * skeleton_tau(0.5 * (gp - gr), P);
+                    gr = gp;
+                    skel = 0;
+                }
+                dir = dsg;
+                const double g = gp + dg;
+                if (!skel && (double)dsg * g >= gm) skel = 1;  // rejoin the skeleton
+                if (skel) gm = fmax(gm, fabs(g));
+                gp = g;
+                th.gp[idx] = gp; th.gr[idx] = gr; th.tr[idx] = tr; th.gm[idx] = gm;
+                th.dir[idx] = dir; th.skel[idx] = skel;
+            }
+            const double xi = skel ? gp : 0.5 * (gp - gr);
+            const double sx = ro_inverse(xi / P.gref, P.beta);
+            const double Gt = P.G0 / (1.0 + (1.0 + P.beta) * pow(fabs(2.0 * sx), P.beta));
+            double hk = 0.0;
+            if (gm > 0.0) {
+                const double em = gm / P.gref;
+                // on the skeleton gm == |gp|, so the inverse above is reused
+                const double sm = (skel && fabs(gp) == gm) ? fabs(sx) : ro_inverse(em, P.beta);
+                hk = P.hmax * (1.0 - sm / em);
+            }
+            hs += hk;
+            const double c = w[s] * Gt;
+            for (int r = 0; r < 6; ++r)
+                for (int q = r; q < 6; ++q) d[sym6(r, q)] += c * n[r] * n[q];
+        }
+        for (int r = 0; r < 3; ++r)
+            for (int q = r; q < 3; ++q) d[sym6(r, q)] += Kb;
+        for (int k = 0; k < 21; ++k) {
+            const long idx = (((long)j * 21 + k) * ne + e) * MB + m;
+            D[idx] = d[k];
+            D32[idx] = (float)d[k];
+        }
+        hsum += hs / ns;
+    }
+    h[e * MB + m] = 0.25 * hsum;
+}
+
+void launch_law(hipStream_t s, const DevMesh& M, int MB, int nm, int e0, int ec, const double* mat, int,
+                const int* nonlinear, int ns, const double* dirs, const double* w, const double* du,
+                void* theta, double* D, float* D32, double* h, const int* stepping)
+{
+    long n = (long)ec * MB;
+    if (n > 0)
+        hipLaunchKernelGGL(k_law, dim3(nblocks(n)), dim3(256), 0, s, M, MB, nm, e0, ec, mat, nonlinear, ns, dirs,
+                           w, du, theta, D, D32, h, stepping);
+}
+
+// ---------------------------------------------------------------------------
+// per-member dot products: deterministic two-stage reduction
+// ---------------------------------------------------------------------------
+
+template <int ND, typename T>
+__global__ __launch_bounds__(256) void k_dots(const T* __restrict__ a0, const T* __restrict__ b0,
+                                             const T* __restrict__ a1, const T* __restrict__ b1,
+                                             const T* __restrict__ a2, const T* __restrict__ b2, long nrows,
+                                             int MB, int MBt, double* __restrict__ partial)
+{
+    __shared__ double sh[ND][256];
+    const int t = threadIdx.x;
+    const int ml = t % MBt, rl = t / MBt, rpb = 256 / MBt;
+    const int m = blockIdx.y * MBt + ml;
+    double acc[ND];
+#pragma unroll
+    for (int k = 0; k < ND; ++k) acc[k] = 0.0;
+    for (long row = (long)blockIdx.x * rpb + rl; row < nrows; row += (long)gridDim.x * rpb) {
+        const long i = row * MB + m;
+        acc[0] += (double)a0[i] * (double)b0[i];
+        if (ND > 1) acc[1] += (double)a1[i] * (double)b1[i];
+        if (ND > 2) acc[2] += (double)a2[i] * (double)b2[i];
+    }
+#pragma unroll
+    for (int k = 0; k < ND; ++k) sh[k][t] = acc[k];
+    __syncthreads();
+    for (int st = 128; st >= MBt; st >>= 1) {
+        if (t < st)
+#pragma unroll
+            for (int k = 0; k < ND; ++k) sh[k][t] += sh[k][t + st];
+        __syncthreads();
+    }
+    if (t < MBt)
+#pragma unroll
+        for (int k = 0; k < ND; ++k) partial[((long)k * gridDim.x + blockIdx.x) * MB + m] = sh[k][t];
+}
+
+template <typename T>
+static void dots_impl(hipStream_t s, int nd, const T* a0, const T* b0, const T* a1, const T* b1, const T* a2,
+                      const T* b2, long nrows, int MB, double* partial, int* nblk_out)
+{
+    const int MBt = MB < 256 ? MB : 256;
+    const int rpb = 256 / MBt;
+    long nb = (nrows + rpb - 1) / rpb;
+    int nblk = (int)(nb < kMaxPartialBlocks ? nb : kMaxPartialBlocks);
+    if (nblk < 1) nblk = 1;
+    dim3 g(nblk, MB / MBt);
+    if (nd == 1) hipLaunchKernelGGL((k_dots<1, T>), g, dim3(256), 0, s, a0, b0, a1, b1, a2, b2, nrows, MB, MBt, partial);
+    else if (nd == 2) hipLaunchKernelGGL((k_dots<2, T>), g, dim3(256), 0, s, a0, b0, a1, b1, a2, b2, nrows, MB, MBt, partial);
+    else hipLaunchKernelGGL((k_dots<3, T>), g, dim3(256), 0, s, a0, b0, a1, b1, a2, b2, nrows, MB, MBt, partial);
+    *nblk_out = nblk;
+}
+
+void launch_dots(hipStream_t s, int nd, const double* a0, const double* b0, const double* a1, const double* b1,
+                 const double* a2, const double* b2, long nrows, int MB, double* partial, int* nblk_out)
+{
+    dots_impl<double>(s, nd, a0, b0, a1, b1, a2, b2, nrows, MB, partial, nblk_out);
+}
+void launch_dots32(hipStream_t s, int nd, const float* a0, const float* b0, const float* a1, const float* b1,
+                   long nrows, int MB, double* partial, int* nblk_out)
+{
+    dots_impl<float>(s, nd, a0, b0, a1, b1, nullptr, nullptr, nrows, MB, partial, nblk_out);
+}
+
+// scalar logic of the CG variants, one thread per member (single block)
+__global__ void k_finalize(int stage, int MB, int nm, const double* __restrict__ partial, int nblk, CgScalars cs,
+                           double tol2, int maxit)
+{
+    __shared__ int any;
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    for (int m = threadIdx.x; m < MB; m += blockDim.x) {
+        double S[3] = {0, 0, 0};
+        const int nd = (stage == FIN_START) ? 3 : (stage == FIN_ALPHA || stage == FIN_FCG_RZ || stage == FIN_FCG_RR || stage == FIN_IN_ALPHA) ? 1 : 2;
+        for (int k = 0; k < nd; ++k)
+            for (int b = 0; b < nblk; ++b) S[k] += partial[((long)k * nblk + b) * MB + m];
+        int act = 0;
+        if (m < nm) {
+            switch (stage) {
+            case FIN_START:
+                cs.bb[m] = S[0];
+                cs.rr[m] = S[1];
+                cs.rz[m] = S[2];
+                cs.iters[m] = 0;
+                act = cs.stepping[m] && S[0] > 0.0 && S[1] > tol2 * S[0];
+                cs.active[m] = act;
+                break;
+            case FIN_ALPHA:
+                act = cs.active[m];
+                cs.pAp[m] = S[0];
+                cs.alpha[m] = act ? cs.rz[m] / S[0] : 0.0;
+                break;
+            case FIN_BETA:
+                act = cs.active[m];
+                if (act) {
+                    cs.iters[m] += 1;
+                    cs.rr[m] = S[0];
+                    if (S[0] <= tol2 * cs.bb[m]) {
+                        act = 0;
+                    } else if (cs.iters[m] >= maxit) {
+                        act = 0;
+                        cs.status[m] = -5;
+                    } else {
+                        cs.beta[m] = S[1] / cs.rz[m];
+                        cs.rz[m] = S[1];
+                    }
+                    cs.active[m] = act;
+                }
+                break;
+            case FIN_FCG_START:
+                cs.bb[m] = S[0];
+                cs.rr[m] = S[1];
+                cs.iters[m] = 0;
+                cs.inner_total[m] = 0;
+                act = cs.stepping[m] && S[0] > 0.0 && S[1] > tol2 * S[0];
+                cs.active[m] = act;
+                break;
+            case FIN_FCG_RZ:
+                act = cs.active[m];
+                cs.rz[m] = S[0];
+                break;
+            case FIN_FCG_RR:
+                act = cs.active[m];
+                if (act) {
+                    cs.iters[m] += 1;
+                    cs.rr[m] = S[0];
+                    if (S[0] <= tol2 * cs.bb[m]) act = 0;
+                    else if (cs.iters[m] >= maxit) { act = 0; cs.status[m] = -5; }
+                    cs.active[m] = act;
+                }
+                break;
+            case FIN_FCG_BETA:  // S0 = z.Ap, S1 = z.r
+                act = cs.active[m];
+                if (act) {
+                    cs.beta[m] = -cs.alpha[m] * S[0] / cs.rz[m];
+                    cs.rz[m] = S[1];
+                }
+                break;
+            case FIN_IN_START:
+                act = cs.active[m] && S[0] > 0.0;
+                cs.ir0[m] = S[0];
+                cs.irz[m] = S[1];
+                cs.inner_iters[m] = 0;
+                cs.inner_active[m] = act;
+                break;
+            case FIN_IN_ALPHA:
+                act = cs.inner_active[m];
+                cs.ialpha[m] = act ? cs.irz[m] / S[0] : 0.0;
+                break;
+            case FIN_IN_BETA:
+                act = cs.inner_active[m];
+                if (act) {
+                    cs.inner_iters[m] += 1;
+                    cs.inner_total[m] += 1;
+                    if (S[0] <= tol2 * cs.ir0[m] || cs.inner_iters[m] >= maxit) {
+                        act = 0;
+                    } else {
+                        cs.ibeta[m] = S[1] / cs.irz[m];
+                        cs.irz[m] = S[1];
+                    }
+                    cs.inner_active[m] = act;
+                }
+                break;
+            }
+        }
+        if (act) atomicOr(&any, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) *cs.any_active = any;
+}
+
+void launch_finalize(hipStream_t s, FinalizeStage st, int MB, int nm, const double* partial, int nblk, CgScalars cs,
+                     double tol2, int maxit)
+{
+    int bs = MB < 1024 ? MB : 1024;
+    if (bs < 64) bs = 64;
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(bs), 0, s, (int)st, MB, nm, partial, nblk, cs, tol2, maxit);
+}
+
+// ---------------------------------------------------------------------------
+// CG vector updates (per node, member; block-Jacobi 3x3 symmetric inverse)
+// ---------------------------------------------------------------------------
+
+template <typename T, typename P>
+__device__ __forceinline__ void apply_pinv(const P* __restrict__ pinv, long node, int MB, int m, const T r[3], T z[3])
+{
+    T a[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) a[k] = (T)pinv[(node * 6 + k) * MB + m];
+    z[0] = a[0] * r[0] + a[1] * r[1] + a[2] * r[2];
+    z[1] = a[1] * r[0] + a[3] * r[1] + a[4] * r[2];
+    z[2] = a[2] * r[0] + a[4] * r[1] + a[5] * r[2];
+}
+
+__global__ void k_pcg_start(int nn, int MB, int nm, const double* __restrict__ b, const double* __restrict__ Ap,
+                            const double* __restrict__ pinv, double* __restrict__ r, double* __restrict__ z,
+                            double* __restrict__ p, const int* __restrict__ stepping)
+{
+    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const int m = (int)(t % MB);
+    const long i = t / MB;
+    if (i >= nn || m >= nm) return;
+    double rv[3], zv[3];
+    for (int c = 0; c < 3; ++c) {
+        const long idx = (i * 3 + c) * MB + m;
+        rv[c] = stepping[m] ? b[idx] - Ap[idx] : 0.0;
+    }
+    apply_pinv<double, double>(pinv, i, MB, m, rv, zv);
+    for (int c = 0; c < 3; ++c) {
+        const long idx = (i * 3 + c) * MB + m;
+        r[idx] = rv[c];
+        z[idx] = zv[c];
+        p[idx] = zv[c];
+    }
+}
+
+void launch_pcg_start(hipStream_t s, int nn, int MB, int nm, const double* b, const double* Ap, const double* pinv,
+                      double* r, double* z, double* p, const int* stepping)
+{
+    long n = (long)nn * MB;
+    hipLaunchKernelGGL(k_pcg_start, dim3(nblocks(n)), dim3(256), 0, s, nn, MB, nm, b, Ap, pinv, r, z, p, stepping);
+}
+
+__global__ void k_pcg_update(int nn, int MB, int nm, double* __restrict__ x, double* __restrict__ r,
+                             double* __restrict__ z, const double* __restrict__ p, const double* __restrict__ Ap,
+                             const double* __restrict__ pinv, const double* __restrict__ alpha,
+                             const int* __restrict__ active)
+{
+    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const int m = (int)(t % MB);
+    const long i = t / MB;
+    if (i >= nn || m >= nm || !active[m]) return;
+    const double al = alpha[m];
+    double rv[3], zv[3];
+    for (int c = 0; c < 3; ++c) {
+        const long idx = (i * 3 + c) * MB + m;
+        x[idx] += al * p[idx];
+        rv[c] = r[idx] - al * Ap[idx];
+        r[idx] = rv[c];
+    }
+    apply_pinv<double, double>(pinv, i, MB, m, rv, zv);
+    for (int c = 0; c < 3; ++c) z[(i * 3 + c) * MB + m] = zv[c];
+}
+
+void launch_pcg_update(hipStream_t s, int nn, int MB, int nm, double* x, double* r, double* z, const double* p,
+                       const double* Ap, const double* pinv, const double* alpha, const int* active)
+{
+    long n = (long)nn * MB;
+    hipLaunchKernelGGL(k_pcg_update, dim3(nblocks(n)), dim3(256), 0, s, nn, MB, nm, x, r, z, p, Ap, pinv, alpha, active);
+}
+
+__global__ void k_axpby_p(long n, int MB, int nm, const double* __restrict__ z, double* __restrict__ p,
+                          const double* __restrict__ beta, const int* __restrict__ active)
+{
+    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const int m = (int)(i % MB);
+    if (i >= n || m >= nm || !active[m]) return;
+    p[i] = z[i] + beta[m] * p[i];
+}
+
+void launch_axpby_p(hipStream_t s, long n, int MB, int nm, const double* z, double* p, const double* beta,
+                    const int* active)
+{
+    long N = n * MB;
+    hipLaunchKernelGGL(k_axpby_p, dim3(nblocks(N)), dim3(256), 0, s, N, MB, nm, z, p, beta, active);
+}
+
+__global__ void k_zero_inactive_start(long n, int MB, int nm, double* __restrict__ x, const double* __restrict__ bb,
+                                      const int* __restrict__ stepping)
+{
+    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const int m = (int)(i % MB);
+    if (i >= n || m >= nm) return;
+    if (stepping[m] && bb[m] == 0.0) x[i] = 0.0;
+}
+
+void launch_zero_inactive_start(hipStream_t s, long n, int MB, int nm, double* x, const double* bb,
+                                const int* stepping)
+{
+    long N = n * MB;
+    hipLaunchKernelGGL(k_zero_inactive_start, dim3(nblocks(N)), dim3(256), 0, s, N, MB, nm, x, bb, stepping);
+}
+
+__global__ void k_xr_update(long n, int MB, int nm, double* __restrict__ x, double* __restrict__ r,
+                            const double* __restrict__ p, const double* __restrict__ Ap,
+                            const double* __restrict__ alpha, const int* __restrict__ active)
+{
+    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const int m = (int)(i % MB);
+    if (i >= n || m >= nm || !active[m]) return;
+    const double al = alpha[m];
+    x[i] += al * p[i];
+    r[i] -= al * Ap[i];
+}
+
+void launch_xr_update(hipStream_t s, long n, int MB, int nm, double* x, double* r, const double* p, const double* Ap,
+                      const double* alpha, const int* active)
+{
+    long N = n * MB;
+    hipLaunchKernelGGL(k_xr_update, dim3(nblocks(N)), dim3(256), 0, s, N, MB, nm, x, r, p, Ap, alpha, active);
+}
+
+__global__ void k_copy_p(long n, int MB, int nm, const double* __restrict__ z, double* __restrict__ p,
+                         const int* __restrict__ active)
+{
+    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const int m = (int)(i % MB);
+    if (i >= n || m >= nm || !active[m]) return;
+    p[i] = z[i];
+}
+
+void launch_copy_p(hipStream_t s, long n, int MB, int nm, const double* z, double* p, const int* active)
+{
+    long N = n * MB;
+    hipLaunchKernelGGL(k_copy_p, dim3(nblocks(N)), dim3(256), 0, s, N, MB, nm, z, p, active);
+}
+
+// inner FP32 block-Jacobi PCG on A z = r (preconditioner of the outer CG)
+__global__ void k_inner_start(int nn, int MB, int nm, const double* __restrict__ r, const float* __restrict__ pinv32,
+                              float* __restrict__ ir, float* __restrict__ iz, float* __restrict__ ip,
+                              float* __restrict__ w, const int* __restrict__ active)
+{
+    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const int m = (int)(t % MB);
+    const long i = t / MB;
+    if (i >= nn || m >= nm || !active[m]) return;
+    float rv[3], zv[3];
+    for (int c = 0; c < 3; ++c) rv[c] = (float)r[(i * 3 + c) * MB + m];
+    apply_pinv<float, float>(pinv32, i, MB, m, rv, zv);
+    for (int c = 0; c < 3; ++c) {
+        const long idx = (i * 3 + c) * MB + m;
+        ir[idx] = rv[c];
+        iz[idx] = 0.0f;
+        w[idx] = zv[c];
+        ip[idx] = zv[c];
+    }
+}
+
+void launch_inner_start(hipStream_t s, int nn, int MB, int nm, const double* r, const float* pinv32, float* ir,
+                        float* iz, float* ip, float* w, const int* active)
+{
+    long n = (long)nn * MB;
+    hipLaunchKernelGGL(k_inner_start, dim3(nblocks(n)), dim3(256), 0, s, nn, MB, nm, r, pinv32, ir, iz, ip, w, active);
+}
+
+__global__ void k_inner_update(int nn, int MB, int nm, float* __restrict__ iz, float* __restrict__ ir,
+                               float* __restrict__ w, const float* __restrict__ ip, const float* __restrict__ iAp,
+                               const float* __restrict__ pinv32, const double* __restrict__ ialpha,
+                               const int* __restrict__ iactive)
+{
+    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const int m = (int)(t % MB);
+    const long i = t / MB;
+    if (i >= nn || m >= nm || !iactive[m]) return;
+    const float al = (float)ialpha[m];
+    float rv[3], zv[3];
+    for (int c = 0; c < 3; ++c) {
+        const long idx = (i * 3 + c) * MB + m;
+        iz[idx] += al * ip[idx];
+        rv[c] = ir[idx] - al * iAp[idx];
+        ir[idx] = rv[c];
+    }
+    apply_pinv<float, float>(pinv32, i, MB, m, rv, zv);
+    for (int c = 0; c < 3; ++c) w[(i * 3 + c) * MB + m] = zv[c];
+}
+
+void launch_inner_update(hipStream_t s, int nn, int MB, int nm, float* iz, float* ir, float* w, const float* ip,
+                         const float* iAp, const float* pinv32, const double* ialpha, const int* iactive)
+{
+    long n = (long)nn * MB;
+    hipLaunchKernelGGL(k_inner_update, dim3(nblocks(n)), dim3(256), 0, s, nn, MB, nm, iz, ir, w, ip, iAp, pinv32,
+                       ialpha, iactive);
+}
+
+__global__ void k_inner_p(long n, int MB, int nm, const float* __restrict__ w, float* __restrict__ ip,
+                          const double* __restrict__ ibeta, const int* __restrict__ iactive)
+{
+    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const int m = (int)(i % MB);
+    if (i >= n || m >= nm || !iactive[m]) return;
+    ip[i] = w[i] + (float)ibeta[m] * ip[i];
+}
+
+void launch_inner_p(hipStream_t s, long n, int MB, int nm, const float* w, float* ip, const double* ibeta,
+                    const int* iactive)
+{
+    long N = n * MB;
+    hipLaunchKernelGGL(k_inner_p, dim3(nblocks(N)), dim3(256), 0, s, N, MB, nm, w, ip, ibeta, iactive);
+}
+
+__global__ void k_inner_out(long n, int MB, int nm, const float* __restrict__ iz, double* __restrict__ z,
+                            const int* __restrict__ active)
+{
+    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const int m = (int)(i % MB);
+    if (i >= n || m >= nm || !active[m]) return;
+    z[i] = (double)iz[i];
+}
+
+void launch_inner_out(hipStream_t s, long n, int MB, int nm, const float* iz, double* z, const int* active)
+{
+    long N = n * MB;
+    hipLaunchKernelGGL(k_inner_out, dim3(nblocks(N)), dim3(256), 0, s, N, MB, nm, iz, z, active);
+}
+
+// ---------------------------------------------------------------------------
+// Newmark state updates (Section 2.1), receivers, incident wave
+// ---------------------------------------------------------------------------
+
+__global__ void k_newmark(long n, int MB, int nm, const double* __restrict__ du, double* __restrict__ u,
+                          double* __restrict__ v, double* __restrict__ a, double dt, const int* __restrict__ stepping)
+{
+    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const int m = (int)(i % MB);
+    if (i >= n || m >= nm || !stepping[m]) return;
+    const double d = du[i], vo = v[i];
+    u[i] += d;
+    a[i] = -a[i] - 4.0 / dt * vo + 4.0 / (dt * dt) * d;
+    v[i] = -vo + 2.0 / dt * d;
+}
+
+void launch_newmark(hipStream_t s, long n, int MB, int nm, const double* du, double* u, double* v, double* a,
+                    double dt, const int* stepping)
+{
+    long N = n * MB;
+    hipLaunchKernelGGL(k_newmark, dim3(nblocks(N)), dim3(256), 0, s, N, MB, nm, du, u, v, a, dt, stepping);
+}
+
+__global__ void k_receivers(int nrecv, const int* __restrict__ recv, int MB, int nm, const double* __restrict__ v,
+                            double* __restrict__ hist, const int* __restrict__ member_step, int ns,
+                            double* __restrict__ vmax, const int* __restrict__ stepping)
+{
+    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const int m = (int)(t % MB);
+    const long r = t / MB;
+    if (r >= nrecv || m >= nm || !stepping[m]) return;
+    const long node = recv[r];
+    const int step = member_step[m];
+    double nrm = 0.0;
+    for (int c = 0; c < 3; ++c) {
+        const double val = v[(node * 3 + c) * MB + m];
+        hist[(((long)m * ns + step) * nrecv + r) * 3 + c] = val;
+        nrm += val * val;
+    }
+    nrm = sqrt(nrm);
+    const long vi = (long)m * nrecv + r;
+    if (nrm > vmax[vi]) vmax[vi] = nrm;
+}
+
+void launch_receivers(hipStream_t s, int nrecv, const int* recv, int MB, int nm, const double* v, double* hist,
+                      const int* member_step, int ns, double* vmax, const int* stepping)
+{
+    long n = (long)nrecv * MB;
+    if (n > 0)
+        hipLaunchKernelGGL(k_receivers, dim3(nblocks(n)), dim3(256), 0, s, nrecv, recv, MB, nm, v, hist, member_step,
+                           ns, vmax, stepping);
+}
+
+// incident velocity by the trapezoid rule from the incident acceleration
+// (zero at t = 0): one thread per (member, component), sequential in time
+__global__ void k_incident_velocity(int nm, int ns, const double* __restrict__ acc, double* __restrict__ vI, double dt)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nm * 3) return;
+    const int m = t / 3, c = t % 3;
+    double v = 0.0, ap = 0.0;
+    for (int n = 0; n < ns; ++n) {
+        const double an = acc[((long)m * ns + n) * 3 + c];
+        v += 0.5 * dt * (ap + an);
+        ap = an;
+        vI[((long)m * ns + n) * 3 + c] = v;
+    }
+}
+
+void launch_incident_velocity(hipStream_t s, int, int nm, int ns, const double* acc, double* vI, double dt)
+{
+    hipLaunchKernelGGL(k_incident_velocity, dim3(nblocks(nm * 3)), dim3(256), 0, s, nm, ns, acc, vI, dt);
+}
+
+// incident velocity of each member at its current step, member-innermost [3][MB]
+__global__ void k_pick_vI(int MB, int nm, int ns, const double* __restrict__ vI_all, const int* __restrict__ member_step,
+                          double* __restrict__ vI_cur)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= MB * 3) return;
+    const int m = t % MB, c = t / MB;
+    double v = 0.0;
+    if (m < nm) {
+        const int st = member_step[m];
+        if (st >= 0 && st < ns) v = vI_all[((long)m * ns + st) * 3 + c];
+    }
+    vI_cur[c * MB + m] = v;
+}
+
+void launch_pick_vI(hipStream_t s, int MB, int nm, int ns, const double* vI_all, const int* member_step,
+                    double* vI_cur)
+{
+    hipLaunchKernelGGL(k_pick_vI, dim3(nblocks(MB * 3)), dim3(256), 0, s, MB, nm, ns, vI_all, member_step, vI_cur);
+}
+
+__global__ void k_record_iters(int MB, int nm, int ns, const int* __restrict__ member_step,
+                               const int* __restrict__ stepping, const int* __restrict__ iters,
+                               const int* __restrict__ inner_total, int* __restrict__ out)
+{
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= nm || !stepping[m]) return;
+    const int st = member_step[m];
+    if (st < 0 || st >= ns) return;
+    out[((long)m * ns + st) * 2] = iters[m];
+    out[((long)m * ns + st) * 2 + 1] = inner_total[m];
+}
+
+void launch_record_iters(hipStream_t s, int MB, int nm, int ns, const int* member_step, const int* stepping,
+                         const int* iters, const int* inner_total, int* out)
+{
+    hipLaunchKernelGGL(k_record_iters, dim3(nblocks(MB)), dim3(256), 0, s, MB, nm, ns, member_step, stepping, iters,
+                       inner_total, out);
+}
+
+}  // namespace nlth

@@ -1,0 +1,196 @@
+// Host runtime of libnlth: contexts, meshes, ensembles (the per-step driver),
+// paging of the law state and the serving loop.  Internal to the library.
+#pragma once
+
+#include <atomic>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/nlth.h"
+#include "nlth_impl.hpp"
+
+namespace nlth {
+
+struct Error {
+    int code;
+    std::string msg;
+};
+
+#define NLTH_HIP(expr)                                                                  \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            throw ::nlth::Error{NLTH_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+
+// device allocation with a byte budget shared by a context
+struct Budget {
+    std::mutex mu;
+    int64_t limit = 0, used = 0;
+    int64_t host_limit = 0, host_used = 0;
+};
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    Budget* budget = nullptr;
+    bool host = false;  // pinned host memory
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    void alloc(Budget* b, size_t n, bool pinned_host = false);
+    void release();
+    template <typename T> T* as() const { return (T*)p; }
+};
+
+struct Ctx;
+
+struct Mesh {
+    Ctx* ctx = nullptr;
+    int nn = 0, ne = 0, nf = 0, nrecv = 0, ncolor = 0, max_layer = 0;
+    double volume = 0.0;
+    // host copies / analysis
+    std::vector<double> xyz;
+    std::vector<int> order;        // sorted position -> input tet
+    std::vector<int> inv_order;    // input tet -> sorted position
+    std::vector<int> color_off;    // [ncolor+1]
+    std::vector<int> recv;
+    // device
+    DevBuf conn, geo64, geo32, layer, bn_node, bn_ptr, bn_face, bn_loc, f_node, f_M, f_n, f_layer, f_kind, recv_d;
+    int nbn = 0;
+    std::atomic<int> refs{0};
+    DevMesh dev() const;
+};
+
+struct Problem {  // host copy of an nlth_problem
+    int nm = 0, nl = 0, ns = 0, n_steps = 0;
+    std::vector<double> rho, vs, nu, gref, hmax, dirs, w, acc;
+    std::vector<int> nonlinear;
+    int damping_mode = 0;
+    double h0 = 0, f_lo = 0.1, f_hi = 10, dt = 1e-3, cg_tol = 1e-8, inner_tol = 0.1;
+    int cg_maxit = 1000, precision = 0, inner_maxit = 50;
+};
+
+struct ProfCat { double ms = 0; int64_t n = 0; int64_t elems = 0; };
+
+struct Ens {
+    Ctx* ctx = nullptr;
+    const Mesh* mesh = nullptr;
+    Problem P;
+    int MB = 1, nm = 0;
+    long ndof = 0;
+    StepConst sc{};
+    hipStream_t s = nullptr;
+    // device state
+    DevBuf mat, dirs, w, nonlinear, acc, vI_all, vI_cur;
+    DevBuf u, v, a, q, du, b, r, z, p, Ap, diag, pinv, pinv32;
+    DevBuf ir, iz, ip, iw, iAp;
+    DevBuf D64, D32, h;
+    DevBuf theta;                       // resident law state (or the device chunk ring)
+    DevBuf theta_host;                  // pinned host state when paged
+    DevBuf hist, vmax, iters_dev;
+    DevBuf partial, scal;               // CG scalars block
+    DevBuf member_step, stepping, status;
+    CgScalars cs{};
+    // paging
+    bool paged = false;
+    int chunk_elems = 0, nchunks = 0, ring = 3;
+    std::vector<long> chunk_off;        // byte offset of each chunk in theta_host
+    std::vector<int> chunk_e0, chunk_ec;
+    hipStream_t s_h2d = nullptr, s_d2h = nullptr;
+    std::vector<hipEvent_t> ev_h2d, ev_law, ev_d2h;
+    std::vector<int> slot_chunk;        // chunk currently held by each slot (-1 none)
+    std::vector<bool> prefetched;
+    // host bookkeeping
+    std::vector<int> h_member_step, h_stepping, h_status;
+    int steps_done = 0;
+    int check_every = 8;
+    // profiling
+    bool profile = false;
+    ProfCat pc_ebe64, pc_ebe32, pc_vec, pc_law, pc_other;
+    std::vector<std::pair<std::pair<hipEvent_t, hipEvent_t>, ProfCat*>> pending;
+    std::vector<hipEvent_t> ev_pool;
+    double ms_total = 0, ms_copy = 0;
+    int64_t outer_total = 0, inner_total = 0, h2d_bytes = 0, d2h_bytes = 0;
+    int64_t dev_bytes = 0, host_bytes = 0;
+    hipEvent_t ev_copy0 = nullptr, ev_copy1 = nullptr;
+
+    void create(Ctx* c, const Mesh* m, const Problem& p, int member_pad = 0);
+    void destroy();
+    ~Ens() { destroy(); }
+    void step_all(int n_steps);        // lockstep members
+    void one_step();                    // uses h_member_step / h_stepping
+    void read(nlth_result* res) const;
+    // pieces
+    void ebe(OpMode mode, const double* x1, const double* x2, double* y, const int* active);
+    void ebe32(const float* x, float* y, const int* active);
+    void build_rhs();
+    void build_diag();
+    void solve_pcg();
+    void solve_fcg();
+    void inner_solve();
+    void law_phase();
+    void prefetch_next();
+    // helpers
+    void dots(int nd, const double* a0, const double* b0, const double* a1, const double* b1,
+              const double* a2, const double* b2, int& nblk);
+    int read_any_active();
+    hipEvent_t ev();
+    void tstart(hipEvent_t& e0);
+    void tstop(hipEvent_t e0, ProfCat* cat, int64_t elems);
+    void collect_prof();
+    void sync();
+    // member slot management (serving)
+    void reset_member(int m);
+};
+
+struct Request;
+
+struct Ctx {
+    int device = -1;
+    bool host_only = true;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    Budget budget;
+    std::mutex mu;  // serialises API calls on the context
+    std::string last_error;
+    int log_level = 0;
+    int max_batch = 64;
+    std::atomic<int> live_meshes{0};
+    // serving
+    std::mutex smu;
+    std::condition_variable scv;
+    std::thread worker;
+    bool stop = false;
+    uint64_t next_ticket = 1;
+    std::map<uint64_t, std::shared_ptr<Request>> requests;
+    std::deque<std::shared_ptr<Request>> queue;
+    void ensure_worker();
+    void worker_loop();
+    ~Ctx();
+};
+
+struct Request {
+    uint64_t ticket = 0;
+    const Mesh* mesh = nullptr;
+    Problem P;  // one member
+    nlth_result res{};
+    std::atomic<int> state{0};  // 0 queued, 1 running, 2 done, 3 cancelled
+    std::atomic<int> cancel{0};
+    int status = 0;
+    int64_t need_bytes = 0;
+};
+
+void set_error(Ctx* c, const Error& e);
+int64_t ensemble_bytes(const Mesh& m, const Problem& p, int MB, bool paged);
+void copy_problem(const nlth_problem* in, Problem& out);
+int pad_members(int nm);
+
+}  // namespace nlth

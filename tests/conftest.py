@@ -18,3 +18,21 @@ def oracle_lib():
     import oracle
     oracle.build()
     return oracle
+
+
+@pytest.fixture(scope="session")
+def nlth_mod():
+    """The ctypes binding; builds libnlth.so only if it is not built yet."""
+    from paper_2604_02755_amd import nlth
+    if not os.path.exists(nlth.LIB_PATH):
+        from paper_2604_02755_amd import build
+        build.build()
+    nlth.lib()
+    return nlth
+
+
+@pytest.fixture(scope="session")
+def gpu_ctx(nlth_mod):
+    ctx = nlth_mod.Context(0, use_torch_stream=False)
+    yield ctx
+    ctx.close()

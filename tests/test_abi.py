@@ -1,0 +1,95 @@
+"""C-ABI library checks that need no GPU: it loads, exports every symbol
+include/nlth.h declares, and its host logic (mesh validation, colouring,
+problem validation) behaves as documented."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2604_02755_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "nlth.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(nlth_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported(nlth_mod):
+    names = _declared()
+    assert len(names) >= 20
+    L = nlth_mod.lib()
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    assert set(names) <= set(nlth_mod.EXPORTS), set(names) - set(nlth_mod.EXPORTS)
+    assert nlth_mod.nlth_version() == 10000
+
+
+@pytest.fixture()
+def host_ctx(nlth_mod):
+    c = nlth_mod.nlth_ctx_create(nlth_mod.NLTH_DEVICE_NONE)
+    yield c
+    nlth_mod.nlth_ctx_destroy(c)
+
+
+def test_colouring_is_conflict_free(nlth_mod, host_ctx):
+    for mesh in (I.box_mesh(6, 5, 3, 1.0, I.two_layer(1.0)), I.perturbed_three_layer_mesh(8, 8, 8, seed=2, amp=0.8, corr=4.0)):
+        mh = nlth_mod.nlth_mesh_create(host_ctx, mesh)
+        info, order, off = nlth_mod.nlth_mesh_query(host_ctx, mh, mesh.n_tets)
+        assert info.n_tets == mesh.n_tets and info.n_nodes == mesh.n_nodes
+        assert sorted(order.tolist()) == list(range(mesh.n_tets))
+        assert off[0] == 0 and off[-1] == mesh.n_tets
+        for c in range(info.n_colors):
+            tets = mesh.tet10[order[off[c]:off[c + 1]]]
+            nodes = tets.ravel()
+            assert np.unique(nodes).size == nodes.size, f"colour {c} shares a node"
+        nx, ny, nz = mesh.dims
+        assert abs(info.volume - nx * ny * nz) < 1e-9 * nx * ny * nz
+        assert info.n_bnodes > 0
+        assert 24 <= info.n_colors <= 64
+        nlth_mod.nlth_mesh_destroy(mh)
+
+
+def test_mesh_validation_errors(nlth_mod, host_ctx):
+    mesh = I.box_mesh(2, 2, 1)
+    bad = I.box_mesh(2, 2, 1)
+    t = bad.tet10.copy()
+    t[3, [1, 2]] = t[3, [2, 1]]
+    bad.tet10 = t
+    with pytest.raises(nlth_mod.NlthError) as ei:
+        nlth_mod.nlth_mesh_create(host_ctx, bad)
+    assert ei.value.code == nlth_mod.NLTH_EINVAL and "tet 3" in str(ei.value)
+    bad = I.box_mesh(2, 2, 1)
+    t = bad.tet10.copy()
+    t[5, 7] = mesh.n_nodes + 4
+    bad.tet10 = t
+    with pytest.raises(nlth_mod.NlthError) as ei:
+        nlth_mod.nlth_mesh_create(host_ctx, bad)
+    assert "tet 5" in str(ei.value)
+    bad = I.box_mesh(2, 2, 1)
+    x = bad.xyz.copy()
+    x[bad.tet10[0, 4]] += 0.01  # curved edge
+    bad.xyz = x
+    with pytest.raises(nlth_mod.NlthError) as ei:
+        nlth_mod.nlth_mesh_create(host_ctx, bad)
+    assert "straight" in str(ei.value)
+
+
+def test_problem_validation_before_device(nlth_mod, host_ctx):
+    import ctypes as C
+    mesh, prob = I.config(0, n_steps=3, mesh_dims=(2, 2, 6))  # two layers
+    mh = nlth_mod.nlth_mesh_create(host_ctx, mesh)
+    keep = []
+    h = C.c_void_p()
+    p = nlth_mod._problem_struct(prob, keep)
+    assert nlth_mod.lib().nlth_ens_create(host_ctx, mh, C.byref(p), C.byref(h)) == nlth_mod.NLTH_EDEVICE
+    p.dt = 0.0
+    assert nlth_mod.lib().nlth_ens_create(host_ctx, mh, C.byref(p), C.byref(h)) == nlth_mod.NLTH_EINVAL
+    p.dt = 1e-3
+    p.n_layers = 1  # mesh uses layer 1
+    rc = nlth_mod.lib().nlth_ens_create(host_ctx, mh, C.byref(p), C.byref(h))
+    nlth_mod.nlth_mesh_destroy(mh)
+    assert rc == nlth_mod.NLTH_EINVAL

@@ -1,0 +1,141 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 CPU oracle.
+
+Bars: FP64 path <= 1e-9 and mixed path <= 1e-6 relative L2 on receiver
+velocity (parity runs use CG tolerance 1e-12 on both sides, so the mixed path
+is held to 1e-9 there as well); single operator applications to 1e-13 (FP64)
+and 2e-6 (FP32, the inner preconditioner's arithmetic).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2604_02755_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _rand_D(rng, ne, G0=4e7, lam=3e8):
+    """SPD D per point: isotropic plus a random symmetric PSD part."""
+    base = np.zeros((6, 6))
+    base[:3, :3] = lam
+    base[np.arange(3), np.arange(3)] += 2 * G0
+    base[3:, 3:] = np.eye(3) * G0
+    L = rng.normal(size=(ne, 4, 6, 6)) * 0.3 * G0 ** 0.5
+    D = base + np.einsum("eiab,eicb->eiac", L, L)
+    iu = np.triu_indices(6)
+    return D[:, :, iu[0], iu[1]]
+
+
+@pytest.mark.parametrize("dims", [(5, 4, 3), (16, 16, 8)])
+def test_operator_parity(gpu_ctx, oracle_lib, dims):
+    mesh, prob = I.config(0, n_steps=1, mesh_dims=dims)
+    say("operator parity", dims, mesh.n_tets)
+    rng = np.random.default_rng(11)
+    D = _rand_D(rng, mesh.n_tets)
+    h = rng.uniform(0, 0.2, mesh.n_tets)
+    x = rng.normal(size=mesh.n_dof)
+    mh = gpu_ctx.mesh(mesh)
+    for which in (0, 1, 2):
+        y_ref = oracle_lib.apply_operator(mesh, prob, which, D, h, x)
+        y = gpu_ctx.apply_operator(mh, prob, which, 0, D, h, x)
+        err = np.linalg.norm(y - y_ref) / np.linalg.norm(y_ref)
+        say("  op", which, "fp64 rel err", err)
+        assert err < 1e-13
+    y_ref = oracle_lib.apply_operator(mesh, prob, 0, D, h, x)
+    y32 = gpu_ctx.apply_operator(mh, prob, 0, 1, D, h, x)
+    err = np.linalg.norm(y32 - y_ref) / np.linalg.norm(y_ref)
+    say("  op A fp32 rel err", err)
+    assert err < 2e-6
+
+
+def _small_problem(n_steps=40, precision=0, tol=1e-12, n_members=1, dims=(5, 4, 3), scale=5.0, ns=150):
+    mesh, prob = I.config(0, n_steps=n_steps, mesh_dims=dims, n_members=n_members, cg_tol=tol,
+                          precision=precision, n_springs=ns)
+    prob.input_acc *= scale  # drive the springs well past gamma_ref
+    return mesh, prob
+
+
+def _oracle_vel(oracle_lib, mesh, prob, m=0):
+    r = oracle_lib.run(mesh, prob, member=m)
+    return r["vel"], r["iters"]
+
+
+def test_fp64_path_parity_small(gpu_ctx, oracle_lib):
+    mesh, prob = _small_problem()
+    say("fp64 path", mesh.n_tets, "tets", prob.n_steps, "steps")
+    vref, itref = _oracle_vel(oracle_lib, mesh, prob)
+    mh = gpu_ctx.mesh(mesh)
+    out = gpu_ctx.solve(mh, mesh, prob)
+    assert out["rc"] == 0
+    err = oracle_lib.rel_l2(out["vel"][0], vref)
+    say("  rel L2", err, "iters gpu", out["iters"][0, :8, 0], "oracle", itref[:8])
+    assert err < 1e-9
+    assert np.max(np.abs(out["iters"][0, :, 0] - itref)) <= 1
+    assert np.isfinite(out["vmax"]).all() and out["vmax"].max() > 0
+
+
+def test_mixed_path_parity_small(gpu_ctx, oracle_lib):
+    mesh, prob = _small_problem(precision=1)
+    say("mixed path", mesh.n_tets, "tets")
+    vref, _ = _oracle_vel(oracle_lib, mesh, prob)
+    mh = gpu_ctx.mesh(mesh)
+    out = gpu_ctx.solve(mh, mesh, prob)
+    assert out["rc"] == 0
+    err = oracle_lib.rel_l2(out["vel"][0], vref)
+    say("  rel L2 (tol 1e-12)", err, "outer/inner", out["iters"][0, 10:14])
+    assert err < 1e-9
+    # throughput tolerance: mixed vs FP64, both at 1e-8
+    mesh, p8 = _small_problem(precision=1, tol=1e-8)
+    _, p64 = _small_problem(precision=0, tol=1e-8)
+    o_mixed = gpu_ctx.solve(mh, mesh, p8)
+    o_fp64 = gpu_ctx.solve(mh, mesh, p64)
+    err = oracle_lib.rel_l2(o_mixed["vel"][0], o_fp64["vel"][0])
+    err_or = oracle_lib.rel_l2(o_mixed["vel"][0], vref)
+    say("  mixed vs fp64 at 1e-8", err, "vs oracle", err_or)
+    assert err < 1e-6 and err_or < 1e-6
+
+
+def test_batch_matches_members_alone_and_oracle(gpu_ctx, oracle_lib):
+    mesh, prob = _small_problem(n_members=3, n_steps=30, ns=12)
+    vs, gr = I.ensemble_members(77, 3, I.CFG0_LAYERS["vs"])
+    prob.vs = vs
+    prob.gamma_ref = np.tile(gr[:, None], (1, 2))
+    say("batch of 3 (padded to 4)")
+    mh = gpu_ctx.mesh(mesh)
+    out = gpu_ctx.solve(mh, mesh, prob)
+    assert out["rc"] == 0
+    for m in range(3):
+        vref, _ = _oracle_vel(oracle_lib, mesh, prob, m)
+        alone = gpu_ctx.solve(mh, mesh, prob, members=[m])
+        e_or = oracle_lib.rel_l2(out["vel"][m], vref)
+        e_al = oracle_lib.rel_l2(out["vel"][m], alone["vel"][0])
+        say("  member", m, "vs oracle", e_or, "batched vs alone", e_al)
+        assert e_or < 1e-9 and e_al < 1e-12
+
+
+def test_nonconvergence_reported(gpu_ctx, nlth_mod):
+    mesh, prob = _small_problem(n_steps=5, tol=1e-12)
+    prob.cg_maxit = 2
+    mh = gpu_ctx.mesh(mesh)
+    out = gpu_ctx.solve(mh, mesh, prob)
+    say("enoconv rc", out["rc"], out["status"])
+    assert out["rc"] == nlth_mod.NLTH_ENOCONV and out["status"][0] == nlth_mod.NLTH_ENOCONV
+
+
+def test_config0_fp64_parity(gpu_ctx, oracle_lib):
+    """16x16x8 cubes, two layers, 150 springs, 1 ms steps (the first 100 of
+    the 200-step record, which covers the ramp and the strong motion)."""
+    mesh, prob = I.config(0, n_steps=100, cg_tol=1e-12)
+    say("config 0 fp64, 100 steps")
+    vref, itref = _oracle_vel(oracle_lib, mesh, prob)
+    mh = gpu_ctx.mesh(mesh)
+    out = gpu_ctx.solve(mh, mesh, prob)
+    err = oracle_lib.rel_l2(out["vel"][0], vref)
+    say("  rel L2", err, "iters", out["iters"][0, 40:44, 0], itref[40:44])
+    assert out["rc"] == 0 and err < 1e-9

@@ -32,8 +32,10 @@ def _rand_tet(rng):
 def test_volumes_sum_to_box(oracle_lib):
     """Second-order tets (Section 2.1): element volumes tile the box exactly."""
     for mesh, vol in ((I.box_mesh(4, 3, 2, 1.0), 24.0),
-                      (I.perturbed_three_layer_mesh(8, 8, 8, seed=3), 512.0)):
-        tot = sum(oracle_lib.tet_geometry(mesh.xyz[t[:4]])[1] for t in mesh.tet10)
+                      (I.perturbed_three_layer_mesh(8, 8, 8, seed=3, amp=0.8, corr=4.0), 512.0)):
+        geo = [oracle_lib.tet_geometry(mesh.xyz[t[:4]]) for t in mesh.tet10]
+        assert all(g[2] == 0 and g[1] > 0 for g in geo)  # every tet positively oriented
+        tot = sum(g[1] for g in geo)
         assert abs(tot - vol) < 1e-11 * vol
 
 
