@@ -599,7 +599,9 @@ void Ens::create(Ctx* c, const Mesh* m, const Problem& prob, int member_pad)
             bb->alloc(bg, (size_t)ndof * MB * 4);
             launch_fill32(s, bb->as<float>(), 0.0f, (long)ndof * MB);
         }
-    const size_t nD = (size_t)m->ne * 4 * 21 * MB;
+    EB = MB >= 64 ? 1 : 64 / MB;
+    ne_pad = (m->ne + EB - 1) / EB * EB;
+    const size_t nD = (size_t)ne_pad * 4 * 21 * MB;
     D64.alloc(bg, nD * 8);
     D32.alloc(bg, nD * 4);
     h.alloc(bg, (size_t)m->ne * MB * 8);
@@ -609,7 +611,7 @@ void Ens::create(Ctx* c, const Mesh* m, const Problem& prob, int member_pad)
 
     // law state: resident if it fits the remaining budget, else paged
     const size_t per_elem = (size_t)4 * P.ns * MB * 40;
-    const size_t theta_bytes = per_elem * m->ne;
+    const size_t theta_bytes = per_elem * ne_pad;
     int64_t avail;
     {
         std::lock_guard<std::mutex> g(bg->mu);
@@ -619,12 +621,13 @@ void Ens::create(Ctx* c, const Mesh* m, const Problem& prob, int member_pad)
     paged = (int64_t)theta_bytes + reserve > avail;
     if (!paged) {
         theta.alloc(bg, theta_bytes);
-        launch_theta_init(s, theta.p, m->ne, P.ns, MB);
+        launch_theta_init(s, theta.p, ne_pad, P.ns, MB);
     } else {
         // chunk ring: the largest chunk with 3 slots fitting a quarter of what is left
         int64_t slot_bytes = std::max<int64_t>((avail - reserve) / 4 / ring, (int64_t)per_elem);
         slot_bytes = std::min<int64_t>(slot_bytes, (int64_t)1 << 31);
-        chunk_elems = (int)std::max<int64_t>(1, std::min<int64_t>(slot_bytes / (int64_t)per_elem, m->ne));
+        chunk_elems = (int)std::max<int64_t>(1, std::min<int64_t>(slot_bytes / (int64_t)per_elem, ne_pad));
+        chunk_elems = std::max(EB, chunk_elems / EB * EB);
         nchunks = (m->ne + chunk_elems - 1) / chunk_elems;
         if (nchunks < ring) ring = std::max(1, nchunks);
         theta_host.alloc(bg, theta_bytes, true);
@@ -634,13 +637,14 @@ void Ens::create(Ctx* c, const Mesh* m, const Problem& prob, int member_pad)
             int e0 = cix * chunk_elems, ec = std::min(chunk_elems, m->ne - e0);
             chunk_e0.push_back(e0);
             chunk_ec.push_back(ec);
+            chunk_ecp.push_back((ec + EB - 1) / EB * EB);
             chunk_off.push_back(off);
-            off += (long)ec * per_elem;
+            off += (long)chunk_ecp.back() * per_elem;
         }
         // initialise each chunk on the device and write it to the host copy
         for (int cix = 0; cix < nchunks; ++cix) {
-            launch_theta_init(s, theta.p, chunk_ec[cix], P.ns, MB);
-            NLTH_HIP(hipMemcpyAsync((char*)theta_host.p + chunk_off[cix], theta.p, (size_t)chunk_ec[cix] * per_elem,
+            launch_theta_init(s, theta.p, chunk_ecp[cix], P.ns, MB);
+            NLTH_HIP(hipMemcpyAsync((char*)theta_host.p + chunk_off[cix], theta.p, (size_t)chunk_ecp[cix] * per_elem,
                                     hipMemcpyDeviceToHost, s));
         }
         NLTH_HIP(hipStreamCreateWithFlags(&s_h2d, hipStreamNonBlocking));
@@ -667,7 +671,7 @@ void Ens::create(Ctx* c, const Mesh* m, const Problem& prob, int member_pad)
     iters_dev.alloc(bg, (size_t)MB * ns_steps * 2 * 4);
     NLTH_HIP(hipMemsetAsync(iters_dev.p, 0, iters_dev.bytes, s));
     partial.alloc(bg, (size_t)3 * kMaxPartialBlocks * MB * 8);
-    // CG scalars: 12 double arrays and 9 int arrays of MB, plus any_active
+    // CG scalars: 12 double arrays and 9 int arrays of MB
     scal.alloc(bg, (size_t)MB * (12 * 8 + 9 * 4) + 64);
     NLTH_HIP(hipMemsetAsync(scal.p, 0, scal.bytes, s));
     double* dptr = scal.as<double>();
@@ -677,7 +681,7 @@ void Ens::create(Ctx* c, const Mesh* m, const Problem& prob, int member_pad)
     int* iptr = (int*)(dptr + 12 * MB);
     cs.active = iptr; cs.iters = iptr + MB; cs.status = iptr + 2 * MB; cs.inner_active = iptr + 3 * MB;
     cs.inner_iters = iptr + 4 * MB; cs.inner_total = iptr + 5 * MB;
-    cs.any_active = iptr + 8 * MB;
+    NLTH_HIP(hipHostMalloc((void**)&h_flags, sizeof(int) * MB, hipHostMallocDefault));
     member_step.alloc(bg, (size_t)MB * 4);
     stepping.alloc(bg, (size_t)MB * 4);
     cs.stepping = stepping.as<int>();
@@ -706,24 +710,12 @@ void Ens::destroy()
     pending.clear();
     for (auto e : ev_pool) (void)hipEventDestroy(e);
     ev_pool.clear();
+    if (h_flags) (void)hipHostFree(h_flags);
+    h_flags = nullptr;
     if (ev_copy0) (void)hipEventDestroy(ev_copy0);
     if (ev_copy1) (void)hipEventDestroy(ev_copy1);
     ev_copy0 = ev_copy1 = nullptr;
     ctx = nullptr;
-}
-
-void Ens::dots(int nd, const double* a0, const double* b0, const double* a1, const double* b1, const double* a2,
-               const double* b2, int& nblk)
-{
-    launch_dots(s, nd, a0, b0, a1, b1, a2, b2, ndof, MB, partial.as<double>(), &nblk);
-}
-
-int Ens::read_any_active()
-{
-    int h = 0;
-    NLTH_HIP(hipMemcpyAsync(&h, cs.any_active, sizeof(int), hipMemcpyDeviceToHost, s));
-    NLTH_HIP(hipStreamSynchronize(s));
-    return h;
 }
 
 void Ens::ebe(OpMode mode, const double* x1, const double* x2, double* y, const int* act)
@@ -774,41 +766,66 @@ void Ens::build_diag()
                        P.precision == NLTH_MIXED ? pinv32.as<float>() : nullptr);
 }
 
+void Ens::dots(int nd, const double* a0, const double* b0, const double* a1, const double* b1, const double* a2,
+               const double* b2, int& nblk)
+{
+    launch_dotsv<double>(s, nd, a0, b0, a1, b1, a2, b2, ndof, MB, nm, nullptr, partial.as<double>(), &nblk);
+}
+
+// any member still iterating?  (one small device-to-host copy of the flags)
+int Ens::read_any_active(const int* flags)
+{
+    NLTH_HIP(hipMemcpyAsync(h_flags, flags, sizeof(int) * nm, hipMemcpyDeviceToHost, s));
+    NLTH_HIP(hipStreamSynchronize(s));
+    for (int m = 0; m < nm; ++m)
+        if (h_flags[m]) return 1;
+    return 0;
+}
+
+void Ens::fin(FinalizeStage st, int nd, int nblk, double tol2, int maxit)
+{
+    launch_finalize(s, st, nd, MB, nm, partial.as<double>(), nblk, cs, tol2, maxit);
+}
+
+void Ens::apply_A64(const double* x, double* y, const int* act)
+{
+    ebe(OP_A, x, nullptr, y, act);
+    launch_dashpot<double>(s, mesh->dev(), MB, nm, mat.as<double>(), P.nl, 2.0 / P.dt, x, y, nullptr, act);
+}
+
+// FP64 block-Jacobi PCG (Section 2.2): x0 = previous increment
 void Ens::solve_pcg()
 {
     const long n = ndof;
     int nblk;
     double* x = du.as<double>();
     const int* st = stepping.as<int>();
-    const double tol2 = P.cg_tol * P.cg_tol;
-    launch_fill(s, Ap.as<double>(), 0.0, n * MB);
-    ebe(OP_A, x, nullptr, Ap.as<double>(), st);
-    launch_dashpot<double>(s, mesh->dev(), MB, nm, mat.as<double>(), P.nl, 2.0 / P.dt, x, Ap.as<double>(), nullptr, st);
-    launch_pcg_start(s, mesh->nn, MB, nm, b.as<double>(), Ap.as<double>(), pinv.as<double>(), r.as<double>(),
-                     z.as<double>(), p.as<double>(), st);
-    dots(3, b.as<double>(), b.as<double>(), r.as<double>(), r.as<double>(), r.as<double>(), z.as<double>(), nblk);
-    launch_finalize(s, FIN_START, MB, nm, partial.as<double>(), nblk, cs, tol2, P.cg_maxit);
-    launch_zero_inactive_start(s, n, MB, nm, x, cs.bb, st);
-    if (!read_any_active()) return;
     const int* act = cs.active;
+    const double tol2 = P.cg_tol * P.cg_tol;
+    double* pd = partial.as<double>();
+    launch_fill(s, Ap.as<double>(), 0.0, n * MB);
+    apply_A64(x, Ap.as<double>(), st);
+    launch_pcg_start(s, mesh->nn, MB, nm, b.as<double>(), Ap.as<double>(), pinv.as<double>(), r.as<double>(),
+                     z.as<double>(), p.as<double>(), st, pd, &nblk);
+    fin(FIN_START, 3, nblk, tol2, P.cg_maxit);
+    launch_zero_if_b0(s, n, MB, nm, x, cs.bb, st);
+    launch_p_update<double>(s, n, MB, nm, z.as<double>(), p.as<double>(), nullptr, nullptr, Ap.as<double>());
+    if (!read_any_active(act)) return;
     for (;;) {
         for (int k = 0; k < check_every; ++k) {
-            launch_fill(s, Ap.as<double>(), 0.0, n * MB);
-            ebe(OP_A, p.as<double>(), nullptr, Ap.as<double>(), act);
-            launch_dashpot<double>(s, mesh->dev(), MB, nm, mat.as<double>(), P.nl, 2.0 / P.dt, p.as<double>(),
-                                   Ap.as<double>(), nullptr, act);
+            apply_A64(p.as<double>(), Ap.as<double>(), act);
             dots(1, p.as<double>(), Ap.as<double>(), nullptr, nullptr, nullptr, nullptr, nblk);
-            launch_finalize(s, FIN_ALPHA, MB, nm, partial.as<double>(), nblk, cs, tol2, P.cg_maxit);
-            launch_pcg_update(s, mesh->nn, MB, nm, x, r.as<double>(), z.as<double>(), p.as<double>(),
-                              Ap.as<double>(), pinv.as<double>(), cs.alpha, act);
-            dots(2, r.as<double>(), r.as<double>(), r.as<double>(), z.as<double>(), nullptr, nullptr, nblk);
-            launch_finalize(s, FIN_BETA, MB, nm, partial.as<double>(), nblk, cs, tol2, P.cg_maxit);
-            launch_axpby_p(s, n, MB, nm, z.as<double>(), p.as<double>(), cs.beta, act);
+            fin(FIN_ALPHA, 1, nblk, tol2, P.cg_maxit);
+            launch_pcg_update(s, mesh->nn, MB, nm, x, r.as<double>(), z.as<double>(), p.as<double>(), Ap.as<double>(),
+                              pinv.as<double>(), cs.alpha, act, pd, &nblk);
+            fin(FIN_BETA, 2, nblk, tol2, P.cg_maxit);
+            launch_p_update<double>(s, n, MB, nm, z.as<double>(), p.as<double>(), cs.beta, act, Ap.as<double>());
         }
-        if (!read_any_active()) break;
+        if (!read_any_active(act)) break;
     }
 }
 
+// inner FP32 block-Jacobi PCG: z ~ A^-1 r to inner_tol relative (preconditioner)
 void Ens::inner_solve()
 {
     const long n = ndof;
@@ -816,32 +833,29 @@ void Ens::inner_solve()
     const int* act = cs.active;
     const int* iact = cs.inner_active;
     const double tol2 = P.inner_tol * P.inner_tol;
+    double* pd = partial.as<double>();
     launch_inner_start(s, mesh->nn, MB, nm, r.as<double>(), pinv32.as<float>(), ir.as<float>(), iz.as<float>(),
-                       ip.as<float>(), iw.as<float>(), act);
-    launch_dots32(s, 2, ir.as<float>(), ir.as<float>(), ir.as<float>(), iw.as<float>(), n, MB, partial.as<double>(),
-                  &nblk);
-    launch_finalize(s, FIN_IN_START, MB, nm, partial.as<double>(), nblk, cs, tol2, P.inner_maxit);
+                       ip.as<float>(), iw.as<float>(), iAp.as<float>(), act, pd, &nblk);
+    fin(FIN_IN_START, 2, nblk, tol2, P.inner_maxit);
     int done_iters = 0;
     while (done_iters < P.inner_maxit) {
         const int chunk = std::min(check_every, P.inner_maxit - done_iters);
         for (int k = 0; k < chunk; ++k) {
-            launch_fill32(s, iAp.as<float>(), 0.0f, n * MB);
             ebe32(ip.as<float>(), iAp.as<float>(), iact);
-            launch_dots32(s, 1, ip.as<float>(), iAp.as<float>(), nullptr, nullptr, n, MB, partial.as<double>(), &nblk);
-            launch_finalize(s, FIN_IN_ALPHA, MB, nm, partial.as<double>(), nblk, cs, tol2, P.inner_maxit);
+            launch_dotsv<float>(s, 1, ip.as<float>(), iAp.as<float>(), nullptr, nullptr, nullptr, nullptr, n, MB, nm,
+                                iact, pd, &nblk);
+            fin(FIN_IN_ALPHA, 1, nblk, tol2, P.inner_maxit);
             launch_inner_update(s, mesh->nn, MB, nm, iz.as<float>(), ir.as<float>(), iw.as<float>(), ip.as<float>(),
-                                iAp.as<float>(), pinv32.as<float>(), cs.ialpha, iact);
-            launch_dots32(s, 2, ir.as<float>(), ir.as<float>(), ir.as<float>(), iw.as<float>(), n, MB,
-                          partial.as<double>(), &nblk);
-            launch_finalize(s, FIN_IN_BETA, MB, nm, partial.as<double>(), nblk, cs, tol2, P.inner_maxit);
-            launch_inner_p(s, n, MB, nm, iw.as<float>(), ip.as<float>(), cs.ibeta, iact);
+                                iAp.as<float>(), pinv32.as<float>(), cs.ialpha, iact, pd, &nblk);
+            fin(FIN_IN_BETA, 2, nblk, tol2, P.inner_maxit);
+            launch_p_update<float>(s, n, MB, nm, iw.as<float>(), ip.as<float>(), cs.ibeta, iact, iAp.as<float>());
         }
         done_iters += chunk;
-        if (!read_any_active()) break;
+        if (!read_any_active(iact)) break;
     }
-    launch_inner_out(s, n, MB, nm, iz.as<float>(), z.as<double>(), act);
 }
 
+// FP64 flexible CG (Polak-Ribiere beta) preconditioned by the inner FP32 PCG
 void Ens::solve_fcg()
 {
     const long n = ndof;
@@ -850,34 +864,30 @@ void Ens::solve_fcg()
     const int* st = stepping.as<int>();
     const int* act = cs.active;
     const double tol2 = P.cg_tol * P.cg_tol;
+    double* pd = partial.as<double>();
     launch_fill(s, Ap.as<double>(), 0.0, n * MB);
-    ebe(OP_A, x, nullptr, Ap.as<double>(), st);
-    launch_dashpot<double>(s, mesh->dev(), MB, nm, mat.as<double>(), P.nl, 2.0 / P.dt, x, Ap.as<double>(), nullptr, st);
+    apply_A64(x, Ap.as<double>(), st);
     launch_pcg_start(s, mesh->nn, MB, nm, b.as<double>(), Ap.as<double>(), pinv.as<double>(), r.as<double>(),
-                     z.as<double>(), p.as<double>(), st);
-    dots(2, b.as<double>(), b.as<double>(), r.as<double>(), r.as<double>(), nullptr, nullptr, nblk);
-    launch_finalize(s, FIN_FCG_START, MB, nm, partial.as<double>(), nblk, cs, tol2, P.cg_maxit);
-    launch_zero_inactive_start(s, n, MB, nm, x, cs.bb, st);
-    if (!read_any_active()) return;
+                     z.as<double>(), p.as<double>(), st, pd, &nblk);
+    fin(FIN_FCG_START, 2, nblk, tol2, P.cg_maxit);
+    launch_zero_if_b0(s, n, MB, nm, x, cs.bb, st);
+    if (!read_any_active(act)) return;
     inner_solve();
-    launch_copy_p(s, n, MB, nm, z.as<double>(), p.as<double>(), act);
-    dots(1, r.as<double>(), z.as<double>(), nullptr, nullptr, nullptr, nullptr, nblk);
-    launch_finalize(s, FIN_FCG_RZ, MB, nm, partial.as<double>(), nblk, cs, tol2, P.cg_maxit);
+    launch_inner_out(s, n, MB, nm, iz.as<float>(), z.as<double>(), Ap.as<double>(), r.as<double>(), act, pd, &nblk);
+    fin(FIN_FCG_RZ, 2, nblk, tol2, P.cg_maxit);
+    launch_p_update<double>(s, n, MB, nm, z.as<double>(), p.as<double>(), nullptr, act, Ap.as<double>());
     for (;;) {
-        launch_fill(s, Ap.as<double>(), 0.0, n * MB);
-        ebe(OP_A, p.as<double>(), nullptr, Ap.as<double>(), act);
-        launch_dashpot<double>(s, mesh->dev(), MB, nm, mat.as<double>(), P.nl, 2.0 / P.dt, p.as<double>(),
-                               Ap.as<double>(), nullptr, act);
+        apply_A64(p.as<double>(), Ap.as<double>(), act);
         dots(1, p.as<double>(), Ap.as<double>(), nullptr, nullptr, nullptr, nullptr, nblk);
-        launch_finalize(s, FIN_ALPHA, MB, nm, partial.as<double>(), nblk, cs, tol2, P.cg_maxit);
-        launch_xr_update(s, n, MB, nm, x, r.as<double>(), p.as<double>(), Ap.as<double>(), cs.alpha, act);
-        dots(1, r.as<double>(), r.as<double>(), nullptr, nullptr, nullptr, nullptr, nblk);
-        launch_finalize(s, FIN_FCG_RR, MB, nm, partial.as<double>(), nblk, cs, tol2, P.cg_maxit);
-        if (!read_any_active()) break;
+        fin(FIN_ALPHA, 1, nblk, tol2, P.cg_maxit);
+        launch_xr_update(s, n, MB, nm, x, r.as<double>(), p.as<double>(), Ap.as<double>(), cs.alpha, act, pd, &nblk);
+        fin(FIN_FCG_RR, 1, nblk, tol2, P.cg_maxit);
+        if (!read_any_active(act)) break;
         inner_solve();
-        dots(2, z.as<double>(), Ap.as<double>(), z.as<double>(), r.as<double>(), nullptr, nullptr, nblk);
-        launch_finalize(s, FIN_FCG_BETA, MB, nm, partial.as<double>(), nblk, cs, tol2, P.cg_maxit);
-        launch_axpby_p(s, n, MB, nm, z.as<double>(), p.as<double>(), cs.beta, act);
+        launch_inner_out(s, n, MB, nm, iz.as<float>(), z.as<double>(), Ap.as<double>(), r.as<double>(), act, pd,
+                         &nblk);
+        fin(FIN_FCG_BETA, 2, nblk, tol2, P.cg_maxit);
+        launch_p_update<double>(s, n, MB, nm, z.as<double>(), p.as<double>(), cs.beta, act, Ap.as<double>());
     }
 }
 
@@ -888,7 +898,7 @@ void Ens::law_phase()
     if (!paged) {
         hipEvent_t t0;
         tstart(t0);
-        launch_law(s, dm, MB, nm, 0, mesh->ne, mat.as<double>(), P.nl, nonlinear.as<int>(), P.ns, dirs.as<double>(),
+        launch_law(s, dm, MB, nm, 0, mesh->ne, ne_pad, mat.as<double>(), P.nl, nonlinear.as<int>(), P.ns, dirs.as<double>(),
                    w.as<double>(), du.as<double>(), theta.p, D64.as<double>(), D32.as<float>(), h.as<double>(),
                    stepping.as<int>());
         tstop(t0, &pc_law, (int64_t)mesh->ne * nm);
@@ -899,7 +909,7 @@ void Ens::law_phase()
     for (int cix = 0; cix < nchunks; ++cix) {
         const int slot = cix % ring;
         char* dslot = (char*)theta.p + (size_t)slot * chunk_elems * per_elem;
-        const size_t bytes = (size_t)chunk_ec[cix] * per_elem;
+        const size_t bytes = (size_t)chunk_ecp[cix] * per_elem;
         if (!prefetched[cix]) {
             if (slot_chunk[slot] >= 0) NLTH_HIP(hipStreamWaitEvent(s_h2d, ev_d2h[slot], 0));
             NLTH_HIP(hipMemcpyAsync(dslot, (char*)theta_host.p + chunk_off[cix], bytes, hipMemcpyHostToDevice, s_h2d));
@@ -911,7 +921,7 @@ void Ens::law_phase()
         NLTH_HIP(hipStreamWaitEvent(s, ev_h2d[slot], 0));
         hipEvent_t t0;
         tstart(t0);
-        launch_law(s, dm, MB, nm, chunk_e0[cix], chunk_ec[cix], mat.as<double>(), P.nl, nonlinear.as<int>(), P.ns,
+        launch_law(s, dm, MB, nm, chunk_e0[cix], chunk_ec[cix], chunk_ecp[cix], mat.as<double>(), P.nl, nonlinear.as<int>(), P.ns,
                    dirs.as<double>(), w.as<double>(), du.as<double>(), dslot, D64.as<double>(), D32.as<float>(),
                    h.as<double>(), stepping.as<int>());
         tstop(t0, &pc_law, (int64_t)chunk_ec[cix] * nm);
@@ -932,7 +942,7 @@ void Ens::prefetch_next()
     for (int cix = 0; cix < std::min(ring - 1, nchunks); ++cix) {
         const int slot = cix % ring;
         char* dslot = (char*)theta.p + (size_t)slot * chunk_elems * per_elem;
-        const size_t bytes = (size_t)chunk_ec[cix] * per_elem;
+        const size_t bytes = (size_t)chunk_ecp[cix] * per_elem;
         // the slot's previous chunk must be back on the host; chunk cix's own
         // write-back precedes that one on the D2H stream
         NLTH_HIP(hipStreamWaitEvent(s_h2d, ev_d2h[slot], 0));
@@ -1293,11 +1303,13 @@ int nlth_apply_operator(nlth_ctx* ctx, const nlth_mesh* mesh, const nlth_problem
     e->create(ctx, mesh, P);
     const int ne = mesh->ne, nn = mesh->nn;
     // D and h into the sorted, member-innermost layout (MB = 1)
-    std::vector<double> Dd((size_t)ne * 84), hd(ne, 0.0);
+    const int EB = e->EB;  // MB = 1
+    std::vector<double> Dd((size_t)e->ne_pad * 84, 0.0), hd(ne, 0.0);
     for (int pos = 0; pos < ne; ++pos) {
         int e0 = mesh->order[pos];
         for (int j = 0; j < 4; ++j)
-            for (int k = 0; k < 21; ++k) Dd[((size_t)(j * 21 + k)) * ne + pos] = D_ip[(size_t)e0 * 84 + j * 21 + k];
+            for (int k = 0; k < 21; ++k)
+                Dd[((size_t)(pos / EB) * 84 + j * 21 + k) * EB + pos % EB] = D_ip[(size_t)e0 * 84 + j * 21 + k];
         if (hh) hd[pos] = hh[e0];
     }
     std::vector<float> Df(Dd.begin(), Dd.end());

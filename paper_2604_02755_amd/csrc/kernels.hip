@@ -146,8 +146,45 @@ void launch_cast32(hipStream_t s, const double* a, float* b, long n)
 // ---------------------------------------------------------------------------
 // element-by-element operator (Eq. 1 left-hand side, Eq. 2 stiffness)
 // ---------------------------------------------------------------------------
+//
+// Per (element, member): gather the 10 nodal displacements, add the mass
+// term (consistent P2 mass applied through corner and edge sums), then the
+// stiffness term of Eq. 2 with the 4-point rule.  Straight-sided tets make the
+// shape-function gradients linear in the barycentrics, so the strain at the
+// four points is a combination of four per-element 6-vectors E_k and the
+// point forces fold back onto the nodes the same way; D_j is streamed once.
 
-template <typename T, int MODE>
+// Voigt symmetric part of u (x) g  (F_cd = u_c g_d, engineering shear)
+template <typename T>
+__device__ __forceinline__ void vsym_acc(const T u[3], const T g[3], T s, T o[6])
+{
+    o[0] += s * u[0] * g[0];
+    o[1] += s * u[1] * g[1];
+    o[2] += s * u[2] * g[2];
+    o[3] += s * (u[0] * g[1] + u[1] * g[0]);
+    o[4] += s * (u[1] * g[2] + u[2] * g[1]);
+    o[5] += s * (u[2] * g[0] + u[0] * g[2]);
+}
+
+// f += s * sigma . g  (sigma in Voigt order xx, yy, zz, xy, yz, zx)
+template <typename T>
+__device__ __forceinline__ void tdot_acc(const T sg[6], const T g[3], T s, T f[3])
+{
+    f[0] += s * (sg[0] * g[0] + sg[3] * g[1] + sg[5] * g[2]);
+    f[1] += s * (sg[3] * g[0] + sg[1] * g[1] + sg[4] * g[2]);
+    f[2] += s * (sg[5] * g[0] + sg[4] * g[1] + sg[2] * g[2]);
+}
+
+// index of D(e, j, k) for member m: elements in blocks of EB so that a
+// wavefront's lanes (EB elements x MB members) read contiguous memory
+__device__ __forceinline__ long d_index(long e, int j, int k, int MB, int EB, int m)
+{
+    return (((e / EB) * 84 + j * 21 + k) * EB + e % EB) * (long)MB + m;
+}
+
+constexpr int kEdgeOpp[6] = {5, 3, 4, 1, 2, 0};  // edge opposite each edge
+
+template <typename T, int MODE, bool WAVE_ELEM>
 __global__ __launch_bounds__(256) void k_ebe(DevMesh M, int MB, int nm, int e0, int e1,
                                             const T* __restrict__ D, const double* __restrict__ h,
                                             const double* __restrict__ mat, StepConst sc,
@@ -156,9 +193,11 @@ __global__ __launch_bounds__(256) void k_ebe(DevMesh M, int MB, int nm, int e0, 
 {
     const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
     const int m = (int)(t % MB);
-    const long e = e0 + t / MB;
+    long e = e0 + t / MB;
+    if (WAVE_ELEM) e = __builtin_amdgcn_readfirstlane((int)e);  // one element per wavefront
     if (e >= e1 || m >= nm) return;
     if (active && !active[m]) return;
+    const int EB = MB >= 64 ? 1 : 64 / MB;
     const long ne = M.ne;
     const T* geo = geo_of<T>(M);
     T gL[4][3];
@@ -187,59 +226,99 @@ __global__ __launch_bounds__(256) void k_ebe(DevMesh M, int MB, int nm, int e0, 
         sk = (T)(sc.bhat * he);
         cv = (T)(4.0 / dt + sc.ahat * he);
     }
-    T xk[10][3], xm[10][3];
-#pragma unroll
-    for (int n = 0; n < 10; ++n)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const long idx = ((long)nodes[n] * 3 + c) * MB + m;
-            T v1 = x1[idx];
-            xk[n][c] = v1;
-            if (MODE == OP_RHS) xm[n][c] = x2[idx] + cv * v1;
-            else xm[n][c] = v1;
-        }
+    T xk[10][3];
     T f[10][3];
+    // ---- mass: consistent P2 mass applied through corner/edge sums
 #pragma unroll
-    for (int n = 0; n < 10; ++n)
+    for (int c = 0; c < 3; ++c) {
+        T xm[10];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) f[n][c] = 0;
-
+        for (int n = 0; n < 10; ++n) {
+            const long idx = ((long)nodes[n] * 3 + c) * MB + m;
+            const T v1 = x1[idx];
+            xk[n][c] = v1;
+            xm[n] = (MODE == OP_RHS) ? x2[idx] + cv * v1 : v1;
+        }
+        if (MODE == OP_K) {
+#pragma unroll
+            for (int n = 0; n < 10; ++n) f[n][c] = 0;
+        } else {
+            constexpr int E[6][2] = {{0, 1}, {1, 2}, {2, 0}, {0, 3}, {1, 3}, {2, 3}};
+            const T Sc = xm[0] + xm[1] + xm[2] + xm[3];
+            const T Se = xm[4] + xm[5] + xm[6] + xm[7] + xm[8] + xm[9];
+            const T s420 = sm * (T)(1.0 / 420.0);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                T A = 0;
+#pragma unroll
+                for (int q = 0; q < 6; ++q)
+                    if (E[q][0] == i || E[q][1] == i) A += xm[4 + q];
+                f[i][c] = s420 * ((T)5 * xm[i] + Sc + (T)2 * A - (T)6 * Se);
+            }
+#pragma unroll
+            for (int q = 0; q < 6; ++q)
+                f[4 + q][c] = s420 * ((T)2 * (xm[E[q][0]] + xm[E[q][1]]) - (T)6 * Sc + (T)16 * xm[4 + q] +
+                                      (T)16 * Se - (T)8 * xm[4 + kEdgeOpp[q]]);
+        }
+    }
+    // ---- stiffness (Eq. 2)
     if (MODE != OP_M && sk != (T)0) {
+        constexpr int E[6][2] = {{0, 1}, {1, 2}, {2, 0}, {0, 3}, {1, 3}, {2, 3}};
+        // E_k = voigt(G_k), G_k = 4 x_k gL_k^T - H + 4 sum_{edges (k,o)} x_ko gL_o^T
+        T Ek[4][6], H[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) Ek[k][q] = 0;
+            vsym_acc<T>(xk[k], gL[k], (T)1, H);
+            vsym_acc<T>(xk[k], gL[k], (T)4, Ek[k]);
+        }
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            vsym_acc<T>(xk[4 + q], gL[E[q][1]], (T)4, Ek[E[q][0]]);
+            vsym_acc<T>(xk[4 + q], gL[E[q][0]], (T)4, Ek[E[q][1]]);
+        }
+        T S[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) Ek[k][q] -= H[q];
+            S[q] = Ek[0][q] + Ek[1][q] + Ek[2][q] + Ek[3][q];
+        }
         const T w = sk * vol * (T)0.25;
-        const T* Dp = D + e * MB + m;
-        const long ds = ne * MB;
+        const T c1 = (T)(QA_ - QB_);
+        T ST[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            T G[10][3], eps[6], d[21], s[6];
-            shape_grads<T>(j, gL, G);
-            strain<T>(G, xk, eps);
+            T eps[6], sg[6];
 #pragma unroll
-            for (int k = 0; k < 21; ++k) d[k] = Dp[(long)(j * 21 + k) * ds];
+            for (int q = 0; q < 6; ++q) eps[q] = (T)QB_ * S[q] + c1 * Ek[j][q];
+            T d[21];
+#pragma unroll
+            for (int k = 0; k < 21; ++k) d[k] = __builtin_nontemporal_load(&D[d_index(e, j, k, MB, EB, m)]);
 #pragma unroll
             for (int r = 0; r < 6; ++r) {
                 T a = 0;
 #pragma unroll
                 for (int c = 0; c < 6; ++c) a += d[sym6(r, c)] * eps[c];
-                s[r] = a * w;
+                sg[r] = a * w;
+                ST[r] += sg[r];
             }
+            // point-j part of the nodal forces
 #pragma unroll
-            for (int n = 0; n < 10; ++n) {
-                f[n][0] += G[n][0] * s[0] + G[n][1] * s[3] + G[n][2] * s[5];
-                f[n][1] += G[n][1] * s[1] + G[n][0] * s[3] + G[n][2] * s[4];
-                f[n][2] += G[n][2] * s[2] + G[n][1] * s[4] + G[n][0] * s[5];
+            for (int i = 0; i < 4; ++i) tdot_acc<T>(sg, gL[i], i == j ? (T)3 * c1 : -c1, f[i]);
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                if (E[q][0] == j) tdot_acc<T>(sg, gL[E[q][1]], (T)4 * c1, f[4 + q]);
+                if (E[q][1] == j) tdot_acc<T>(sg, gL[E[q][0]], (T)4 * c1, f[4 + q]);
             }
         }
-    }
-    if (MODE != OP_K) {
 #pragma unroll
-        for (int a = 0; a < 10; ++a)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                T acc = 0;
-#pragma unroll
-                for (int b = 0; b < 10; ++b) acc += (T)mass_ref(a, b) * xm[b][c];
-                f[a][c] += sm * acc;
-            }
+        for (int q = 0; q < 6; ++q) {
+            T g[3] = {gL[E[q][0]][0] + gL[E[q][1]][0], gL[E[q][0]][1] + gL[E[q][1]][1],
+                      gL[E[q][0]][2] + gL[E[q][1]][2]};
+            tdot_acc<T>(ST, g, (T)(4.0 * QB_), f[4 + q]);
+        }
     }
 #pragma unroll
     for (int n = 0; n < 10; ++n)
@@ -250,6 +329,17 @@ __global__ __launch_bounds__(256) void k_ebe(DevMesh M, int MB, int nm, int e0, 
         }
 }
 
+template <typename T, int MODE>
+static void ebe_dispatch(hipStream_t s, dim3 g, const DevMesh& M, int MB, int nm, int e0, int e1, const T* D,
+                         const double* h, const double* mat, StepConst sc, const T* x1, const T* x2, T* y,
+                         const int* active)
+{
+    if (MB >= 64)
+        hipLaunchKernelGGL((k_ebe<T, MODE, true>), g, dim3(256), 0, s, M, MB, nm, e0, e1, D, h, mat, sc, x1, x2, y, active);
+    else
+        hipLaunchKernelGGL((k_ebe<T, MODE, false>), g, dim3(256), 0, s, M, MB, nm, e0, e1, D, h, mat, sc, x1, x2, y, active);
+}
+
 template <typename T>
 void launch_ebe(hipStream_t s, OpMode mode, const DevMesh& M, int MB, int nm, int e0, int e1, const T* D,
                 const double* h, const double* mat, int, StepConst sc, const T* x1, const T* x2, T* y,
@@ -257,12 +347,12 @@ void launch_ebe(hipStream_t s, OpMode mode, const DevMesh& M, int MB, int nm, in
 {
     long n = (long)(e1 - e0) * MB;
     if (n <= 0) return;
-    dim3 g(nblocks(n)), b(256);
+    dim3 g(nblocks(n));
     switch (mode) {
-    case OP_A: hipLaunchKernelGGL((k_ebe<T, OP_A>), g, b, 0, s, M, MB, nm, e0, e1, D, h, mat, sc, x1, x2, y, active); break;
-    case OP_K: hipLaunchKernelGGL((k_ebe<T, OP_K>), g, b, 0, s, M, MB, nm, e0, e1, D, h, mat, sc, x1, x2, y, active); break;
-    case OP_M: hipLaunchKernelGGL((k_ebe<T, OP_M>), g, b, 0, s, M, MB, nm, e0, e1, D, h, mat, sc, x1, x2, y, active); break;
-    case OP_RHS: hipLaunchKernelGGL((k_ebe<T, OP_RHS>), g, b, 0, s, M, MB, nm, e0, e1, D, h, mat, sc, x1, x2, y, active); break;
+    case OP_A: ebe_dispatch<T, OP_A>(s, g, M, MB, nm, e0, e1, D, h, mat, sc, x1, x2, y, active); break;
+    case OP_K: ebe_dispatch<T, OP_K>(s, g, M, MB, nm, e0, e1, D, h, mat, sc, x1, x2, y, active); break;
+    case OP_M: ebe_dispatch<T, OP_M>(s, g, M, MB, nm, e0, e1, D, h, mat, sc, x1, x2, y, active); break;
+    case OP_RHS: ebe_dispatch<T, OP_RHS>(s, g, M, MB, nm, e0, e1, D, h, mat, sc, x1, x2, y, active); break;
     }
 }
 template void launch_ebe<double>(hipStream_t, OpMode, const DevMesh&, int, int, int, int, const double*,
@@ -356,12 +446,12 @@ __global__ __launch_bounds__(256) void k_diag(DevMesh M, int MB, int nm, int e0,
         double md = sm * mass_ref(n, n);
         blk[n][0] = md; blk[n][1] = 0; blk[n][2] = 0; blk[n][3] = md; blk[n][4] = 0; blk[n][5] = md;
     }
-    const double* Dp = D + e * MB + m;
-    const long ds = ne * MB;
+    const int EB = MB >= 64 ? 1 : 64 / MB;
+#pragma unroll 1
     for (int j = 0; j < 4; ++j) {
         double G[10][3], d[21];
         shape_grads<double>(j, gL, G);
-        for (int k = 0; k < 21; ++k) d[k] = Dp[(long)(j * 21 + k) * ds];
+        for (int k = 0; k < 21; ++k) d[k] = D[d_index(e, j, k, MB, EB, m)];
         for (int n = 0; n < 10; ++n) {
             const double gx = G[n][0], gy = G[n][1], gz = G[n][2];
             // columns of B for this node (6 strains x 3 displacement components)
@@ -477,6 +567,7 @@ __device__ __forceinline__ double ro_inverse(double e, double beta)
     const double a = fabs(e);
     if (a == 0.0) return 0.0;
     double s = fmin(a, pow(a / exp2(beta), 1.0 / (1.0 + beta)));
+#pragma unroll 1
     for (int it = 0; it < 60; ++it) {
         const double p = pow(2.0 * s, beta);
         const double f = s * (1.0 + p) - a;
@@ -495,35 +586,46 @@ __device__ __forceinline__ double skeleton_tau(double g, const SpringPar& p)
     return p.G0 * p.gref * ro_inverse(g / p.gref, p.beta);
 }
 
-struct ThetaPtrs {
-    double *gp, *gr, *tr, *gm;
-    int *dir, *skel;
+// Law state of a chunk of ecp elements (ecp a multiple of EB): four FP64
+// fields (gp, gr, tr, gm) then two int32 fields (dir, skel); within a field,
+// element blocks of EB, then spring, point, element-in-block, member.
+struct ThetaView {
+    double* d;
+    int* i;
+    long field_n;  // entries per field = ecp * 4 * ns * MB
+    int ns, MB, EB;
+    __device__ __forceinline__ long at(long el, int s, int j, int m) const
+    {
+        return (((el / EB) * ns + s) * 4 + j) * (long)EB * MB * 1 + (el % EB) * MB + m;
+    }
 };
 
-__device__ __forceinline__ ThetaPtrs theta_fields(void* base, long ec, int ns, int MB)
+__device__ __forceinline__ ThetaView theta_view(void* base, long ecp, int ns, int MB)
 {
-    const long n = ec * 4 * (long)ns * MB;
-    ThetaPtrs t;
-    double* d = (double*)base;
-    t.gp = d; t.gr = d + n; t.tr = d + 2 * n; t.gm = d + 3 * n;
-    int* iflag = (int*)(d + 4 * n);
-    t.dir = iflag; t.skel = iflag + n;
-    return t;
+    ThetaView v;
+    v.field_n = ecp * 4 * (long)ns * MB;
+    v.d = (double*)base;
+    v.i = (int*)(v.d + 4 * v.field_n);
+    v.ns = ns;
+    v.MB = MB;
+    v.EB = MB >= 64 ? 1 : 64 / MB;
+    return v;
 }
 
-__global__ void k_theta_init(void* base, long ec, int ns, int MB)
+__global__ void k_theta_init(void* base, long ecp, int ns, int MB)
 {
-    const long n = ec * 4 * (long)ns * MB;
+    ThetaView v = theta_view(base, ecp, ns, MB);
     const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    ThetaPtrs t = theta_fields(base, ec, ns, MB);
-    t.gp[i] = 0; t.gr[i] = 0; t.tr[i] = 0; t.gm[i] = 0; t.dir[i] = 0; t.skel[i] = 1;
+    if (i >= v.field_n) return;
+    for (int f = 0; f < 4; ++f) v.d[f * v.field_n + i] = 0.0;
+    v.i[i] = 0;              // dir: no loading yet
+    v.i[v.field_n + i] = 1;  // skel: on the skeleton
 }
 
-void launch_theta_init(hipStream_t s, void* base, long ec, int ns, int MB)
+void launch_theta_init(hipStream_t s, void* base, long ecp, int ns, int MB)
 {
-    long n = ec * 4 * (long)ns * MB;
-    if (n > 0) hipLaunchKernelGGL(k_theta_init, dim3(nblocks(n)), dim3(256), 0, s, base, ec, ns, MB);
+    long n = ecp * 4 * (long)ns * MB;
+    if (n > 0) hipLaunchKernelGGL(k_theta_init, dim3(nblocks(n)), dim3(256), 0, s, base, ecp, ns, MB);
 }
 
 // D of a point from the spring tangents: Kb m m^T + sum c_k G_k n_k n_k^T
@@ -535,7 +637,7 @@ __global__ void k_law_init(DevMesh M, int MB, int nm, const double* __restrict__
     const int m = (int)(t % MB);
     const long e = t / MB;
     if (e >= M.ne || m >= nm) return;
-    const long ne = M.ne;
+    const int EB = MB >= 64 ? 1 : 64 / MB;
     const int l = M.layer[e];
     const double G0 = matv(mat, l, MAT_G0, MB, m), Kb = matv(mat, l, MAT_KB, MB, m);
     double d[21];
@@ -550,7 +652,7 @@ __global__ void k_law_init(DevMesh M, int MB, int nm, const double* __restrict__
         for (int q = r; q < 3; ++q) d[sym6(r, q)] += Kb;
     for (int j = 0; j < 4; ++j)
         for (int k = 0; k < 21; ++k) {
-            const long idx = (((long)j * 21 + k) * ne + e) * MB + m;
+            const long idx = d_index(e, j, k, MB, EB, m);
             D[idx] = d[k];
             D32[idx] = (float)d[k];
         }
@@ -564,7 +666,10 @@ void launch_law_init(hipStream_t s, const DevMesh& M, int MB, int nm, const doub
     if (n > 0) hipLaunchKernelGGL(k_law_init, dim3(nblocks(n)), dim3(256), 0, s, M, MB, nm, mat, ns, dirs, w, D, D32, h);
 }
 
-__global__ __launch_bounds__(256) void k_law(DevMesh M, int MB, int nm, int e0, int ec,
+// One lane per (element, member) of the chunk [e0, e0 + ec): strain
+// increments at the four points from du, then every spring's Masing/RO update
+// and tangent, D = Kb m m^T + sum c_k G_t n n^T, and the element damping h.
+__global__ __launch_bounds__(256) void k_law(DevMesh M, int MB, int nm, int e0, int ec, long ecp,
                                             const double* __restrict__ mat, const int* __restrict__ nonlinear,
                                             int ns, const double* __restrict__ dirs,
                                             const double* __restrict__ w, const double* __restrict__ du,
@@ -580,35 +685,50 @@ __global__ __launch_bounds__(256) void k_law(DevMesh M, int MB, int nm, int e0, 
     const long ne = M.ne;
     const int l = M.layer[e];
     if (!nonlinear[l]) return;
+    const int EB = MB >= 64 ? 1 : 64 / MB;
     SpringPar P;
     P.G0 = matv(mat, l, MAT_G0, MB, m);
     P.gref = matv(mat, l, MAT_GREF, MB, m);
     P.hmax = matv(mat, l, MAT_HMAX, MB, m);
     P.beta = matv(mat, l, MAT_BETA, MB, m);
     const double Kb = matv(mat, l, MAT_KB, MB, m);
-    double gL[4][3];
-    for (int k = 0; k < 12; ++k) gL[k / 3][k % 3] = M.geo64[k * ne + e];
-    double u[10][3];
-    for (int n = 0; n < 10; ++n) {
-        const long node = M.conn[n * ne + e];
-        for (int c = 0; c < 3; ++c) u[n][c] = du[(node * 3 + c) * MB + m];
+    // strain increments at the four points
+    double eps4[4][6];
+    {
+        double gL[4][3];
+        for (int k = 0; k < 12; ++k) gL[k / 3][k % 3] = M.geo64[k * ne + e];
+        double u[10][3];
+        for (int n = 0; n < 10; ++n) {
+            const long node = M.conn[n * ne + e];
+            for (int c = 0; c < 3; ++c) u[n][c] = du[(node * 3 + c) * MB + m];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            double G[10][3];
+            shape_grads<double>(j, gL, G);
+            strain<double>(G, u, eps4[j]);
+        }
     }
-    ThetaPtrs th = theta_fields(theta, ec, ns, MB);
+    ThetaView th = theta_view(theta, ecp, ns, MB);
+    const long fn = th.field_n;
     double hsum = 0.0;
+#pragma unroll 1
     for (int j = 0; j < 4; ++j) {
-        double G[10][3], eps[6];
-        shape_grads<double>(j, gL, G);
-        strain<double>(G, u, eps);
+        double ej[6];  // select without dynamic register indexing
+#pragma unroll
+        for (int q = 0; q < 6; ++q)
+            ej[q] = j == 0 ? eps4[0][q] : (j == 1 ? eps4[1][q] : (j == 2 ? eps4[2][q] : eps4[3][q]));
         double d[21];
+#pragma unroll
         for (int k = 0; k < 21; ++k) d[k] = 0;
         double hs = 0.0;
+#pragma unroll 1
         for (int s = 0; s < ns; ++s) {
             const double* n = dirs + 6 * s;
-            const double dg = n[0] * eps[0] + n[1] * eps[1] + n[2] * eps[2] + n[3] * eps[3] +
-                              n[4] * eps[4] + n[5] * eps[5];
-            const long idx = (((long)s * 4 + j) * ec + el) * MB + m;
-            double gp = th.gp[idx], gr = th.gr[idx], tr = th.tr[idx], gm = th.gm[idx];
-            int dir = th.dir[idx], skel = th.skel[idx];
+            const double dg = n[0] * ej[0] + n[1] * ej[1] + n[2] * ej[2] + n[3] * ej[3] + n[4] * ej[4] + n[5] * ej[5];
+            const long idx = th.at(el, s, j, m);
+            double gp = th.d[idx], gr = th.d[fn + idx], tr = th.d[2 * fn + idx], gm = th.d[3 * fn + idx];
+            int dir = th.i[idx], skel = th.i[fn + idx];
             if (dg != 0.0) {
                 const int dsg = dg > 0.0 ? 1 : -1;
                 if (dir != 0 && dsg != dir) {  // reversal: a Masing branch starts here
@@ -621,8 +741,8 @@ __global__ __launch_bounds__(256) void k_law(DevMesh M, int MB, int nm, int e0, 
                 if (!skel && (double)dsg * g >= gm) skel = 1;  // rejoin the skeleton
                 if (skel) gm = fmax(gm, fabs(g));
                 gp = g;
-                th.gp[idx] = gp; th.gr[idx] = gr; th.tr[idx] = tr; th.gm[idx] = gm;
-                th.dir[idx] = dir; th.skel[idx] = skel;
+                th.d[idx] = gp; th.d[fn + idx] = gr; th.d[2 * fn + idx] = tr; th.d[3 * fn + idx] = gm;
+                th.i[idx] = dir; th.i[fn + idx] = skel;
             }
             const double xi = skel ? gp : 0.5 * (gp - gr);
             const double sx = ro_inverse(xi / P.gref, P.beta);
@@ -636,13 +756,18 @@ __global__ __launch_bounds__(256) void k_law(DevMesh M, int MB, int nm, int e0, 
             }
             hs += hk;
             const double c = w[s] * Gt;
+#pragma unroll
             for (int r = 0; r < 6; ++r)
+#pragma unroll
                 for (int q = r; q < 6; ++q) d[sym6(r, q)] += c * n[r] * n[q];
         }
+#pragma unroll
         for (int r = 0; r < 3; ++r)
+#pragma unroll
             for (int q = r; q < 3; ++q) d[sym6(r, q)] += Kb;
+#pragma unroll
         for (int k = 0; k < 21; ++k) {
-            const long idx = (((long)j * 21 + k) * ne + e) * MB + m;
+            const long idx = d_index(e, j, k, MB, EB, m);
             D[idx] = d[k];
             D32[idx] = (float)d[k];
         }
@@ -651,419 +776,14 @@ __global__ __launch_bounds__(256) void k_law(DevMesh M, int MB, int nm, int e0, 
     h[e * MB + m] = 0.25 * hsum;
 }
 
-void launch_law(hipStream_t s, const DevMesh& M, int MB, int nm, int e0, int ec, const double* mat, int,
+void launch_law(hipStream_t s, const DevMesh& M, int MB, int nm, int e0, int ec, long ecp, const double* mat, int,
                 const int* nonlinear, int ns, const double* dirs, const double* w, const double* du,
                 void* theta, double* D, float* D32, double* h, const int* stepping)
 {
     long n = (long)ec * MB;
     if (n > 0)
-        hipLaunchKernelGGL(k_law, dim3(nblocks(n)), dim3(256), 0, s, M, MB, nm, e0, ec, mat, nonlinear, ns, dirs,
+        hipLaunchKernelGGL(k_law, dim3(nblocks(n)), dim3(256), 0, s, M, MB, nm, e0, ec, ecp, mat, nonlinear, ns, dirs,
                            w, du, theta, D, D32, h, stepping);
-}
-
-// ---------------------------------------------------------------------------
-// per-member dot products: deterministic two-stage reduction
-// ---------------------------------------------------------------------------
-
-template <int ND, typename T>
-__global__ __launch_bounds__(256) void k_dots(const T* __restrict__ a0, const T* __restrict__ b0,
-                                             const T* __restrict__ a1, const T* __restrict__ b1,
-                                             const T* __restrict__ a2, const T* __restrict__ b2, long nrows,
-                                             int MB, int MBt, double* __restrict__ partial)
-{
-    __shared__ double sh[ND][256];
-    const int t = threadIdx.x;
-    const int ml = t % MBt, rl = t / MBt, rpb = 256 / MBt;
-    const int m = blockIdx.y * MBt + ml;
-    double acc[ND];
-#pragma unroll
-    for (int k = 0; k < ND; ++k) acc[k] = 0.0;
-    for (long row = (long)blockIdx.x * rpb + rl; row < nrows; row += (long)gridDim.x * rpb) {
-        const long i = row * MB + m;
-        acc[0] += (double)a0[i] * (double)b0[i];
-        if (ND > 1) acc[1] += (double)a1[i] * (double)b1[i];
-        if (ND > 2) acc[2] += (double)a2[i] * (double)b2[i];
-    }
-#pragma unroll
-    for (int k = 0; k < ND; ++k) sh[k][t] = acc[k];
-    __syncthreads();
-    for (int st = 128; st >= MBt; st >>= 1) {
-        if (t < st)
-#pragma unroll
-            for (int k = 0; k < ND; ++k) sh[k][t] += sh[k][t + st];
-        __syncthreads();
-    }
-    if (t < MBt)
-#pragma unroll
-        for (int k = 0; k < ND; ++k) partial[((long)k * gridDim.x + blockIdx.x) * MB + m] = sh[k][t];
-}
-
-template <typename T>
-static void dots_impl(hipStream_t s, int nd, const T* a0, const T* b0, const T* a1, const T* b1, const T* a2,
-                      const T* b2, long nrows, int MB, double* partial, int* nblk_out)
-{
-    const int MBt = MB < 256 ? MB : 256;
-    const int rpb = 256 / MBt;
-    long nb = (nrows + rpb - 1) / rpb;
-    int nblk = (int)(nb < kMaxPartialBlocks ? nb : kMaxPartialBlocks);
-    if (nblk < 1) nblk = 1;
-    dim3 g(nblk, MB / MBt);
-    if (nd == 1) hipLaunchKernelGGL((k_dots<1, T>), g, dim3(256), 0, s, a0, b0, a1, b1, a2, b2, nrows, MB, MBt, partial);
-    else if (nd == 2) hipLaunchKernelGGL((k_dots<2, T>), g, dim3(256), 0, s, a0, b0, a1, b1, a2, b2, nrows, MB, MBt, partial);
-    else hipLaunchKernelGGL((k_dots<3, T>), g, dim3(256), 0, s, a0, b0, a1, b1, a2, b2, nrows, MB, MBt, partial);
-    *nblk_out = nblk;
-}
-
-void launch_dots(hipStream_t s, int nd, const double* a0, const double* b0, const double* a1, const double* b1,
-                 const double* a2, const double* b2, long nrows, int MB, double* partial, int* nblk_out)
-{
-    dots_impl<double>(s, nd, a0, b0, a1, b1, a2, b2, nrows, MB, partial, nblk_out);
-}
-void launch_dots32(hipStream_t s, int nd, const float* a0, const float* b0, const float* a1, const float* b1,
-                   long nrows, int MB, double* partial, int* nblk_out)
-{
-    dots_impl<float>(s, nd, a0, b0, a1, b1, nullptr, nullptr, nrows, MB, partial, nblk_out);
-}
-
-// scalar logic of the CG variants, one thread per member (single block)
-__global__ void k_finalize(int stage, int MB, int nm, const double* __restrict__ partial, int nblk, CgScalars cs,
-                           double tol2, int maxit)
-{
-    __shared__ int any;
-    if (threadIdx.x == 0) any = 0;
-    __syncthreads();
-    for (int m = threadIdx.x; m < MB; m += blockDim.x) {
-        double S[3] = {0, 0, 0};
-        const int nd = (stage == FIN_START) ? 3 : (stage == FIN_ALPHA || stage == FIN_FCG_RZ || stage == FIN_FCG_RR || stage == FIN_IN_ALPHA) ? 1 : 2;
-        for (int k = 0; k < nd; ++k)
-            for (int b = 0; b < nblk; ++b) S[k] += partial[((long)k * nblk + b) * MB + m];
-        int act = 0;
-        if (m < nm) {
-            switch (stage) {
-            case FIN_START:
-                cs.bb[m] = S[0];
-                cs.rr[m] = S[1];
-                cs.rz[m] = S[2];
-                cs.iters[m] = 0;
-                act = cs.stepping[m] && S[0] > 0.0 && S[1] > tol2 * S[0];
-                cs.active[m] = act;
-                break;
-            case FIN_ALPHA:
-                act = cs.active[m];
-                cs.pAp[m] = S[0];
-                cs.alpha[m] = act ? cs.rz[m] / S[0] : 0.0;
-                break;
-            case FIN_BETA:
-                act = cs.active[m];
-                if (act) {
-                    cs.iters[m] += 1;
-                    cs.rr[m] = S[0];
-                    if (S[0] <= tol2 * cs.bb[m]) {
-                        act = 0;
-                    } else if (cs.iters[m] >= maxit) {
-                        act = 0;
-                        cs.status[m] = -5;
-                    } else {
-                        cs.beta[m] = S[1] / cs.rz[m];
-                        cs.rz[m] = S[1];
-                    }
-                    cs.active[m] = act;
-                }
-                break;
-            case FIN_FCG_START:
-                cs.bb[m] = S[0];
-                cs.rr[m] = S[1];
-                cs.iters[m] = 0;
-                cs.inner_total[m] = 0;
-                act = cs.stepping[m] && S[0] > 0.0 && S[1] > tol2 * S[0];
-                cs.active[m] = act;
-                break;
-            case FIN_FCG_RZ:
-                act = cs.active[m];
-                cs.rz[m] = S[0];
-                break;
-            case FIN_FCG_RR:
-                act = cs.active[m];
-                if (act) {
-                    cs.iters[m] += 1;
-                    cs.rr[m] = S[0];
-                    if (S[0] <= tol2 * cs.bb[m]) act = 0;
-                    else if (cs.iters[m] >= maxit) { act = 0; cs.status[m] = -5; }
-                    cs.active[m] = act;
-                }
-                break;
-            case FIN_FCG_BETA:  // S0 = z.Ap, S1 = z.r
-                act = cs.active[m];
-                if (act) {
-                    cs.beta[m] = -cs.alpha[m] * S[0] / cs.rz[m];
-                    cs.rz[m] = S[1];
-                }
-                break;
-            case FIN_IN_START:
-                act = cs.active[m] && S[0] > 0.0;
-                cs.ir0[m] = S[0];
-                cs.irz[m] = S[1];
-                cs.inner_iters[m] = 0;
-                cs.inner_active[m] = act;
-                break;
-            case FIN_IN_ALPHA:
-                act = cs.inner_active[m];
-                cs.ialpha[m] = act ? cs.irz[m] / S[0] : 0.0;
-                break;
-            case FIN_IN_BETA:
-                act = cs.inner_active[m];
-                if (act) {
-                    cs.inner_iters[m] += 1;
-                    cs.inner_total[m] += 1;
-                    if (S[0] <= tol2 * cs.ir0[m] || cs.inner_iters[m] >= maxit) {
-                        act = 0;
-                    } else {
-                        cs.ibeta[m] = S[1] / cs.irz[m];
-                        cs.irz[m] = S[1];
-                    }
-                    cs.inner_active[m] = act;
-                }
-                break;
-            }
-        }
-        if (act) atomicOr(&any, 1);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) *cs.any_active = any;
-}
-
-void launch_finalize(hipStream_t s, FinalizeStage st, int MB, int nm, const double* partial, int nblk, CgScalars cs,
-                     double tol2, int maxit)
-{
-    int bs = MB < 1024 ? MB : 1024;
-    if (bs < 64) bs = 64;
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(bs), 0, s, (int)st, MB, nm, partial, nblk, cs, tol2, maxit);
-}
-
-// ---------------------------------------------------------------------------
-// CG vector updates (per node, member; block-Jacobi 3x3 symmetric inverse)
-// ---------------------------------------------------------------------------
-
-template <typename T, typename P>
-__device__ __forceinline__ void apply_pinv(const P* __restrict__ pinv, long node, int MB, int m, const T r[3], T z[3])
-{
-    T a[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) a[k] = (T)pinv[(node * 6 + k) * MB + m];
-    z[0] = a[0] * r[0] + a[1] * r[1] + a[2] * r[2];
-    z[1] = a[1] * r[0] + a[3] * r[1] + a[4] * r[2];
-    z[2] = a[2] * r[0] + a[4] * r[1] + a[5] * r[2];
-}
-
-__global__ void k_pcg_start(int nn, int MB, int nm, const double* __restrict__ b, const double* __restrict__ Ap,
-                            const double* __restrict__ pinv, double* __restrict__ r, double* __restrict__ z,
-                            double* __restrict__ p, const int* __restrict__ stepping)
-{
-    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    const int m = (int)(t % MB);
-    const long i = t / MB;
-    if (i >= nn || m >= nm) return;
-    double rv[3], zv[3];
-    for (int c = 0; c < 3; ++c) {
-        const long idx = (i * 3 + c) * MB + m;
-        rv[c] = stepping[m] ? b[idx] - Ap[idx] : 0.0;
-    }
-    apply_pinv<double, double>(pinv, i, MB, m, rv, zv);
-    for (int c = 0; c < 3; ++c) {
-        const long idx = (i * 3 + c) * MB + m;
-        r[idx] = rv[c];
-        z[idx] = zv[c];
-        p[idx] = zv[c];
-    }
-}
-
-void launch_pcg_start(hipStream_t s, int nn, int MB, int nm, const double* b, const double* Ap, const double* pinv,
-                      double* r, double* z, double* p, const int* stepping)
-{
-    long n = (long)nn * MB;
-    hipLaunchKernelGGL(k_pcg_start, dim3(nblocks(n)), dim3(256), 0, s, nn, MB, nm, b, Ap, pinv, r, z, p, stepping);
-}
-
-__global__ void k_pcg_update(int nn, int MB, int nm, double* __restrict__ x, double* __restrict__ r,
-                             double* __restrict__ z, const double* __restrict__ p, const double* __restrict__ Ap,
-                             const double* __restrict__ pinv, const double* __restrict__ alpha,
-                             const int* __restrict__ active)
-{
-    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    const int m = (int)(t % MB);
-    const long i = t / MB;
-    if (i >= nn || m >= nm || !active[m]) return;
-    const double al = alpha[m];
-    double rv[3], zv[3];
-    for (int c = 0; c < 3; ++c) {
-        const long idx = (i * 3 + c) * MB + m;
-        x[idx] += al * p[idx];
-        rv[c] = r[idx] - al * Ap[idx];
-        r[idx] = rv[c];
-    }
-    apply_pinv<double, double>(pinv, i, MB, m, rv, zv);
-    for (int c = 0; c < 3; ++c) z[(i * 3 + c) * MB + m] = zv[c];
-}
-
-void launch_pcg_update(hipStream_t s, int nn, int MB, int nm, double* x, double* r, double* z, const double* p,
-                       const double* Ap, const double* pinv, const double* alpha, const int* active)
-{
-    long n = (long)nn * MB;
-    hipLaunchKernelGGL(k_pcg_update, dim3(nblocks(n)), dim3(256), 0, s, nn, MB, nm, x, r, z, p, Ap, pinv, alpha, active);
-}
-
-__global__ void k_axpby_p(long n, int MB, int nm, const double* __restrict__ z, double* __restrict__ p,
-                          const double* __restrict__ beta, const int* __restrict__ active)
-{
-    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    const int m = (int)(i % MB);
-    if (i >= n || m >= nm || !active[m]) return;
-    p[i] = z[i] + beta[m] * p[i];
-}
-
-void launch_axpby_p(hipStream_t s, long n, int MB, int nm, const double* z, double* p, const double* beta,
-                    const int* active)
-{
-    long N = n * MB;
-    hipLaunchKernelGGL(k_axpby_p, dim3(nblocks(N)), dim3(256), 0, s, N, MB, nm, z, p, beta, active);
-}
-
-__global__ void k_zero_inactive_start(long n, int MB, int nm, double* __restrict__ x, const double* __restrict__ bb,
-                                      const int* __restrict__ stepping)
-{
-    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    const int m = (int)(i % MB);
-    if (i >= n || m >= nm) return;
-    if (stepping[m] && bb[m] == 0.0) x[i] = 0.0;
-}
-
-void launch_zero_inactive_start(hipStream_t s, long n, int MB, int nm, double* x, const double* bb,
-                                const int* stepping)
-{
-    long N = n * MB;
-    hipLaunchKernelGGL(k_zero_inactive_start, dim3(nblocks(N)), dim3(256), 0, s, N, MB, nm, x, bb, stepping);
-}
-
-__global__ void k_xr_update(long n, int MB, int nm, double* __restrict__ x, double* __restrict__ r,
-                            const double* __restrict__ p, const double* __restrict__ Ap,
-                            const double* __restrict__ alpha, const int* __restrict__ active)
-{
-    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    const int m = (int)(i % MB);
-    if (i >= n || m >= nm || !active[m]) return;
-    const double al = alpha[m];
-    x[i] += al * p[i];
-    r[i] -= al * Ap[i];
-}
-
-void launch_xr_update(hipStream_t s, long n, int MB, int nm, double* x, double* r, const double* p, const double* Ap,
-                      const double* alpha, const int* active)
-{
-    long N = n * MB;
-    hipLaunchKernelGGL(k_xr_update, dim3(nblocks(N)), dim3(256), 0, s, N, MB, nm, x, r, p, Ap, alpha, active);
-}
-
-__global__ void k_copy_p(long n, int MB, int nm, const double* __restrict__ z, double* __restrict__ p,
-                         const int* __restrict__ active)
-{
-    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    const int m = (int)(i % MB);
-    if (i >= n || m >= nm || !active[m]) return;
-    p[i] = z[i];
-}
-
-void launch_copy_p(hipStream_t s, long n, int MB, int nm, const double* z, double* p, const int* active)
-{
-    long N = n * MB;
-    hipLaunchKernelGGL(k_copy_p, dim3(nblocks(N)), dim3(256), 0, s, N, MB, nm, z, p, active);
-}
-
-// inner FP32 block-Jacobi PCG on A z = r (preconditioner of the outer CG)
-__global__ void k_inner_start(int nn, int MB, int nm, const double* __restrict__ r, const float* __restrict__ pinv32,
-                              float* __restrict__ ir, float* __restrict__ iz, float* __restrict__ ip,
-                              float* __restrict__ w, const int* __restrict__ active)
-{
-    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    const int m = (int)(t % MB);
-    const long i = t / MB;
-    if (i >= nn || m >= nm || !active[m]) return;
-    float rv[3], zv[3];
-    for (int c = 0; c < 3; ++c) rv[c] = (float)r[(i * 3 + c) * MB + m];
-    apply_pinv<float, float>(pinv32, i, MB, m, rv, zv);
-    for (int c = 0; c < 3; ++c) {
-        const long idx = (i * 3 + c) * MB + m;
-        ir[idx] = rv[c];
-        iz[idx] = 0.0f;
-        w[idx] = zv[c];
-        ip[idx] = zv[c];
-    }
-}
-
-void launch_inner_start(hipStream_t s, int nn, int MB, int nm, const double* r, const float* pinv32, float* ir,
-                        float* iz, float* ip, float* w, const int* active)
-{
-    long n = (long)nn * MB;
-    hipLaunchKernelGGL(k_inner_start, dim3(nblocks(n)), dim3(256), 0, s, nn, MB, nm, r, pinv32, ir, iz, ip, w, active);
-}
-
-__global__ void k_inner_update(int nn, int MB, int nm, float* __restrict__ iz, float* __restrict__ ir,
-                               float* __restrict__ w, const float* __restrict__ ip, const float* __restrict__ iAp,
-                               const float* __restrict__ pinv32, const double* __restrict__ ialpha,
-                               const int* __restrict__ iactive)
-{
-    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    const int m = (int)(t % MB);
-    const long i = t / MB;
-    if (i >= nn || m >= nm || !iactive[m]) return;
-    const float al = (float)ialpha[m];
-    float rv[3], zv[3];
-    for (int c = 0; c < 3; ++c) {
-        const long idx = (i * 3 + c) * MB + m;
-        iz[idx] += al * ip[idx];
-        rv[c] = ir[idx] - al * iAp[idx];
-        ir[idx] = rv[c];
-    }
-    apply_pinv<float, float>(pinv32, i, MB, m, rv, zv);
-    for (int c = 0; c < 3; ++c) w[(i * 3 + c) * MB + m] = zv[c];
-}
-
-void launch_inner_update(hipStream_t s, int nn, int MB, int nm, float* iz, float* ir, float* w, const float* ip,
-                         const float* iAp, const float* pinv32, const double* ialpha, const int* iactive)
-{
-    long n = (long)nn * MB;
-    hipLaunchKernelGGL(k_inner_update, dim3(nblocks(n)), dim3(256), 0, s, nn, MB, nm, iz, ir, w, ip, iAp, pinv32,
-                       ialpha, iactive);
-}
-
-__global__ void k_inner_p(long n, int MB, int nm, const float* __restrict__ w, float* __restrict__ ip,
-                          const double* __restrict__ ibeta, const int* __restrict__ iactive)
-{
-    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    const int m = (int)(i % MB);
-    if (i >= n || m >= nm || !iactive[m]) return;
-    ip[i] = w[i] + (float)ibeta[m] * ip[i];
-}
-
-void launch_inner_p(hipStream_t s, long n, int MB, int nm, const float* w, float* ip, const double* ibeta,
-                    const int* iactive)
-{
-    long N = n * MB;
-    hipLaunchKernelGGL(k_inner_p, dim3(nblocks(N)), dim3(256), 0, s, N, MB, nm, w, ip, ibeta, iactive);
-}
-
-__global__ void k_inner_out(long n, int MB, int nm, const float* __restrict__ iz, double* __restrict__ z,
-                            const int* __restrict__ active)
-{
-    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    const int m = (int)(i % MB);
-    if (i >= n || m >= nm || !active[m]) return;
-    z[i] = (double)iz[i];
-}
-
-void launch_inner_out(hipStream_t s, long n, int MB, int nm, const float* iz, double* z, const int* active)
-{
-    long N = n * MB;
-    hipLaunchKernelGGL(k_inner_out, dim3(nblocks(N)), dim3(256), 0, s, N, MB, nm, iz, z, active);
 }
 
 // ---------------------------------------------------------------------------

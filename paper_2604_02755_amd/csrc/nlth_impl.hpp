@@ -4,11 +4,14 @@
 //   stored at q[i*MB + m] with MB the padded member count, so a wavefront of
 //   lanes that share an element but differ in member reads contiguous memory.
 //   node vectors   v[(node*3 + c)*MB + m]
-//   D per point    D[((ip*21 + k)*ne + e)*MB + m]   (upper triangle, row by row)
+//   elements are grouped in blocks of EB = max(1, 64/MB) so that the EB x MB
+//   lanes of a wavefront read contiguous memory:
+//   D per point    D[(((e/EB)*84 + ip*21 + k)*EB + e%EB)*MB + m]  (upper
+//                  triangle of the symmetric 6x6, row by row)
 //   element h      h[e*MB + m]
-//   law state      per chunk of elements [e0, e0+ec): field f in {gp, gr, tr,
-//                  gm} (FP64) then {dir, skel} (int32), each
-//                  f[((s*4 + ip)*ec + e_local)*MB + m]
+//   law state      per chunk of ecp elements (a multiple of EB): four FP64
+//                  fields {gp, gr, tr, gm} then two int32 fields {dir, skel},
+//                  each f[((((el/EB)*ns + s)*4 + ip)*EB + el%EB)*MB + m]
 //   mesh arrays    conn[k*ne + e], geo[k*ne + e] (k: 12 barycentric-gradient
 //                  entries then the volume), in colour-sorted element order.
 #pragma once
@@ -20,7 +23,7 @@ namespace nlth {
 
 enum OpMode { OP_A = 0, OP_K = 1, OP_M = 2, OP_RHS = 3 };
 
-constexpr int kMaxPartialBlocks = 512;
+constexpr int kMaxPartialBlocks = 2048;
 
 // Per-member material of one layer, member-innermost: mat[(l*MAT_N + field)*MB + m]
 enum MatField { MAT_RHO = 0, MAT_G0, MAT_KB, MAT_VS, MAT_VP, MAT_GREF, MAT_HMAX, MAT_BETA, MAT_N };
@@ -76,67 +79,57 @@ void launch_invert_diag(hipStream_t s, int nn, int MB, int nm, const double* dia
 // law
 void launch_law_init(hipStream_t s, const DevMesh& M, int MB, int nm, const double* mat, int n_layers,
                      int ns, const double* dirs, const double* w, double* D, float* D32, double* h);
-void launch_theta_init(hipStream_t s, void* theta_chunk, long ec, int ns, int MB);
-void launch_law(hipStream_t s, const DevMesh& M, int MB, int nm, int e0, int ec, const double* mat,
+void launch_theta_init(hipStream_t s, void* theta_chunk, long ecp, int ns, int MB);
+void launch_law(hipStream_t s, const DevMesh& M, int MB, int nm, int e0, int ec, long ecp, const double* mat,
                 int n_layers, const int* nonlinear, int ns, const double* dirs, const double* w,
                 const double* du, void* theta_chunk, double* D, float* D32, double* h,
                 const int* stepping);
 
-// vectors (FP64 CG)
-// dots: partial[k][blk][MB] for k < nd of  sum a_k . b_k
-void launch_dots(hipStream_t s, int nd, const double* a0, const double* b0, const double* a1,
-                 const double* b1, const double* a2, const double* b2, long nrows, int MB,
-                 double* partial, int* nblk_out);
-void launch_dots32(hipStream_t s, int nd, const float* a0, const float* b0, const float* a1,
-                   const float* b1, long nrows, int MB, double* partial, int* nblk_out);
+// ---- CG vectors (vec.hip): partial sums go to partial[(k*nblk + blk)*MB + m]
+template <typename T>
+void launch_dotsv(hipStream_t s, int nd, const T* a0, const T* b0, const T* a1, const T* b1, const T* a2,
+                  const T* b2, long nrows, int MB, int nm, const int* flag, double* partial, int* nblk);
 
 struct CgScalars {  // per member [MB] device arrays
     double *bb, *rr, *rz, *alpha, *beta, *pAp, *r0;
     int *active, *iters, *status, *stepping;  // stepping: member takes part in this step
     int *inner_active, *inner_iters, *inner_total;
     double *irr, *irz, *ialpha, *ibeta, *ir0;
-    int* any_active;  // [1]
 };
 
 enum FinalizeStage {
-    FIN_START = 0,   // partial {bb, rr, rz}: set active, rz
-    FIN_ALPHA,       // partial {pAp}: alpha = rz / pAp
-    FIN_BETA,        // partial {rr, rz}: convergence, beta = rz_new / rz (PCG)
-    FIN_FCG_START,   // partial {bb, rr}: flexible CG start (outer)
-    FIN_FCG_RZ,      // partial {rz}: rz = r.z after the first preconditioner call
-    FIN_FCG_BETA,    // partial {zAp, rz}: beta = -alpha zAp / rz_old ; rz = rz_new
-    FIN_FCG_RR,      // partial {rr}: outer convergence check
-    FIN_IN_START,    // partial {rr, rz} (inner): inner_active, irz
-    FIN_IN_ALPHA,    // partial {pAp} inner
-    FIN_IN_BETA      // partial {rr, rz} inner
+    FIN_START = 0,   // (b.b, r.r, r.z): PCG start, active flags
+    FIN_ALPHA,       // (p.Ap): alpha = rz / pAp
+    FIN_BETA,        // (r.r, r.z): convergence, beta = rz_new / rz (PCG)
+    FIN_FCG_START,   // (b.b, r.r): flexible CG start (outer)
+    FIN_FCG_RZ,      // (z.Ap, z.r): rz = z.r after the first preconditioner call
+    FIN_FCG_BETA,    // (z.Ap, z.r): beta = -alpha z.Ap / rz_old ; rz = z.r
+    FIN_FCG_RR,      // (r.r): outer convergence check
+    FIN_IN_START,    // (ir.ir, ir.w) inner start
+    FIN_IN_ALPHA,    // (ip.iAp) inner alpha
+    FIN_IN_BETA      // (ir.ir, ir.w) inner convergence, beta
 };
-void launch_finalize(hipStream_t s, FinalizeStage st, int MB, int nm, const double* partial, int nblk,
+void launch_finalize(hipStream_t s, FinalizeStage st, int nd, int MB, int nm, const double* partial, int nblk,
                      CgScalars cs, double tol2, int maxit);
 
-// r = b - Ap; z = Pinv r; p = z (members active) ; x zeroed for members with bb == 0 later
-void launch_pcg_start(hipStream_t s, int nn, int MB, int nm, const double* b, const double* Ap,
-                      const double* pinv, double* r, double* z, double* p, const int* stepping);
-void launch_pcg_update(hipStream_t s, int nn, int MB, int nm, double* x, double* r, double* z,
-                       const double* p, const double* Ap, const double* pinv, const double* alpha,
-                       const int* active);
-void launch_axpby_p(hipStream_t s, long n, int MB, int nm, const double* z, double* p,
-                    const double* beta, const int* active);
-void launch_zero_inactive_start(hipStream_t s, long n, int MB, int nm, double* x, const double* bb,
-                                const int* stepping);
-// FCG helpers
-void launch_xr_update(hipStream_t s, long n, int MB, int nm, double* x, double* r, const double* p,
-                      const double* Ap, const double* alpha, const int* active);
-void launch_copy_p(hipStream_t s, long n, int MB, int nm, const double* z, double* p, const int* active);
-// inner FP32 PCG
-void launch_inner_start(hipStream_t s, int nn, int MB, int nm, const double* r, const float* pinv32,
-                        float* ir, float* iz, float* ip, float* w, const int* active);
-void launch_inner_update(hipStream_t s, int nn, int MB, int nm, float* iz, float* ir, float* w,
-                         const float* ip, const float* iAp, const float* pinv32, const double* ialpha,
-                         const int* iactive);
-void launch_inner_p(hipStream_t s, long n, int MB, int nm, const float* w, float* ip,
-                    const double* ibeta, const int* iactive);
-void launch_inner_out(hipStream_t s, long n, int MB, int nm, const float* iz, double* z,
-                      const int* active);
+void launch_pcg_start(hipStream_t s, int nn, int MB, int nm, const double* b, const double* Ap, const double* pinv,
+                      double* r, double* z, double* p, const int* stepping, double* partial, int* nblk);
+void launch_pcg_update(hipStream_t s, int nn, int MB, int nm, double* x, double* r, double* z, const double* p,
+                       const double* Ap, const double* pinv, const double* alpha, const int* active, double* partial,
+                       int* nblk);
+template <typename T>
+void launch_p_update(hipStream_t s, long nrows, int MB, int nm, const T* z, T* p, const double* beta, const int* active,
+                     T* y);
+void launch_xr_update(hipStream_t s, long nrows, int MB, int nm, double* x, double* r, const double* p, const double* Ap,
+                      const double* alpha, const int* active, double* partial, int* nblk);
+void launch_inner_start(hipStream_t s, int nn, int MB, int nm, const double* r, const float* pinv32, float* ir,
+                        float* iz, float* ip, float* w, float* iAp, const int* active, double* partial, int* nblk);
+void launch_inner_update(hipStream_t s, int nn, int MB, int nm, float* iz, float* ir, float* w, const float* ip,
+                         const float* iAp, const float* pinv32, const double* ialpha, const int* iactive,
+                         double* partial, int* nblk);
+void launch_inner_out(hipStream_t s, long nrows, int MB, int nm, const float* iz, double* z, const double* Ap,
+                      const double* r, const int* active, double* partial, int* nblk);
+void launch_zero_if_b0(hipStream_t s, long nrows, int MB, int nm, double* x, const double* bb, const int* stepping);
 
 // Newmark state updates (Section 2.1) and receivers
 void launch_newmark(hipStream_t s, long n, int MB, int nm, const double* du, double* u, double* v,

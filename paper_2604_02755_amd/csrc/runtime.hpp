@@ -84,7 +84,7 @@ struct Ens {
     Ctx* ctx = nullptr;
     const Mesh* mesh = nullptr;
     Problem P;
-    int MB = 1, nm = 0;
+    int MB = 1, nm = 0, EB = 1, ne_pad = 0;  // EB: elements per layout block
     long ndof = 0;
     StepConst sc{};
     hipStream_t s = nullptr;
@@ -103,7 +103,7 @@ struct Ens {
     bool paged = false;
     int chunk_elems = 0, nchunks = 0, ring = 3;
     std::vector<long> chunk_off;        // byte offset of each chunk in theta_host
-    std::vector<int> chunk_e0, chunk_ec;
+    std::vector<int> chunk_e0, chunk_ec, chunk_ecp;
     hipStream_t s_h2d = nullptr, s_d2h = nullptr;
     std::vector<hipEvent_t> ev_h2d, ev_law, ev_d2h;
     std::vector<int> slot_chunk;        // chunk currently held by each slot (-1 none)
@@ -141,7 +141,10 @@ struct Ens {
     // helpers
     void dots(int nd, const double* a0, const double* b0, const double* a1, const double* b1,
               const double* a2, const double* b2, int& nblk);
-    int read_any_active();
+    int read_any_active(const int* flags);
+    void fin(FinalizeStage st, int nd, int nblk, double tol2, int maxit);
+    void apply_A64(const double* x, double* y, const int* act);
+    int* h_flags = nullptr;             // pinned copy of per-member flags
     hipEvent_t ev();
     void tstart(hipEvent_t& e0);
     void tstop(hipEvent_t e0, ProfCat* cat, int64_t elems);

@@ -1,0 +1,701 @@
+// CG vector kernels of libnlth: fused updates with the dot products of the
+// next step folded into the same pass, per-member deterministic reductions,
+// and the per-member scalar logic of the CG variants.
+//
+// Vectors are member-innermost (v[(row)*MB + m]).  A thread handles VEC
+// consecutive members of one row (16-byte loads when MB is a multiple of 4)
+// and loops over rows with a grid stride; a block of 256 threads covers
+// 256/(MB/VEC) rows per iteration.  Partial sums are reduced in LDS by a
+// fixed tree and written as partial[(k*nblk + blk)*MB + m]; the finalize
+// kernel reduces them over blocks by a fixed tree as well, so results do not
+// depend on timing.
+#include <math.h>
+
+#include "nlth_impl.hpp"
+
+namespace nlth {
+
+constexpr int kMaxBlocks = kMaxPartialBlocks;
+
+template <typename T, int VEC> struct Pk { T a[VEC]; };
+
+template <typename T, int VEC>
+__device__ __forceinline__ Pk<T, VEC> ld(const T* __restrict__ p)
+{
+    Pk<T, VEC> r;
+    if constexpr (VEC == 4 && sizeof(T) == 4) {
+        const float4 q = *reinterpret_cast<const float4*>(p);
+        r.a[0] = q.x; r.a[1] = q.y; r.a[2] = q.z; r.a[3] = q.w;
+    } else if constexpr (VEC == 4 && sizeof(T) == 8) {
+        const double2 q0 = *reinterpret_cast<const double2*>(p);
+        const double2 q1 = *reinterpret_cast<const double2*>(p + 2);
+        r.a[0] = q0.x; r.a[1] = q0.y; r.a[2] = q1.x; r.a[3] = q1.y;
+    } else {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) r.a[v] = p[v];
+    }
+    return r;
+}
+
+template <typename T, int VEC>
+__device__ __forceinline__ void st(T* __restrict__ p, const Pk<T, VEC>& r)
+{
+    if constexpr (VEC == 4 && sizeof(T) == 4) {
+        *reinterpret_cast<float4*>(p) = make_float4(r.a[0], r.a[1], r.a[2], r.a[3]);
+    } else if constexpr (VEC == 4 && sizeof(T) == 8) {
+        *reinterpret_cast<double2*>(p) = make_double2(r.a[0], r.a[1]);
+        *reinterpret_cast<double2*>(p + 2) = make_double2(r.a[2], r.a[3]);
+    } else {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) p[v] = r.a[v];
+    }
+}
+
+static inline int vec_of(int MB) { return (MB % 4 == 0) ? 4 : 1; }
+
+static inline int grid_for(long rows, int rpb)
+{
+    long g = (rows + rpb - 1) / rpb;
+    if (g > kMaxBlocks) g = kMaxBlocks;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+// block-level reduction of ND accumulators per member and store of partials
+template <int ND, int VEC>
+__device__ __forceinline__ void block_partials(double acc[ND][VEC], int QB, int MB, double* __restrict__ partial)
+{
+    __shared__ double sh[ND][VEC][256];
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < ND; ++k)
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) sh[k][v][t] = acc[k][v];
+    __syncthreads();
+    for (int s = 128; s >= QB; s >>= 1) {
+        if (t < s)
+#pragma unroll
+            for (int k = 0; k < ND; ++k)
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) sh[k][v][t] += sh[k][v][t + s];
+        __syncthreads();
+    }
+    if (t < QB) {
+        const int m0 = t * VEC;
+#pragma unroll
+        for (int k = 0; k < ND; ++k)
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) partial[((long)k * gridDim.x + blockIdx.x) * MB + m0 + v] = sh[k][v][t];
+    }
+}
+
+__device__ __forceinline__ bool member_mask(const int* __restrict__ flag, int m0, int VEC, int nm, bool act[4])
+{
+    bool any = false;
+    for (int v = 0; v < VEC; ++v) {
+        const int m = m0 + v;
+        act[v] = m < nm && (flag ? flag[m] != 0 : true);
+        any |= act[v];
+    }
+    return any;
+}
+
+// ---------------------------------------------------------------------------
+// generic partial dots sum_rows a_k . b_k
+// ---------------------------------------------------------------------------
+
+template <typename T, int VEC, int ND>
+__global__ __launch_bounds__(256) void k_dotsv(const T* __restrict__ a0, const T* __restrict__ b0,
+                                              const T* __restrict__ a1, const T* __restrict__ b1,
+                                              const T* __restrict__ a2, const T* __restrict__ b2, long nrows,
+                                              int MB, int nm, const int* __restrict__ flag,
+                                              double* __restrict__ partial)
+{
+    const int QB = MB / VEC, rpb = 256 / QB;
+    const int t = threadIdx.x, q = t % QB, rl = t / QB, m0 = q * VEC;
+    double acc[ND][VEC];
+#pragma unroll
+    for (int k = 0; k < ND; ++k)
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) acc[k][v] = 0.0;
+    bool act[4];
+    if (member_mask(flag, m0, VEC, nm, act)) {
+        for (long row = (long)blockIdx.x * rpb + rl; row < nrows; row += (long)gridDim.x * rpb) {
+            const long i = row * MB + m0;
+            const Pk<T, VEC> A0 = ld<T, VEC>(a0 + i), B0 = ld<T, VEC>(b0 + i);
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) acc[0][v] += (double)A0.a[v] * (double)B0.a[v];
+            if constexpr (ND > 1) {
+                const Pk<T, VEC> A1 = ld<T, VEC>(a1 + i), B1 = ld<T, VEC>(b1 + i);
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) acc[1][v] += (double)A1.a[v] * (double)B1.a[v];
+            }
+            if constexpr (ND > 2) {
+                const Pk<T, VEC> A2 = ld<T, VEC>(a2 + i), B2 = ld<T, VEC>(b2 + i);
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) acc[2][v] += (double)A2.a[v] * (double)B2.a[v];
+            }
+        }
+    }
+    block_partials<ND, VEC>(acc, QB, MB, partial);
+}
+
+template <typename T>
+void launch_dotsv(hipStream_t s, int nd, const T* a0, const T* b0, const T* a1, const T* b1, const T* a2,
+                  const T* b2, long nrows, int MB, int nm, const int* flag, double* partial, int* nblk)
+{
+    const int VEC = vec_of(MB), QB = MB / VEC, rpb = 256 / QB;
+    const int g = grid_for(nrows, rpb);
+    *nblk = g;
+#define DOTS_L(V, N) hipLaunchKernelGGL((k_dotsv<T, V, N>), dim3(g), dim3(256), 0, s, a0, b0, a1, b1, a2, b2, nrows, MB, nm, flag, partial)
+    if (VEC == 4) {
+        if (nd == 1) DOTS_L(4, 1); else if (nd == 2) DOTS_L(4, 2); else DOTS_L(4, 3);
+    } else {
+        if (nd == 1) DOTS_L(1, 1); else if (nd == 2) DOTS_L(1, 2); else DOTS_L(1, 3);
+    }
+#undef DOTS_L
+}
+template void launch_dotsv<double>(hipStream_t, int, const double*, const double*, const double*, const double*,
+                                   const double*, const double*, long, int, int, const int*, double*, int*);
+template void launch_dotsv<float>(hipStream_t, int, const float*, const float*, const float*, const float*,
+                                  const float*, const float*, long, int, int, const int*, double*, int*);
+
+// ---------------------------------------------------------------------------
+// per-node updates with the block-Jacobi 3x3 symmetric inverse
+// ---------------------------------------------------------------------------
+
+template <typename T, int VEC>
+__device__ __forceinline__ void pinv_apply(const T* __restrict__ pinv, long node, int MB, int m0, const Pk<T, VEC> r[3],
+                                           Pk<T, VEC> z[3])
+{
+    Pk<T, VEC> a[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) a[k] = ld<T, VEC>(pinv + (node * 6 + k) * MB + m0);
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+        z[0].a[v] = a[0].a[v] * r[0].a[v] + a[1].a[v] * r[1].a[v] + a[2].a[v] * r[2].a[v];
+        z[1].a[v] = a[1].a[v] * r[0].a[v] + a[3].a[v] * r[1].a[v] + a[4].a[v] * r[2].a[v];
+        z[2].a[v] = a[2].a[v] * r[0].a[v] + a[4].a[v] * r[1].a[v] + a[5].a[v] * r[2].a[v];
+    }
+}
+
+// FP64 PCG start: r = b - Ap, z = P r, p = z; partials (b.b, r.r, r.z)
+template <int VEC>
+__global__ __launch_bounds__(256) void k_pcg_start(int nn, int MB, int nm, const double* __restrict__ b,
+                                                  const double* __restrict__ Ap, const double* __restrict__ pinv,
+                                                  double* __restrict__ r, double* __restrict__ z,
+                                                  double* __restrict__ p, const int* __restrict__ stepping,
+                                                  double* __restrict__ partial)
+{
+    const int QB = MB / VEC, npb = 256 / QB;
+    const int t = threadIdx.x, q = t % QB, m0 = q * VEC;
+    double acc[3][VEC];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) acc[k][v] = 0.0;
+    bool act[4];
+    if (member_mask(stepping, m0, VEC, nm, act)) {
+        for (long node = (long)blockIdx.x * npb + t / QB; node < nn; node += (long)gridDim.x * npb) {
+            Pk<double, VEC> R[3], Z[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const long i = (node * 3 + c) * MB + m0;
+                const Pk<double, VEC> B = ld<double, VEC>(b + i), A = ld<double, VEC>(Ap + i);
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) {
+                    R[c].a[v] = act[v] ? B.a[v] - A.a[v] : 0.0;
+                    acc[0][v] += B.a[v] * B.a[v];
+                }
+            }
+            pinv_apply<double, VEC>(pinv, node, MB, m0, R, Z);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const long i = (node * 3 + c) * MB + m0;
+                st<double, VEC>(r + i, R[c]);
+                st<double, VEC>(z + i, Z[c]);
+                st<double, VEC>(p + i, Z[c]);
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) {
+                    acc[1][v] += R[c].a[v] * R[c].a[v];
+                    acc[2][v] += R[c].a[v] * Z[c].a[v];
+                }
+            }
+        }
+    }
+    block_partials<3, VEC>(acc, QB, MB, partial);
+}
+
+void launch_pcg_start(hipStream_t s, int nn, int MB, int nm, const double* b, const double* Ap, const double* pinv,
+                      double* r, double* z, double* p, const int* stepping, double* partial, int* nblk)
+{
+    const int VEC = vec_of(MB), QB = MB / VEC;
+    const int g = grid_for(nn, 256 / QB);
+    *nblk = g;
+    if (VEC == 4) hipLaunchKernelGGL((k_pcg_start<4>), dim3(g), dim3(256), 0, s, nn, MB, nm, b, Ap, pinv, r, z, p, stepping, partial);
+    else hipLaunchKernelGGL((k_pcg_start<1>), dim3(g), dim3(256), 0, s, nn, MB, nm, b, Ap, pinv, r, z, p, stepping, partial);
+}
+
+// FP64 PCG: x += a p, r -= a Ap, z = P r; partials (r.r, r.z)
+template <int VEC>
+__global__ __launch_bounds__(256) void k_pcg_update(int nn, int MB, int nm, double* __restrict__ x,
+                                                   double* __restrict__ r, double* __restrict__ z,
+                                                   const double* __restrict__ p, const double* __restrict__ Ap,
+                                                   const double* __restrict__ pinv, const double* __restrict__ alpha,
+                                                   const int* __restrict__ active, double* __restrict__ partial)
+{
+    const int QB = MB / VEC, npb = 256 / QB;
+    const int t = threadIdx.x, q = t % QB, m0 = q * VEC;
+    double acc[2][VEC];
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) acc[k][v] = 0.0;
+    bool act[4];
+    if (member_mask(active, m0, VEC, nm, act)) {
+        double al[VEC];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) al[v] = act[v] ? alpha[m0 + v] : 0.0;
+        for (long node = (long)blockIdx.x * npb + t / QB; node < nn; node += (long)gridDim.x * npb) {
+            Pk<double, VEC> R[3], Z[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const long i = (node * 3 + c) * MB + m0;
+                Pk<double, VEC> X = ld<double, VEC>(x + i);
+                const Pk<double, VEC> P = ld<double, VEC>(p + i), A = ld<double, VEC>(Ap + i);
+                R[c] = ld<double, VEC>(r + i);
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) {
+                    X.a[v] += al[v] * P.a[v];
+                    R[c].a[v] -= al[v] * A.a[v];
+                }
+                st<double, VEC>(x + i, X);
+                st<double, VEC>(r + i, R[c]);
+            }
+            pinv_apply<double, VEC>(pinv, node, MB, m0, R, Z);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                st<double, VEC>(z + (node * 3 + c) * MB + m0, Z[c]);
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) {
+                    acc[0][v] += R[c].a[v] * R[c].a[v];
+                    acc[1][v] += R[c].a[v] * Z[c].a[v];
+                }
+            }
+        }
+    }
+    block_partials<2, VEC>(acc, QB, MB, partial);
+}
+
+void launch_pcg_update(hipStream_t s, int nn, int MB, int nm, double* x, double* r, double* z, const double* p,
+                       const double* Ap, const double* pinv, const double* alpha, const int* active, double* partial,
+                       int* nblk)
+{
+    const int VEC = vec_of(MB), QB = MB / VEC;
+    const int g = grid_for(nn, 256 / QB);
+    *nblk = g;
+    if (VEC == 4) hipLaunchKernelGGL((k_pcg_update<4>), dim3(g), dim3(256), 0, s, nn, MB, nm, x, r, z, p, Ap, pinv, alpha, active, partial);
+    else hipLaunchKernelGGL((k_pcg_update<1>), dim3(g), dim3(256), 0, s, nn, MB, nm, x, r, z, p, Ap, pinv, alpha, active, partial);
+}
+
+// p = z + beta p for active members (beta == NULL: p = z); y = 0 everywhere
+template <typename T, int VEC>
+__global__ __launch_bounds__(256) void k_p_update(long nrows, int MB, int nm, const T* __restrict__ z,
+                                                 T* __restrict__ p, const double* __restrict__ beta,
+                                                 const int* __restrict__ active, T* __restrict__ y)
+{
+    const int QB = MB / VEC, rpb = 256 / QB;
+    const int t = threadIdx.x, q = t % QB, m0 = q * VEC;
+    bool act[4];
+    const bool any = member_mask(active, m0, VEC, nm, act);
+    T be[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) be[v] = (beta && act[v]) ? (T)beta[m0 + v] : (T)0;
+    Pk<T, VEC> zero;
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) zero.a[v] = 0;
+    for (long row = (long)blockIdx.x * rpb + t / QB; row < nrows; row += (long)gridDim.x * rpb) {
+        const long i = row * MB + m0;
+        if (any) {
+            const Pk<T, VEC> Z = ld<T, VEC>(z + i);
+            Pk<T, VEC> P = ld<T, VEC>(p + i);
+#pragma unroll
+            for (int v = 0; v < VEC; ++v)
+                if (act[v]) P.a[v] = Z.a[v] + be[v] * P.a[v];
+            st<T, VEC>(p + i, P);
+        }
+        if (y) st<T, VEC>(y + i, zero);
+    }
+}
+
+template <typename T>
+void launch_p_update(hipStream_t s, long nrows, int MB, int nm, const T* z, T* p, const double* beta, const int* active,
+                     T* y)
+{
+    const int VEC = vec_of(MB), QB = MB / VEC;
+    const int g = grid_for(nrows, 256 / QB);
+    if (VEC == 4) hipLaunchKernelGGL((k_p_update<T, 4>), dim3(g), dim3(256), 0, s, nrows, MB, nm, z, p, beta, active, y);
+    else hipLaunchKernelGGL((k_p_update<T, 1>), dim3(g), dim3(256), 0, s, nrows, MB, nm, z, p, beta, active, y);
+}
+template void launch_p_update<double>(hipStream_t, long, int, int, const double*, double*, const double*, const int*, double*);
+template void launch_p_update<float>(hipStream_t, long, int, int, const float*, float*, const double*, const int*, float*);
+
+// flexible CG: x += a p, r -= a Ap; partial r.r
+template <int VEC>
+__global__ __launch_bounds__(256) void k_xr_update(long nrows, int MB, int nm, double* __restrict__ x,
+                                                  double* __restrict__ r, const double* __restrict__ p,
+                                                  const double* __restrict__ Ap, const double* __restrict__ alpha,
+                                                  const int* __restrict__ active, double* __restrict__ partial)
+{
+    const int QB = MB / VEC, rpb = 256 / QB;
+    const int t = threadIdx.x, q = t % QB, m0 = q * VEC;
+    double acc[1][VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) acc[0][v] = 0.0;
+    bool act[4];
+    if (member_mask(active, m0, VEC, nm, act)) {
+        double al[VEC];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) al[v] = act[v] ? alpha[m0 + v] : 0.0;
+        for (long row = (long)blockIdx.x * rpb + t / QB; row < nrows; row += (long)gridDim.x * rpb) {
+            const long i = row * MB + m0;
+            Pk<double, VEC> X = ld<double, VEC>(x + i), R = ld<double, VEC>(r + i);
+            const Pk<double, VEC> P = ld<double, VEC>(p + i), A = ld<double, VEC>(Ap + i);
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) {
+                X.a[v] += al[v] * P.a[v];
+                R.a[v] -= al[v] * A.a[v];
+                acc[0][v] += R.a[v] * R.a[v];
+            }
+            st<double, VEC>(x + i, X);
+            st<double, VEC>(r + i, R);
+        }
+    }
+    block_partials<1, VEC>(acc, QB, MB, partial);
+}
+
+void launch_xr_update(hipStream_t s, long nrows, int MB, int nm, double* x, double* r, const double* p, const double* Ap,
+                      const double* alpha, const int* active, double* partial, int* nblk)
+{
+    const int VEC = vec_of(MB), QB = MB / VEC;
+    const int g = grid_for(nrows, 256 / QB);
+    *nblk = g;
+    if (VEC == 4) hipLaunchKernelGGL((k_xr_update<4>), dim3(g), dim3(256), 0, s, nrows, MB, nm, x, r, p, Ap, alpha, active, partial);
+    else hipLaunchKernelGGL((k_xr_update<1>), dim3(g), dim3(256), 0, s, nrows, MB, nm, x, r, p, Ap, alpha, active, partial);
+}
+
+// inner FP32 PCG start on A w = r: ir = r, iz = 0, w = P ir, ip = w, iAp = 0;
+// partials (ir.ir, ir.w)
+template <int VEC>
+__global__ __launch_bounds__(256) void k_inner_start(int nn, int MB, int nm, const double* __restrict__ r,
+                                                    const float* __restrict__ pinv32, float* __restrict__ ir,
+                                                    float* __restrict__ iz, float* __restrict__ ip,
+                                                    float* __restrict__ w, float* __restrict__ iAp,
+                                                    const int* __restrict__ active, double* __restrict__ partial)
+{
+    const int QB = MB / VEC, npb = 256 / QB;
+    const int t = threadIdx.x, q = t % QB, m0 = q * VEC;
+    double acc[2][VEC];
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) acc[k][v] = 0.0;
+    bool act[4];
+    const bool any = member_mask(active, m0, VEC, nm, act);
+    Pk<float, VEC> zero;
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) zero.a[v] = 0.0f;
+    for (long node = (long)blockIdx.x * npb + t / QB; node < nn; node += (long)gridDim.x * npb) {
+        if (any) {
+            Pk<float, VEC> R[3], W[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const Pk<double, VEC> Rd = ld<double, VEC>(r + (node * 3 + c) * MB + m0);
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) R[c].a[v] = act[v] ? (float)Rd.a[v] : 0.0f;
+            }
+            pinv_apply<float, VEC>(pinv32, node, MB, m0, R, W);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const long i = (node * 3 + c) * MB + m0;
+                st<float, VEC>(ir + i, R[c]);
+                st<float, VEC>(iz + i, zero);
+                st<float, VEC>(w + i, W[c]);
+                st<float, VEC>(ip + i, W[c]);
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) {
+                    acc[0][v] += (double)R[c].a[v] * (double)R[c].a[v];
+                    acc[1][v] += (double)R[c].a[v] * (double)W[c].a[v];
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) st<float, VEC>(iAp + (node * 3 + c) * MB + m0, zero);
+    }
+    block_partials<2, VEC>(acc, QB, MB, partial);
+}
+
+void launch_inner_start(hipStream_t s, int nn, int MB, int nm, const double* r, const float* pinv32, float* ir,
+                        float* iz, float* ip, float* w, float* iAp, const int* active, double* partial, int* nblk)
+{
+    const int VEC = vec_of(MB), QB = MB / VEC;
+    const int g = grid_for(nn, 256 / QB);
+    *nblk = g;
+    if (VEC == 4) hipLaunchKernelGGL((k_inner_start<4>), dim3(g), dim3(256), 0, s, nn, MB, nm, r, pinv32, ir, iz, ip, w, iAp, active, partial);
+    else hipLaunchKernelGGL((k_inner_start<1>), dim3(g), dim3(256), 0, s, nn, MB, nm, r, pinv32, ir, iz, ip, w, iAp, active, partial);
+}
+
+// inner: iz += a ip, ir -= a iAp, w = P ir; partials (ir.ir, ir.w)
+template <int VEC>
+__global__ __launch_bounds__(256) void k_inner_update(int nn, int MB, int nm, float* __restrict__ iz,
+                                                     float* __restrict__ ir, float* __restrict__ w,
+                                                     const float* __restrict__ ip, const float* __restrict__ iAp,
+                                                     const float* __restrict__ pinv32,
+                                                     const double* __restrict__ ialpha,
+                                                     const int* __restrict__ iactive, double* __restrict__ partial)
+{
+    const int QB = MB / VEC, npb = 256 / QB;
+    const int t = threadIdx.x, q = t % QB, m0 = q * VEC;
+    double acc[2][VEC];
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) acc[k][v] = 0.0;
+    bool act[4];
+    if (member_mask(iactive, m0, VEC, nm, act)) {
+        float al[VEC];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) al[v] = act[v] ? (float)ialpha[m0 + v] : 0.0f;
+        for (long node = (long)blockIdx.x * npb + t / QB; node < nn; node += (long)gridDim.x * npb) {
+            Pk<float, VEC> R[3], W[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const long i = (node * 3 + c) * MB + m0;
+                Pk<float, VEC> Z = ld<float, VEC>(iz + i);
+                const Pk<float, VEC> P = ld<float, VEC>(ip + i), A = ld<float, VEC>(iAp + i);
+                R[c] = ld<float, VEC>(ir + i);
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) {
+                    Z.a[v] += al[v] * P.a[v];
+                    R[c].a[v] -= al[v] * A.a[v];
+                }
+                st<float, VEC>(iz + i, Z);
+                st<float, VEC>(ir + i, R[c]);
+            }
+            pinv_apply<float, VEC>(pinv32, node, MB, m0, R, W);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                st<float, VEC>(w + (node * 3 + c) * MB + m0, W[c]);
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) {
+                    acc[0][v] += (double)R[c].a[v] * (double)R[c].a[v];
+                    acc[1][v] += (double)R[c].a[v] * (double)W[c].a[v];
+                }
+            }
+        }
+    }
+    block_partials<2, VEC>(acc, QB, MB, partial);
+}
+
+void launch_inner_update(hipStream_t s, int nn, int MB, int nm, float* iz, float* ir, float* w, const float* ip,
+                         const float* iAp, const float* pinv32, const double* ialpha, const int* iactive,
+                         double* partial, int* nblk)
+{
+    const int VEC = vec_of(MB), QB = MB / VEC;
+    const int g = grid_for(nn, 256 / QB);
+    *nblk = g;
+    if (VEC == 4) hipLaunchKernelGGL((k_inner_update<4>), dim3(g), dim3(256), 0, s, nn, MB, nm, iz, ir, w, ip, iAp, pinv32, ialpha, iactive, partial);
+    else hipLaunchKernelGGL((k_inner_update<1>), dim3(g), dim3(256), 0, s, nn, MB, nm, iz, ir, w, ip, iAp, pinv32, ialpha, iactive, partial);
+}
+
+// preconditioner output z = iz (FP64) for outer-active members; partials (z.Ap, z.r)
+template <int VEC>
+__global__ __launch_bounds__(256) void k_inner_out(long nrows, int MB, int nm, const float* __restrict__ iz,
+                                                  double* __restrict__ z, const double* __restrict__ Ap,
+                                                  const double* __restrict__ r, const int* __restrict__ active,
+                                                  double* __restrict__ partial)
+{
+    const int QB = MB / VEC, rpb = 256 / QB;
+    const int t = threadIdx.x, q = t % QB, m0 = q * VEC;
+    double acc[2][VEC];
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) acc[k][v] = 0.0;
+    bool act[4];
+    if (member_mask(active, m0, VEC, nm, act)) {
+        for (long row = (long)blockIdx.x * rpb + t / QB; row < nrows; row += (long)gridDim.x * rpb) {
+            const long i = row * MB + m0;
+            const Pk<float, VEC> Zf = ld<float, VEC>(iz + i);
+            const Pk<double, VEC> A = ld<double, VEC>(Ap + i), R = ld<double, VEC>(r + i);
+            Pk<double, VEC> Z = ld<double, VEC>(z + i);
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) {
+                if (act[v]) Z.a[v] = (double)Zf.a[v];
+                acc[0][v] += Z.a[v] * A.a[v];
+                acc[1][v] += Z.a[v] * R.a[v];
+            }
+            st<double, VEC>(z + i, Z);
+        }
+    }
+    block_partials<2, VEC>(acc, QB, MB, partial);
+}
+
+void launch_inner_out(hipStream_t s, long nrows, int MB, int nm, const float* iz, double* z, const double* Ap,
+                      const double* r, const int* active, double* partial, int* nblk)
+{
+    const int VEC = vec_of(MB), QB = MB / VEC;
+    const int g = grid_for(nrows, 256 / QB);
+    *nblk = g;
+    if (VEC == 4) hipLaunchKernelGGL((k_inner_out<4>), dim3(g), dim3(256), 0, s, nrows, MB, nm, iz, z, Ap, r, active, partial);
+    else hipLaunchKernelGGL((k_inner_out<1>), dim3(g), dim3(256), 0, s, nrows, MB, nm, iz, z, Ap, r, active, partial);
+}
+
+// ---------------------------------------------------------------------------
+// per-member scalar logic: one block per member reduces its partials by a
+// fixed tree, then thread 0 applies the stage
+// ---------------------------------------------------------------------------
+
+__device__ void stage_logic(int stage, int m, const double S[3], CgScalars& cs, double tol2, int maxit)
+{
+    switch (stage) {
+    case FIN_START:  // S = (b.b, r.r, r.z)
+        cs.bb[m] = S[0];
+        cs.rr[m] = S[1];
+        cs.rz[m] = S[2];
+        cs.iters[m] = 0;
+        cs.active[m] = cs.stepping[m] && S[0] > 0.0 && S[1] > tol2 * S[0];
+        break;
+    case FIN_ALPHA:  // S = (p.Ap)
+        cs.pAp[m] = S[0];
+        cs.alpha[m] = cs.active[m] ? cs.rz[m] / S[0] : 0.0;
+        break;
+    case FIN_BETA:  // S = (r.r, r.z)
+        if (cs.active[m]) {
+            cs.iters[m] += 1;
+            cs.rr[m] = S[0];
+            if (S[0] <= tol2 * cs.bb[m]) {
+                cs.active[m] = 0;
+            } else if (cs.iters[m] >= maxit) {
+                cs.active[m] = 0;
+                cs.status[m] = -5;
+            } else {
+                cs.beta[m] = S[1] / cs.rz[m];
+                cs.rz[m] = S[1];
+            }
+        }
+        break;
+    case FIN_FCG_START:  // S = (b.b, r.r, -)
+        cs.bb[m] = S[0];
+        cs.rr[m] = S[1];
+        cs.iters[m] = 0;
+        cs.inner_total[m] = 0;
+        cs.active[m] = cs.stepping[m] && S[0] > 0.0 && S[1] > tol2 * S[0];
+        break;
+    case FIN_FCG_RZ:  // S = (z.Ap, z.r)
+        cs.rz[m] = S[1];
+        break;
+    case FIN_FCG_RR:  // S = (r.r)
+        if (cs.active[m]) {
+            cs.iters[m] += 1;
+            cs.rr[m] = S[0];
+            if (S[0] <= tol2 * cs.bb[m]) cs.active[m] = 0;
+            else if (cs.iters[m] >= maxit) { cs.active[m] = 0; cs.status[m] = -5; }
+        }
+        break;
+    case FIN_FCG_BETA:  // S = (z.Ap, z.r): flexible (Polak-Ribiere) beta
+        if (cs.active[m]) {
+            cs.beta[m] = -cs.alpha[m] * S[0] / cs.rz[m];
+            cs.rz[m] = S[1];
+        }
+        break;
+    case FIN_IN_START:  // S = (ir.ir, ir.w)
+        cs.ir0[m] = S[0];
+        cs.irz[m] = S[1];
+        cs.inner_iters[m] = 0;
+        cs.inner_active[m] = cs.active[m] && S[0] > 0.0;
+        break;
+    case FIN_IN_ALPHA:  // S = (ip.iAp)
+        cs.ialpha[m] = cs.inner_active[m] ? cs.irz[m] / S[0] : 0.0;
+        break;
+    case FIN_IN_BETA:  // S = (ir.ir, ir.w)
+        if (cs.inner_active[m]) {
+            cs.inner_iters[m] += 1;
+            cs.inner_total[m] += 1;
+            if (S[0] <= tol2 * cs.ir0[m] || cs.inner_iters[m] >= maxit) {
+                cs.inner_active[m] = 0;
+            } else {
+                cs.ibeta[m] = S[1] / cs.irz[m];
+                cs.irz[m] = S[1];
+            }
+        }
+        break;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_finalize(int stage, int nd, int MB, int nm, const double* __restrict__ partial,
+                                                 int nblk, CgScalars cs, double tol2, int maxit)
+{
+    const int m = blockIdx.x;
+    if (m >= nm) return;
+    __shared__ double sh[3][256];
+    const int t = threadIdx.x;
+    for (int k = 0; k < 3; ++k) {
+        double a = 0.0;
+        if (k < nd)
+            for (int b = t; b < nblk; b += 256) a += partial[((long)k * nblk + b) * MB + m];
+        sh[k][t] = a;
+    }
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (t < s)
+            for (int k = 0; k < 3; ++k) sh[k][t] += sh[k][t + s];
+        __syncthreads();
+    }
+    if (t == 0) {
+        double S[3] = {sh[0][0], sh[1][0], sh[2][0]};
+        stage_logic(stage, m, S, cs, tol2, maxit);
+    }
+}
+
+void launch_finalize(hipStream_t s, FinalizeStage st, int nd, int MB, int nm, const double* partial, int nblk,
+                     CgScalars cs, double tol2, int maxit)
+{
+    hipLaunchKernelGGL(k_finalize, dim3(nm), dim3(256), 0, s, (int)st, nd, MB, nm, partial, nblk, cs, tol2, maxit);
+}
+
+}  // namespace nlth
+
+namespace nlth {
+
+// members whose right-hand side is zero take du = 0 (Eq. 1 with b = 0)
+template <int VEC>
+__global__ __launch_bounds__(256) void k_zero_if_b0(long nrows, int MB, int nm, double* __restrict__ x,
+                                                   const double* __restrict__ bb, const int* __restrict__ stepping)
+{
+    const int QB = MB / VEC, rpb = 256 / QB;
+    const int t = threadIdx.x, q = t % QB, m0 = q * VEC;
+    bool zero[4], any = false;
+    for (int v = 0; v < VEC; ++v) {
+        const int m = m0 + v;
+        zero[v] = m < nm && stepping[m] && bb[m] == 0.0;
+        any |= zero[v];
+    }
+    if (!any) return;
+    for (long row = (long)blockIdx.x * rpb + t / QB; row < nrows; row += (long)gridDim.x * rpb) {
+        Pk<double, VEC> X = ld<double, VEC>(x + row * MB + m0);
+        for (int v = 0; v < VEC; ++v)
+            if (zero[v]) X.a[v] = 0.0;
+        st<double, VEC>(x + row * MB + m0, X);
+    }
+}
+
+void launch_zero_if_b0(hipStream_t s, long nrows, int MB, int nm, double* x, const double* bb, const int* stepping)
+{
+    const int VEC = vec_of(MB), QB = MB / VEC;
+    const int g = grid_for(nrows, 256 / QB);
+    if (VEC == 4) hipLaunchKernelGGL((k_zero_if_b0<4>), dim3(g), dim3(256), 0, s, nrows, MB, nm, x, bb, stepping);
+    else hipLaunchKernelGGL((k_zero_if_b0<1>), dim3(g), dim3(256), 0, s, nrows, MB, nm, x, bb, stepping);
+}
+
+}  // namespace nlth
