@@ -1,0 +1,216 @@
+"""Benchmark: batched ensemble throughput of the nonlinear time-history hot path.
+
+Workload (one GPU): 64 members on a shared 64x64x32-cube quadratic-tet mesh
+(786,432 tets, 3,244,995 DOF per member), two layers with per-member lognormal
+Vs and uniform gamma_ref, 12 springs per point, independent seeded incident
+waves, FP64 flexible CG with the FP32 block-Jacobi PCG preconditioner, tol 1e-8.
+
+A step is one pass of the whole hot path for all members: right-hand side,
+block-Jacobi diagonal, CG solve, q and Newmark updates, multi-spring law,
+receiver recording.  Inputs are resident in HBM before the timed region.
+
+Prints one JSON line: the mixed-precision throughput (DOF-steps/s summed over
+members), the same members through the plain FP64 path on the same GPU with the
+relative L2 difference of their receiver velocities, the roofline of the
+dominant kernel (the FP32 element-by-element operator) and the CPU oracle
+timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "ensemble DOF-steps/s vs plain FP64 at 1e-6 rel err; p50/p99 solve latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def ebe32_algorithmic_bytes(n_tets: int, n_nodes: int, members_padded: int) -> float:
+    """Algorithmic bytes of one FP32 operator application per element-member:
+    D streamed once (4 points x 21 FP32), x read once and y written once per
+    DOF (attributed per element), connectivity + geometry once per element
+    (shared by the members of a wavefront)."""
+    d = 4 * 21 * 4
+    vec = 2 * 4 * 3 * n_nodes / n_tets
+    mesh = (10 * 4 + 13 * 4 + 4) / members_padded
+    return d + vec + mesh
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "vec.hip"):
+        with open(os.path.join(ROOT, "paper_2604_02755_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(src_hash: str):
+    """HBM bytes per FP32-operator launch from the committed rocprofv3 --pmc
+    summary, if it was taken on the current kernel sources (else None)."""
+    p = os.path.join(ROOT, "profiles", "ebe32_traffic_config2.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as fh:
+        d = json.load(fh)
+    if d.get("kernel_source_hash") != src_hash:
+        return None
+    return d.get("bytes_per_launch")
+
+
+def run_gpu(mesh, prob, warmup, steps, profile):
+    from paper_2604_02755_amd import nlth
+    import torch
+    ctx = nlth.Context(0, use_torch_stream=True)
+    try:
+        mh = ctx.mesh(mesh)
+        ens = ctx.ensemble(mh, mesh, prob)
+        ens.step(warmup)
+        ens.reset_stats()
+        ens.set_profile(profile)
+        st0 = ens.stats()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ens.step(steps)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        st = ens.stats()
+        out = ens.read()
+        ens.close()
+    finally:
+        ctx.close()
+    return elapsed, st0, st, out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--members", type=int, default=64)
+    ap.add_argument("--mesh", type=str, default="64x64x32")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--acc-members", type=int, default=4)
+    ap.add_argument("--acc-steps", type=int, default=150)
+    ap.add_argument("--no-profile", action="store_true", help="no per-launch event timing")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); members shard across GPUs "
+              "with no exchange, so the one-GPU rate is the per-GPU figure", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_2604_02755_amd import inputs as I
+    dims = tuple(int(v) for v in args.mesh.split("x"))
+    n_total = args.warmup + args.steps
+    t0 = time.perf_counter()
+    mesh, prob = I.config(2, n_members=args.members, mesh_dims=dims)
+    # the first warmup+steps samples of the 1500-step records (scaled on the full records)
+    prob.input_acc = np.ascontiguousarray(prob.input_acc[:, :n_total])
+    prob.n_steps = n_total
+    log(f"inputs: {mesh.n_tets} tets, {mesh.n_dof} DOF/member, {args.members} members ({time.perf_counter()-t0:.1f}s)")
+    ndof = mesh.n_dof
+
+    # batched mixed precision (the headline)
+    el, st0, st, out_mixed = run_gpu(mesh, prob, args.warmup, args.steps, not args.no_profile)
+    value = args.members * ndof * args.steps / el
+    log(f"mixed: {el/args.steps*1e3:.1f} ms/step, {value:.3e} DOF-steps/s")
+
+    # roofline of the FP32 element-by-element operator over the timed region
+    inner = out_mixed["iters"][:, args.warmup:n_total, 1].astype(np.int64).sum()
+    roofline = None
+    if st["n_ebe32"] > 0 and st["ms_ebe32"] > 0:
+        per_unit = ebe32_algorithmic_bytes(mesh.n_tets, mesh.n_nodes, st["members_padded"])
+        units = int(inner) * mesh.n_tets  # active element-members over all launches
+        total_bytes = per_unit * units
+        avg_ms = st["ms_ebe32"] / st["n_ebe32"]
+        achieved = total_bytes / (st["ms_ebe32"] * 1e-3) / 1e9
+        src = kernel_source_hash()
+        tb = traffic_from_profile(src)
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": tb,
+                    "kernel": "nlth::k_ebe<float, OP_A, true>",
+                    "launches": int(st["n_ebe32"]), "avg_launch_us": round(avg_ms * 1e3, 2),
+                    "algorithmic_bytes_per_launch": round(total_bytes / st["n_ebe32"], 0),
+                    "bytes_per_element_member": round(per_unit, 1)}
+
+    # plain FP64 on the same GPU, same members and steps
+    fp64 = None
+    if not args.no_fp64:
+        prob64 = I.config(2, n_members=args.members, mesh_dims=dims, precision=I.PRECISION_FP64)[1]
+        prob64.input_acc = np.ascontiguousarray(prob64.input_acc[:, :n_total])
+        prob64.n_steps = n_total
+        el64, _, st64, out64 = run_gpu(mesh, prob64, args.warmup, args.steps, False)
+        v64 = args.members * ndof * args.steps / el64
+        sl = slice(args.warmup, n_total)
+        fp64 = {"value": v64, "ms_per_step": el64 / args.steps * 1e3, "speedup": value / v64,
+                "iters_per_member_step": float(out64["iters"][:, sl, 0].mean())}
+        log(f"fp64: {el64/args.steps*1e3:.1f} ms/step, {v64:.3e} DOF-steps/s")
+        # accuracy of the mixed path against FP64: the first members over a
+        # record long enough for the incident wave to reach the surface
+        na, ns_acc = min(args.members, args.acc_members), args.acc_steps
+        errs = []
+        outs = []
+        for prec in (I.PRECISION_MIXED, I.PRECISION_FP64):
+            pa = I.config(2, n_members=args.members, mesh_dims=dims, precision=prec)[1]
+            for f in ("rho", "vs", "nu", "gamma_ref", "input_acc"):
+                setattr(pa, f, np.ascontiguousarray(getattr(pa, f)[:na]))
+            pa.input_acc = np.ascontiguousarray(pa.input_acc[:, :ns_acc])
+            pa.n_members, pa.n_steps = na, ns_acc
+            outs.append(run_gpu(mesh, pa, 0, ns_acc, False)[3])
+        for m in range(na):
+            a, b = outs[0]["vel"][m], outs[1]["vel"][m]
+            errs.append(float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)))
+        fp64["rel_err_max"] = max(errs)
+        fp64["rel_err_sample"] = f"members 0-{na - 1}, steps 1-{ns_acc}, receiver velocity, relative L2"
+        log(f"mixed vs fp64 over {ns_acc} steps, {na} members: max rel err {max(errs):.2e}")
+
+    # CPU oracle on a bounded sample of the same workload
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        oracle.build()
+        r = oracle.run(mesh, prob, member=0, n_steps=args.cpu_steps)
+        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        cpu = {"value": ndof * args.cpu_steps / r["seconds"], "unit": "DOF-steps/s", "cores": cores,
+               "kind": "oracle",
+               "sample": f"member 0, steps 1-{args.cpu_steps} of the same record on the same mesh "
+                         f"(FP64 CRS-PCG, tol 1e-8, setup included), {r['seconds']:.1f} s"}
+        log(f"cpu oracle: {cpu['value']:.3e} DOF-steps/s on {cores} threads")
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "DOF-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32",
+        "data": "synthetic (seeded meshes, layer properties and band-limited input waves)",
+        "config": {"workload": f"batched ensemble: {args.members} members on a {args.mesh}-cube tet10 mesh, "
+                               f"12 springs/point, mixed FP64/FP32 CG, tol 1e-8",
+                   "members": args.members, "dof_per_member": ndof, "tets": mesh.n_tets,
+                   "parallelism": "members batched in one launch"},
+        "iterations": {"outer_per_member_step": float(out_mixed["iters"][:, args.warmup:n_total, 0].mean()),
+                       "inner_per_member_step": float(out_mixed["iters"][:, args.warmup:n_total, 1].mean())},
+        "phase_ms": {"ebe64": st["ms_ebe64"], "ebe32": st["ms_ebe32"], "law": st["ms_law"],
+                     "rhs_diag_q": st["ms_other"]} if not args.no_profile else None,
+        "fp64_plain": fp64,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

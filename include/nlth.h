@@ -57,6 +57,11 @@ extern "C" {
 #define NLTH_FP64 0
 #define NLTH_MIXED 1
 
+/* storage of D for the inner FP32 operator of NLTH_MIXED: bfloat16 (half the
+ * bytes; the outer FP64 iteration keeps the solution at FP64 tolerance) or FP32 */
+#define NLTH_INNER_BF16 0
+#define NLTH_INNER_FP32 1
+
 /* operator selector for nlth_apply_operator */
 #define NLTH_OP_A 0 /* 4/dt^2 M + 2/dt C + K (Eq. 1 left-hand side) */
 #define NLTH_OP_K 1 /* K */
@@ -162,6 +167,7 @@ typedef struct {
     int32_t precision;         /* NLTH_FP64 or NLTH_MIXED */
     double inner_tol;
     int32_t inner_maxit;
+    int32_t inner_dtype;       /* NLTH_INNER_BF16 (default) or NLTH_INNER_FP32 */
 } nlth_problem;
 
 /* Result buffers (caller-owned host memory; NULL fields are skipped).
@@ -221,7 +227,8 @@ int nlth_cancel(nlth_ctx* ctx, uint64_t ticket);
 
 /* Diagnostic: one element-by-element operator application y = Op x for
  * member 0 of `prob` (Eq. 1 left-hand side with K from the given D and C from
- * the given h), on the device, in FP64 or FP32 (precision).  D_ip:
+ * the given h), on the device, in FP64 or (precision = NLTH_MIXED) the inner
+ * FP32 operator with D stored as prob->inner_dtype says.  D_ip:
  * [n_tets*4*21] upper triangle of D row by row per integration point (input
  * tet order); h: [n_tets] element damping (NULL = 0); x, y: [3*n_nodes]. */
 int nlth_apply_operator(nlth_ctx* ctx, const nlth_mesh* mesh, const nlth_problem* prob, int32_t which,

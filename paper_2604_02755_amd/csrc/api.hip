@@ -453,6 +453,9 @@ void copy_problem(const nlth_problem* in, Problem& P)
     P.precision = in->precision;
     P.inner_tol = in->inner_tol;
     P.inner_maxit = in->inner_maxit;
+    if (in->inner_dtype != NLTH_INNER_BF16 && in->inner_dtype != NLTH_INNER_FP32)
+        throw Error{NLTH_EINVAL, "problem: inner_dtype must be NLTH_INNER_BF16 or NLTH_INNER_FP32"};
+    P.inner_dtype = in->inner_dtype;
 }
 
 // least-squares Rayleigh fit: minimise int (a/(4 pi f) + pi b f - 1)^2 df over [f_lo, f_hi]
@@ -476,7 +479,8 @@ int64_t ensemble_bytes(const Mesh& m, const Problem& p, int MB, bool paged)
     int64_t bytes = 10 * v;                                  // u v a q du b r z p Ap
     bytes += 2 * (int64_t)m.nn * 6 * MB * 8 + (int64_t)m.nn * 6 * MB * 4;  // diag, pinv, pinv32
     if (p.precision == NLTH_MIXED) bytes += 5 * ndof * MB * 4;
-    bytes += (int64_t)m.ne * 4 * 21 * MB * 12;              // D64 + D32
+    bytes += (int64_t)m.ne * 4 * 21 * MB * 8;               // D64
+    if (p.precision == NLTH_MIXED) bytes += (int64_t)m.ne * 4 * (p.inner_dtype == NLTH_INNER_FP32 ? 84 : 44) * MB;
     bytes += (int64_t)m.ne * MB * 8;                        // h
     bytes += (int64_t)p.n_steps * std::max(1, m.nrecv) * 3 * MB * 8;  // receiver history
     bytes += (int64_t)p.n_steps * 3 * MB * 8 * 2;           // acc, vI
@@ -603,11 +607,12 @@ void Ens::create(Ctx* c, const Mesh* m, const Problem& prob, int member_pad)
     ne_pad = (m->ne + EB - 1) / EB * EB;
     const size_t nD = (size_t)ne_pad * 4 * 21 * MB;
     D64.alloc(bg, nD * 8);
-    D32.alloc(bg, nD * 4);
+    if (P.precision == NLTH_MIXED && P.inner_dtype == NLTH_INNER_FP32) D32.alloc(bg, nD * 4);
+    if (P.precision == NLTH_MIXED && P.inner_dtype == NLTH_INNER_BF16) D16.alloc(bg, (size_t)ne_pad * 4 * 11 * MB * 4);
     h.alloc(bg, (size_t)m->ne * MB * 8);
     const DevMesh dm = m->dev();
     launch_law_init(s, dm, MB, MB, mat.as<double>(), P.nl, P.ns, dirs.as<double>(), w.as<double>(),
-                    D64.as<double>(), D32.as<float>(), h.as<double>());
+                    D64.as<double>(), D32.as<float>(), D16.as<uint32_t>(), h.as<double>());
 
     // law state: resident if it fits the remaining budget, else paged
     const size_t per_elem = (size_t)4 * P.ns * MB * 40;
@@ -738,8 +743,8 @@ void Ens::ebe32(const float* x, float* y, const int* act)
         const int e0 = mesh->color_off[c], e1 = mesh->color_off[c + 1];
         hipEvent_t t0;
         tstart(t0);
-        launch_ebe<float>(s, OP_A, dm, MB, nm, e0, e1, D32.as<float>(), h.as<double>(), mat.as<double>(), P.nl, sc,
-                          x, nullptr, y, act);
+        launch_ebe32(s, dm, MB, nm, e0, e1, D32.as<float>(), D16.as<uint32_t>(), h.as<double>(), mat.as<double>(), sc,
+                     x, y, act);
         tstop(t0, &pc_ebe32, (int64_t)(e1 - e0) * nm);
     }
     launch_dashpot<float>(s, dm, MB, nm, mat.as<double>(), P.nl, (float)(2.0 / P.dt), x, y, nullptr, act);
@@ -899,7 +904,7 @@ void Ens::law_phase()
         hipEvent_t t0;
         tstart(t0);
         launch_law(s, dm, MB, nm, 0, mesh->ne, ne_pad, mat.as<double>(), P.nl, nonlinear.as<int>(), P.ns, dirs.as<double>(),
-                   w.as<double>(), du.as<double>(), theta.p, D64.as<double>(), D32.as<float>(), h.as<double>(),
+                   w.as<double>(), du.as<double>(), theta.p, D64.as<double>(), D32.as<float>(), D16.as<uint32_t>(), h.as<double>(),
                    stepping.as<int>());
         tstop(t0, &pc_law, (int64_t)mesh->ne * nm);
         return;
@@ -922,7 +927,7 @@ void Ens::law_phase()
         hipEvent_t t0;
         tstart(t0);
         launch_law(s, dm, MB, nm, chunk_e0[cix], chunk_ec[cix], chunk_ecp[cix], mat.as<double>(), P.nl, nonlinear.as<int>(), P.ns,
-                   dirs.as<double>(), w.as<double>(), du.as<double>(), dslot, D64.as<double>(), D32.as<float>(),
+                   dirs.as<double>(), w.as<double>(), du.as<double>(), dslot, D64.as<double>(), D32.as<float>(), D16.as<uint32_t>(),
                    h.as<double>(), stepping.as<int>());
         tstop(t0, &pc_law, (int64_t)chunk_ec[cix] * nm);
         NLTH_HIP(hipEventRecord(ev_law[slot], s));
@@ -1298,6 +1303,11 @@ int nlth_apply_operator(nlth_ctx* ctx, const nlth_mesh* mesh, const nlth_problem
     nlth_problem p1 = *prob;
     p1.n_members = 1;
     p1.n_steps = 0;
+    p1.precision = precision;  // allocates the inner operator's D storage for NLTH_MIXED
+    if (precision == NLTH_MIXED) {
+        if (!(p1.inner_tol > 0)) p1.inner_tol = 0.1;
+        if (p1.inner_maxit <= 0) p1.inner_maxit = 1;
+    }
     copy_problem(&p1, P);
     std::unique_ptr<nlth_ens> e(new nlth_ens());
     e->create(ctx, mesh, P);
@@ -1312,9 +1322,29 @@ int nlth_apply_operator(nlth_ctx* ctx, const nlth_mesh* mesh, const nlth_problem
                 Dd[((size_t)(pos / EB) * 84 + j * 21 + k) * EB + pos % EB] = D_ip[(size_t)e0 * 84 + j * 21 + k];
         if (hh) hd[pos] = hh[e0];
     }
-    std::vector<float> Df(Dd.begin(), Dd.end());
     NLTH_HIP(hipMemcpy(e->D64.p, Dd.data(), Dd.size() * 8, hipMemcpyHostToDevice));
-    NLTH_HIP(hipMemcpy(e->D32.p, Df.data(), Df.size() * 4, hipMemcpyHostToDevice));
+    if (e->D32.p) {
+        std::vector<float> Df(Dd.begin(), Dd.end());
+        NLTH_HIP(hipMemcpy(e->D32.p, Df.data(), Df.size() * 4, hipMemcpyHostToDevice));
+    }
+    if (e->D16.p) {  // bfloat16 pairs, round to nearest even on the FP32 bits
+        auto bf = [](double x) {
+            float f = (float)x;
+            uint32_t u;
+            memcpy(&u, &f, 4);
+            return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+        };
+        std::vector<uint32_t> Dh((size_t)e->ne_pad * 44, 0u);
+        for (int pos = 0; pos < ne; ++pos)
+            for (int j = 0; j < 4; ++j)
+                for (int q = 0; q < 11; ++q) {
+                    const size_t src = ((size_t)(pos / EB) * 84 + j * 21) * EB + pos % EB;
+                    const uint32_t lo = bf(Dd[src + (size_t)(2 * q) * EB]);
+                    const uint32_t hi = (2 * q + 1 < 21) ? bf(Dd[src + (size_t)(2 * q + 1) * EB]) : 0u;
+                    Dh[((size_t)(pos / EB) * 44 + j * 11 + q) * EB + pos % EB] = lo | (hi << 16);
+                }
+        NLTH_HIP(hipMemcpy(e->D16.p, Dh.data(), Dh.size() * 4, hipMemcpyHostToDevice));
+    }
     NLTH_HIP(hipMemcpy(e->h.p, hd.data(), hd.size() * 8, hipMemcpyHostToDevice));
     const long n = 3L * nn;
     int one = 1;

@@ -182,11 +182,26 @@ __device__ __forceinline__ long d_index(long e, int j, int k, int MB, int EB, in
     return (((e / EB) * 84 + j * 21 + k) * EB + e % EB) * (long)MB + m;
 }
 
+// bfloat16 storage of D for the inner operator: pairs of consecutive upper-
+// triangle entries (k = 2q, 2q+1; k = 21 is padding) packed in one 32-bit word
+__device__ __forceinline__ long d16_index(long e, int j, int q, int MB, int EB, int m)
+{
+    return (((e / EB) * 44 + j * 11 + q) * EB + e % EB) * (long)MB + m;
+}
+__device__ __forceinline__ uint32_t f2bf(double x)
+{
+    // round to nearest even on the FP32 bit pattern
+    const uint32_t u = __float_as_uint((float)x);
+    return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+__device__ __forceinline__ float bf2f(uint32_t b) { return __uint_as_float(b << 16); }
+
 constexpr int kEdgeOpp[6] = {5, 3, 4, 1, 2, 0};  // edge opposite each edge
 
-template <typename T, int MODE, bool WAVE_ELEM>
+// DK: storage of D, 0 = T itself, 1 = bfloat16 pairs (uint32 words)
+template <typename T, int DK, int MODE, bool WAVE_ELEM>
 __global__ __launch_bounds__(256) void k_ebe(DevMesh M, int MB, int nm, int e0, int e1,
-                                            const T* __restrict__ D, const double* __restrict__ h,
+                                            const void* __restrict__ Dv, const double* __restrict__ h,
                                             const double* __restrict__ mat, StepConst sc,
                                             const T* __restrict__ x1, const T* __restrict__ x2,
                                             T* __restrict__ y, const int* __restrict__ active)
@@ -226,18 +241,23 @@ __global__ __launch_bounds__(256) void k_ebe(DevMesh M, int MB, int nm, int e0, 
         sk = (T)(sc.bhat * he);
         cv = (T)(4.0 / dt + sc.ahat * he);
     }
+    // addresses: a base per node (wave-uniform when a wavefront is one element)
+    // plus a 32-bit lane offset, so loads use a scalar base and no 64-bit math
+    size_t nbase[10];
+#pragma unroll
+    for (int n = 0; n < 10; ++n) nbase[n] = (size_t)nodes[n] * 3 * MB;
     T xk[10][3];
     T f[10][3];
     // ---- mass: consistent P2 mass applied through corner/edge sums
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         T xm[10];
+        const uint32_t off = (uint32_t)(c * MB + m);
 #pragma unroll
         for (int n = 0; n < 10; ++n) {
-            const long idx = ((long)nodes[n] * 3 + c) * MB + m;
-            const T v1 = x1[idx];
+            const T v1 = (x1 + nbase[n])[off];
             xk[n][c] = v1;
-            xm[n] = (MODE == OP_RHS) ? x2[idx] + cv * v1 : v1;
+            xm[n] = (MODE == OP_RHS) ? (x2 + nbase[n])[off] + cv * v1 : v1;
         }
         if (MODE == OP_K) {
 #pragma unroll
@@ -293,9 +313,24 @@ __global__ __launch_bounds__(256) void k_ebe(DevMesh M, int MB, int nm, int e0, 
             T eps[6], sg[6];
 #pragma unroll
             for (int q = 0; q < 6; ++q) eps[q] = (T)QB_ * S[q] + c1 * Ek[j][q];
-            T d[21];
+            T d[22];
+            // element base (uniform per wavefront) + 32-bit row offsets
+            const size_t eb = (size_t)(e / EB) * EB, ei = (size_t)(e % EB);
+            const uint32_t rs = (uint32_t)(EB * MB);  // stride between rows (j, k)
+            if constexpr (DK == 0) {
+                const T* D = (const T*)Dv + (eb * 84 + ei) * MB;
 #pragma unroll
-            for (int k = 0; k < 21; ++k) d[k] = __builtin_nontemporal_load(&D[d_index(e, j, k, MB, EB, m)]);
+                for (int k = 0; k < 21; ++k)
+                    d[k] = __builtin_nontemporal_load(&D[(uint32_t)(j * 21 + k) * rs + (uint32_t)m]);
+            } else {
+                const uint32_t* D = (const uint32_t*)Dv + (eb * 44 + ei) * MB;
+#pragma unroll
+                for (int q = 0; q < 11; ++q) {
+                    const uint32_t wv = __builtin_nontemporal_load(&D[(uint32_t)(j * 11 + q) * rs + (uint32_t)m]);
+                    d[2 * q] = (T)bf2f(wv & 0xFFFFu);
+                    d[2 * q + 1] = (T)bf2f(wv >> 16);
+                }
+            }
 #pragma unroll
             for (int r = 0; r < 6; ++r) {
                 T a = 0;
@@ -321,12 +356,11 @@ __global__ __launch_bounds__(256) void k_ebe(DevMesh M, int MB, int nm, int e0, 
         }
     }
 #pragma unroll
-    for (int n = 0; n < 10; ++n)
+    for (int n = 0; n < 10; ++n) {
+        T* yb = y + nbase[n];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const long idx = ((long)nodes[n] * 3 + c) * MB + m;
-            y[idx] += f[n][c];
-        }
+        for (int c = 0; c < 3; ++c) yb[(uint32_t)(c * MB + m)] += f[n][c];
+    }
 }
 
 template <typename T, int MODE>
@@ -335,9 +369,27 @@ static void ebe_dispatch(hipStream_t s, dim3 g, const DevMesh& M, int MB, int nm
                          const int* active)
 {
     if (MB >= 64)
-        hipLaunchKernelGGL((k_ebe<T, MODE, true>), g, dim3(256), 0, s, M, MB, nm, e0, e1, D, h, mat, sc, x1, x2, y, active);
+        hipLaunchKernelGGL((k_ebe<T, 0, MODE, true>), g, dim3(256), 0, s, M, MB, nm, e0, e1, (const void*)D, h, mat, sc, x1, x2, y, active);
     else
-        hipLaunchKernelGGL((k_ebe<T, MODE, false>), g, dim3(256), 0, s, M, MB, nm, e0, e1, D, h, mat, sc, x1, x2, y, active);
+        hipLaunchKernelGGL((k_ebe<T, 0, MODE, false>), g, dim3(256), 0, s, M, MB, nm, e0, e1, (const void*)D, h, mat, sc, x1, x2, y, active);
+}
+
+// inner FP32 operator (Eq. 1 left-hand side) with D stored in FP32 or bfloat16
+void launch_ebe32(hipStream_t s, const DevMesh& M, int MB, int nm, int e0, int e1, const float* D32,
+                  const uint32_t* D16, const double* h, const double* mat, StepConst sc, const float* x, float* y,
+                  const int* active)
+{
+    long n = (long)(e1 - e0) * MB;
+    if (n <= 0) return;
+    dim3 g(nblocks(n));
+    if (D16) {
+        if (MB >= 64)
+            hipLaunchKernelGGL((k_ebe<float, 1, OP_A, true>), g, dim3(256), 0, s, M, MB, nm, e0, e1, (const void*)D16, h, mat, sc, x, nullptr, y, active);
+        else
+            hipLaunchKernelGGL((k_ebe<float, 1, OP_A, false>), g, dim3(256), 0, s, M, MB, nm, e0, e1, (const void*)D16, h, mat, sc, x, nullptr, y, active);
+    } else {
+        ebe_dispatch<float, OP_A>(s, g, M, MB, nm, e0, e1, D32, h, mat, sc, x, nullptr, y, active);
+    }
 }
 
 template <typename T>
@@ -628,10 +680,32 @@ void launch_theta_init(hipStream_t s, void* base, long ecp, int ns, int MB)
     if (n > 0) hipLaunchKernelGGL(k_theta_init, dim3(nblocks(n)), dim3(256), 0, s, base, ecp, ns, MB);
 }
 
+// write D of point j in FP64 and in the inner operator's storage (FP32 or
+// bfloat16 pairs, whichever is allocated)
+__device__ __forceinline__ void store_D(const double d[21], long e, int j, int MB, int EB, int m,
+                                        double* __restrict__ D, float* __restrict__ D32, uint32_t* __restrict__ D16)
+{
+#pragma unroll
+    for (int k = 0; k < 21; ++k) {
+        const long idx = d_index(e, j, k, MB, EB, m);
+        D[idx] = d[k];
+        if (D32) D32[idx] = (float)d[k];
+    }
+    if (D16) {
+#pragma unroll
+        for (int q = 0; q < 11; ++q) {
+            const uint32_t lo = f2bf(d[2 * q]);
+            const uint32_t hi = (2 * q + 1 < 21) ? f2bf(d[2 * q + 1]) : 0u;
+            D16[d16_index(e, j, q, MB, EB, m)] = lo | (hi << 16);
+        }
+    }
+}
+
 // D of a point from the spring tangents: Kb m m^T + sum c_k G_k n_k n_k^T
 __global__ void k_law_init(DevMesh M, int MB, int nm, const double* __restrict__ mat, int ns,
                            const double* __restrict__ dirs, const double* __restrict__ w,
-                           double* __restrict__ D, float* __restrict__ D32, double* __restrict__ h)
+                           double* __restrict__ D, float* __restrict__ D32, uint32_t* __restrict__ D16,
+                           double* __restrict__ h)
 {
     const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
     const int m = (int)(t % MB);
@@ -650,20 +724,16 @@ __global__ void k_law_init(DevMesh M, int MB, int nm, const double* __restrict__
     }
     for (int r = 0; r < 3; ++r)
         for (int q = r; q < 3; ++q) d[sym6(r, q)] += Kb;
-    for (int j = 0; j < 4; ++j)
-        for (int k = 0; k < 21; ++k) {
-            const long idx = d_index(e, j, k, MB, EB, m);
-            D[idx] = d[k];
-            D32[idx] = (float)d[k];
-        }
+    for (int j = 0; j < 4; ++j) store_D(d, e, j, MB, EB, m, D, D32, D16);
     h[e * MB + m] = 0.0;
 }
 
 void launch_law_init(hipStream_t s, const DevMesh& M, int MB, int nm, const double* mat, int, int ns,
-                     const double* dirs, const double* w, double* D, float* D32, double* h)
+                     const double* dirs, const double* w, double* D, float* D32, uint32_t* D16, double* h)
 {
     long n = (long)M.ne * MB;
-    if (n > 0) hipLaunchKernelGGL(k_law_init, dim3(nblocks(n)), dim3(256), 0, s, M, MB, nm, mat, ns, dirs, w, D, D32, h);
+    if (n > 0)
+        hipLaunchKernelGGL(k_law_init, dim3(nblocks(n)), dim3(256), 0, s, M, MB, nm, mat, ns, dirs, w, D, D32, D16, h);
 }
 
 // One lane per (element, member) of the chunk [e0, e0 + ec): strain
@@ -674,7 +744,8 @@ __global__ __launch_bounds__(256) void k_law(DevMesh M, int MB, int nm, int e0, 
                                             int ns, const double* __restrict__ dirs,
                                             const double* __restrict__ w, const double* __restrict__ du,
                                             void* theta, double* __restrict__ D, float* __restrict__ D32,
-                                            double* __restrict__ h, const int* __restrict__ stepping)
+                                            uint32_t* __restrict__ D16, double* __restrict__ h,
+                                            const int* __restrict__ stepping)
 {
     const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
     const int m = (int)(t % MB);
@@ -765,12 +836,7 @@ __global__ __launch_bounds__(256) void k_law(DevMesh M, int MB, int nm, int e0, 
         for (int r = 0; r < 3; ++r)
 #pragma unroll
             for (int q = r; q < 3; ++q) d[sym6(r, q)] += Kb;
-#pragma unroll
-        for (int k = 0; k < 21; ++k) {
-            const long idx = d_index(e, j, k, MB, EB, m);
-            D[idx] = d[k];
-            D32[idx] = (float)d[k];
-        }
+        store_D(d, e, j, MB, EB, m, D, D32, D16);
         hsum += hs / ns;
     }
     h[e * MB + m] = 0.25 * hsum;
@@ -778,12 +844,12 @@ __global__ __launch_bounds__(256) void k_law(DevMesh M, int MB, int nm, int e0, 
 
 void launch_law(hipStream_t s, const DevMesh& M, int MB, int nm, int e0, int ec, long ecp, const double* mat, int,
                 const int* nonlinear, int ns, const double* dirs, const double* w, const double* du,
-                void* theta, double* D, float* D32, double* h, const int* stepping)
+                void* theta, double* D, float* D32, uint32_t* D16, double* h, const int* stepping)
 {
     long n = (long)ec * MB;
     if (n > 0)
         hipLaunchKernelGGL(k_law, dim3(nblocks(n)), dim3(256), 0, s, M, MB, nm, e0, ec, ecp, mat, nonlinear, ns, dirs,
-                           w, du, theta, D, D32, h, stepping);
+                           w, du, theta, D, D32, D16, h, stepping);
 }
 
 // ---------------------------------------------------------------------------

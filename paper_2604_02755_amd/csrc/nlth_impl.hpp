@@ -78,11 +78,16 @@ void launch_invert_diag(hipStream_t s, int nn, int MB, int nm, const double* dia
 
 // law
 void launch_law_init(hipStream_t s, const DevMesh& M, int MB, int nm, const double* mat, int n_layers,
-                     int ns, const double* dirs, const double* w, double* D, float* D32, double* h);
+                     int ns, const double* dirs, const double* w, double* D, float* D32, uint32_t* D16,
+                     double* h);
+// inner FP32 operator (A) with D in FP32 (D32) or bfloat16 pairs (D16, if non-null)
+void launch_ebe32(hipStream_t s, const DevMesh& M, int MB, int nm, int e0, int e1, const float* D32,
+                  const uint32_t* D16, const double* h, const double* mat, StepConst sc, const float* x, float* y,
+                  const int* active);
 void launch_theta_init(hipStream_t s, void* theta_chunk, long ecp, int ns, int MB);
 void launch_law(hipStream_t s, const DevMesh& M, int MB, int nm, int e0, int ec, long ecp, const double* mat,
                 int n_layers, const int* nonlinear, int ns, const double* dirs, const double* w,
-                const double* du, void* theta_chunk, double* D, float* D32, double* h,
+                const double* du, void* theta_chunk, double* D, float* D32, uint32_t* D16, double* h,
                 const int* stepping);
 
 // ---- CG vectors (vec.hip): partial sums go to partial[(k*nblk + blk)*MB + m]

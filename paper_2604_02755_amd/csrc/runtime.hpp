@@ -75,7 +75,7 @@ struct Problem {  // host copy of an nlth_problem
     std::vector<int> nonlinear;
     int damping_mode = 0;
     double h0 = 0, f_lo = 0.1, f_hi = 10, dt = 1e-3, cg_tol = 1e-8, inner_tol = 0.1;
-    int cg_maxit = 1000, precision = 0, inner_maxit = 50;
+    int cg_maxit = 1000, precision = 0, inner_maxit = 50, inner_dtype = 0;
 };
 
 struct ProfCat { double ms = 0; int64_t n = 0; int64_t elems = 0; };
@@ -92,7 +92,7 @@ struct Ens {
     DevBuf mat, dirs, w, nonlinear, acc, vI_all, vI_cur;
     DevBuf u, v, a, q, du, b, r, z, p, Ap, diag, pinv, pinv32;
     DevBuf ir, iz, ip, iw, iAp;
-    DevBuf D64, D32, h;
+    DevBuf D64, D32, D16, h;             // D16: bfloat16 pairs for the inner operator
     DevBuf theta;                       // resident law state (or the device chunk ring)
     DevBuf theta_host;                  // pinned host state when paged
     DevBuf hist, vmax, iters_dev;

@@ -354,6 +354,7 @@ class Problem:
     precision: int = PRECISION_FP64
     inner_tol: float = 0.1
     inner_maxit: int = 50
+    inner_dtype: int = 0   # 0: bfloat16 D for the inner operator, 1: FP32
 
     @property
     def n_springs(self) -> int:

@@ -30,6 +30,7 @@ NLTH_ECANCELED = -7
 NLTH_ETIMEDOUT = -8
 NLTH_ENOTFOUND = -9
 NLTH_FP64, NLTH_MIXED = 0, 1
+NLTH_INNER_BF16, NLTH_INNER_FP32 = 0, 1
 NLTH_OP_A, NLTH_OP_K, NLTH_OP_M = 0, 1, 2
 NLTH_DEVICE_NONE = -1
 
@@ -60,7 +61,8 @@ class nlth_problem(C.Structure):
                 ("damping_mode", C.c_int32), ("h0", C.c_double), ("f_lo", C.c_double),
                 ("f_hi", C.c_double), ("dt", C.c_double), ("n_steps", C.c_int32),
                 ("input_acc", _dp), ("cg_tol", C.c_double), ("cg_maxit", C.c_int32),
-                ("precision", C.c_int32), ("inner_tol", C.c_double), ("inner_maxit", C.c_int32)]
+                ("precision", C.c_int32), ("inner_tol", C.c_double), ("inner_maxit", C.c_int32),
+                ("inner_dtype", C.c_int32)]
 
 
 class nlth_result(C.Structure):
@@ -216,7 +218,8 @@ def _problem_struct(prob, keep, members=None, n_steps=None):
                         _ptr(hm), _ptr(nl, _ip), int(dirs.shape[0]), _ptr(dirs), _ptr(w),
                         int(prob.damping_mode), float(prob.h0), float(prob.f_lo), float(prob.f_hi),
                         float(prob.dt), ns, _ptr(acc), float(prob.cg_tol), int(prob.cg_maxit),
-                        int(prob.precision), float(prob.inner_tol), int(prob.inner_maxit))
+                        int(prob.precision), float(prob.inner_tol), int(prob.inner_maxit),
+                        int(getattr(prob, "inner_dtype", 0)))
 
 
 def _result_buffers(nm, ns, nrecv):

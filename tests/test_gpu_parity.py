@@ -48,10 +48,16 @@ def test_operator_parity(gpu_ctx, oracle_lib, dims):
         say("  op", which, "fp64 rel err", err)
         assert err < 1e-13
     y_ref = oracle_lib.apply_operator(mesh, prob, 0, D, h, x)
+    prob.inner_dtype = 1  # FP32 D
     y32 = gpu_ctx.apply_operator(mh, prob, 0, 1, D, h, x)
     err = np.linalg.norm(y32 - y_ref) / np.linalg.norm(y_ref)
     say("  op A fp32 rel err", err)
     assert err < 2e-6
+    prob.inner_dtype = 0  # bfloat16 D (the inner preconditioner's default): 8-bit mantissa
+    y16 = gpu_ctx.apply_operator(mh, prob, 0, 1, D, h, x)
+    err = np.linalg.norm(y16 - y_ref) / np.linalg.norm(y_ref)
+    say("  op A fp32/bf16-D rel err", err)
+    assert err < 4e-3
 
 
 def _small_problem(n_steps=40, precision=0, tol=1e-12, n_members=1, dims=(5, 4, 3), scale=5.0, ns=150):
