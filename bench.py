@@ -38,12 +38,13 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def ebe32_algorithmic_bytes(n_tets: int, n_nodes: int, members_padded: int) -> float:
-    """Algorithmic bytes of one FP32 operator application per element-member:
-    D streamed once (4 points x 21 FP32), x read once and y written once per
-    DOF (attributed per element), connectivity + geometry once per element
-    (shared by the members of a wavefront)."""
-    d = 4 * 21 * 4
+def ebe32_algorithmic_bytes(n_tets: int, n_nodes: int, members_padded: int, inner_dtype: int = 0) -> float:
+    """Algorithmic bytes of one inner (FP32) operator application per
+    element-member: D streamed once (4 points x 21 entries, as 11 bfloat16
+    pairs per point = 176 B, or 84 FP32 = 336 B), x read once and y written
+    once per DOF (attributed per element), connectivity + geometry once per
+    element (shared by the members of a wavefront)."""
+    d = 4 * 11 * 4 if inner_dtype == 0 else 4 * 21 * 4
     vec = 2 * 4 * 3 * n_nodes / n_tets
     mesh = (10 * 4 + 13 * 4 + 4) / members_padded
     return d + vec + mesh
@@ -133,7 +134,7 @@ def main():
     inner = out_mixed["iters"][:, args.warmup:n_total, 1].astype(np.int64).sum()
     roofline = None
     if st["n_ebe32"] > 0 and st["ms_ebe32"] > 0:
-        per_unit = ebe32_algorithmic_bytes(mesh.n_tets, mesh.n_nodes, st["members_padded"])
+        per_unit = ebe32_algorithmic_bytes(mesh.n_tets, mesh.n_nodes, st["members_padded"], prob.inner_dtype)
         units = int(inner) * mesh.n_tets  # active element-members over all launches
         total_bytes = per_unit * units
         avg_ms = st["ms_ebe32"] / st["n_ebe32"]
@@ -143,7 +144,7 @@ def main():
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4),
                     "traffic": tb,
-                    "kernel": "nlth::k_ebe<float, OP_A, true>",
+                    "kernel": "nlth::k_ebe<float, 1, 0, true> (inner operator, bfloat16 D)",
                     "launches": int(st["n_ebe32"]), "avg_launch_us": round(avg_ms * 1e3, 2),
                     "algorithmic_bytes_per_launch": round(total_bytes / st["n_ebe32"], 0),
                     "bytes_per_element_member": round(per_unit, 1)}

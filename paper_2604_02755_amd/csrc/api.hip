@@ -1027,6 +1027,7 @@ Ctx::~Ctx()
     }
     scv.notify_all();
     if (worker.joinable()) worker.join();
+    serve_shutdown(this);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
 }
 

@@ -705,11 +705,11 @@ __device__ __forceinline__ void store_D(const double d[21], long e, int j, int M
 __global__ void k_law_init(DevMesh M, int MB, int nm, const double* __restrict__ mat, int ns,
                            const double* __restrict__ dirs, const double* __restrict__ w,
                            double* __restrict__ D, float* __restrict__ D32, uint32_t* __restrict__ D16,
-                           double* __restrict__ h)
+                           double* __restrict__ h, int only_m)
 {
     const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    const int m = (int)(t % MB);
-    const long e = t / MB;
+    const int m = only_m >= 0 ? only_m : (int)(t % MB);
+    const long e = only_m >= 0 ? t : t / MB;
     if (e >= M.ne || m >= nm) return;
     const int EB = MB >= 64 ? 1 : 64 / MB;
     const int l = M.layer[e];
@@ -729,11 +729,46 @@ __global__ void k_law_init(DevMesh M, int MB, int nm, const double* __restrict__
 }
 
 void launch_law_init(hipStream_t s, const DevMesh& M, int MB, int nm, const double* mat, int, int ns,
-                     const double* dirs, const double* w, double* D, float* D32, uint32_t* D16, double* h)
+                     const double* dirs, const double* w, double* D, float* D32, uint32_t* D16, double* h,
+                     int only_m)
 {
-    long n = (long)M.ne * MB;
+    long n = only_m >= 0 ? (long)M.ne : (long)M.ne * MB;
     if (n > 0)
-        hipLaunchKernelGGL(k_law_init, dim3(nblocks(n)), dim3(256), 0, s, M, MB, nm, mat, ns, dirs, w, D, D32, D16, h);
+        hipLaunchKernelGGL(k_law_init, dim3(nblocks(n)), dim3(256), 0, s, M, MB, nm, mat, ns, dirs, w, D, D32, D16, h,
+                           only_m);
+}
+
+// reset the law state of one member (serving: a new request takes the slot)
+__global__ void k_theta_reset_member(void* base, long ecp, int ns, int MB, int m)
+{
+    ThetaView v = theta_view(base, ecp, ns, MB);
+    const long n = ecp * 4 * (long)ns;  // (element, spring, point) triples
+    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const long el = t / (4L * ns);
+    const int s = (int)((t / 4) % ns), j = (int)(t % 4);
+    const long idx = v.at(el, s, j, m);
+    for (int f = 0; f < 4; ++f) v.d[f * v.field_n + idx] = 0.0;
+    v.i[idx] = 0;
+    v.i[v.field_n + idx] = 1;
+}
+
+void launch_theta_reset_member(hipStream_t s, void* base, long ecp, int ns, int MB, int m)
+{
+    long n = ecp * 4 * (long)ns;
+    if (n > 0) hipLaunchKernelGGL(k_theta_reset_member, dim3(nblocks(n)), dim3(256), 0, s, base, ecp, ns, MB, m);
+}
+
+// zero column m of a member-innermost array with `rows` rows
+__global__ void k_zero_member(double* p, long rows, int MB, int m)
+{
+    const long r = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (r < rows) p[r * MB + m] = 0.0;
+}
+
+void launch_zero_member(hipStream_t s, double* p, long rows, int MB, int m)
+{
+    if (rows > 0) hipLaunchKernelGGL(k_zero_member, dim3(nblocks(rows)), dim3(256), 0, s, p, rows, MB, m);
 }
 
 // One lane per (element, member) of the chunk [e0, e0 + ec): strain

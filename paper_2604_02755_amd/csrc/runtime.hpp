@@ -65,7 +65,7 @@ struct Mesh {
     // device
     DevBuf conn, geo64, geo32, layer, bn_node, bn_ptr, bn_face, bn_loc, f_node, f_M, f_n, f_layer, f_kind, recv_d;
     int nbn = 0;
-    std::atomic<int> refs{0};
+    mutable std::atomic<int> refs{0};  // pending requests using the mesh
     DevMesh dev() const;
 };
 
@@ -188,8 +188,11 @@ struct Request {
     std::atomic<int> state{0};  // 0 queued, 1 running, 2 done, 3 cancelled
     std::atomic<int> cancel{0};
     int status = 0;
+    int members_left = 0;  // guarded by the context's request lock
     int64_t need_bytes = 0;
 };
+
+void serve_shutdown(Ctx* c);
 
 void set_error(Ctx* c, const Error& e);
 int64_t ensemble_bytes(const Mesh& m, const Problem& p, int MB, bool paged);

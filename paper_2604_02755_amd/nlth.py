@@ -331,6 +331,29 @@ class Context:
     def apply_operator(self, mesh_h, prob, which, precision, D_ip, h, x):
         return nlth_apply_operator(self.h, mesh_h, prob, which, precision, D_ip, h, x)
 
+    # -- continuous-batching request loop
+    def submit(self, mesh_h, mesh, prob):
+        """Queue a solve; returns (ticket, result dict filled on completion)."""
+        keep = []
+        p = _problem_struct(prob, keep)
+        out, res = _result_buffers(p.n_members, p.n_steps, int(np.asarray(mesh.recv).size))
+        t = C.c_uint64()
+        _check(lib().nlth_submit(self.h, mesh_h, C.byref(p), C.byref(res), C.byref(t)), self.h)
+        self._pending = getattr(self, "_pending", {})
+        self._pending[t.value] = (keep, res, out)
+        return t.value, out
+
+    def poll(self, ticket):
+        done = C.c_int32()
+        rc = lib().nlth_poll(self.h, C.c_uint64(ticket), C.byref(done))
+        return bool(done.value), rc
+
+    def wait(self, ticket, timeout_s=-1.0):
+        return lib().nlth_wait(self.h, C.c_uint64(ticket), float(timeout_s))
+
+    def cancel(self, ticket):
+        return lib().nlth_cancel(self.h, C.c_uint64(ticket))
+
     def close(self):
         for mh in self._meshes:
             lib().nlth_mesh_destroy(mh)

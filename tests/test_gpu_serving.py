@@ -1,0 +1,76 @@
+"""Continuous-batching request loop: requests of mixed mesh sizes admitted into
+member slots while others run; each result must equal the same problem solved
+alone (FP64 path: 1e-12 relative, i.e. reduction-order level; mixed path:
+1e-6, the mixed-precision bar).  Cancellation and budget refusal are checked
+from the host."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_2604_02755_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _request(dims, seed, steps, precision):
+    mesh, prob = I.config(0, n_steps=steps, mesh_dims=dims, cg_tol=1e-10, precision=precision,
+                          n_springs=12)
+    rng = np.random.default_rng(seed)
+    prob.vs = prob.vs * np.exp(0.2 * rng.standard_normal(prob.vs.shape))
+    prob.input_acc = 5.0 * I.member_waves(4, [seed], steps, prob.dt)
+    return mesh, prob
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 1e-6)])
+def test_results_alone_and_in_the_mix(nlth_mod, precision, tol):
+    ctx = nlth_mod.Context(0, max_batch=4, use_torch_stream=False)
+    try:
+        meshes = {}
+        plan = [((4, 4, 2), 1, 14), ((5, 4, 3), 2, 20), ((4, 4, 2), 3, 9), ((5, 4, 3), 4, 16),
+                ((4, 4, 2), 5, 22), ((4, 4, 2), 6, 12)]
+        reqs = []
+        for k, (dims, seed, steps) in enumerate(plan):
+            mesh, prob = _request(dims, seed, steps, precision)
+            if dims not in meshes:
+                meshes[dims] = (ctx.mesh(mesh), mesh)
+            if k == 3:
+                time.sleep(0.05)  # later arrivals join while the first ones run
+            t, out = ctx.submit(meshes[dims][0], mesh, prob)
+            reqs.append((t, out, mesh, prob, dims))
+            print("submitted", k, dims, steps, flush=True)
+        for t, out, mesh, prob, dims in reqs:
+            rc = ctx.wait(t, 120.0)
+            assert rc == 0, rc
+            alone = ctx.solve(meshes[dims][0], mesh, prob)
+            err = np.linalg.norm(out["vel"] - alone["vel"]) / np.linalg.norm(alone["vel"])
+            print("  ticket", t, dims, "in the mix vs alone", err, flush=True)
+            assert err < tol
+            assert np.array_equal(out["iters"][0, :, 0] > 0, alone["iters"][0, :, 0] > 0)
+    finally:
+        ctx.close()
+
+
+def test_cancel_and_budget_refusal(nlth_mod):
+    ctx = nlth_mod.Context(0, max_batch=2, use_torch_stream=False)
+    try:
+        mesh, prob = _request((4, 4, 2), 9, 400, 0)
+        mh = ctx.mesh(mesh)
+        t, _ = ctx.submit(mh, mesh, prob)
+        ctx.cancel(t)
+        rc = ctx.wait(t, 60.0)
+        print("cancel rc", rc, flush=True)
+        assert rc == nlth_mod.NLTH_ECANCELED
+    finally:
+        ctx.close()
+    # 2 MiB holds the mesh but never the request (its law state alone is ~2.9 MB)
+    small = nlth_mod.Context(0, hbm_budget=2 << 20, use_torch_stream=False)
+    try:
+        mesh, prob = _request((8, 8, 4), 10, 50, 0)
+        mh = small.mesh(mesh)
+        with pytest.raises(nlth_mod.NlthError) as ei:
+            small.submit(mh, mesh, prob)
+        print("budget refusal", ei.value.code, str(ei.value), flush=True)
+        assert ei.value.code == nlth_mod.NLTH_EBUSY
+    finally:
+        small.close()
