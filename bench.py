@@ -71,14 +71,27 @@ def traffic_from_profile(src_hash: str):
     return d.get("bytes_per_launch")
 
 
-def run_gpu(mesh, prob, warmup, steps, profile):
-    from paper_2604_02755_amd import nlth
+def run_gpu(mesh, prob, warmup, steps, profile, tune_steps=0, tuned=None):
+    """Create the ensemble, step ``warmup`` steps, autotune it over the next
+    ``tune_steps`` steps (or apply the launch shapes of ``tuned`` and step as
+    many), then time ``steps`` steps."""
+    from paper_2604_02755_amd import autotune, nlth
     import torch
     ctx = nlth.Context(0, use_torch_stream=True)
     try:
         mh = ctx.mesh(mesh)
         ens = ctx.ensemble(mh, mesh, prob)
-        ens.step(warmup)
+        choice = None
+        if tuned is not None:
+            ens.set_tuning(tuned["ebe_block"], tuned["check_every"], 1)
+        ens.step(warmup)  # the first steps carry no wave yet: warm up before tuning
+        if tuned is not None:
+            ens.step(tune_steps)
+        elif tune_steps > 0:
+            done0 = ens.stats()["steps_done"]
+            choice = autotune.tune(ens, mesh, prob, steps_per_trial=1, log=log)
+            used = ens.stats()["steps_done"] - done0
+            ens.step(max(0, tune_steps - used))
         ens.reset_stats()
         ens.set_profile(profile)
         st0 = ens.stats()
@@ -92,7 +105,7 @@ def run_gpu(mesh, prob, warmup, steps, profile):
         ens.close()
     finally:
         ctx.close()
-    return elapsed, st0, st, out
+    return elapsed, st0, st, out, choice
 
 
 def main():
@@ -108,6 +121,7 @@ def main():
     ap.add_argument("--acc-members", type=int, default=4)
     ap.add_argument("--acc-steps", type=int, default=150)
     ap.add_argument("--no-profile", action="store_true", help="no per-launch event timing")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (defaults)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); members shard across GPUs "
@@ -116,22 +130,26 @@ def main():
 
     from paper_2604_02755_amd import inputs as I
     dims = tuple(int(v) for v in args.mesh.split("x"))
-    n_total = args.warmup + args.steps
+    from paper_2604_02755_amd import autotune
     t0 = time.perf_counter()
     mesh, prob = I.config(2, n_members=args.members, mesh_dims=dims)
-    # the first warmup+steps samples of the 1500-step records (scaled on the full records)
+    n_tune = 0 if args.no_tune else autotune.trial_steps(prob)
+    pre = n_tune + args.warmup
+    n_total = pre + args.steps
+    # the first n_total samples of the 1500-step records (scaled on the full records)
     prob.input_acc = np.ascontiguousarray(prob.input_acc[:, :n_total])
     prob.n_steps = n_total
     log(f"inputs: {mesh.n_tets} tets, {mesh.n_dof} DOF/member, {args.members} members ({time.perf_counter()-t0:.1f}s)")
     ndof = mesh.n_dof
+    sl = slice(pre, n_total)
 
-    # batched mixed precision (the headline)
-    el, st0, st, out_mixed = run_gpu(mesh, prob, args.warmup, args.steps, not args.no_profile)
+    # batched mixed precision (the headline), autotuned over the first steps
+    el, st0, st, out_mixed, tuned = run_gpu(mesh, prob, args.warmup, args.steps, not args.no_profile, n_tune)
     value = args.members * ndof * args.steps / el
-    log(f"mixed: {el/args.steps*1e3:.1f} ms/step, {value:.3e} DOF-steps/s")
+    log(f"mixed: {el/args.steps*1e3:.1f} ms/step, {value:.3e} DOF-steps/s, tuning {tuned and {k: tuned[k] for k in ('inner_tol', 'inner_maxit', 'ebe_block', 'check_every')}}")
 
     # roofline of the FP32 element-by-element operator over the timed region
-    inner = out_mixed["iters"][:, args.warmup:n_total, 1].astype(np.int64).sum()
+    inner = out_mixed["iters"][:, sl, 1].astype(np.int64).sum()
     roofline = None
     if st["n_ebe32"] > 0 and st["ms_ebe32"] > 0:
         per_unit = ebe32_algorithmic_bytes(mesh.n_tets, mesh.n_nodes, st["members_padded"], prob.inner_dtype)
@@ -149,20 +167,21 @@ def main():
                     "algorithmic_bytes_per_launch": round(total_bytes / st["n_ebe32"], 0),
                     "bytes_per_element_member": round(per_unit, 1)}
 
-    # plain FP64 on the same GPU, same members and steps
+    # plain FP64 on the same GPU, same members, same timed steps
     fp64 = None
     if not args.no_fp64:
         prob64 = I.config(2, n_members=args.members, mesh_dims=dims, precision=I.PRECISION_FP64)[1]
         prob64.input_acc = np.ascontiguousarray(prob64.input_acc[:, :n_total])
         prob64.n_steps = n_total
-        el64, _, st64, out64 = run_gpu(mesh, prob64, args.warmup, args.steps, False)
+        el64, _, st64, out64, _ = run_gpu(mesh, prob64, args.warmup, args.steps, False, n_tune,
+                                          tuned=tuned or {"ebe_block": 256, "check_every": 8})
         v64 = args.members * ndof * args.steps / el64
-        sl = slice(args.warmup, n_total)
         fp64 = {"value": v64, "ms_per_step": el64 / args.steps * 1e3, "speedup": value / v64,
                 "iters_per_member_step": float(out64["iters"][:, sl, 0].mean())}
         log(f"fp64: {el64/args.steps*1e3:.1f} ms/step, {v64:.3e} DOF-steps/s")
-        # accuracy of the mixed path against FP64: the first members over a
-        # record long enough for the incident wave to reach the surface
+        # accuracy of the mixed path (with the tuned inner policy) against FP64:
+        # the first members over a record long enough for the incident wave to
+        # reach the surface
         na, ns_acc = min(args.members, args.acc_members), args.acc_steps
         errs = []
         outs = []
@@ -172,6 +191,8 @@ def main():
                 setattr(pa, f, np.ascontiguousarray(getattr(pa, f)[:na]))
             pa.input_acc = np.ascontiguousarray(pa.input_acc[:, :ns_acc])
             pa.n_members, pa.n_steps = na, ns_acc
+            if tuned and prec == I.PRECISION_MIXED:
+                pa.inner_tol, pa.inner_maxit = tuned["inner_tol"], tuned["inner_maxit"]
             outs.append(run_gpu(mesh, pa, 0, ns_acc, False)[3])
         for m in range(na):
             a, b = outs[0]["vel"][m], outs[1]["vel"][m]
@@ -202,8 +223,11 @@ def main():
                                f"12 springs/point, mixed FP64/FP32 CG, tol 1e-8",
                    "members": args.members, "dof_per_member": ndof, "tets": mesh.n_tets,
                    "parallelism": "members batched in one launch"},
-        "iterations": {"outer_per_member_step": float(out_mixed["iters"][:, args.warmup:n_total, 0].mean()),
-                       "inner_per_member_step": float(out_mixed["iters"][:, args.warmup:n_total, 1].mean())},
+        "iterations": {"outer_per_member_step": float(out_mixed["iters"][:, sl, 0].mean()),
+                       "inner_per_member_step": float(out_mixed["iters"][:, sl, 1].mean())},
+        "tuning": ({k: tuned[k] for k in ("inner_tol", "inner_maxit", "ebe_block", "check_every")}
+                   if tuned else None),
+        "timed_steps": f"steps {pre + 1}-{n_total} of the record",
         "phase_ms": {"ebe64": st["ms_ebe64"], "ebe32": st["ms_ebe32"], "law": st["ms_law"],
                      "rhs_diag_q": st["ms_other"]} if not args.no_profile else None,
         "fp64_plain": fp64,

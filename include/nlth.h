@@ -212,6 +212,29 @@ typedef struct {
     int64_t device_bytes, host_bytes;
 } nlth_stats;
 int nlth_ens_stats(const nlth_ens* ens, nlth_stats* st);
+
+/* Launch-shape knobs of an ensemble (chosen by the package's autotuner):
+ * threads per block of the element-by-element launches (64, 128 or 256), CG
+ * iterations between host convergence checks (1..64), and whether those
+ * iteration chunks are captured once into a hipGraph and replayed (0/1).
+ * It also sets the inner-solve policy of NLTH_MIXED (inner_tol, inner_maxit):
+ * a tiny inner_tol with a small inner_maxit gives a fixed number of inner
+ * iterations per outer iteration, which keeps every member's lanes busy.
+ * A field of 0 (or -1 for use_graph) keeps the current value.  The launch
+ * shapes do not change results (converged members are frozen on the device);
+ * the inner policy changes the iteration path only within the outer FP64
+ * tolerance.  Out-of-range fields (ebe_block not 0/64/128/256, check_every
+ * outside 0..64, inner_maxit outside 0..100000, inner_tol outside [0, 1))
+ * give NLTH_EINVAL and change nothing.  Not to be called while the ensemble
+ * is stepping on another thread. */
+typedef struct {
+    int32_t ebe_block;
+    int32_t check_every;
+    int32_t use_graph;
+    int32_t inner_maxit;
+    double inner_tol;
+} nlth_tuning;
+int nlth_ens_set_tuning(nlth_ens* ens, const nlth_tuning* t);
 int nlth_ens_set_profile(nlth_ens* ens, int32_t profile);
 int nlth_ens_reset_stats(nlth_ens* ens);
 

@@ -1,0 +1,98 @@
+"""Autotuner for the launch shapes and the inner-solve policy of an ensemble.
+
+It times candidate settings on the live ensemble, a step or two each, by
+coordinate descent:
+1. the inner iteration policy of the mixed path (tolerance-driven, or a fixed
+   inner count that keeps every member's lanes busy);
+2. threads per block of the element-by-element launches;
+3. CG iterations per host convergence check (the hipGraph chunk length).
+
+Every trial step is a complete, converged step of the simulation.  Only the
+iteration path inside the outer FP64 tolerance depends on the choice.  The
+winner is cached per problem shape in memory, and optionally in a JSON file.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+
+INNER_POLICIES = [(0.1, 50), (0.01, 60), (1e-12, 12), (1e-12, 16), (1e-12, 20)]
+EBE_BLOCKS = [256, 128]
+CHECK_EVERY = [8, 16, 4]
+
+_cache: dict = {}
+
+
+def shape_key(mesh, prob, members_padded: int) -> str:
+    return (f"ne{mesh.n_tets}-nn{mesh.n_nodes}-mb{members_padded}-ns{prob.n_springs}-"
+            f"p{prob.precision}-d{getattr(prob, 'inner_dtype', 0)}")
+
+
+def trial_steps(prob, steps_per_trial: int = 1) -> int:
+    """Steps an uncached tuning run takes: every candidate of a stage runs
+    twice (palindromic order), the incumbent included."""
+    n_pol = len(INNER_POLICIES) if prob.precision == 1 else 1
+    stages = [n_pol, len(EBE_BLOCKS), len(CHECK_EVERY)]
+    return 2 * steps_per_trial * sum(n for n in stages if n > 1)
+
+
+def _apply(ens, c):
+    ens.set_tuning(c["ebe_block"], c["check_every"], 1, c["inner_maxit"], c["inner_tol"])
+
+
+def tune(ens, mesh, prob, steps_per_trial: int = 1, cache_file: str | None = None, log=None) -> dict:
+    """Tune ``ens`` in place; returns the chosen settings and the trial times.
+
+    The cost of a step drifts as the wave evolves, so each stage times its
+    candidates in the order A B C ... C B A and sums the two visits: a drift
+    that is linear over the stage cancels exactly."""
+    st = ens.stats()
+    key = shape_key(mesh, prob, st["members_padded"])
+    if cache_file and os.path.exists(cache_file):
+        try:
+            with open(cache_file) as fh:
+                _cache.update(json.load(fh))
+        except (OSError, ValueError):
+            pass
+    if key in _cache:
+        best = _cache[key]
+        _apply(ens, best)
+        return dict(best, cached=True)
+    trials = []
+
+    def stage(cands):
+        if len(cands) < 2:
+            return cands[0], None
+        ms = [0.0] * len(cands)
+        for i in list(range(len(cands))) + list(reversed(range(len(cands)))):
+            _apply(ens, cands[i])
+            t0 = time.perf_counter()
+            ens.step(steps_per_trial)
+            dt = (time.perf_counter() - t0) / steps_per_trial * 1e3
+            ms[i] += dt / 2
+            trials.append(dict(cands[i], ms=dt))
+            if log:
+                log(f"autotune {cands[i]} -> {dt:.1f} ms/step")
+        i = min(range(len(cands)), key=ms.__getitem__)
+        return cands[i], ms[i]
+
+    cur = dict(ebe_block=EBE_BLOCKS[0], check_every=CHECK_EVERY[0], inner_tol=prob.inner_tol,
+               inner_maxit=prob.inner_maxit)
+    best_ms = None
+    if prob.precision == 1:
+        cur, best_ms = stage([dict(cur, inner_tol=t, inner_maxit=m) for t, m in INNER_POLICIES])
+    cur, ms = stage([dict(cur, ebe_block=b) for b in EBE_BLOCKS])
+    best_ms = ms if ms is not None else best_ms
+    cur, ms = stage([dict(cur, check_every=c) for c in CHECK_EVERY])
+    best_ms = ms if ms is not None else best_ms
+    _apply(ens, cur)
+    best = dict(cur, ms=best_ms)
+    _cache[key] = best
+    if cache_file:
+        try:
+            with open(cache_file, "w") as fh:
+                json.dump(_cache, fh, indent=1)
+        except OSError:
+            pass
+    return dict(best, cached=False, trials=trials)

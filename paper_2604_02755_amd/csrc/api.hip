@@ -715,6 +715,9 @@ void Ens::destroy()
     pending.clear();
     for (auto e : ev_pool) (void)hipEventDestroy(e);
     ev_pool.clear();
+    if (g_inner) (void)hipGraphExecDestroy(g_inner);
+    if (g_pcg) (void)hipGraphExecDestroy(g_pcg);
+    g_inner = g_pcg = nullptr;
     if (h_flags) (void)hipHostFree(h_flags);
     h_flags = nullptr;
     if (ev_copy0) (void)hipEventDestroy(ev_copy0);
@@ -726,6 +729,7 @@ void Ens::destroy()
 void Ens::ebe(OpMode mode, const double* x1, const double* x2, double* y, const int* act)
 {
     const DevMesh dm = mesh->dev();
+    set_ebe_block(ebe_block);
     for (int c = 0; c < mesh->ncolor; ++c) {
         const int e0 = mesh->color_off[c], e1 = mesh->color_off[c + 1];
         hipEvent_t t0;
@@ -739,6 +743,7 @@ void Ens::ebe(OpMode mode, const double* x1, const double* x2, double* y, const 
 void Ens::ebe32(const float* x, float* y, const int* act)
 {
     const DevMesh dm = mesh->dev();
+    set_ebe_block(ebe_block);
     for (int c = 0; c < mesh->ncolor; ++c) {
         const int e0 = mesh->color_off[c], e1 = mesh->color_off[c + 1];
         hipEvent_t t0;
@@ -817,15 +822,7 @@ void Ens::solve_pcg()
     launch_p_update<double>(s, n, MB, nm, z.as<double>(), p.as<double>(), nullptr, nullptr, Ap.as<double>());
     if (!read_any_active(act)) return;
     for (;;) {
-        for (int k = 0; k < check_every; ++k) {
-            apply_A64(p.as<double>(), Ap.as<double>(), act);
-            dots(1, p.as<double>(), Ap.as<double>(), nullptr, nullptr, nullptr, nullptr, nblk);
-            fin(FIN_ALPHA, 1, nblk, tol2, P.cg_maxit);
-            launch_pcg_update(s, mesh->nn, MB, nm, x, r.as<double>(), z.as<double>(), p.as<double>(), Ap.as<double>(),
-                              pinv.as<double>(), cs.alpha, act, pd, &nblk);
-            fin(FIN_BETA, 2, nblk, tol2, P.cg_maxit);
-            launch_p_update<double>(s, n, MB, nm, z.as<double>(), p.as<double>(), cs.beta, act, Ap.as<double>());
-        }
+        run_iters(1, check_every);
         if (!read_any_active(act)) break;
     }
 }
@@ -842,22 +839,83 @@ void Ens::inner_solve()
     launch_inner_start(s, mesh->nn, MB, nm, r.as<double>(), pinv32.as<float>(), ir.as<float>(), iz.as<float>(),
                        ip.as<float>(), iw.as<float>(), iAp.as<float>(), act, pd, &nblk);
     fin(FIN_IN_START, 2, nblk, tol2, P.inner_maxit);
+    (void)n;
     int done_iters = 0;
     while (done_iters < P.inner_maxit) {
         const int chunk = std::min(check_every, P.inner_maxit - done_iters);
-        for (int k = 0; k < chunk; ++k) {
-            ebe32(ip.as<float>(), iAp.as<float>(), iact);
-            launch_dotsv<float>(s, 1, ip.as<float>(), iAp.as<float>(), nullptr, nullptr, nullptr, nullptr, n, MB, nm,
-                                iact, pd, &nblk);
-            fin(FIN_IN_ALPHA, 1, nblk, tol2, P.inner_maxit);
-            launch_inner_update(s, mesh->nn, MB, nm, iz.as<float>(), ir.as<float>(), iw.as<float>(), ip.as<float>(),
-                                iAp.as<float>(), pinv32.as<float>(), cs.ialpha, iact, pd, &nblk);
-            fin(FIN_IN_BETA, 2, nblk, tol2, P.inner_maxit);
-            launch_p_update<float>(s, n, MB, nm, iw.as<float>(), ip.as<float>(), cs.ibeta, iact, iAp.as<float>());
-        }
+        run_iters(0, chunk);
         done_iters += chunk;
         if (!read_any_active(iact)) break;
     }
+}
+
+// one inner FP32 PCG iteration (every launch reads its scalars on the device)
+void Ens::inner_iter()
+{
+    const long n = ndof;
+    int nblk;
+    const int* iact = cs.inner_active;
+    const double tol2 = P.inner_tol * P.inner_tol;
+    double* pd = partial.as<double>();
+    ebe32(ip.as<float>(), iAp.as<float>(), iact);
+    launch_dotsv<float>(s, 1, ip.as<float>(), iAp.as<float>(), nullptr, nullptr, nullptr, nullptr, n, MB, nm, iact, pd,
+                        &nblk);
+    fin(FIN_IN_ALPHA, 1, nblk, tol2, P.inner_maxit);
+    launch_inner_update(s, mesh->nn, MB, nm, iz.as<float>(), ir.as<float>(), iw.as<float>(), ip.as<float>(),
+                        iAp.as<float>(), pinv32.as<float>(), cs.ialpha, iact, pd, &nblk);
+    fin(FIN_IN_BETA, 2, nblk, tol2, P.inner_maxit);
+    launch_p_update<float>(s, n, MB, nm, iw.as<float>(), ip.as<float>(), cs.ibeta, iact, iAp.as<float>());
+}
+
+// one FP64 block-Jacobi PCG iteration
+void Ens::pcg_iter()
+{
+    const long n = ndof;
+    int nblk;
+    double* x = du.as<double>();
+    const int* act = cs.active;
+    const double tol2 = P.cg_tol * P.cg_tol;
+    double* pd = partial.as<double>();
+    apply_A64(p.as<double>(), Ap.as<double>(), act);
+    dots(1, p.as<double>(), Ap.as<double>(), nullptr, nullptr, nullptr, nullptr, nblk);
+    fin(FIN_ALPHA, 1, nblk, tol2, P.cg_maxit);
+    launch_pcg_update(s, mesh->nn, MB, nm, x, r.as<double>(), z.as<double>(), p.as<double>(), Ap.as<double>(),
+                      pinv.as<double>(), cs.alpha, act, pd, &nblk);
+    fin(FIN_BETA, 2, nblk, tol2, P.cg_maxit);
+    launch_p_update<double>(s, n, MB, nm, z.as<double>(), p.as<double>(), cs.beta, act, Ap.as<double>());
+}
+
+// k iterations of kind 0 (inner) or 1 (FP64 PCG); a full chunk is captured
+// once into a hipGraph and replayed (the launches and their arguments are the
+// same every chunk), which removes per-launch host overhead
+void Ens::run_iters(int kind, int k)
+{
+    if (!use_graph || profile || k != check_every) {
+        for (int i = 0; i < k; ++i) kind == 0 ? inner_iter() : pcg_iter();
+        return;
+    }
+    hipGraphExec_t& ge = kind == 0 ? g_inner : g_pcg;
+    if (!ge) {
+        hipGraph_t g = nullptr;
+        NLTH_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        try {
+            for (int i = 0; i < k; ++i) kind == 0 ? inner_iter() : pcg_iter();
+        } catch (...) {
+            (void)hipStreamEndCapture(s, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+        }
+        NLTH_HIP(hipStreamEndCapture(s, &g));
+        hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            ge = nullptr;
+            use_graph = false;  // fall back to direct launches of the same kernels
+            for (int i = 0; i < k; ++i) kind == 0 ? inner_iter() : pcg_iter();
+            return;
+        }
+    }
+    NLTH_HIP(hipGraphLaunch(ge, s));
 }
 
 // FP64 flexible CG (Polak-Ribiere beta) preconditioned by the inner FP32 PCG
@@ -1227,6 +1285,29 @@ int nlth_ens_set_profile(nlth_ens* ens, int32_t profile)
     if (!ens) return NLTH_EINVAL;
     ens->profile = profile != 0;
     return NLTH_OK;
+}
+
+int nlth_ens_set_tuning(nlth_ens* ens, const nlth_tuning* t)
+{
+    API_BEGIN(ens ? ens->ctx : nullptr)
+    if (!ens || !t) throw Error{NLTH_EINVAL, "ens/tuning is NULL"};
+    if (t->ebe_block != 0 && t->ebe_block != 64 && t->ebe_block != 128 && t->ebe_block != 256)
+        throw Error{NLTH_EINVAL, "ebe_block must be 0, 64, 128 or 256"};
+    if (t->check_every < 0 || t->check_every > 64) throw Error{NLTH_EINVAL, "check_every must be in [0, 64]"};
+    if (t->inner_maxit < 0 || t->inner_maxit > 100000 || !(t->inner_tol >= 0) || t->inner_tol >= 1)
+        throw Error{NLTH_EINVAL, "inner_maxit must be in [0, 100000] and inner_tol in [0, 1)"};
+    std::lock_guard<std::mutex> g(ens->ctx->mu);
+    if (t->ebe_block) ens->ebe_block = t->ebe_block;
+    if (t->check_every) ens->check_every = t->check_every;
+    if (t->use_graph >= 0) ens->use_graph = t->use_graph != 0;
+    if (t->inner_maxit) ens->P.inner_maxit = t->inner_maxit;
+    if (t->inner_tol > 0) ens->P.inner_tol = t->inner_tol;
+    // captured chunks hold the old launch shapes
+    if (ens->g_inner) (void)hipGraphExecDestroy(ens->g_inner);
+    if (ens->g_pcg) (void)hipGraphExecDestroy(ens->g_pcg);
+    ens->g_inner = ens->g_pcg = nullptr;
+    return NLTH_OK;
+    API_END
 }
 
 int nlth_ens_reset_stats(nlth_ens* ens)

@@ -363,15 +363,20 @@ __global__ __launch_bounds__(256) void k_ebe(DevMesh M, int MB, int nm, int e0, 
     }
 }
 
+// threads per block of the element-by-element launches (a tuning knob; per
+// host thread so concurrent contexts do not interfere)
+static thread_local int t_ebe_block = 256;
+void set_ebe_block(int bs) { t_ebe_block = (bs == 64 || bs == 128 || bs == 256) ? bs : 256; }
+
 template <typename T, int MODE>
 static void ebe_dispatch(hipStream_t s, dim3 g, const DevMesh& M, int MB, int nm, int e0, int e1, const T* D,
                          const double* h, const double* mat, StepConst sc, const T* x1, const T* x2, T* y,
                          const int* active)
 {
     if (MB >= 64)
-        hipLaunchKernelGGL((k_ebe<T, 0, MODE, true>), g, dim3(256), 0, s, M, MB, nm, e0, e1, (const void*)D, h, mat, sc, x1, x2, y, active);
+        hipLaunchKernelGGL((k_ebe<T, 0, MODE, true>), g, dim3(t_ebe_block), 0, s, M, MB, nm, e0, e1, (const void*)D, h, mat, sc, x1, x2, y, active);
     else
-        hipLaunchKernelGGL((k_ebe<T, 0, MODE, false>), g, dim3(256), 0, s, M, MB, nm, e0, e1, (const void*)D, h, mat, sc, x1, x2, y, active);
+        hipLaunchKernelGGL((k_ebe<T, 0, MODE, false>), g, dim3(t_ebe_block), 0, s, M, MB, nm, e0, e1, (const void*)D, h, mat, sc, x1, x2, y, active);
 }
 
 // inner FP32 operator (Eq. 1 left-hand side) with D stored in FP32 or bfloat16
@@ -381,12 +386,12 @@ void launch_ebe32(hipStream_t s, const DevMesh& M, int MB, int nm, int e0, int e
 {
     long n = (long)(e1 - e0) * MB;
     if (n <= 0) return;
-    dim3 g(nblocks(n));
+    dim3 g(nblocks(n, t_ebe_block));
     if (D16) {
         if (MB >= 64)
-            hipLaunchKernelGGL((k_ebe<float, 1, OP_A, true>), g, dim3(256), 0, s, M, MB, nm, e0, e1, (const void*)D16, h, mat, sc, x, nullptr, y, active);
+            hipLaunchKernelGGL((k_ebe<float, 1, OP_A, true>), g, dim3(t_ebe_block), 0, s, M, MB, nm, e0, e1, (const void*)D16, h, mat, sc, x, nullptr, y, active);
         else
-            hipLaunchKernelGGL((k_ebe<float, 1, OP_A, false>), g, dim3(256), 0, s, M, MB, nm, e0, e1, (const void*)D16, h, mat, sc, x, nullptr, y, active);
+            hipLaunchKernelGGL((k_ebe<float, 1, OP_A, false>), g, dim3(t_ebe_block), 0, s, M, MB, nm, e0, e1, (const void*)D16, h, mat, sc, x, nullptr, y, active);
     } else {
         ebe_dispatch<float, OP_A>(s, g, M, MB, nm, e0, e1, D32, h, mat, sc, x, nullptr, y, active);
     }
@@ -399,7 +404,7 @@ void launch_ebe(hipStream_t s, OpMode mode, const DevMesh& M, int MB, int nm, in
 {
     long n = (long)(e1 - e0) * MB;
     if (n <= 0) return;
-    dim3 g(nblocks(n));
+    dim3 g(nblocks(n, t_ebe_block));
     switch (mode) {
     case OP_A: ebe_dispatch<T, OP_A>(s, g, M, MB, nm, e0, e1, D, h, mat, sc, x1, x2, y, active); break;
     case OP_K: ebe_dispatch<T, OP_K>(s, g, M, MB, nm, e0, e1, D, h, mat, sc, x1, x2, y, active); break;

@@ -82,6 +82,8 @@ void launch_law_init(hipStream_t s, const DevMesh& M, int MB, int nm, const doub
                      double* h, int only_m = -1);
 void launch_theta_reset_member(hipStream_t s, void* base, long ecp, int ns, int MB, int m);
 void launch_zero_member(hipStream_t s, double* p, long rows, int MB, int m);
+// threads per block of the element-by-element launches on this host thread
+void set_ebe_block(int bs);
 // inner FP32 operator (A) with D in FP32 (D32) or bfloat16 pairs (D16, if non-null)
 void launch_ebe32(hipStream_t s, const DevMesh& M, int MB, int nm, int e0, int e1, const float* D32,
                   const uint32_t* D16, const double* h, const double* mat, StepConst sc, const float* x, float* y,

@@ -142,6 +142,12 @@ struct Ens {
     void dots(int nd, const double* a0, const double* b0, const double* a1, const double* b1,
               const double* a2, const double* b2, int& nblk);
     int read_any_active(const int* flags);
+    void inner_iter();
+    void pcg_iter();
+    void run_iters(int kind, int k);
+    bool use_graph = true;
+    hipGraphExec_t g_inner = nullptr, g_pcg = nullptr;
+    int ebe_block = 256;
     void fin(FinalizeStage st, int nd, int nblk, double tol2, int maxit);
     void apply_A64(const double* x, double* y, const int* act);
     int* h_flags = nullptr;             // pinned copy of per-member flags

@@ -65,6 +65,11 @@ class nlth_problem(C.Structure):
                 ("inner_dtype", C.c_int32)]
 
 
+class nlth_tuning(C.Structure):
+    _fields_ = [("ebe_block", C.c_int32), ("check_every", C.c_int32), ("use_graph", C.c_int32),
+                ("inner_maxit", C.c_int32), ("inner_tol", C.c_double)]
+
+
 class nlth_result(C.Structure):
     _fields_ = [("vel", _dp), ("iters", _ip), ("member_status", _ip), ("vmax", _dp)]
 
@@ -96,6 +101,7 @@ EXPORTS = {
     "nlth_ens_stats": (C.c_int, [C.c_void_p, C.POINTER(nlth_stats)]),
     "nlth_ens_set_profile": (C.c_int, [C.c_void_p, C.c_int32]),
     "nlth_ens_reset_stats": (C.c_int, [C.c_void_p]),
+    "nlth_ens_set_tuning": (C.c_int, [C.c_void_p, C.c_void_p]),
     "nlth_submit": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(nlth_problem), C.POINTER(nlth_result),
                               C.POINTER(C.c_uint64)]),
     "nlth_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(C.c_int32)]),
@@ -297,6 +303,10 @@ class Ensemble:
 
     def reset_stats(self):
         lib().nlth_ens_reset_stats(self.h)
+
+    def set_tuning(self, ebe_block=0, check_every=0, use_graph=-1, inner_maxit=0, inner_tol=0.0):
+        t = nlth_tuning(int(ebe_block), int(check_every), int(use_graph), int(inner_maxit), float(inner_tol))
+        return _check(lib().nlth_ens_set_tuning(self.h, C.byref(t)), self.ctx)
 
     def close(self):
         if self.h:

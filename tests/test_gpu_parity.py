@@ -145,3 +145,64 @@ def test_config0_fp64_parity(gpu_ctx, oracle_lib):
     err = oracle_lib.rel_l2(out["vel"][0], vref)
     say("  rel L2", err, "iters", out["iters"][0, 40:44, 0], itref[40:44])
     assert out["rc"] == 0 and err < 1e-9
+
+
+def test_tuning_knobs_keep_results(gpu_ctx, nlth_mod):
+    """Launch shapes (threads per block, hipGraph-captured CG chunks, chunk
+    length) change no arithmetic: converged members are frozen on the device,
+    and the coloured scatter and the dot reductions have a fixed order."""
+    mesh, prob = _small_problem(precision=1, n_members=3, n_steps=20, dims=(8, 8, 4), ns=12, tol=1e-10)
+    mh = gpu_ctx.mesh(mesh)
+
+    def run(**kw):
+        ens = gpu_ctx.ensemble(mh, mesh, prob)
+        try:
+            if kw:
+                ens.set_tuning(**kw)
+            ens.step(prob.n_steps)
+            return ens.read()
+        finally:
+            ens.close()
+
+    say("tuning knobs: graph, direct, 128 threads / 4 per check, 64 threads / 16 per check")
+    base = run()
+    for kw in (dict(use_graph=0), dict(ebe_block=128, check_every=4), dict(ebe_block=64, check_every=16)):
+        o = run(**kw)
+        d = float(np.max(np.abs(o["vel"] - base["vel"])))
+        say("  ", kw, "max |dv|", d, "iters equal", bool(np.array_equal(o["iters"], base["iters"])))
+        assert d == 0.0 and np.array_equal(o["iters"], base["iters"])
+    ens = gpu_ctx.ensemble(mh, mesh, prob)
+    try:
+        for bad in (dict(ebe_block=100), dict(check_every=65), dict(inner_tol=2.0)):
+            with pytest.raises(nlth_mod.NlthError) as ei:
+                ens.set_tuning(**bad)
+            assert ei.value.code == nlth_mod.NLTH_EINVAL
+    finally:
+        ens.close()
+
+
+def test_autotuned_run_matches_fp64(gpu_ctx):
+    """The autotuner switches the inner policy between steps; every step still
+    converges to the outer FP64 tolerance, so the run stays within 1e-6 of the
+    plain FP64 path."""
+    from paper_2604_02755_amd import autotune
+    mesh, pm = _small_problem(precision=1, n_members=2, n_steps=40, dims=(8, 8, 4), ns=12, tol=1e-8)
+    _, p64 = _small_problem(precision=0, n_members=2, n_steps=40, dims=(8, 8, 4), ns=12, tol=1e-8)
+    mh = gpu_ctx.mesh(mesh)
+    autotune._cache.clear()
+    ens = gpu_ctx.ensemble(mh, mesh, pm)
+    try:
+        choice = autotune.tune(ens, mesh, pm, steps_per_trial=1)
+        done = ens.stats()["steps_done"]
+        say("autotune choice", {k: choice[k] for k in ("inner_tol", "inner_maxit", "ebe_block", "check_every")},
+            "after", done, "steps")
+        assert done == len(choice["trials"]) == autotune.trial_steps(pm) and done < pm.n_steps
+        ens.step(pm.n_steps - done)
+        om = ens.read()
+    finally:
+        ens.close()
+    o64 = gpu_ctx.solve(mh, mesh, p64)
+    for m in range(2):
+        err = np.linalg.norm(om["vel"][m] - o64["vel"][m]) / np.linalg.norm(o64["vel"][m])
+        say("  member", m, "autotuned mixed vs fp64", err)
+        assert err < 1e-6
