@@ -71,13 +71,13 @@ def traffic_from_profile(src_hash: str):
     return d.get("bytes_per_launch")
 
 
-def run_gpu(mesh, prob, warmup, steps, profile, tune_steps=0, tuned=None):
+def run_gpu(mesh, prob, warmup, steps, profile, tune_steps=0, tuned=None, ctx_kw=None):
     """Create the ensemble, step ``warmup`` steps, autotune it over the next
     ``tune_steps`` steps (or apply the launch shapes of ``tuned`` and step as
     many), then time ``steps`` steps."""
     from paper_2604_02755_amd import autotune, nlth
     import torch
-    ctx = nlth.Context(0, use_torch_stream=True)
+    ctx = nlth.Context(0, use_torch_stream=True, **(ctx_kw or {}))
     try:
         mh = ctx.mesh(mesh)
         ens = ctx.ensemble(mh, mesh, prob)
@@ -108,6 +108,149 @@ def run_gpu(mesh, prob, warmup, steps, profile, tune_steps=0, tuned=None):
     return elapsed, st0, st, out, choice
 
 
+def serve_run(rate, window_s, steps_range, sizes=(32, 48, 64), max_batch=16, n_check=3, seed=4000):
+    """Serving stream of single-member requests (Poisson arrivals, mixed mesh
+    sizes) through the library's request loop; latency = completion - arrival.
+    A few requests are re-run alone afterwards (batch invariance)."""
+    from paper_2604_02755_amd import inputs as I, nlth
+    reqs = I.serving_requests(rate=rate, window_s=window_s, seed=seed, sizes=sizes, steps_range=steps_range)
+    meshes = {n: I.serving_mesh(n) for n in sizes}
+    probs = [I.serving_problem(r) for r in reqs]
+    ctx = nlth.Context(0, max_batch=max_batch, use_torch_stream=False)
+    lat, rcs, outs = {}, {}, {}
+    try:
+        mh = {n: ctx.mesh(meshes[n]) for n in sizes}
+        pending = {}
+        i = 0
+        t0 = time.perf_counter()
+        last_log = t0
+        while i < len(reqs) or pending:
+            now = time.perf_counter() - t0
+            while i < len(reqs) and reqs[i]["t"] <= now:
+                tk, out = ctx.submit(mh[reqs[i]["n"]], meshes[reqs[i]["n"]], probs[i])
+                pending[tk] = i
+                outs[i] = out
+                i += 1
+            for tk in list(pending):
+                d, _ = ctx.poll(tk)
+                if d:
+                    j = pending.pop(tk)
+                    lat[j] = time.perf_counter() - t0 - reqs[j]["t"]
+                    rcs[j] = ctx.wait(tk, 0.0)
+            if time.perf_counter() - last_log > 15:
+                last_log = time.perf_counter()
+                log(f"serve: t={now:.0f}s submitted {i}/{len(reqs)}, in flight {len(pending)}, done {len(lat)}")
+            time.sleep(0.002)
+        wall = time.perf_counter() - t0
+        work = sum(meshes[r["n"]].n_dof * r["steps"] for r in reqs)
+        # batch invariance: re-run a few requests alone
+        inv = []
+        for j in np.linspace(0, len(reqs) - 1, min(n_check, len(reqs))).astype(int):
+            alone = ctx.solve(mh[reqs[j]["n"]], meshes[reqs[j]["n"]], probs[j])
+            b = alone["vel"]
+            inv.append(float(np.linalg.norm(outs[j]["vel"] - b) / max(np.linalg.norm(b), 1e-300)))
+    finally:
+        ctx.close()
+    L = np.array([lat[j] for j in range(len(reqs))])
+    return {"requests": len(reqs), "rate_per_s": rate, "window_s": window_s,
+            "steps_range": list(steps_range), "mesh_sizes": [f"{n}x{n}x16" for n in sizes],
+            "max_batch": max_batch, "p50_s": float(np.percentile(L, 50)), "p99_s": float(np.percentile(L, 99)),
+            "mean_s": float(L.mean()), "failed": int(sum(1 for v in rcs.values() if v != 0)),
+            "throughput_dof_steps_per_s": work / wall, "wall_s": wall,
+            "batch_invariance_rel_err_max": max(inv) if inv else None}
+
+
+def bench_single(args):
+    """One large member (the 128x128x32-cube, three perturbed layers, 150
+    springs workload): mixed and plain FP64 on the same steps, and their
+    receiver-velocity difference over a longer prefix."""
+    from paper_2604_02755_amd import inputs as I
+    dims = tuple(int(v) for v in args.mesh.split("x")) if args.mesh != "64x64x32" else (128, 128, 32)
+    pre = args.warmup
+    n_total = pre + args.steps
+    t0 = time.perf_counter()
+    mesh, pm = I.config(1, n_steps=max(n_total, args.acc_steps), mesh_dims=dims, precision=I.PRECISION_MIXED)
+    _, p64 = I.config(1, n_steps=max(n_total, args.acc_steps), mesh_dims=dims, precision=I.PRECISION_FP64)
+    log(f"inputs: {mesh.n_tets} tets, {mesh.n_dof} DOF, {pm.n_springs} springs ({time.perf_counter()-t0:.1f}s)")
+    res = {}
+    for name, pr in (("mixed", pm), ("fp64", p64)):
+        el, _, st, out, _ = run_gpu(mesh, pr, args.warmup, args.steps, not args.no_profile)
+        res[name] = {"value": mesh.n_dof * args.steps / el, "ms_per_step": el / args.steps * 1e3,
+                     "iters": out["iters"][0, pre:n_total].tolist(),
+                     "phase_ms": {"ebe64": st["ms_ebe64"], "ebe32": st["ms_ebe32"], "law": st["ms_law"],
+                                  "rhs_diag_q": st["ms_other"]} if not args.no_profile else None,
+                     "device_gb": st["device_bytes"] / 1e9}
+        log(f"{name}: {el/args.steps*1e3:.1f} ms/step")
+    acc = None
+    if args.acc_steps > 0:
+        vels = []
+        for pr in (pm, p64):
+            q = I.config(1, n_steps=args.acc_steps, mesh_dims=dims, precision=pr.precision)[1]
+            vels.append(run_gpu(mesh, q, 0, args.acc_steps, False)[3]["vel"][0])
+        acc = float(np.linalg.norm(vels[0] - vels[1]) / max(np.linalg.norm(vels[1]), 1e-300))
+        log(f"mixed vs fp64 over {args.acc_steps} steps: {acc:.2e}")
+    line = {
+        "metric": METRIC, "value": res["mixed"]["value"], "unit": "DOF-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["mixed"]["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32",
+        "data": "synthetic (seeded perturbed three-layer mesh and band-limited input wave)",
+        "config": {"workload": f"single member: {'x'.join(map(str, dims))}-cube tet10 mesh, three perturbed "
+                               f"layers, 150 springs/point, mixed FP64/FP32 CG vs plain FP64, tol 1e-8",
+                   "dof": mesh.n_dof, "tets": mesh.n_tets},
+        "mixed": res["mixed"], "fp64_plain": res["fp64"],
+        "speedup_vs_fp64": res["mixed"]["value"] / res["fp64"]["value"],
+        "mixed_vs_fp64_rel_err": acc, "acc_steps": args.acc_steps,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_paged(args):
+    """Ensemble whose law state does not fit the device budget: the state is
+    paged through pinned host memory every step (chunk ring on two copy
+    streams, overlapped with the law on other chunks)."""
+    from paper_2604_02755_amd import inputs as I
+    dims = tuple(int(v) for v in args.mesh.split("x"))
+    n_total = args.warmup + args.steps
+    mesh, prob = I.config(3, n_members=args.members, mesh_dims=dims, n_steps=n_total)
+    theta_gb = mesh.n_tets * 4 * prob.n_springs * args.members * 40 / 1e9
+    log(f"paged ensemble: {args.members} members, law state {theta_gb:.1f} GB, device budget {args.hbm_budget_gb} GB")
+    el, _, st, out, _ = run_gpu(mesh, prob, args.warmup, args.steps, False,
+                                ctx_kw=dict(hbm_budget=int(args.hbm_budget_gb * 2**30),
+                                            host_budget=int((theta_gb * 1.05 + 8) * 1e9)))
+    value = args.members * mesh.n_dof * args.steps / el
+    line = {
+        "metric": METRIC, "value": value, "unit": "DOF-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32",
+        "data": "synthetic (seeded meshes, layer properties and band-limited input waves)",
+        "config": {"workload": f"paged ensemble: {args.members} members on a {args.mesh}-cube tet10 mesh, 12 "
+                               f"springs/point, mixed, law state {theta_gb:.1f} GB in pinned host memory",
+                   "members": args.members, "hbm_budget_gb": args.hbm_budget_gb},
+        "paged": bool(st["paged"]),
+        "host_link": {"h2d_gb_per_step": st["h2d_bytes"] / args.steps / 1e9,
+                      "d2h_gb_per_step": st["d2h_bytes"] / args.steps / 1e9,
+                      "h2d_gbps": st["h2d_bytes"] / el / 1e9, "d2h_gbps": st["d2h_bytes"] / el / 1e9},
+        "device_gb": st["device_bytes"] / 1e9, "host_gb": st["host_bytes"] / 1e9,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_serve(args):
+    """The request stream at the given rate (default: the specified 4/s over
+    60 s) with records shortened by --serve-scale."""
+    sc = args.serve_scale
+    r = serve_run(args.serve_rate, args.serve_window, (int(500 * sc), int(2000 * sc)), max_batch=args.max_batch)
+    line = {
+        "metric": METRIC, "value": r["p99_s"], "unit": "s (p99 solve latency)", "n_gpus": 1, "steps": None,
+        "warmup": 0, "ms_per_step": None, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64+f32", "data": "synthetic (Poisson request stream, seeded meshes and waves)",
+        "config": {"workload": f"serving: Poisson {args.serve_rate}/s over {args.serve_window} s, meshes "
+                               f"{{32,48,64}}^2x16 cubes, steps x{sc} of [500, 2000], 12 springs, mixed"},
+        "serving": r,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,11 +265,25 @@ def main():
     ap.add_argument("--acc-steps", type=int, default=150)
     ap.add_argument("--no-profile", action="store_true", help="no per-launch event timing")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (defaults)")
+    ap.add_argument("--config", type=int, default=2, choices=(1, 2, 3, 4),
+                    help="2: batched ensemble (default); 1: one large member; 3: paged ensemble; 4: serving")
+    ap.add_argument("--hbm-budget-gb", type=float, default=96.0, help="device budget of --config 3")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving sub-run of --config 2")
+    ap.add_argument("--serve-rate", type=float, default=4.0)
+    ap.add_argument("--serve-window", type=float, default=60.0)
+    ap.add_argument("--serve-scale", type=float, default=0.1, help="record-length factor of --config 4")
+    ap.add_argument("--max-batch", type=int, default=16)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); members shard across GPUs "
               "with no exchange, so the one-GPU rate is the per-GPU figure", file=sys.stderr)
         sys.exit(2)
+    if args.config == 1:
+        return bench_single(args)
+    if args.config == 3:
+        return bench_paged(args)
+    if args.config == 4:
+        return bench_serve(args)
 
     from paper_2604_02755_amd import inputs as I
     dims = tuple(int(v) for v in args.mesh.split("x"))
@@ -148,23 +305,28 @@ def main():
     value = args.members * ndof * args.steps / el
     log(f"mixed: {el/args.steps*1e3:.1f} ms/step, {value:.3e} DOF-steps/s, tuning {tuned and {k: tuned[k] for k in ('inner_tol', 'inner_maxit', 'ebe_block', 'check_every')}}")
 
-    # roofline of the FP32 element-by-element operator over the timed region
+    # roofline of the inner FP32 operator over the timed region: the element
+    # kernel plus the node gather of its outputs (one application each)
     inner = out_mixed["iters"][:, sl, 1].astype(np.int64).sum()
     roofline = None
     if st["n_ebe32"] > 0 and st["ms_ebe32"] > 0:
         per_unit = ebe32_algorithmic_bytes(mesh.n_tets, mesh.n_nodes, st["members_padded"], prob.inner_dtype)
-        units = int(inner) * mesh.n_tets  # active element-members over all launches
+        units = int(inner) * mesh.n_tets  # active element-members over all applications
         total_bytes = per_unit * units
-        avg_ms = st["ms_ebe32"] / st["n_ebe32"]
-        achieved = total_bytes / (st["ms_ebe32"] * 1e-3) / 1e9
+        n_app = st["n_ebe32"]
+        ms = st["ms_ebe32"] + st["ms_gather32"]
+        achieved = total_bytes / (ms * 1e-3) / 1e9
         src = kernel_source_hash()
         tb = traffic_from_profile(src)
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4),
                     "traffic": tb,
-                    "kernel": "nlth::k_ebe<float, 1, 0, true> (inner operator, bfloat16 D)",
-                    "launches": int(st["n_ebe32"]), "avg_launch_us": round(avg_ms * 1e3, 2),
-                    "algorithmic_bytes_per_launch": round(total_bytes / st["n_ebe32"], 0),
+                    "kernel": "inner operator: nlth::k_ebe<float, 1, 0, true, 1> (element forces, bfloat16 D) "
+                              "+ nlth::k_gather<float> (node sums)",
+                    "launches": int(n_app), "avg_launch_us": round(ms / n_app * 1e3, 2),
+                    "avg_element_kernel_us": round(st["ms_ebe32"] / n_app * 1e3, 2),
+                    "avg_gather_kernel_us": round(st["ms_gather32"] / max(1, st["n_gather32"]) * 1e3, 2),
+                    "algorithmic_bytes_per_launch": round(total_bytes / n_app, 0),
                     "bytes_per_element_member": round(per_unit, 1)}
 
     # plain FP64 on the same GPU, same members, same timed steps
@@ -214,6 +376,13 @@ def main():
                          f"(FP64 CRS-PCG, tol 1e-8, setup included), {r['seconds']:.1f} s"}
         log(f"cpu oracle: {cpu['value']:.3e} DOF-steps/s on {cores} threads")
 
+    # latency: a short request stream at a rate the GPU sustains, with
+    # records one tenth of the specified length
+    serving = None
+    if not args.no_serve:
+        serving = serve_run(1.0, 20.0, (50, 200), max_batch=args.max_batch)
+        log(f"serving: p50 {serving['p50_s']:.2f} s, p99 {serving['p99_s']:.2f} s over {serving['requests']} requests")
+
     line = {
         "metric": METRIC, "value": value, "unit": "DOF-steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3, "higher_is_better": True,
@@ -228,11 +397,12 @@ def main():
         "tuning": ({k: tuned[k] for k in ("inner_tol", "inner_maxit", "ebe_block", "check_every")}
                    if tuned else None),
         "timed_steps": f"steps {pre + 1}-{n_total} of the record",
-        "phase_ms": {"ebe64": st["ms_ebe64"], "ebe32": st["ms_ebe32"], "law": st["ms_law"],
-                     "rhs_diag_q": st["ms_other"]} if not args.no_profile else None,
+        "phase_ms": {"ebe64": st["ms_ebe64"], "ebe32": st["ms_ebe32"], "gather32": st["ms_gather32"],
+                     "law": st["ms_law"], "rhs_diag_q": st["ms_other"]} if not args.no_profile else None,
         "fp64_plain": fp64,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "serving": serving,
     }
     print(json.dumps(line), flush=True)
 

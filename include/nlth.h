@@ -118,9 +118,9 @@ int nlth_mesh_create(nlth_ctx* ctx, const nlth_mesh_desc* d, nlth_mesh** out);
 int nlth_mesh_destroy(nlth_mesh* mesh);
 
 /* Mesh analysis results (host logic, available on a host-only context).
- * elem_order (optional, [n_tets]) receives the processing order: position ->
- * input tet id; color_offsets (optional, [n_colors+1]) the start of each
- * colour in that order.  Tets of one colour share no node. */
+ * elem_order (optional, [n_tets]) receives the tets grouped by colour (input
+ * tet ids); color_offsets (optional, [n_colors+1]) the start of each colour
+ * in that list.  Tets of one colour share no node. */
 typedef struct {
     int32_t n_nodes, n_tets, n_colors, n_bnodes;
     double volume;
@@ -210,6 +210,8 @@ typedef struct {
     double ms_copy;            /* copy-stream busy time while paging */
     int32_t n_members, members_padded, n_colors;
     int64_t device_bytes, host_bytes;
+    double ms_gather32;        /* node gather of the inner operator's element outputs */
+    int64_t n_gather32;
 } nlth_stats;
 int nlth_ens_stats(const nlth_ens* ens, nlth_stats* st);
 
@@ -223,9 +225,12 @@ int nlth_ens_stats(const nlth_ens* ens, nlth_stats* st);
  * A field of 0 (or -1 for use_graph) keeps the current value.  The launch
  * shapes do not change results (converged members are frozen on the device);
  * the inner policy changes the iteration path only within the outer FP64
- * tolerance.  Out-of-range fields (ebe_block not 0/64/128/256, check_every
- * outside 0..64, inner_maxit outside 0..100000, inner_tol outside [0, 1))
- * give NLTH_EINVAL and change nothing.  Not to be called while the ensemble
+ * tolerance.  scatter picks how element forces reach the nodes: element
+ * outputs summed per node in a fixed order (two launches, the default), or
+ * one launch per element colour adding into the nodal vector.
+ * Out-of-range fields (ebe_block not 0/64/128/256, check_every outside
+ * 0..64, inner_maxit outside 0..100000, inner_tol outside [0, 1), scatter
+ * outside -1..1) give NLTH_EINVAL and change nothing.  Not to be called while the ensemble
  * is stepping on another thread. */
 typedef struct {
     int32_t ebe_block;
@@ -233,6 +238,7 @@ typedef struct {
     int32_t use_graph;
     int32_t inner_maxit;
     double inner_tol;
+    int32_t scatter;           /* -1 keep; 0 element outputs + node gather; 1 one launch per colour */
 } nlth_tuning;
 int nlth_ens_set_tuning(nlth_ens* ens, const nlth_tuning* t);
 int nlth_ens_set_profile(nlth_ens* ens, int32_t profile);

@@ -230,13 +230,56 @@ static void build_mesh(Ctx* ctx, const nlth_mesh_desc* d, Mesh& M)
     }
     M.volume = vtot;
 
-    // greedy colouring: a tet takes the lowest colour no tet sharing a node has
+    // storage order: elements sorted along a Morton curve through their
+    // centroids (isotropic scaling), so that consecutive elements share nodes
+    // and a sweep over the elements re-reads nodal vectors from cache
+    {
+        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+        for (long i = 0; i < nn; ++i)
+            for (int c = 0; c < 3; ++c) {
+                lo[c] = std::min(lo[c], d->xyz[3 * i + c]);
+                hi[c] = std::max(hi[c], d->xyz[3 * i + c]);
+            }
+        const double ext = std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2], 1e-300});
+        const double sc = (double)(1 << 21) / ext;
+        auto spread = [](uint64_t v) {  // 21 bits -> every third bit
+            v &= 0x1FFFFF;
+            v = (v | v << 32) & 0x1F00000000FFFFull;
+            v = (v | v << 16) & 0x1F0000FF0000FFull;
+            v = (v | v << 8) & 0x100F00F00F00F00Full;
+            v = (v | v << 4) & 0x10C30C30C30C30C3ull;
+            v = (v | v << 2) & 0x1249249249249249ull;
+            return v;
+        };
+        std::vector<std::pair<uint64_t, int>> key(ne);
+        for (int e = 0; e < ne; ++e) {
+            const int* t = d->tet10 + 10L * e;
+            uint64_t code = 0;
+            for (int c = 0; c < 3; ++c) {
+                double x = 0;
+                for (int a = 0; a < 4; ++a) x += 0.25 * d->xyz[3L * t[a] + c];
+                const uint64_t q = (uint64_t)std::min(std::max((x - lo[c]) * sc, 0.0), (double)((1 << 21) - 1));
+                code |= spread(q) << c;
+            }
+            key[e] = {code, e};
+        }
+        std::sort(key.begin(), key.end());
+        M.order.resize(ne);
+        M.inv_order.resize(ne);
+        for (int pos = 0; pos < ne; ++pos) {
+            M.order[pos] = key[pos].second;
+            M.inv_order[key[pos].second] = pos;
+        }
+    }
+
+    // greedy colouring in storage order: a tet takes the lowest colour no tet
+    // sharing a node has; colour classes are kept as lists of storage positions
     const int W = 4;  // up to 256 colours
     std::vector<uint64_t> used((size_t)nn * W, 0);
     std::vector<int> color(ne);
     int ncol = 0;
-    for (int e = 0; e < ne; ++e) {
-        const int* t = d->tet10 + 10L * e;
+    for (int pos = 0; pos < ne; ++pos) {
+        const int* t = d->tet10 + 10L * M.order[pos];
         uint64_t u[W] = {0, 0, 0, 0};
         for (int a = 0; a < 10; ++a)
             for (int w = 0; w < W; ++w) u[w] |= used[(size_t)t[a] * W + w];
@@ -244,24 +287,31 @@ static void build_mesh(Ctx* ctx, const nlth_mesh_desc* d, Mesh& M)
         for (int w = 0; w < W && c < 0; ++w)
             if (~u[w]) c = 64 * w + __builtin_ctzll(~u[w]);
         if (c < 0) throw Error{NLTH_EINVAL, "mesh: more than 256 colours needed"};
-        color[e] = c;
+        color[pos] = c;
         ncol = std::max(ncol, c + 1);
         for (int a = 0; a < 10; ++a) used[(size_t)t[a] * W + c / 64] |= 1ull << (c % 64);
     }
     M.ncolor = ncol;
     M.color_off.assign(ncol + 1, 0);
-    for (int e = 0; e < ne; ++e) M.color_off[color[e] + 1]++;
+    for (int pos = 0; pos < ne; ++pos) M.color_off[color[pos] + 1]++;
     for (int c = 0; c < ncol; ++c) M.color_off[c + 1] += M.color_off[c];
-    M.order.resize(ne);
-    M.inv_order.resize(ne);
+    M.color_elems.resize(ne);
     {
         std::vector<int> fill(M.color_off.begin(), M.color_off.end() - 1);
-        for (int e = 0; e < ne; ++e) {
-            int pos = fill[color[e]]++;
-            M.order[pos] = e;
-            M.inv_order[e] = pos;
-        }
+        for (int pos = 0; pos < ne; ++pos) M.color_elems[fill[color[pos]]++] = pos;
     }
+    // node -> (element, local node) incidences in storage order, for the
+    // deterministic gather of element outputs
+    std::vector<int> inc_ptr(nn + 1, 0), inc(10L * ne);
+    for (int pos = 0; pos < ne; ++pos)
+        for (int a = 0; a < 10; ++a) inc_ptr[d->tet10[10L * M.order[pos] + a] + 1]++;
+    for (int i = 0; i < nn; ++i) inc_ptr[i + 1] += inc_ptr[i];
+    {
+        std::vector<int> fill(inc_ptr.begin(), inc_ptr.end() - 1);
+        for (int pos = 0; pos < ne; ++pos)
+            for (int a = 0; a < 10; ++a) inc[fill[d->tet10[10L * M.order[pos] + a]]++] = pos * 10 + a;
+    }
+    if (10L * ne > INT32_MAX) throw Error{NLTH_EINVAL, "mesh: more than 214,748,364 tets"};
     // sorted SoA arrays
     std::vector<int> conn(10L * ne), lay(ne);
     std::vector<double> g64(13L * ne);
@@ -376,6 +426,9 @@ static void build_mesh(Ctx* ctx, const nlth_mesh_desc* d, Mesh& M)
     upload(b, M.f_layer, flayer);
     upload(b, M.f_kind, fkind);
     upload(b, M.recv_d, M.recv);
+    upload(b, M.inc_ptr, inc_ptr);
+    upload(b, M.inc, inc);
+    upload(b, M.celem, M.color_elems);
 }
 
 DevMesh Mesh::dev() const
@@ -397,6 +450,9 @@ DevMesh Mesh::dev() const
     d.f_n = f_n.as<double>();
     d.f_layer = f_layer.as<int>();
     d.f_kind = f_kind.as<uint8_t>();
+    d.inc_ptr = inc_ptr.as<int>();
+    d.inc = inc.as<int>();
+    d.celem = celem.as<int>();
     return d;
 }
 
@@ -482,6 +538,7 @@ int64_t ensemble_bytes(const Mesh& m, const Problem& p, int MB, bool paged)
     bytes += (int64_t)m.ne * 4 * 21 * MB * 8;               // D64
     if (p.precision == NLTH_MIXED) bytes += (int64_t)m.ne * 4 * (p.inner_dtype == NLTH_INNER_FP32 ? 84 : 44) * MB;
     bytes += (int64_t)m.ne * MB * 8;                        // h
+    bytes += (int64_t)m.ne * 30 * MB * 8;                   // element outputs
     bytes += (int64_t)p.n_steps * std::max(1, m.nrecv) * 3 * MB * 8;  // receiver history
     bytes += (int64_t)p.n_steps * 3 * MB * 8 * 2;           // acc, vI
     if (!paged) bytes += (int64_t)m.ne * 4 * p.ns * MB * 40;
@@ -610,6 +667,7 @@ void Ens::create(Ctx* c, const Mesh* m, const Problem& prob, int member_pad)
     if (P.precision == NLTH_MIXED && P.inner_dtype == NLTH_INNER_FP32) D32.alloc(bg, nD * 4);
     if (P.precision == NLTH_MIXED && P.inner_dtype == NLTH_INNER_BF16) D16.alloc(bg, (size_t)ne_pad * 4 * 11 * MB * 4);
     h.alloc(bg, (size_t)m->ne * MB * 8);
+    fbuf.alloc(bg, (size_t)ne_pad * 30 * MB * 8);
     const DevMesh dm = m->dev();
     launch_law_init(s, dm, MB, MB, mat.as<double>(), P.nl, P.ns, dirs.as<double>(), w.as<double>(),
                     D64.as<double>(), D32.as<float>(), D16.as<uint32_t>(), h.as<double>());
@@ -726,31 +784,62 @@ void Ens::destroy()
     ctx = nullptr;
 }
 
-void Ens::ebe(OpMode mode, const double* x1, const double* x2, double* y, const int* act)
+// y (+)= A-type operator of mode applied to x1 (and x2 for the right-hand
+// side).  Gather path: one launch writes every element's nodal forces, a
+// second sums them per node (y = sum + bscale * base).  Colour path: one
+// launch per colour adds the forces into y (y must hold base beforehand).
+void Ens::ebe(OpMode mode, const double* x1, const double* x2, double* y, const int* act, const double* base,
+              double bscale)
 {
     const DevMesh dm = mesh->dev();
     set_ebe_block(ebe_block);
+    if (!scatter) {
+        hipEvent_t t0;
+        tstart(t0);
+        launch_ebe<double>(s, mode, dm, MB, nm, 0, mesh->ne, D64.as<double>(), h.as<double>(), mat.as<double>(), P.nl,
+                           sc, x1, x2, fbuf.as<double>(), act, true);
+        launch_gather<double>(s, dm, MB, nm, fbuf.as<double>(), base, bscale, y, act);
+        tstop(t0, &pc_ebe64, (int64_t)mesh->ne * nm);
+        return;
+    }
+    if (!base) launch_fill(s, y, 0.0, (long)ndof * MB);
+    else if (base != y && bscale == -1.0) launch_neg_copy(s, base, y, (long)ndof * MB);
+    else if (base != y || bscale != 1.0) throw Error{NLTH_EINVAL, "operator base: -1 * other array or 1 * y only"};
     for (int c = 0; c < mesh->ncolor; ++c) {
         const int e0 = mesh->color_off[c], e1 = mesh->color_off[c + 1];
         hipEvent_t t0;
         tstart(t0);
         launch_ebe<double>(s, mode, dm, MB, nm, e0, e1, D64.as<double>(), h.as<double>(), mat.as<double>(), P.nl, sc,
-                           x1, x2, y, act);
+                           x1, x2, y, act, false);
         tstop(t0, &pc_ebe64, (int64_t)(e1 - e0) * nm);
     }
 }
 
+// y = A x with the inner operator's arithmetic (FP32, D in FP32 or bfloat16)
 void Ens::ebe32(const float* x, float* y, const int* act)
 {
     const DevMesh dm = mesh->dev();
     set_ebe_block(ebe_block);
-    for (int c = 0; c < mesh->ncolor; ++c) {
-        const int e0 = mesh->color_off[c], e1 = mesh->color_off[c + 1];
+    if (!scatter) {
+        float* f = (float*)fbuf.p;
         hipEvent_t t0;
         tstart(t0);
-        launch_ebe32(s, dm, MB, nm, e0, e1, D32.as<float>(), D16.as<uint32_t>(), h.as<double>(), mat.as<double>(), sc,
-                     x, y, act);
-        tstop(t0, &pc_ebe32, (int64_t)(e1 - e0) * nm);
+        launch_ebe32(s, dm, MB, nm, 0, mesh->ne, D32.as<float>(), D16.as<uint32_t>(), h.as<double>(),
+                     mat.as<double>(), sc, x, f, act, true);
+        tstop(t0, &pc_ebe32, (int64_t)mesh->ne * nm);
+        tstart(t0);
+        launch_gather<float>(s, dm, MB, nm, f, nullptr, 0.0f, y, act);
+        tstop(t0, &pc_gather32, (int64_t)mesh->nn * nm);
+    } else {
+        launch_fill32(s, y, 0.0f, (long)ndof * MB);
+        for (int c = 0; c < mesh->ncolor; ++c) {
+            const int e0 = mesh->color_off[c], e1 = mesh->color_off[c + 1];
+            hipEvent_t t0;
+            tstart(t0);
+            launch_ebe32(s, dm, MB, nm, e0, e1, D32.as<float>(), D16.as<uint32_t>(), h.as<double>(), mat.as<double>(),
+                         sc, x, y, act, false);
+            tstop(t0, &pc_ebe32, (int64_t)(e1 - e0) * nm);
+        }
     }
     launch_dashpot<float>(s, dm, MB, nm, mat.as<double>(), P.nl, (float)(2.0 / P.dt), x, y, nullptr, act);
 }
@@ -758,8 +847,7 @@ void Ens::ebe32(const float* x, float* y, const int* act)
 void Ens::build_rhs()
 {
     // b = f - q + C v + M (a + 4/dt v), f = 2 C_base v_I
-    launch_neg_copy(s, q.as<double>(), b.as<double>(), (long)ndof * MB);
-    ebe(OP_RHS, v.as<double>(), a.as<double>(), b.as<double>(), stepping.as<int>());
+    ebe(OP_RHS, v.as<double>(), a.as<double>(), b.as<double>(), stepping.as<int>(), q.as<double>(), -1.0);
     launch_dashpot<double>(s, mesh->dev(), MB, nm, mat.as<double>(), P.nl, 1.0, v.as<double>(), b.as<double>(),
                            vI_cur.as<double>(), stepping.as<int>());
 }
@@ -799,7 +887,7 @@ void Ens::fin(FinalizeStage st, int nd, int nblk, double tol2, int maxit)
 
 void Ens::apply_A64(const double* x, double* y, const int* act)
 {
-    ebe(OP_A, x, nullptr, y, act);
+    ebe(OP_A, x, nullptr, y, act, nullptr, 0.0);
     launch_dashpot<double>(s, mesh->dev(), MB, nm, mat.as<double>(), P.nl, 2.0 / P.dt, x, y, nullptr, act);
 }
 
@@ -813,13 +901,12 @@ void Ens::solve_pcg()
     const int* act = cs.active;
     const double tol2 = P.cg_tol * P.cg_tol;
     double* pd = partial.as<double>();
-    launch_fill(s, Ap.as<double>(), 0.0, n * MB);
     apply_A64(x, Ap.as<double>(), st);
     launch_pcg_start(s, mesh->nn, MB, nm, b.as<double>(), Ap.as<double>(), pinv.as<double>(), r.as<double>(),
                      z.as<double>(), p.as<double>(), st, pd, &nblk);
     fin(FIN_START, 3, nblk, tol2, P.cg_maxit);
     launch_zero_if_b0(s, n, MB, nm, x, cs.bb, st);
-    launch_p_update<double>(s, n, MB, nm, z.as<double>(), p.as<double>(), nullptr, nullptr, Ap.as<double>());
+    launch_p_update<double>(s, n, MB, nm, z.as<double>(), p.as<double>(), nullptr, nullptr, nullptr);
     if (!read_any_active(act)) return;
     for (;;) {
         run_iters(1, check_every);
@@ -864,7 +951,7 @@ void Ens::inner_iter()
     launch_inner_update(s, mesh->nn, MB, nm, iz.as<float>(), ir.as<float>(), iw.as<float>(), ip.as<float>(),
                         iAp.as<float>(), pinv32.as<float>(), cs.ialpha, iact, pd, &nblk);
     fin(FIN_IN_BETA, 2, nblk, tol2, P.inner_maxit);
-    launch_p_update<float>(s, n, MB, nm, iw.as<float>(), ip.as<float>(), cs.ibeta, iact, iAp.as<float>());
+    launch_p_update<float>(s, n, MB, nm, iw.as<float>(), ip.as<float>(), cs.ibeta, iact, nullptr);
 }
 
 // one FP64 block-Jacobi PCG iteration
@@ -882,7 +969,7 @@ void Ens::pcg_iter()
     launch_pcg_update(s, mesh->nn, MB, nm, x, r.as<double>(), z.as<double>(), p.as<double>(), Ap.as<double>(),
                       pinv.as<double>(), cs.alpha, act, pd, &nblk);
     fin(FIN_BETA, 2, nblk, tol2, P.cg_maxit);
-    launch_p_update<double>(s, n, MB, nm, z.as<double>(), p.as<double>(), cs.beta, act, Ap.as<double>());
+    launch_p_update<double>(s, n, MB, nm, z.as<double>(), p.as<double>(), cs.beta, act, nullptr);
 }
 
 // k iterations of kind 0 (inner) or 1 (FP64 PCG); a full chunk is captured
@@ -928,7 +1015,6 @@ void Ens::solve_fcg()
     const int* act = cs.active;
     const double tol2 = P.cg_tol * P.cg_tol;
     double* pd = partial.as<double>();
-    launch_fill(s, Ap.as<double>(), 0.0, n * MB);
     apply_A64(x, Ap.as<double>(), st);
     launch_pcg_start(s, mesh->nn, MB, nm, b.as<double>(), Ap.as<double>(), pinv.as<double>(), r.as<double>(),
                      z.as<double>(), p.as<double>(), st, pd, &nblk);
@@ -938,7 +1024,7 @@ void Ens::solve_fcg()
     inner_solve();
     launch_inner_out(s, n, MB, nm, iz.as<float>(), z.as<double>(), Ap.as<double>(), r.as<double>(), act, pd, &nblk);
     fin(FIN_FCG_RZ, 2, nblk, tol2, P.cg_maxit);
-    launch_p_update<double>(s, n, MB, nm, z.as<double>(), p.as<double>(), nullptr, act, Ap.as<double>());
+    launch_p_update<double>(s, n, MB, nm, z.as<double>(), p.as<double>(), nullptr, act, nullptr);
     for (;;) {
         apply_A64(p.as<double>(), Ap.as<double>(), act);
         dots(1, p.as<double>(), Ap.as<double>(), nullptr, nullptr, nullptr, nullptr, nblk);
@@ -950,7 +1036,7 @@ void Ens::solve_fcg()
         launch_inner_out(s, n, MB, nm, iz.as<float>(), z.as<double>(), Ap.as<double>(), r.as<double>(), act, pd,
                          &nblk);
         fin(FIN_FCG_BETA, 2, nblk, tol2, P.cg_maxit);
-        launch_p_update<double>(s, n, MB, nm, z.as<double>(), p.as<double>(), cs.beta, act, Ap.as<double>());
+        launch_p_update<double>(s, n, MB, nm, z.as<double>(), p.as<double>(), cs.beta, act, nullptr);
     }
 }
 
@@ -1031,7 +1117,7 @@ void Ens::one_step()
     if (P.precision == NLTH_FP64) solve_pcg();
     else solve_fcg();
     tstart(t0);
-    ebe(OP_K, du.as<double>(), nullptr, q.as<double>(), stepping.as<int>());
+    ebe(OP_K, du.as<double>(), nullptr, q.as<double>(), stepping.as<int>(), q.as<double>(), 1.0);
     launch_newmark(s, ndof, MB, nm, du.as<double>(), u.as<double>(), v.as<double>(), a.as<double>(), P.dt,
                    stepping.as<int>());
     tstop(t0, &pc_other, 0);
@@ -1221,7 +1307,8 @@ int nlth_mesh_query(const nlth_mesh* mesh, nlth_mesh_info* info, int32_t* elem_o
         info->n_bnodes = mesh->nbn;
         info->volume = mesh->volume;
     }
-    if (elem_order) std::copy(mesh->order.begin(), mesh->order.end(), elem_order);
+    if (elem_order)
+        for (int i = 0; i < mesh->ne; ++i) elem_order[i] = mesh->order[mesh->color_elems[i]];
     if (color_offsets) std::copy(mesh->color_off.begin(), mesh->color_off.end(), color_offsets);
     API_END
 }
@@ -1296,12 +1383,14 @@ int nlth_ens_set_tuning(nlth_ens* ens, const nlth_tuning* t)
     if (t->check_every < 0 || t->check_every > 64) throw Error{NLTH_EINVAL, "check_every must be in [0, 64]"};
     if (t->inner_maxit < 0 || t->inner_maxit > 100000 || !(t->inner_tol >= 0) || t->inner_tol >= 1)
         throw Error{NLTH_EINVAL, "inner_maxit must be in [0, 100000] and inner_tol in [0, 1)"};
+    if (t->scatter < -1 || t->scatter > 1) throw Error{NLTH_EINVAL, "scatter must be -1, 0 or 1"};
     std::lock_guard<std::mutex> g(ens->ctx->mu);
     if (t->ebe_block) ens->ebe_block = t->ebe_block;
     if (t->check_every) ens->check_every = t->check_every;
     if (t->use_graph >= 0) ens->use_graph = t->use_graph != 0;
     if (t->inner_maxit) ens->P.inner_maxit = t->inner_maxit;
     if (t->inner_tol > 0) ens->P.inner_tol = t->inner_tol;
+    if (t->scatter >= 0) ens->scatter = t->scatter;
     // captured chunks hold the old launch shapes
     if (ens->g_inner) (void)hipGraphExecDestroy(ens->g_inner);
     if (ens->g_pcg) (void)hipGraphExecDestroy(ens->g_pcg);
@@ -1313,7 +1402,7 @@ int nlth_ens_set_tuning(nlth_ens* ens, const nlth_tuning* t)
 int nlth_ens_reset_stats(nlth_ens* ens)
 {
     if (!ens) return NLTH_EINVAL;
-    ens->pc_ebe64 = ens->pc_ebe32 = ens->pc_vec = ens->pc_law = ens->pc_other = ProfCat{};
+    ens->pc_ebe64 = ens->pc_ebe32 = ens->pc_gather32 = ens->pc_vec = ens->pc_law = ens->pc_other = ProfCat{};
     ens->ms_total = ens->ms_copy = 0;
     ens->h2d_bytes = ens->d2h_bytes = 0;
     return NLTH_OK;
@@ -1352,6 +1441,8 @@ int nlth_ens_stats(const nlth_ens* ens, nlth_stats* st)
     st->n_colors = ens->mesh->ncolor;
     st->device_bytes = ens->dev_bytes;
     st->host_bytes = ens->host_bytes;
+    st->ms_gather32 = ens->pc_gather32.ms;
+    st->n_gather32 = ens->pc_gather32.n;
     API_END
 }
 
@@ -1435,7 +1526,7 @@ int nlth_apply_operator(nlth_ctx* ctx, const nlth_mesh* mesh, const nlth_problem
     if (precision == NLTH_FP64) {
         NLTH_HIP(hipMemcpy(e->p.p, x, n * 8, hipMemcpyHostToDevice));
         launch_fill(s, e->Ap.as<double>(), 0.0, n);
-        e->ebe((OpMode)which, e->p.as<double>(), nullptr, e->Ap.as<double>(), e->stepping.as<int>());
+        e->ebe((OpMode)which, e->p.as<double>(), nullptr, e->Ap.as<double>(), e->stepping.as<int>(), nullptr, 0.0);
         if (which == NLTH_OP_A)
             launch_dashpot<double>(s, mesh->dev(), 1, 1, e->mat.as<double>(), P.nl, 2.0 / P.dt, e->p.as<double>(),
                                    e->Ap.as<double>(), nullptr, e->stepping.as<int>());

@@ -198,20 +198,34 @@ __device__ __forceinline__ float bf2f(uint32_t b) { return __uint_as_float(b << 
 
 constexpr int kEdgeOpp[6] = {5, 3, 4, 1, 2, 0};  // edge opposite each edge
 
-// DK: storage of D, 0 = T itself, 1 = bfloat16 pairs (uint32 words)
-template <typename T, int DK, int MODE, bool WAVE_ELEM>
+// element outputs (the 30 nodal forces of an element-member) stored for the
+// gather: row r = 3 * local node + component, element blocks of EB as for D
+__device__ __forceinline__ size_t f_index(long e, int r, int MB, int EB, int m)
+{
+    return (((size_t)(e / EB) * 30 + r) * EB + e % EB) * (size_t)MB + m;
+}
+
+// DK: storage of D, 0 = T itself, 1 = bfloat16 pairs (uint32 words).
+// OUT = 0: positions [e0, e1) of the colour lists (tets of one colour share no
+// node), forces added into y.  OUT = 1: storage positions [e0, e1), forces
+// written to the element-output array y (f_index); the grid is a multiple of
+// 8 blocks and each XCD takes a contiguous range of elements.
+template <typename T, int DK, int MODE, bool WAVE_ELEM, int OUT>
 __global__ __launch_bounds__(256) void k_ebe(DevMesh M, int MB, int nm, int e0, int e1,
                                             const void* __restrict__ Dv, const double* __restrict__ h,
                                             const double* __restrict__ mat, StepConst sc,
                                             const T* __restrict__ x1, const T* __restrict__ x2,
                                             T* __restrict__ y, const int* __restrict__ active)
 {
-    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    long blk = blockIdx.x;
+    if (OUT) blk = (blk % 8) * (gridDim.x / 8) + blk / 8;
+    const long t = blk * blockDim.x + threadIdx.x;
     const int m = (int)(t % MB);
     long e = e0 + t / MB;
     if (WAVE_ELEM) e = __builtin_amdgcn_readfirstlane((int)e);  // one element per wavefront
     if (e >= e1 || m >= nm) return;
     if (active && !active[m]) return;
+    if (!OUT) e = WAVE_ELEM ? __builtin_amdgcn_readfirstlane(M.celem[e]) : M.celem[e];
     const int EB = MB >= 64 ? 1 : 64 / MB;
     const long ne = M.ne;
     const T* geo = geo_of<T>(M);
@@ -355,69 +369,126 @@ __global__ __launch_bounds__(256) void k_ebe(DevMesh M, int MB, int nm, int e0, 
             tdot_acc<T>(ST, g, (T)(4.0 * QB_), f[4 + q]);
         }
     }
+    if (OUT) {
+        // row bases are uniform per wavefront when EB == 1; the lane adds m
+        T* fb = y + f_index(e, 0, MB, EB, 0);
+        const size_t rs = (size_t)EB * MB;
 #pragma unroll
-    for (int n = 0; n < 10; ++n) {
-        T* yb = y + nbase[n];
+        for (int n = 0; n < 10; ++n)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) yb[(uint32_t)(c * MB + m)] += f[n][c];
+            for (int c = 0; c < 3; ++c) (fb + (3 * n + c) * rs)[m] = f[n][c];
+    } else {
+#pragma unroll
+        for (int n = 0; n < 10; ++n) {
+            T* yb = y + nbase[n];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) yb[(uint32_t)(c * MB + m)] += f[n][c];
+        }
     }
 }
+
+// y = sum of the element outputs at each node (incidences in ascending
+// order, so the sum is reproducible) + bscale * base (base may be NULL; it may
+// alias y).  One lane per (node, member); members with active[m] == 0 keep y.
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather(DevMesh M, int MB, int nm, const T* __restrict__ f,
+                                               const T* base, T bscale, T* y, const int* __restrict__ active)
+{
+    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const int m = (int)(t % MB);
+    long node = t / MB;
+    if (MB >= 64) node = __builtin_amdgcn_readfirstlane((int)node);
+    if (node >= M.nn || m >= nm) return;
+    if (active && !active[m]) return;
+    const int EB = MB >= 64 ? 1 : 64 / MB;
+    const uint32_t rs = (uint32_t)(EB * MB);
+    T a0 = 0, a1 = 0, a2 = 0;
+    const int q1 = M.inc_ptr[node + 1];
+    for (int q = M.inc_ptr[node]; q < q1; ++q) {
+        const int ent = M.inc[q];
+        const int e = ent / 10, k = ent - 10 * e;
+        const T* fb = f + f_index(e, 3 * k, MB, EB, m);
+        a0 += fb[0];
+        a1 += fb[rs];
+        a2 += fb[2 * rs];
+    }
+    const size_t yi = (size_t)node * 3 * MB + m;
+    if (base) {
+        a0 += bscale * base[yi];
+        a1 += bscale * base[yi + MB];
+        a2 += bscale * base[yi + 2 * MB];
+    }
+    y[yi] = a0;
+    y[yi + MB] = a1;
+    y[yi + 2 * MB] = a2;
+}
+
+template <typename T>
+void launch_gather(hipStream_t s, const DevMesh& M, int MB, int nm, const T* f, const T* base, T bscale, T* y,
+                   const int* active)
+{
+    long n = (long)M.nn * MB;
+    if (n > 0) hipLaunchKernelGGL((k_gather<T>), dim3(nblocks(n)), dim3(256), 0, s, M, MB, nm, f, base, bscale, y, active);
+}
+template void launch_gather<double>(hipStream_t, const DevMesh&, int, int, const double*, const double*, double,
+                                    double*, const int*);
+template void launch_gather<float>(hipStream_t, const DevMesh&, int, int, const float*, const float*, float, float*,
+                                   const int*);
 
 // threads per block of the element-by-element launches (a tuning knob; per
 // host thread so concurrent contexts do not interfere)
 static thread_local int t_ebe_block = 256;
 void set_ebe_block(int bs) { t_ebe_block = (bs == 64 || bs == 128 || bs == 256) ? bs : 256; }
 
-template <typename T, int MODE>
-static void ebe_dispatch(hipStream_t s, dim3 g, const DevMesh& M, int MB, int nm, int e0, int e1, const T* D,
-                         const double* h, const double* mat, StepConst sc, const T* x1, const T* x2, T* y,
-                         const int* active)
+// grid of an element launch: OUT launches round up to a multiple of 8 blocks
+static dim3 ebe_grid(long n, bool out)
 {
-    if (MB >= 64)
-        hipLaunchKernelGGL((k_ebe<T, 0, MODE, true>), g, dim3(t_ebe_block), 0, s, M, MB, nm, e0, e1, (const void*)D, h, mat, sc, x1, x2, y, active);
-    else
-        hipLaunchKernelGGL((k_ebe<T, 0, MODE, false>), g, dim3(t_ebe_block), 0, s, M, MB, nm, e0, e1, (const void*)D, h, mat, sc, x1, x2, y, active);
+    unsigned g = nblocks(n, t_ebe_block);
+    if (out) g = (g + 7) / 8 * 8;
+    return dim3(g);
+}
+
+template <typename T, int DK, int MODE>
+static void ebe_dispatch(hipStream_t s, const DevMesh& M, int MB, int nm, int e0, int e1, const void* D,
+                         const double* h, const double* mat, StepConst sc, const T* x1, const T* x2, T* y,
+                         const int* active, bool out)
+{
+    const dim3 g = ebe_grid((long)(e1 - e0) * MB, out), b(t_ebe_block);
+    if (MB >= 64) {
+        if (out) hipLaunchKernelGGL((k_ebe<T, DK, MODE, true, 1>), g, b, 0, s, M, MB, nm, e0, e1, D, h, mat, sc, x1, x2, y, active);
+        else hipLaunchKernelGGL((k_ebe<T, DK, MODE, true, 0>), g, b, 0, s, M, MB, nm, e0, e1, D, h, mat, sc, x1, x2, y, active);
+    } else {
+        if (out) hipLaunchKernelGGL((k_ebe<T, DK, MODE, false, 1>), g, b, 0, s, M, MB, nm, e0, e1, D, h, mat, sc, x1, x2, y, active);
+        else hipLaunchKernelGGL((k_ebe<T, DK, MODE, false, 0>), g, b, 0, s, M, MB, nm, e0, e1, D, h, mat, sc, x1, x2, y, active);
+    }
 }
 
 // inner FP32 operator (Eq. 1 left-hand side) with D stored in FP32 or bfloat16
 void launch_ebe32(hipStream_t s, const DevMesh& M, int MB, int nm, int e0, int e1, const float* D32,
                   const uint32_t* D16, const double* h, const double* mat, StepConst sc, const float* x, float* y,
-                  const int* active)
+                  const int* active, bool out)
 {
-    long n = (long)(e1 - e0) * MB;
-    if (n <= 0) return;
-    dim3 g(nblocks(n, t_ebe_block));
-    if (D16) {
-        if (MB >= 64)
-            hipLaunchKernelGGL((k_ebe<float, 1, OP_A, true>), g, dim3(t_ebe_block), 0, s, M, MB, nm, e0, e1, (const void*)D16, h, mat, sc, x, nullptr, y, active);
-        else
-            hipLaunchKernelGGL((k_ebe<float, 1, OP_A, false>), g, dim3(t_ebe_block), 0, s, M, MB, nm, e0, e1, (const void*)D16, h, mat, sc, x, nullptr, y, active);
-    } else {
-        ebe_dispatch<float, OP_A>(s, g, M, MB, nm, e0, e1, D32, h, mat, sc, x, nullptr, y, active);
-    }
+    if (e1 <= e0) return;
+    if (D16) ebe_dispatch<float, 1, OP_A>(s, M, MB, nm, e0, e1, D16, h, mat, sc, x, nullptr, y, active, out);
+    else ebe_dispatch<float, 0, OP_A>(s, M, MB, nm, e0, e1, D32, h, mat, sc, x, nullptr, y, active, out);
 }
 
 template <typename T>
 void launch_ebe(hipStream_t s, OpMode mode, const DevMesh& M, int MB, int nm, int e0, int e1, const T* D,
                 const double* h, const double* mat, int, StepConst sc, const T* x1, const T* x2, T* y,
-                const int* active)
+                const int* active, bool out)
 {
-    long n = (long)(e1 - e0) * MB;
-    if (n <= 0) return;
-    dim3 g(nblocks(n, t_ebe_block));
+    if (e1 <= e0) return;
     switch (mode) {
-    case OP_A: ebe_dispatch<T, OP_A>(s, g, M, MB, nm, e0, e1, D, h, mat, sc, x1, x2, y, active); break;
-    case OP_K: ebe_dispatch<T, OP_K>(s, g, M, MB, nm, e0, e1, D, h, mat, sc, x1, x2, y, active); break;
-    case OP_M: ebe_dispatch<T, OP_M>(s, g, M, MB, nm, e0, e1, D, h, mat, sc, x1, x2, y, active); break;
-    case OP_RHS: ebe_dispatch<T, OP_RHS>(s, g, M, MB, nm, e0, e1, D, h, mat, sc, x1, x2, y, active); break;
+    case OP_A: ebe_dispatch<T, 0, OP_A>(s, M, MB, nm, e0, e1, D, h, mat, sc, x1, x2, y, active, out); break;
+    case OP_K: ebe_dispatch<T, 0, OP_K>(s, M, MB, nm, e0, e1, D, h, mat, sc, x1, x2, y, active, out); break;
+    case OP_M: ebe_dispatch<T, 0, OP_M>(s, M, MB, nm, e0, e1, D, h, mat, sc, x1, x2, y, active, out); break;
+    case OP_RHS: ebe_dispatch<T, 0, OP_RHS>(s, M, MB, nm, e0, e1, D, h, mat, sc, x1, x2, y, active, out); break;
     }
 }
 template void launch_ebe<double>(hipStream_t, OpMode, const DevMesh&, int, int, int, int, const double*,
                                  const double*, const double*, int, StepConst, const double*,
-                                 const double*, double*, const int*);
-template void launch_ebe<float>(hipStream_t, OpMode, const DevMesh&, int, int, int, int, const float*,
-                                const double*, const double*, int, StepConst, const float*,
-                                const float*, float*, const int*);
+                                 const double*, double*, const int*, bool);
 
 // ---------------------------------------------------------------------------
 // absorbing boundary: node-centric gather over boundary faces (deterministic)
@@ -484,8 +555,9 @@ __global__ __launch_bounds__(256) void k_diag(DevMesh M, int MB, int nm, int e0,
 {
     const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
     const int m = (int)(t % MB);
-    const long e = e0 + t / MB;
-    if (e >= e1 || m >= nm) return;
+    const long pos = e0 + t / MB;  // position in the colour lists
+    if (pos >= e1 || m >= nm) return;
+    const long e = M.celem[pos];
     const long ne = M.ne;
     double gL[4][3];
     for (int k = 0; k < 12; ++k) gL[k / 3][k % 3] = M.geo64[k * ne + e];

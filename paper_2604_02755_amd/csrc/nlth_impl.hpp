@@ -45,6 +45,10 @@ struct DevMesh {
     const double* f_n;    // [nf*3] unit normal
     const int* f_layer;   // [nf]
     const uint8_t* f_kind;
+    // node -> incidences (storage element * 10 + local node), ascending
+    const int* inc_ptr;   // [nn+1]
+    const int* inc;       // [10*ne]
+    const int* celem;     // [ne] storage positions grouped by colour
 };
 
 struct StepConst {
@@ -63,7 +67,11 @@ void launch_neg_copy(hipStream_t s, const double* a, double* b, long n);
 template <typename T>
 void launch_ebe(hipStream_t s, OpMode mode, const DevMesh& M, int MB, int nm, int e0, int e1,
                 const T* D, const double* h, const double* mat, int n_layers, StepConst sc,
-                const T* x1, const T* x2, T* y, const int* active);
+                const T* x1, const T* x2, T* y, const int* active, bool out);
+// y = sum over incident elements of the element outputs f (+ bscale * base)
+template <typename T>
+void launch_gather(hipStream_t s, const DevMesh& M, int MB, int nm, const T* f, const T* base, T bscale, T* y,
+                   const int* active);
 // node-centric absorbing-boundary dashpot: y += coef * C_abs x1 (+ 2 C_base vI for RHS)
 template <typename T>
 void launch_dashpot(hipStream_t s, const DevMesh& M, int MB, int nm, const double* mat, int n_layers,
@@ -87,7 +95,7 @@ void set_ebe_block(int bs);
 // inner FP32 operator (A) with D in FP32 (D32) or bfloat16 pairs (D16, if non-null)
 void launch_ebe32(hipStream_t s, const DevMesh& M, int MB, int nm, int e0, int e1, const float* D32,
                   const uint32_t* D16, const double* h, const double* mat, StepConst sc, const float* x, float* y,
-                  const int* active);
+                  const int* active, bool out);
 void launch_theta_init(hipStream_t s, void* theta_chunk, long ecp, int ns, int MB);
 void launch_law(hipStream_t s, const DevMesh& M, int MB, int nm, int e0, int ec, long ecp, const double* mat,
                 int n_layers, const int* nonlinear, int ns, const double* dirs, const double* w,

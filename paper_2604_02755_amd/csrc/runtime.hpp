@@ -58,12 +58,14 @@ struct Mesh {
     double volume = 0.0;
     // host copies / analysis
     std::vector<double> xyz;
-    std::vector<int> order;        // sorted position -> input tet
-    std::vector<int> inv_order;    // input tet -> sorted position
-    std::vector<int> color_off;    // [ncolor+1]
+    std::vector<int> order;        // storage position -> input tet (Morton order)
+    std::vector<int> inv_order;    // input tet -> storage position
+    std::vector<int> color_off;    // [ncolor+1] into color_elems
+    std::vector<int> color_elems;  // storage positions grouped by colour
     std::vector<int> recv;
     // device
     DevBuf conn, geo64, geo32, layer, bn_node, bn_ptr, bn_face, bn_loc, f_node, f_M, f_n, f_layer, f_kind, recv_d;
+    DevBuf inc_ptr, inc, celem;
     int nbn = 0;
     mutable std::atomic<int> refs{0};  // pending requests using the mesh
     DevMesh dev() const;
@@ -93,6 +95,8 @@ struct Ens {
     DevBuf u, v, a, q, du, b, r, z, p, Ap, diag, pinv, pinv32;
     DevBuf ir, iz, ip, iw, iAp;
     DevBuf D64, D32, D16, h;             // D16: bfloat16 pairs for the inner operator
+    DevBuf fbuf;                        // element outputs of the gather path (FP64 or FP32)
+    int scatter = 0;                    // 0: element outputs + node gather; 1: colour launches
     DevBuf theta;                       // resident law state (or the device chunk ring)
     DevBuf theta_host;                  // pinned host state when paged
     DevBuf hist, vmax, iters_dev;
@@ -114,7 +118,7 @@ struct Ens {
     int check_every = 8;
     // profiling
     bool profile = false;
-    ProfCat pc_ebe64, pc_ebe32, pc_vec, pc_law, pc_other;
+    ProfCat pc_ebe64, pc_ebe32, pc_gather32, pc_vec, pc_law, pc_other;
     std::vector<std::pair<std::pair<hipEvent_t, hipEvent_t>, ProfCat*>> pending;
     std::vector<hipEvent_t> ev_pool;
     double ms_total = 0, ms_copy = 0;
@@ -129,7 +133,8 @@ struct Ens {
     void one_step();                    // uses h_member_step / h_stepping
     void read(nlth_result* res) const;
     // pieces
-    void ebe(OpMode mode, const double* x1, const double* x2, double* y, const int* active);
+    void ebe(OpMode mode, const double* x1, const double* x2, double* y, const int* active, const double* base,
+             double bscale);
     void ebe32(const float* x, float* y, const int* active);
     void build_rhs();
     void build_diag();

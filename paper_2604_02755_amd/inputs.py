@@ -442,6 +442,22 @@ def config(c: int, n_steps: int | None = None, n_members: int | None = None,
     raise ValueError(c)
 
 
+def serving_mesh(n: int, recv_stride: int = 4) -> Mesh:
+    """Request mesh of the serving stream: n x n x 16 one-metre cubes with the
+    config-0 layers."""
+    return box_mesh(n, n, 16, 1.0, two_layer(4.0), recv_stride)
+
+
+def serving_problem(req: dict, precision: int = PRECISION_MIXED, **kw) -> Problem:
+    """Problem of one serving request: one member, its own layer Vs and wave
+    (seeded by the request index), gamma_ref 1e-3, 12 springs."""
+    acc = member_waves(4, [req["wave_seed_member"]], req["steps"], 1e-3)
+    prob = make_problem(1, CFG0_LAYERS["vs"], CFG0_LAYERS["rho"], n_springs=12, n_steps=req["steps"],
+                        input_acc=acc, precision=precision, **kw)
+    prob.vs = np.ascontiguousarray(np.asarray(req["vs"], float)[None, :])
+    return prob
+
+
 def serving_requests(rate: float = 4.0, window_s: float = 60.0, seed: int = 4000,
                      sizes=(32, 48, 64), steps_range=(500, 2000)):
     """Poisson request stream: list of dicts (t_arrival, n, steps, vs, seed)."""

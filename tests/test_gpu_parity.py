@@ -164,16 +164,22 @@ def test_tuning_knobs_keep_results(gpu_ctx, nlth_mod):
         finally:
             ens.close()
 
-    say("tuning knobs: graph, direct, 128 threads / 4 per check, 64 threads / 16 per check")
+    say("tuning knobs: graph, direct, 128 threads / 4 per check, 64 threads / 16 per check, colours")
     base = run()
     for kw in (dict(use_graph=0), dict(ebe_block=128, check_every=4), dict(ebe_block=64, check_every=16)):
         o = run(**kw)
         d = float(np.max(np.abs(o["vel"] - base["vel"])))
         say("  ", kw, "max |dv|", d, "iters equal", bool(np.array_equal(o["iters"], base["iters"])))
         assert d == 0.0 and np.array_equal(o["iters"], base["iters"])
+    # one launch per colour adding into y: another summation order, same
+    # operator; the runs agree to the solver tolerance
+    o = run(scatter=1)
+    err = float(np.linalg.norm(o["vel"] - base["vel"]) / np.linalg.norm(base["vel"]))
+    say("   colour path vs gather path rel err", err)
+    assert err < 1e-8
     ens = gpu_ctx.ensemble(mh, mesh, prob)
     try:
-        for bad in (dict(ebe_block=100), dict(check_every=65), dict(inner_tol=2.0)):
+        for bad in (dict(ebe_block=100), dict(check_every=65), dict(inner_tol=2.0), dict(scatter=2)):
             with pytest.raises(nlth_mod.NlthError) as ei:
                 ens.set_tuning(**bad)
             assert ei.value.code == nlth_mod.NLTH_EINVAL
