@@ -137,6 +137,7 @@ def serve_run(rate, window_s, steps_range, sizes=(32, 48, 64), max_batch=16, n_c
                     j = pending.pop(tk)
                     lat[j] = time.perf_counter() - t0 - reqs[j]["t"]
                     rcs[j] = ctx.wait(tk, 0.0)
+                    ctx.release(tk)
             if time.perf_counter() - last_log > 15:
                 last_log = time.perf_counter()
                 log(f"serve: t={now:.0f}s submitted {i}/{len(reqs)}, in flight {len(pending)}, done {len(lat)}")

@@ -78,7 +78,8 @@ typedef struct {
     int64_t host_budget;  /* pinned host bytes for paged law state; 0 = 64 GiB */
     void* stream;         /* optional hipStream_t for compute (e.g. torch's); NULL = own */
     int32_t log_level;    /* 0 silent, 1 per solve, 2 per step */
-    int32_t max_batch;    /* serving: members per batch (0 = 64) */
+    int32_t max_batch;    /* serving: most members per batch (0 = 64); a batch is sized,
+                             in powers of two, for the members waiting when it forms */
 } nlth_ctx_opts;
 
 /* Create a context on HIP device `device` (or NLTH_DEVICE_NONE).  `opts` may
@@ -253,6 +254,10 @@ int nlth_poll(nlth_ctx* ctx, uint64_t ticket, int32_t* done);
 /* returns the request's final status, or NLTH_ETIMEDOUT */
 int nlth_wait(nlth_ctx* ctx, uint64_t ticket, double timeout_s);
 int nlth_cancel(nlth_ctx* ctx, uint64_t ticket);
+/* Forget a finished or cancelled request (its ticket becomes unknown); the
+ * context keeps every request's bookkeeping until then.  NLTH_EBUSY while it
+ * is queued or running, NLTH_ENOTFOUND for an unknown ticket. */
+int nlth_release(nlth_ctx* ctx, uint64_t ticket);
 
 /* Diagnostic: one element-by-element operator application y = Op x for
  * member 0 of `prob` (Eq. 1 left-hand side with K from the given D and C from

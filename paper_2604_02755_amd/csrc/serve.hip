@@ -163,12 +163,19 @@ void Ctx::worker_loop()
                         break;
                     }
                 if (!target) {
-                    // a new batch: the largest power-of-two slot count that fits the budget
+                    // a new batch sized for the members now waiting for this mesh and
+                    // these shared parameters (a step costs the same for every slot,
+                    // busy or not), halved until it fits the budget
                     std::unique_ptr<Batch> nb(new Batch());
                     nb->mesh = r->mesh;
                     nb->key = r->P;
                     nb->cap_steps = std::max(r->P.n_steps, 2048);
-                    int slots = std::max(max_batch, need);
+                    int waiting = need;
+                    for (auto& q : queue)
+                        if (q->mesh == r->mesh && same_shared(q->P, r->P) && !q->cancel.load()) waiting += q->P.nm;
+                    int slots = 1;
+                    while (slots < std::min(waiting, max_batch)) slots *= 2;
+                    slots = std::max(slots, need);
                     bool made = false;
                     std::string why;
                     while (!made && slots >= need) {
@@ -246,6 +253,7 @@ void Ctx::worker_loop()
                     ++placed;
                 }
                 r->state = 1;
+                std::vector<double>().swap(r->P.acc);  // the batch holds its own copy
             }
             for (auto& r : keep) queue.push_back(r);
         }
@@ -414,6 +422,23 @@ int nlth_cancel(nlth_ctx* ctx, uint64_t ticket)
         it->second->cancel = 1;
     }
     ctx->scv.notify_all();
+    return NLTH_OK;
+}
+
+int nlth_release(nlth_ctx* ctx, uint64_t ticket)
+{
+    if (!ctx) return NLTH_EINVAL;
+    std::lock_guard<std::mutex> g(ctx->smu);
+    auto it = ctx->requests.find(ticket);
+    if (it == ctx->requests.end()) {
+        set_error(ctx, Error{NLTH_ENOTFOUND, "unknown ticket"});
+        return NLTH_ENOTFOUND;
+    }
+    if (it->second->state.load() < 2) {
+        set_error(ctx, Error{NLTH_EBUSY, "request still queued or running"});
+        return NLTH_EBUSY;
+    }
+    ctx->requests.erase(it);
     return NLTH_OK;
 }
 

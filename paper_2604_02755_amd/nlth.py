@@ -108,6 +108,7 @@ EXPORTS = {
     "nlth_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(C.c_int32)]),
     "nlth_wait": (C.c_int, [C.c_void_p, C.c_uint64, C.c_double]),
     "nlth_cancel": (C.c_int, [C.c_void_p, C.c_uint64]),
+    "nlth_release": (C.c_int, [C.c_void_p, C.c_uint64]),
     "nlth_apply_operator": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(nlth_problem), C.c_int32,
                                       C.c_int32, _dp, _dp, _dp, _dp]),
 }
@@ -365,6 +366,13 @@ class Context:
 
     def cancel(self, ticket):
         return lib().nlth_cancel(self.h, C.c_uint64(ticket))
+
+    def release(self, ticket):
+        """Forget a finished request; its result dict stays valid."""
+        rc = lib().nlth_release(self.h, C.c_uint64(ticket))
+        if rc == NLTH_OK:
+            getattr(self, "_pending", {}).pop(ticket, None)
+        return rc
 
     def close(self):
         for mh in self._meshes:

@@ -47,6 +47,8 @@ def test_results_alone_and_in_the_mix(nlth_mod, precision, tol):
             print("  ticket", t, dims, "in the mix vs alone", err, flush=True)
             assert err < tol
             assert np.array_equal(out["iters"][0, :, 0] > 0, alone["iters"][0, :, 0] > 0)
+            assert ctx.release(t) == 0
+            assert ctx.poll(t)[1] == nlth_mod.NLTH_ENOTFOUND
     finally:
         ctx.close()
 
