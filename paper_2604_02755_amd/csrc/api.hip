@@ -403,6 +403,8 @@ static void build_mesh(Ctx* ctx, const nlth_mesh_desc* d, Mesh& M)
         bn_ptr.push_back((int)bn_face.size());
     }
     M.nbn = (int)bn_node.size();
+    std::vector<int> bn_of_node(nn, -1);
+    for (int i = 0; i < M.nbn; ++i) bn_of_node[bn_node[i]] = i;
     M.nrecv = d->n_recv;
     M.recv.assign(d->recv, d->recv + d->n_recv);
     for (int r = 0; r < d->n_recv; ++r)
@@ -429,6 +431,7 @@ static void build_mesh(Ctx* ctx, const nlth_mesh_desc* d, Mesh& M)
     upload(b, M.inc_ptr, inc_ptr);
     upload(b, M.inc, inc);
     upload(b, M.celem, M.color_elems);
+    upload(b, M.bn_of, bn_of_node);
 }
 
 DevMesh Mesh::dev() const
@@ -453,6 +456,7 @@ DevMesh Mesh::dev() const
     d.inc_ptr = inc_ptr.as<int>();
     d.inc = inc.as<int>();
     d.celem = celem.as<int>();
+    d.bn_of_node = bn_of.as<int>();
     return d;
 }
 
@@ -538,7 +542,7 @@ int64_t ensemble_bytes(const Mesh& m, const Problem& p, int MB, bool paged)
     bytes += (int64_t)m.ne * 4 * 21 * MB * 8;               // D64
     if (p.precision == NLTH_MIXED) bytes += (int64_t)m.ne * 4 * (p.inner_dtype == NLTH_INNER_FP32 ? 84 : 44) * MB;
     bytes += (int64_t)m.ne * MB * 8;                        // h
-    bytes += (int64_t)m.ne * 30 * MB * 8;                   // element outputs
+    if (MB <= 256) bytes += (int64_t)m.ne * 30 * MB * 8;    // element outputs
     bytes += (int64_t)p.n_steps * std::max(1, m.nrecv) * 3 * MB * 8;  // receiver history
     bytes += (int64_t)p.n_steps * 3 * MB * 8 * 2;           // acc, vI
     if (!paged) bytes += (int64_t)m.ne * 4 * p.ns * MB * 40;
@@ -667,7 +671,10 @@ void Ens::create(Ctx* c, const Mesh* m, const Problem& prob, int member_pad)
     if (P.precision == NLTH_MIXED && P.inner_dtype == NLTH_INNER_FP32) D32.alloc(bg, nD * 4);
     if (P.precision == NLTH_MIXED && P.inner_dtype == NLTH_INNER_BF16) D16.alloc(bg, (size_t)ne_pad * 4 * 11 * MB * 4);
     h.alloc(bg, (size_t)m->ne * MB * 8);
-    fbuf.alloc(bg, (size_t)ne_pad * 30 * MB * 8);
+    // element outputs of the gather path; the node gather covers at most 256
+    // member slots per block, wider ensembles take the colour path
+    if (MB <= 256) fbuf.alloc(bg, (size_t)ne_pad * 30 * MB * 8);
+    else scatter = 1;
     const DevMesh dm = m->dev();
     launch_law_init(s, dm, MB, MB, mat.as<double>(), P.nl, P.ns, dirs.as<double>(), w.as<double>(),
                     D64.as<double>(), D32.as<float>(), D16.as<uint32_t>(), h.as<double>());
@@ -733,7 +740,7 @@ void Ens::create(Ctx* c, const Mesh* m, const Problem& prob, int member_pad)
     launch_fill(s, vmax.as<double>(), 0.0, (long)MB * std::max(1, m->nrecv));
     iters_dev.alloc(bg, (size_t)MB * ns_steps * 2 * 4);
     NLTH_HIP(hipMemsetAsync(iters_dev.p, 0, iters_dev.bytes, s));
-    partial.alloc(bg, (size_t)3 * kMaxPartialBlocks * MB * 8);
+    partial.alloc(bg, (size_t)kPartialRows * MB * 8);
     // CG scalars: 12 double arrays and 9 int arrays of MB
     scal.alloc(bg, (size_t)MB * (12 * 8 + 9 * 4) + 64);
     NLTH_HIP(hipMemsetAsync(scal.p, 0, scal.bytes, s));
@@ -784,12 +791,15 @@ void Ens::destroy()
     ctx = nullptr;
 }
 
-// y (+)= A-type operator of mode applied to x1 (and x2 for the right-hand
-// side).  Gather path: one launch writes every element's nodal forces, a
-// second sums them per node (y = sum + bscale * base).  Colour path: one
-// launch per colour adds the forces into y (y must hold base beforehand).
+// y = operator of `mode` applied to x1 (and x2 for the right-hand side)
+//     + bscale * base + the boundary dashpot dcoef * C_abs x1 (+ 2 C_base vI),
+// and with nblk the per-member block partials of x1 . y in `partial`.
+// Gather path: one launch writes every element's nodal forces, a second sums
+// them per node with the base, the dashpot and the dot fused in.  Colour
+// path: one launch per colour adds the forces into y, then the dashpot and
+// the dot as launches of their own.
 void Ens::ebe(OpMode mode, const double* x1, const double* x2, double* y, const int* act, const double* base,
-              double bscale)
+              double bscale, double dcoef, const double* vI, int* nblk)
 {
     const DevMesh dm = mesh->dev();
     set_ebe_block(ebe_block);
@@ -798,7 +808,9 @@ void Ens::ebe(OpMode mode, const double* x1, const double* x2, double* y, const 
         tstart(t0);
         launch_ebe<double>(s, mode, dm, MB, nm, 0, mesh->ne, D64.as<double>(), h.as<double>(), mat.as<double>(), P.nl,
                            sc, x1, x2, fbuf.as<double>(), act, true);
-        launch_gather<double>(s, dm, MB, nm, fbuf.as<double>(), base, bscale, y, act);
+        double* pd = nblk ? partial.as<double>() : nullptr;
+        launch_gather<double>(s, dm, MB, nm, fbuf.as<double>(), base, bscale, y, act, x1, pd, nblk);
+        if (dcoef != 0.0) launch_dashpot<double>(s, dm, MB, nm, mat.as<double>(), P.nl, dcoef, x1, y, vI, act, pd, nblk);
         tstop(t0, &pc_ebe64, (int64_t)mesh->ne * nm);
         return;
     }
@@ -813,13 +825,17 @@ void Ens::ebe(OpMode mode, const double* x1, const double* x2, double* y, const 
                            x1, x2, y, act, false);
         tstop(t0, &pc_ebe64, (int64_t)(e1 - e0) * nm);
     }
+    if (dcoef != 0.0) launch_dashpot<double>(s, dm, MB, nm, mat.as<double>(), P.nl, dcoef, x1, y, vI, act);
+    if (nblk) dots(1, x1, y, nullptr, nullptr, nullptr, nullptr, *nblk);
 }
 
-// y = A x with the inner operator's arithmetic (FP32, D in FP32 or bfloat16)
-void Ens::ebe32(const float* x, float* y, const int* act)
+// y = A x with the inner operator's arithmetic (FP32, D in FP32 or bfloat16),
+// dashpot included; with nblk the per-member block partials of x . y
+void Ens::ebe32(const float* x, float* y, const int* act, int* nblk)
 {
     const DevMesh dm = mesh->dev();
     set_ebe_block(ebe_block);
+    const double dc = 2.0 / P.dt;
     if (!scatter) {
         float* f = (float*)fbuf.p;
         hipEvent_t t0;
@@ -828,28 +844,32 @@ void Ens::ebe32(const float* x, float* y, const int* act)
                      mat.as<double>(), sc, x, f, act, true);
         tstop(t0, &pc_ebe32, (int64_t)mesh->ne * nm);
         tstart(t0);
-        launch_gather<float>(s, dm, MB, nm, f, nullptr, 0.0f, y, act);
+        double* pd = nblk ? partial.as<double>() : nullptr;
+        launch_gather<float>(s, dm, MB, nm, f, nullptr, 0.0f, y, act, x, pd, nblk);
         tstop(t0, &pc_gather32, (int64_t)mesh->nn * nm);
-    } else {
-        launch_fill32(s, y, 0.0f, (long)ndof * MB);
-        for (int c = 0; c < mesh->ncolor; ++c) {
-            const int e0 = mesh->color_off[c], e1 = mesh->color_off[c + 1];
-            hipEvent_t t0;
-            tstart(t0);
-            launch_ebe32(s, dm, MB, nm, e0, e1, D32.as<float>(), D16.as<uint32_t>(), h.as<double>(), mat.as<double>(),
-                         sc, x, y, act, false);
-            tstop(t0, &pc_ebe32, (int64_t)(e1 - e0) * nm);
-        }
+        launch_dashpot<float>(s, dm, MB, nm, mat.as<double>(), P.nl, (float)dc, x, y, nullptr, act, pd, nblk);
+        return;
     }
-    launch_dashpot<float>(s, dm, MB, nm, mat.as<double>(), P.nl, (float)(2.0 / P.dt), x, y, nullptr, act);
+    launch_fill32(s, y, 0.0f, (long)ndof * MB);
+    for (int c = 0; c < mesh->ncolor; ++c) {
+        const int e0 = mesh->color_off[c], e1 = mesh->color_off[c + 1];
+        hipEvent_t t0;
+        tstart(t0);
+        launch_ebe32(s, dm, MB, nm, e0, e1, D32.as<float>(), D16.as<uint32_t>(), h.as<double>(), mat.as<double>(),
+                     sc, x, y, act, false);
+        tstop(t0, &pc_ebe32, (int64_t)(e1 - e0) * nm);
+    }
+    launch_dashpot<float>(s, dm, MB, nm, mat.as<double>(), P.nl, (float)dc, x, y, nullptr, act);
+    if (nblk)
+        launch_dotsv<float>(s, 1, x, y, nullptr, nullptr, nullptr, nullptr, ndof, MB, nm, act, partial.as<double>(),
+                            nblk);
 }
 
 void Ens::build_rhs()
 {
     // b = f - q + C v + M (a + 4/dt v), f = 2 C_base v_I
-    ebe(OP_RHS, v.as<double>(), a.as<double>(), b.as<double>(), stepping.as<int>(), q.as<double>(), -1.0);
-    launch_dashpot<double>(s, mesh->dev(), MB, nm, mat.as<double>(), P.nl, 1.0, v.as<double>(), b.as<double>(),
-                           vI_cur.as<double>(), stepping.as<int>());
+    ebe(OP_RHS, v.as<double>(), a.as<double>(), b.as<double>(), stepping.as<int>(), q.as<double>(), -1.0, 1.0,
+        vI_cur.as<double>(), nullptr);
 }
 
 void Ens::build_diag()
@@ -885,10 +905,9 @@ void Ens::fin(FinalizeStage st, int nd, int nblk, double tol2, int maxit)
     launch_finalize(s, st, nd, MB, nm, partial.as<double>(), nblk, cs, tol2, maxit);
 }
 
-void Ens::apply_A64(const double* x, double* y, const int* act)
+void Ens::apply_A64(const double* x, double* y, const int* act, int* nblk)
 {
-    ebe(OP_A, x, nullptr, y, act, nullptr, 0.0);
-    launch_dashpot<double>(s, mesh->dev(), MB, nm, mat.as<double>(), P.nl, 2.0 / P.dt, x, y, nullptr, act);
+    ebe(OP_A, x, nullptr, y, act, nullptr, 0.0, 2.0 / P.dt, nullptr, nblk);
 }
 
 // FP64 block-Jacobi PCG (Section 2.2): x0 = previous increment
@@ -944,9 +963,7 @@ void Ens::inner_iter()
     const int* iact = cs.inner_active;
     const double tol2 = P.inner_tol * P.inner_tol;
     double* pd = partial.as<double>();
-    ebe32(ip.as<float>(), iAp.as<float>(), iact);
-    launch_dotsv<float>(s, 1, ip.as<float>(), iAp.as<float>(), nullptr, nullptr, nullptr, nullptr, n, MB, nm, iact, pd,
-                        &nblk);
+    ebe32(ip.as<float>(), iAp.as<float>(), iact, &nblk);
     fin(FIN_IN_ALPHA, 1, nblk, tol2, P.inner_maxit);
     launch_inner_update(s, mesh->nn, MB, nm, iz.as<float>(), ir.as<float>(), iw.as<float>(), ip.as<float>(),
                         iAp.as<float>(), pinv32.as<float>(), cs.ialpha, iact, pd, &nblk);
@@ -963,8 +980,7 @@ void Ens::pcg_iter()
     const int* act = cs.active;
     const double tol2 = P.cg_tol * P.cg_tol;
     double* pd = partial.as<double>();
-    apply_A64(p.as<double>(), Ap.as<double>(), act);
-    dots(1, p.as<double>(), Ap.as<double>(), nullptr, nullptr, nullptr, nullptr, nblk);
+    apply_A64(p.as<double>(), Ap.as<double>(), act, &nblk);
     fin(FIN_ALPHA, 1, nblk, tol2, P.cg_maxit);
     launch_pcg_update(s, mesh->nn, MB, nm, x, r.as<double>(), z.as<double>(), p.as<double>(), Ap.as<double>(),
                       pinv.as<double>(), cs.alpha, act, pd, &nblk);
@@ -1026,8 +1042,7 @@ void Ens::solve_fcg()
     fin(FIN_FCG_RZ, 2, nblk, tol2, P.cg_maxit);
     launch_p_update<double>(s, n, MB, nm, z.as<double>(), p.as<double>(), nullptr, act, nullptr);
     for (;;) {
-        apply_A64(p.as<double>(), Ap.as<double>(), act);
-        dots(1, p.as<double>(), Ap.as<double>(), nullptr, nullptr, nullptr, nullptr, nblk);
+        apply_A64(p.as<double>(), Ap.as<double>(), act, &nblk);
         fin(FIN_ALPHA, 1, nblk, tol2, P.cg_maxit);
         launch_xr_update(s, n, MB, nm, x, r.as<double>(), p.as<double>(), Ap.as<double>(), cs.alpha, act, pd, &nblk);
         fin(FIN_FCG_RR, 1, nblk, tol2, P.cg_maxit);
@@ -1117,7 +1132,8 @@ void Ens::one_step()
     if (P.precision == NLTH_FP64) solve_pcg();
     else solve_fcg();
     tstart(t0);
-    ebe(OP_K, du.as<double>(), nullptr, q.as<double>(), stepping.as<int>(), q.as<double>(), 1.0);
+    ebe(OP_K, du.as<double>(), nullptr, q.as<double>(), stepping.as<int>(), q.as<double>(), 1.0, 0.0, nullptr,
+        nullptr);
     launch_newmark(s, ndof, MB, nm, du.as<double>(), u.as<double>(), v.as<double>(), a.as<double>(), P.dt,
                    stepping.as<int>());
     tstop(t0, &pc_other, 0);
@@ -1384,6 +1400,7 @@ int nlth_ens_set_tuning(nlth_ens* ens, const nlth_tuning* t)
     if (t->inner_maxit < 0 || t->inner_maxit > 100000 || !(t->inner_tol >= 0) || t->inner_tol >= 1)
         throw Error{NLTH_EINVAL, "inner_maxit must be in [0, 100000] and inner_tol in [0, 1)"};
     if (t->scatter < -1 || t->scatter > 1) throw Error{NLTH_EINVAL, "scatter must be -1, 0 or 1"};
+    if (t->scatter == 0 && ens->MB > 256) throw Error{NLTH_EINVAL, "the node gather needs at most 256 member slots"};
     std::lock_guard<std::mutex> g(ens->ctx->mu);
     if (t->ebe_block) ens->ebe_block = t->ebe_block;
     if (t->check_every) ens->check_every = t->check_every;
@@ -1526,10 +1543,8 @@ int nlth_apply_operator(nlth_ctx* ctx, const nlth_mesh* mesh, const nlth_problem
     if (precision == NLTH_FP64) {
         NLTH_HIP(hipMemcpy(e->p.p, x, n * 8, hipMemcpyHostToDevice));
         launch_fill(s, e->Ap.as<double>(), 0.0, n);
-        e->ebe((OpMode)which, e->p.as<double>(), nullptr, e->Ap.as<double>(), e->stepping.as<int>(), nullptr, 0.0);
-        if (which == NLTH_OP_A)
-            launch_dashpot<double>(s, mesh->dev(), 1, 1, e->mat.as<double>(), P.nl, 2.0 / P.dt, e->p.as<double>(),
-                                   e->Ap.as<double>(), nullptr, e->stepping.as<int>());
+        e->ebe((OpMode)which, e->p.as<double>(), nullptr, e->Ap.as<double>(), e->stepping.as<int>(), nullptr, 0.0,
+               which == NLTH_OP_A ? 2.0 / P.dt : 0.0, nullptr, nullptr);
         NLTH_HIP(hipStreamSynchronize(s));
         NLTH_HIP(hipMemcpy(y, e->Ap.p, n * 8, hipMemcpyDeviceToHost));
     } else {

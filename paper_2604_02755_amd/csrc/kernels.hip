@@ -388,52 +388,86 @@ __global__ __launch_bounds__(256) void k_ebe(DevMesh M, int MB, int nm, int e0, 
 }
 
 // y = sum of the element outputs at each node (incidences in ascending
-// order, so the sum is reproducible) + bscale * base (base may be NULL; it may
-// alias y).  One lane per (node, member); members with active[m] == 0 keep y.
-template <typename T>
+// order, so the sum is reproducible) + bscale * base (base may be NULL and may
+// alias y).  With DOT the per-member partial sums of x . y over the block's
+// nodes go to partial[blockIdx * MB + m] (a fixed tree in LDS).  A block
+// covers 256 / MB nodes per pass (MB <= 256) and strides over the nodes;
+// members with active[m] == 0 keep y and add nothing.
+template <typename T, bool DOT>
 __global__ __launch_bounds__(256) void k_gather(DevMesh M, int MB, int nm, const T* __restrict__ f,
-                                               const T* base, T bscale, T* y, const int* __restrict__ active)
+                                               const T* base, T bscale, T* y, const int* __restrict__ active,
+                                               const T* __restrict__ x, double* __restrict__ partial)
 {
-    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    const int m = (int)(t % MB);
-    long node = t / MB;
-    if (MB >= 64) node = __builtin_amdgcn_readfirstlane((int)node);
-    if (node >= M.nn || m >= nm) return;
-    if (active && !active[m]) return;
+    const int t = threadIdx.x, m = t % MB;
+    const int rpb = 256 / MB;
+    const int slot = t / MB;
+    const bool act = m < nm && (!active || active[m]);
     const int EB = MB >= 64 ? 1 : 64 / MB;
-    const uint32_t rs = (uint32_t)(EB * MB);
-    T a0 = 0, a1 = 0, a2 = 0;
-    const int q1 = M.inc_ptr[node + 1];
-    for (int q = M.inc_ptr[node]; q < q1; ++q) {
-        const int ent = M.inc[q];
-        const int e = ent / 10, k = ent - 10 * e;
-        const T* fb = f + f_index(e, 3 * k, MB, EB, m);
-        a0 += fb[0];
-        a1 += fb[rs];
-        a2 += fb[2 * rs];
+    const size_t rs = (size_t)EB * MB;
+    double dot = 0.0;
+    for (long nd = (long)blockIdx.x * rpb + slot; nd < M.nn; nd += (long)gridDim.x * rpb) {
+        const int node = MB >= 64 ? __builtin_amdgcn_readfirstlane((int)nd) : (int)nd;
+        if (!act) continue;
+        T a0 = 0, a1 = 0, a2 = 0;
+        const int q1 = M.inc_ptr[node + 1];
+        for (int q = M.inc_ptr[node]; q < q1; ++q) {
+            const int ent = M.inc[q];
+            const int e = ent / 10, k = ent - 10 * e;
+            const T* fb = f + f_index(e, 3 * k, MB, EB, m);
+            a0 += fb[0];
+            a1 += fb[rs];
+            a2 += fb[2 * rs];
+        }
+        const size_t yi = (size_t)node * 3 * MB + m;
+        if (base) {
+            a0 += bscale * base[yi];
+            a1 += bscale * base[yi + MB];
+            a2 += bscale * base[yi + 2 * MB];
+        }
+        y[yi] = a0;
+        y[yi + MB] = a1;
+        y[yi + 2 * MB] = a2;
+        if (DOT) dot += (double)x[yi] * (double)a0 + (double)x[yi + MB] * (double)a1 + (double)x[yi + 2 * MB] * (double)a2;
     }
-    const size_t yi = (size_t)node * 3 * MB + m;
-    if (base) {
-        a0 += bscale * base[yi];
-        a1 += bscale * base[yi + MB];
-        a2 += bscale * base[yi + 2 * MB];
+    if (DOT) {
+        __shared__ double sh[256];
+        sh[t] = dot;
+        __syncthreads();
+        for (int s = 128; s >= MB; s >>= 1) {
+            if (t < s) sh[t] += sh[t + s];
+            __syncthreads();
+        }
+        if (t < MB) partial[(size_t)blockIdx.x * MB + t] = sh[t];
     }
-    y[yi] = a0;
-    y[yi + MB] = a1;
-    y[yi + 2 * MB] = a2;
+}
+
+// blocks of a gather launch: node passes of 256 / MB nodes, at most maxblk
+static int gather_blocks(int nn, int MB, int maxblk)
+{
+    const long rpb = 256 / MB;
+    const long g = (nn + rpb - 1) / rpb;
+    return (int)(g < 1 ? 1 : (g > maxblk ? maxblk : g));
 }
 
 template <typename T>
 void launch_gather(hipStream_t s, const DevMesh& M, int MB, int nm, const T* f, const T* base, T bscale, T* y,
-                   const int* active)
+                   const int* active, const T* x, double* partial, int* nblk)
 {
-    long n = (long)M.nn * MB;
-    if (n > 0) hipLaunchKernelGGL((k_gather<T>), dim3(nblocks(n)), dim3(256), 0, s, M, MB, nm, f, base, bscale, y, active);
+    if (partial) {
+        const int g = gather_blocks(M.nn, MB, kGatherBlocks);
+        *nblk = g;
+        hipLaunchKernelGGL((k_gather<T, true>), dim3(g), dim3(256), 0, s, M, MB, nm, f, base, bscale, y, active, x,
+                           partial);
+    } else {
+        const int g = gather_blocks(M.nn, MB, 1 << 24);
+        hipLaunchKernelGGL((k_gather<T, false>), dim3(g), dim3(256), 0, s, M, MB, nm, f, base, bscale, y, active,
+                           x, nullptr);
+    }
 }
 template void launch_gather<double>(hipStream_t, const DevMesh&, int, int, const double*, const double*, double,
-                                    double*, const int*);
+                                    double*, const int*, const double*, double*, int*);
 template void launch_gather<float>(hipStream_t, const DevMesh&, int, int, const float*, const float*, float, float*,
-                                   const int*);
+                                   const int*, const float*, double*, int*);
 
 // threads per block of the element-by-element launches (a tuning knob; per
 // host thread so concurrent contexts do not interfere)
@@ -495,18 +529,14 @@ template void launch_ebe<double>(hipStream_t, OpMode, const DevMesh&, int, int, 
 // dashpot on a face: rho (Vp n n^T + Vs (I - n n^T)) times int N_a N_b dA
 // ---------------------------------------------------------------------------
 
+// dashpot force at boundary node i (index into the boundary-node lists) for
+// member m: coef * sum over its faces of rho (Vp n n^T + Vs (I - n n^T)) int N_a N_b dA x_b,
+// plus, with vI, the incident-wave force 2 C_base v_I on base faces
 template <typename T>
-__global__ void k_dashpot(DevMesh M, int MB, int nm, const double* __restrict__ mat, T coef,
-                          const T* __restrict__ x, T* __restrict__ y, const double* __restrict__ vI,
-                          const int* __restrict__ active)
+__device__ __forceinline__ void dashpot_at(const DevMesh& M, int MB, int m, int i, const double* __restrict__ mat,
+                                           double coef, const T* __restrict__ x, const double* __restrict__ vI,
+                                           double acc[3])
 {
-    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    const int m = (int)(t % MB);
-    const long i = t / MB;
-    if (i >= M.nbn || m >= nm) return;
-    if (active && !active[m]) return;
-    const int node = M.bn_node[i];
-    double acc[3] = {0, 0, 0};
     for (int q = M.bn_ptr[i]; q < M.bn_ptr[i + 1]; ++q) {
         const int f = M.bn_face[q], a = M.bn_loc[q];
         const int l = M.f_layer[f];
@@ -522,27 +552,88 @@ __global__ void k_dashpot(DevMesh M, int MB, int nm, const double* __restrict__ 
             for (int c = 0; c < 3; ++c) X[c] += Mab * (double)x[(nb * 3 + c) * MB + m];
         }
         double nx = nv[0] * X[0] + nv[1] * X[1] + nv[2] * X[2];
-        for (int c = 0; c < 3; ++c) acc[c] += (double)coef * rho * (vs * X[c] + (vp - vs) * nx * nv[c]);
+        for (int c = 0; c < 3; ++c) acc[c] += coef * rho * (vs * X[c] + (vp - vs) * nx * nv[c]);
         if (vI && M.f_kind[f] == 0) {  // incident wave: 2 C_base v_I
             double V[3] = {vI[0 * MB + m], vI[1 * MB + m], vI[2 * MB + m]};
             double nV = nv[0] * V[0] + nv[1] * V[1] + nv[2] * V[2];
             for (int c = 0; c < 3; ++c) acc[c] += 2.0 * rs * rho * (vs * V[c] + (vp - vs) * nV * nv[c]);
         }
     }
-    for (int c = 0; c < 3; ++c) y[((long)node * 3 + c) * MB + m] += (T)acc[c];
+}
+
+// y += dashpot at the boundary nodes; with DOT also the per-member partial
+// sums of x . (dashpot x) over the block's nodes, written to
+// partial[(boff + blockIdx) * MB + m] (a fixed tree in LDS).  Lane t of a
+// block takes member t % MB of boundary node (block pass) * (256 / MB) + t / MB
+// when MB <= 256 (a grid-stride loop over the nodes); wider ensembles (no DOT)
+// map one (node, member) pair per thread.
+template <typename T, bool DOT>
+__global__ __launch_bounds__(256) void k_dashpot(DevMesh M, int MB, int nm, const double* __restrict__ mat, double coef,
+                                                const T* __restrict__ x, T* __restrict__ y,
+                                                const double* __restrict__ vI, const int* __restrict__ active,
+                                                double* __restrict__ partial, int boff)
+{
+    const int t = threadIdx.x;
+    int m;
+    long first, stride;
+    if (MB <= 256) {
+        m = t % MB;
+        first = (long)blockIdx.x * (256 / MB) + t / MB;
+        stride = (long)gridDim.x * (256 / MB);
+    } else {
+        const long g = (long)blockIdx.x * 256 + t;
+        m = (int)(g % MB);
+        first = g / MB;
+        stride = M.nbn;  // one pair per thread
+    }
+    const bool act = m < nm && (!active || active[m]);
+    double dot = 0.0;
+    for (long i = first; i < M.nbn; i += stride) {
+        if (!act) continue;
+        const int node = M.bn_node[i];
+        double acc[3] = {0, 0, 0};
+        dashpot_at<T>(M, MB, m, (int)i, mat, coef, x, vI, acc);
+        for (int c = 0; c < 3; ++c) {
+            const size_t yi = ((size_t)node * 3 + c) * MB + m;
+            y[yi] += (T)acc[c];
+            if (DOT) dot += (double)x[yi] * (double)(T)acc[c];
+        }
+    }
+    if (DOT) {
+        __shared__ double sh[256];
+        sh[t] = dot;
+        __syncthreads();
+        for (int s = 128; s >= MB; s >>= 1) {
+            if (t < s) sh[t] += sh[t + s];
+            __syncthreads();
+        }
+        if (t < MB) partial[((size_t)boff + blockIdx.x) * MB + t] = sh[t];
+    }
 }
 
 template <typename T>
 void launch_dashpot(hipStream_t s, const DevMesh& M, int MB, int nm, const double* mat, int, T coef, const T* x,
-                    T* y, const double* vI, const int* active)
+                    T* y, const double* vI, const int* active, double* partial, int* nblk)
 {
-    long n = (long)M.nbn * MB;
-    if (n > 0) hipLaunchKernelGGL((k_dashpot<T>), dim3(nblocks(n)), dim3(256), 0, s, M, MB, nm, mat, coef, x, y, vI, active);
+    if (M.nbn <= 0) return;
+    if (partial && MB <= 256) {
+        // appended to the *nblk partials already written (same layout)
+        const long rpb = 256 / MB;
+        long g = ((long)M.nbn + rpb - 1) / rpb;
+        g = g < kDashpotBlocks ? g : kDashpotBlocks;
+        hipLaunchKernelGGL((k_dashpot<T, true>), dim3(g), dim3(256), 0, s, M, MB, nm, mat, (double)coef, x, y, vI,
+                           active, partial, *nblk);
+        *nblk += (int)g;
+        return;
+    }
+    const long g = MB <= 256 ? ((long)M.nbn + 256 / MB - 1) / (256 / MB) : ((long)M.nbn * MB + 255) / 256;
+    hipLaunchKernelGGL((k_dashpot<T, false>), dim3(g), dim3(256), 0, s, M, MB, nm, mat, (double)coef, x, y, vI,
+                       active, nullptr, 0);
 }
 template void launch_dashpot<double>(hipStream_t, const DevMesh&, int, int, const double*, int, double,
-                                     const double*, double*, const double*, const int*);
+                                     const double*, double*, const double*, const int*, double*, int*);
 template void launch_dashpot<float>(hipStream_t, const DevMesh&, int, int, const double*, int, float,
-                                    const float*, float*, const double*, const int*);
+                                    const float*, float*, const double*, const int*, double*, int*);
 
 // ---------------------------------------------------------------------------
 // 3x3 block-Jacobi preconditioner (Section 2.2): diagonal blocks of A
@@ -689,23 +780,51 @@ void launch_invert_diag(hipStream_t s, int nn, int MB, int nm, const double* dia
 // multi-spring law (Section 2.1): modified Ramberg-Osgood skeleton + Masing
 // ---------------------------------------------------------------------------
 
-// normalised skeleton inverse: s with s (1 + |2s|^beta) = e; Newton from the
-// upper bound min(|e|, (|e| / 2^beta)^(1/(1+beta))) decreases monotonically.
-__device__ __forceinline__ double ro_inverse(double e, double beta)
+// normalised skeleton inverse: s with s (1 + |2s|^beta) = e.  Newton in FP32
+// (hardware log2/exp2) from the upper bound min(|e|, (|e| / 2^beta)^(1/(1+beta))),
+// on which the iteration decreases monotonically, then Newton in FP64 until the
+// step is below 2^-44 |s| (quadratic convergence: the error left is ~ step^2,
+// so the root is exact to rounding; two FP64 steps in the usual case).  *pw
+// receives |2s|^beta at the last FP64 iterate (relative error ~ that step).
+__device__ __forceinline__ float pow2s_f32(float s, float beta)
+{
+    return __builtin_amdgcn_exp2f(beta * __builtin_amdgcn_logf(2.0f * s));
+}
+
+__device__ __forceinline__ double ro_inverse_pw(double e, double beta, double* pw)
 {
     const double a = fabs(e);
-    if (a == 0.0) return 0.0;
-    double s = fmin(a, pow(a / exp2(beta), 1.0 / (1.0 + beta)));
+    if (!(a >= 1e-30)) {  // (2a)^beta < 1e-27: s = a to FP64 precision
+        *pw = a == 0.0 ? 0.0 : pow(2.0 * a, beta);
+        return e;
+    }
+    const float af = (float)a, bf = (float)beta;
+    float sf = fminf(af, __builtin_amdgcn_exp2f((__builtin_amdgcn_logf(af) - bf) / (1.0f + bf)));
+#pragma unroll 1
+    for (int it = 0; it < 12; ++it) {
+        const float p = pow2s_f32(sf, bf);
+        const float f = sf * (1.0f + p) - af;
+        if (f <= 0.0f) break;
+        const float ds = f / (1.0f + (1.0f + bf) * p);
+        sf -= ds;
+        if (ds <= 1e-7f * sf) break;
+    }
+    double s = (double)sf, p = 0.0;
 #pragma unroll 1
     for (int it = 0; it < 60; ++it) {
-        const double p = pow(2.0 * s, beta);
-        const double f = s * (1.0 + p) - a;
-        if (f <= 0.0) break;
-        const double ds = f / (1.0 + (1.0 + beta) * p);
+        p = pow(2.0 * s, beta);
+        const double ds = (s * (1.0 + p) - a) / (1.0 + (1.0 + beta) * p);
         s -= ds;
-        if (ds <= 0x1p-52 * s) break;
+        if (fabs(ds) <= 0x1p-44 * s) break;
     }
+    *pw = p;
     return e < 0 ? -s : s;
+}
+
+__device__ __forceinline__ double ro_inverse(double e, double beta)
+{
+    double pw;
+    return ro_inverse_pw(e, beta, &pw);
 }
 
 struct SpringPar { double G0, gref, hmax, beta; };
@@ -848,9 +967,11 @@ void launch_zero_member(hipStream_t s, double* p, long rows, int MB, int m)
     if (rows > 0) hipLaunchKernelGGL(k_zero_member, dim3(nblocks(rows)), dim3(256), 0, s, p, rows, MB, m);
 }
 
-// One lane per (element, member) of the chunk [e0, e0 + ec): strain
-// increments at the four points from du, then every spring's Masing/RO update
-// and tangent, D = Kb m m^T + sum c_k G_t n n^T, and the element damping h.
+// One lane per (element, point, member) of the chunk [e0, e0 + ec), the four
+// points of an element-member in adjacent lanes: strain increment at the point
+// from du, then every spring's Masing/RO update and tangent,
+// D = Kb m m^T + sum c_k G_t n n^T at the point, and the element damping h
+// (the mean over the four points, summed across the four lanes).
 __global__ __launch_bounds__(256) void k_law(DevMesh M, int MB, int nm, int e0, int ec, long ecp,
                                             const double* __restrict__ mat, const int* __restrict__ nonlinear,
                                             int ns, const double* __restrict__ dirs,
@@ -860,8 +981,10 @@ __global__ __launch_bounds__(256) void k_law(DevMesh M, int MB, int nm, int e0, 
                                             const int* __restrict__ stepping)
 {
     const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    const int m = (int)(t % MB);
-    const long el = t / MB;
+    const int j = (int)(t & 3);
+    const long q = t >> 2;
+    const int m = (int)(q % MB);
+    const long el = q / MB;
     if (el >= ec || m >= nm) return;
     if (stepping && !stepping[m]) return;
     const long e = e0 + el;
@@ -875,8 +998,8 @@ __global__ __launch_bounds__(256) void k_law(DevMesh M, int MB, int nm, int e0, 
     P.hmax = matv(mat, l, MAT_HMAX, MB, m);
     P.beta = matv(mat, l, MAT_BETA, MB, m);
     const double Kb = matv(mat, l, MAT_KB, MB, m);
-    // strain increments at the four points
-    double eps4[4][6];
+    // strain increment at point j
+    double ej[6];
     {
         double gL[4][3];
         for (int k = 0; k < 12; ++k) gL[k / 3][k % 3] = M.geo64[k * ne + e];
@@ -885,80 +1008,98 @@ __global__ __launch_bounds__(256) void k_law(DevMesh M, int MB, int nm, int e0, 
             const long node = M.conn[n * ne + e];
             for (int c = 0; c < 3; ++c) u[n][c] = du[(node * 3 + c) * MB + m];
         }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            double G[10][3];
-            shape_grads<double>(j, gL, G);
-            strain<double>(G, u, eps4[j]);
-        }
+        double G[10][3];
+        shape_grads<double>(j, gL, G);
+        strain<double>(G, u, ej);
     }
     ThetaView th = theta_view(theta, ecp, ns, MB);
     const long fn = th.field_n;
-    double hsum = 0.0;
+    double d[21];
+#pragma unroll
+    for (int k = 0; k < 21; ++k) d[k] = 0;
+    double hs = 0.0;
+    // the next spring's state is loaded while this one is updated
+    long nidx = th.at(el, 0, j, m);
+    double ngp = th.d[nidx], ngr = th.d[fn + nidx], ntr = th.d[2 * fn + nidx], ngm = th.d[3 * fn + nidx];
+    int ndir = th.i[nidx], nskel = th.i[fn + nidx];
 #pragma unroll 1
-    for (int j = 0; j < 4; ++j) {
-        double ej[6];  // select without dynamic register indexing
-#pragma unroll
-        for (int q = 0; q < 6; ++q)
-            ej[q] = j == 0 ? eps4[0][q] : (j == 1 ? eps4[1][q] : (j == 2 ? eps4[2][q] : eps4[3][q]));
-        double d[21];
-#pragma unroll
-        for (int k = 0; k < 21; ++k) d[k] = 0;
-        double hs = 0.0;
-#pragma unroll 1
-        for (int s = 0; s < ns; ++s) {
-            const double* n = dirs + 6 * s;
-            const double dg = n[0] * ej[0] + n[1] * ej[1] + n[2] * ej[2] + n[3] * ej[3] + n[4] * ej[4] + n[5] * ej[5];
-            const long idx = th.at(el, s, j, m);
-            double gp = th.d[idx], gr = th.d[fn + idx], tr = th.d[2 * fn + idx], gm = th.d[3 * fn + idx];
-            int dir = th.i[idx], skel = th.i[fn + idx];
-            if (dg != 0.0) {
-                const int dsg = dg > 0.0 ? 1 : -1;
-                if (dir != 0 && dsg != dir) {  // reversal: a Masing branch starts here
-                    tr = skel ? skeleton_tau(gp, P) : tr + 2.0 * skeleton_tau(0.5 * (gp - gr), P);
-                    gr = gp;
-                    skel = 0;
-                }
-                dir = dsg;
-                const double g = gp + dg;
-                if (!skel && (double)dsg * g >= gm) skel = 1;  // rejoin the skeleton
-                if (skel) gm = fmax(gm, fabs(g));
-                gp = g;
-                th.d[idx] = gp; th.d[fn + idx] = gr; th.d[2 * fn + idx] = tr; th.d[3 * fn + idx] = gm;
-                th.i[idx] = dir; th.i[fn + idx] = skel;
-            }
-            const double xi = skel ? gp : 0.5 * (gp - gr);
-            const double sx = ro_inverse(xi / P.gref, P.beta);
-            const double Gt = P.G0 / (1.0 + (1.0 + P.beta) * pow(fabs(2.0 * sx), P.beta));
-            double hk = 0.0;
-            if (gm > 0.0) {
-                const double em = gm / P.gref;
-                // on the skeleton gm == |gp|, so the inverse above is reused
-                const double sm = (skel && fabs(gp) == gm) ? fabs(sx) : ro_inverse(em, P.beta);
-                hk = P.hmax * (1.0 - sm / em);
-            }
-            hs += hk;
-            const double c = w[s] * Gt;
-#pragma unroll
-            for (int r = 0; r < 6; ++r)
-#pragma unroll
-                for (int q = r; q < 6; ++q) d[sym6(r, q)] += c * n[r] * n[q];
+    for (int sp = 0; sp < ns; ++sp) {
+        const double* n = dirs + 6 * sp;
+        const double dg = n[0] * ej[0] + n[1] * ej[1] + n[2] * ej[2] + n[3] * ej[3] + n[4] * ej[4] + n[5] * ej[5];
+        const long idx = nidx;
+        double gp = ngp, gr = ngr, tr = ntr, gm = ngm;
+        int dir = ndir, skel = nskel;
+        if (sp + 1 < ns) {
+            nidx = th.at(el, sp + 1, j, m);
+            ngp = th.d[nidx]; ngr = th.d[fn + nidx]; ntr = th.d[2 * fn + nidx]; ngm = th.d[3 * fn + nidx];
+            ndir = th.i[nidx]; nskel = th.i[fn + nidx];
         }
+        int rev = 0;           // 1: reversal on the skeleton, 2: reversal on a branch
+        double rev_arg = 0.0;  // strain whose skeleton stress the reversal needs
+        if (dg != 0.0) {
+            const int dsg = dg > 0.0 ? 1 : -1;
+            if (dir != 0 && dsg != dir) {  // reversal: a Masing branch starts here
+                rev = skel ? 1 : 2;
+                rev_arg = skel ? gp : 0.5 * (gp - gr);
+                gr = gp;
+                skel = 0;
+            }
+            dir = dsg;
+            const double g = gp + dg;
+            if (!skel && (double)dsg * g >= gm) skel = 1;  // rejoin the skeleton
+            if (skel) gm = fmax(gm, fabs(g));
+            gp = g;
+        }
+        const double xi = skel ? gp : 0.5 * (gp - gr);
+        // on the skeleton gm == |gp| reuses the inverse at xi for the damping
+        const bool em_own = gm > 0.0 && !(skel && fabs(gp) == gm);
+        // up to three skeleton inversions through one copy of the solver
+        double s_rev = 0.0, s_xi = 0.0, s_em = 0.0, pw = 0.0;
+#pragma unroll 1
+        for (int k = 0; k < 3; ++k) {
+            if (k == 0 ? rev == 0 : (k == 2 && !em_own)) continue;
+            const double arg = k == 0 ? rev_arg : (k == 1 ? xi : gm);
+            double pk;
+            const double sv = ro_inverse_pw(arg / P.gref, P.beta, &pk);
+            if (k == 0) s_rev = sv;
+            else if (k == 1) { s_xi = sv; pw = pk; }
+            else s_em = sv;
+        }
+        if (rev) tr = rev == 1 ? P.G0 * P.gref * s_rev : tr + 2.0 * P.G0 * P.gref * s_rev;
+        if (dg != 0.0) {
+            th.d[idx] = gp; th.d[fn + idx] = gr; th.d[2 * fn + idx] = tr; th.d[3 * fn + idx] = gm;
+            th.i[idx] = dir; th.i[fn + idx] = skel;
+        }
+        const double Gt = P.G0 / (1.0 + (1.0 + P.beta) * pw);
+        double hk = 0.0;
+        if (gm > 0.0) {
+            const double em = gm / P.gref;
+            hk = P.hmax * (1.0 - (em_own ? s_em : fabs(s_xi)) / em);
+        }
+        hs += hk;
+        const double c = w[sp] * Gt;
 #pragma unroll
-        for (int r = 0; r < 3; ++r)
+        for (int r = 0; r < 6; ++r)
 #pragma unroll
-            for (int q = r; q < 3; ++q) d[sym6(r, q)] += Kb;
-        store_D(d, e, j, MB, EB, m, D, D32, D16);
-        hsum += hs / ns;
+            for (int qq = r; qq < 6; ++qq) d[sym6(r, qq)] += c * n[r] * n[qq];
     }
-    h[e * MB + m] = 0.25 * hsum;
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int qq = r; qq < 3; ++qq) d[sym6(r, qq)] += Kb;
+    store_D(d, e, j, MB, EB, m, D, D32, D16);
+    // element damping: mean over the 4 points (adjacent lanes) and the springs
+    double hsum = hs / ns;
+    hsum += __shfl_xor(hsum, 1);
+    hsum += __shfl_xor(hsum, 2);
+    if (j == 0) h[e * MB + m] = 0.25 * hsum;
 }
 
 void launch_law(hipStream_t s, const DevMesh& M, int MB, int nm, int e0, int ec, long ecp, const double* mat, int,
                 const int* nonlinear, int ns, const double* dirs, const double* w, const double* du,
                 void* theta, double* D, float* D32, uint32_t* D16, double* h, const int* stepping)
 {
-    long n = (long)ec * MB;
+    long n = (long)ec * MB * 4;
     if (n > 0)
         hipLaunchKernelGGL(k_law, dim3(nblocks(n)), dim3(256), 0, s, M, MB, nm, e0, ec, ecp, mat, nonlinear, ns, dirs,
                            w, du, theta, D, D32, D16, h, stepping);

@@ -23,7 +23,12 @@ namespace nlth {
 
 enum OpMode { OP_A = 0, OP_K = 1, OP_M = 2, OP_RHS = 3 };
 
-constexpr int kMaxPartialBlocks = 2048;
+constexpr int kMaxPartialBlocks = 2048;   // blocks of a fused vector kernel's partial sums
+constexpr int kGatherBlocks = 16384;      // blocks of a node gather with partial sums
+constexpr int kDashpotBlocks = 1024;      // blocks of a dashpot launch with partial sums
+// length (in MB-rows of doubles) of the partial-sum buffer
+constexpr int kPartialRows = (3 * kMaxPartialBlocks > kGatherBlocks + kDashpotBlocks)
+                                 ? 3 * kMaxPartialBlocks : kGatherBlocks + kDashpotBlocks;
 
 // Per-member material of one layer, member-innermost: mat[(l*MAT_N + field)*MB + m]
 enum MatField { MAT_RHO = 0, MAT_G0, MAT_KB, MAT_VS, MAT_VP, MAT_GREF, MAT_HMAX, MAT_BETA, MAT_N };
@@ -49,6 +54,7 @@ struct DevMesh {
     const int* inc_ptr;   // [nn+1]
     const int* inc;       // [10*ne]
     const int* celem;     // [ne] storage positions grouped by colour
+    const int* bn_of_node;  // [nn] index into bn_node, or -1
 };
 
 struct StepConst {
@@ -68,14 +74,25 @@ template <typename T>
 void launch_ebe(hipStream_t s, OpMode mode, const DevMesh& M, int MB, int nm, int e0, int e1,
                 const T* D, const double* h, const double* mat, int n_layers, StepConst sc,
                 const T* x1, const T* x2, T* y, const int* active, bool out);
-// y = sum over incident elements of the element outputs f (+ bscale * base)
+// y = sum over incident elements of the element outputs f (+ bscale * base);
+// with partial, also the per-member block partials of x . y (*nblk blocks).
+// MB <= 256.
 template <typename T>
 void launch_gather(hipStream_t s, const DevMesh& M, int MB, int nm, const T* f, const T* base, T bscale, T* y,
-                   const int* active);
-// node-centric absorbing-boundary dashpot: y += coef * C_abs x1 (+ 2 C_base vI for RHS)
+                   const int* active, const T* x, double* partial, int* nblk);
+// with partial, also the per-member block partials of x . y (*nblk blocks).
+// MB <= 256.
+template <typename T>
+void launch_gather(hipStream_t s, const DevMesh& M, int MB, int nm, const T* f, const T* base, T bscale, T* y,
+                   const int* active, const double* mat, double dcoef, const T* x, const double* vI,
+                   double* partial, int* nblk);
+// node-centric absorbing-boundary dashpot: y += coef * C_abs x (+ 2 C_base vI for
+// the right-hand side); with partial (MB <= 256), the per-member block partials
+// of x . (C_abs x) are appended after the *nblk already written, *nblk grows
 template <typename T>
 void launch_dashpot(hipStream_t s, const DevMesh& M, int MB, int nm, const double* mat, int n_layers,
-                    T coef, const T* x, T* y, const double* vI, const int* active);
+                    T coef, const T* x, T* y, const double* vI, const int* active, double* partial = nullptr,
+                    int* nblk = nullptr);
 // diagonal 3x3 blocks of A (sym, 6 entries per node) over elements [e0, e1)
 void launch_diag(hipStream_t s, const DevMesh& M, int MB, int nm, int e0, int e1, const double* D,
                  const double* h, const double* mat, int n_layers, StepConst sc, double* diag);

@@ -65,7 +65,7 @@ struct Mesh {
     std::vector<int> recv;
     // device
     DevBuf conn, geo64, geo32, layer, bn_node, bn_ptr, bn_face, bn_loc, f_node, f_M, f_n, f_layer, f_kind, recv_d;
-    DevBuf inc_ptr, inc, celem;
+    DevBuf inc_ptr, inc, celem, bn_of;
     int nbn = 0;
     mutable std::atomic<int> refs{0};  // pending requests using the mesh
     DevMesh dev() const;
@@ -134,8 +134,8 @@ struct Ens {
     void read(nlth_result* res) const;
     // pieces
     void ebe(OpMode mode, const double* x1, const double* x2, double* y, const int* active, const double* base,
-             double bscale);
-    void ebe32(const float* x, float* y, const int* active);
+             double bscale, double dcoef, const double* vI, int* nblk);
+    void ebe32(const float* x, float* y, const int* active, int* nblk = nullptr);
     void build_rhs();
     void build_diag();
     void solve_pcg();
@@ -154,7 +154,7 @@ struct Ens {
     hipGraphExec_t g_inner = nullptr, g_pcg = nullptr;
     int ebe_block = 256;
     void fin(FinalizeStage st, int nd, int nblk, double tol2, int maxit);
-    void apply_A64(const double* x, double* y, const int* act);
+    void apply_A64(const double* x, double* y, const int* act, int* nblk = nullptr);
     int* h_flags = nullptr;             // pinned copy of per-member flags
     hipEvent_t ev();
     void tstart(hipEvent_t& e0);
