@@ -58,20 +58,23 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(src_hash: str):
-    """HBM bytes per FP32-operator launch from the committed rocprofv3 --pmc
-    summary, if it was taken on the current kernel sources (else None)."""
-    p = os.path.join(ROOT, "profiles", "ebe32_traffic_config2.json")
+def traffic_from_profile(src_hash: str, element_members_per_launch: float):
+    """HBM bytes per inner-operator application from the committed rocprofv3
+    --pmc summary (FETCH_SIZE and WRITE_SIZE of the element kernel and the
+    node gather, scaled by the copy calibration), taken per active
+    element-member and applied to this run's launches; None if the summary
+    was taken on other kernel sources."""
+    p = os.path.join(ROOT, "profiles", "inner_operator_traffic_64x64x32.json")
     if not os.path.exists(p):
         return None
     with open(p) as fh:
         d = json.load(fh)
     if d.get("kernel_source_hash") != src_hash:
         return None
-    return d.get("bytes_per_launch")
+    return round(d["bytes_per_element_member"] * element_members_per_launch, 0)
 
 
-def run_gpu(mesh, prob, warmup, steps, profile, tune_steps=0, tuned=None, ctx_kw=None):
+def run_gpu(mesh, prob, warmup, steps, profile, tune_steps=0, tuned=None, ctx_kw=None, fixed=None):
     """Create the ensemble, step ``warmup`` steps, autotune it over the next
     ``tune_steps`` steps (or apply the launch shapes of ``tuned`` and step as
     many), then time ``steps`` steps."""
@@ -82,6 +85,9 @@ def run_gpu(mesh, prob, warmup, steps, profile, tune_steps=0, tuned=None, ctx_kw
         mh = ctx.mesh(mesh)
         ens = ctx.ensemble(mh, mesh, prob)
         choice = None
+        if fixed is not None:
+            ens.set_tuning(fixed["ebe_block"], fixed["check_every"], 1, fixed["inner_maxit"], fixed["inner_tol"])
+            choice = dict(fixed)
         if tuned is not None:
             ens.set_tuning(tuned["ebe_block"], tuned["check_every"], 1)
         ens.step(warmup)  # the first steps carry no wave yet: warm up before tuning
@@ -215,9 +221,11 @@ def bench_paged(args):
     mesh, prob = I.config(3, n_members=args.members, mesh_dims=dims, n_steps=n_total)
     theta_gb = mesh.n_tets * 4 * prob.n_springs * args.members * 40 / 1e9
     log(f"paged ensemble: {args.members} members, law state {theta_gb:.1f} GB, device budget {args.hbm_budget_gb} GB")
+    t0 = time.perf_counter()
     el, _, st, out, _ = run_gpu(mesh, prob, args.warmup, args.steps, False,
                                 ctx_kw=dict(hbm_budget=int(args.hbm_budget_gb * 2**30),
                                             host_budget=int((theta_gb * 1.05 + 8) * 1e9)))
+    log(f"paged: {el / args.steps * 1e3:.0f} ms/step, paged={st['paged']}, total {time.perf_counter() - t0:.0f} s")
     value = args.members * mesh.n_dof * args.steps / el
     line = {
         "metric": METRIC, "value": value, "unit": "DOF-steps/s", "n_gpus": 1, "steps": args.steps,
@@ -266,9 +274,11 @@ def main():
     ap.add_argument("--acc-steps", type=int, default=150)
     ap.add_argument("--no-profile", action="store_true", help="no per-launch event timing")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (defaults)")
+    ap.add_argument("--set-tuning", type=str, default=None,
+                    help="JSON with inner_tol, inner_maxit, ebe_block, check_every: use these, no autotuner")
     ap.add_argument("--config", type=int, default=2, choices=(1, 2, 3, 4),
                     help="2: batched ensemble (default); 1: one large member; 3: paged ensemble; 4: serving")
-    ap.add_argument("--hbm-budget-gb", type=float, default=96.0, help="device budget of --config 3")
+    ap.add_argument("--hbm-budget-gb", type=float, default=0.0, help="device budget of --config 3 (0: 90%% of free)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving sub-run of --config 2")
     ap.add_argument("--serve-rate", type=float, default=4.0)
     ap.add_argument("--serve-window", type=float, default=60.0)
@@ -291,7 +301,8 @@ def main():
     from paper_2604_02755_amd import autotune
     t0 = time.perf_counter()
     mesh, prob = I.config(2, n_members=args.members, mesh_dims=dims)
-    n_tune = 0 if args.no_tune else autotune.trial_steps(prob)
+    fixed = json.loads(args.set_tuning) if args.set_tuning else None
+    n_tune = 0 if (args.no_tune or fixed) else autotune.trial_steps(prob)
     pre = n_tune + args.warmup
     n_total = pre + args.steps
     # the first n_total samples of the 1500-step records (scaled on the full records)
@@ -302,7 +313,8 @@ def main():
     sl = slice(pre, n_total)
 
     # batched mixed precision (the headline), autotuned over the first steps
-    el, st0, st, out_mixed, tuned = run_gpu(mesh, prob, args.warmup, args.steps, not args.no_profile, n_tune)
+    el, st0, st, out_mixed, tuned = run_gpu(mesh, prob, args.warmup, args.steps, not args.no_profile, n_tune,
+                                            fixed=fixed)
     value = args.members * ndof * args.steps / el
     log(f"mixed: {el/args.steps*1e3:.1f} ms/step, {value:.3e} DOF-steps/s, tuning {tuned and {k: tuned[k] for k in ('inner_tol', 'inner_maxit', 'ebe_block', 'check_every')}}")
 
@@ -318,7 +330,7 @@ def main():
         ms = st["ms_ebe32"] + st["ms_gather32"]
         achieved = total_bytes / (ms * 1e-3) / 1e9
         src = kernel_source_hash()
-        tb = traffic_from_profile(src)
+        tb = traffic_from_profile(src, units / n_app)
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4),
                     "traffic": tb,
