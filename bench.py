@@ -334,8 +334,11 @@ def main():
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4),
                     "traffic": tb,
-                    "kernel": "inner operator: nlth::k_ebe<float, 1, 0, true, 1> (element forces, bfloat16 D) "
-                              "+ nlth::k_gather<float> (node sums)",
+                    "kernel": ("inner operator: nlth::k_ebe_cluster<float, 1, 0> (element forces summed per "
+                               "cluster in LDS, bfloat16 D) + nlth::k_gather<float, true, true> (node sums)")
+                              if st["members_padded"] >= 64 else
+                              ("inner operator: nlth::k_ebe<float, 1, 0, false, 1> (element forces, bfloat16 D) "
+                               "+ nlth::k_gather<float, true, false> (node sums)"),
                     "launches": int(n_app), "avg_launch_us": round(ms / n_app * 1e3, 2),
                     "avg_element_kernel_us": round(st["ms_ebe32"] / n_app * 1e3, 2),
                     "avg_gather_kernel_us": round(st["ms_gather32"] / max(1, st["n_gather32"]) * 1e3, 2),

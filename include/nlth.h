@@ -125,6 +125,8 @@ int nlth_mesh_destroy(nlth_mesh* mesh);
 typedef struct {
     int32_t n_nodes, n_tets, n_colors, n_bnodes;
     double volume;
+    int32_t n_clusters;        /* element clusters of the cluster path */
+    int64_t cluster_rows;      /* node rows of all clusters */
 } nlth_mesh_info;
 int nlth_mesh_query(const nlth_mesh* mesh, nlth_mesh_info* info, int32_t* elem_order,
                     int32_t* color_offsets);
@@ -226,12 +228,15 @@ int nlth_ens_stats(const nlth_ens* ens, nlth_stats* st);
  * A field of 0 (or -1 for use_graph) keeps the current value.  The launch
  * shapes do not change results (converged members are frozen on the device);
  * the inner policy changes the iteration path only within the outer FP64
- * tolerance.  scatter picks how element forces reach the nodes: element
- * outputs summed per node in a fixed order (two launches, the default), or
- * one launch per element colour adding into the nodal vector.
+ * tolerance.  scatter picks how element forces reach the nodes (the default
+ * depends on the member slots): per-element outputs summed per node in a
+ * fixed order; clusters of consecutive elements summed in LDS in a fixed
+ * order, then per node; or one launch per element colour adding into the
+ * nodal vector.
  * Out-of-range fields (ebe_block not 0/64/128/256, check_every outside
  * 0..64, inner_maxit outside 0..100000, inner_tol outside [0, 1), scatter
- * outside -1..1) give NLTH_EINVAL and change nothing.  Not to be called while the ensemble
+ * outside -1..2 or not available for this ensemble) give NLTH_EINVAL and
+ * change nothing.  Not to be called while the ensemble
  * is stepping on another thread. */
 typedef struct {
     int32_t ebe_block;
@@ -239,7 +244,9 @@ typedef struct {
     int32_t use_graph;
     int32_t inner_maxit;
     double inner_tol;
-    int32_t scatter;           /* -1 keep; 0 element outputs + node gather; 1 one launch per colour */
+    int32_t scatter;           /* -1 keep; 0 element outputs + node gather (fewer than 64 member
+                                  slots); 1 one launch per colour; 2 element clusters + node gather
+                                  (64..256 slots, a multiple of 64) */
 } nlth_tuning;
 int nlth_ens_set_tuning(nlth_ens* ens, const nlth_tuning* t);
 int nlth_ens_set_profile(nlth_ens* ens, int32_t profile);

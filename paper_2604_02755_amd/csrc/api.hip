@@ -312,6 +312,52 @@ static void build_mesh(Ctx* ctx, const nlth_mesh_desc* d, Mesh& M)
             for (int a = 0; a < 10; ++a) inc[fill[d->tet10[10L * M.order[pos] + a]]++] = pos * 10 + a;
     }
     if (10L * ne > INT32_MAX) throw Error{NLTH_EINVAL, "mesh: more than 214,748,364 tets"};
+    // element clusters: runs of consecutive storage elements, closed when the
+    // next element would bring more than kClusterElems elements or
+    // kClusterNodes distinct nodes; local node lists in first-use order
+    std::vector<int> cl_off(1, 0), cl_noff(1, 0), cl_node;
+    std::vector<uint8_t> cl_lconn(10L * ne);
+    {
+        std::vector<int> loc(nn, -1);
+        std::vector<int> cur;  // the open cluster's nodes
+        int start = 0;
+        auto close = [&](int end) {
+            for (int g : cur) loc[g] = -1;
+            cl_node.insert(cl_node.end(), cur.begin(), cur.end());
+            cl_noff.push_back((int)cl_node.size());
+            cl_off.push_back(end);
+            cur.clear();
+            start = end;
+        };
+        for (int pos = 0; pos < ne; ++pos) {
+            const int* t = d->tet10 + 10L * M.order[pos];
+            int add = 0;
+            for (int a = 0; a < 10; ++a) {
+                bool seen = loc[t[a]] >= 0;
+                for (int b = 0; b < a && !seen; ++b) seen = t[b] == t[a];
+                add += !seen;
+            }
+            if (pos > start && (pos - start >= kClusterElems || (int)cur.size() + add > kClusterNodes)) close(pos);
+            for (int a = 0; a < 10; ++a) {
+                if (loc[t[a]] < 0) {
+                    loc[t[a]] = (int)cur.size();
+                    cur.push_back(t[a]);
+                }
+                cl_lconn[10L * pos + a] = (uint8_t)loc[t[a]];
+            }
+        }
+        close(ne);
+    }
+    M.ncl = (int)cl_off.size() - 1;
+    // node -> cluster rows, ascending
+    std::vector<int> cn_ptr(nn + 1, 0), cn_row(cl_node.size());
+    for (int g : cl_node) cn_ptr[g + 1]++;
+    for (int i = 0; i < nn; ++i) cn_ptr[i + 1] += cn_ptr[i];
+    {
+        std::vector<int> fill(cn_ptr.begin(), cn_ptr.end() - 1);
+        for (int r = 0; r < (int)cl_node.size(); ++r) cn_row[fill[cl_node[r]]++] = r;
+    }
+    M.cl_rows = (long)cl_node.size();
     // sorted SoA arrays
     std::vector<int> conn(10L * ne), lay(ne);
     std::vector<double> g64(13L * ne);
@@ -432,6 +478,11 @@ static void build_mesh(Ctx* ctx, const nlth_mesh_desc* d, Mesh& M)
     upload(b, M.inc, inc);
     upload(b, M.celem, M.color_elems);
     upload(b, M.bn_of, bn_of_node);
+    upload(b, M.cl_off_d, cl_off);
+    upload(b, M.cl_noff_d, cl_noff);
+    upload(b, M.cl_lconn_d, cl_lconn);
+    upload(b, M.cn_ptr_d, cn_ptr);
+    upload(b, M.cn_row_d, cn_row);
 }
 
 DevMesh Mesh::dev() const
@@ -457,6 +508,12 @@ DevMesh Mesh::dev() const
     d.inc = inc.as<int>();
     d.celem = celem.as<int>();
     d.bn_of_node = bn_of.as<int>();
+    d.ncl = ncl;
+    d.cl_off = cl_off_d.as<int>();
+    d.cl_noff = cl_noff_d.as<int>();
+    d.cl_lconn = cl_lconn_d.as<uint8_t>();
+    d.cn_ptr = cn_ptr_d.as<int>();
+    d.cn_row = cn_row_d.as<int>();
     return d;
 }
 
@@ -542,7 +599,8 @@ int64_t ensemble_bytes(const Mesh& m, const Problem& p, int MB, bool paged)
     bytes += (int64_t)m.ne * 4 * 21 * MB * 8;               // D64
     if (p.precision == NLTH_MIXED) bytes += (int64_t)m.ne * 4 * (p.inner_dtype == NLTH_INNER_FP32 ? 84 : 44) * MB;
     bytes += (int64_t)m.ne * MB * 8;                        // h
-    if (MB <= 256) bytes += (int64_t)m.ne * 30 * MB * 8;    // element outputs
+    if (MB >= 64 && MB <= 256) bytes += (int64_t)m.cl_rows * 3 * MB * 8;  // cluster rows
+    else if (MB < 64) bytes += (int64_t)m.ne * 30 * MB * 8;             // element outputs
     bytes += (int64_t)p.n_steps * std::max(1, m.nrecv) * 3 * MB * 8;  // receiver history
     bytes += (int64_t)p.n_steps * 3 * MB * 8 * 2;           // acc, vI
     if (!paged) bytes += (int64_t)m.ne * 4 * p.ns * MB * 40;
@@ -671,10 +729,18 @@ void Ens::create(Ctx* c, const Mesh* m, const Problem& prob, int member_pad)
     if (P.precision == NLTH_MIXED && P.inner_dtype == NLTH_INNER_FP32) D32.alloc(bg, nD * 4);
     if (P.precision == NLTH_MIXED && P.inner_dtype == NLTH_INNER_BF16) D16.alloc(bg, (size_t)ne_pad * 4 * 11 * MB * 4);
     h.alloc(bg, (size_t)m->ne * MB * 8);
-    // element outputs of the gather path; the node gather covers at most 256
-    // member slots per block, wider ensembles take the colour path
-    if (MB <= 256) fbuf.alloc(bg, (size_t)ne_pad * 30 * MB * 8);
-    else scatter = 1;
+    // operator path: element clusters (64-member groups) when MB is a multiple
+    // of 64, element outputs below that, colours above 256 member slots (the
+    // node gather covers at most 256 slots per block)
+    if (MB > 256) {
+        scatter = 1;
+    } else if (MB >= 64) {
+        scatter = 2;
+        cbuf.alloc(bg, (size_t)m->cl_rows * 3 * MB * 8);
+    } else {
+        scatter = 0;
+        fbuf.alloc(bg, (size_t)ne_pad * 30 * MB * 8);
+    }
     const DevMesh dm = m->dev();
     launch_law_init(s, dm, MB, MB, mat.as<double>(), P.nl, P.ns, dirs.as<double>(), w.as<double>(),
                     D64.as<double>(), D32.as<float>(), D16.as<uint32_t>(), h.as<double>());
@@ -803,13 +869,19 @@ void Ens::ebe(OpMode mode, const double* x1, const double* x2, double* y, const 
 {
     const DevMesh dm = mesh->dev();
     set_ebe_block(ebe_block);
-    if (!scatter) {
+    if (scatter != 1) {
         hipEvent_t t0;
         tstart(t0);
-        launch_ebe<double>(s, mode, dm, MB, nm, 0, mesh->ne, D64.as<double>(), h.as<double>(), mat.as<double>(), P.nl,
-                           sc, x1, x2, fbuf.as<double>(), act, true);
         double* pd = nblk ? partial.as<double>() : nullptr;
-        launch_gather<double>(s, dm, MB, nm, fbuf.as<double>(), base, bscale, y, act, x1, pd, nblk);
+        if (scatter == 2) {
+            launch_ebe_cluster64(s, mode, dm, MB, nm, D64.as<double>(), h.as<double>(), mat.as<double>(), sc, x1, x2,
+                                 cbuf.as<double>(), act);
+            launch_gather<double>(s, dm, MB, nm, cbuf.as<double>(), base, bscale, y, act, x1, pd, nblk, true);
+        } else {
+            launch_ebe<double>(s, mode, dm, MB, nm, 0, mesh->ne, D64.as<double>(), h.as<double>(), mat.as<double>(),
+                               P.nl, sc, x1, x2, fbuf.as<double>(), act, true);
+            launch_gather<double>(s, dm, MB, nm, fbuf.as<double>(), base, bscale, y, act, x1, pd, nblk, false);
+        }
         if (dcoef != 0.0) launch_dashpot<double>(s, dm, MB, nm, mat.as<double>(), P.nl, dcoef, x1, y, vI, act, pd, nblk);
         tstop(t0, &pc_ebe64, (int64_t)mesh->ne * nm);
         return;
@@ -836,16 +908,21 @@ void Ens::ebe32(const float* x, float* y, const int* act, int* nblk)
     const DevMesh dm = mesh->dev();
     set_ebe_block(ebe_block);
     const double dc = 2.0 / P.dt;
-    if (!scatter) {
-        float* f = (float*)fbuf.p;
+    if (scatter != 1) {
+        const bool cl = scatter == 2;
+        float* f = cl ? (float*)cbuf.p : (float*)fbuf.p;
         hipEvent_t t0;
         tstart(t0);
-        launch_ebe32(s, dm, MB, nm, 0, mesh->ne, D32.as<float>(), D16.as<uint32_t>(), h.as<double>(),
-                     mat.as<double>(), sc, x, f, act, true);
+        if (cl)
+            launch_ebe_cluster32(s, dm, MB, nm, D32.as<float>(), D16.as<uint32_t>(), h.as<double>(), mat.as<double>(),
+                                 sc, x, f, act);
+        else
+            launch_ebe32(s, dm, MB, nm, 0, mesh->ne, D32.as<float>(), D16.as<uint32_t>(), h.as<double>(),
+                         mat.as<double>(), sc, x, f, act, true);
         tstop(t0, &pc_ebe32, (int64_t)mesh->ne * nm);
         tstart(t0);
         double* pd = nblk ? partial.as<double>() : nullptr;
-        launch_gather<float>(s, dm, MB, nm, f, nullptr, 0.0f, y, act, x, pd, nblk);
+        launch_gather<float>(s, dm, MB, nm, f, nullptr, 0.0f, y, act, x, pd, nblk, cl);
         tstop(t0, &pc_gather32, (int64_t)mesh->nn * nm);
         launch_dashpot<float>(s, dm, MB, nm, mat.as<double>(), P.nl, (float)dc, x, y, nullptr, act, pd, nblk);
         return;
@@ -1320,6 +1397,8 @@ int nlth_mesh_query(const nlth_mesh* mesh, nlth_mesh_info* info, int32_t* elem_o
         info->n_nodes = mesh->nn;
         info->n_tets = mesh->ne;
         info->n_colors = mesh->ncolor;
+        info->n_clusters = mesh->ncl;
+        info->cluster_rows = mesh->cl_rows;
         info->n_bnodes = mesh->nbn;
         info->volume = mesh->volume;
     }
@@ -1399,8 +1478,9 @@ int nlth_ens_set_tuning(nlth_ens* ens, const nlth_tuning* t)
     if (t->check_every < 0 || t->check_every > 64) throw Error{NLTH_EINVAL, "check_every must be in [0, 64]"};
     if (t->inner_maxit < 0 || t->inner_maxit > 100000 || !(t->inner_tol >= 0) || t->inner_tol >= 1)
         throw Error{NLTH_EINVAL, "inner_maxit must be in [0, 100000] and inner_tol in [0, 1)"};
-    if (t->scatter < -1 || t->scatter > 1) throw Error{NLTH_EINVAL, "scatter must be -1, 0 or 1"};
-    if (t->scatter == 0 && ens->MB > 256) throw Error{NLTH_EINVAL, "the node gather needs at most 256 member slots"};
+    if (t->scatter < -1 || t->scatter > 2) throw Error{NLTH_EINVAL, "scatter must be -1, 0, 1 or 2"};
+    if ((t->scatter == 0 && !ens->fbuf.p) || (t->scatter == 2 && !ens->cbuf.p))
+        throw Error{NLTH_EINVAL, "scatter: element outputs need fewer than 64 member slots, clusters 64..256"};
     std::lock_guard<std::mutex> g(ens->ctx->mu);
     if (t->ebe_block) ens->ebe_block = t->ebe_block;
     if (t->check_every) ens->check_every = t->check_every;

@@ -210,22 +210,15 @@ __device__ __forceinline__ size_t f_index(long e, int r, int MB, int EB, int m)
 // node), forces added into y.  OUT = 1: storage positions [e0, e1), forces
 // written to the element-output array y (f_index); the grid is a multiple of
 // 8 blocks and each XCD takes a contiguous range of elements.
-template <typename T, int DK, int MODE, bool WAVE_ELEM, int OUT>
-__global__ __launch_bounds__(256) void k_ebe(DevMesh M, int MB, int nm, int e0, int e1,
-                                            const void* __restrict__ Dv, const double* __restrict__ h,
-                                            const double* __restrict__ mat, StepConst sc,
-                                            const T* __restrict__ x1, const T* __restrict__ x2,
-                                            T* __restrict__ y, const int* __restrict__ active)
+// Forces of one element-member (element e, member m): the 30 nodal values of
+// the operator of MODE applied to x1 (and x2), written to f; nbase[n] is the
+// offset of node n's row in the nodal vectors.
+template <typename T, int DK, int MODE>
+__device__ __forceinline__ void ebe_element(const DevMesh& M, int MB, int m, long e, const void* __restrict__ Dv,
+                                            const double* __restrict__ h, const double* __restrict__ mat,
+                                            const StepConst& sc, const T* __restrict__ x1,
+                                            const T* __restrict__ x2, T f[10][3], size_t nbase[10])
 {
-    long blk = blockIdx.x;
-    if (OUT) blk = (blk % 8) * (gridDim.x / 8) + blk / 8;
-    const long t = blk * blockDim.x + threadIdx.x;
-    const int m = (int)(t % MB);
-    long e = e0 + t / MB;
-    if (WAVE_ELEM) e = __builtin_amdgcn_readfirstlane((int)e);  // one element per wavefront
-    if (e >= e1 || m >= nm) return;
-    if (active && !active[m]) return;
-    if (!OUT) e = WAVE_ELEM ? __builtin_amdgcn_readfirstlane(M.celem[e]) : M.celem[e];
     const int EB = MB >= 64 ? 1 : 64 / MB;
     const long ne = M.ne;
     const T* geo = geo_of<T>(M);
@@ -257,11 +250,9 @@ __global__ __launch_bounds__(256) void k_ebe(DevMesh M, int MB, int nm, int e0, 
     }
     // addresses: a base per node (wave-uniform when a wavefront is one element)
     // plus a 32-bit lane offset, so loads use a scalar base and no 64-bit math
-    size_t nbase[10];
 #pragma unroll
     for (int n = 0; n < 10; ++n) nbase[n] = (size_t)nodes[n] * 3 * MB;
     T xk[10][3];
-    T f[10][3];
     // ---- mass: consistent P2 mass applied through corner/edge sums
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -369,6 +360,28 @@ __global__ __launch_bounds__(256) void k_ebe(DevMesh M, int MB, int nm, int e0, 
             tdot_acc<T>(ST, g, (T)(4.0 * QB_), f[4 + q]);
         }
     }
+}
+
+template <typename T, int DK, int MODE, bool WAVE_ELEM, int OUT>
+__global__ __launch_bounds__(256) void k_ebe(DevMesh M, int MB, int nm, int e0, int e1,
+                                            const void* __restrict__ Dv, const double* __restrict__ h,
+                                            const double* __restrict__ mat, StepConst sc,
+                                            const T* __restrict__ x1, const T* __restrict__ x2,
+                                            T* __restrict__ y, const int* __restrict__ active)
+{
+    long blk = blockIdx.x;
+    if (OUT) blk = (blk % 8) * (gridDim.x / 8) + blk / 8;
+    const long t = blk * blockDim.x + threadIdx.x;
+    const int m = (int)(t % MB);
+    long e = e0 + t / MB;
+    if (WAVE_ELEM) e = __builtin_amdgcn_readfirstlane((int)e);  // one element per wavefront
+    if (e >= e1 || m >= nm) return;
+    if (active && !active[m]) return;
+    if (!OUT) e = WAVE_ELEM ? __builtin_amdgcn_readfirstlane(M.celem[e]) : M.celem[e];
+    const int EB = MB >= 64 ? 1 : 64 / MB;
+    size_t nbase[10];
+    T f[10][3];
+    ebe_element<T, DK, MODE>(M, MB, m, e, Dv, h, mat, sc, x1, x2, f, nbase);
     if (OUT) {
         // row bases are uniform per wavefront when EB == 1; the lane adds m
         T* fb = y + f_index(e, 0, MB, EB, 0);
@@ -387,13 +400,110 @@ __global__ __launch_bounds__(256) void k_ebe(DevMesh M, int MB, int nm, int e0, 
     }
 }
 
+// Cluster form of the operator (members padded to a multiple of 64): a block
+// takes one cluster of consecutive storage elements (at most kClusterNodes
+// distinct nodes) and 64 members; its four wavefronts compute four elements
+// at a time (one element, 64 members per wavefront) and add their forces into
+// the cluster's node rows in LDS, wavefront after wavefront, so the order of
+// the sums is fixed.  The cluster's node rows are then written to
+// co[(row * 3 + c) * MB + m] (row = the cluster's first row + local node) and
+// a gather over the node -> rows lists finishes the sum.
+template <typename T, int DK, int MODE>
+__global__ __launch_bounds__(256) void k_ebe_cluster(DevMesh M, int MB, int nm, int ngroups, int ncl,
+                                                    const void* __restrict__ Dv, const double* __restrict__ h,
+                                                    const double* __restrict__ mat, StepConst sc,
+                                                    const T* __restrict__ x1, const T* __restrict__ x2,
+                                                    T* __restrict__ co, const int* __restrict__ active)
+{
+    __shared__ T ys[kClusterNodes * 3 * 64];
+    const long blk = (blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;  // XCD-contiguous clusters
+    const int c = (int)(blk / ngroups), g = (int)(blk % ngroups);
+    if (c >= ncl) return;  // whole block: padding of the grid to a multiple of 8
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int m = g * 64 + lane;
+    const int e0 = M.cl_off[c], nec = M.cl_off[c + 1] - e0;
+    const int r0 = M.cl_noff[c], ncn = M.cl_noff[c + 1] - r0;
+    for (int i = t; i < ncn * 3 * 64; i += 256) ys[i] = (T)0;
+    const bool act = m < nm && (!active || active[m]);
+    __syncthreads();
+    for (int r = 0; r < nec; r += 4) {
+        const int le = r + w;
+        T f[10][3];
+        int ln[10];
+        if (le < nec && act) {
+            size_t nbase[10];
+            ebe_element<T, DK, MODE>(M, MB, m, e0 + le, Dv, h, mat, sc, x1, x2, f, nbase);
+        } else {
+#pragma unroll
+            for (int n = 0; n < 10; ++n) f[n][0] = f[n][1] = f[n][2] = (T)0;
+        }
+        if (le < nec) {
+#pragma unroll
+            for (int n = 0; n < 10; ++n) ln[n] = M.cl_lconn[(size_t)(e0 + le) * 10 + n];
+        }
+        for (int ww = 0; ww < 4; ++ww) {
+            __syncthreads();
+            if (w == ww && le < nec) {
+#pragma unroll
+                for (int n = 0; n < 10; ++n)
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) ys[(ln[n] * 3 + k) * 64 + lane] += f[n][k];
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = t; i < ncn * 3 * 64; i += 256) {
+        const int q = i >> 6;  // row * 3 + component within the cluster
+        co[((size_t)r0 * 3 + q) * MB + g * 64 + (i & 63)] = ys[i];
+    }
+}
+
+template <typename T, int DK>
+static void cluster_dispatch(hipStream_t s, OpMode mode, const DevMesh& M, int MB, int nm, const void* D,
+                             const double* h, const double* mat, StepConst sc, const T* x1, const T* x2, T* co,
+                             const int* active)
+{
+    const int ngroups = MB / 64;
+    long g = (long)M.ncl * ngroups;
+    g = (g + 7) / 8 * 8;
+    const dim3 grid((unsigned)g), b(256);
+    switch (mode) {
+    case OP_A: hipLaunchKernelGGL((k_ebe_cluster<T, DK, OP_A>), grid, b, 0, s, M, MB, nm, ngroups, M.ncl, D, h, mat, sc, x1, x2, co, active); break;
+    case OP_K: hipLaunchKernelGGL((k_ebe_cluster<T, DK, OP_K>), grid, b, 0, s, M, MB, nm, ngroups, M.ncl, D, h, mat, sc, x1, x2, co, active); break;
+    case OP_M: hipLaunchKernelGGL((k_ebe_cluster<T, DK, OP_M>), grid, b, 0, s, M, MB, nm, ngroups, M.ncl, D, h, mat, sc, x1, x2, co, active); break;
+    case OP_RHS: hipLaunchKernelGGL((k_ebe_cluster<T, DK, OP_RHS>), grid, b, 0, s, M, MB, nm, ngroups, M.ncl, D, h, mat, sc, x1, x2, co, active); break;
+    }
+}
+
+void launch_ebe_cluster64(hipStream_t s, OpMode mode, const DevMesh& M, int MB, int nm, const double* D,
+                          const double* h, const double* mat, StepConst sc, const double* x1, const double* x2,
+                          double* co, const int* active)
+{
+    cluster_dispatch<double, 0>(s, mode, M, MB, nm, D, h, mat, sc, x1, x2, co, active);
+}
+
+void launch_ebe_cluster32(hipStream_t s, const DevMesh& M, int MB, int nm, const float* D32, const uint32_t* D16,
+                          const double* h, const double* mat, StepConst sc, const float* x, float* co,
+                          const int* active)
+{
+    if (D16) {
+        const int ngroups = MB / 64;
+        long g = (long)M.ncl * ngroups;
+        g = (g + 7) / 8 * 8;
+        hipLaunchKernelGGL((k_ebe_cluster<float, 1, OP_A>), dim3((unsigned)g), dim3(256), 0, s, M, MB, nm, ngroups,
+                           M.ncl, (const void*)D16, h, mat, sc, x, (const float*)nullptr, co, active);
+    } else {
+        cluster_dispatch<float, 0>(s, OP_A, M, MB, nm, D32, h, mat, sc, x, nullptr, co, active);
+    }
+}
+
 // y = sum of the element outputs at each node (incidences in ascending
 // order, so the sum is reproducible) + bscale * base (base may be NULL and may
 // alias y).  With DOT the per-member partial sums of x . y over the block's
 // nodes go to partial[blockIdx * MB + m] (a fixed tree in LDS).  A block
 // covers 256 / MB nodes per pass (MB <= 256) and strides over the nodes;
 // members with active[m] == 0 keep y and add nothing.
-template <typename T, bool DOT>
+template <typename T, bool DOT, bool CL>
 __global__ __launch_bounds__(256) void k_gather(DevMesh M, int MB, int nm, const T* __restrict__ f,
                                                const T* base, T bscale, T* y, const int* __restrict__ active,
                                                const T* __restrict__ x, double* __restrict__ partial)
@@ -409,14 +519,24 @@ __global__ __launch_bounds__(256) void k_gather(DevMesh M, int MB, int nm, const
         const int node = MB >= 64 ? __builtin_amdgcn_readfirstlane((int)nd) : (int)nd;
         if (!act) continue;
         T a0 = 0, a1 = 0, a2 = 0;
-        const int q1 = M.inc_ptr[node + 1];
-        for (int q = M.inc_ptr[node]; q < q1; ++q) {
-            const int ent = M.inc[q];
-            const int e = ent / 10, k = ent - 10 * e;
-            const T* fb = f + f_index(e, 3 * k, MB, EB, m);
-            a0 += fb[0];
-            a1 += fb[rs];
-            a2 += fb[2 * rs];
+        if (CL) {  // cluster rows of the node, ascending
+            const int q1 = M.cn_ptr[node + 1];
+            for (int q = M.cn_ptr[node]; q < q1; ++q) {
+                const T* fb = f + (size_t)M.cn_row[q] * 3 * MB + m;
+                a0 += fb[0];
+                a1 += fb[MB];
+                a2 += fb[2 * MB];
+            }
+        } else {  // element outputs of the node, ascending
+            const int q1 = M.inc_ptr[node + 1];
+            for (int q = M.inc_ptr[node]; q < q1; ++q) {
+                const int ent = M.inc[q];
+                const int e = ent / 10, k = ent - 10 * e;
+                const T* fb = f + f_index(e, 3 * k, MB, EB, m);
+                a0 += fb[0];
+                a1 += fb[rs];
+                a2 += fb[2 * rs];
+            }
         }
         const size_t yi = (size_t)node * 3 * MB + m;
         if (base) {
@@ -451,23 +571,31 @@ static int gather_blocks(int nn, int MB, int maxblk)
 
 template <typename T>
 void launch_gather(hipStream_t s, const DevMesh& M, int MB, int nm, const T* f, const T* base, T bscale, T* y,
-                   const int* active, const T* x, double* partial, int* nblk)
+                   const int* active, const T* x, double* partial, int* nblk, bool clusters)
 {
     if (partial) {
         const int g = gather_blocks(M.nn, MB, kGatherBlocks);
         *nblk = g;
-        hipLaunchKernelGGL((k_gather<T, true>), dim3(g), dim3(256), 0, s, M, MB, nm, f, base, bscale, y, active, x,
-                           partial);
+        if (clusters)
+            hipLaunchKernelGGL((k_gather<T, true, true>), dim3(g), dim3(256), 0, s, M, MB, nm, f, base, bscale, y,
+                               active, x, partial);
+        else
+            hipLaunchKernelGGL((k_gather<T, true, false>), dim3(g), dim3(256), 0, s, M, MB, nm, f, base, bscale, y,
+                               active, x, partial);
     } else {
         const int g = gather_blocks(M.nn, MB, 1 << 24);
-        hipLaunchKernelGGL((k_gather<T, false>), dim3(g), dim3(256), 0, s, M, MB, nm, f, base, bscale, y, active,
-                           x, nullptr);
+        if (clusters)
+            hipLaunchKernelGGL((k_gather<T, false, true>), dim3(g), dim3(256), 0, s, M, MB, nm, f, base, bscale, y,
+                               active, x, nullptr);
+        else
+            hipLaunchKernelGGL((k_gather<T, false, false>), dim3(g), dim3(256), 0, s, M, MB, nm, f, base, bscale, y,
+                               active, x, nullptr);
     }
 }
 template void launch_gather<double>(hipStream_t, const DevMesh&, int, int, const double*, const double*, double,
-                                    double*, const int*, const double*, double*, int*);
+                                    double*, const int*, const double*, double*, int*, bool);
 template void launch_gather<float>(hipStream_t, const DevMesh&, int, int, const float*, const float*, float, float*,
-                                   const int*, const float*, double*, int*);
+                                   const int*, const float*, double*, int*, bool);
 
 // threads per block of the element-by-element launches (a tuning knob; per
 // host thread so concurrent contexts do not interfere)

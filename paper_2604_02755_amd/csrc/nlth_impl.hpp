@@ -26,6 +26,8 @@ enum OpMode { OP_A = 0, OP_K = 1, OP_M = 2, OP_RHS = 3 };
 constexpr int kMaxPartialBlocks = 2048;   // blocks of a fused vector kernel's partial sums
 constexpr int kGatherBlocks = 16384;      // blocks of a node gather with partial sums
 constexpr int kDashpotBlocks = 1024;      // blocks of a dashpot launch with partial sums
+constexpr int kClusterNodes = 48;         // most distinct nodes of an element cluster
+constexpr int kClusterElems = 16;         // most elements of an element cluster
 // length (in MB-rows of doubles) of the partial-sum buffer
 constexpr int kPartialRows = (3 * kMaxPartialBlocks > kGatherBlocks + kDashpotBlocks)
                                  ? 3 * kMaxPartialBlocks : kGatherBlocks + kDashpotBlocks;
@@ -55,6 +57,13 @@ struct DevMesh {
     const int* inc;       // [10*ne]
     const int* celem;     // [ne] storage positions grouped by colour
     const int* bn_of_node;  // [nn] index into bn_node, or -1
+    // element clusters: consecutive storage elements with few distinct nodes
+    int ncl;
+    const int* cl_off;      // [ncl+1] storage positions
+    const int* cl_noff;     // [ncl+1] rows of the clusters' node lists
+    const uint8_t* cl_lconn;  // [ne*10] local node of each element node
+    const int* cn_ptr;      // [nn+1] node -> cluster rows
+    const int* cn_row;      // [rows] ascending per node
 };
 
 struct StepConst {
@@ -74,7 +83,19 @@ template <typename T>
 void launch_ebe(hipStream_t s, OpMode mode, const DevMesh& M, int MB, int nm, int e0, int e1,
                 const T* D, const double* h, const double* mat, int n_layers, StepConst sc,
                 const T* x1, const T* x2, T* y, const int* active, bool out);
-// y = sum over incident elements of the element outputs f (+ bscale * base);
+// y = sum over incident elements of the element outputs f, or over the
+// node's cluster rows when clusters is set (+ bscale * base); with partial,
+// also the per-member block partials of x . y (*nblk blocks).  MB <= 256.
+template <typename T>
+void launch_gather(hipStream_t s, const DevMesh& M, int MB, int nm, const T* f, const T* base, T bscale, T* y,
+                   const int* active, const T* x, double* partial, int* nblk, bool clusters);
+// cluster form of the operator (MB a multiple of 64): cluster node rows to co
+void launch_ebe_cluster64(hipStream_t s, OpMode mode, const DevMesh& M, int MB, int nm, const double* D,
+                          const double* h, const double* mat, StepConst sc, const double* x1, const double* x2,
+                          double* co, const int* active);
+void launch_ebe_cluster32(hipStream_t s, const DevMesh& M, int MB, int nm, const float* D32, const uint32_t* D16,
+                          const double* h, const double* mat, StepConst sc, const float* x, float* co,
+                          const int* active);
 // with partial, also the per-member block partials of x . y (*nblk blocks).
 // MB <= 256.
 template <typename T>

@@ -66,6 +66,9 @@ struct Mesh {
     // device
     DevBuf conn, geo64, geo32, layer, bn_node, bn_ptr, bn_face, bn_loc, f_node, f_M, f_n, f_layer, f_kind, recv_d;
     DevBuf inc_ptr, inc, celem, bn_of;
+    DevBuf cl_off_d, cl_noff_d, cl_lconn_d, cn_ptr_d, cn_row_d;
+    int ncl = 0;
+    long cl_rows = 0;  // total rows of the clusters' node lists
     int nbn = 0;
     mutable std::atomic<int> refs{0};  // pending requests using the mesh
     DevMesh dev() const;
@@ -96,7 +99,8 @@ struct Ens {
     DevBuf ir, iz, ip, iw, iAp;
     DevBuf D64, D32, D16, h;             // D16: bfloat16 pairs for the inner operator
     DevBuf fbuf;                        // element outputs of the gather path (FP64 or FP32)
-    int scatter = 0;                    // 0: element outputs + node gather; 1: colour launches
+    DevBuf cbuf;                        // cluster node rows of the cluster path (FP64 or FP32)
+    int scatter = 0;                    // 0: element outputs + gather; 1: colour launches; 2: clusters + gather
     DevBuf theta;                       // resident law state (or the device chunk ring)
     DevBuf theta_host;                  // pinned host state when paged
     DevBuf hist, vmax, iters_dev;

@@ -51,7 +51,8 @@ class nlth_mesh_desc(C.Structure):
 
 class nlth_mesh_info(C.Structure):
     _fields_ = [("n_nodes", C.c_int32), ("n_tets", C.c_int32), ("n_colors", C.c_int32),
-                ("n_bnodes", C.c_int32), ("volume", C.c_double)]
+                ("n_bnodes", C.c_int32), ("volume", C.c_double), ("n_clusters", C.c_int32),
+                ("cluster_rows", C.c_int64)]
 
 
 class nlth_problem(C.Structure):

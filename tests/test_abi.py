@@ -50,6 +50,12 @@ def test_colouring_is_conflict_free(nlth_mod, host_ctx):
         assert abs(info.volume - nx * ny * nz) < 1e-9 * nx * ny * nz
         assert info.n_bnodes > 0
         assert 24 <= info.n_colors <= 64
+        # element clusters: at most 16 elements and 48 distinct nodes each, so
+        # on average fewer than 10 node rows per element
+        assert 0 < info.n_clusters <= mesh.n_tets
+        assert mesh.n_tets / 16 <= info.n_clusters
+        assert info.cluster_rows <= 48 * info.n_clusters
+        assert info.cluster_rows < 10 * mesh.n_tets
         nlth_mod.nlth_mesh_destroy(mh)
 
 

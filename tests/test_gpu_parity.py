@@ -212,3 +212,37 @@ def test_autotuned_run_matches_fp64(gpu_ctx):
         err = np.linalg.norm(om["vel"][m] - o64["vel"][m]) / np.linalg.norm(o64["vel"][m])
         say("  member", m, "autotuned mixed vs fp64", err)
         assert err < 1e-6
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_cluster_path_64_members(gpu_ctx, oracle_lib, precision):
+    """64 member slots take the cluster path (element clusters summed in LDS,
+    then per node): members match the oracle and the colour path."""
+    mesh, prob = _small_problem(precision=precision, n_members=64, n_steps=24, dims=(6, 5, 3), ns=12, tol=1e-12)
+    vs, gr = I.ensemble_members(91, 64, I.CFG0_LAYERS["vs"])
+    prob.vs = vs
+    prob.gamma_ref = np.tile(gr[:, None], (1, 2))
+    prob.input_acc = 5.0 * I.member_waves(2, range(64), prob.n_steps, prob.dt)
+    mh = gpu_ctx.mesh(mesh)
+
+    def run(**kw):
+        ens = gpu_ctx.ensemble(mh, mesh, prob)
+        try:
+            if kw:
+                ens.set_tuning(**kw)
+            ens.step(prob.n_steps)
+            return ens.read()
+        finally:
+            ens.close()
+
+    say("cluster path, 64 members, precision", precision)
+    cl = run()
+    col = run(scatter=1)
+    d = float(np.max(np.abs(cl["vel"] - col["vel"])) / np.max(np.abs(col["vel"])))
+    say("  cluster vs colour max rel diff", d)
+    assert d < 1e-9
+    for m in (0, 37, 63):
+        vref, _ = _oracle_vel(oracle_lib, mesh, prob, m)
+        err = oracle_lib.rel_l2(cl["vel"][m], vref)
+        say("  member", m, "vs oracle", err)
+        assert err < 1e-9
