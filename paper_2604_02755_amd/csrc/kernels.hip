@@ -429,7 +429,6 @@ __global__ __launch_bounds__(256) void k_ebe_cluster(DevMesh M, int MB, int nm, 
     for (int r = 0; r < nec; r += 4) {
         const int le = r + w;
         T f[10][3];
-        int ln[10];
         if (le < nec && act) {
             size_t nbase[10];
             ebe_element<T, DK, MODE>(M, MB, m, e0 + le, Dv, h, mat, sc, x1, x2, f, nbase);
@@ -437,17 +436,17 @@ __global__ __launch_bounds__(256) void k_ebe_cluster(DevMesh M, int MB, int nm, 
 #pragma unroll
             for (int n = 0; n < 10; ++n) f[n][0] = f[n][1] = f[n][2] = (T)0;
         }
-        if (le < nec) {
-#pragma unroll
-            for (int n = 0; n < 10; ++n) ln[n] = M.cl_lconn[(size_t)(e0 + le) * 10 + n];
-        }
         for (int ww = 0; ww < 4; ++ww) {
             __syncthreads();
             if (w == ww && le < nec) {
+                const uint8_t* lc = M.cl_lconn + (size_t)(e0 + le) * 10;
 #pragma unroll
-                for (int n = 0; n < 10; ++n)
-#pragma unroll
-                    for (int k = 0; k < 3; ++k) ys[(ln[n] * 3 + k) * 64 + lane] += f[n][k];
+                for (int n = 0; n < 10; ++n) {
+                    T* yr = ys + (int)lc[n] * 3 * 64 + lane;
+                    yr[0] += f[n][0];
+                    yr[64] += f[n][1];
+                    yr[128] += f[n][2];
+                }
             }
         }
     }
