@@ -86,10 +86,11 @@ def run_gpu(mesh, prob, warmup, steps, profile, tune_steps=0, tuned=None, ctx_kw
         ens = ctx.ensemble(mh, mesh, prob)
         choice = None
         if fixed is not None:
-            ens.set_tuning(fixed["ebe_block"], fixed["check_every"], 1, fixed["inner_maxit"], fixed["inner_tol"])
+            ens.set_tuning(fixed["ebe_block"], fixed["check_every"], 1, fixed["inner_maxit"], fixed["inner_tol"],
+                           cluster_blocks=fixed.get("cluster_blocks", 0))
             choice = dict(fixed)
         if tuned is not None:
-            ens.set_tuning(tuned["ebe_block"], tuned["check_every"], 1)
+            ens.set_tuning(tuned["ebe_block"], tuned["check_every"], 1, cluster_blocks=tuned.get("cluster_blocks", 0))
         ens.step(warmup)  # the first steps carry no wave yet: warm up before tuning
         if tuned is not None:
             ens.step(tune_steps)
@@ -274,6 +275,8 @@ def main():
     ap.add_argument("--acc-steps", type=int, default=150)
     ap.add_argument("--no-profile", action="store_true", help="no per-launch event timing")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (defaults)")
+    ap.add_argument("--inner-dtype", type=int, default=2,
+                    help="storage of the inner operator's D: 0 bfloat16 per point, 1 FP32, 2 bfloat16 element mean")
     ap.add_argument("--set-tuning", type=str, default=None,
                     help="JSON with inner_tol, inner_maxit, ebe_block, check_every: use these, no autotuner")
     ap.add_argument("--config", type=int, default=2, choices=(1, 2, 3, 4),
@@ -301,6 +304,7 @@ def main():
     from paper_2604_02755_amd import autotune
     t0 = time.perf_counter()
     mesh, prob = I.config(2, n_members=args.members, mesh_dims=dims)
+    prob.inner_dtype = args.inner_dtype
     fixed = json.loads(args.set_tuning) if args.set_tuning else None
     n_tune = 0 if (args.no_tune or fixed) else autotune.trial_steps(prob)
     pre = n_tune + args.warmup
@@ -316,7 +320,7 @@ def main():
     el, st0, st, out_mixed, tuned = run_gpu(mesh, prob, args.warmup, args.steps, not args.no_profile, n_tune,
                                             fixed=fixed)
     value = args.members * ndof * args.steps / el
-    log(f"mixed: {el/args.steps*1e3:.1f} ms/step, {value:.3e} DOF-steps/s, tuning {tuned and {k: tuned[k] for k in ('inner_tol', 'inner_maxit', 'ebe_block', 'check_every')}}")
+    log(f"mixed: {el/args.steps*1e3:.1f} ms/step, {value:.3e} DOF-steps/s, tuning {tuned and {k: tuned.get(k) for k in ('inner_tol', 'inner_maxit', 'ebe_block', 'check_every', 'cluster_blocks')}}")
 
     # roofline of the inner FP32 operator over the timed region: the element
     # kernel plus the node gather of its outputs (one application each)
@@ -369,8 +373,10 @@ def main():
                 setattr(pa, f, np.ascontiguousarray(getattr(pa, f)[:na]))
             pa.input_acc = np.ascontiguousarray(pa.input_acc[:, :ns_acc])
             pa.n_members, pa.n_steps = na, ns_acc
-            if tuned and prec == I.PRECISION_MIXED:
-                pa.inner_tol, pa.inner_maxit = tuned["inner_tol"], tuned["inner_maxit"]
+            if prec == I.PRECISION_MIXED:
+                pa.inner_dtype = prob.inner_dtype
+                if tuned:
+                    pa.inner_tol, pa.inner_maxit = tuned["inner_tol"], tuned["inner_maxit"]
             outs.append(run_gpu(mesh, pa, 0, ns_acc, False)[3])
         for m in range(na):
             a, b = outs[0]["vel"][m], outs[1]["vel"][m]
@@ -406,12 +412,14 @@ def main():
         "data": "synthetic (seeded meshes, layer properties and band-limited input waves)",
         "config": {"workload": f"batched ensemble: {args.members} members on a {args.mesh}-cube tet10 mesh, "
                                f"12 springs/point, mixed FP64/FP32 CG, tol 1e-8",
+                   "inner_d_storage": {0: "bfloat16 per point", 1: "FP32 per point",
+                                       2: "bfloat16 element mean"}[args.inner_dtype],
                    "members": args.members, "dof_per_member": ndof, "tets": mesh.n_tets,
                    "parallelism": "members batched in one launch"},
         "iterations": {"outer_per_member_step": float(out_mixed["iters"][:, sl, 0].mean()),
                        "inner_per_member_step": float(out_mixed["iters"][:, sl, 1].mean())},
-        "tuning": ({k: tuned[k] for k in ("inner_tol", "inner_maxit", "ebe_block", "check_every")}
-                   if tuned else None),
+        "tuning": ({k: tuned[k] for k in ("inner_tol", "inner_maxit", "ebe_block", "check_every", "cluster_blocks")
+                    if k in tuned} if tuned else None),
         "timed_steps": f"steps {pre + 1}-{n_total} of the record",
         "phase_ms": {"ebe64": st["ms_ebe64"], "ebe32": st["ms_ebe32"], "gather32": st["ms_gather32"],
                      "law": st["ms_law"], "rhs_diag_q": st["ms_other"]} if not args.no_profile else None,

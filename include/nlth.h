@@ -61,6 +61,7 @@ extern "C" {
  * bytes; the outer FP64 iteration keeps the solution at FP64 tolerance) or FP32 */
 #define NLTH_INNER_BF16 0
 #define NLTH_INNER_FP32 1
+#define NLTH_INNER_BF16_MEAN 2
 
 /* operator selector for nlth_apply_operator */
 #define NLTH_OP_A 0 /* 4/dt^2 M + 2/dt C + K (Eq. 1 left-hand side) */
@@ -170,7 +171,12 @@ typedef struct {
     int32_t precision;         /* NLTH_FP64 or NLTH_MIXED */
     double inner_tol;
     int32_t inner_maxit;
-    int32_t inner_dtype;       /* NLTH_INNER_BF16 (default) or NLTH_INNER_FP32 */
+    int32_t inner_dtype;       /* storage of D for the inner (FP32) operator: NLTH_INNER_BF16
+                                  (default; bfloat16 per point), NLTH_INNER_FP32 (FP32 per
+                                  point) or NLTH_INNER_BF16_MEAN (bfloat16, one D per element:
+                                  the mean over its four points; the preconditioner then
+                                  applies a slightly different operator, which the FP64 outer
+                                  iteration corrects) */
 } nlth_problem;
 
 /* Result buffers (caller-owned host memory; NULL fields are skipped).
@@ -234,7 +240,8 @@ int nlth_ens_stats(const nlth_ens* ens, nlth_stats* st);
  * order, then per node; or one launch per element colour adding into the
  * nodal vector.
  * Out-of-range fields (ebe_block not 0/64/128/256, check_every outside
- * 0..64, inner_maxit outside 0..100000, inner_tol outside [0, 1), scatter
+ * 0..64, inner_maxit outside 0..100000, inner_tol outside [0, 1), cluster_blocks
+ * not 0/2/3/4, scatter
  * outside -1..2 or not available for this ensemble) give NLTH_EINVAL and
  * change nothing.  Not to be called while the ensemble
  * is stepping on another thread. */
@@ -247,6 +254,7 @@ typedef struct {
     int32_t scatter;           /* -1 keep; 0 element outputs + node gather (fewer than 64 member
                                   slots); 1 one launch per colour; 2 element clusters + node gather
                                   (64..256 slots, a multiple of 64) */
+    int32_t cluster_blocks;    /* 0 keep; 2, 3 or 4 co-resident FP32 cluster blocks per CU (default 3) */
 } nlth_tuning;
 int nlth_ens_set_tuning(nlth_ens* ens, const nlth_tuning* t);
 int nlth_ens_set_profile(nlth_ens* ens, int32_t profile);

@@ -5,7 +5,8 @@ coordinate descent:
 1. the inner iteration policy of the mixed path (tolerance-driven, or a fixed
    inner count that keeps every member's lanes busy);
 2. threads per block of the element-by-element launches;
-3. CG iterations per host convergence check (the hipGraph chunk length).
+3. CG iterations per host convergence check (the hipGraph chunk length);
+4. co-resident blocks per CU of the cluster launches (64 and more member slots).
 
 Every trial step is a complete, converged step of the simulation.  Only the
 iteration path inside the outer FP64 tolerance depends on the choice.  The
@@ -20,6 +21,7 @@ import time
 INNER_POLICIES = [(0.1, 50), (0.01, 60), (1e-12, 12), (1e-12, 16), (1e-12, 20)]
 EBE_BLOCKS = [256, 128]
 CHECK_EVERY = [8, 16, 4]
+CLUSTER_BLOCKS = [3, 2, 4]
 
 _cache: dict = {}
 
@@ -29,16 +31,31 @@ def shape_key(mesh, prob, members_padded: int) -> str:
             f"p{prob.precision}-d{getattr(prob, 'inner_dtype', 0)}")
 
 
+def members_padded(n: int) -> int:
+    """Member slots of an ensemble of n members (the library pads to a power
+    of two up to 256, then to a multiple of 256)."""
+    if n <= 1:
+        return 1
+    if n <= 256:
+        p = 1
+        while p < n:
+            p *= 2
+        return p
+    return (n + 255) // 256 * 256
+
+
 def trial_steps(prob, steps_per_trial: int = 1) -> int:
     """Steps an uncached tuning run takes: every candidate of a stage runs
     twice (palindromic order), the incumbent included."""
     n_pol = len(INNER_POLICIES) if prob.precision == 1 else 1
-    stages = [n_pol, len(EBE_BLOCKS), len(CHECK_EVERY)]
+    n_cl = len(CLUSTER_BLOCKS) if 64 <= members_padded(prob.n_members) <= 256 else 1
+    stages = [n_pol, len(EBE_BLOCKS), len(CHECK_EVERY), n_cl]
     return 2 * steps_per_trial * sum(n for n in stages if n > 1)
 
 
 def _apply(ens, c):
-    ens.set_tuning(c["ebe_block"], c["check_every"], 1, c["inner_maxit"], c["inner_tol"])
+    ens.set_tuning(c["ebe_block"], c["check_every"], 1, c["inner_maxit"], c["inner_tol"],
+                   cluster_blocks=c["cluster_blocks"])
 
 
 def tune(ens, mesh, prob, steps_per_trial: int = 1, cache_file: str | None = None, log=None) -> dict:
@@ -77,8 +94,8 @@ def tune(ens, mesh, prob, steps_per_trial: int = 1, cache_file: str | None = Non
         i = min(range(len(cands)), key=ms.__getitem__)
         return cands[i], ms[i]
 
-    cur = dict(ebe_block=EBE_BLOCKS[0], check_every=CHECK_EVERY[0], inner_tol=prob.inner_tol,
-               inner_maxit=prob.inner_maxit)
+    cur = dict(ebe_block=EBE_BLOCKS[0], check_every=CHECK_EVERY[0], cluster_blocks=CLUSTER_BLOCKS[0],
+               inner_tol=prob.inner_tol, inner_maxit=prob.inner_maxit)
     best_ms = None
     if prob.precision == 1:
         cur, best_ms = stage([dict(cur, inner_tol=t, inner_maxit=m) for t, m in INNER_POLICIES])
@@ -86,6 +103,9 @@ def tune(ens, mesh, prob, steps_per_trial: int = 1, cache_file: str | None = Non
     best_ms = ms if ms is not None else best_ms
     cur, ms = stage([dict(cur, check_every=c) for c in CHECK_EVERY])
     best_ms = ms if ms is not None else best_ms
+    if 64 <= st["members_padded"] <= 256:  # the cluster path
+        cur, ms = stage([dict(cur, cluster_blocks=b) for b in CLUSTER_BLOCKS])
+        best_ms = ms if ms is not None else best_ms
     _apply(ens, cur)
     best = dict(cur, ms=best_ms)
     _cache[key] = best

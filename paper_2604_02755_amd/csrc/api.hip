@@ -316,7 +316,7 @@ static void build_mesh(Ctx* ctx, const nlth_mesh_desc* d, Mesh& M)
     // next element would bring more than kClusterElems elements or
     // kClusterNodes distinct nodes; local node lists in first-use order
     std::vector<int> cl_off(1, 0), cl_noff(1, 0), cl_node;
-    std::vector<uint8_t> cl_lconn(10L * ne);
+    std::vector<uint32_t> cl_lconn(4L * ne, 0u);
     {
         std::vector<int> loc(nn, -1);
         std::vector<int> cur;  // the open cluster's nodes
@@ -343,7 +343,7 @@ static void build_mesh(Ctx* ctx, const nlth_mesh_desc* d, Mesh& M)
                     loc[t[a]] = (int)cur.size();
                     cur.push_back(t[a]);
                 }
-                cl_lconn[10L * pos + a] = (uint8_t)loc[t[a]];
+                cl_lconn[4L * pos + a / 4] |= (uint32_t)loc[t[a]] << (8 * (a % 4));
             }
         }
         close(ne);
@@ -511,7 +511,7 @@ DevMesh Mesh::dev() const
     d.ncl = ncl;
     d.cl_off = cl_off_d.as<int>();
     d.cl_noff = cl_noff_d.as<int>();
-    d.cl_lconn = cl_lconn_d.as<uint8_t>();
+    d.cl_lconn = cl_lconn_d.as<uint32_t>();
     d.cn_ptr = cn_ptr_d.as<int>();
     d.cn_row = cn_row_d.as<int>();
     return d;
@@ -570,8 +570,9 @@ void copy_problem(const nlth_problem* in, Problem& P)
     P.precision = in->precision;
     P.inner_tol = in->inner_tol;
     P.inner_maxit = in->inner_maxit;
-    if (in->inner_dtype != NLTH_INNER_BF16 && in->inner_dtype != NLTH_INNER_FP32)
-        throw Error{NLTH_EINVAL, "problem: inner_dtype must be NLTH_INNER_BF16 or NLTH_INNER_FP32"};
+    if (in->inner_dtype != NLTH_INNER_BF16 && in->inner_dtype != NLTH_INNER_FP32 &&
+        in->inner_dtype != NLTH_INNER_BF16_MEAN)
+        throw Error{NLTH_EINVAL, "problem: inner_dtype must be NLTH_INNER_BF16, NLTH_INNER_FP32 or NLTH_INNER_BF16_MEAN"};
     P.inner_dtype = in->inner_dtype;
 }
 
@@ -597,7 +598,9 @@ int64_t ensemble_bytes(const Mesh& m, const Problem& p, int MB, bool paged)
     bytes += 2 * (int64_t)m.nn * 6 * MB * 8 + (int64_t)m.nn * 6 * MB * 4;  // diag, pinv, pinv32
     if (p.precision == NLTH_MIXED) bytes += 5 * ndof * MB * 4;
     bytes += (int64_t)m.ne * 4 * 21 * MB * 8;               // D64
-    if (p.precision == NLTH_MIXED) bytes += (int64_t)m.ne * 4 * (p.inner_dtype == NLTH_INNER_FP32 ? 84 : 44) * MB;
+    if (p.precision == NLTH_MIXED)
+        bytes += (int64_t)m.ne * 4 *
+                 (p.inner_dtype == NLTH_INNER_FP32 ? 84 : (p.inner_dtype == NLTH_INNER_BF16_MEAN ? 11 : 44)) * MB;
     bytes += (int64_t)m.ne * MB * 8;                        // h
     if (MB >= 64 && MB <= 256) bytes += (int64_t)m.cl_rows * 3 * MB * 8;  // cluster rows
     else if (MB < 64) bytes += (int64_t)m.ne * 30 * MB * 8;             // element outputs
@@ -728,6 +731,8 @@ void Ens::create(Ctx* c, const Mesh* m, const Problem& prob, int member_pad)
     D64.alloc(bg, nD * 8);
     if (P.precision == NLTH_MIXED && P.inner_dtype == NLTH_INNER_FP32) D32.alloc(bg, nD * 4);
     if (P.precision == NLTH_MIXED && P.inner_dtype == NLTH_INNER_BF16) D16.alloc(bg, (size_t)ne_pad * 4 * 11 * MB * 4);
+    if (P.precision == NLTH_MIXED && P.inner_dtype == NLTH_INNER_BF16_MEAN) D16.alloc(bg, (size_t)ne_pad * 11 * MB * 4);
+    d16_mean = P.inner_dtype == NLTH_INNER_BF16_MEAN;
     h.alloc(bg, (size_t)m->ne * MB * 8);
     // operator path: element clusters (64-member groups) when MB is a multiple
     // of 64, element outputs below that, colours above 256 member slots (the
@@ -743,7 +748,7 @@ void Ens::create(Ctx* c, const Mesh* m, const Problem& prob, int member_pad)
     }
     const DevMesh dm = m->dev();
     launch_law_init(s, dm, MB, MB, mat.as<double>(), P.nl, P.ns, dirs.as<double>(), w.as<double>(),
-                    D64.as<double>(), D32.as<float>(), D16.as<uint32_t>(), h.as<double>());
+                    D64.as<double>(), D32.as<float>(), D16.as<uint32_t>(), h.as<double>(), -1, d16_mean);
 
     // law state: resident if it fits the remaining budget, else paged
     const size_t per_elem = (size_t)4 * P.ns * MB * 40;
@@ -869,6 +874,7 @@ void Ens::ebe(OpMode mode, const double* x1, const double* x2, double* y, const 
 {
     const DevMesh dm = mesh->dev();
     set_ebe_block(ebe_block);
+    set_cluster_blocks(cluster_blocks);
     if (scatter != 1) {
         hipEvent_t t0;
         tstart(t0);
@@ -907,6 +913,7 @@ void Ens::ebe32(const float* x, float* y, const int* act, int* nblk)
 {
     const DevMesh dm = mesh->dev();
     set_ebe_block(ebe_block);
+    set_cluster_blocks(cluster_blocks);
     const double dc = 2.0 / P.dt;
     if (scatter != 1) {
         const bool cl = scatter == 2;
@@ -915,10 +922,10 @@ void Ens::ebe32(const float* x, float* y, const int* act, int* nblk)
         tstart(t0);
         if (cl)
             launch_ebe_cluster32(s, dm, MB, nm, D32.as<float>(), D16.as<uint32_t>(), h.as<double>(), mat.as<double>(),
-                                 sc, x, f, act);
+                                 sc, x, f, act, d16_mean);
         else
             launch_ebe32(s, dm, MB, nm, 0, mesh->ne, D32.as<float>(), D16.as<uint32_t>(), h.as<double>(),
-                         mat.as<double>(), sc, x, f, act, true);
+                         mat.as<double>(), sc, x, f, act, true, d16_mean);
         tstop(t0, &pc_ebe32, (int64_t)mesh->ne * nm);
         tstart(t0);
         double* pd = nblk ? partial.as<double>() : nullptr;
@@ -933,7 +940,7 @@ void Ens::ebe32(const float* x, float* y, const int* act, int* nblk)
         hipEvent_t t0;
         tstart(t0);
         launch_ebe32(s, dm, MB, nm, e0, e1, D32.as<float>(), D16.as<uint32_t>(), h.as<double>(), mat.as<double>(),
-                     sc, x, y, act, false);
+                     sc, x, y, act, false, d16_mean);
         tstop(t0, &pc_ebe32, (int64_t)(e1 - e0) * nm);
     }
     launch_dashpot<float>(s, dm, MB, nm, mat.as<double>(), P.nl, (float)dc, x, y, nullptr, act);
@@ -1141,7 +1148,7 @@ void Ens::law_phase()
         tstart(t0);
         launch_law(s, dm, MB, nm, 0, mesh->ne, ne_pad, mat.as<double>(), P.nl, nonlinear.as<int>(), P.ns, dirs.as<double>(),
                    w.as<double>(), du.as<double>(), theta.p, D64.as<double>(), D32.as<float>(), D16.as<uint32_t>(), h.as<double>(),
-                   stepping.as<int>());
+                   stepping.as<int>(), d16_mean);
         tstop(t0, &pc_law, (int64_t)mesh->ne * nm);
         return;
     }
@@ -1164,7 +1171,7 @@ void Ens::law_phase()
         tstart(t0);
         launch_law(s, dm, MB, nm, chunk_e0[cix], chunk_ec[cix], chunk_ecp[cix], mat.as<double>(), P.nl, nonlinear.as<int>(), P.ns,
                    dirs.as<double>(), w.as<double>(), du.as<double>(), dslot, D64.as<double>(), D32.as<float>(), D16.as<uint32_t>(),
-                   h.as<double>(), stepping.as<int>());
+                   h.as<double>(), stepping.as<int>(), d16_mean);
         tstop(t0, &pc_law, (int64_t)chunk_ec[cix] * nm);
         NLTH_HIP(hipEventRecord(ev_law[slot], s));
         NLTH_HIP(hipStreamWaitEvent(s_d2h, ev_law[slot], 0));
@@ -1479,6 +1486,8 @@ int nlth_ens_set_tuning(nlth_ens* ens, const nlth_tuning* t)
     if (t->inner_maxit < 0 || t->inner_maxit > 100000 || !(t->inner_tol >= 0) || t->inner_tol >= 1)
         throw Error{NLTH_EINVAL, "inner_maxit must be in [0, 100000] and inner_tol in [0, 1)"};
     if (t->scatter < -1 || t->scatter > 2) throw Error{NLTH_EINVAL, "scatter must be -1, 0, 1 or 2"};
+    if (t->cluster_blocks != 0 && (t->cluster_blocks < 2 || t->cluster_blocks > 4))
+        throw Error{NLTH_EINVAL, "cluster_blocks must be 0, 2, 3 or 4"};
     if ((t->scatter == 0 && !ens->fbuf.p) || (t->scatter == 2 && !ens->cbuf.p))
         throw Error{NLTH_EINVAL, "scatter: element outputs need fewer than 64 member slots, clusters 64..256"};
     std::lock_guard<std::mutex> g(ens->ctx->mu);
@@ -1488,6 +1497,7 @@ int nlth_ens_set_tuning(nlth_ens* ens, const nlth_tuning* t)
     if (t->inner_maxit) ens->P.inner_maxit = t->inner_maxit;
     if (t->inner_tol > 0) ens->P.inner_tol = t->inner_tol;
     if (t->scatter >= 0) ens->scatter = t->scatter;
+    if (t->cluster_blocks > 0) ens->cluster_blocks = t->cluster_blocks;
     // captured chunks hold the old launch shapes
     if (ens->g_inner) (void)hipGraphExecDestroy(ens->g_inner);
     if (ens->g_pcg) (void)hipGraphExecDestroy(ens->g_pcg);
@@ -1604,15 +1614,31 @@ int nlth_apply_operator(nlth_ctx* ctx, const nlth_mesh* mesh, const nlth_problem
             memcpy(&u, &f, 4);
             return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
         };
-        std::vector<uint32_t> Dh((size_t)e->ne_pad * 44, 0u);
-        for (int pos = 0; pos < ne; ++pos)
+        const bool mean = e->d16_mean;  // one D per element: the mean over its points
+        std::vector<uint32_t> Dh((size_t)e->ne_pad * (mean ? 11 : 44), 0u);
+        for (int pos = 0; pos < ne; ++pos) {
+            const size_t base = (size_t)(pos / EB) * 84 * EB + pos % EB;
+            if (mean) {
+                double dmean[21];
+                for (int k = 0; k < 21; ++k) {
+                    dmean[k] = 0.0;
+                    for (int j = 0; j < 4; ++j) dmean[k] += Dd[base + (size_t)(j * 21 + k) * EB];
+                    dmean[k] *= 0.25;
+                }
+                for (int q = 0; q < 11; ++q) {
+                    const uint32_t lo = bf(dmean[2 * q]), hi = (2 * q + 1 < 21) ? bf(dmean[2 * q + 1]) : 0u;
+                    Dh[((size_t)(pos / EB) * 11 + q) * EB + pos % EB] = lo | (hi << 16);
+                }
+                continue;
+            }
             for (int j = 0; j < 4; ++j)
                 for (int q = 0; q < 11; ++q) {
-                    const size_t src = ((size_t)(pos / EB) * 84 + j * 21) * EB + pos % EB;
+                    const size_t src = base + (size_t)(j * 21) * EB;
                     const uint32_t lo = bf(Dd[src + (size_t)(2 * q) * EB]);
                     const uint32_t hi = (2 * q + 1 < 21) ? bf(Dd[src + (size_t)(2 * q + 1) * EB]) : 0u;
                     Dh[((size_t)(pos / EB) * 44 + j * 11 + q) * EB + pos % EB] = lo | (hi << 16);
                 }
+        }
         NLTH_HIP(hipMemcpy(e->D16.p, Dh.data(), Dh.size() * 4, hipMemcpyHostToDevice));
     }
     NLTH_HIP(hipMemcpy(e->h.p, hd.data(), hd.size() * 8, hipMemcpyHostToDevice));

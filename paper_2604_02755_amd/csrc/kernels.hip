@@ -188,6 +188,11 @@ __device__ __forceinline__ long d16_index(long e, int j, int q, int MB, int EB, 
 {
     return (((e / EB) * 44 + j * 11 + q) * EB + e % EB) * (long)MB + m;
 }
+// element-mean D of the inner operator in bfloat16 pairs: 11 words per element
+__device__ __forceinline__ long d16m_index(long e, int q, int MB, int EB, int m)
+{
+    return (((e / EB) * 11 + q) * EB + e % EB) * (long)MB + m;
+}
 __device__ __forceinline__ uint32_t f2bf(double x)
 {
     // round to nearest even on the FP32 bit pattern
@@ -312,6 +317,18 @@ __device__ __forceinline__ void ebe_element(const DevMesh& M, int MB, int m, lon
         }
         const T w = sk * vol * (T)0.25;
         const T c1 = (T)(QA_ - QB_);
+        T dm[22];  // DK 4: one D for the element, read once
+        if constexpr (DK == 4) {
+            const size_t eb = (size_t)(e / EB) * EB, ei = (size_t)(e % EB);
+            const uint32_t rs = (uint32_t)(EB * MB);
+            const uint32_t* D = (const uint32_t*)Dv + (eb * 11 + ei) * MB;
+#pragma unroll
+            for (int q = 0; q < 11; ++q) {
+                const uint32_t wv = __builtin_nontemporal_load(&D[(uint32_t)q * rs + (uint32_t)m]);
+                dm[2 * q] = (T)bf2f(wv & 0xFFFFu);
+                dm[2 * q + 1] = (T)bf2f(wv >> 16);
+            }
+        }
         T ST[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -322,7 +339,10 @@ __device__ __forceinline__ void ebe_element(const DevMesh& M, int MB, int m, lon
             // element base (uniform per wavefront) + 32-bit row offsets
             const size_t eb = (size_t)(e / EB) * EB, ei = (size_t)(e % EB);
             const uint32_t rs = (uint32_t)(EB * MB);  // stride between rows (j, k)
-            if constexpr (DK == 0) {
+            if constexpr (DK == 4) {
+#pragma unroll
+                for (int k = 0; k < 22; ++k) d[k] = dm[k];
+            } else if constexpr (DK == 0) {
                 const T* D = (const T*)Dv + (eb * 84 + ei) * MB;
 #pragma unroll
                 for (int k = 0; k < 21; ++k)
@@ -408,14 +428,26 @@ __global__ __launch_bounds__(256) void k_ebe(DevMesh M, int MB, int nm, int e0, 
 // the sums is fixed.  The cluster's node rows are then written to
 // co[(row * 3 + c) * MB + m] (row = the cluster's first row + local node) and
 // a gather over the node -> rows lists finishes the sum.
-template <typename T, int DK, int MODE>
+// LDS of a cluster block: the node rows, padded so that NB blocks share a CU
+// (160 KB of LDS per CU, allocated in 8 KB steps).  Three FP32 blocks per CU
+// measured fastest: four thrash the L2 that holds the nodal rows shared by
+// neighbouring clusters, two leave too few wavefronts to cover latency.
+template <typename T, int NB>
+constexpr int cluster_lds_elems()
+{
+    constexpr int rows = kClusterNodes * 3 * 64;
+    constexpr int want = (NB == 3 ? 46 * 1024 : (NB == 2 ? 64 * 1024 : 0)) / (int)sizeof(T);
+    return want > rows ? want : rows;
+}
+
+template <typename T, int DK, int MODE, int NB>
 __global__ __launch_bounds__(256) void k_ebe_cluster(DevMesh M, int MB, int nm, int ngroups, int ncl,
                                                     const void* __restrict__ Dv, const double* __restrict__ h,
                                                     const double* __restrict__ mat, StepConst sc,
                                                     const T* __restrict__ x1, const T* __restrict__ x2,
                                                     T* __restrict__ co, const int* __restrict__ active)
 {
-    __shared__ T ys[kClusterNodes * 3 * 64];
+    __shared__ T ys[cluster_lds_elems<T, NB>()];
     const long blk = (blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;  // XCD-contiguous clusters
     const int c = (int)(blk / ngroups), g = (int)(blk % ngroups);
     if (c >= ncl) return;  // whole block: padding of the grid to a multiple of 8
@@ -436,13 +468,20 @@ __global__ __launch_bounds__(256) void k_ebe_cluster(DevMesh M, int MB, int nm, 
 #pragma unroll
             for (int n = 0; n < 10; ++n) f[n][0] = f[n][1] = f[n][2] = (T)0;
         }
+        // local node indices, four per 32-bit word (uniform: scalar loads)
+        uint32_t lw[3] = {0u, 0u, 0u};
+        if (le < nec) {
+            const uint32_t* lp = M.cl_lconn + (size_t)(e0 + le) * 4;
+            lw[0] = lp[0];
+            lw[1] = lp[1];
+            lw[2] = lp[2];
+        }
         for (int ww = 0; ww < 4; ++ww) {
             __syncthreads();
             if (w == ww && le < nec) {
-                const uint8_t* lc = M.cl_lconn + (size_t)(e0 + le) * 10;
 #pragma unroll
                 for (int n = 0; n < 10; ++n) {
-                    T* yr = ys + (int)lc[n] * 3 * 64 + lane;
+                    T* yr = ys + (int)((lw[n / 4] >> (8 * (n % 4))) & 0xFFu) * 3 * 64 + lane;
                     yr[0] += f[n][0];
                     yr[64] += f[n][1];
                     yr[128] += f[n][2];
@@ -457,7 +496,11 @@ __global__ __launch_bounds__(256) void k_ebe_cluster(DevMesh M, int MB, int nm, 
     }
 }
 
-template <typename T, int DK>
+// blocks of the FP32 cluster launches per CU (a tuning knob, per host thread)
+static thread_local int t_cluster_blocks = 3;
+void set_cluster_blocks(int b) { t_cluster_blocks = (b == 2 || b == 3 || b == 4) ? b : 3; }
+
+template <typename T, int DK, int NB>
 static void cluster_dispatch(hipStream_t s, OpMode mode, const DevMesh& M, int MB, int nm, const void* D,
                              const double* h, const double* mat, StepConst sc, const T* x1, const T* x2, T* co,
                              const int* active)
@@ -467,10 +510,27 @@ static void cluster_dispatch(hipStream_t s, OpMode mode, const DevMesh& M, int M
     g = (g + 7) / 8 * 8;
     const dim3 grid((unsigned)g), b(256);
     switch (mode) {
-    case OP_A: hipLaunchKernelGGL((k_ebe_cluster<T, DK, OP_A>), grid, b, 0, s, M, MB, nm, ngroups, M.ncl, D, h, mat, sc, x1, x2, co, active); break;
-    case OP_K: hipLaunchKernelGGL((k_ebe_cluster<T, DK, OP_K>), grid, b, 0, s, M, MB, nm, ngroups, M.ncl, D, h, mat, sc, x1, x2, co, active); break;
-    case OP_M: hipLaunchKernelGGL((k_ebe_cluster<T, DK, OP_M>), grid, b, 0, s, M, MB, nm, ngroups, M.ncl, D, h, mat, sc, x1, x2, co, active); break;
-    case OP_RHS: hipLaunchKernelGGL((k_ebe_cluster<T, DK, OP_RHS>), grid, b, 0, s, M, MB, nm, ngroups, M.ncl, D, h, mat, sc, x1, x2, co, active); break;
+    case OP_A: hipLaunchKernelGGL((k_ebe_cluster<T, DK, OP_A, NB>), grid, b, 0, s, M, MB, nm, ngroups, M.ncl, D, h, mat, sc, x1, x2, co, active); break;
+    case OP_K: hipLaunchKernelGGL((k_ebe_cluster<T, DK, OP_K, NB>), grid, b, 0, s, M, MB, nm, ngroups, M.ncl, D, h, mat, sc, x1, x2, co, active); break;
+    case OP_M: hipLaunchKernelGGL((k_ebe_cluster<T, DK, OP_M, NB>), grid, b, 0, s, M, MB, nm, ngroups, M.ncl, D, h, mat, sc, x1, x2, co, active); break;
+    case OP_RHS: hipLaunchKernelGGL((k_ebe_cluster<T, DK, OP_RHS, NB>), grid, b, 0, s, M, MB, nm, ngroups, M.ncl, D, h, mat, sc, x1, x2, co, active); break;
+    }
+}
+
+// FP32 operator (A) with D storage DK, NB blocks per CU
+template <int DK>
+static void cluster32(hipStream_t s, const DevMesh& M, int MB, int nm, const void* D, const double* h,
+                      const double* mat, StepConst sc, const float* x, float* co, const int* active)
+{
+    const int ngroups = MB / 64;
+    long g = (long)M.ncl * ngroups;
+    g = (g + 7) / 8 * 8;
+    const dim3 grid((unsigned)g), b(256);
+    const float* none = nullptr;
+    switch (t_cluster_blocks) {
+    case 2: hipLaunchKernelGGL((k_ebe_cluster<float, DK, OP_A, 2>), grid, b, 0, s, M, MB, nm, ngroups, M.ncl, D, h, mat, sc, x, none, co, active); break;
+    case 4: hipLaunchKernelGGL((k_ebe_cluster<float, DK, OP_A, 4>), grid, b, 0, s, M, MB, nm, ngroups, M.ncl, D, h, mat, sc, x, none, co, active); break;
+    default: hipLaunchKernelGGL((k_ebe_cluster<float, DK, OP_A, 3>), grid, b, 0, s, M, MB, nm, ngroups, M.ncl, D, h, mat, sc, x, none, co, active); break;
     }
 }
 
@@ -478,22 +538,17 @@ void launch_ebe_cluster64(hipStream_t s, OpMode mode, const DevMesh& M, int MB, 
                           const double* h, const double* mat, StepConst sc, const double* x1, const double* x2,
                           double* co, const int* active)
 {
-    cluster_dispatch<double, 0>(s, mode, M, MB, nm, D, h, mat, sc, x1, x2, co, active);
+    // FP64 rows take 72 KB: two blocks per CU
+    cluster_dispatch<double, 0, 2>(s, mode, M, MB, nm, D, h, mat, sc, x1, x2, co, active);
 }
 
 void launch_ebe_cluster32(hipStream_t s, const DevMesh& M, int MB, int nm, const float* D32, const uint32_t* D16,
                           const double* h, const double* mat, StepConst sc, const float* x, float* co,
-                          const int* active)
+                          const int* active, bool d16_mean)
 {
-    if (D16) {
-        const int ngroups = MB / 64;
-        long g = (long)M.ncl * ngroups;
-        g = (g + 7) / 8 * 8;
-        hipLaunchKernelGGL((k_ebe_cluster<float, 1, OP_A>), dim3((unsigned)g), dim3(256), 0, s, M, MB, nm, ngroups,
-                           M.ncl, (const void*)D16, h, mat, sc, x, (const float*)nullptr, co, active);
-    } else {
-        cluster_dispatch<float, 0>(s, OP_A, M, MB, nm, D32, h, mat, sc, x, nullptr, co, active);
-    }
+    if (D16 && d16_mean) cluster32<4>(s, M, MB, nm, D16, h, mat, sc, x, co, active);
+    else if (D16) cluster32<1>(s, M, MB, nm, D16, h, mat, sc, x, co, active);
+    else cluster32<0>(s, M, MB, nm, D32, h, mat, sc, x, co, active);
 }
 
 // y = sum of the element outputs at each node (incidences in ascending
@@ -627,10 +682,11 @@ static void ebe_dispatch(hipStream_t s, const DevMesh& M, int MB, int nm, int e0
 // inner FP32 operator (Eq. 1 left-hand side) with D stored in FP32 or bfloat16
 void launch_ebe32(hipStream_t s, const DevMesh& M, int MB, int nm, int e0, int e1, const float* D32,
                   const uint32_t* D16, const double* h, const double* mat, StepConst sc, const float* x, float* y,
-                  const int* active, bool out)
+                  const int* active, bool out, bool d16_mean)
 {
     if (e1 <= e0) return;
-    if (D16) ebe_dispatch<float, 1, OP_A>(s, M, MB, nm, e0, e1, D16, h, mat, sc, x, nullptr, y, active, out);
+    if (D16 && d16_mean) ebe_dispatch<float, 4, OP_A>(s, M, MB, nm, e0, e1, D16, h, mat, sc, x, nullptr, y, active, out);
+    else if (D16) ebe_dispatch<float, 1, OP_A>(s, M, MB, nm, e0, e1, D16, h, mat, sc, x, nullptr, y, active, out);
     else ebe_dispatch<float, 0, OP_A>(s, M, MB, nm, e0, e1, D32, h, mat, sc, x, nullptr, y, active, out);
 }
 
@@ -1028,7 +1084,7 @@ __device__ __forceinline__ void store_D(const double d[21], long e, int j, int M
 __global__ void k_law_init(DevMesh M, int MB, int nm, const double* __restrict__ mat, int ns,
                            const double* __restrict__ dirs, const double* __restrict__ w,
                            double* __restrict__ D, float* __restrict__ D32, uint32_t* __restrict__ D16,
-                           double* __restrict__ h, int only_m)
+                           double* __restrict__ h, int only_m, bool d16_mean)
 {
     const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
     const int m = only_m >= 0 ? only_m : (int)(t % MB);
@@ -1047,18 +1103,21 @@ __global__ void k_law_init(DevMesh M, int MB, int nm, const double* __restrict__
     }
     for (int r = 0; r < 3; ++r)
         for (int q = r; q < 3; ++q) d[sym6(r, q)] += Kb;
-    for (int j = 0; j < 4; ++j) store_D(d, e, j, MB, EB, m, D, D32, D16);
+    for (int j = 0; j < 4; ++j) store_D(d, e, j, MB, EB, m, D, D32, d16_mean ? nullptr : D16);
+    if (d16_mean && D16)
+        for (int q = 0; q < 11; ++q)
+            D16[d16m_index(e, q, MB, EB, m)] = f2bf(d[2 * q]) | ((2 * q + 1 < 21 ? f2bf(d[2 * q + 1]) : 0u) << 16);
     h[e * MB + m] = 0.0;
 }
 
 void launch_law_init(hipStream_t s, const DevMesh& M, int MB, int nm, const double* mat, int, int ns,
                      const double* dirs, const double* w, double* D, float* D32, uint32_t* D16, double* h,
-                     int only_m)
+                     int only_m, bool d16_mean)
 {
     long n = only_m >= 0 ? (long)M.ne : (long)M.ne * MB;
     if (n > 0)
         hipLaunchKernelGGL(k_law_init, dim3(nblocks(n)), dim3(256), 0, s, M, MB, nm, mat, ns, dirs, w, D, D32, D16, h,
-                           only_m);
+                           only_m, d16_mean);
 }
 
 // reset the law state of one member (serving: a new request takes the slot)
@@ -1105,7 +1164,7 @@ __global__ __launch_bounds__(256) void k_law(DevMesh M, int MB, int nm, int e0, 
                                             const double* __restrict__ w, const double* __restrict__ du,
                                             void* theta, double* __restrict__ D, float* __restrict__ D32,
                                             uint32_t* __restrict__ D16, double* __restrict__ h,
-                                            const int* __restrict__ stepping)
+                                            const int* __restrict__ stepping, bool d16_mean)
 {
     const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
     const int j = (int)(t & 3);
@@ -1214,7 +1273,19 @@ __global__ __launch_bounds__(256) void k_law(DevMesh M, int MB, int nm, int e0, 
     for (int r = 0; r < 3; ++r)
 #pragma unroll
         for (int qq = r; qq < 3; ++qq) d[sym6(r, qq)] += Kb;
-    store_D(d, e, j, MB, EB, m, D, D32, D16);
+    store_D(d, e, j, MB, EB, m, D, D32, d16_mean ? nullptr : D16);
+    if (d16_mean && D16) {  // element-mean D of the inner operator (the four point lanes)
+#pragma unroll
+        for (int k = 0; k < 21; ++k) {
+            d[k] += __shfl_xor(d[k], 1);
+            d[k] += __shfl_xor(d[k], 2);
+        }
+        if (j == 0)
+#pragma unroll
+            for (int q = 0; q < 11; ++q)
+                D16[d16m_index(e, q, MB, EB, m)] =
+                    f2bf(0.25 * d[2 * q]) | ((2 * q + 1 < 21 ? f2bf(0.25 * d[2 * q + 1]) : 0u) << 16);
+    }
     // element damping: mean over the 4 points (adjacent lanes) and the springs
     double hsum = hs / ns;
     hsum += __shfl_xor(hsum, 1);
@@ -1224,12 +1295,12 @@ __global__ __launch_bounds__(256) void k_law(DevMesh M, int MB, int nm, int e0, 
 
 void launch_law(hipStream_t s, const DevMesh& M, int MB, int nm, int e0, int ec, long ecp, const double* mat, int,
                 const int* nonlinear, int ns, const double* dirs, const double* w, const double* du,
-                void* theta, double* D, float* D32, uint32_t* D16, double* h, const int* stepping)
+                void* theta, double* D, float* D32, uint32_t* D16, double* h, const int* stepping, bool d16_mean)
 {
     long n = (long)ec * MB * 4;
     if (n > 0)
         hipLaunchKernelGGL(k_law, dim3(nblocks(n)), dim3(256), 0, s, M, MB, nm, e0, ec, ecp, mat, nonlinear, ns, dirs,
-                           w, du, theta, D, D32, D16, h, stepping);
+                           w, du, theta, D, D32, D16, h, stepping, d16_mean);
 }
 
 // ---------------------------------------------------------------------------

@@ -61,7 +61,7 @@ struct DevMesh {
     int ncl;
     const int* cl_off;      // [ncl+1] storage positions
     const int* cl_noff;     // [ncl+1] rows of the clusters' node lists
-    const uint8_t* cl_lconn;  // [ne*10] local node of each element node
+    const uint32_t* cl_lconn; // [ne*4] local nodes of each element, four 8-bit indices per word
     const int* cn_ptr;      // [nn+1] node -> cluster rows
     const int* cn_row;      // [rows] ascending per node
 };
@@ -95,7 +95,7 @@ void launch_ebe_cluster64(hipStream_t s, OpMode mode, const DevMesh& M, int MB, 
                           double* co, const int* active);
 void launch_ebe_cluster32(hipStream_t s, const DevMesh& M, int MB, int nm, const float* D32, const uint32_t* D16,
                           const double* h, const double* mat, StepConst sc, const float* x, float* co,
-                          const int* active);
+                          const int* active, bool d16_mean);
 // with partial, also the per-member block partials of x . y (*nblk blocks).
 // MB <= 256.
 template <typename T>
@@ -125,20 +125,22 @@ void launch_invert_diag(hipStream_t s, int nn, int MB, int nm, const double* dia
 // law
 void launch_law_init(hipStream_t s, const DevMesh& M, int MB, int nm, const double* mat, int n_layers,
                      int ns, const double* dirs, const double* w, double* D, float* D32, uint32_t* D16,
-                     double* h, int only_m = -1);
+                     double* h, int only_m = -1, bool d16_mean = false);
 void launch_theta_reset_member(hipStream_t s, void* base, long ecp, int ns, int MB, int m);
 void launch_zero_member(hipStream_t s, double* p, long rows, int MB, int m);
 // threads per block of the element-by-element launches on this host thread
 void set_ebe_block(int bs);
+// blocks per CU of the cluster launches on this host thread
+void set_cluster_blocks(int b);
 // inner FP32 operator (A) with D in FP32 (D32) or bfloat16 pairs (D16, if non-null)
 void launch_ebe32(hipStream_t s, const DevMesh& M, int MB, int nm, int e0, int e1, const float* D32,
                   const uint32_t* D16, const double* h, const double* mat, StepConst sc, const float* x, float* y,
-                  const int* active, bool out);
+                  const int* active, bool out, bool d16_mean);
 void launch_theta_init(hipStream_t s, void* theta_chunk, long ecp, int ns, int MB);
 void launch_law(hipStream_t s, const DevMesh& M, int MB, int nm, int e0, int ec, long ecp, const double* mat,
                 int n_layers, const int* nonlinear, int ns, const double* dirs, const double* w,
                 const double* du, void* theta_chunk, double* D, float* D32, uint32_t* D16, double* h,
-                const int* stepping);
+                const int* stepping, bool d16_mean);
 
 // ---- CG vectors (vec.hip): partial sums go to partial[(k*nblk + blk)*MB + m]
 template <typename T>

@@ -98,6 +98,7 @@ struct Ens {
     DevBuf u, v, a, q, du, b, r, z, p, Ap, diag, pinv, pinv32;
     DevBuf ir, iz, ip, iw, iAp;
     DevBuf D64, D32, D16, h;             // D16: bfloat16 pairs for the inner operator
+    bool d16_mean = false;              // inner D: one bfloat16 D per element (the mean over its points)
     DevBuf fbuf;                        // element outputs of the gather path (FP64 or FP32)
     DevBuf cbuf;                        // cluster node rows of the cluster path (FP64 or FP32)
     int scatter = 0;                    // 0: element outputs + gather; 1: colour launches; 2: clusters + gather
@@ -157,6 +158,7 @@ struct Ens {
     bool use_graph = true;
     hipGraphExec_t g_inner = nullptr, g_pcg = nullptr;
     int ebe_block = 256;
+    int cluster_blocks = 3;             // co-resident cluster blocks per CU
     void fin(FinalizeStage st, int nd, int nblk, double tol2, int maxit);
     void apply_A64(const double* x, double* y, const int* act, int* nblk = nullptr);
     int* h_flags = nullptr;             // pinned copy of per-member flags

@@ -96,7 +96,7 @@ void Ens::reset_member(int m)
     launch_fill(s, vmax.as<double>() + (size_t)m * std::max(1, mesh->nrecv), 0.0, std::max(1, mesh->nrecv));
     launch_theta_reset_member(s, theta.p, ne_pad, P.ns, MB, m);
     launch_law_init(s, dm, MB, nm, mat.as<double>(), P.nl, P.ns, dirs.as<double>(), w.as<double>(), D64.as<double>(),
-                    D32.as<float>(), D16.as<uint32_t>(), h.as<double>(), m);
+                    D32.as<float>(), D16.as<uint32_t>(), h.as<double>(), m, d16_mean);
     int zero = 0;
     NLTH_HIP(hipMemcpyAsync(cs.status + m, &zero, 4, hipMemcpyHostToDevice, s));
     h_status[m] = 0;

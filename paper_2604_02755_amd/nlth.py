@@ -30,7 +30,7 @@ NLTH_ECANCELED = -7
 NLTH_ETIMEDOUT = -8
 NLTH_ENOTFOUND = -9
 NLTH_FP64, NLTH_MIXED = 0, 1
-NLTH_INNER_BF16, NLTH_INNER_FP32 = 0, 1
+NLTH_INNER_BF16, NLTH_INNER_FP32, NLTH_INNER_BF16_MEAN = 0, 1, 2
 NLTH_OP_A, NLTH_OP_K, NLTH_OP_M = 0, 1, 2
 NLTH_DEVICE_NONE = -1
 
@@ -68,7 +68,8 @@ class nlth_problem(C.Structure):
 
 class nlth_tuning(C.Structure):
     _fields_ = [("ebe_block", C.c_int32), ("check_every", C.c_int32), ("use_graph", C.c_int32),
-                ("inner_maxit", C.c_int32), ("inner_tol", C.c_double), ("scatter", C.c_int32)]
+                ("inner_maxit", C.c_int32), ("inner_tol", C.c_double), ("scatter", C.c_int32),
+                ("cluster_blocks", C.c_int32)]
 
 
 class nlth_result(C.Structure):
@@ -307,9 +308,10 @@ class Ensemble:
     def reset_stats(self):
         lib().nlth_ens_reset_stats(self.h)
 
-    def set_tuning(self, ebe_block=0, check_every=0, use_graph=-1, inner_maxit=0, inner_tol=0.0, scatter=-1):
+    def set_tuning(self, ebe_block=0, check_every=0, use_graph=-1, inner_maxit=0, inner_tol=0.0, scatter=-1,
+                   cluster_blocks=0):
         t = nlth_tuning(int(ebe_block), int(check_every), int(use_graph), int(inner_maxit), float(inner_tol),
-                        int(scatter))
+                        int(scatter), int(cluster_blocks))
         return _check(lib().nlth_ens_set_tuning(self.h, C.byref(t)), self.ctx)
 
     def close(self):

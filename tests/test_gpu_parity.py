@@ -58,6 +58,16 @@ def test_operator_parity(gpu_ctx, oracle_lib, dims):
     err = np.linalg.norm(y16 - y_ref) / np.linalg.norm(y_ref)
     say("  op A fp32/bf16-D rel err", err)
     assert err < 4e-3
+    # one bfloat16 D per element, the mean of its four points: the oracle
+    # applied with that mean at every point
+    prob.inner_dtype = 2
+    Dm = np.repeat(D.mean(axis=1, keepdims=True), 4, axis=1)
+    ym_ref = oracle_lib.apply_operator(mesh, prob, 0, Dm, h, x)
+    ym = gpu_ctx.apply_operator(mh, prob, 0, 1, D, h, x)
+    err = np.linalg.norm(ym - ym_ref) / np.linalg.norm(ym_ref)
+    say("  op A fp32/bf16 element-mean D rel err", err)
+    assert err < 4e-3
+    prob.inner_dtype = 0
 
 
 def _small_problem(n_steps=40, precision=0, tol=1e-12, n_members=1, dims=(5, 4, 3), scale=5.0, ns=150):
@@ -105,6 +115,14 @@ def test_mixed_path_parity_small(gpu_ctx, oracle_lib):
     err_or = oracle_lib.rel_l2(o_mixed["vel"][0], vref)
     say("  mixed vs fp64 at 1e-8", err, "vs oracle", err_or)
     assert err < 1e-6 and err_or < 1e-6
+    # inner operator with one D per element: the outer FP64 iteration still
+    # converges to the same solution
+    mesh, pm = _small_problem(precision=1, tol=1e-12)
+    pm.inner_dtype = 2
+    o_mean = gpu_ctx.solve(mh, mesh, pm)
+    err = oracle_lib.rel_l2(o_mean["vel"][0], vref)
+    say("  mixed, element-mean inner D, tol 1e-12, vs oracle", err, "outer/inner", o_mean["iters"][0, 10:14])
+    assert o_mean["rc"] == 0 and err < 1e-9
 
 
 def test_batch_matches_members_alone_and_oracle(gpu_ctx, oracle_lib):
