@@ -40,14 +40,24 @@ def log(*a):
 
 def ebe32_algorithmic_bytes(n_tets: int, n_nodes: int, members_padded: int, inner_dtype: int = 0) -> float:
     """Algorithmic bytes of one inner (FP32) operator application per
-    element-member: D streamed once (4 points x 21 entries, as 11 bfloat16
-    pairs per point = 176 B, or 84 FP32 = 336 B), x read once and y written
-    once per DOF (attributed per element), connectivity + geometry once per
-    element (shared by the members of a wavefront)."""
-    d = 4 * 11 * 4 if inner_dtype == 0 else 4 * 21 * 4
+    element-member: D streamed once (bfloat16 pairs: 11 words per point, 4
+    points = 176 B; FP32: 84 x 4 = 336 B; element-mean bfloat16: 11 words =
+    44 B), x read once and y written once per DOF (attributed per element),
+    connectivity + geometry once per element (shared by the members of a
+    wavefront)."""
+    d = {0: 4 * 11 * 4, 1: 4 * 21 * 4, 2: 11 * 4}[inner_dtype]
     vec = 2 * 4 * 3 * n_nodes / n_tets
     mesh = (10 * 4 + 13 * 4 + 4) / members_padded
     return d + vec + mesh
+
+
+# FP32 arithmetic of one element-member of the operator (an FMA counts 2),
+# counted from the kernel's source: consistent mass through corner/edge sums
+# 3 x 110; strain generators E_k (20 symmetric outer products of 24) and their
+# sums 522; per point (x4) strain 18 + D.eps 72 + scaling and sum 12 + force
+# folding onto 4 corners and 3 edges 147; edge terms of the point sum 144
+EBE32_FLOPS = 3 * 110 + 522 + 4 * (18 + 72 + 12 + 147) + 144
+FP32_PEAK_TFLOPS = 157.3
 
 
 def kernel_source_hash() -> str:
@@ -323,31 +333,38 @@ def main():
     log(f"mixed: {el/args.steps*1e3:.1f} ms/step, {value:.3e} DOF-steps/s, tuning {tuned and {k: tuned.get(k) for k in ('inner_tol', 'inner_maxit', 'ebe_block', 'check_every', 'cluster_blocks')}}")
 
     # roofline of the inner FP32 operator over the timed region: the element
-    # kernel plus the node gather of its outputs (one application each)
+    # kernel plus the node gather of its outputs (one application each).  Its
+    # bound follows from the arithmetic intensity: FP32 ALU when flops per
+    # algorithmic byte exceed the ridge point (157.3 TFLOP/s / 8 TB/s), HBM else.
     inner = out_mixed["iters"][:, sl, 1].astype(np.int64).sum()
     roofline = None
     if st["n_ebe32"] > 0 and st["ms_ebe32"] > 0:
         per_unit = ebe32_algorithmic_bytes(mesh.n_tets, mesh.n_nodes, st["members_padded"], prob.inner_dtype)
         units = int(inner) * mesh.n_tets  # active element-members over all applications
-        total_bytes = per_unit * units
         n_app = st["n_ebe32"]
         ms = st["ms_ebe32"] + st["ms_gather32"]
-        achieved = total_bytes / (ms * 1e-3) / 1e9
+        alu = EBE32_FLOPS / per_unit > FP32_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
+        gbs = per_unit * units / (ms * 1e-3) / 1e9
+        tfl = EBE32_FLOPS * units / (ms * 1e-3) / 1e12
         src = kernel_source_hash()
         tb = traffic_from_profile(src, units / n_app)
-        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4),
+        achieved, peak = (tfl, FP32_PEAK_TFLOPS) if alu else (gbs, HBM_PEAK_GBS)
+        roofline = {"bound": "alu" if alu else "hbm", "achieved": round(achieved, 2), "peak": peak,
+                    "unit": "TFLOP/s" if alu else "GB/s", "frac": round(achieved / peak, 4),
                     "traffic": tb,
-                    "kernel": ("inner operator: nlth::k_ebe_cluster<float, 1, 0> (element forces summed per "
-                               "cluster in LDS, bfloat16 D) + nlth::k_gather<float, true, true> (node sums)")
+                    "kernel": ("inner operator: nlth::k_ebe_cluster<float, %d, 0, 3> (element forces summed per "
+                               "cluster in LDS) + nlth::k_gather<float, true, true> (node sums)"
+                               % {0: 1, 1: 0, 2: 4}[prob.inner_dtype])
                               if st["members_padded"] >= 64 else
-                              ("inner operator: nlth::k_ebe<float, 1, 0, false, 1> (element forces, bfloat16 D) "
+                              ("inner operator: nlth::k_ebe<float, 1, 0, false, 1> (element forces) "
                                "+ nlth::k_gather<float, true, false> (node sums)"),
                     "launches": int(n_app), "avg_launch_us": round(ms / n_app * 1e3, 2),
                     "avg_element_kernel_us": round(st["ms_ebe32"] / n_app * 1e3, 2),
                     "avg_gather_kernel_us": round(st["ms_gather32"] / max(1, st["n_gather32"]) * 1e3, 2),
-                    "algorithmic_bytes_per_launch": round(total_bytes / n_app, 0),
-                    "bytes_per_element_member": round(per_unit, 1)}
+                    "algorithmic_bytes_per_launch": round(per_unit * units / n_app, 0),
+                    "bytes_per_element_member": round(per_unit, 1),
+                    "flops_per_element_member": EBE32_FLOPS,
+                    "hbm_gbs_algorithmic": round(gbs, 1), "fp32_tflops": round(tfl, 2)}
 
     # plain FP64 on the same GPU, same members, same timed steps
     fp64 = None
@@ -398,11 +415,11 @@ def main():
                          f"(FP64 CRS-PCG, tol 1e-8, setup included), {r['seconds']:.1f} s"}
         log(f"cpu oracle: {cpu['value']:.3e} DOF-steps/s on {cores} threads")
 
-    # latency: a short request stream at a rate the GPU sustains, with
-    # records one tenth of the specified length
+    # latency: a short request stream at a rate the GPU sustains (0.4/s of
+    # requests of about 1M DOF), with records one tenth of the specified length
     serving = None
     if not args.no_serve:
-        serving = serve_run(1.0, 20.0, (50, 200), max_batch=args.max_batch)
+        serving = serve_run(0.4, 30.0, (50, 200), max_batch=args.max_batch)
         log(f"serving: p50 {serving['p50_s']:.2f} s, p99 {serving['p99_s']:.2f} s over {serving['requests']} requests")
 
     line = {
