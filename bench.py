@@ -352,9 +352,9 @@ def main():
         roofline = {"bound": "alu" if alu else "hbm", "achieved": round(achieved, 2), "peak": peak,
                     "unit": "TFLOP/s" if alu else "GB/s", "frac": round(achieved / peak, 4),
                     "traffic": tb,
-                    "kernel": ("inner operator: nlth::k_ebe_cluster<float, %d, 0, 3> (element forces summed per "
+                    "kernel": ("inner operator: nlth::k_ebe_cluster<float, %d, 0, %d> (element forces summed per "
                                "cluster in LDS) + nlth::k_gather<float, true, true> (node sums)"
-                               % {0: 1, 1: 0, 2: 4}[prob.inner_dtype])
+                               % ({0: 1, 1: 0, 2: 4}[prob.inner_dtype], (tuned or {}).get("cluster_blocks", 3)))
                               if st["members_padded"] >= 64 else
                               ("inner operator: nlth::k_ebe<float, 1, 0, false, 1> (element forces) "
                                "+ nlth::k_gather<float, true, false> (node sums)"),
