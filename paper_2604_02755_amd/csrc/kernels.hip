@@ -967,18 +967,23 @@ void launch_invert_diag(hipStream_t s, int nn, int MB, int nm, const double* dia
 // (hardware log2/exp2) from the upper bound min(|e|, (|e| / 2^beta)^(1/(1+beta))),
 // on which the iteration decreases monotonically, then Newton in FP64 until the
 // step is below 2^-44 |s| (quadratic convergence: the error left is ~ step^2,
-// so the root is exact to rounding; two FP64 steps in the usual case).  *pw
-// receives |2s|^beta at the last FP64 iterate (relative error ~ that step).
+// so the root is exact to rounding; two FP64 steps in the usual case).  The
+// FP64 power is evaluated once, p0 = (2 s0)^beta at the FP32 root s0, and at
+// the later iterates s = s0 (1 + d) as p0 (1 + d)^beta from its series, which
+// is exact to rounding for |d| < 1e-4 (the FP32 root is good to ~1e-7).
+// *pw receives |2s|^beta at the last FP64 iterate.
 __device__ __forceinline__ float pow2s_f32(float s, float beta)
 {
     return __builtin_amdgcn_exp2f(beta * __builtin_amdgcn_logf(2.0f * s));
 }
 
+__device__ __forceinline__ double pow2s_f64(double s, double beta) { return exp2(beta * log2(2.0 * s)); }
+
 __device__ __forceinline__ double ro_inverse_pw(double e, double beta, double* pw)
 {
     const double a = fabs(e);
     if (!(a >= 1e-30)) {  // (2a)^beta < 1e-27: s = a to FP64 precision
-        *pw = a == 0.0 ? 0.0 : pow(2.0 * a, beta);
+        *pw = a == 0.0 ? 0.0 : pow2s_f64(a, beta);
         return e;
     }
     const float af = (float)a, bf = (float)beta;
@@ -992,12 +997,15 @@ __device__ __forceinline__ double ro_inverse_pw(double e, double beta, double* p
         sf -= ds;
         if (ds <= 1e-7f * sf) break;
     }
-    double s = (double)sf, p = 0.0;
+    const double s0 = (double)sf, p0 = pow2s_f64(s0, beta);
+    const double c1 = beta, c2 = 0.5 * beta * (beta - 1.0), c3 = c2 * (beta - 2.0) / 3.0;
+    double s = s0, p = p0;
 #pragma unroll 1
     for (int it = 0; it < 60; ++it) {
-        p = pow(2.0 * s, beta);
         const double ds = (s * (1.0 + p) - a) / (1.0 + (1.0 + beta) * p);
         s -= ds;
+        const double d = (s - s0) / s0;
+        p = fabs(d) < 1e-4 ? p0 * (1.0 + d * (c1 + d * (c2 + d * c3))) : pow2s_f64(s, beta);
         if (fabs(ds) <= 0x1p-44 * s) break;
     }
     *pw = p;
