@@ -54,9 +54,12 @@ def ebe32_algorithmic_bytes(n_tets: int, n_nodes: int, members_padded: int, inne
 # FP32 arithmetic of one element-member of the operator (an FMA counts 2),
 # counted from the kernel's source: consistent mass through corner/edge sums
 # 3 x 110; strain generators E_k (20 symmetric outer products of 24) and their
-# sums 522; per point (x4) strain 18 + D.eps 72 + scaling and sum 12 + force
-# folding onto 4 corners and 3 edges 147; edge terms of the point sum 144
-EBE32_FLOPS = 3 * 110 + 522 + 4 * (18 + 72 + 12 + 147) + 144
+# sums 522; then, with D per point, per point (x4) strain 18 + D.eps 72 +
+# scaling and sum 12 + force folding onto 4 corners and 3 edges 147, and edge
+# terms of the point sum 144; with one D per element, the closed form: 4 stresses
+# D E_k with their sum 336, corner forces 4 x 30, edge forces 6 x 54
+EBE32_FLOPS_PER_POINT_D = 3 * 110 + 522 + 4 * (18 + 72 + 12 + 147) + 144
+EBE32_FLOPS_ELEMENT_D = 3 * 110 + 522 + 336 + 4 * 30 + 6 * 54
 FP32_PEAK_TFLOPS = 157.3
 
 
@@ -343,9 +346,10 @@ def main():
         units = int(inner) * mesh.n_tets  # active element-members over all applications
         n_app = st["n_ebe32"]
         ms = st["ms_ebe32"] + st["ms_gather32"]
-        alu = EBE32_FLOPS / per_unit > FP32_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
+        flops = EBE32_FLOPS_ELEMENT_D if prob.inner_dtype == 2 else EBE32_FLOPS_PER_POINT_D
+        alu = flops / per_unit > FP32_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
         gbs = per_unit * units / (ms * 1e-3) / 1e9
-        tfl = EBE32_FLOPS * units / (ms * 1e-3) / 1e12
+        tfl = flops * units / (ms * 1e-3) / 1e12
         src = kernel_source_hash()
         tb = traffic_from_profile(src, units / n_app)
         achieved, peak = (tfl, FP32_PEAK_TFLOPS) if alu else (gbs, HBM_PEAK_GBS)
@@ -363,7 +367,7 @@ def main():
                     "avg_gather_kernel_us": round(st["ms_gather32"] / max(1, st["n_gather32"]) * 1e3, 2),
                     "algorithmic_bytes_per_launch": round(per_unit * units / n_app, 0),
                     "bytes_per_element_member": round(per_unit, 1),
-                    "flops_per_element_member": EBE32_FLOPS,
+                    "flops_per_element_member": flops,
                     "hbm_gbs_algorithmic": round(gbs, 1), "fp32_tflops": round(tfl, 2)}
 
     # plain FP64 on the same GPU, same members, same timed steps

@@ -294,27 +294,30 @@ __device__ __forceinline__ void ebe_element(const DevMesh& M, int MB, int m, lon
     // ---- stiffness (Eq. 2)
     if (MODE != OP_M && sk != (T)0) {
         constexpr int E[6][2] = {{0, 1}, {1, 2}, {2, 0}, {0, 3}, {1, 3}, {2, 3}};
-        // E_k = voigt(G_k), G_k = 4 x_k gL_k^T - H + 4 sum_{edges (k,o)} x_ko gL_o^T
-        T Ek[4][6], H[6] = {0, 0, 0, 0, 0, 0};
+        // E_k = voigt(G_k), G_k = 4 x_k gL_k^T - H + 4 sum_{edges (k,o)} x_ko gL_o^T,
+        // H = sum_k x_k gL_k^T: the corner products P_k are formed once
+        T Ek[4][6], H[6];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
 #pragma unroll
             for (int q = 0; q < 6; ++q) Ek[k][q] = 0;
-            vsym_acc<T>(xk[k], gL[k], (T)1, H);
-            vsym_acc<T>(xk[k], gL[k], (T)4, Ek[k]);
+            vsym_acc<T>(xk[k], gL[k], (T)1, Ek[k]);
         }
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
-            vsym_acc<T>(xk[4 + q], gL[E[q][1]], (T)4, Ek[E[q][0]]);
-            vsym_acc<T>(xk[4 + q], gL[E[q][0]], (T)4, Ek[E[q][1]]);
+            H[q] = Ek[0][q] + Ek[1][q] + Ek[2][q] + Ek[3][q];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) Ek[k][q] = (T)4 * Ek[k][q] - H[q];
+        }
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            const T u4[3] = {(T)4 * xk[4 + q][0], (T)4 * xk[4 + q][1], (T)4 * xk[4 + q][2]};
+            vsym_acc<T>(u4, gL[E[q][1]], (T)1, Ek[E[q][0]]);
+            vsym_acc<T>(u4, gL[E[q][0]], (T)1, Ek[E[q][1]]);
         }
         T S[6];
 #pragma unroll
-        for (int q = 0; q < 6; ++q) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) Ek[k][q] -= H[q];
-            S[q] = Ek[0][q] + Ek[1][q] + Ek[2][q] + Ek[3][q];
-        }
+        for (int q = 0; q < 6; ++q) S[q] = Ek[0][q] + Ek[1][q] + Ek[2][q] + Ek[3][q];
         const T w = sk * vol * (T)0.25;
         const T c1 = (T)(QA_ - QB_);
         T dm[22];  // DK 4: one D for the element, read once
@@ -328,6 +331,47 @@ __device__ __forceinline__ void ebe_element(const DevMesh& M, int MB, int m, lon
                 dm[2 * q] = (T)bf2f(wv & 0xFFFFu);
                 dm[2 * q + 1] = (T)bf2f(wv >> 16);
             }
+        }
+        if constexpr (DK == 4) {
+            // One D for the element: the stress sigma(L) = sum_k L_k D E_k is
+            // linear in the barycentrics and the forces integrate in closed form
+            // with int L_a L_b dV = V (1 + delta_ab) / 20:
+            //   corner i:     (V/20) (4 s_i - T) . gL_i,
+            //   edge (a, b):  (4V/20) ((T + s_a) . gL_b + (T + s_b) . gL_a),
+            // with s_k = D E_k and T = s_1 + ... + s_4 (the 4-point rule gives the
+            // same values for constant D).
+            const T v20 = sk * vol * (T)0.05;
+            T sgk[4][6], T6[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+#pragma unroll
+                for (int r = 0; r < 6; ++r) {
+                    T a = 0;
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) a += dm[sym6(r, c)] * Ek[k][c];
+                    sgk[k][r] = a * v20;
+                    T6[r] += sgk[k][r];
+                }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                T v[6];
+#pragma unroll
+                for (int r = 0; r < 6; ++r) v[r] = (T)4 * sgk[i][r] - T6[r];
+                tdot_acc<T>(v, gL[i], (T)1, f[i]);
+            }
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                const int a = E[q][0], b = E[q][1];
+                T va[6], vb[6];
+#pragma unroll
+                for (int r = 0; r < 6; ++r) {
+                    va[r] = T6[r] + sgk[a][r];
+                    vb[r] = T6[r] + sgk[b][r];
+                }
+                tdot_acc<T>(va, gL[b], (T)4, f[4 + q]);
+                tdot_acc<T>(vb, gL[a], (T)4, f[4 + q]);
+            }
+            return;
         }
         T ST[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
