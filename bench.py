@@ -198,8 +198,8 @@ def bench_single(args):
         el, _, st, out, _ = run_gpu(mesh, pr, args.warmup, args.steps, not args.no_profile)
         res[name] = {"value": mesh.n_dof * args.steps / el, "ms_per_step": el / args.steps * 1e3,
                      "iters": out["iters"][0, pre:n_total].tolist(),
-                     "phase_ms": {"ebe64": st["ms_ebe64"], "ebe32": st["ms_ebe32"], "law": st["ms_law"],
-                                  "rhs_diag_q": st["ms_other"]} if not args.no_profile else None,
+                     "phase_ms": {"ebe64": st["ms_ebe64"], "ebe32": st["ms_ebe32"], "gather32": st["ms_gather32"],
+                                  "law": st["ms_law"], "rhs_diag_q": st["ms_other"]} if not args.no_profile else None,
                      "device_gb": st["device_bytes"] / 1e9}
         log(f"{name}: {el/args.steps*1e3:.1f} ms/step")
     acc = None
