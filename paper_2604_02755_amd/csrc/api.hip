@@ -171,6 +171,32 @@ static Key3 key3(int x, int y, int z)
     return Key3{v[0], v[1], v[2]};
 }
 
+// Morton key of a point in a box scaled isotropically to 2^21 cells per side
+static uint64_t morton3(const double x[3], const double lo[3], double sc)
+{
+    auto spread = [](uint64_t v) {  // 21 bits -> every third bit
+        v &= 0x1FFFFF;
+        v = (v | v << 32) & 0x1F00000000FFFFull;
+        v = (v | v << 16) & 0x1F0000FF0000FFull;
+        v = (v | v << 8) & 0x100F00F00F00F00Full;
+        v = (v | v << 4) & 0x10C30C30C30C30C3ull;
+        v = (v | v << 2) & 0x1249249249249249ull;
+        return v;
+    };
+    uint64_t code = 0;
+    for (int c = 0; c < 3; ++c) {
+        const uint64_t q = (uint64_t)std::min(std::max((x[c] - lo[c]) * sc, 0.0), (double)((1 << 21) - 1));
+        code |= spread(q) << c;
+    }
+    return code;
+}
+
+static void build_mesh_internal(Ctx* ctx, const nlth_mesh_desc* d, Mesh& M);
+
+// Validates the node references, renumbers the nodes in Morton order of their
+// coordinates (nodal vectors then follow the spatial order of the elements,
+// which keeps the gathers of single members local), and builds the mesh on
+// the renumbered description.  M.node_new maps input node ids to storage ids.
 static void build_mesh(Ctx* ctx, const nlth_mesh_desc* d, Mesh& M)
 {
     if (!d || d->n_nodes <= 0 || d->n_tets <= 0 || !d->xyz || !d->tet10 || !d->layer)
@@ -179,16 +205,58 @@ static void build_mesh(Ctx* ctx, const nlth_mesh_desc* d, Mesh& M)
         throw Error{NLTH_EINVAL, "mesh: bface6/bface_kind missing"};
     if (d->n_recv < 0 || (d->n_recv > 0 && !d->recv)) throw Error{NLTH_EINVAL, "mesh: recv missing"};
     const int nn = d->n_nodes, ne = d->n_tets;
-    M.ctx = ctx;
-    M.nn = nn;
-    M.ne = ne;
-    M.xyz.assign(d->xyz, d->xyz + 3L * nn);
     char buf[256];
     for (long i = 0; i < 10L * ne; ++i)
         if (d->tet10[i] < 0 || d->tet10[i] >= nn) {
             snprintf(buf, sizeof buf, "mesh: tet %ld references node %d outside [0, %d)", i / 10, d->tet10[i], nn);
             throw Error{NLTH_EINVAL, buf};
         }
+    for (long i = 0; i < 6L * d->n_bfaces; ++i)
+        if (d->bface6[i] < 0 || d->bface6[i] >= nn) {
+            snprintf(buf, sizeof buf, "mesh: boundary face %ld references node %d outside [0, %d)", i / 6,
+                     d->bface6[i], nn);
+            throw Error{NLTH_EINVAL, buf};
+        }
+    for (int r = 0; r < d->n_recv; ++r)
+        if (d->recv[r] < 0 || d->recv[r] >= nn) {
+            snprintf(buf, sizeof buf, "mesh: receiver %d is node %d outside [0, %d)", r, d->recv[r], nn);
+            throw Error{NLTH_EINVAL, buf};
+        }
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (long i = 0; i < nn; ++i)
+        for (int c = 0; c < 3; ++c) {
+            lo[c] = std::min(lo[c], d->xyz[3 * i + c]);
+            hi[c] = std::max(hi[c], d->xyz[3 * i + c]);
+        }
+    const double ext = std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2], 1e-300});
+    std::vector<std::pair<uint64_t, int>> key(nn);
+    for (int i = 0; i < nn; ++i) key[i] = {morton3(d->xyz + 3L * i, lo, (double)(1 << 21) / ext), i};
+    std::sort(key.begin(), key.end());
+    M.node_new.resize(nn);
+    for (int k = 0; k < nn; ++k) M.node_new[key[k].second] = k;
+    std::vector<double> xyz(3L * nn);
+    for (int k = 0; k < nn; ++k)
+        for (int c = 0; c < 3; ++c) xyz[3L * k + c] = d->xyz[3L * key[k].second + c];
+    std::vector<int> tet(10L * ne), bf(6L * d->n_bfaces), rc(d->n_recv);
+    for (long i = 0; i < 10L * ne; ++i) tet[i] = M.node_new[d->tet10[i]];
+    for (long i = 0; i < 6L * d->n_bfaces; ++i) bf[i] = M.node_new[d->bface6[i]];
+    for (int r = 0; r < d->n_recv; ++r) rc[r] = M.node_new[d->recv[r]];
+    nlth_mesh_desc dn = *d;
+    dn.xyz = xyz.data();
+    dn.tet10 = tet.data();
+    dn.bface6 = d->n_bfaces > 0 ? bf.data() : d->bface6;
+    dn.recv = d->n_recv > 0 ? rc.data() : d->recv;
+    build_mesh_internal(ctx, &dn, M);
+}
+
+static void build_mesh_internal(Ctx* ctx, const nlth_mesh_desc* d, Mesh& M)
+{
+    const int nn = d->n_nodes, ne = d->n_tets;
+    M.ctx = ctx;
+    M.nn = nn;
+    M.ne = ne;
+    M.xyz.assign(d->xyz, d->xyz + 3L * nn);
+    char buf[256];
     M.max_layer = 0;
     for (int e = 0; e < ne; ++e) {
         if (d->layer[e] < 0) {
@@ -242,26 +310,15 @@ static void build_mesh(Ctx* ctx, const nlth_mesh_desc* d, Mesh& M)
             }
         const double ext = std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2], 1e-300});
         const double sc = (double)(1 << 21) / ext;
-        auto spread = [](uint64_t v) {  // 21 bits -> every third bit
-            v &= 0x1FFFFF;
-            v = (v | v << 32) & 0x1F00000000FFFFull;
-            v = (v | v << 16) & 0x1F0000FF0000FFull;
-            v = (v | v << 8) & 0x100F00F00F00F00Full;
-            v = (v | v << 4) & 0x10C30C30C30C30C3ull;
-            v = (v | v << 2) & 0x1249249249249249ull;
-            return v;
-        };
         std::vector<std::pair<uint64_t, int>> key(ne);
         for (int e = 0; e < ne; ++e) {
             const int* t = d->tet10 + 10L * e;
-            uint64_t code = 0;
+            double x[3];
             for (int c = 0; c < 3; ++c) {
-                double x = 0;
-                for (int a = 0; a < 4; ++a) x += 0.25 * d->xyz[3L * t[a] + c];
-                const uint64_t q = (uint64_t)std::min(std::max((x - lo[c]) * sc, 0.0), (double)((1 << 21) - 1));
-                code |= spread(q) << c;
+                x[c] = 0;
+                for (int a = 0; a < 4; ++a) x[c] += 0.25 * d->xyz[3L * t[a] + c];
             }
-            key[e] = {code, e};
+            key[e] = {morton3(x, lo, sc), e};
         }
         std::sort(key.begin(), key.end());
         M.order.resize(ne);
@@ -1646,6 +1703,13 @@ int nlth_apply_operator(nlth_ctx* ctx, const nlth_mesh* mesh, const nlth_problem
     int one = 1;
     NLTH_HIP(hipMemcpy(e->stepping.p, &one, 4, hipMemcpyHostToDevice));
     hipStream_t s = e->s;
+    // x and y are in input node order; the library stores nodes in Morton order
+    std::vector<double> xs(n), ys(n);
+    for (int i = 0; i < nn; ++i)
+        for (int c = 0; c < 3; ++c) xs[3L * mesh->node_new[i] + c] = x[3L * i + c];
+    x = xs.data();
+    double* y_user = y;
+    y = ys.data();
     if (precision == NLTH_FP64) {
         NLTH_HIP(hipMemcpy(e->p.p, x, n * 8, hipMemcpyHostToDevice));
         launch_fill(s, e->Ap.as<double>(), 0.0, n);
@@ -1665,6 +1729,8 @@ int nlth_apply_operator(nlth_ctx* ctx, const nlth_mesh* mesh, const nlth_problem
         NLTH_HIP(hipMemcpy(yf.data(), yd.p, n * 4, hipMemcpyDeviceToHost));
         for (long i = 0; i < n; ++i) y[i] = yf[i];
     }
+    for (int i = 0; i < nn; ++i)
+        for (int c = 0; c < 3; ++c) y_user[3L * i + c] = ys[3L * mesh->node_new[i] + c];
     API_END
 }
 

@@ -598,8 +598,10 @@ void launch_ebe_cluster32(hipStream_t s, const DevMesh& M, int MB, int nm, const
 // y = sum of the element outputs at each node (incidences in ascending
 // order, so the sum is reproducible) + bscale * base (base may be NULL and may
 // alias y).  With DOT the per-member partial sums of x . y over the block's
-// nodes go to partial[blockIdx * MB + m] (a fixed tree in LDS).  A block
-// covers 256 / MB nodes per pass (MB <= 256) and strides over the nodes;
+// nodes go to partial[blockIdx * MB + m] (a fixed tree in LDS).  A block takes
+// a contiguous range of nodes, 256 / MB nodes per pass (MB <= 256): with nodes
+// in Morton order, interleaving the blocks' passes over the whole range was
+// 40 % slower (concurrent blocks then read cluster rows of one small region);
 // members with active[m] == 0 keep y and add nothing.
 template <typename T, bool DOT, bool CL>
 __global__ __launch_bounds__(256) void k_gather(DevMesh M, int MB, int nm, const T* __restrict__ f,
@@ -613,7 +615,9 @@ __global__ __launch_bounds__(256) void k_gather(DevMesh M, int MB, int nm, const
     const int EB = MB >= 64 ? 1 : 64 / MB;
     const size_t rs = (size_t)EB * MB;
     double dot = 0.0;
-    for (long nd = (long)blockIdx.x * rpb + slot; nd < M.nn; nd += (long)gridDim.x * rpb) {
+    const long per = ((M.nn + gridDim.x - 1) / gridDim.x + rpb - 1) / rpb * rpb;
+    const long n0 = (long)blockIdx.x * per, n1 = n0 + per < M.nn ? n0 + per : M.nn;
+    for (long nd = n0 + slot; nd < n1; nd += rpb) {
         const int node = MB >= 64 ? __builtin_amdgcn_readfirstlane((int)nd) : (int)nd;
         if (!act) continue;
         T a0 = 0, a1 = 0, a2 = 0;

@@ -58,6 +58,7 @@ struct Mesh {
     double volume = 0.0;
     // host copies / analysis
     std::vector<double> xyz;
+    std::vector<int> node_new;     // input node -> storage node (Morton order)
     std::vector<int> order;        // storage position -> input tet (Morton order)
     std::vector<int> inv_order;    // input tet -> storage position
     std::vector<int> color_off;    // [ncolor+1] into color_elems
