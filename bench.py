@@ -72,11 +72,10 @@ def kernel_source_hash() -> str:
 
 
 def traffic_from_profile(src_hash: str, element_members_per_launch: float):
-    """HBM bytes per inner-operator application from the committed rocprofv3
-    --pmc summary (FETCH_SIZE and WRITE_SIZE of the element kernel and the
-    node gather, scaled by the copy calibration), taken per active
-    element-member and applied to this run's launches; None if the summary
-    was taken on other kernel sources."""
+    """HBM bytes per launch of the inner operator's element kernel from the
+    committed rocprofv3 --pmc summary (FETCH_SIZE and WRITE_SIZE scaled by
+    the copy calibration), taken per element-member and applied to this run's
+    launches; None if the summary was taken on other kernel sources."""
     p = os.path.join(ROOT, "profiles", "inner_operator_traffic_64x64x32.json")
     if not os.path.exists(p):
         return None
@@ -84,7 +83,7 @@ def traffic_from_profile(src_hash: str, element_members_per_launch: float):
         d = json.load(fh)
     if d.get("kernel_source_hash") != src_hash:
         return None
-    return round(d["bytes_per_element_member"] * element_members_per_launch, 0)
+    return round(d["element"]["bytes_per_element_member"] * element_members_per_launch, 0)
 
 
 def run_gpu(mesh, prob, warmup, steps, profile, tune_steps=0, tuned=None, ctx_kw=None, fixed=None):
@@ -335,17 +334,18 @@ def main():
     value = args.members * ndof * args.steps / el
     log(f"mixed: {el/args.steps*1e3:.1f} ms/step, {value:.3e} DOF-steps/s, tuning {tuned and {k: tuned.get(k) for k in ('inner_tol', 'inner_maxit', 'ebe_block', 'check_every', 'cluster_blocks')}}")
 
-    # roofline of the inner FP32 operator over the timed region: the element
-    # kernel plus the node gather of its outputs (one application each).  Its
-    # bound follows from the arithmetic intensity: FP32 ALU when flops per
-    # algorithmic byte exceed the ridge point (157.3 TFLOP/s / 8 TB/s), HBM else.
+    # roofline of the dominant kernel, the inner operator's element kernel, over
+    # the timed region (the node gather that completes each application is a
+    # separate, HBM-bound kernel, reported beside it).  The bound follows from
+    # the arithmetic intensity: FP32 ALU when flops per algorithmic byte exceed
+    # the ridge point (157.3 TFLOP/s / 8 TB/s), HBM else.
     inner = out_mixed["iters"][:, sl, 1].astype(np.int64).sum()
     roofline = None
     if st["n_ebe32"] > 0 and st["ms_ebe32"] > 0:
         per_unit = ebe32_algorithmic_bytes(mesh.n_tets, mesh.n_nodes, st["members_padded"], prob.inner_dtype)
         units = int(inner) * mesh.n_tets  # active element-members over all applications
         n_app = st["n_ebe32"]
-        ms = st["ms_ebe32"] + st["ms_gather32"]
+        ms = st["ms_ebe32"]
         flops = EBE32_FLOPS_ELEMENT_D if prob.inner_dtype == 2 else EBE32_FLOPS_PER_POINT_D
         alu = flops / per_unit > FP32_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
         gbs = per_unit * units / (ms * 1e-3) / 1e9
@@ -353,22 +353,24 @@ def main():
         src = kernel_source_hash()
         tb = traffic_from_profile(src, units / n_app)
         achieved, peak = (tfl, FP32_PEAK_TFLOPS) if alu else (gbs, HBM_PEAK_GBS)
+        cb = (tuned or {}).get("cluster_blocks", 3)
         roofline = {"bound": "alu" if alu else "hbm", "achieved": round(achieved, 2), "peak": peak,
                     "unit": "TFLOP/s" if alu else "GB/s", "frac": round(achieved / peak, 4),
                     "traffic": tb,
-                    "kernel": ("inner operator: nlth::k_ebe_cluster<float, %d, 0, %d> (element forces summed per "
-                               "cluster in LDS) + nlth::k_gather<float, true, true> (node sums)"
-                               % ({0: 1, 1: 0, 2: 4}[prob.inner_dtype], (tuned or {}).get("cluster_blocks", 3)))
+                    "kernel": ("nlth::k_ebe_cluster<float, %d, 0, %d> (inner operator: element forces summed per "
+                               "cluster in LDS)" % ({0: 1, 1: 0, 2: 4}[prob.inner_dtype], cb))
                               if st["members_padded"] >= 64 else
-                              ("inner operator: nlth::k_ebe<float, 1, 0, false, 1> (element forces) "
-                               "+ nlth::k_gather<float, true, false> (node sums)"),
+                              "nlth::k_ebe<float, 1, 0, false, 1> (inner operator: element forces)",
                     "launches": int(n_app), "avg_launch_us": round(ms / n_app * 1e3, 2),
-                    "avg_element_kernel_us": round(st["ms_ebe32"] / n_app * 1e3, 2),
-                    "avg_gather_kernel_us": round(st["ms_gather32"] / max(1, st["n_gather32"]) * 1e3, 2),
                     "algorithmic_bytes_per_launch": round(per_unit * units / n_app, 0),
+                    "algorithmic_flops_per_launch": round(flops * units / n_app, 0),
                     "bytes_per_element_member": round(per_unit, 1),
                     "flops_per_element_member": flops,
-                    "hbm_gbs_algorithmic": round(gbs, 1), "fp32_tflops": round(tfl, 2)}
+                    "hbm_gbs_algorithmic": round(gbs, 1), "fp32_tflops": round(tfl, 2),
+                    "fp32_nonpacked_frac": round(tfl / (FP32_PEAK_TFLOPS / 2), 4),
+                    "gather_kernel": "nlth::k_gather<float, true, true> (node sums of the cluster rows, dot fused)",
+                    "gather_avg_launch_us": round(st["ms_gather32"] / max(1, st["n_gather32"]) * 1e3, 2),
+                    "operator_avg_us": round((st["ms_ebe32"] + st["ms_gather32"]) / n_app * 1e3, 2)}
 
     # plain FP64 on the same GPU, same members, same timed steps
     fp64 = None
