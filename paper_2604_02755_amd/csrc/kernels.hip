@@ -218,6 +218,22 @@ __device__ __forceinline__ size_t f_index(long e, int r, int MB, int EB, int m)
 // Forces of one element-member (element e, member m): the 30 nodal values of
 // the operator of MODE applied to x1 (and x2), written to f; nbase[n] is the
 // offset of node n's row in the nodal vectors.
+// element i of an array at a wavefront-uniform base: the byte offset is
+// formed in 32 bits, so the load takes the scalar-base + 32-bit vector-offset
+// form (no per-lane 64-bit address arithmetic).  i * sizeof(T) < 2^32.
+template <typename T>
+__device__ __forceinline__ T ld_u(const T* base, uint32_t i)
+{
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + i * (uint32_t)sizeof(T));
+}
+
+template <typename T>
+__device__ __forceinline__ T ld_u_nt(const T* base, uint32_t i)
+{
+    return __builtin_nontemporal_load(
+        reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + i * (uint32_t)sizeof(T)));
+}
+
 template <typename T, int DK, int MODE>
 __device__ __forceinline__ void ebe_element(const DevMesh& M, int MB, int m, long e, const void* __restrict__ Dv,
                                             const double* __restrict__ h, const double* __restrict__ mat,
@@ -265,9 +281,9 @@ __device__ __forceinline__ void ebe_element(const DevMesh& M, int MB, int m, lon
         const uint32_t off = (uint32_t)(c * MB + m);
 #pragma unroll
         for (int n = 0; n < 10; ++n) {
-            const T v1 = (x1 + nbase[n])[off];
+            const T v1 = ld_u(x1 + nbase[n], off);
             xk[n][c] = v1;
-            xm[n] = (MODE == OP_RHS) ? (x2 + nbase[n])[off] + cv * v1 : v1;
+            xm[n] = (MODE == OP_RHS) ? ld_u(x2 + nbase[n], off) + cv * v1 : v1;
         }
         if (MODE == OP_K) {
 #pragma unroll
@@ -327,7 +343,7 @@ __device__ __forceinline__ void ebe_element(const DevMesh& M, int MB, int m, lon
             const uint32_t* D = (const uint32_t*)Dv + (eb * 11 + ei) * MB;
 #pragma unroll
             for (int q = 0; q < 11; ++q) {
-                const uint32_t wv = __builtin_nontemporal_load(&D[(uint32_t)q * rs + (uint32_t)m]);
+                const uint32_t wv = ld_u_nt(D, (uint32_t)q * rs + (uint32_t)m);
                 dm[2 * q] = (T)bf2f(wv & 0xFFFFu);
                 dm[2 * q + 1] = (T)bf2f(wv >> 16);
             }
@@ -390,12 +406,12 @@ __device__ __forceinline__ void ebe_element(const DevMesh& M, int MB, int m, lon
                 const T* D = (const T*)Dv + (eb * 84 + ei) * MB;
 #pragma unroll
                 for (int k = 0; k < 21; ++k)
-                    d[k] = __builtin_nontemporal_load(&D[(uint32_t)(j * 21 + k) * rs + (uint32_t)m]);
+                    d[k] = ld_u_nt(D, (uint32_t)(j * 21 + k) * rs + (uint32_t)m);
             } else {
                 const uint32_t* D = (const uint32_t*)Dv + (eb * 44 + ei) * MB;
 #pragma unroll
                 for (int q = 0; q < 11; ++q) {
-                    const uint32_t wv = __builtin_nontemporal_load(&D[(uint32_t)(j * 11 + q) * rs + (uint32_t)m]);
+                    const uint32_t wv = ld_u_nt(D, (uint32_t)(j * 11 + q) * rs + (uint32_t)m);
                     d[2 * q] = (T)bf2f(wv & 0xFFFFu);
                     d[2 * q + 1] = (T)bf2f(wv >> 16);
                 }
@@ -495,7 +511,10 @@ __global__ __launch_bounds__(256) void k_ebe_cluster(DevMesh M, int MB, int nm, 
     const long blk = (blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;  // XCD-contiguous clusters
     const int c = (int)(blk / ngroups), g = (int)(blk % ngroups);
     if (c >= ncl) return;  // whole block: padding of the grid to a multiple of 8
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    // the wavefront index is uniform: saying so keeps the element's
+    // connectivity and row bases in scalar registers (scalar loads and
+    // address arithmetic instead of per-lane 64-bit adds)
+    const int t = threadIdx.x, lane = t & 63, w = __builtin_amdgcn_readfirstlane(t >> 6);
     const int m = g * 64 + lane;
     const int e0 = M.cl_off[c], nec = M.cl_off[c + 1] - e0;
     const int r0 = M.cl_noff[c], ncn = M.cl_noff[c + 1] - r0;
@@ -525,6 +544,8 @@ __global__ __launch_bounds__(256) void k_ebe_cluster(DevMesh M, int MB, int nm, 
             if (w == ww && le < nec) {
 #pragma unroll
                 for (int n = 0; n < 10; ++n) {
+                    // (LDS read-add-write: the no-return LDS atomic add measured
+                    // 3.5x slower for the whole kernel)
                     T* yr = ys + (int)((lw[n / 4] >> (8 * (n % 4))) & 0xFFu) * 3 * 64 + lane;
                     yr[0] += f[n][0];
                     yr[64] += f[n][1];
@@ -870,6 +891,45 @@ template void launch_dashpot<float>(hipStream_t, const DevMesh&, int, int, const
 // 3x3 block-Jacobi preconditioner (Section 2.2): diagonal blocks of A
 // ---------------------------------------------------------------------------
 
+// Diagonal 3x3 block of node n of one element:
+//   c_M rho V Mref(n, n) I + c_K (V/4) sum_j B_n(j)^T D_j B_n(j)
+// with B_n^T D B_n [c][d] = sum_{p,q} g_p g_q D[v(c, p)][v(d, q)], g = grad N_n
+// at point j and v(c, p) the Voigt index of du_c/dx_p.  Per point the 6 x 6
+// coefficients of the quadratic forms in (gx^2, gy^2, gz^2, gx gy, gy gz, gz gx)
+// are formed once and shared by the nodes.  A thread takes one element-member
+// and one part of the nodes (the 4 corners, edges 01 12 20, or edges 03 13
+// 23), so it holds at most 4 blocks: FP64 register pressure sets the
+// occupancy here, and each part re-reads D (from L2).
+__device__ __forceinline__ constexpr int voigt_of(int c, int p)
+{
+    return c == p ? c : ((c + p == 1) ? 3 : ((c + p == 3) ? 4 : 5));
+}
+
+// adds w g^T C g (the 6 entries of the symmetric 3x3 block) for node n (a
+// compile-time index after unrolling) with g = grad N_n at barycentrics L
+__device__ __forceinline__ void diag_node_add(int n, const double L[4], const double gL[4][3], const double C[6][6],
+                                              double w, double acc[6])
+{
+    constexpr int E[6][2] = {{0, 1}, {1, 2}, {2, 0}, {0, 3}, {1, 3}, {2, 3}};
+    double g[3];
+    if (n < 4) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) g[a] = (4.0 * L[n] - 1.0) * gL[n][a];
+    } else {
+        const int ea = E[n - 4][0], eb = E[n - 4][1];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) g[a] = 4.0 * (L[ea] * gL[eb][a] + L[eb] * gL[ea][a]);
+    }
+    const double gg[6] = {g[0] * g[0], g[1] * g[1], g[2] * g[2], g[0] * g[1], g[1] * g[2], g[2] * g[0]};
+#pragma unroll
+    for (int cd = 0; cd < 6; ++cd) {
+        double a = 0.0;
+#pragma unroll
+        for (int pq = 0; pq < 6; ++pq) a += gg[pq] * C[cd][pq];
+        acc[cd] += w * a;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_diag(DevMesh M, int MB, int nm, int e0, int e1,
                                              const double* __restrict__ D, const double* __restrict__ h,
                                              const double* __restrict__ mat, StepConst sc,
@@ -877,11 +937,15 @@ __global__ __launch_bounds__(256) void k_diag(DevMesh M, int MB, int nm, int e0,
 {
     const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
     const int m = (int)(t % MB);
-    const long pos = e0 + t / MB;  // position in the colour lists
+    long r = t / MB;
+    if (MB >= 64) r = __builtin_amdgcn_readfirstlane((int)r);  // wavefront-uniform element and part
+    const int part = (int)(r % 3);
+    const long pos = e0 + r / 3;  // position in the colour lists
     if (pos >= e1 || m >= nm) return;
-    const long e = M.celem[pos];
+    const long e = MB >= 64 ? (long)__builtin_amdgcn_readfirstlane(M.celem[pos]) : (long)M.celem[pos];
     const long ne = M.ne;
     double gL[4][3];
+#pragma unroll
     for (int k = 0; k < 12; ++k) gL[k / 3][k % 3] = M.geo64[k * ne + e];
     const double vol = M.geo64[12 * ne + e];
     const int l = M.layer[e];
@@ -892,49 +956,67 @@ __global__ __launch_bounds__(256) void k_diag(DevMesh M, int MB, int nm, int e0,
     const double dt = sc.dt;
     const double sm = rho * vol * (4.0 / (dt * dt) + 2.0 * sc.ahat * he / dt);
     const double w = (1.0 + 2.0 * sc.bhat * he / dt) * vol * 0.25;
-    double blk[10][6];
-    for (int n = 0; n < 10; ++n) {
-        double md = sm * mass_ref(n, n);
-        blk[n][0] = md; blk[n][1] = 0; blk[n][2] = 0; blk[n][3] = md; blk[n][4] = 0; blk[n][5] = md;
-    }
+    constexpr int PQ[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {1, 2}, {2, 0}};
+    constexpr int CD[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
+    double blk[4][6];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) blk[i][k] = 0.0;
     const int EB = MB >= 64 ? 1 : 64 / MB;
 #pragma unroll 1
     for (int j = 0; j < 4; ++j) {
-        double G[10][3], d[21];
-        shape_grads<double>(j, gL, G);
-        for (int k = 0; k < 21; ++k) d[k] = D[d_index(e, j, k, MB, EB, m)];
-        for (int n = 0; n < 10; ++n) {
-            const double gx = G[n][0], gy = G[n][1], gz = G[n][2];
-            // columns of B for this node (6 strains x 3 displacement components)
-            const double b[3][6] = {{gx, 0, 0, gy, 0, gz}, {0, gy, 0, gx, gz, 0}, {0, 0, gz, 0, gy, gx}};
-            double Db[3][6];
-            for (int c = 0; c < 3; ++c)
-                for (int r = 0; r < 6; ++r) {
-                    double a = 0;
-                    for (int k = 0; k < 6; ++k) a += d[sym6(r, k)] * b[c][k];
-                    Db[c][r] = a;
+        double C[6][6];  // C[cd][pq]
+        {
+            double d[21];
+            const double* Dj = D + d_index(e, j, 0, MB, EB, 0);  // uniform when MB >= 64
+            const uint32_t rs = (uint32_t)(EB * MB);
+#pragma unroll
+            for (int k = 0; k < 21; ++k) d[k] = ld_u(Dj, (uint32_t)k * rs + (uint32_t)m);
+#pragma unroll
+            for (int cd = 0; cd < 6; ++cd)
+#pragma unroll
+                for (int pq = 0; pq < 6; ++pq) {
+                    const int c = CD[cd][0], dd = CD[cd][1], p = PQ[pq][0], q = PQ[pq][1];
+                    double v = d[sym6(voigt_of(c, p), voigt_of(dd, q))];
+                    if (p != q) v += d[sym6(voigt_of(c, q), voigt_of(dd, p))];
+                    C[cd][pq] = v;
                 }
-            double K[3][3];
-            for (int c = 0; c < 3; ++c)
-                for (int dd = 0; dd < 3; ++dd) {
-                    double a = 0;
-                    for (int r = 0; r < 6; ++r) a += b[c][r] * Db[dd][r];
-                    K[c][dd] = a;
-                }
-            blk[n][0] += w * K[0][0]; blk[n][1] += w * K[0][1]; blk[n][2] += w * K[0][2];
-            blk[n][3] += w * K[1][1]; blk[n][4] += w * K[1][2]; blk[n][5] += w * K[2][2];
+        }
+        double L[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) L[i] = (i == j) ? QA_ : QB_;
+        if (part == 0) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) diag_node_add(i, L, gL, C, w, blk[i]);
+        } else if (part == 1) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) diag_node_add(4 + i, L, gL, C, w, blk[i]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) diag_node_add(7 + i, L, gL, C, w, blk[i]);
         }
     }
-    for (int n = 0; n < 10; ++n) {
+    const int nn = part == 0 ? 4 : 3, n0 = part == 0 ? 0 : 1 + 3 * part;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if (i >= nn) break;
+        const int n = n0 + i;
         const long node = M.conn[n * ne + e];
-        for (int k = 0; k < 6; ++k) diag[(node * 6 + k) * MB + m] += blk[n][k];
+        const double md = sm * mass_ref(n, n);
+        double* dg = diag + node * 6 * MB;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            double& o = *reinterpret_cast<double*>(reinterpret_cast<char*>(dg) + (uint32_t)(k * MB + m) * 8u);
+            o += blk[i][k] + ((k == 0 || k == 3 || k == 5) ? md : 0.0);
+        }
     }
 }
 
 void launch_diag(hipStream_t s, const DevMesh& M, int MB, int nm, int e0, int e1, const double* D, const double* h,
                  const double* mat, int, StepConst sc, double* diag)
 {
-    long n = (long)(e1 - e0) * MB;
+    long n = (long)(e1 - e0) * 3 * MB;
     if (n > 0) hipLaunchKernelGGL(k_diag, dim3(nblocks(n)), dim3(256), 0, s, M, MB, nm, e0, e1, D, h, mat, sc, diag);
 }
 
