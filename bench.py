@@ -99,7 +99,7 @@ def run_gpu(mesh, prob, warmup, steps, profile, tune_steps=0, tuned=None, ctx_kw
         choice = None
         if fixed is not None:
             ens.set_tuning(fixed["ebe_block"], fixed["check_every"], 1, fixed["inner_maxit"], fixed["inner_tol"],
-                           cluster_blocks=fixed.get("cluster_blocks", 0))
+                           cluster_blocks=fixed.get("cluster_blocks", 0), inner_method=fixed.get("inner_method", 0))
             choice = dict(fixed)
         if tuned is not None:
             ens.set_tuning(tuned["ebe_block"], tuned["check_every"], 1, cluster_blocks=tuned.get("cluster_blocks", 0))
@@ -332,7 +332,7 @@ def main():
     el, st0, st, out_mixed, tuned = run_gpu(mesh, prob, args.warmup, args.steps, not args.no_profile, n_tune,
                                             fixed=fixed)
     value = args.members * ndof * args.steps / el
-    log(f"mixed: {el/args.steps*1e3:.1f} ms/step, {value:.3e} DOF-steps/s, tuning {tuned and {k: tuned.get(k) for k in ('inner_tol', 'inner_maxit', 'ebe_block', 'check_every', 'cluster_blocks')}}")
+    log(f"mixed: {el/args.steps*1e3:.1f} ms/step, {value:.3e} DOF-steps/s, tuning {tuned and {k: tuned.get(k) for k in ('inner_method', 'inner_tol', 'inner_maxit', 'ebe_block', 'check_every', 'cluster_blocks')}}")
 
     # roofline of the dominant kernel, the inner operator's element kernel, over
     # the timed region (the node gather that completes each application is a
@@ -441,7 +441,8 @@ def main():
                    "parallelism": "members batched in one launch"},
         "iterations": {"outer_per_member_step": float(out_mixed["iters"][:, sl, 0].mean()),
                        "inner_per_member_step": float(out_mixed["iters"][:, sl, 1].mean())},
-        "tuning": ({k: tuned[k] for k in ("inner_tol", "inner_maxit", "ebe_block", "check_every", "cluster_blocks")
+        "tuning": ({k: tuned.get(k, 0) for k in ("inner_method", "inner_tol", "inner_maxit", "ebe_block", "check_every",
+                                                 "cluster_blocks")
                     if k in tuned} if tuned else None),
         "timed_steps": f"steps {pre + 1}-{n_total} of the record",
         "phase_ms": {"ebe64": st["ms_ebe64"], "ebe32": st["ms_ebe32"], "gather32": st["ms_gather32"],

@@ -221,6 +221,8 @@ typedef struct {
     int64_t device_bytes, host_bytes;
     double ms_gather32;        /* node gather of the inner operator's element outputs */
     int64_t n_gather32;
+    double cheb_lo_min;        /* Chebyshev inner bounds of the last step: smallest lower bound and */
+    double cheb_hi_max;        /* largest upper bound over the members (0 without Chebyshev) */
 } nlth_stats;
 int nlth_ens_stats(const nlth_ens* ens, nlth_stats* st);
 
@@ -241,8 +243,8 @@ int nlth_ens_stats(const nlth_ens* ens, nlth_stats* st);
  * nodal vector.
  * Out-of-range fields (ebe_block not 0/64/128/256, check_every outside
  * 0..64, inner_maxit outside 0..100000, inner_tol outside [0, 1), cluster_blocks
- * not 0/2/3/4, scatter
- * outside -1..2 or not available for this ensemble) give NLTH_EINVAL and
+ * not 0/2/3/4, scatter outside -1..2 or not available for this ensemble,
+ * inner_method outside -1..1, or Chebyshev with a degree above 64) give NLTH_EINVAL and
  * change nothing.  Not to be called while the ensemble
  * is stepping on another thread. */
 typedef struct {
@@ -255,6 +257,10 @@ typedef struct {
                                   slots); 1 one launch per colour; 2 element clusters + node gather
                                   (64..256 slots, a multiple of 64) */
     int32_t cluster_blocks;    /* 0 keep; 2, 3 or 4 co-resident FP32 cluster blocks per CU (default 3) */
+    int32_t inner_method;      /* -1 keep; 0 inner CG (default); 1 Chebyshev iteration of degree
+                                  inner_maxit (at most 64, inner_tol unused) on the block-Jacobi
+                                  preconditioned operator, with each member's spectrum bounds taken
+                                  from the Lanczos matrix of the step's first inner CG solve */
 } nlth_tuning;
 int nlth_ens_set_tuning(nlth_ens* ens, const nlth_tuning* t);
 int nlth_ens_set_profile(nlth_ens* ens, int32_t profile);

@@ -2,8 +2,9 @@
 
 It times candidate settings on the live ensemble, a step or two each, by
 coordinate descent:
-1. the inner iteration policy of the mixed path (tolerance-driven, or a fixed
-   inner count that keeps every member's lanes busy);
+1. the inner iteration policy of the mixed path (tolerance-driven CG, a fixed
+   CG count that keeps every member's lanes busy, or a fixed-degree Chebyshev
+   iteration after the step's first CG solve);
 2. threads per block of the element-by-element launches;
 3. CG iterations per host convergence check (the hipGraph chunk length);
 4. co-resident blocks per CU of the cluster launches (64 and more member slots).
@@ -18,7 +19,9 @@ import json
 import os
 import time
 
-INNER_POLICIES = [(0.1, 50), (0.01, 60), (1e-12, 12), (1e-12, 16), (1e-12, 20)]
+# (inner_tol, inner_maxit, inner_method): method 0 CG, 1 Chebyshev of degree inner_maxit
+INNER_POLICIES = [(0.1, 50, 0), (0.01, 60, 0), (1e-12, 12, 0), (1e-12, 16, 0), (1e-12, 20, 0),
+                  (1e-12, 12, 1), (1e-12, 16, 1), (1e-12, 20, 1)]
 EBE_BLOCKS = [256, 128]
 CHECK_EVERY = [8, 16, 4]
 CLUSTER_BLOCKS = [3, 2, 4]
@@ -46,16 +49,17 @@ def members_padded(n: int) -> int:
 
 def trial_steps(prob, steps_per_trial: int = 1) -> int:
     """Steps an uncached tuning run takes: every candidate of a stage runs
-    twice (palindromic order), the incumbent included."""
+    twice (palindromic order), the incumbent included; the mixed path adds
+    one untimed step that makes the Chebyshev spectrum estimate."""
     n_pol = len(INNER_POLICIES) if prob.precision == 1 else 1
     n_cl = len(CLUSTER_BLOCKS) if 64 <= members_padded(prob.n_members) <= 256 else 1
     stages = [n_pol, len(EBE_BLOCKS), len(CHECK_EVERY), n_cl]
-    return 2 * steps_per_trial * sum(n for n in stages if n > 1)
+    return 2 * steps_per_trial * sum(n for n in stages if n > 1) + (1 if prob.precision == 1 else 0)
 
 
 def _apply(ens, c):
     ens.set_tuning(c["ebe_block"], c["check_every"], 1, c["inner_maxit"], c["inner_tol"],
-                   cluster_blocks=c["cluster_blocks"])
+                   cluster_blocks=c["cluster_blocks"], inner_method=c.get("inner_method", 0))
 
 
 def tune(ens, mesh, prob, steps_per_trial: int = 1, cache_file: str | None = None, log=None) -> dict:
@@ -95,10 +99,16 @@ def tune(ens, mesh, prob, steps_per_trial: int = 1, cache_file: str | None = Non
         return cands[i], ms[i]
 
     cur = dict(ebe_block=EBE_BLOCKS[0], check_every=CHECK_EVERY[0], cluster_blocks=CLUSTER_BLOCKS[0],
-               inner_tol=prob.inner_tol, inner_maxit=prob.inner_maxit)
+               inner_tol=prob.inner_tol, inner_maxit=prob.inner_maxit, inner_method=0)
     best_ms = None
     if prob.precision == 1:
-        cur, best_ms = stage([dict(cur, inner_tol=t, inner_maxit=m) for t, m in INNER_POLICIES])
+        # the first Chebyshev step also estimates the top of the spectrum (a
+        # cost shared by the next 32 steps): make it here, untimed
+        cheb = [p for p in INNER_POLICIES if p[2] == 1]
+        if cheb:
+            _apply(ens, dict(cur, inner_tol=cheb[0][0], inner_maxit=cheb[0][1], inner_method=1))
+            ens.step(1)
+        cur, best_ms = stage([dict(cur, inner_tol=t, inner_maxit=m, inner_method=k) for t, m, k in INNER_POLICIES])
     cur, ms = stage([dict(cur, ebe_block=b) for b in EBE_BLOCKS])
     best_ms = ms if ms is not None else best_ms
     cur, ms = stage([dict(cur, check_every=c) for c in CHECK_EVERY])

@@ -653,7 +653,11 @@ int64_t ensemble_bytes(const Mesh& m, const Problem& p, int MB, bool paged)
     int64_t v = ndof * MB * 8;
     int64_t bytes = 10 * v;                                  // u v a q du b r z p Ap
     bytes += 2 * (int64_t)m.nn * 6 * MB * 8 + (int64_t)m.nn * 6 * MB * 4;  // diag, pinv, pinv32
-    if (p.precision == NLTH_MIXED) bytes += 5 * ndof * MB * 4;
+    if (p.precision == NLTH_MIXED) {
+        bytes += 5 * ndof * MB * 4;
+        bytes += (int64_t)(2 * kLanczosMax * 8 + (2 * kChebMax + 1) * 4 + 16) * MB;  // Lanczos, Chebyshev tables
+        if (MB >= 64 && MB <= 256) bytes += (int64_t)m.nbn * 3 * MB * 4;           // dashpot rows
+    }
     bytes += (int64_t)m.ne * 4 * 21 * MB * 8;               // D64
     if (p.precision == NLTH_MIXED)
         bytes += (int64_t)m.ne * 4 *
@@ -777,11 +781,19 @@ void Ens::create(Ctx* c, const Mesh* m, const Problem& prob, int member_pad)
     diag.alloc(bg, (size_t)m->nn * 6 * MB * 8);
     pinv.alloc(bg, (size_t)m->nn * 6 * MB * 8);
     pinv32.alloc(bg, (size_t)m->nn * 6 * MB * 4);
-    if (P.precision == NLTH_MIXED)
+    if (P.precision == NLTH_MIXED) {
         for (DevBuf* bb : {&ir, &iz, &ip, &iw, &iAp}) {
             bb->alloc(bg, (size_t)ndof * MB * 4);
             launch_fill32(s, bb->as<float>(), 0.0f, (long)ndof * MB);
         }
+        lz.alloc(bg, (size_t)2 * kLanczosMax * MB * 8);
+        launch_fill(s, lz.as<double>(), 0.0, (long)2 * kLanczosMax * MB);
+        chebc.alloc(bg, (size_t)(2 * kChebMax + 1) * MB * 4);
+        launch_fill32(s, chebc.as<float>(), 0.0f, (long)(2 * kChebMax + 1) * MB);
+        cheb_bounds.alloc(bg, (size_t)(2 * MB + 1) * 8);  // per-member lo, hi; the running upper bound
+        launch_fill(s, cheb_bounds.as<double>(), 0.0, (long)2 * MB + 1);
+        if (MB >= 64 && MB <= 256 && m->nbn > 0) qb.alloc(bg, (size_t)m->nbn * 3 * MB * 4);
+    }
     EB = MB >= 64 ? 1 : 64 / MB;
     ne_pad = (m->ne + EB - 1) / EB * EB;
     const size_t nD = (size_t)ne_pad * 4 * 21 * MB;
@@ -879,6 +891,7 @@ void Ens::create(Ctx* c, const Mesh* m, const Problem& prob, int member_pad)
     int* iptr = (int*)(dptr + 12 * MB);
     cs.active = iptr; cs.iters = iptr + MB; cs.status = iptr + 2 * MB; cs.inner_active = iptr + 3 * MB;
     cs.inner_iters = iptr + 4 * MB; cs.inner_total = iptr + 5 * MB;
+    cs.lz = lz.as<double>();
     NLTH_HIP(hipHostMalloc((void**)&h_flags, sizeof(int) * MB, hipHostMallocDefault));
     member_step.alloc(bg, (size_t)MB * 4);
     stepping.alloc(bg, (size_t)MB * 4);
@@ -910,7 +923,8 @@ void Ens::destroy()
     ev_pool.clear();
     if (g_inner) (void)hipGraphExecDestroy(g_inner);
     if (g_pcg) (void)hipGraphExecDestroy(g_pcg);
-    g_inner = g_pcg = nullptr;
+    if (g_cheb) (void)hipGraphExecDestroy(g_cheb);
+    g_inner = g_pcg = g_cheb = nullptr;
     if (h_flags) (void)hipHostFree(h_flags);
     h_flags = nullptr;
     if (ev_copy0) (void)hipEventDestroy(ev_copy0);
@@ -1096,6 +1110,105 @@ void Ens::inner_solve()
     }
 }
 
+// Chebyshev inner solve of degree inner_maxit for the outer-active members,
+// with the coefficient table of the step (from the first inner CG solve).
+// The whole solve has fixed launches, so it is captured once into a hipGraph.
+void Ens::cheb_body()
+{
+    const int n = std::min(P.inner_maxit, kChebMax);
+    const int* act = cs.active;
+    const DevMesh dm = mesh->dev();
+    const float* cheb = chebc.as<float>();
+    const float* pv = pinv32.as<float>();
+    launch_cheb_start(s, mesh->nn, MB, nm, r.as<double>(), pv, cheb, ir.as<float>(), iz.as<float>(), ip.as<float>(),
+                      act);
+    float* d = ip.as<float>();
+    float* dn = iw.as<float>();
+    const bool fused = scatter == 2 && (qb.p || dm.nbn == 0);
+    for (int k = 0; k < n; ++k) {
+        const bool last = k + 1 == n;
+        if (fused) {
+            set_cluster_blocks(cluster_blocks);
+            hipEvent_t t0;
+            tstart(t0);
+            launch_ebe_cluster32(s, dm, MB, nm, D32.as<float>(), D16.as<uint32_t>(), h.as<double>(),
+                                 mat.as<double>(), sc, d, (float*)cbuf.p, act, d16_mean);
+            tstop(t0, &pc_ebe32, (int64_t)mesh->ne * nm);
+            launch_dashpot_rows(s, dm, MB, nm, mat.as<double>(), (float)(2.0 / P.dt), d, qb.as<float>(), act);
+            tstart(t0);
+            launch_gather_cheb(s, dm, MB, nm, k, last, (const float*)cbuf.p, qb.as<float>(), iz.as<float>(),
+                               ir.as<float>(), d, dn, pv, cheb, act);
+            tstop(t0, &pc_gather32, (int64_t)mesh->nn * nm);
+        } else {
+            ebe32(d, iAp.as<float>(), act, nullptr);
+            launch_cheb_update(s, mesh->nn, MB, nm, k, last, iz.as<float>(), ir.as<float>(), d, iAp.as<float>(), dn,
+                               pv, cheb, act);
+        }
+        std::swap(d, dn);
+    }
+    launch_finalize(s, FIN_CHEB_COUNT, 0, MB, nm, partial.as<double>(), 0, cs, 0.0, n);
+}
+
+// Largest eigenvalue of the block-Jacobi preconditioned inner operator, from
+// cheb_est_iters inner CG iterations on a random right-hand side for the
+// members of this step (z serves as that vector: the outer solve overwrites
+// it before reading it).  Raises the running upper bound of the Chebyshev
+// interval; runs before the step's solve every cheb_est_every steps.
+void Ens::cheb_estimate()
+{
+    const long n = ndof;
+    int nblk;
+    launch_fill_random(s, z.as<double>(), n * MB, 0x5851F42D4C957F2Dull + (uint64_t)steps_done);
+    launch_inner_start(s, mesh->nn, MB, nm, z.as<double>(), pinv32.as<float>(), ir.as<float>(), iz.as<float>(),
+                       ip.as<float>(), iw.as<float>(), iAp.as<float>(), stepping.as<int>(), partial.as<double>(),
+                       &nblk);
+    fin(FIN_EST_START, 2, nblk, 0.0, 0);
+    const int keep_it = P.inner_maxit;
+    const double keep_tol = P.inner_tol;
+    P.inner_maxit = std::min(cheb_est_iters, kLanczosMax);
+    P.inner_tol = 0.0;
+    est_iters = P.inner_maxit;
+    try {
+        for (int i = 0; i < P.inner_maxit; ++i) inner_iter();
+    } catch (...) {
+        P.inner_maxit = keep_it;
+        P.inner_tol = keep_tol;
+        throw;
+    }
+    P.inner_maxit = keep_it;
+    P.inner_tol = keep_tol;
+    launch_cheb_hi_estimate(s, MB, nm, cs, cheb_est_scale, cheb_bounds.as<double>());
+}
+
+void Ens::cheb_solve()
+{
+    if (!use_graph || profile) {
+        cheb_body();
+        return;
+    }
+    if (!g_cheb) {
+        hipGraph_t g = nullptr;
+        NLTH_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        try {
+            cheb_body();
+        } catch (...) {
+            (void)hipStreamEndCapture(s, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+        }
+        NLTH_HIP(hipStreamEndCapture(s, &g));
+        hipError_t e = hipGraphInstantiate(&g_cheb, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            g_cheb = nullptr;
+            use_graph = false;
+            cheb_body();
+            return;
+        }
+    }
+    NLTH_HIP(hipGraphLaunch(g_cheb, s));
+}
+
 // one inner FP32 PCG iteration (every launch reads its scalars on the device)
 void Ens::inner_iter()
 {
@@ -1176,9 +1289,19 @@ void Ens::solve_fcg()
     launch_pcg_start(s, mesh->nn, MB, nm, b.as<double>(), Ap.as<double>(), pinv.as<double>(), r.as<double>(),
                      z.as<double>(), p.as<double>(), st, pd, &nblk);
     fin(FIN_FCG_START, 2, nblk, tol2, P.cg_maxit);
+    if (est_iters) {  // the spectrum estimate of this step counts as inner iterations
+        fin(FIN_CHEB_COUNT, 0, 0, 0.0, est_iters);
+        est_iters = 0;
+    }
     launch_zero_if_b0(s, n, MB, nm, x, cs.bb, st);
     if (!read_any_active(act)) return;
     inner_solve();
+    // Chebyshev for the later preconditioner calls of this step: spectrum
+    // bounds of each member from the Lanczos matrix of the CG solve just done
+    const bool cheb = inner_method == 1 && P.inner_maxit >= 1;
+    if (cheb)
+        launch_cheb_bounds(s, MB, nm, cs, std::min(P.inner_maxit, kChebMax), cheb_lo, cheb_hi, chebc.as<float>(),
+                           cheb_bounds.as<double>());
     launch_inner_out(s, n, MB, nm, iz.as<float>(), z.as<double>(), Ap.as<double>(), r.as<double>(), act, pd, &nblk);
     fin(FIN_FCG_RZ, 2, nblk, tol2, P.cg_maxit);
     launch_p_update<double>(s, n, MB, nm, z.as<double>(), p.as<double>(), nullptr, act, nullptr);
@@ -1188,7 +1311,8 @@ void Ens::solve_fcg()
         launch_xr_update(s, n, MB, nm, x, r.as<double>(), p.as<double>(), Ap.as<double>(), cs.alpha, act, pd, &nblk);
         fin(FIN_FCG_RR, 1, nblk, tol2, P.cg_maxit);
         if (!read_any_active(act)) break;
-        inner_solve();
+        if (cheb) cheb_solve();
+        else inner_solve();
         launch_inner_out(s, n, MB, nm, iz.as<float>(), z.as<double>(), Ap.as<double>(), r.as<double>(), act, pd,
                          &nblk);
         fin(FIN_FCG_BETA, 2, nblk, tol2, P.cg_maxit);
@@ -1270,6 +1394,12 @@ void Ens::one_step()
     build_rhs();
     build_diag();
     tstop(t0, &pc_other, 0);
+    if (P.precision == NLTH_MIXED && inner_method == 1 &&
+        (cheb_est_age < 0 || cheb_est_age >= cheb_est_every)) {
+        cheb_estimate();
+        cheb_est_age = 0;
+    }
+    if (cheb_est_age >= 0) ++cheb_est_age;
     if (P.precision == NLTH_FP64) solve_pcg();
     else solve_fcg();
     tstart(t0);
@@ -1547,6 +1677,10 @@ int nlth_ens_set_tuning(nlth_ens* ens, const nlth_tuning* t)
         throw Error{NLTH_EINVAL, "cluster_blocks must be 0, 2, 3 or 4"};
     if ((t->scatter == 0 && !ens->fbuf.p) || (t->scatter == 2 && !ens->cbuf.p))
         throw Error{NLTH_EINVAL, "scatter: element outputs need fewer than 64 member slots, clusters 64..256"};
+    if (t->inner_method < -1 || t->inner_method > 1) throw Error{NLTH_EINVAL, "inner_method must be -1, 0 or 1"};
+    if ((t->inner_method == 1 || (t->inner_method == -1 && ens->inner_method == 1)) &&
+        (t->inner_maxit ? t->inner_maxit : ens->P.inner_maxit) > kChebMax)
+        throw Error{NLTH_EINVAL, "the Chebyshev degree (inner_maxit) must be at most 64"};
     std::lock_guard<std::mutex> g(ens->ctx->mu);
     if (t->ebe_block) ens->ebe_block = t->ebe_block;
     if (t->check_every) ens->check_every = t->check_every;
@@ -1555,10 +1689,12 @@ int nlth_ens_set_tuning(nlth_ens* ens, const nlth_tuning* t)
     if (t->inner_tol > 0) ens->P.inner_tol = t->inner_tol;
     if (t->scatter >= 0) ens->scatter = t->scatter;
     if (t->cluster_blocks > 0) ens->cluster_blocks = t->cluster_blocks;
+    if (t->inner_method >= 0) ens->inner_method = t->inner_method;
     // captured chunks hold the old launch shapes
     if (ens->g_inner) (void)hipGraphExecDestroy(ens->g_inner);
     if (ens->g_pcg) (void)hipGraphExecDestroy(ens->g_pcg);
-    ens->g_inner = ens->g_pcg = nullptr;
+    if (ens->g_cheb) (void)hipGraphExecDestroy(ens->g_cheb);
+    ens->g_inner = ens->g_pcg = ens->g_cheb = nullptr;
     return NLTH_OK;
     API_END
 }
@@ -1607,6 +1743,15 @@ int nlth_ens_stats(const nlth_ens* ens, nlth_stats* st)
     st->host_bytes = ens->host_bytes;
     st->ms_gather32 = ens->pc_gather32.ms;
     st->n_gather32 = ens->pc_gather32.n;
+    if (ens->cheb_bounds.p && ens->inner_method == 1) {
+        std::vector<double> bd((size_t)2 * ens->MB);
+        NLTH_HIP(hipMemcpy(bd.data(), ens->cheb_bounds.p, bd.size() * 8, hipMemcpyDeviceToHost));
+        st->cheb_lo_min = 1e300;
+        for (int m = 0; m < ens->nm; ++m) {
+            st->cheb_lo_min = std::min(st->cheb_lo_min, bd[m]);
+            st->cheb_hi_max = std::max(st->cheb_hi_max, bd[ens->MB + m]);
+        }
+    }
     API_END
 }
 

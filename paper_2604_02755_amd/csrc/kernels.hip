@@ -887,6 +887,103 @@ template void launch_dashpot<double>(hipStream_t, const DevMesh&, int, int, cons
 template void launch_dashpot<float>(hipStream_t, const DevMesh&, int, int, const double*, int, float,
                                     const float*, float*, const double*, const int*, double*, int*);
 
+// dashpot rows of the boundary nodes for the fused Chebyshev gather:
+// qb[(i * 3 + c) * MB + m] = (dashpot x)(boundary node i), active members only
+__global__ __launch_bounds__(256) void k_dashpot_rows(DevMesh M, int MB, int nm, const double* __restrict__ mat,
+                                                     double coef, const float* __restrict__ x,
+                                                     float* __restrict__ qb, const int* __restrict__ active)
+{
+    const int t = threadIdx.x, m = t % MB;
+    const long first = (long)blockIdx.x * (256 / MB) + t / MB, stride = (long)gridDim.x * (256 / MB);
+    if (m >= nm || (active && !active[m])) return;
+    for (long i = first; i < M.nbn; i += stride) {
+        double acc[3] = {0, 0, 0};
+        dashpot_at<float>(M, MB, m, (int)i, mat, coef, x, nullptr, acc);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) qb[((size_t)i * 3 + c) * MB + m] = (float)acc[c];
+    }
+}
+
+void launch_dashpot_rows(hipStream_t s, const DevMesh& M, int MB, int nm, const double* mat, float coef,
+                         const float* x, float* qb, const int* active)
+{
+    if (M.nbn <= 0) return;
+    const long g = ((long)M.nbn + 256 / MB - 1) / (256 / MB);  // MB <= 256 on the cluster path
+    hipLaunchKernelGGL(k_dashpot_rows, dim3(g), dim3(256), 0, s, M, MB, nm, mat, (double)coef, x, qb, active);
+}
+
+// One fused Chebyshev iteration on the cluster path (MB = 64..256): per node
+// the cluster rows are summed in ascending order (as the gather does), the
+// boundary nodes add their dashpot row, and with q = that sum
+//   iz += id,  ir -= q,  id_next = c1_k id + c2_k P ir   (no id_next on the last)
+// so the operator result never goes to memory.  Node ranges per block as in
+// the gather.
+__global__ __launch_bounds__(256) void k_gather_cheb(DevMesh M, int MB, int nm, int k, int last,
+                                                    const float* __restrict__ rows, const float* __restrict__ qb,
+                                                    float* __restrict__ iz, float* __restrict__ ir,
+                                                    const float* __restrict__ id, float* __restrict__ id_next,
+                                                    const float* __restrict__ pinv32, const float* __restrict__ cheb,
+                                                    const int* __restrict__ active)
+{
+    const int t = threadIdx.x, m = t % MB;
+    const int rpb = 256 / MB;
+    const int slot = t / MB;
+    const bool act = m < nm && (!active || active[m]);
+    if (!act) return;
+    float c1 = 0.0f, c2 = 0.0f;
+    if (!last) {
+        c1 = cheb[(long)(2 * k) * MB + m];
+        c2 = cheb[(long)(2 * k + 1) * MB + m];
+    }
+    const long per = ((M.nn + gridDim.x - 1) / gridDim.x + rpb - 1) / rpb * rpb;
+    const long n0 = (long)blockIdx.x * per, n1 = n0 + per < M.nn ? n0 + per : M.nn;
+    for (long nd = n0 + slot; nd < n1; nd += rpb) {
+        const int node = __builtin_amdgcn_readfirstlane((int)nd);
+        float a0 = 0, a1 = 0, a2 = 0;
+        const int q1 = M.cn_ptr[node + 1];
+        for (int q = M.cn_ptr[node]; q < q1; ++q) {
+            const float* fb = rows + (size_t)M.cn_row[q] * 3 * MB + m;
+            a0 += fb[0];
+            a1 += fb[MB];
+            a2 += fb[2 * MB];
+        }
+        const int bi = M.bn_of_node[node];
+        if (bi >= 0) {
+            const float* qp = qb + (size_t)bi * 3 * MB + m;
+            a0 += qp[0];
+            a1 += qp[MB];
+            a2 += qp[2 * MB];
+        }
+        const size_t yi = (size_t)node * 3 * MB + m;
+        const float d0 = id[yi], d1 = id[yi + MB], d2 = id[yi + 2 * MB];
+        iz[yi] += d0;
+        iz[yi + MB] += d1;
+        iz[yi + 2 * MB] += d2;
+        const float r0 = ir[yi] - a0, r1 = ir[yi + MB] - a1, r2 = ir[yi + 2 * MB] - a2;
+        ir[yi] = r0;
+        ir[yi + MB] = r1;
+        ir[yi + 2 * MB] = r2;
+        if (last) continue;
+        const float* pv = pinv32 + (size_t)node * 6 * MB + m;
+        const float p0 = pv[0], p1 = pv[MB], p2 = pv[2 * MB], p3 = pv[3 * MB], p4 = pv[4 * MB], p5 = pv[5 * MB];
+        const float w0 = p0 * r0 + p1 * r1 + p2 * r2;
+        const float w1 = p1 * r0 + p3 * r1 + p4 * r2;
+        const float w2 = p2 * r0 + p4 * r1 + p5 * r2;
+        id_next[yi] = c1 * d0 + c2 * w0;
+        id_next[yi + MB] = c1 * d1 + c2 * w1;
+        id_next[yi + 2 * MB] = c1 * d2 + c2 * w2;
+    }
+}
+
+void launch_gather_cheb(hipStream_t s, const DevMesh& M, int MB, int nm, int k, bool last, const float* rows,
+                        const float* qb, float* iz, float* ir, const float* id, float* id_next, const float* pinv32,
+                        const float* cheb, const int* active)
+{
+    const int g = gather_blocks(M.nn, MB, 1 << 24);
+    hipLaunchKernelGGL(k_gather_cheb, dim3(g), dim3(256), 0, s, M, MB, nm, k, (int)last, rows, qb, iz, ir, id, id_next,
+                       pinv32, cheb, active);
+}
+
 // ---------------------------------------------------------------------------
 // 3x3 block-Jacobi preconditioner (Section 2.2): diagonal blocks of A
 // ---------------------------------------------------------------------------

@@ -152,7 +152,14 @@ struct CgScalars {  // per member [MB] device arrays
     int *active, *iters, *status, *stepping;  // stepping: member takes part in this step
     int *inner_active, *inner_iters, *inner_total;
     double *irr, *irz, *ialpha, *ibeta, *ir0;
+    double* lz;  // inner CG coefficients: alpha_k at [k * MB + m], beta_k at [(kLanczosMax + k) * MB + m]
 };
+
+// inner CG iterations whose coefficients are kept for the spectrum estimate
+constexpr int kLanczosMax = 64;
+// Chebyshev degree limit; coefficient table cheb[(2 k + 0/1) * MB + m] =
+// (c1_k, c2_k), k < kChebMax, and cheb[2 kChebMax * MB + m] = c0
+constexpr int kChebMax = 64;
 
 enum FinalizeStage {
     FIN_START = 0,   // (b.b, r.r, r.z): PCG start, active flags
@@ -164,7 +171,9 @@ enum FinalizeStage {
     FIN_FCG_RR,      // (r.r): outer convergence check
     FIN_IN_START,    // (ir.ir, ir.w) inner start
     FIN_IN_ALPHA,    // (ip.iAp) inner alpha
-    FIN_IN_BETA      // (ir.ir, ir.w) inner convergence, beta
+    FIN_IN_BETA,     // (ir.ir, ir.w) inner convergence, beta
+    FIN_CHEB_COUNT,  // (-): inner_total += degree for the outer-active members
+    FIN_EST_START    // (ir.ir, ir.w) inner CG start on a random vector, for the members in this step
 };
 void launch_finalize(hipStream_t s, FinalizeStage st, int nd, int MB, int nm, const double* partial, int nblk,
                      CgScalars cs, double tol2, int maxit);
@@ -187,6 +196,22 @@ void launch_inner_update(hipStream_t s, int nn, int MB, int nm, float* iz, float
 void launch_inner_out(hipStream_t s, long nrows, int MB, int nm, const float* iz, double* z, const double* Ap,
                       const double* r, const int* active, double* partial, int* nblk);
 void launch_zero_if_b0(hipStream_t s, long nrows, int MB, int nm, double* x, const double* bb, const int* stepping);
+
+// Chebyshev inner solve (preconditioner of the outer flexible CG)
+void launch_cheb_bounds(hipStream_t s, int MB, int nm, CgScalars cs, int degree, double lo_scale, double hi_scale,
+                        float* cheb, double* bounds);
+void launch_cheb_hi_estimate(hipStream_t s, int MB, int nm, CgScalars cs, double scale, double* bounds);
+void launch_fill_random(hipStream_t s, double* x, long n, uint64_t seed);
+void launch_cheb_start(hipStream_t s, int nn, int MB, int nm, const double* r, const float* pinv32,
+                       const float* cheb, float* ir, float* iz, float* id, const int* active);
+void launch_cheb_update(hipStream_t s, int nn, int MB, int nm, int k, bool last, float* iz, float* ir,
+                        const float* id, const float* iAp, float* id_next, const float* pinv32, const float* cheb,
+                        const int* active);
+void launch_dashpot_rows(hipStream_t s, const DevMesh& M, int MB, int nm, const double* mat, float coef,
+                         const float* x, float* qb, const int* active);
+void launch_gather_cheb(hipStream_t s, const DevMesh& M, int MB, int nm, int k, bool last, const float* rows,
+                        const float* qb, float* iz, float* ir, const float* id, float* id_next, const float* pinv32,
+                        const float* cheb, const int* active);
 
 // Newmark state updates (Section 2.1) and receivers
 void launch_newmark(hipStream_t s, long n, int MB, int nm, const double* du, double* u, double* v,

@@ -98,6 +98,12 @@ struct Ens {
     DevBuf mat, dirs, w, nonlinear, acc, vI_all, vI_cur;
     DevBuf u, v, a, q, du, b, r, z, p, Ap, diag, pinv, pinv32;
     DevBuf ir, iz, ip, iw, iAp;
+    DevBuf lz, chebc, cheb_bounds, qb;  // inner CG coefficients, Chebyshev table and bounds, dashpot rows
+    int inner_method = 0;               // 0: inner CG; 1: Chebyshev after one inner CG per step
+    double cheb_lo = 1.0, cheb_hi = 1.05;  // scales of the Lanczos extreme eigenvalues of a step's first inner CG
+    double cheb_est_scale = 1.1;           // scale of the random-start estimate of the largest eigenvalue
+    int cheb_est_iters = 20, cheb_est_every = 32, cheb_est_age = -1;  // -1: no estimate yet
+    int est_iters = 0;                  // estimate iterations of this step, not yet counted
     DevBuf D64, D32, D16, h;             // D16: bfloat16 pairs for the inner operator
     bool d16_mean = false;              // inner D: one bfloat16 D per element (the mean over its points)
     DevBuf fbuf;                        // element outputs of the gather path (FP64 or FP32)
@@ -147,6 +153,9 @@ struct Ens {
     void solve_pcg();
     void solve_fcg();
     void inner_solve();
+    void cheb_solve();
+    void cheb_estimate();
+    void cheb_body();
     void law_phase();
     void prefetch_next();
     // helpers
@@ -157,7 +166,7 @@ struct Ens {
     void pcg_iter();
     void run_iters(int kind, int k);
     bool use_graph = true;
-    hipGraphExec_t g_inner = nullptr, g_pcg = nullptr;
+    hipGraphExec_t g_inner = nullptr, g_pcg = nullptr, g_cheb = nullptr;
     int ebe_block = 256;
     int cluster_blocks = 3;             // co-resident cluster blocks per CU
     void fin(FinalizeStage st, int nd, int nblk, double tol2, int maxit);

@@ -552,11 +552,282 @@ void launch_inner_out(hipStream_t s, long nrows, int MB, int nm, const float* iz
 }
 
 // ---------------------------------------------------------------------------
+// Chebyshev inner solve: A z = r by the Chebyshev iteration on the block-
+// Jacobi preconditioned operator (Saad, Iterative Methods for Sparse Linear
+// Systems, 2nd ed., Algorithm 12.1), with the spectrum bounds of each member
+// taken from the Lanczos matrix of an inner CG solve of the same step.  It
+// needs no inner products, so an iteration is the operator plus one update.
+// ---------------------------------------------------------------------------
+
+// eigenvalues of the Lanczos tridiagonal below x (Sturm count); T from the CG
+// coefficients: T_00 = 1/a_0, T_ii = 1/a_i + b_{i-1}/a_{i-1}, T_{i,i+1}^2 = b_i/a_i^2
+__device__ int lanczos_count(const double* __restrict__ lz, int MB, int m, int n, double x)
+{
+    int cnt = 0;
+    double q = 1.0;
+    for (int i = 0; i < n; ++i) {
+        const double ai = lz[(long)i * MB + m];
+        double diag = 1.0 / ai;
+        double off2 = 0.0;
+        if (i > 0) {
+            const double ap = lz[(long)(i - 1) * MB + m], bp = lz[(long)(kLanczosMax + i - 1) * MB + m];
+            diag += bp / ap;
+            off2 = bp / (ap * ap);
+        }
+        q = diag - x - (i > 0 ? off2 / q : 0.0);
+        if (q == 0.0) q = -1e-300;
+        if (q < 0.0) ++cnt;
+    }
+    return cnt;
+}
+
+// Ritz extremes of member m's Lanczos matrix (0, 0 without coefficients)
+__device__ void lanczos_extremes(const CgScalars& cs, int MB, int m, double* lmin, double* lmax)
+{
+    const int n = cs.inner_iters[m] < kLanczosMax ? cs.inner_iters[m] : kLanczosMax;
+    *lmin = *lmax = 0.0;
+    if (n <= 0) return;
+    // Gershgorin interval of T, then bisection on the Sturm count
+    double g0 = 1e300, g1 = -1e300;
+    for (int i = 0; i < n; ++i) {
+        const double ai = cs.lz[(long)i * MB + m];
+        double diag = 1.0 / ai, rad = 0.0;
+        if (i > 0) {
+            const double ap = cs.lz[(long)(i - 1) * MB + m], bp = cs.lz[(long)(kLanczosMax + i - 1) * MB + m];
+            diag += bp / ap;
+            rad += sqrt(fabs(bp)) / fabs(ap);
+        }
+        if (i + 1 < n) rad += sqrt(fabs(cs.lz[(long)(kLanczosMax + i) * MB + m])) / fabs(ai);
+        g0 = fmin(g0, diag - rad);
+        g1 = fmax(g1, diag + rad);
+    }
+    if (!(g1 > g0)) return;  // non-finite coefficients
+    double a = g0, b = g1;  // smallest: count(a) = 0, count(b) >= 1
+    for (int it = 0; it < 200 && b - a > 1e-12 * fabs(b); ++it) {
+        const double x = 0.5 * (a + b);
+        if (lanczos_count(cs.lz, MB, m, n, x) >= 1) b = x;
+        else a = x;
+    }
+    *lmin = 0.5 * (a + b);
+    a = g0; b = g1;  // largest: count(a) < n, count(b) = n
+    for (int it = 0; it < 200 && b - a > 1e-12 * fabs(b); ++it) {
+        const double x = 0.5 * (a + b);
+        if (lanczos_count(cs.lz, MB, m, n, x) >= n) b = x;
+        else a = x;
+    }
+    *lmax = 0.5 * (a + b);
+}
+
+// One block.  Lower bound per member: its smallest Ritz value (x lo_scale).
+// Upper bound shared by the members and never lowered: hi_scale x the
+// largest Ritz value over the members and the steps so far (bounds[2 MB]).
+// A Ritz value lies inside the spectrum, so the largest one can fall short
+// of the true largest eigenvalue when a member's residual has little weight
+// there, and Chebyshev amplifies the components above the upper bound; the
+// members share the mesh, whose consistent mass sets the top of the spectrum.
+__global__ __launch_bounds__(256) void k_cheb_bounds(int MB, int nm, CgScalars cs, int degree, double lo_scale,
+                                                    double hi_scale, float* __restrict__ cheb,
+                                                    double* __restrict__ bounds)
+{
+    __shared__ double smax[256];
+    const int t = threadIdx.x;
+    double mx = 0.0;
+    for (int m = t; m < nm; m += 256) {
+        double lmin, lmax;
+        lanczos_extremes(cs, MB, m, &lmin, &lmax);
+        if (lmax > 0.0 && isfinite(lmax)) mx = fmax(mx, lmax);
+        bounds[m] = (lmin > 0.0 && isfinite(lmin) && lmin < lmax) ? lmin * lo_scale : 0.0;
+    }
+    smax[t] = mx;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (t < s) smax[t] = fmax(smax[t], smax[t + s]);
+        __syncthreads();
+    }
+    const double hi = fmax(smax[0] * hi_scale, bounds[2 * MB]);
+    __syncthreads();
+    if (t == 0) bounds[2 * MB] = hi;
+    if (!(hi > 0.0)) return;
+    for (int m = t; m < nm; m += 256) {
+        double lo = bounds[m];
+        if (!(lo > 0.0) || lo > 0.99 * hi) lo = 0.01 * hi;  // no usable estimate
+        bounds[m] = lo;
+        bounds[MB + m] = hi;
+        const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+        double rho = 1.0 / sigma;
+        for (int k = 0; k < degree && k < kChebMax; ++k) {
+            const double rn = 1.0 / (2.0 * sigma - rho);
+            cheb[(long)(2 * k) * MB + m] = (float)(rn * rho);
+            cheb[(long)(2 * k + 1) * MB + m] = (float)(2.0 * rn / delta);
+            rho = rn;
+        }
+        cheb[(long)(2 * kChebMax) * MB + m] = (float)(1.0 / theta);
+    }
+}
+
+void launch_cheb_bounds(hipStream_t s, int MB, int nm, CgScalars cs, int degree, double lo_scale, double hi_scale,
+                        float* cheb, double* bounds)
+{
+    hipLaunchKernelGGL(k_cheb_bounds, dim3(1), dim3(256), 0, s, MB, nm, cs, degree, lo_scale, hi_scale, cheb, bounds);
+}
+
+// Upper spectrum bound from inner CG iterations on a random right-hand side
+// (which weights every eigenvector): bounds[2 MB] = max(bounds[2 MB], scale x
+// the largest Ritz value over the members).
+__global__ __launch_bounds__(256) void k_cheb_hi_estimate(int MB, int nm, CgScalars cs, double scale,
+                                                         double* __restrict__ bounds)
+{
+    __shared__ double smax[256];
+    const int t = threadIdx.x;
+    double mx = 0.0;
+    for (int m = t; m < nm; m += 256) {
+        double lmin, lmax;
+        lanczos_extremes(cs, MB, m, &lmin, &lmax);
+        if (lmax > 0.0 && isfinite(lmax)) mx = fmax(mx, lmax);
+    }
+    smax[t] = mx;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (t < s) smax[t] = fmax(smax[t], smax[t + s]);
+        __syncthreads();
+    }
+    if (t == 0) bounds[2 * MB] = fmax(bounds[2 * MB], smax[0] * scale);
+}
+
+void launch_cheb_hi_estimate(hipStream_t s, int MB, int nm, CgScalars cs, double scale, double* bounds)
+{
+    hipLaunchKernelGGL(k_cheb_hi_estimate, dim3(1), dim3(256), 0, s, MB, nm, cs, scale, bounds);
+}
+
+// x[i] uniform in [-1, 1) from the SplitMix64 sequence (Steele, Lea, Flood,
+// OOPSLA 2014) at counter seed + i
+__global__ void k_fill_random(double* __restrict__ x, long n, uint64_t seed)
+{
+    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint64_t z = seed + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    x[i] = (double)(z >> 11) * 0x1.0p-52 - 1.0;
+}
+
+void launch_fill_random(hipStream_t s, double* x, long n, uint64_t seed)
+{
+    if (n > 0) hipLaunchKernelGGL(k_fill_random, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n, seed);
+}
+
+// start: ir = r, iz = 0, id = c0 P ir (members outside active: zeros)
+template <int VEC>
+__global__ __launch_bounds__(256) void k_cheb_start(int nn, int MB, int nm, const double* __restrict__ r,
+                                                   const float* __restrict__ pinv32, const float* __restrict__ cheb,
+                                                   float* __restrict__ ir, float* __restrict__ iz,
+                                                   float* __restrict__ id, const int* __restrict__ active)
+{
+    const int QB = MB / VEC, npb = 256 / QB;
+    const int t = threadIdx.x, q = t % QB, m0 = q * VEC;
+    bool act[4];
+    if (!member_mask(active, m0, VEC, nm, act)) return;
+    float c0[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) c0[v] = cheb[(long)(2 * kChebMax) * MB + m0 + v];
+    Pk<float, VEC> zero;
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) zero.a[v] = 0.0f;
+    for (long node = (long)blockIdx.x * npb + t / QB; node < nn; node += (long)gridDim.x * npb) {
+        Pk<float, VEC> R[3], W[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const Pk<double, VEC> Rd = ld<double, VEC>(r + (node * 3 + c) * MB + m0);
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) R[c].a[v] = act[v] ? (float)Rd.a[v] : 0.0f;
+        }
+        pinv_apply<float, VEC>(pinv32, node, MB, m0, R, W);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const long i = (node * 3 + c) * MB + m0;
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) W[c].a[v] *= c0[v];
+            st<float, VEC>(ir + i, R[c]);
+            st<float, VEC>(iz + i, zero);
+            st<float, VEC>(id + i, W[c]);
+        }
+    }
+}
+
+void launch_cheb_start(hipStream_t s, int nn, int MB, int nm, const double* r, const float* pinv32,
+                       const float* cheb, float* ir, float* iz, float* id, const int* active)
+{
+    const int VEC = vec_of(MB), QB = MB / VEC;
+    const int g = grid_for(nn, 256 / QB);
+    if (VEC == 4) hipLaunchKernelGGL((k_cheb_start<4>), dim3(g), dim3(256), 0, s, nn, MB, nm, r, pinv32, cheb, ir, iz, id, active);
+    else hipLaunchKernelGGL((k_cheb_start<1>), dim3(g), dim3(256), 0, s, nn, MB, nm, r, pinv32, cheb, ir, iz, id, active);
+}
+
+// iteration k after iAp = A id: iz += id, ir -= iAp, id_next = c1_k id + c2_k P ir
+// (id_next is not formed on the last iteration)
+template <int VEC>
+__global__ __launch_bounds__(256) void k_cheb_update(int nn, int MB, int nm, int k, bool last, float* __restrict__ iz,
+                                                    float* __restrict__ ir, const float* __restrict__ id,
+                                                    const float* __restrict__ iAp, float* __restrict__ id_next,
+                                                    const float* __restrict__ pinv32, const float* __restrict__ cheb,
+                                                    const int* __restrict__ active)
+{
+    const int QB = MB / VEC, npb = 256 / QB;
+    const int t = threadIdx.x, q = t % QB, m0 = q * VEC;
+    bool act[4];
+    if (!member_mask(active, m0, VEC, nm, act)) return;
+    float c1[VEC], c2[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+        c1[v] = cheb[(long)(2 * k) * MB + m0 + v];
+        c2[v] = cheb[(long)(2 * k + 1) * MB + m0 + v];
+    }
+    for (long node = (long)blockIdx.x * npb + t / QB; node < nn; node += (long)gridDim.x * npb) {
+        Pk<float, VEC> R[3], D[3], W[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const long i = (node * 3 + c) * MB + m0;
+            Pk<float, VEC> Z = ld<float, VEC>(iz + i);
+            D[c] = ld<float, VEC>(id + i);
+            const Pk<float, VEC> A = ld<float, VEC>(iAp + i);
+            R[c] = ld<float, VEC>(ir + i);
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) {
+                if (!act[v]) continue;
+                Z.a[v] += D[c].a[v];
+                R[c].a[v] -= A.a[v];
+            }
+            st<float, VEC>(iz + i, Z);
+            st<float, VEC>(ir + i, R[c]);
+        }
+        if (last) continue;
+        pinv_apply<float, VEC>(pinv32, node, MB, m0, R, W);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) W[c].a[v] = act[v] ? c1[v] * D[c].a[v] + c2[v] * W[c].a[v] : 0.0f;
+            st<float, VEC>(id_next + (node * 3 + c) * MB + m0, W[c]);
+        }
+    }
+}
+
+void launch_cheb_update(hipStream_t s, int nn, int MB, int nm, int k, bool last, float* iz, float* ir,
+                        const float* id, const float* iAp, float* id_next, const float* pinv32, const float* cheb,
+                        const int* active)
+{
+    const int VEC = vec_of(MB), QB = MB / VEC;
+    const int g = grid_for(nn, 256 / QB);
+    if (VEC == 4) hipLaunchKernelGGL((k_cheb_update<4>), dim3(g), dim3(256), 0, s, nn, MB, nm, k, last, iz, ir, id, iAp, id_next, pinv32, cheb, active);
+    else hipLaunchKernelGGL((k_cheb_update<1>), dim3(g), dim3(256), 0, s, nn, MB, nm, k, last, iz, ir, id, iAp, id_next, pinv32, cheb, active);
+}
+
+// ---------------------------------------------------------------------------
 // per-member scalar logic: one block per member reduces its partials by a
 // fixed tree, then thread 0 applies the stage
 // ---------------------------------------------------------------------------
 
-__device__ void stage_logic(int stage, int m, const double S[3], CgScalars& cs, double tol2, int maxit)
+__device__ void stage_logic(int stage, int m, int MB, const double S[3], CgScalars& cs, double tol2, int maxit)
 {
     switch (stage) {
     case FIN_START:  // S = (b.b, r.r, r.z)
@@ -617,6 +888,8 @@ __device__ void stage_logic(int stage, int m, const double S[3], CgScalars& cs, 
         break;
     case FIN_IN_ALPHA:  // S = (ip.iAp)
         cs.ialpha[m] = cs.inner_active[m] ? cs.irz[m] / S[0] : 0.0;
+        if (cs.inner_active[m] && cs.inner_iters[m] < kLanczosMax)
+            cs.lz[(long)cs.inner_iters[m] * MB + m] = cs.ialpha[m];
         break;
     case FIN_IN_BETA:  // S = (ir.ir, ir.w)
         if (cs.inner_active[m]) {
@@ -627,8 +900,19 @@ __device__ void stage_logic(int stage, int m, const double S[3], CgScalars& cs, 
             } else {
                 cs.ibeta[m] = S[1] / cs.irz[m];
                 cs.irz[m] = S[1];
+                if (cs.inner_iters[m] <= kLanczosMax)
+                    cs.lz[(long)(kLanczosMax + cs.inner_iters[m] - 1) * MB + m] = cs.ibeta[m];
             }
         }
+        break;
+    case FIN_CHEB_COUNT:  // maxit = the Chebyshev degree
+        if (cs.active[m]) cs.inner_total[m] += maxit;
+        break;
+    case FIN_EST_START:  // S = (ir.ir, ir.w)
+        cs.ir0[m] = S[0];
+        cs.irz[m] = S[1];
+        cs.inner_iters[m] = 0;
+        cs.inner_active[m] = cs.stepping[m] && S[0] > 0.0;
         break;
     }
 }
@@ -654,7 +938,7 @@ __global__ __launch_bounds__(256) void k_finalize(int stage, int nd, int MB, int
     }
     if (t == 0) {
         double S[3] = {sh[0][0], sh[1][0], sh[2][0]};
-        stage_logic(stage, m, S, cs, tol2, maxit);
+        stage_logic(stage, m, MB, S, cs, tol2, maxit);
     }
 }
 

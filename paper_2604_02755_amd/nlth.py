@@ -31,6 +31,7 @@ NLTH_ETIMEDOUT = -8
 NLTH_ENOTFOUND = -9
 NLTH_FP64, NLTH_MIXED = 0, 1
 NLTH_INNER_BF16, NLTH_INNER_FP32, NLTH_INNER_BF16_MEAN = 0, 1, 2
+INNER_CG, INNER_CHEBYSHEV = 0, 1  # nlth_tuning.inner_method
 NLTH_OP_A, NLTH_OP_K, NLTH_OP_M = 0, 1, 2
 NLTH_DEVICE_NONE = -1
 
@@ -69,7 +70,7 @@ class nlth_problem(C.Structure):
 class nlth_tuning(C.Structure):
     _fields_ = [("ebe_block", C.c_int32), ("check_every", C.c_int32), ("use_graph", C.c_int32),
                 ("inner_maxit", C.c_int32), ("inner_tol", C.c_double), ("scatter", C.c_int32),
-                ("cluster_blocks", C.c_int32)]
+                ("cluster_blocks", C.c_int32), ("inner_method", C.c_int32)]
 
 
 class nlth_result(C.Structure):
@@ -85,7 +86,7 @@ class nlth_stats(C.Structure):
                 ("h2d_bytes", C.c_int64), ("d2h_bytes", C.c_int64), ("ms_copy", C.c_double),
                 ("n_members", C.c_int32), ("members_padded", C.c_int32), ("n_colors", C.c_int32),
                 ("device_bytes", C.c_int64), ("host_bytes", C.c_int64), ("ms_gather32", C.c_double),
-                ("n_gather32", C.c_int64)]
+                ("n_gather32", C.c_int64), ("cheb_lo_min", C.c_double), ("cheb_hi_max", C.c_double)]
 
 
 EXPORTS = {
@@ -309,9 +310,9 @@ class Ensemble:
         lib().nlth_ens_reset_stats(self.h)
 
     def set_tuning(self, ebe_block=0, check_every=0, use_graph=-1, inner_maxit=0, inner_tol=0.0, scatter=-1,
-                   cluster_blocks=0):
+                   cluster_blocks=0, inner_method=-1):
         t = nlth_tuning(int(ebe_block), int(check_every), int(use_graph), int(inner_maxit), float(inner_tol),
-                        int(scatter), int(cluster_blocks))
+                        int(scatter), int(cluster_blocks), int(inner_method))
         return _check(lib().nlth_ens_set_tuning(self.h, C.byref(t)), self.ctx)
 
     def close(self):

@@ -230,7 +230,8 @@ def test_autotuned_run_matches_fp64(gpu_ctx):
         done = ens.stats()["steps_done"]
         say("autotune choice", {k: choice[k] for k in ("inner_tol", "inner_maxit", "ebe_block", "check_every")},
             "after", done, "steps")
-        assert done == len(choice["trials"]) == autotune.trial_steps(pm) and done < pm.n_steps
+        # every timed trial is one step, plus one untimed step for the Chebyshev estimate
+        assert done == autotune.trial_steps(pm) == len(choice["trials"]) + 1 and done < pm.n_steps
         ens.step(pm.n_steps - done)
         om = ens.read()
     finally:
@@ -274,3 +275,70 @@ def test_cluster_path_64_members(gpu_ctx, oracle_lib, precision):
         err = oracle_lib.rel_l2(cl["vel"][m], vref)
         say("  member", m, "vs oracle", err)
         assert err < 1e-9
+
+
+def test_chebyshev_inner_matches_oracle(gpu_ctx, oracle_lib, nlth_mod):
+    """Inner Chebyshev iteration (bounds from the step's first inner CG): the
+    outer FP64 flexible CG still converges to its tolerance, so members match
+    the oracle; the fused cluster-gather update (64 slots) and the separate
+    update (colour path, and fewer than 64 slots) agree."""
+    mesh, prob = _small_problem(precision=1, n_members=64, n_steps=24, dims=(6, 5, 3), ns=12, tol=1e-12)
+    vs, gr = I.ensemble_members(91, 64, I.CFG0_LAYERS["vs"])
+    prob.vs = vs
+    prob.gamma_ref = np.tile(gr[:, None], (1, 2))
+    prob.input_acc = 5.0 * I.member_waves(2, range(64), prob.n_steps, prob.dt)
+    mh = gpu_ctx.mesh(mesh)
+
+    def run(p, **kw):
+        ens = gpu_ctx.ensemble(mh, mesh, p)
+        try:
+            ens.set_tuning(**kw)
+            ens.step(p.n_steps)
+            return ens.read()
+        finally:
+            ens.close()
+
+    say("chebyshev inner, 64 members (fused cluster gather) and colour path")
+    cg = run(prob, inner_maxit=16, inner_tol=1e-12, inner_method=0)
+    ch = run(prob, inner_maxit=16, inner_tol=1e-12, inner_method=1)
+    chc = run(prob, inner_maxit=16, inner_tol=1e-12, inner_method=1, scatter=1)
+    ens = gpu_ctx.ensemble(mh, mesh, prob)
+    try:
+        ens.set_tuning(inner_maxit=16, inner_tol=1e-12, inner_method=1)
+        ens.step(3)
+        st = ens.stats()
+        say("  Chebyshev interval after 3 steps", st["cheb_lo_min"], st["cheb_hi_max"])
+        assert 0 < st["cheb_lo_min"] < st["cheb_hi_max"] < 100
+    finally:
+        ens.close()
+    o_cg, o_ch = cg["iters"][:, :, 0].mean(), ch["iters"][:, :, 0].mean()
+    say("  outer iterations per member-step: CG inner", o_cg, "Chebyshev inner", o_ch)
+    assert o_ch <= 1.5 * o_cg
+    d = float(np.max(np.abs(ch["vel"] - chc["vel"])) / np.max(np.abs(chc["vel"])))
+    say("  fused vs separate update max rel diff", d)
+    assert d < 1e-9
+    for m in (0, 37, 63):
+        vref, _ = _oracle_vel(oracle_lib, mesh, prob, m)
+        err = oracle_lib.rel_l2(ch["vel"][m], vref)
+        say("  member", m, "vs oracle", err)
+        assert err < 1e-9
+    # fewer than 64 slots (element outputs + gather, separate update), at the
+    # throughput tolerance against the plain FP64 path
+    mesh2, p8 = _small_problem(precision=1, n_members=2, tol=1e-8)
+    _, p64 = _small_problem(precision=0, n_members=2, tol=1e-8)
+    mh2 = gpu_ctx.mesh(mesh2)
+    ens = gpu_ctx.ensemble(mh2, mesh2, p8)
+    try:
+        ens.set_tuning(inner_maxit=12, inner_tol=1e-12, inner_method=1)
+        ens.step(p8.n_steps)
+        om = ens.read()
+        with pytest.raises(nlth_mod.NlthError) as ei:
+            ens.set_tuning(inner_maxit=65, inner_method=1)
+        assert ei.value.code == nlth_mod.NLTH_EINVAL
+    finally:
+        ens.close()
+    o64 = gpu_ctx.solve(mh2, mesh2, p64)
+    for m in range(2):
+        err = oracle_lib.rel_l2(om["vel"][m], o64["vel"][m])
+        say("  2 members, member", m, "chebyshev mixed vs fp64 at 1e-8", err)
+        assert err < 1e-6
