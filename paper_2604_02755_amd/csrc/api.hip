@@ -890,7 +890,7 @@ void Ens::create(Ctx* c, const Mesh* m, const Problem& prob, int member_pad)
     cs.ialpha = dptr + 9 * MB; cs.ibeta = dptr + 10 * MB; cs.ir0 = dptr + 11 * MB;
     int* iptr = (int*)(dptr + 12 * MB);
     cs.active = iptr; cs.iters = iptr + MB; cs.status = iptr + 2 * MB; cs.inner_active = iptr + 3 * MB;
-    cs.inner_iters = iptr + 4 * MB; cs.inner_total = iptr + 5 * MB;
+    cs.inner_iters = iptr + 4 * MB; cs.inner_total = iptr + 5 * MB; cs.inner_upd = iptr + 6 * MB;
     cs.lz = lz.as<double>();
     NLTH_HIP(hipHostMalloc((void**)&h_flags, sizeof(int) * MB, hipHostMallocDefault));
     member_step.alloc(bg, (size_t)MB * 4);
@@ -1219,10 +1219,10 @@ void Ens::inner_iter()
     double* pd = partial.as<double>();
     ebe32(ip.as<float>(), iAp.as<float>(), iact, &nblk);
     fin(FIN_IN_ALPHA, 1, nblk, tol2, P.inner_maxit);
-    launch_inner_update(s, mesh->nn, MB, nm, iz.as<float>(), ir.as<float>(), iw.as<float>(), ip.as<float>(),
-                        iAp.as<float>(), pinv32.as<float>(), cs.ialpha, iact, pd, &nblk);
+    launch_inner_update(s, mesh->nn, MB, nm, ir.as<float>(), iw.as<float>(), iAp.as<float>(), pinv32.as<float>(),
+                        cs.ialpha, iact, pd, &nblk);
     fin(FIN_IN_BETA, 2, nblk, tol2, P.inner_maxit);
-    launch_p_update<float>(s, n, MB, nm, iw.as<float>(), ip.as<float>(), cs.ibeta, iact, nullptr);
+    launch_inner_pz(s, n, MB, nm, iz.as<float>(), ip.as<float>(), iw.as<float>(), cs.ialpha, cs.ibeta, cs.inner_upd);
 }
 
 // one FP64 block-Jacobi PCG iteration

@@ -151,6 +151,7 @@ struct CgScalars {  // per member [MB] device arrays
     double *bb, *rr, *rz, *alpha, *beta, *pAp, *r0;
     int *active, *iters, *status, *stepping;  // stepping: member takes part in this step
     int *inner_active, *inner_iters, *inner_total;
+    int* inner_upd;  // members whose inner alpha was formed this iteration (their iz, ip still update)
     double *irr, *irz, *ialpha, *ibeta, *ir0;
     double* lz;  // inner CG coefficients: alpha_k at [k * MB + m], beta_k at [(kLanczosMax + k) * MB + m]
 };
@@ -190,9 +191,10 @@ void launch_xr_update(hipStream_t s, long nrows, int MB, int nm, double* x, doub
                       const double* alpha, const int* active, double* partial, int* nblk);
 void launch_inner_start(hipStream_t s, int nn, int MB, int nm, const double* r, const float* pinv32, float* ir,
                         float* iz, float* ip, float* w, float* iAp, const int* active, double* partial, int* nblk);
-void launch_inner_update(hipStream_t s, int nn, int MB, int nm, float* iz, float* ir, float* w, const float* ip,
-                         const float* iAp, const float* pinv32, const double* ialpha, const int* iactive,
-                         double* partial, int* nblk);
+void launch_inner_update(hipStream_t s, int nn, int MB, int nm, float* ir, float* w, const float* iAp,
+                         const float* pinv32, const double* ialpha, const int* iactive, double* partial, int* nblk);
+void launch_inner_pz(hipStream_t s, long nrows, int MB, int nm, float* iz, float* ip, const float* w,
+                     const double* ialpha, const double* ibeta, const int* upd);
 void launch_inner_out(hipStream_t s, long nrows, int MB, int nm, const float* iz, double* z, const double* Ap,
                       const double* r, const int* active, double* partial, int* nblk);
 void launch_zero_if_b0(hipStream_t s, long nrows, int MB, int nm, double* x, const double* bb, const int* stepping);

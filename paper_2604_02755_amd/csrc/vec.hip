@@ -445,11 +445,11 @@ void launch_inner_start(hipStream_t s, int nn, int MB, int nm, const double* r, 
     else hipLaunchKernelGGL((k_inner_start<1>), dim3(g), dim3(256), 0, s, nn, MB, nm, r, pinv32, ir, iz, ip, w, iAp, active, partial);
 }
 
-// inner: iz += a ip, ir -= a iAp, w = P ir; partials (ir.ir, ir.w)
+// inner: ir -= a iAp, w = P ir; partials (ir.ir, ir.w).  (iz += a ip is
+// done with the p update, which reads ip anyway: 4 B less per DOF.)
 template <int VEC>
-__global__ __launch_bounds__(256) void k_inner_update(int nn, int MB, int nm, float* __restrict__ iz,
-                                                     float* __restrict__ ir, float* __restrict__ w,
-                                                     const float* __restrict__ ip, const float* __restrict__ iAp,
+__global__ __launch_bounds__(256) void k_inner_update(int nn, int MB, int nm, float* __restrict__ ir,
+                                                     float* __restrict__ w, const float* __restrict__ iAp,
                                                      const float* __restrict__ pinv32,
                                                      const double* __restrict__ ialpha,
                                                      const int* __restrict__ iactive, double* __restrict__ partial)
@@ -471,15 +471,10 @@ __global__ __launch_bounds__(256) void k_inner_update(int nn, int MB, int nm, fl
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const long i = (node * 3 + c) * MB + m0;
-                Pk<float, VEC> Z = ld<float, VEC>(iz + i);
-                const Pk<float, VEC> P = ld<float, VEC>(ip + i), A = ld<float, VEC>(iAp + i);
+                const Pk<float, VEC> A = ld<float, VEC>(iAp + i);
                 R[c] = ld<float, VEC>(ir + i);
 #pragma unroll
-                for (int v = 0; v < VEC; ++v) {
-                    Z.a[v] += al[v] * P.a[v];
-                    R[c].a[v] -= al[v] * A.a[v];
-                }
-                st<float, VEC>(iz + i, Z);
+                for (int v = 0; v < VEC; ++v) R[c].a[v] -= al[v] * A.a[v];
                 st<float, VEC>(ir + i, R[c]);
             }
             pinv_apply<float, VEC>(pinv32, node, MB, m0, R, W);
@@ -497,15 +492,57 @@ __global__ __launch_bounds__(256) void k_inner_update(int nn, int MB, int nm, fl
     block_partials<2, VEC>(acc, QB, MB, partial);
 }
 
-void launch_inner_update(hipStream_t s, int nn, int MB, int nm, float* iz, float* ir, float* w, const float* ip,
-                         const float* iAp, const float* pinv32, const double* ialpha, const int* iactive,
-                         double* partial, int* nblk)
+void launch_inner_update(hipStream_t s, int nn, int MB, int nm, float* ir, float* w, const float* iAp,
+                         const float* pinv32, const double* ialpha, const int* iactive, double* partial, int* nblk)
 {
     const int VEC = vec_of(MB), QB = MB / VEC;
     const int g = grid_for(nn, 256 / QB);
     *nblk = g;
-    if (VEC == 4) hipLaunchKernelGGL((k_inner_update<4>), dim3(g), dim3(256), 0, s, nn, MB, nm, iz, ir, w, ip, iAp, pinv32, ialpha, iactive, partial);
-    else hipLaunchKernelGGL((k_inner_update<1>), dim3(g), dim3(256), 0, s, nn, MB, nm, iz, ir, w, ip, iAp, pinv32, ialpha, iactive, partial);
+    if (VEC == 4) hipLaunchKernelGGL((k_inner_update<4>), dim3(g), dim3(256), 0, s, nn, MB, nm, ir, w, iAp, pinv32, ialpha, iactive, partial);
+    else hipLaunchKernelGGL((k_inner_update<1>), dim3(g), dim3(256), 0, s, nn, MB, nm, ir, w, iAp, pinv32, ialpha, iactive, partial);
+}
+
+// inner: iz += a ip (with this iteration's ip), then ip = w + b ip, for the
+// members whose alpha was formed this iteration (upd); a member that has just
+// converged takes its last iz update, and its ip is not used again
+template <int VEC>
+__global__ __launch_bounds__(256) void k_inner_pz(long nrows, int MB, int nm, float* __restrict__ iz,
+                                                 float* __restrict__ ip, const float* __restrict__ w,
+                                                 const double* __restrict__ ialpha, const double* __restrict__ ibeta,
+                                                 const int* __restrict__ upd)
+{
+    const int QB = MB / VEC, rpb = 256 / QB;
+    const int t = threadIdx.x, q = t % QB, m0 = q * VEC;
+    bool act[4];
+    if (!member_mask(upd, m0, VEC, nm, act)) return;
+    float al[VEC], be[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+        al[v] = act[v] ? (float)ialpha[m0 + v] : 0.0f;
+        be[v] = act[v] ? (float)ibeta[m0 + v] : 0.0f;
+    }
+    for (long row = (long)blockIdx.x * rpb + t / QB; row < nrows; row += (long)gridDim.x * rpb) {
+        const long i = row * MB + m0;
+        Pk<float, VEC> Z = ld<float, VEC>(iz + i), P = ld<float, VEC>(ip + i);
+        const Pk<float, VEC> W = ld<float, VEC>(w + i);
+#pragma unroll
+        for (int v = 0; v < VEC; ++v)
+            if (act[v]) {
+                Z.a[v] += al[v] * P.a[v];
+                P.a[v] = W.a[v] + be[v] * P.a[v];
+            }
+        st<float, VEC>(iz + i, Z);
+        st<float, VEC>(ip + i, P);
+    }
+}
+
+void launch_inner_pz(hipStream_t s, long nrows, int MB, int nm, float* iz, float* ip, const float* w,
+                     const double* ialpha, const double* ibeta, const int* upd)
+{
+    const int VEC = vec_of(MB), QB = MB / VEC;
+    const int g = grid_for(nrows, 256 / QB);
+    if (VEC == 4) hipLaunchKernelGGL((k_inner_pz<4>), dim3(g), dim3(256), 0, s, nrows, MB, nm, iz, ip, w, ialpha, ibeta, upd);
+    else hipLaunchKernelGGL((k_inner_pz<1>), dim3(g), dim3(256), 0, s, nrows, MB, nm, iz, ip, w, ialpha, ibeta, upd);
 }
 
 // preconditioner output z = iz (FP64) for outer-active members; partials (z.Ap, z.r)
@@ -888,6 +925,7 @@ __device__ void stage_logic(int stage, int m, int MB, const double S[3], CgScala
         break;
     case FIN_IN_ALPHA:  // S = (ip.iAp)
         cs.ialpha[m] = cs.inner_active[m] ? cs.irz[m] / S[0] : 0.0;
+        cs.inner_upd[m] = cs.inner_active[m];
         if (cs.inner_active[m] && cs.inner_iters[m] < kLanczosMax)
             cs.lz[(long)cs.inner_iters[m] * MB + m] = cs.ialpha[m];
         break;
