@@ -667,7 +667,7 @@ int64_t ensemble_bytes(const Mesh& m, const Problem& p, int MB, bool paged)
     else if (MB < 64) bytes += (int64_t)m.ne * 30 * MB * 8;             // element outputs
     bytes += (int64_t)p.n_steps * std::max(1, m.nrecv) * 3 * MB * 8;  // receiver history
     bytes += (int64_t)p.n_steps * 3 * MB * 8 * 2;           // acc, vI
-    if (!paged) bytes += (int64_t)m.ne * 4 * p.ns * MB * 40;
+    if (!paged) bytes += (int64_t)m.ne * 4 * p.ns * MB * kThetaBytes;
     return bytes;
 }
 
@@ -820,7 +820,7 @@ void Ens::create(Ctx* c, const Mesh* m, const Problem& prob, int member_pad)
                     D64.as<double>(), D32.as<float>(), D16.as<uint32_t>(), h.as<double>(), -1, d16_mean);
 
     // law state: resident if it fits the remaining budget, else paged
-    const size_t per_elem = (size_t)4 * P.ns * MB * 40;
+    const size_t per_elem = (size_t)4 * P.ns * MB * kThetaBytes;
     const size_t theta_bytes = per_elem * ne_pad;
     int64_t avail;
     {
@@ -1323,7 +1323,7 @@ void Ens::solve_fcg()
 void Ens::law_phase()
 {
     const DevMesh dm = mesh->dev();
-    const size_t per_elem = (size_t)4 * P.ns * MB * 40;
+    const size_t per_elem = (size_t)4 * P.ns * MB * kThetaBytes;
     if (!paged) {
         hipEvent_t t0;
         tstart(t0);
@@ -1367,7 +1367,7 @@ void Ens::law_phase()
 
 void Ens::prefetch_next()
 {
-    const size_t per_elem = (size_t)4 * P.ns * MB * 40;
+    const size_t per_elem = (size_t)4 * P.ns * MB * kThetaBytes;
     for (int cix = 0; cix < std::min(ring - 1, nchunks); ++cix) {
         const int slot = cix % ring;
         char* dslot = (char*)theta.p + (size_t)slot * chunk_elems * per_elem;

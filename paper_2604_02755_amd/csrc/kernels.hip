@@ -1253,8 +1253,12 @@ __device__ __forceinline__ double skeleton_tau(double g, const SpringPar& p)
 }
 
 // Law state of a chunk of ecp elements (ecp a multiple of EB): four FP64
-// fields (gp, gr, tr, gm) then two int32 fields (dir, skel); within a field,
-// element blocks of EB, then spring, point, element-in-block, member.
+// fields (gp, gr, tr, gm) then one int32 field packing the loading direction
+// and the skeleton flag, (dir + 1) | skel << 2 (36 B per spring and point);
+// within a field, element blocks of EB, then spring, point, element-in-block,
+// member.
+__device__ __forceinline__ int theta_flags(int dir, int skel) { return (dir + 1) | (skel << 2); }
+
 struct ThetaView {
     double* d;
     int* i;
@@ -1284,8 +1288,7 @@ __global__ void k_theta_init(void* base, long ecp, int ns, int MB)
     const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (i >= v.field_n) return;
     for (int f = 0; f < 4; ++f) v.d[f * v.field_n + i] = 0.0;
-    v.i[i] = 0;              // dir: no loading yet
-    v.i[v.field_n + i] = 1;  // skel: on the skeleton
+    v.i[i] = theta_flags(0, 1);  // no loading yet, on the skeleton
 }
 
 void launch_theta_init(hipStream_t s, void* base, long ecp, int ns, int MB)
@@ -1366,8 +1369,7 @@ __global__ void k_theta_reset_member(void* base, long ecp, int ns, int MB, int m
     const int s = (int)((t / 4) % ns), j = (int)(t % 4);
     const long idx = v.at(el, s, j, m);
     for (int f = 0; f < 4; ++f) v.d[f * v.field_n + idx] = 0.0;
-    v.i[idx] = 0;
-    v.i[v.field_n + idx] = 1;
+    v.i[idx] = theta_flags(0, 1);
 }
 
 void launch_theta_reset_member(hipStream_t s, void* base, long ecp, int ns, int MB, int m)
@@ -1442,18 +1444,18 @@ __global__ __launch_bounds__(256) void k_law(DevMesh M, int MB, int nm, int e0, 
     // the next spring's state is loaded while this one is updated
     long nidx = th.at(el, 0, j, m);
     double ngp = th.d[nidx], ngr = th.d[fn + nidx], ntr = th.d[2 * fn + nidx], ngm = th.d[3 * fn + nidx];
-    int ndir = th.i[nidx], nskel = th.i[fn + nidx];
+    int nfl = th.i[nidx];
 #pragma unroll 1
     for (int sp = 0; sp < ns; ++sp) {
         const double* n = dirs + 6 * sp;
         const double dg = n[0] * ej[0] + n[1] * ej[1] + n[2] * ej[2] + n[3] * ej[3] + n[4] * ej[4] + n[5] * ej[5];
         const long idx = nidx;
         double gp = ngp, gr = ngr, tr = ntr, gm = ngm;
-        int dir = ndir, skel = nskel;
+        int dir = (nfl & 3) - 1, skel = nfl >> 2;
         if (sp + 1 < ns) {
             nidx = th.at(el, sp + 1, j, m);
             ngp = th.d[nidx]; ngr = th.d[fn + nidx]; ntr = th.d[2 * fn + nidx]; ngm = th.d[3 * fn + nidx];
-            ndir = th.i[nidx]; nskel = th.i[fn + nidx];
+            nfl = th.i[nidx];
         }
         int rev = 0;           // 1: reversal on the skeleton, 2: reversal on a branch
         double rev_arg = 0.0;  // strain whose skeleton stress the reversal needs
@@ -1489,7 +1491,7 @@ __global__ __launch_bounds__(256) void k_law(DevMesh M, int MB, int nm, int e0, 
         if (rev) tr = rev == 1 ? P.G0 * P.gref * s_rev : tr + 2.0 * P.G0 * P.gref * s_rev;
         if (dg != 0.0) {
             th.d[idx] = gp; th.d[fn + idx] = gr; th.d[2 * fn + idx] = tr; th.d[3 * fn + idx] = gm;
-            th.i[idx] = dir; th.i[fn + idx] = skel;
+            th.i[idx] = theta_flags(dir, skel);
         }
         const double Gt = P.G0 / (1.0 + (1.0 + P.beta) * pw);
         double hk = 0.0;

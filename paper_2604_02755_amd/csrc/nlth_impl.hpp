@@ -158,6 +158,8 @@ struct CgScalars {  // per member [MB] device arrays
 
 // inner CG iterations whose coefficients are kept for the spectrum estimate
 constexpr int kLanczosMax = 64;
+// law state per spring and integration point: 4 FP64 + one int32 of flags
+constexpr int kThetaBytes = 36;
 // Chebyshev degree limit; coefficient table cheb[(2 k + 0/1) * MB + m] =
 // (c1_k, c2_k), k < kChebMax, and cheb[2 kChebMax * MB + m] = c0
 constexpr int kChebMax = 64;

@@ -175,11 +175,14 @@ def test_spring_table_isotropic(oracle_lib, ns):
 
 
 def test_state_bytes_per_element_match_paper():
-    """Section 2.1: four doubles and two flags per spring (40 B), 150 springs
-    per point, four points per tet -> 24 kB per element."""
-    per_spring = 4 * 8 + 2 * 4
-    assert per_spring == 40
-    assert per_spring * 150 * 4 == 24000
+    """Section 2.1: four doubles and two flags per spring; the flags (direction
+    in -1..1, skeleton 0/1) fit in 3 bits, so one int32 holds both: 36 B per
+    spring, 150 springs per point, four points per tet -> 21.6 kB per element."""
+    per_spring = 4 * 8 + 4
+    assert all(0 <= (d + 1) | (k << 2) < 8 and ((((d + 1) | (k << 2)) & 3) - 1, ((d + 1) | (k << 2)) >> 2) == (d, k)
+               for d in (-1, 0, 1) for k in (0, 1))
+    assert per_spring == 36
+    assert per_spring * 150 * 4 == 21600
 
 
 def test_skeleton_closed_forms(oracle_lib):
