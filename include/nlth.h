@@ -280,6 +280,24 @@ int nlth_cancel(nlth_ctx* ctx, uint64_t ticket);
  * is queued or running, NLTH_ENOTFOUND for an unknown ticket. */
 int nlth_release(nlth_ctx* ctx, uint64_t ticket);
 
+/* Velocity response spectra of ground-velocity records (Section 3 compares
+ * the computed surface waveforms through velocity response spectra with
+ * damping ratio h = 0.05), on the device.  vel: [n_series][n_steps] samples
+ * v_1..v_N at t_n = n dt (v_0 = 0), e.g. receiver components from
+ * nlth_result.vel; the velocity is taken linear between samples, so the
+ * ground acceleration is constant on each step.  For each period T (> 0,
+ * seconds) the oscillator x'' + 2 h w x' + w^2 x = -a_g, w = 2 pi / T, starts
+ * at rest and is advanced exactly step by step; out: [n_series][n_periods],
+ * kind NLTH_SPEC_VELOCITY max_n |x'_n| (relative velocity) or
+ * NLTH_SPEC_PSEUDO_VELOCITY w max_n |x_n|.  Host pointers, caller-owned,
+ * read or written during the call (synchronous).  NLTH_EINVAL for NULL
+ * pointers, empty sizes, dt <= 0, h outside [0, 1), a period <= 0 or an
+ * unknown kind. */
+#define NLTH_SPEC_VELOCITY 0
+#define NLTH_SPEC_PSEUDO_VELOCITY 1
+int nlth_response_spectra(nlth_ctx* ctx, const double* vel, int32_t n_series, int32_t n_steps, double dt,
+                          const double* periods, int32_t n_periods, double h, int32_t kind, double* out);
+
 /* Diagnostic: one element-by-element operator application y = Op x for
  * member 0 of `prob` (Eq. 1 left-hand side with K from the given D and C from
  * the given h), on the device, in FP64 or (precision = NLTH_MIXED) the inner

@@ -388,3 +388,42 @@ def rel_l2(a, b):
     b = np.asarray(b, float)
     nb = np.linalg.norm(b)
     return float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a - b))
+
+
+# ---------------------------------------------------------------------------
+# velocity response spectra of receiver records (Section 3: the surface
+# waveforms are compared through velocity response spectra with h = 0.05)
+# ---------------------------------------------------------------------------
+
+def response_spectra(vel, dt, periods, h=0.05, kind=0):
+    """Response spectra of ground-velocity records.
+
+    vel: [n_series, n_steps] samples v_1..v_N at t_n = n dt, with v_0 = 0.
+    The velocity is taken linear between samples, so the ground acceleration
+    is constant on each step, a_n = (v_n - v_{n-1}) / dt.  The oscillator
+    x'' + 2 h w x' + w^2 x = -a_g (w = 2 pi / T, x relative to the ground)
+    starts at rest and is advanced exactly over each step: the state
+    (x, x', a) evolves under a constant augmented matrix, so one step is the
+    matrix exponential of that matrix times dt (a library routine).
+    kind 0: relative velocity spectrum max_n |x'_n|; kind 1: pseudo-velocity
+    w max_n |x_n|.  Returns [n_series, n_periods]."""
+    from scipy.linalg import expm
+    v = np.asarray(vel, dtype=np.float64)
+    v = v.reshape(1, -1) if v.ndim == 1 else v
+    ns, nt = v.shape
+    a = np.diff(np.concatenate([np.zeros((ns, 1)), v], axis=1), axis=1) / dt
+    out = np.zeros((ns, len(periods)))
+    for k, T in enumerate(periods):
+        w = 2.0 * np.pi / T
+        Maug = np.array([[0.0, 1.0, 0.0], [-w * w, -2.0 * h * w, -1.0], [0.0, 0.0, 0.0]])
+        E = expm(Maug * dt)
+        Phi, Gam = E[:2, :2], E[:2, 2]
+        x = np.zeros((2, ns))
+        peak_x = np.zeros(ns)
+        peak_v = np.zeros(ns)
+        for n in range(nt):
+            x = Phi @ x + np.outer(Gam, a[:, n])
+            peak_x = np.maximum(peak_x, np.abs(x[0]))
+            peak_v = np.maximum(peak_v, np.abs(x[1]))
+        out[:, k] = peak_v if kind == 0 else w * peak_x
+    return out

@@ -1771,6 +1771,37 @@ int nlth_solve(nlth_ctx* ctx, const nlth_mesh* mesh, const nlth_problem* prob, n
     return rr;
 }
 
+int nlth_response_spectra(nlth_ctx* ctx, const double* vel, int32_t n_series, int32_t n_steps, double dt,
+                          const double* periods, int32_t n_periods, double h, int32_t kind, double* out)
+{
+    API_BEGIN(ctx)
+    if (!ctx || !vel || !periods || !out) throw Error{NLTH_EINVAL, "NULL argument"};
+    if (n_series <= 0 || n_steps <= 0 || n_periods <= 0) throw Error{NLTH_EINVAL, "empty series, steps or periods"};
+    if (!(dt > 0.0) || !(h >= 0.0 && h < 1.0)) throw Error{NLTH_EINVAL, "dt must be > 0 and h in [0, 1)"};
+    if (kind != NLTH_SPEC_VELOCITY && kind != NLTH_SPEC_PSEUDO_VELOCITY)
+        throw Error{NLTH_EINVAL, "kind must be NLTH_SPEC_VELOCITY or NLTH_SPEC_PSEUDO_VELOCITY"};
+    for (int k = 0; k < n_periods; ++k)
+        if (!(periods[k] > 0.0)) throw Error{NLTH_EINVAL, "periods must be > 0"};
+    if (ctx->host_only) throw Error{NLTH_EDEVICE, "host-only context"};
+    std::lock_guard<std::mutex> g(ctx->mu);
+    NLTH_HIP(hipSetDevice(ctx->device));
+    const size_t nv = (size_t)n_series * n_steps, no = (size_t)n_series * n_periods;
+    DevBuf dv, dp, dout;
+    dv.alloc(nullptr, nv * 8);
+    dp.alloc(nullptr, (size_t)n_periods * 8);
+    dout.alloc(nullptr, no * 8);
+    hipStream_t s = ctx->stream;
+    NLTH_HIP(hipMemcpyAsync(dv.p, vel, nv * 8, hipMemcpyHostToDevice, s));
+    NLTH_HIP(hipMemcpyAsync(dp.p, periods, (size_t)n_periods * 8, hipMemcpyHostToDevice, s));
+    launch_response_spectra(s, dv.as<double>(), n_series, n_steps, dt, dp.as<double>(), n_periods, h, kind,
+                            dout.as<double>());
+    NLTH_HIP(hipGetLastError());
+    NLTH_HIP(hipMemcpyAsync(out, dout.p, no * 8, hipMemcpyDeviceToHost, s));
+    NLTH_HIP(hipStreamSynchronize(s));
+    return NLTH_OK;
+    API_END
+}
+
 int nlth_apply_operator(nlth_ctx* ctx, const nlth_mesh* mesh, const nlth_problem* prob, int32_t which,
                         int32_t precision, const double* D_ip, const double* hh, const double* x, double* y)
 {

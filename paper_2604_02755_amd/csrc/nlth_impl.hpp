@@ -228,5 +228,7 @@ void launch_incident_velocity(hipStream_t s, int MB, int nm, int n_steps, const 
 void launch_pick_vI(hipStream_t s, int MB, int nm, int n_steps, const double* vI_all,
                     const int* member_step, double* vI_cur);
 void launch_cast32(hipStream_t s, const double* a, float* b, long n);
+void launch_response_spectra(hipStream_t s, const double* vel, int ns, int nt, double dt, const double* periods, int np,
+                             double h, int kind, double* out);
 
 }  // namespace nlth

@@ -32,6 +32,7 @@ NLTH_ENOTFOUND = -9
 NLTH_FP64, NLTH_MIXED = 0, 1
 NLTH_INNER_BF16, NLTH_INNER_FP32, NLTH_INNER_BF16_MEAN = 0, 1, 2
 INNER_CG, INNER_CHEBYSHEV = 0, 1  # nlth_tuning.inner_method
+NLTH_SPEC_VELOCITY, NLTH_SPEC_PSEUDO_VELOCITY = 0, 1
 NLTH_OP_A, NLTH_OP_K, NLTH_OP_M = 0, 1, 2
 NLTH_DEVICE_NONE = -1
 
@@ -114,6 +115,8 @@ EXPORTS = {
     "nlth_release": (C.c_int, [C.c_void_p, C.c_uint64]),
     "nlth_apply_operator": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(nlth_problem), C.c_int32,
                                       C.c_int32, _dp, _dp, _dp, _dp]),
+    "nlth_response_spectra": (C.c_int, [C.c_void_p, _dp, C.c_int32, C.c_int32, C.c_double, _dp, C.c_int32,
+                                        C.c_double, C.c_int32, _dp]),
 }
 
 _lib = None
@@ -252,6 +255,18 @@ def nlth_solve(ctx, mesh_h, mesh, prob, n_steps=None, members=None):
     return out
 
 
+def nlth_response_spectra(ctx, vel, dt, periods, h=0.05, kind=0):
+    """Velocity response spectra of records vel [n_series, n_steps] (or one
+    record); returns [n_series, n_periods]."""
+    v = _f64(vel)
+    v = v.reshape(1, -1) if v.ndim == 1 else v
+    T = _f64(periods).reshape(-1)
+    out = np.zeros((v.shape[0], T.size))
+    _check(lib().nlth_response_spectra(ctx, _ptr(v), int(v.shape[0]), int(v.shape[1]), float(dt), _ptr(T),
+                                       int(T.size), float(h), int(kind), _ptr(out)), ctx)
+    return out
+
+
 def nlth_apply_operator(ctx, mesh_h, prob, which, precision, D_ip, h, x):
     keep = []
     p = _problem_struct(prob, keep, [0], 0)
@@ -347,6 +362,9 @@ class Context:
 
     def apply_operator(self, mesh_h, prob, which, precision, D_ip, h, x):
         return nlth_apply_operator(self.h, mesh_h, prob, which, precision, D_ip, h, x)
+
+    def response_spectra(self, vel, dt, periods, h=0.05, kind=0):
+        return nlth_response_spectra(self.h, vel, dt, periods, h, kind)
 
     # -- continuous-batching request loop
     def submit(self, mesh_h, mesh, prob):

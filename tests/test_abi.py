@@ -99,3 +99,18 @@ def test_problem_validation_before_device(nlth_mod, host_ctx):
     rc = nlth_mod.lib().nlth_ens_create(host_ctx, mh, C.byref(p), C.byref(h))
     nlth_mod.nlth_mesh_destroy(mh)
     assert rc == nlth_mod.NLTH_EINVAL
+
+
+def test_response_spectra_argument_checks(nlth_mod, host_ctx):
+    """Invalid arguments are refused before any device work; valid ones on a
+    context without a device give NLTH_EDEVICE."""
+    v = np.zeros((2, 10))
+    for kw in (dict(dt=0.0), dict(h=1.0), dict(h=-0.1), dict(kind=2), dict(periods=[0.5, 0.0])):
+        args = dict(vel=v, dt=1e-3, periods=[0.5, 1.0], h=0.05, kind=0)
+        args.update(kw)
+        with pytest.raises(nlth_mod.NlthError) as ei:
+            nlth_mod.nlth_response_spectra(host_ctx, **args)
+        assert ei.value.code == nlth_mod.NLTH_EINVAL
+    with pytest.raises(nlth_mod.NlthError) as ei:
+        nlth_mod.nlth_response_spectra(host_ctx, v, 1e-3, [0.5])
+    assert ei.value.code == nlth_mod.NLTH_EDEVICE

@@ -1,0 +1,50 @@
+"""Parity at the benchmark's full size and launch configuration: the batched
+ensemble (64 members, 64x64x32-cube mesh, 12 springs, mixed precision,
+element-mean bfloat16 inner D, the cluster path with 3 blocks per CU) against
+the oracle run of single members, on the first steps of the seeded records
+(scaled 30x).  In a few steps the wave has not yet reached the surface (32 m
+at up to 400 m/s), so the receivers are nodes in the first metres above the
+base, where it has.  Tolerance 1e-12 on both sides, so the bar is the FP64
+one (1e-9 relative L2 on receiver velocity)."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2604_02755_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def test_full_size_members_match_oracle(gpu_ctx, oracle_lib):
+    n_steps = 6
+    mesh, prob = I.config(2, n_steps=n_steps, cg_tol=1e-12)
+    z = mesh.xyz[:, 2]
+    low = np.flatnonzero((z <= z.min() + 1.5 + 1e-9) & (np.round(mesh.xyz[:, 0] * 2) % 8 == 0)
+                         & (np.round(mesh.xyz[:, 1] * 2) % 8 == 0))
+    mesh.recv = np.ascontiguousarray(low.astype(np.int32))
+    prob.input_acc = np.ascontiguousarray(prob.input_acc[:, :n_steps] * 30.0)
+    prob.inner_dtype = 2
+    say("full size:", mesh.n_tets, "tets,", mesh.n_dof, "DOF per member,", prob.n_members, "members,", n_steps, "steps,",
+        mesh.recv.size, "receivers within 1.5 m of the base")
+    mh = gpu_ctx.mesh(mesh)
+    ens = gpu_ctx.ensemble(mh, mesh, prob)
+    try:
+        ens.set_tuning(128, 16, 1, 16, 1e-12, cluster_blocks=3)
+        ens.step(n_steps)
+        out = ens.read()
+    finally:
+        ens.close()
+    assert np.all(out["status"] == 0)
+    for m in (0, 63):
+        ref = oracle_lib.run(mesh, prob, member=m)
+        vref = ref["vel"]
+        err = oracle_lib.rel_l2(out["vel"][m], vref)
+        peak = float(np.max(np.abs(vref)))
+        say("  member", m, "rel L2 vs oracle", err, "peak |v|", peak, "outer/inner iterations", out["iters"][m].tolist())
+        assert peak > 1e-6 and err < 1e-9

@@ -243,11 +243,13 @@ def test_autotuned_run_matches_fp64(gpu_ctx):
         assert err < 1e-6
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_cluster_path_64_members(gpu_ctx, oracle_lib, precision):
+@pytest.mark.parametrize("precision,inner_dtype", [(0, 0), (1, 0), (1, 2)])
+def test_cluster_path_64_members(gpu_ctx, oracle_lib, precision, inner_dtype):
     """64 member slots take the cluster path (element clusters summed in LDS,
-    then per node): members match the oracle and the colour path."""
+    then per node): members match the oracle and the colour path; inner_dtype
+    2 is the benchmark's inner operator (one bfloat16 D per element)."""
     mesh, prob = _small_problem(precision=precision, n_members=64, n_steps=24, dims=(6, 5, 3), ns=12, tol=1e-12)
+    prob.inner_dtype = inner_dtype
     vs, gr = I.ensemble_members(91, 64, I.CFG0_LAYERS["vs"])
     prob.vs = vs
     prob.gamma_ref = np.tile(gr[:, None], (1, 2))
@@ -264,7 +266,7 @@ def test_cluster_path_64_members(gpu_ctx, oracle_lib, precision):
         finally:
             ens.close()
 
-    say("cluster path, 64 members, precision", precision)
+    say("cluster path, 64 members, precision", precision, "inner dtype", inner_dtype)
     cl = run()
     col = run(scatter=1)
     d = float(np.max(np.abs(cl["vel"] - col["vel"])) / np.max(np.abs(col["vel"])))
@@ -342,3 +344,25 @@ def test_chebyshev_inner_matches_oracle(gpu_ctx, oracle_lib, nlth_mod):
         err = oracle_lib.rel_l2(om["vel"][m], o64["vel"][m])
         say("  2 members, member", m, "chebyshev mixed vs fp64 at 1e-8", err)
         assert err < 1e-6
+
+
+def test_response_spectra_matches_oracle(gpu_ctx, oracle_lib, nlth_mod):
+    """Velocity response spectra (h = 0.05) on the device against the oracle's
+    matrix-exponential stepping: band-limited records and the receiver
+    histories of a nonlinear run, both spectrum kinds, to 1e-10 of the peak."""
+    dt = 1e-3
+    recs = [np.cumsum(I.band_limited_wave(7000 + k, 3000, dt)) * dt for k in range(5)]
+    mesh, prob = _small_problem(precision=0, n_steps=60, scale=20.0)
+    out = gpu_ctx.solve(gpu_ctx.mesh(mesh), mesh, prob)
+    hist = out["vel"][0].transpose(1, 2, 0).reshape(-1, prob.n_steps)[:12]  # receiver components over time
+    periods = np.geomspace(0.02, 5.0, 37)
+    for vel, step in ((np.array(recs), dt), (np.ascontiguousarray(hist), prob.dt)):
+        for kind in (0, 1):
+            g = gpu_ctx.response_spectra(vel, step, periods, 0.05, kind)
+            o = oracle_lib.response_spectra(vel, step, periods, 0.05, kind)
+            err = float(np.max(np.abs(g - o)) / np.max(np.abs(o)))
+            say("response spectra, kind", kind, vel.shape, "max rel err", err)
+            assert np.max(np.abs(o)) > 0 and err < 1e-10
+    with pytest.raises(nlth_mod.NlthError) as ei:
+        gpu_ctx.response_spectra(recs[0], dt, [0.1, -1.0])
+    assert ei.value.code == nlth_mod.NLTH_EINVAL

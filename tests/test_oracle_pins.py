@@ -405,3 +405,40 @@ def test_invalid_mesh_rejected(oracle_lib):
     with pytest.raises(oracle_lib.OracleError) as ei:
         oracle_lib.run(mesh, prob)
     assert ei.value.code == -1
+
+
+def _ramped_harmonic(f, V, dt, n_ramp=30, n_total=80):
+    """Ground velocity whose acceleration is V 2 pi f env(t) cos(2 pi f t),
+    env a raised-cosine ramp over n_ramp forcing periods (a slow start keeps
+    the free transient of the oscillator small)."""
+    Om = 2 * np.pi * f
+    t = np.arange(1, int(n_total / f / dt) + 1) * dt
+    env = 0.5 - 0.5 * np.cos(np.pi * np.clip(t / (n_ramp / f), 0, 1))
+    return np.cumsum(V * Om * env * np.cos(Om * t)) * dt
+
+
+def test_response_spectra_closed_forms(oracle_lib):
+    """Velocity response spectra (Section 3, h = 0.05): under a slowly ramped
+    harmonic ground motion the oscillator settles to the textbook steady
+    state, |x| = (a_g / w^2) / sqrt((1 - r^2)^2 + (2 h r)^2) and |x'| = W |x|
+    (r = W / w, W the forcing frequency), below, near and above resonance;
+    a very stiff oscillator follows the ground acceleration (w^2 max|x| = PGA)
+    and a very soft one stays put (max|x'| = PGV); no input gives zero."""
+    h, T, dt, V = 0.05, 0.5, 2e-4, 0.3
+    w = 2 * np.pi / T
+    for f in (0.7, 1.7, 3.1):
+        Om = 2 * np.pi * f
+        v = _ramped_harmonic(f, V, dt)
+        r = Om / w
+        X = (V * Om / w ** 2) / np.sqrt((1 - r * r) ** 2 + (2 * h * r) ** 2)
+        sv, psv = (oracle_lib.response_spectra(v, dt, [T], h, kind=k)[0, 0] for k in (0, 1))
+        assert abs(psv / w / X - 1) < 5e-3, (f, psv / w, X)
+        assert abs(sv / (Om * X) - 1) < 5e-3, (f, sv, Om * X)
+    rng = np.random.default_rng(5)
+    v = np.cumsum(np.convolve(rng.normal(size=4000), np.hanning(200), mode="same")) * 1e-3
+    a = np.diff(np.concatenate([[0.0], v])) / 1e-3
+    stiff = oracle_lib.response_spectra(v, 1e-3, [0.003], h, kind=1)[0, 0] * (2 * np.pi / 0.003)
+    soft = oracle_lib.response_spectra(v, 1e-3, [5000.0], h, kind=0)[0, 0]
+    assert abs(stiff / np.abs(a).max() - 1) < 2e-2
+    assert abs(soft / np.abs(v).max() - 1) < 1e-3
+    assert np.all(oracle_lib.response_spectra(np.zeros((2, 50)), 1e-3, [0.1, 1.0], h) == 0.0)
