@@ -86,7 +86,7 @@ def traffic_from_profile(src_hash: str, element_members_per_launch: float):
     return round(d["element"]["bytes_per_element_member"] * element_members_per_launch, 0)
 
 
-def run_gpu(mesh, prob, warmup, steps, profile, tune_steps=0, tuned=None, ctx_kw=None, fixed=None):
+def run_gpu(mesh, prob, warmup, steps, profile, tune_steps=0, tuned=None, ctx_kw=None, fixed=None, tuning_kw=None):
     """Create the ensemble, step ``warmup`` steps, autotune it over the next
     ``tune_steps`` steps (or apply the launch shapes of ``tuned`` and step as
     many), then time ``steps`` steps."""
@@ -103,6 +103,8 @@ def run_gpu(mesh, prob, warmup, steps, profile, tune_steps=0, tuned=None, ctx_kw
             choice = dict(fixed)
         if tuned is not None:
             ens.set_tuning(tuned["ebe_block"], tuned["check_every"], 1, cluster_blocks=tuned.get("cluster_blocks", 0))
+        if tuning_kw:
+            ens.set_tuning(**tuning_kw)
         ens.step(warmup)  # the first steps carry no wave yet: warm up before tuning
         if tuned is not None:
             ens.step(tune_steps)
@@ -254,6 +256,20 @@ def bench_paged(args):
                       "h2d_gbps": st["h2d_bytes"] / el / 1e9, "d2h_gbps": st["d2h_bytes"] / el / 1e9},
         "device_gb": st["device_bytes"] / 1e9, "host_gb": st["host_bytes"] / 1e9,
     }
+    if args.zero_copy_steps > 0:
+        # ablation of the pipeline: the law kernel works on the pinned host
+        # state over the host link (the form the footnote of Section 2.3 times)
+        el_zc, _, st_zc, out_zc, _ = run_gpu(mesh, prob, args.warmup, args.zero_copy_steps, False,
+                                             ctx_kw=dict(hbm_budget=int(args.hbm_budget_gb * 2**30),
+                                                         host_budget=int((theta_gb * 1.05 + 8) * 1e9)),
+                                             tuning_kw={"zero_copy": 1})
+        ms_zc = el_zc / args.zero_copy_steps * 1e3
+        k = min(args.steps, args.zero_copy_steps)
+        same = bool(np.array_equal(out_zc["vel"][:, :args.warmup + k], out["vel"][:, :args.warmup + k]))
+        log(f"zero-copy law: {ms_zc:.0f} ms/step, results equal to the pipelined run: {same}")
+        line["zero_copy_ablation"] = {"steps": args.zero_copy_steps, "ms_per_step": ms_zc,
+                                      "slowdown_vs_pipelined": ms_zc / line["ms_per_step"],
+                                      "results_equal_to_pipelined": same}
     print(json.dumps(line), flush=True)
 
 
@@ -294,6 +310,8 @@ def main():
     ap.add_argument("--config", type=int, default=2, choices=(1, 2, 3, 4),
                     help="2: batched ensemble (default); 1: one large member; 3: paged ensemble; 4: serving")
     ap.add_argument("--hbm-budget-gb", type=float, default=0.0, help="device budget of --config 3 (0: 90%% of free)")
+    ap.add_argument("--zero-copy-steps", type=int, default=0,
+                    help="--config 3: also time this many steps with the law on the host state directly (ablation)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving sub-run of --config 2")
     ap.add_argument("--serve-rate", type=float, default=4.0)
     ap.add_argument("--serve-window", type=float, default=60.0)

@@ -244,7 +244,8 @@ int nlth_ens_stats(const nlth_ens* ens, nlth_stats* st);
  * Out-of-range fields (ebe_block not 0/64/128/256, check_every outside
  * 0..64, inner_maxit outside 0..100000, inner_tol outside [0, 1), cluster_blocks
  * not 0/2/3/4, scatter outside -1..2 or not available for this ensemble,
- * inner_method outside -1..1, or Chebyshev with a degree above 64) give NLTH_EINVAL and
+ * inner_method outside -1..1, Chebyshev with a degree above 64, zero_copy outside
+ * -1..1 or 1 for an ensemble whose state is resident) give NLTH_EINVAL and
  * change nothing.  Not to be called while the ensemble
  * is stepping on another thread. */
 typedef struct {
@@ -261,6 +262,10 @@ typedef struct {
                                   inner_maxit (at most 64, inner_tol unused) on the block-Jacobi
                                   preconditioned operator, with each member's spectrum bounds taken
                                   from the Lanczos matrix of the step's first inner CG solve */
+    int32_t zero_copy;         /* -1 keep; 0 paged law state moved by the pipelined chunk copies
+                                  (default); 1 the law kernel reads and writes the pinned host state
+                                  over the host link itself (an ablation of the pipeline; only for an
+                                  ensemble whose state is paged) */
 } nlth_tuning;
 int nlth_ens_set_tuning(nlth_ens* ens, const nlth_tuning* t);
 int nlth_ens_set_profile(nlth_ens* ens, int32_t profile);

@@ -870,6 +870,7 @@ void Ens::create(Ctx* c, const Mesh* m, const Problem& prob, int member_pad)
         }
         slot_chunk.assign(ring, -1);
         prefetched.assign(nchunks, false);
+        NLTH_HIP(hipEventCreateWithFlags(&ev_zc, hipEventDisableTiming));
         NLTH_HIP(hipEventCreate(&ev_copy0));
         NLTH_HIP(hipEventCreate(&ev_copy1));
     }
@@ -917,6 +918,8 @@ void Ens::destroy()
     for (auto e : ev_law) (void)hipEventDestroy(e);
     for (auto e : ev_d2h) (void)hipEventDestroy(e);
     ev_h2d.clear(); ev_law.clear(); ev_d2h.clear();
+    if (ev_zc) (void)hipEventDestroy(ev_zc);
+    ev_zc = nullptr;
     for (auto& pe : pending) { (void)hipEventDestroy(pe.first.first); (void)hipEventDestroy(pe.first.second); }
     pending.clear();
     for (auto e : ev_pool) (void)hipEventDestroy(e);
@@ -1333,6 +1336,25 @@ void Ens::law_phase()
         tstop(t0, &pc_law, (int64_t)mesh->ne * nm);
         return;
     }
+    if (zero_copy) {
+        // ablation of the pipeline: the kernel reads and writes the pinned
+        // host state over the host link itself, chunk by chunk (the footnote
+        // of Section 2.3 measures this form on GH200).  Earlier write-backs of
+        // the pipelined form must have landed first.
+        for (int slot = 0; slot < ring; ++slot) NLTH_HIP(hipStreamWaitEvent(s, ev_d2h[slot], 0));
+        for (int cix = 0; cix < nchunks; ++cix) {
+            hipEvent_t t0;
+            tstart(t0);
+            launch_law(s, dm, MB, nm, chunk_e0[cix], chunk_ec[cix], chunk_ecp[cix], mat.as<double>(), P.nl,
+                       nonlinear.as<int>(), P.ns, dirs.as<double>(), w.as<double>(), du.as<double>(),
+                       (char*)theta_host.p + chunk_off[cix], D64.as<double>(), D32.as<float>(), D16.as<uint32_t>(),
+                       h.as<double>(), stepping.as<int>(), d16_mean);
+            tstop(t0, &pc_law, (int64_t)chunk_ec[cix] * nm);
+            prefetched[cix] = false;
+        }
+        NLTH_HIP(hipEventRecord(ev_zc, s));
+        return;
+    }
     // Algorithm 3 pipeline: chunk c computes while c-1 goes to the host and
     // c+1 comes to the device, on two copy streams and a ring of slots
     for (int cix = 0; cix < nchunks; ++cix) {
@@ -1341,6 +1363,7 @@ void Ens::law_phase()
         const size_t bytes = (size_t)chunk_ecp[cix] * per_elem;
         if (!prefetched[cix]) {
             if (slot_chunk[slot] >= 0) NLTH_HIP(hipStreamWaitEvent(s_h2d, ev_d2h[slot], 0));
+            NLTH_HIP(hipStreamWaitEvent(s_h2d, ev_zc, 0));  // host state written by a zero-copy pass
             NLTH_HIP(hipMemcpyAsync(dslot, (char*)theta_host.p + chunk_off[cix], bytes, hipMemcpyHostToDevice, s_h2d));
             NLTH_HIP(hipEventRecord(ev_h2d[slot], s_h2d));
             h2d_bytes += bytes;
@@ -1678,6 +1701,8 @@ int nlth_ens_set_tuning(nlth_ens* ens, const nlth_tuning* t)
     if ((t->scatter == 0 && !ens->fbuf.p) || (t->scatter == 2 && !ens->cbuf.p))
         throw Error{NLTH_EINVAL, "scatter: element outputs need fewer than 64 member slots, clusters 64..256"};
     if (t->inner_method < -1 || t->inner_method > 1) throw Error{NLTH_EINVAL, "inner_method must be -1, 0 or 1"};
+    if (t->zero_copy < -1 || t->zero_copy > 1) throw Error{NLTH_EINVAL, "zero_copy must be -1, 0 or 1"};
+    if (t->zero_copy == 1 && !ens->paged) throw Error{NLTH_EINVAL, "zero_copy needs an ensemble whose law state is paged"};
     if ((t->inner_method == 1 || (t->inner_method == -1 && ens->inner_method == 1)) &&
         (t->inner_maxit ? t->inner_maxit : ens->P.inner_maxit) > kChebMax)
         throw Error{NLTH_EINVAL, "the Chebyshev degree (inner_maxit) must be at most 64"};
@@ -1690,6 +1715,7 @@ int nlth_ens_set_tuning(nlth_ens* ens, const nlth_tuning* t)
     if (t->scatter >= 0) ens->scatter = t->scatter;
     if (t->cluster_blocks > 0) ens->cluster_blocks = t->cluster_blocks;
     if (t->inner_method >= 0) ens->inner_method = t->inner_method;
+    if (t->zero_copy >= 0) ens->zero_copy = t->zero_copy != 0;
     // captured chunks hold the old launch shapes
     if (ens->g_inner) (void)hipGraphExecDestroy(ens->g_inner);
     if (ens->g_pcg) (void)hipGraphExecDestroy(ens->g_pcg);

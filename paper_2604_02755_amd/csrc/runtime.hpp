@@ -117,11 +117,13 @@ struct Ens {
     CgScalars cs{};
     // paging
     bool paged = false;
+    bool zero_copy = false;             // paged state: the law kernel works on the pinned host copy directly
     int chunk_elems = 0, nchunks = 0, ring = 3;
     std::vector<long> chunk_off;        // byte offset of each chunk in theta_host
     std::vector<int> chunk_e0, chunk_ec, chunk_ecp;
     hipStream_t s_h2d = nullptr, s_d2h = nullptr;
     std::vector<hipEvent_t> ev_h2d, ev_law, ev_d2h;
+    hipEvent_t ev_zc = nullptr;         // end of the last zero-copy law pass (the copies wait for it)
     std::vector<int> slot_chunk;        // chunk currently held by each slot (-1 none)
     std::vector<bool> prefetched;
     // host bookkeeping

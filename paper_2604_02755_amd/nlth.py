@@ -71,7 +71,7 @@ class nlth_problem(C.Structure):
 class nlth_tuning(C.Structure):
     _fields_ = [("ebe_block", C.c_int32), ("check_every", C.c_int32), ("use_graph", C.c_int32),
                 ("inner_maxit", C.c_int32), ("inner_tol", C.c_double), ("scatter", C.c_int32),
-                ("cluster_blocks", C.c_int32), ("inner_method", C.c_int32)]
+                ("cluster_blocks", C.c_int32), ("inner_method", C.c_int32), ("zero_copy", C.c_int32)]
 
 
 class nlth_result(C.Structure):
@@ -325,9 +325,9 @@ class Ensemble:
         lib().nlth_ens_reset_stats(self.h)
 
     def set_tuning(self, ebe_block=0, check_every=0, use_graph=-1, inner_maxit=0, inner_tol=0.0, scatter=-1,
-                   cluster_blocks=0, inner_method=-1):
+                   cluster_blocks=0, inner_method=-1, zero_copy=-1):
         t = nlth_tuning(int(ebe_block), int(check_every), int(use_graph), int(inner_maxit), float(inner_tol),
-                        int(scatter), int(cluster_blocks), int(inner_method))
+                        int(scatter), int(cluster_blocks), int(inner_method), int(zero_copy))
         return _check(lib().nlth_ens_set_tuning(self.h, C.byref(t)), self.ctx)
 
     def close(self):

@@ -36,3 +36,37 @@ def test_paged_state_matches_resident_bitwise(nlth_mod):
     assert np.array_equal(outs[0]["vel"], outs[1]["vel"])
     assert np.array_equal(outs[0]["iters"], outs[1]["iters"])
     assert np.abs(outs[0]["vel"]).max() > 0
+
+
+def test_zero_copy_law_matches_resident_bitwise(nlth_mod):
+    """The ablation of the pipeline (the law kernel working on the pinned host
+    state over the host link) computes the same thing: bitwise equal to the
+    resident run, also when it alternates with the pipelined copies; a
+    resident ensemble refuses it."""
+    mesh, prob = I.config(0, n_steps=12, mesh_dims=(5, 4, 3), n_members=3, cg_tol=1e-10,
+                          precision=I.PRECISION_MIXED)
+    prob.input_acc *= 5.0
+    outs = []
+    for budget, plan in ((0, None), (24 << 20, (1, 0, 1))):
+        print("zero-copy case: hbm budget", budget, "plan", plan, flush=True)
+        ctx = nlth_mod.Context(0, hbm_budget=budget, use_torch_stream=False)
+        try:
+            mh = ctx.mesh(mesh)
+            ens = ctx.ensemble(mh, mesh, prob)
+            if plan is None:
+                with pytest.raises(nlth_mod.NlthError) as ei:
+                    ens.set_tuning(zero_copy=1)
+                assert ei.value.code == nlth_mod.NLTH_EINVAL
+                ens.step(prob.n_steps)
+            else:
+                for zc in plan:  # zero-copy, pipelined, zero-copy: 4 steps each
+                    ens.set_tuning(zero_copy=zc)
+                    ens.step(prob.n_steps // len(plan))
+                assert ens.stats()["paged"] == 1
+            outs.append(ens.read())
+            ens.close()
+        finally:
+            ctx.close()
+    assert np.array_equal(outs[0]["vel"], outs[1]["vel"])
+    assert np.array_equal(outs[0]["iters"], outs[1]["iters"])
+    assert np.abs(outs[0]["vel"]).max() > 0
