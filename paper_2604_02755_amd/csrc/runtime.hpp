@@ -41,6 +41,7 @@ struct DevBuf {
     size_t bytes = 0;
     Budget* budget = nullptr;
     bool host = false;  // pinned host memory
+    size_t base_off = 0;  // p = the allocation + base_off (device buffers are staggered)
     DevBuf() = default;
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
