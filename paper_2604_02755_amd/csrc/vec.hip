@@ -384,8 +384,10 @@ void launch_xr_update(hipStream_t s, long nrows, int MB, int nm, double* x, doub
     else hipLaunchKernelGGL((k_xr_update<1>), dim3(g), dim3(256), 0, s, nrows, MB, nm, x, r, p, Ap, alpha, active, partial);
 }
 
-// inner FP32 PCG start on A w = r: ir = r, iz = 0, w = P ir, ip = w, iAp = 0;
-// partials (ir.ir, ir.w)
+// inner FP32 PCG start on A w = r: ir = r, iz = 0, ip = P ir; partials
+// (ir.ir, ir.ip).  w and iAp need no clearing: the first iteration writes
+// them before reading them, and a member outside the mask multiplies its
+// (finite, stale) iAp by a zero alpha.
 template <int VEC>
 __global__ __launch_bounds__(256) void k_inner_start(int nn, int MB, int nm, const double* __restrict__ r,
                                                     const float* __restrict__ pinv32, float* __restrict__ ir,
@@ -420,7 +422,6 @@ __global__ __launch_bounds__(256) void k_inner_start(int nn, int MB, int nm, con
                 const long i = (node * 3 + c) * MB + m0;
                 st<float, VEC>(ir + i, R[c]);
                 st<float, VEC>(iz + i, zero);
-                st<float, VEC>(w + i, W[c]);
                 st<float, VEC>(ip + i, W[c]);
 #pragma unroll
                 for (int v = 0; v < VEC; ++v) {
@@ -429,8 +430,6 @@ __global__ __launch_bounds__(256) void k_inner_start(int nn, int MB, int nm, con
                 }
             }
         }
-#pragma unroll
-        for (int c = 0; c < 3; ++c) st<float, VEC>(iAp + (node * 3 + c) * MB + m0, zero);
     }
     block_partials<2, VEC>(acc, QB, MB, partial);
 }
@@ -545,7 +544,8 @@ void launch_inner_pz(hipStream_t s, long nrows, int MB, int nm, float* iz, float
     else hipLaunchKernelGGL((k_inner_pz<1>), dim3(g), dim3(256), 0, s, nrows, MB, nm, iz, ip, w, ialpha, ibeta, upd);
 }
 
-// preconditioner output z = iz (FP64) for outer-active members; partials (z.Ap, z.r)
+// preconditioner output z = iz (FP64) for outer-active members (0 for the
+// others, whose z is not used again in the step); partials (z.Ap, z.r)
 template <int VEC>
 __global__ __launch_bounds__(256) void k_inner_out(long nrows, int MB, int nm, const float* __restrict__ iz,
                                                   double* __restrict__ z, const double* __restrict__ Ap,
@@ -565,10 +565,10 @@ __global__ __launch_bounds__(256) void k_inner_out(long nrows, int MB, int nm, c
             const long i = row * MB + m0;
             const Pk<float, VEC> Zf = ld<float, VEC>(iz + i);
             const Pk<double, VEC> A = ld<double, VEC>(Ap + i), R = ld<double, VEC>(r + i);
-            Pk<double, VEC> Z = ld<double, VEC>(z + i);
+            Pk<double, VEC> Z;
 #pragma unroll
             for (int v = 0; v < VEC; ++v) {
-                if (act[v]) Z.a[v] = (double)Zf.a[v];
+                Z.a[v] = act[v] ? (double)Zf.a[v] : 0.0;
                 acc[0][v] += Z.a[v] * A.a[v];
                 acc[1][v] += Z.a[v] * R.a[v];
             }
