@@ -99,7 +99,8 @@ def run_gpu(mesh, prob, warmup, steps, profile, tune_steps=0, tuned=None, ctx_kw
         choice = None
         if fixed is not None:
             ens.set_tuning(fixed["ebe_block"], fixed["check_every"], 1, fixed["inner_maxit"], fixed["inner_tol"],
-                           cluster_blocks=fixed.get("cluster_blocks", 0), inner_method=fixed.get("inner_method", 0))
+                           cluster_blocks=fixed.get("cluster_blocks", 0), inner_method=fixed.get("inner_method", 0),
+                           tail_members=fixed.get("tail_members", -1))
             choice = dict(fixed)
         if tuned is not None:
             ens.set_tuning(tuned["ebe_block"], tuned["check_every"], 1, cluster_blocks=tuned.get("cluster_blocks", 0))
@@ -350,7 +351,7 @@ def main():
     el, st0, st, out_mixed, tuned = run_gpu(mesh, prob, args.warmup, args.steps, not args.no_profile, n_tune,
                                             fixed=fixed)
     value = args.members * ndof * args.steps / el
-    log(f"mixed: {el/args.steps*1e3:.1f} ms/step, {value:.3e} DOF-steps/s, tuning {tuned and {k: tuned.get(k) for k in ('inner_method', 'inner_tol', 'inner_maxit', 'ebe_block', 'check_every', 'cluster_blocks')}}")
+    log(f"mixed: {el/args.steps*1e3:.1f} ms/step, {value:.3e} DOF-steps/s, tuning {tuned and {k: tuned.get(k) for k in ('inner_method', 'inner_tol', 'inner_maxit', 'ebe_block', 'check_every', 'cluster_blocks', 'tail_members')}}")
 
     # roofline of the dominant kernel, the inner operator's element kernel, over
     # the timed region (the node gather that completes each application is a
@@ -361,7 +362,9 @@ def main():
     roofline = None
     if st["n_ebe32"] > 0 and st["ms_ebe32"] > 0:
         per_unit = ebe32_algorithmic_bytes(mesh.n_tets, mesh.n_nodes, st["members_padded"], prob.inner_dtype)
-        units = int(inner) * mesh.n_tets  # active element-members over all applications
+        # active element-members over all applications, less those of the
+        # launches on the list of the last active members
+        units = int(inner) * mesh.n_tets - int(st["elems_tail32"])
         n_app = st["n_ebe32"]
         ms = st["ms_ebe32"]
         flops = EBE32_FLOPS_ELEMENT_D if prob.inner_dtype == 2 else EBE32_FLOPS_PER_POINT_D
@@ -460,11 +463,12 @@ def main():
         "iterations": {"outer_per_member_step": float(out_mixed["iters"][:, sl, 0].mean()),
                        "inner_per_member_step": float(out_mixed["iters"][:, sl, 1].mean())},
         "tuning": ({k: tuned.get(k, 0) for k in ("inner_method", "inner_tol", "inner_maxit", "ebe_block", "check_every",
-                                                 "cluster_blocks")
+                                                 "cluster_blocks", "tail_members")
                     if k in tuned} if tuned else None),
         "timed_steps": f"steps {pre + 1}-{n_total} of the record",
         "phase_ms": {"ebe64": st["ms_ebe64"], "ebe32": st["ms_ebe32"], "gather32": st["ms_gather32"],
-                     "law": st["ms_law"], "rhs_diag_q": st["ms_other"]} if not args.no_profile else None,
+                     "tail32": st["ms_tail32"], "law": st["ms_law"], "rhs_diag_q": st["ms_other"]}
+        if not args.no_profile else None,
         "fp64_plain": fp64,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -223,6 +223,10 @@ typedef struct {
     int64_t n_gather32;
     double cheb_lo_min;        /* Chebyshev inner bounds of the last step: smallest lower bound and */
     double cheb_hi_max;        /* largest upper bound over the members (0 without Chebyshev) */
+    double ms_tail32;          /* inner operator on the list of the last active members (element
+                                  kernel and node gather) */
+    int64_t n_tail32;
+    int64_t elems_tail32;      /* element-member pairs of those launches (listed members only) */
 } nlth_stats;
 int nlth_ens_stats(const nlth_ens* ens, nlth_stats* st);
 
@@ -245,7 +249,8 @@ int nlth_ens_stats(const nlth_ens* ens, nlth_stats* st);
  * 0..64, inner_maxit outside 0..100000, inner_tol outside [0, 1), cluster_blocks
  * not 0/2/3/4, scatter outside -1..2 or not available for this ensemble,
  * inner_method outside -1..1, Chebyshev with a degree above 64, zero_copy outside
- * -1..1 or 1 for an ensemble whose state is resident) give NLTH_EINVAL and
+ * -1..1 or 1 for an ensemble whose state is resident, tail_members not -1/0/16/32
+ * or above 0 for an FP64 ensemble or one outside 64..256 slots) give NLTH_EINVAL and
  * change nothing.  Not to be called while the ensemble
  * is stepping on another thread. */
 typedef struct {
@@ -266,6 +271,14 @@ typedef struct {
                                   (default); 1 the law kernel reads and writes the pinned host state
                                   over the host link itself (an ablation of the pipeline; only for an
                                   ensemble whose state is paged) */
+    int32_t tail_members;      /* -1 keep; 0 off; 16 or 32: once at most this many members are
+                                  still iterating in the outer CG, their inner CG runs on compact
+                                  copies of their rows (16 or 32 lanes instead of all member slots);
+                                  results equal the full path's to rounding order.  Mixed precision
+                                  with the element-mean inner D, 64..256 slots, inner CG only
+                                  (default 32 there, 0 elsewhere).  The copies take 32 lanes of
+                                  172 B per element and 84 B per node, allocated at first use; if
+                                  that fails the path stays off for the ensemble */
 } nlth_tuning;
 int nlth_ens_set_tuning(nlth_ens* ens, const nlth_tuning* t);
 int nlth_ens_set_profile(nlth_ens* ens, int32_t profile);

@@ -811,6 +811,7 @@ void Ens::create(Ctx* c, const Mesh* m, const Problem& prob, int member_pad)
     if (P.precision == NLTH_MIXED && P.inner_dtype == NLTH_INNER_BF16) D16.alloc(bg, (size_t)ne_pad * 4 * 11 * MB * 4);
     if (P.precision == NLTH_MIXED && P.inner_dtype == NLTH_INNER_BF16_MEAN) D16.alloc(bg, (size_t)ne_pad * 11 * MB * 4);
     d16_mean = P.inner_dtype == NLTH_INNER_BF16_MEAN;
+    tail_max = P.precision == NLTH_MIXED && MB >= 64 && MB <= 256 && d16_mean ? 32 : 0;
     h.alloc(bg, (size_t)m->ne * MB * 8);
     // operator path: element clusters (64-member groups) when MB is a multiple
     // of 64, element outputs below that, colours above 256 member slots (the
@@ -936,7 +937,13 @@ void Ens::destroy()
     if (g_inner) (void)hipGraphExecDestroy(g_inner);
     if (g_pcg) (void)hipGraphExecDestroy(g_pcg);
     if (g_cheb) (void)hipGraphExecDestroy(g_cheb);
+    for (auto& gt : g_inner_tail) {
+        if (gt) (void)hipGraphExecDestroy(gt);
+        gt = nullptr;
+    }
     g_inner = g_pcg = g_cheb = nullptr;
+    if (h_tlist) (void)hipHostFree(h_tlist);
+    h_tlist = nullptr;
     if (h_flags) (void)hipHostFree(h_flags);
     h_flags = nullptr;
     if (ev_copy0) (void)hipEventDestroy(ev_copy0);
@@ -1109,10 +1116,13 @@ void Ens::inner_solve()
     const int* iact = cs.inner_active;
     const double tol2 = P.inner_tol * P.inner_tol;
     double* pd = partial.as<double>();
-    launch_inner_start(s, mesh->nn, MB, nm, r.as<double>(), pinv32.as<float>(), ir.as<float>(), iz.as<float>(),
-                       ip.as<float>(), iw.as<float>(), iAp.as<float>(), act, pd, &nblk);
+    if (tail_g)
+        launch_tail_start(s, mesh->nn, MB, nm, tail_g, tlist.as<int>(), r.as<double>(), tb.pinv, tb.ir, tb.iz, tb.ip,
+                          act, pd, &nblk);
+    else
+        launch_inner_start(s, mesh->nn, MB, nm, r.as<double>(), pinv32.as<float>(), ir.as<float>(), iz.as<float>(),
+                           ip.as<float>(), iw.as<float>(), iAp.as<float>(), act, pd, &nblk);
     fin(FIN_IN_START, 2, nblk, tol2, P.inner_maxit);
-    (void)n;
     int done_iters = 0;
     while (done_iters < P.inner_maxit) {
         const int chunk = std::min(check_every, P.inner_maxit - done_iters);
@@ -1120,6 +1130,87 @@ void Ens::inner_solve()
         done_iters += chunk;
         if (!read_any_active(iact)) break;
     }
+    // the listed members' result back to the full rows (the others are not
+    // outer-active: the output step writes zero for them)
+    if (tail_g) launch_tail_unpack(s, n, MB, tail_g, tlist.as<int>(), tb.iz, iz.as<float>());
+}
+
+// Choose the inner operator for the next preconditioner calls from the
+// outer-active flags just read into h_flags: with at most tail_max of them,
+// the list goes to the device (count first) and the tail path runs on it.
+void Ens::update_tail()
+{
+    tail_g = 0;
+    if (tail_max <= 0 || inner_method == 1) return;
+    int na = 0;
+    for (int m = 0; m < nm; ++m) na += h_flags[m] != 0;
+    if (na == 0 || na > tail_max) return;
+    if (!tail_mem.p) {
+        // compact rows of 32 lanes: D (elements padded to blocks of 4), h,
+        // material, inverse blocks, five CG vectors, element outputs
+        const size_t ne4 = ((size_t)mesh->ne + 3) / 4 * 4, nn = mesh->nn, L = 32;
+        const size_t sz[11] = {ne4 * 11 * L * 4, (size_t)mesh->ne * L * 8, (size_t)P.nl * MAT_N * L * 8,
+                               nn * 6 * L * 4, nn * 3 * L * 4, nn * 3 * L * 4, nn * 3 * L * 4, nn * 3 * L * 4,
+                               nn * 3 * L * 4, (size_t)mesh->ne * 30 * L * 4, 0};
+        size_t off[11], tot = 0;
+        for (int i = 0; i < 11; ++i) {
+            off[i] = tot;
+            tot += (sz[i] + 255) / 256 * 256;
+        }
+        try {
+            tail_mem.alloc(&ctx->budget, tot);
+            tlist.alloc(&ctx->budget, (size_t)(1 + MB) * 4);
+        } catch (const Error&) {  // no room: keep the full operator
+            tail_mem.release();
+            tlist.release();
+            tail_max = 0;
+            return;
+        }
+        char* b = (char*)tail_mem.p;
+        tb.D = (uint32_t*)(b + off[0]);
+        tb.h = (double*)(b + off[1]);
+        tb.mat = (double*)(b + off[2]);
+        tb.pinv = (float*)(b + off[3]);
+        tb.ir = (float*)(b + off[4]);
+        tb.iz = (float*)(b + off[5]);
+        tb.ip = (float*)(b + off[6]);
+        tb.w = (float*)(b + off[7]);
+        tb.Ap = (float*)(b + off[8]);
+        tb.f = (float*)(b + off[9]);
+        NLTH_HIP(hipHostMalloc((void**)&h_tlist, sizeof(int) * (1 + MB), hipHostMallocDefault));
+    }
+    h_tlist[0] = na;
+    int k = 1;
+    for (int m = 0; m < nm; ++m)
+        if (h_flags[m]) h_tlist[k++] = m;
+    // the previous list copy has completed: the caller synchronised to read h_flags
+    NLTH_HIP(hipMemcpyAsync(tlist.p, h_tlist, sizeof(int) * (1 + na), hipMemcpyHostToDevice, s));
+    tail_g = na <= 16 ? 16 : 32;
+    launch_tail_pack(s, mesh->dev(), MB, tail_g, P.nl, tlist.as<int>(), D16.as<uint32_t>(), h.as<double>(),
+                     mat.as<double>(), pinv32.as<float>(), tb.D, tb.h, tb.mat, tb.pinv);
+}
+
+// one inner CG iteration of the listed members on the compact rows: the
+// operator (element outputs, node sums, dashpot), then the updates of the
+// full path with the same per-member stage logic
+void Ens::tail_iter()
+{
+    const DevMesh dm = mesh->dev();
+    const int* tl = tlist.as<int>();
+    const int* iact = cs.inner_active;
+    const double tol2 = P.inner_tol * P.inner_tol;
+    double* pd = partial.as<double>();
+    int nblk;
+    hipEvent_t t0;
+    tstart(t0);
+    launch_ebe32_tail(s, dm, tail_g, tl, tb.D, tb.h, tb.mat, sc, tb.ip, tb.f);
+    launch_gather_tail(s, dm, MB, nm, tail_g, tl, tb.f, tb.Ap, iact, tb.ip, pd, &nblk);
+    launch_dashpot_tail(s, dm, MB, nm, tail_g, tl, tb.mat, (float)(2.0 / P.dt), tb.ip, tb.Ap, iact, pd, &nblk);
+    tstop(t0, &pc_tail32, (int64_t)mesh->ne * h_tlist[0]);
+    fin(FIN_IN_ALPHA, 1, nblk, tol2, P.inner_maxit);
+    launch_tail_update(s, mesh->nn, MB, nm, tail_g, tl, tb.ir, tb.w, tb.Ap, tb.pinv, cs.ialpha, iact, pd, &nblk);
+    fin(FIN_IN_BETA, 2, nblk, tol2, P.inner_maxit);
+    launch_tail_pz(s, ndof, nm, tail_g, tl, tb.iz, tb.ip, tb.w, cs.ialpha, cs.ibeta, cs.inner_upd);
 }
 
 // Chebyshev inner solve of degree inner_maxit for the outer-active members,
@@ -1224,6 +1315,10 @@ void Ens::cheb_solve()
 // one inner FP32 PCG iteration (every launch reads its scalars on the device)
 void Ens::inner_iter()
 {
+    if (tail_g) {
+        tail_iter();
+        return;
+    }
     const long n = ndof;
     int nblk;
     const int* iact = cs.inner_active;
@@ -1263,7 +1358,7 @@ void Ens::run_iters(int kind, int k)
         for (int i = 0; i < k; ++i) kind == 0 ? inner_iter() : pcg_iter();
         return;
     }
-    hipGraphExec_t& ge = kind == 0 ? g_inner : g_pcg;
+    hipGraphExec_t& ge = kind == 1 ? g_pcg : (tail_g ? g_inner_tail[tail_g == 16 ? 0 : 1] : g_inner);
     if (!ge) {
         hipGraph_t g = nullptr;
         NLTH_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -1297,6 +1392,7 @@ void Ens::solve_fcg()
     const int* act = cs.active;
     const double tol2 = P.cg_tol * P.cg_tol;
     double* pd = partial.as<double>();
+    tail_g = 0;
     apply_A64(x, Ap.as<double>(), st);
     launch_pcg_start(s, mesh->nn, MB, nm, b.as<double>(), Ap.as<double>(), pinv.as<double>(), r.as<double>(),
                      z.as<double>(), p.as<double>(), st, pd, &nblk);
@@ -1307,6 +1403,7 @@ void Ens::solve_fcg()
     }
     launch_zero_if_b0(s, n, MB, nm, x, cs.bb, st);
     if (!read_any_active(act)) return;
+    update_tail();
     inner_solve();
     // Chebyshev for the later preconditioner calls of this step: spectrum
     // bounds of each member from the Lanczos matrix of the CG solve just done
@@ -1323,6 +1420,7 @@ void Ens::solve_fcg()
         launch_xr_update(s, n, MB, nm, x, r.as<double>(), p.as<double>(), Ap.as<double>(), cs.alpha, act, pd, &nblk);
         fin(FIN_FCG_RR, 1, nblk, tol2, P.cg_maxit);
         if (!read_any_active(act)) break;
+        update_tail();
         if (cheb) cheb_solve();
         else inner_solve();
         launch_inner_out(s, n, MB, nm, iz.as<float>(), z.as<double>(), Ap.as<double>(), r.as<double>(), act, pd,
@@ -1330,6 +1428,7 @@ void Ens::solve_fcg()
         fin(FIN_FCG_BETA, 2, nblk, tol2, P.cg_maxit);
         launch_p_update<double>(s, n, MB, nm, z.as<double>(), p.as<double>(), cs.beta, act, nullptr);
     }
+    tail_g = 0;
 }
 
 void Ens::law_phase()
@@ -1711,6 +1810,11 @@ int nlth_ens_set_tuning(nlth_ens* ens, const nlth_tuning* t)
         throw Error{NLTH_EINVAL, "scatter: element outputs need fewer than 64 member slots, clusters 64..256"};
     if (t->inner_method < -1 || t->inner_method > 1) throw Error{NLTH_EINVAL, "inner_method must be -1, 0 or 1"};
     if (t->zero_copy < -1 || t->zero_copy > 1) throw Error{NLTH_EINVAL, "zero_copy must be -1, 0 or 1"};
+    if (t->tail_members != -1 && t->tail_members != 0 && t->tail_members != 16 && t->tail_members != 32)
+        throw Error{NLTH_EINVAL, "tail_members must be -1, 0, 16 or 32"};
+    if (t->tail_members > 0 && (ens->MB < 64 || ens->MB > 256 || ens->P.precision != NLTH_MIXED || !ens->d16_mean))
+        throw Error{NLTH_EINVAL, "tail_members needs a mixed-precision ensemble of 64..256 member slots with the "
+                                 "element-mean inner D"};
     if (t->zero_copy == 1 && !ens->paged) throw Error{NLTH_EINVAL, "zero_copy needs an ensemble whose law state is paged"};
     if ((t->inner_method == 1 || (t->inner_method == -1 && ens->inner_method == 1)) &&
         (t->inner_maxit ? t->inner_maxit : ens->P.inner_maxit) > kChebMax)
@@ -1725,11 +1829,17 @@ int nlth_ens_set_tuning(nlth_ens* ens, const nlth_tuning* t)
     if (t->cluster_blocks > 0) ens->cluster_blocks = t->cluster_blocks;
     if (t->inner_method >= 0) ens->inner_method = t->inner_method;
     if (t->zero_copy >= 0) ens->zero_copy = t->zero_copy != 0;
+    if (t->tail_members >= 0) ens->tail_max = t->tail_members;
+    ens->tail_g = 0;
     // captured chunks hold the old launch shapes
     if (ens->g_inner) (void)hipGraphExecDestroy(ens->g_inner);
     if (ens->g_pcg) (void)hipGraphExecDestroy(ens->g_pcg);
     if (ens->g_cheb) (void)hipGraphExecDestroy(ens->g_cheb);
     ens->g_inner = ens->g_pcg = ens->g_cheb = nullptr;
+    for (auto& gt : ens->g_inner_tail) {
+        if (gt) (void)hipGraphExecDestroy(gt);
+        gt = nullptr;
+    }
     return NLTH_OK;
     API_END
 }
@@ -1737,7 +1847,8 @@ int nlth_ens_set_tuning(nlth_ens* ens, const nlth_tuning* t)
 int nlth_ens_reset_stats(nlth_ens* ens)
 {
     if (!ens) return NLTH_EINVAL;
-    ens->pc_ebe64 = ens->pc_ebe32 = ens->pc_gather32 = ens->pc_vec = ens->pc_law = ens->pc_other = ProfCat{};
+    ens->pc_ebe64 = ens->pc_ebe32 = ens->pc_gather32 = ens->pc_vec = ens->pc_law = ens->pc_other = ens->pc_tail32 =
+        ProfCat{};
     ens->ms_total = ens->ms_copy = 0;
     ens->h2d_bytes = ens->d2h_bytes = 0;
     return NLTH_OK;
@@ -1778,6 +1889,9 @@ int nlth_ens_stats(const nlth_ens* ens, nlth_stats* st)
     st->host_bytes = ens->host_bytes;
     st->ms_gather32 = ens->pc_gather32.ms;
     st->n_gather32 = ens->pc_gather32.n;
+    st->ms_tail32 = ens->pc_tail32.ms;
+    st->n_tail32 = ens->pc_tail32.n;
+    st->elems_tail32 = ens->pc_tail32.elems;
     if (ens->cheb_bounds.p && ens->inner_method == 1) {
         std::vector<double> bd((size_t)2 * ens->MB);
         NLTH_HIP(hipMemcpy(bd.data(), ens->cheb_bounds.p, bd.size() * 8, hipMemcpyDeviceToHost));

@@ -644,6 +644,7 @@ __global__ __launch_bounds__(256) void k_gather(DevMesh M, int MB, int nm, const
         T a0 = 0, a1 = 0, a2 = 0;
         if (CL) {  // cluster rows of the node, ascending
             const int q1 = M.cn_ptr[node + 1];
+#pragma unroll 4
             for (int q = M.cn_ptr[node]; q < q1; ++q) {
                 const T* fb = f + (size_t)M.cn_row[q] * 3 * MB + m;
                 a0 += fb[0];
@@ -652,6 +653,7 @@ __global__ __launch_bounds__(256) void k_gather(DevMesh M, int MB, int nm, const
             }
         } else {  // element outputs of the node, ascending
             const int q1 = M.inc_ptr[node + 1];
+#pragma unroll 4
             for (int q = M.inc_ptr[node]; q < q1; ++q) {
                 const int ent = M.inc[q];
                 const int e = ent / 10, k = ent - 10 * e;
@@ -757,6 +759,150 @@ void launch_ebe32(hipStream_t s, const DevMesh& M, int MB, int nm, int e0, int e
     if (D16 && d16_mean) ebe_dispatch<float, 4, OP_A>(s, M, MB, nm, e0, e1, D16, h, mat, sc, x, nullptr, y, active, out);
     else if (D16) ebe_dispatch<float, 1, OP_A>(s, M, MB, nm, e0, e1, D16, h, mat, sc, x, nullptr, y, active, out);
     else ebe_dispatch<float, 0, OP_A>(s, M, MB, nm, e0, e1, D32, h, mat, sc, x, nullptr, y, active, out);
+}
+
+// ---------------------------------------------------------------------------
+// convergence tail: once at most G (16 or 32) members are still iterating in
+// the outer CG, their inner solve runs on compact copies, lane k of a row being
+// member tl[1 + k] (tl[0] = the count): the member-innermost rows of the full
+// arrays would otherwise be fetched whole for a few members each.  D, h, the
+// material rows and the block-Jacobi inverse are packed once per outer
+// iteration; the operator writes compact element outputs, summed per node into
+// a compact result.  Partial sums keep the full [block][MB] layout (zero for
+// members not listed), so the per-member stage logic is the same.
+// ---------------------------------------------------------------------------
+
+// rows of a member-innermost array, listed members only: compact row rc of G
+// lanes <-> full row r of MB lanes.  With EBc > 1 the rows are W per element
+// and the compact copy is blocked by EBc elements (the D layout of G slots).
+template <typename T, bool UNPACK>
+__global__ __launch_bounds__(256) void k_tail_rows(long nrows, int MB, int G, int W, int EBc,
+                                                  const int* __restrict__ tl, const T* __restrict__ src,
+                                                  T* __restrict__ dst)
+{
+    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const int k = (int)(t % G);
+    const long r = t / G;
+    if (r >= nrows || k >= min(tl[0], G)) return;
+    const int m = tl[1 + k];
+    long rc = r;
+    if (EBc > 1) {
+        const long e = r / W;
+        rc = ((e / EBc) * W + (r - e * W)) * EBc + e % EBc;
+    }
+    if (UNPACK) dst[r * MB + m] = src[rc * G + k];
+    else dst[rc * G + k] = src[r * MB + m];
+}
+
+template <typename T>
+static void tail_rows(hipStream_t s, long nrows, int MB, int G, int W, int EBc, const int* tl, const T* src, T* dst,
+                      bool unpack)
+{
+    const long n = nrows * G;
+    if (n <= 0) return;
+    if (unpack)
+        hipLaunchKernelGGL((k_tail_rows<T, true>), dim3(nblocks(n)), dim3(256), 0, s, nrows, MB, G, W, EBc, tl, src, dst);
+    else
+        hipLaunchKernelGGL((k_tail_rows<T, false>), dim3(nblocks(n)), dim3(256), 0, s, nrows, MB, G, W, EBc, tl, src, dst);
+}
+
+void launch_tail_pack(hipStream_t s, const DevMesh& M, int MB, int G, int n_layers, const int* tl,
+                      const uint32_t* D16, const double* h, const double* mat, const float* pinv32, uint32_t* cD,
+                      double* ch, double* cmat, float* cpinv)
+{
+    tail_rows<uint32_t>(s, (long)M.ne * 11, MB, G, 11, 64 / G, tl, D16, cD, false);
+    if (h) tail_rows<double>(s, M.ne, MB, G, 1, 1, tl, h, ch, false);
+    tail_rows<double>(s, (long)n_layers * MAT_N, MB, G, 1, 1, tl, mat, cmat, false);
+    tail_rows<float>(s, (long)M.nn * 6, MB, G, 1, 1, tl, pinv32, cpinv, false);
+}
+
+void launch_tail_unpack(hipStream_t s, long nrows, int MB, int G, const int* tl, const float* c, float* full)
+{
+    tail_rows<float>(s, nrows, MB, G, 1, 1, tl, c, full, true);
+}
+
+// inner operator A on the compact rows: lane (element, k), element-mean D;
+// outputs f[(e * 30 + 3n + c) * G + k]
+template <int G>
+__global__ __launch_bounds__(256) void k_ebe_tail(DevMesh M, const int* __restrict__ tl,
+                                                 const uint32_t* __restrict__ cD, const double* __restrict__ ch,
+                                                 const double* __restrict__ cmat, StepConst sc,
+                                                 const float* __restrict__ x, float* __restrict__ f)
+{
+    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const int k = (int)(t % G);
+    const long e = t / G;
+    if (e >= M.ne || k >= min(tl[0], G)) return;
+    float fe[10][3];
+    size_t nbase[10];
+    ebe_element<float, 4, OP_A>(M, G, k, e, cD, ch, cmat, sc, x, nullptr, fe, nbase);
+    float* fb = f + (size_t)e * 30 * G + k;
+#pragma unroll
+    for (int n = 0; n < 10; ++n)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) fb[(3 * n + c) * G] = fe[n][c];
+}
+
+void launch_ebe32_tail(hipStream_t s, const DevMesh& M, int G, const int* tl, const uint32_t* cD, const double* ch,
+                       const double* cmat, StepConst sc, const float* x, float* f)
+{
+    const long n = (long)M.ne * G;
+    if (n <= 0) return;
+    if (G == 16) hipLaunchKernelGGL((k_ebe_tail<16>), dim3(nblocks(n)), dim3(256), 0, s, M, tl, cD, ch, cmat, sc, x, f);
+    else hipLaunchKernelGGL((k_ebe_tail<32>), dim3(nblocks(n)), dim3(256), 0, s, M, tl, cD, ch, cmat, sc, x, f);
+}
+
+// node sums of the compact element outputs (incidences in ascending order)
+// into the compact y of the listed, active members; with partial, the x . y
+// partials of the block's nodes
+template <int G>
+__global__ __launch_bounds__(256) void k_gather_tail(DevMesh M, int MB, int nm, const int* __restrict__ tl,
+                                                    const float* __restrict__ fc, float* __restrict__ y,
+                                                    const int* __restrict__ active, const float* __restrict__ x,
+                                                    double* __restrict__ partial)
+{
+    constexpr int NPB = 256 / G;  // nodes per block pass
+    const int t = threadIdx.x, k = t % G, slot = t / G;
+    const int m = k < min(tl[0], G) ? tl[1 + k] : -1;
+    const bool act = m >= 0 && m < nm && (!active || active[m]);
+    double dot = 0.0;
+    const long per = ((M.nn + gridDim.x - 1) / gridDim.x + NPB - 1) / NPB * NPB;
+    const long n0 = (long)blockIdx.x * per, n1 = n0 + per < M.nn ? n0 + per : M.nn;
+    if (act) {
+        for (long nd = n0 + slot; nd < n1; nd += NPB) {
+            float a0 = 0, a1 = 0, a2 = 0;
+            const int q1 = M.inc_ptr[nd + 1];
+#pragma unroll 4
+            for (int q = M.inc_ptr[nd]; q < q1; ++q) {
+                // incidence e * 10 + local node: its output rows start at 3 * incidence
+                const float* fb = fc + (size_t)3 * M.inc[q] * G + k;
+                a0 += fb[0];
+                a1 += fb[G];
+                a2 += fb[2 * G];
+            }
+            const size_t yi = (size_t)nd * 3 * G + k;
+            y[yi] = a0;
+            y[yi + G] = a1;
+            y[yi + 2 * G] = a2;
+            if (partial)
+                dot += (double)x[yi] * (double)a0 + (double)x[yi + G] * (double)a1 + (double)x[yi + 2 * G] * (double)a2;
+        }
+    }
+    if (partial) {
+        double acc[1] = {dot};
+        tail_partials<1, G>(acc, MB, m, partial, 0, gridDim.x);
+    }
+}
+
+void launch_gather_tail(hipStream_t s, const DevMesh& M, int MB, int nm, int G, const int* tl, const float* fc,
+                        float* y, const int* active, const float* x, double* partial, int* nblk)
+{
+    const int g = gather_blocks(M.nn, G, partial ? kGatherBlocks : (1 << 24));
+    if (partial) *nblk = g;
+    if (G == 16)
+        hipLaunchKernelGGL((k_gather_tail<16>), dim3(g), dim3(256), 0, s, M, MB, nm, tl, fc, y, active, x, partial);
+    else
+        hipLaunchKernelGGL((k_gather_tail<32>), dim3(g), dim3(256), 0, s, M, MB, nm, tl, fc, y, active, x, partial);
 }
 
 template <typename T>
@@ -887,6 +1033,58 @@ template void launch_dashpot<double>(hipStream_t, const DevMesh&, int, int, cons
 template void launch_dashpot<float>(hipStream_t, const DevMesh&, int, int, const double*, int, float,
                                     const float*, float*, const double*, const int*, double*, int*);
 
+// dashpot of the compact rows (material rows packed, lane k = member tl[1 + k]):
+// y += coef C x at the boundary nodes for the listed, active members; partials
+// of x . (C x) appended after the boff blocks already written
+template <int G>
+__global__ __launch_bounds__(256) void k_dashpot_tail(DevMesh M, int MB, int nm, const int* __restrict__ tl,
+                                                     const double* __restrict__ cmat, double coef,
+                                                     const float* __restrict__ x, float* __restrict__ y,
+                                                     const int* __restrict__ active, double* __restrict__ partial,
+                                                     int boff, int nblk)
+{
+    constexpr int NPB = 256 / G;
+    const int t = threadIdx.x, k = t % G;
+    const int m = k < min(tl[0], G) ? tl[1 + k] : -1;
+    const bool act = m >= 0 && m < nm && (!active || active[m]);
+    double dot = 0.0;
+    if (act) {
+        for (long i = (long)blockIdx.x * NPB + t / G; i < M.nbn; i += (long)gridDim.x * NPB) {
+            const int node = M.bn_node[i];
+            double acc[3] = {0, 0, 0};
+            dashpot_at<float>(M, G, k, (int)i, cmat, coef, x, nullptr, acc);
+            for (int c = 0; c < 3; ++c) {
+                const size_t yi = ((size_t)node * 3 + c) * G + k;
+                y[yi] += (float)acc[c];
+                if (partial) dot += (double)x[yi] * (double)(float)acc[c];
+            }
+        }
+    }
+    if (partial) {
+        double a1[1] = {dot};
+        tail_partials<1, G>(a1, MB, m, partial, boff, nblk);
+    }
+}
+
+void launch_dashpot_tail(hipStream_t s, const DevMesh& M, int MB, int nm, int G, const int* tl, const double* cmat,
+                         float coef, const float* x, float* y, const int* active, double* partial, int* nblk)
+{
+    if (M.nbn <= 0) return;
+    const long rpb = 256 / G;
+    long g = ((long)M.nbn + rpb - 1) / rpb;
+    g = g < kDashpotBlocks ? g : kDashpotBlocks;
+    const int boff = partial ? *nblk : 0;
+    // the partials of one part: rows boff .. boff + g of the gather's layout,
+    // so the row count passed as nblk is irrelevant for part 0
+    if (G == 16)
+        hipLaunchKernelGGL((k_dashpot_tail<16>), dim3(g), dim3(256), 0, s, M, MB, nm, tl, cmat, (double)coef, x, y,
+                           active, partial, boff, 0);
+    else
+        hipLaunchKernelGGL((k_dashpot_tail<32>), dim3(g), dim3(256), 0, s, M, MB, nm, tl, cmat, (double)coef, x, y,
+                           active, partial, boff, 0);
+    if (partial) *nblk += (int)g;
+}
+
 // dashpot rows of the boundary nodes for the fused Chebyshev gather:
 // qb[(i * 3 + c) * MB + m] = (dashpot x)(boundary node i), active members only
 __global__ __launch_bounds__(256) void k_dashpot_rows(DevMesh M, int MB, int nm, const double* __restrict__ mat,
@@ -941,6 +1139,7 @@ __global__ __launch_bounds__(256) void k_gather_cheb(DevMesh M, int MB, int nm, 
         const int node = __builtin_amdgcn_readfirstlane((int)nd);
         float a0 = 0, a1 = 0, a2 = 0;
         const int q1 = M.cn_ptr[node + 1];
+#pragma unroll 4
         for (int q = M.cn_ptr[node]; q < q1; ++q) {
             const float* fb = rows + (size_t)M.cn_row[q] * 3 * MB + m;
             a0 += fb[0];

@@ -132,6 +132,27 @@ void launch_zero_member(hipStream_t s, double* p, long rows, int MB, int m);
 void set_ebe_block(int bs);
 // blocks per CU of the cluster launches on this host thread
 void set_cluster_blocks(int b);
+// convergence tail: the inner solve of at most G (16 or 32) listed members on
+// compact rows (lane k = member tl[1 + k], tl[0] = the count); partial sums in
+// the full [block][MB] layout
+void launch_tail_pack(hipStream_t s, const DevMesh& M, int MB, int G, int n_layers, const int* tl,
+                      const uint32_t* D16, const double* h, const double* mat, const float* pinv32, uint32_t* cD,
+                      double* ch, double* cmat, float* cpinv);
+void launch_tail_unpack(hipStream_t s, long nrows, int MB, int G, const int* tl, const float* c, float* full);
+void launch_ebe32_tail(hipStream_t s, const DevMesh& M, int G, const int* tl, const uint32_t* cD, const double* ch,
+                       const double* cmat, StepConst sc, const float* x, float* f);
+void launch_gather_tail(hipStream_t s, const DevMesh& M, int MB, int nm, int G, const int* tl, const float* fc,
+                        float* y, const int* active, const float* x, double* partial, int* nblk);
+void launch_dashpot_tail(hipStream_t s, const DevMesh& M, int MB, int nm, int G, const int* tl, const double* cmat,
+                         float coef, const float* x, float* y, const int* active, double* partial, int* nblk);
+void launch_tail_start(hipStream_t s, int nn, int MB, int nm, int G, const int* tl, const double* r,
+                       const float* cpinv, float* cir, float* ciz, float* cip, const int* active, double* partial,
+                       int* nblk);
+void launch_tail_update(hipStream_t s, int nn, int MB, int nm, int G, const int* tl, float* cir, float* cw,
+                        const float* ciAp, const float* cpinv, const double* ialpha, const int* iactive,
+                        double* partial, int* nblk);
+void launch_tail_pz(hipStream_t s, long nrows, int nm, int G, const int* tl, float* ciz, float* cip, const float* cw,
+                    const double* ialpha, const double* ibeta, const int* upd);
 // inner FP32 operator (A) with D in FP32 (D32) or bfloat16 pairs (D16, if non-null)
 void launch_ebe32(hipStream_t s, const DevMesh& M, int MB, int nm, int e0, int e1, const float* D32,
                   const uint32_t* D16, const double* h, const double* mat, StepConst sc, const float* x, float* y,
@@ -178,6 +199,38 @@ enum FinalizeStage {
     FIN_CHEB_COUNT,  // (-): inner_total += degree for the outer-active members
     FIN_EST_START    // (ir.ir, ir.w) inner CG start on a random vector, for the members in this step
 };
+// per-member block partials of a compact kernel: lane k's sum over the block's
+// rows (a fixed tree in LDS) goes to partial[(j * gridDim + blockIdx) * MB +
+// tl[1 + k]], zero for the members not listed
+template <int ND, int G>
+__device__ __forceinline__ void tail_partials(double acc[ND], int MB, int m, double* __restrict__ partial, int boff,
+                                              int nblk)
+{
+    __shared__ double sh[ND][256];
+    __shared__ double pm[ND][256];
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < ND; ++j) sh[j][t] = acc[j];
+    __syncthreads();
+    for (int s = 128; s >= G; s >>= 1) {  // s a multiple of G: lane k stays lane k
+        if (t < s)
+#pragma unroll
+            for (int j = 0; j < ND; ++j) sh[j][t] += sh[j][t + s];
+        __syncthreads();
+    }
+    if (t < MB)
+#pragma unroll
+        for (int j = 0; j < ND; ++j) pm[j][t] = 0.0;
+    __syncthreads();
+    if (t < G && m >= 0 && m < MB)
+#pragma unroll
+        for (int j = 0; j < ND; ++j) pm[j][m] = sh[j][t];  // listed members are distinct
+    __syncthreads();
+    if (t < MB)
+#pragma unroll
+        for (int j = 0; j < ND; ++j) partial[((size_t)j * nblk + boff + blockIdx.x) * MB + t] = pm[j][t];
+}
+
 void launch_finalize(hipStream_t s, FinalizeStage st, int nd, int MB, int nm, const double* partial, int nblk,
                      CgScalars cs, double tol2, int maxit);
 

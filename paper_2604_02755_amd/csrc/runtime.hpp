@@ -101,6 +101,18 @@ struct Ens {
     DevBuf ir, iz, ip, iw, iAp;
     DevBuf lz, chebc, cheb_bounds, qb;  // inner CG coefficients, Chebyshev table and bounds, dashpot rows
     int inner_method = 0;               // 0: inner CG; 1: Chebyshev after one inner CG per step
+    // convergence tail: with at most tail_max (16 or 32; 0 off) members still
+    // active, the inner operator runs on their list only (tail_g lanes per element)
+    int tail_max = 0, tail_g = 0;      // tail_max: 32 for mixed ensembles of 64..256 slots
+    DevBuf tlist, tail_mem;             // [1 + MB] count then member indices; compact copies
+    struct {                            // in tail_mem, G <= 32 lanes per row
+        uint32_t* D;                    // element-mean D, element blocks of 64 / G
+        double *h, *mat;
+        float *pinv, *ir, *iz, *ip, *w, *Ap, *f;
+    } tb{};
+    int* h_tlist = nullptr;             // pinned staging of the list
+    void update_tail();                 // from h_flags (the outer-active members just read)
+    void tail_iter();                   // one inner CG iteration on the compact rows
     double cheb_lo = 1.0, cheb_hi = 1.05;  // scales of the Lanczos extreme eigenvalues of a step's first inner CG
     double cheb_est_scale = 1.1;           // scale of the random-start estimate of the largest eigenvalue
     int cheb_est_iters = 20, cheb_est_every = 32, cheb_est_age = -1;  // -1: no estimate yet
@@ -133,7 +145,7 @@ struct Ens {
     int check_every = 8;
     // profiling
     bool profile = false;
-    ProfCat pc_ebe64, pc_ebe32, pc_gather32, pc_vec, pc_law, pc_other;
+    ProfCat pc_ebe64, pc_ebe32, pc_gather32, pc_vec, pc_law, pc_other, pc_tail32;
     std::vector<std::pair<std::pair<hipEvent_t, hipEvent_t>, ProfCat*>> pending;
     std::vector<hipEvent_t> ev_pool;
     double ms_total = 0, ms_copy = 0;
@@ -169,7 +181,7 @@ struct Ens {
     void pcg_iter();
     void run_iters(int kind, int k);
     bool use_graph = true;
-    hipGraphExec_t g_inner = nullptr, g_pcg = nullptr, g_cheb = nullptr;
+    hipGraphExec_t g_inner = nullptr, g_pcg = nullptr, g_cheb = nullptr, g_inner_tail[2] = {nullptr, nullptr};
     int ebe_block = 256;
     int cluster_blocks = 3;             // co-resident cluster blocks per CU
     void fin(FinalizeStage st, int nd, int nblk, double tol2, int maxit);

@@ -589,6 +589,128 @@ void launch_inner_out(hipStream_t s, long nrows, int MB, int nm, const float* iz
 }
 
 // ---------------------------------------------------------------------------
+// inner CG of the convergence tail on compact rows (lane k = member tl[1 + k],
+// G lanes per row): the start, update and p/z steps above, partials in the
+// full [block][MB] layout
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int tail_member(const int* __restrict__ tl, int k, int G)
+{
+    return k < min(tl[0], G) ? tl[1 + k] : -1;
+}
+
+template <int G>
+__global__ __launch_bounds__(256) void k_tail_start(int nn, int MB, int nm, const int* __restrict__ tl,
+                                                   const double* __restrict__ r, const float* __restrict__ cpinv,
+                                                   float* __restrict__ cir, float* __restrict__ ciz,
+                                                   float* __restrict__ cip, const int* __restrict__ active,
+                                                   double* __restrict__ partial)
+{
+    constexpr int NPB = 256 / G;
+    const int t = threadIdx.x, k = t % G;
+    const int m = tail_member(tl, k, G);
+    double acc[2] = {0.0, 0.0};
+    if (m >= 0 && m < nm && (!active || active[m])) {
+        for (long node = (long)blockIdx.x * NPB + t / G; node < nn; node += (long)gridDim.x * NPB) {
+            Pk<float, 1> R[3], W[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) R[c].a[0] = (float)r[(node * 3 + c) * MB + m];
+            pinv_apply<float, 1>(cpinv, node, G, k, R, W);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const long i = (node * 3 + c) * G + k;
+                cir[i] = R[c].a[0];
+                ciz[i] = 0.0f;
+                cip[i] = W[c].a[0];
+                acc[0] += (double)R[c].a[0] * (double)R[c].a[0];
+                acc[1] += (double)R[c].a[0] * (double)W[c].a[0];
+            }
+        }
+    }
+    tail_partials<2, G>(acc, MB, m, partial, 0, gridDim.x);
+}
+
+template <int G>
+__global__ __launch_bounds__(256) void k_tail_update(int nn, int MB, int nm, const int* __restrict__ tl,
+                                                    float* __restrict__ cir, float* __restrict__ cw,
+                                                    const float* __restrict__ ciAp, const float* __restrict__ cpinv,
+                                                    const double* __restrict__ ialpha,
+                                                    const int* __restrict__ iactive, double* __restrict__ partial)
+{
+    constexpr int NPB = 256 / G;
+    const int t = threadIdx.x, k = t % G;
+    const int m = tail_member(tl, k, G);
+    double acc[2] = {0.0, 0.0};
+    if (m >= 0 && m < nm && iactive[m]) {
+        const float al = (float)ialpha[m];
+        for (long node = (long)blockIdx.x * NPB + t / G; node < nn; node += (long)gridDim.x * NPB) {
+            Pk<float, 1> R[3], W[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const long i = (node * 3 + c) * G + k;
+                R[c].a[0] = cir[i] - al * ciAp[i];
+                cir[i] = R[c].a[0];
+            }
+            pinv_apply<float, 1>(cpinv, node, G, k, R, W);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                cw[(node * 3 + c) * G + k] = W[c].a[0];
+                acc[0] += (double)R[c].a[0] * (double)R[c].a[0];
+                acc[1] += (double)R[c].a[0] * (double)W[c].a[0];
+            }
+        }
+    }
+    tail_partials<2, G>(acc, MB, m, partial, 0, gridDim.x);
+}
+
+template <int G>
+__global__ __launch_bounds__(256) void k_tail_pz(long nrows, int nm, const int* __restrict__ tl,
+                                                float* __restrict__ ciz, float* __restrict__ cip,
+                                                const float* __restrict__ cw, const double* __restrict__ ialpha,
+                                                const double* __restrict__ ibeta, const int* __restrict__ upd)
+{
+    constexpr int NPB = 256 / G;
+    const int t = threadIdx.x, k = t % G;
+    const int m = tail_member(tl, k, G);
+    if (m < 0 || m >= nm || !upd[m]) return;
+    const float al = (float)ialpha[m], be = (float)ibeta[m];
+    for (long row = (long)blockIdx.x * NPB + t / G; row < nrows; row += (long)gridDim.x * NPB) {
+        const long i = row * G + k;
+        const float P = cip[i];
+        ciz[i] += al * P;
+        cip[i] = cw[i] + be * P;
+    }
+}
+
+void launch_tail_start(hipStream_t s, int nn, int MB, int nm, int G, const int* tl, const double* r,
+                       const float* cpinv, float* cir, float* ciz, float* cip, const int* active, double* partial,
+                       int* nblk)
+{
+    const int g = grid_for(nn, 256 / G);
+    *nblk = g;
+    if (G == 16) hipLaunchKernelGGL((k_tail_start<16>), dim3(g), dim3(256), 0, s, nn, MB, nm, tl, r, cpinv, cir, ciz, cip, active, partial);
+    else hipLaunchKernelGGL((k_tail_start<32>), dim3(g), dim3(256), 0, s, nn, MB, nm, tl, r, cpinv, cir, ciz, cip, active, partial);
+}
+
+void launch_tail_update(hipStream_t s, int nn, int MB, int nm, int G, const int* tl, float* cir, float* cw,
+                        const float* ciAp, const float* cpinv, const double* ialpha, const int* iactive,
+                        double* partial, int* nblk)
+{
+    const int g = grid_for(nn, 256 / G);
+    *nblk = g;
+    if (G == 16) hipLaunchKernelGGL((k_tail_update<16>), dim3(g), dim3(256), 0, s, nn, MB, nm, tl, cir, cw, ciAp, cpinv, ialpha, iactive, partial);
+    else hipLaunchKernelGGL((k_tail_update<32>), dim3(g), dim3(256), 0, s, nn, MB, nm, tl, cir, cw, ciAp, cpinv, ialpha, iactive, partial);
+}
+
+void launch_tail_pz(hipStream_t s, long nrows, int nm, int G, const int* tl, float* ciz, float* cip, const float* cw,
+                    const double* ialpha, const double* ibeta, const int* upd)
+{
+    const int g = grid_for(nrows, 256 / G);
+    if (G == 16) hipLaunchKernelGGL((k_tail_pz<16>), dim3(g), dim3(256), 0, s, nrows, nm, tl, ciz, cip, cw, ialpha, ibeta, upd);
+    else hipLaunchKernelGGL((k_tail_pz<32>), dim3(g), dim3(256), 0, s, nrows, nm, tl, ciz, cip, cw, ialpha, ibeta, upd);
+}
+
+// ---------------------------------------------------------------------------
 // Chebyshev inner solve: A z = r by the Chebyshev iteration on the block-
 // Jacobi preconditioned operator (Saad, Iterative Methods for Sparse Linear
 // Systems, 2nd ed., Algorithm 12.1), with the spectrum bounds of each member

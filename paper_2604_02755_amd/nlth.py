@@ -71,7 +71,8 @@ class nlth_problem(C.Structure):
 class nlth_tuning(C.Structure):
     _fields_ = [("ebe_block", C.c_int32), ("check_every", C.c_int32), ("use_graph", C.c_int32),
                 ("inner_maxit", C.c_int32), ("inner_tol", C.c_double), ("scatter", C.c_int32),
-                ("cluster_blocks", C.c_int32), ("inner_method", C.c_int32), ("zero_copy", C.c_int32)]
+                ("cluster_blocks", C.c_int32), ("inner_method", C.c_int32), ("zero_copy", C.c_int32),
+                ("tail_members", C.c_int32)]
 
 
 class nlth_result(C.Structure):
@@ -87,7 +88,8 @@ class nlth_stats(C.Structure):
                 ("h2d_bytes", C.c_int64), ("d2h_bytes", C.c_int64), ("ms_copy", C.c_double),
                 ("n_members", C.c_int32), ("members_padded", C.c_int32), ("n_colors", C.c_int32),
                 ("device_bytes", C.c_int64), ("host_bytes", C.c_int64), ("ms_gather32", C.c_double),
-                ("n_gather32", C.c_int64), ("cheb_lo_min", C.c_double), ("cheb_hi_max", C.c_double)]
+                ("n_gather32", C.c_int64), ("cheb_lo_min", C.c_double), ("cheb_hi_max", C.c_double),
+                ("ms_tail32", C.c_double), ("n_tail32", C.c_int64), ("elems_tail32", C.c_int64)]
 
 
 EXPORTS = {
@@ -325,9 +327,9 @@ class Ensemble:
         lib().nlth_ens_reset_stats(self.h)
 
     def set_tuning(self, ebe_block=0, check_every=0, use_graph=-1, inner_maxit=0, inner_tol=0.0, scatter=-1,
-                   cluster_blocks=0, inner_method=-1, zero_copy=-1):
+                   cluster_blocks=0, inner_method=-1, zero_copy=-1, tail_members=-1):
         t = nlth_tuning(int(ebe_block), int(check_every), int(use_graph), int(inner_maxit), float(inner_tol),
-                        int(scatter), int(cluster_blocks), int(inner_method), int(zero_copy))
+                        int(scatter), int(cluster_blocks), int(inner_method), int(zero_copy), int(tail_members))
         return _check(lib().nlth_ens_set_tuning(self.h, C.byref(t)), self.ctx)
 
     def close(self):

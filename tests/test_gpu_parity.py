@@ -279,6 +279,59 @@ def test_cluster_path_64_members(gpu_ctx, oracle_lib, precision, inner_dtype):
         assert err < 1e-9
 
 
+@pytest.mark.parametrize("n_live,tail", [(20, 32), (10, 16)])
+def test_tail_operator_matches_full_and_oracle(gpu_ctx, oracle_lib, n_live, tail):
+    """With at most `tail` members still iterating in the outer CG, their
+    inner CG runs on compact copies of their rows.  Members without input are
+    inactive from the start, so the compact path runs in every outer
+    iteration: results match the full path and the oracle, silent members stay
+    at rest, graph replay equals direct launches bitwise, and the profile
+    counts the listed element-member pairs."""
+    mesh, prob = _small_problem(precision=1, n_members=64, n_steps=24, dims=(6, 5, 3), ns=12, tol=1e-12)
+    prob.inner_dtype = 2
+    vs, gr = I.ensemble_members(91, 64, I.CFG0_LAYERS["vs"])
+    prob.vs = vs
+    prob.gamma_ref = np.tile(gr[:, None], (1, 2))
+    live = np.arange(3, 64, 64 // n_live)[:n_live]  # spread over the member lanes
+    acc = 5.0 * I.member_waves(2, range(64), prob.n_steps, prob.dt)
+    mask = np.zeros(64, dtype=bool)
+    mask[live] = True
+    acc[~mask] = 0.0
+    prob.input_acc = acc
+    mh = gpu_ctx.mesh(mesh)
+
+    def run(profile=False, **kw):
+        ens = gpu_ctx.ensemble(mh, mesh, prob)
+        try:
+            ens.set_tuning(**kw)
+            if profile:
+                ens.set_profile(True)
+            ens.step(prob.n_steps)
+            return ens.read(), ens.stats()
+        finally:
+            ens.close()
+
+    say("tail operator:", n_live, "live members, list of at most", tail)
+    full, _ = run(tail_members=0)
+    lst, _ = run(tail_members=tail)
+    prof, st = run(profile=True, tail_members=tail)
+    say("  tail launches", st["n_tail32"], "element-member pairs", st["elems_tail32"], "full launches", st["n_ebe32"])
+    assert st["n_tail32"] > 0 and st["n_ebe32"] == 0
+    assert st["elems_tail32"] <= st["n_tail32"] * mesh.n_tets * n_live
+    assert st["elems_tail32"] % mesh.n_tets == 0
+    assert np.all(lst["vel"][~mask] == 0.0)
+    scale = np.max(np.abs(full["vel"]))
+    d = float(np.max(np.abs(lst["vel"] - full["vel"])) / scale)
+    dp = float(np.max(np.abs(prof["vel"] - lst["vel"])) / scale)
+    say("  list vs full max rel diff", d, "profiled vs graph-replayed", dp)
+    assert d < 1e-9 and dp == 0.0
+    for m in (live[0], live[-1]):
+        vref, _ = _oracle_vel(oracle_lib, mesh, prob, int(m))
+        err = oracle_lib.rel_l2(lst["vel"][m], vref)
+        say("  member", int(m), "vs oracle", err)
+        assert err < 1e-9
+
+
 def test_chebyshev_inner_matches_oracle(gpu_ctx, oracle_lib, nlth_mod):
     """Inner Chebyshev iteration (bounds from the step's first inner CG): the
     outer FP64 flexible CG still converges to its tolerance, so members match
