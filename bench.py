@@ -257,7 +257,9 @@ def bench_paged(args):
                       "h2d_gbps": st["h2d_bytes"] / el / 1e9, "d2h_gbps": st["d2h_bytes"] / el / 1e9},
         "device_gb": st["device_bytes"] / 1e9, "host_gb": st["host_bytes"] / 1e9,
     }
-    if args.zero_copy_steps > 0:
+    if args.zero_copy_steps > 0 and not st["paged"]:
+        log("zero-copy ablation skipped: the law state fits the device budget (not paged)")
+    elif args.zero_copy_steps > 0:
         # ablation of the pipeline: the law kernel works on the pinned host
         # state over the host link (the form the footnote of Section 2.3 times)
         el_zc, _, st_zc, out_zc, _ = run_gpu(mesh, prob, args.warmup, args.zero_copy_steps, False,

@@ -21,7 +21,7 @@ import time
 
 # (inner_tol, inner_maxit, inner_method): method 0 CG, 1 Chebyshev of degree inner_maxit
 INNER_POLICIES = [(0.1, 50, 0), (0.01, 60, 0), (1e-12, 12, 0), (1e-12, 16, 0), (1e-12, 20, 0),
-                  (1e-12, 12, 1), (1e-12, 16, 1), (1e-12, 20, 1)]
+                  (1e-12, 24, 0), (1e-12, 16, 1), (1e-12, 20, 1)]
 EBE_BLOCKS = [256, 128]
 CHECK_EVERY = [8, 16, 4]
 CLUSTER_BLOCKS = [3, 2, 4]
