@@ -114,3 +114,34 @@ def test_response_spectra_argument_checks(nlth_mod, host_ctx):
     with pytest.raises(nlth_mod.NlthError) as ei:
         nlth_mod.nlth_response_spectra(host_ctx, v, 1e-3, [0.5])
     assert ei.value.code == nlth_mod.NLTH_EDEVICE
+
+
+def test_struct_layouts_match_header(nlth_mod, tmp_path):
+    """The ctypes structures of the binding have the sizes and field offsets
+    that a C compiler gives the structures of include/nlth.h."""
+    import ctypes as C
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    names = ["nlth_ctx_opts", "nlth_mesh_desc", "nlth_mesh_info", "nlth_problem", "nlth_result", "nlth_stats",
+             "nlth_tuning"]
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "nlth.h"', "int main(void) {"]
+    want = {}
+    for n in names:
+        cls = getattr(nlth_mod, n)
+        lines.append(f'printf("{n} %zu\\n", sizeof({n}));')
+        want[n] = C.sizeof(cls)
+        for f, _ in cls._fields_:
+            lines.append(f'printf("{n}.{f} %zu\\n", offsetof({n}, {f}));')
+            want[f"{n}.{f}"] = getattr(cls, f).offset
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = {k: int(v) for k, v in (ln.split() for ln in out.splitlines())}
+    diff = {k: (got[k], want[k]) for k in want if got[k] != want[k]}
+    assert not diff, diff
