@@ -1149,11 +1149,11 @@ void Ens::update_tail()
         // compact rows of 32 lanes: D (elements padded to blocks of 4), h,
         // material, inverse blocks, five CG vectors, element outputs
         const size_t ne4 = ((size_t)mesh->ne + 3) / 4 * 4, nn = mesh->nn, L = 32;
-        const size_t sz[11] = {ne4 * 11 * L * 4, (size_t)mesh->ne * L * 8, (size_t)P.nl * MAT_N * L * 8,
+        const size_t sz[10] = {ne4 * 11 * L * 4, (size_t)mesh->ne * L * 8, (size_t)P.nl * MAT_N * L * 8,
                                nn * 6 * L * 4, nn * 3 * L * 4, nn * 3 * L * 4, nn * 3 * L * 4, nn * 3 * L * 4,
-                               nn * 3 * L * 4, (size_t)mesh->ne * 30 * L * 4, 0};
-        size_t off[11], tot = 0;
-        for (int i = 0; i < 11; ++i) {
+                               nn * 3 * L * 4, (size_t)mesh->ne * 30 * L * 4};
+        size_t off[10], tot = 0;
+        for (int i = 0; i < 10; ++i) {
             off[i] = tot;
             tot += (sz[i] + 255) / 256 * 256;
         }
