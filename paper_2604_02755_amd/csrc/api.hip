@@ -1160,9 +1160,11 @@ void Ens::update_tail()
         try {
             tail_mem.alloc(&ctx->budget, tot);
             tlist.alloc(&ctx->budget, (size_t)(1 + MB) * 4);
+            NLTH_HIP(hipHostMalloc((void**)&h_tlist, sizeof(int) * (1 + MB), hipHostMallocDefault));
         } catch (const Error&) {  // no room: keep the full operator
             tail_mem.release();
             tlist.release();
+            h_tlist = nullptr;
             tail_max = 0;
             return;
         }
@@ -1177,7 +1179,6 @@ void Ens::update_tail()
         tb.w = (float*)(b + off[7]);
         tb.Ap = (float*)(b + off[8]);
         tb.f = (float*)(b + off[9]);
-        NLTH_HIP(hipHostMalloc((void**)&h_tlist, sizeof(int) * (1 + MB), hipHostMallocDefault));
     }
     h_tlist[0] = na;
     int k = 1;
