@@ -153,6 +153,23 @@ def test_batch_matches_members_alone_and_oracle(gpu_ctx, oracle_lib):
         assert e_or < 1e-9 and e_al < 1e-12
 
 
+@pytest.mark.parametrize("flags", [(1, 0), (0, 1)])
+def test_per_layer_elastic_flag_matches_oracle(gpu_ctx, oracle_lib, flags):
+    """A layer flagged elastic keeps its springs linear (D = the elastic
+    tangent, no hysteretic damping) while the other layer's springs yield:
+    FP64 and mixed runs match the oracle."""
+    for precision in (0, 1):
+        mesh, prob = _small_problem(precision=precision, n_steps=30, ns=12)
+        prob.nonlinear = np.array(flags, dtype=np.int32)
+        say("layer flags", flags, "precision", precision)
+        vref, _ = _oracle_vel(oracle_lib, mesh, prob)
+        mh = gpu_ctx.mesh(mesh)
+        out = gpu_ctx.solve(mh, mesh, prob)
+        err = oracle_lib.rel_l2(out["vel"][0], vref)
+        say("  rel L2", err)
+        assert out["rc"] == 0 and err < 1e-9
+
+
 def test_nonconvergence_reported(gpu_ctx, nlth_mod):
     mesh, prob = _small_problem(n_steps=5, tol=1e-12)
     prob.cg_maxit = 2
