@@ -96,17 +96,6 @@ void launch_ebe_cluster64(hipStream_t s, OpMode mode, const DevMesh& M, int MB, 
 void launch_ebe_cluster32(hipStream_t s, const DevMesh& M, int MB, int nm, const float* D32, const uint32_t* D16,
                           const double* h, const double* mat, StepConst sc, const float* x, float* co,
                           const int* active, bool d16_mean);
-// with partial, also the per-member block partials of x . y (*nblk blocks).
-// MB <= 256.
-template <typename T>
-void launch_gather(hipStream_t s, const DevMesh& M, int MB, int nm, const T* f, const T* base, T bscale, T* y,
-                   const int* active, const T* x, double* partial, int* nblk);
-// with partial, also the per-member block partials of x . y (*nblk blocks).
-// MB <= 256.
-template <typename T>
-void launch_gather(hipStream_t s, const DevMesh& M, int MB, int nm, const T* f, const T* base, T bscale, T* y,
-                   const int* active, const double* mat, double dcoef, const T* x, const double* vI,
-                   double* partial, int* nblk);
 // node-centric absorbing-boundary dashpot: y += coef * C_abs x (+ 2 C_base vI for
 // the right-hand side); with partial (MB <= 256), the per-member block partials
 // of x . (C_abs x) are appended after the *nblk already written, *nblk grows
