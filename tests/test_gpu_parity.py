@@ -296,22 +296,23 @@ def test_cluster_path_64_members(gpu_ctx, oracle_lib, precision, inner_dtype):
         assert err < 1e-9
 
 
-@pytest.mark.parametrize("n_live,tail", [(20, 32), (10, 16)])
-def test_tail_operator_matches_full_and_oracle(gpu_ctx, oracle_lib, n_live, tail):
+@pytest.mark.parametrize("n_members,n_live,tail", [(64, 20, 32), (64, 10, 16), (128, 24, 32)])
+def test_tail_operator_matches_full_and_oracle(gpu_ctx, oracle_lib, n_members, n_live, tail):
     """With at most `tail` members still iterating in the outer CG, their
     inner CG runs on compact copies of their rows.  Members without input are
     inactive from the start, so the compact path runs in every outer
     iteration: results match the full path and the oracle, silent members stay
     at rest, graph replay equals direct launches bitwise, and the profile
     counts the listed element-member pairs."""
-    mesh, prob = _small_problem(precision=1, n_members=64, n_steps=24, dims=(6, 5, 3), ns=12, tol=1e-12)
+    nmb = n_members
+    mesh, prob = _small_problem(precision=1, n_members=nmb, n_steps=24, dims=(6, 5, 3), ns=12, tol=1e-12)
     prob.inner_dtype = 2
-    vs, gr = I.ensemble_members(91, 64, I.CFG0_LAYERS["vs"])
+    vs, gr = I.ensemble_members(91, nmb, I.CFG0_LAYERS["vs"])
     prob.vs = vs
     prob.gamma_ref = np.tile(gr[:, None], (1, 2))
-    live = np.arange(3, 64, 64 // n_live)[:n_live]  # spread over the member lanes
-    acc = 5.0 * I.member_waves(2, range(64), prob.n_steps, prob.dt)
-    mask = np.zeros(64, dtype=bool)
+    live = np.arange(3, nmb, nmb // n_live)[:n_live]  # spread over the member lanes
+    acc = 5.0 * I.member_waves(2, range(nmb), prob.n_steps, prob.dt)
+    mask = np.zeros(nmb, dtype=bool)
     mask[live] = True
     acc[~mask] = 0.0
     prob.input_acc = acc
@@ -328,7 +329,7 @@ def test_tail_operator_matches_full_and_oracle(gpu_ctx, oracle_lib, n_live, tail
         finally:
             ens.close()
 
-    say("tail operator:", n_live, "live members, list of at most", tail)
+    say("tail operator:", n_live, "of", nmb, "members live, list of at most", tail)
     full, _ = run(tail_members=0)
     lst, _ = run(tail_members=tail)
     prof, st = run(profile=True, tail_members=tail)
