@@ -328,6 +328,8 @@ class Ensemble:
 
     def set_tuning(self, ebe_block=0, check_every=0, use_graph=-1, inner_maxit=0, inner_tol=0.0, scatter=-1,
                    cluster_blocks=0, inner_method=-1, zero_copy=-1, tail_members=-1):
+        """nlth_ens_set_tuning: the defaults (0, or -1 where 0 is a setting) keep
+        the current value; include/nlth.h documents each field."""
         t = nlth_tuning(int(ebe_block), int(check_every), int(use_graph), int(inner_maxit), float(inner_tol),
                         int(scatter), int(cluster_blocks), int(inner_method), int(zero_copy), int(tail_members))
         return _check(lib().nlth_ens_set_tuning(self.h, C.byref(t)), self.ctx)
