@@ -59,7 +59,8 @@ class _Problem(C.Structure):
 
 class _Result(C.Structure):
     _fields_ = [("vel", _dp), ("iters", _ip), ("du_hist", _dp), ("u_final", _dp),
-                ("v_final", _dp), ("D_final", _dp), ("h_final", _dp), ("theta_final", _dp), ("steps_done", C.c_int)]
+                ("v_final", _dp), ("D_final", _dp), ("h_final", _dp), ("theta_final", _dp), ("vmax", _dp),
+                ("law_events", C.c_long * 3), ("setup_seconds", C.c_double), ("steps_done", C.c_int)]
 
 
 def lib():
@@ -81,6 +82,7 @@ def lib():
         _lib.or_rayleigh.argtypes = [C.c_double, C.c_double, _dp, _dp]
         _lib.or_ip_law.argtypes = [_dp, _dp, C.c_int, _dp, _dp, C.c_double, C.c_double,
                                    C.c_double, C.c_double, _dp, _dp]
+        _lib.or_set_threads.argtypes = [C.c_int]
     return _lib
 
 
@@ -107,9 +109,12 @@ def run(mesh, prob, member: int = 0, alias=None, want_du: bool = False, want_sta
         n_steps: int | None = None, cg_tol: float | None = None, v0=None):
     """Run one member of ``prob`` on ``mesh``.  Returns a dict of numpy arrays.
 
-    ``vel``: [n_steps, n_recv, 3]; ``iters``: [n_steps]; optional ``du``
-    [n_steps, n_dof]; ``u``, ``D`` [n_tets, 4, 21], ``h`` [n_tets],
-    ``theta`` [n_tets, 4, n_springs, 6]; ``seconds`` wall time.
+    ``vel``: [n_steps, n_recv, 3]; ``vmax``: [n_recv], the largest velocity
+    norm over the run at each receiver; ``iters``: [n_steps]; ``law_events``:
+    counts over the run of (reversals on the skeleton, reversals on a Masing
+    branch, rejoins of the skeleton); optional ``du`` [n_steps, n_dof]; ``u``,
+    ``D`` [n_tets, 4, 21], ``h`` [n_tets], ``theta`` [n_tets, 4, n_springs, 6];
+    ``seconds`` wall time, of which ``setup_seconds`` before the first step.
     """
     L = lib()
     keep = []
@@ -140,7 +145,7 @@ def run(mesh, prob, member: int = 0, alias=None, want_du: bool = False, want_sta
                  float(prob.f_lo), float(prob.f_hi), float(prob.dt), ns, _p(acc),
                  float(cg_tol if cg_tol is not None else prob.cg_tol), int(prob.cg_maxit),
                  _p(k(_f64(v0))) if v0 is not None else None, -1, None, None, None, None)
-    out = dict(vel=np.zeros((ns, rc.size, 3)), iters=np.zeros(ns, np.int32))
+    out = dict(vel=np.zeros((ns, rc.size, 3)), iters=np.zeros(ns, np.int32), vmax=np.zeros(rc.size))
     if want_du:
         out["du"] = np.zeros((ns, 3 * mesh.n_nodes))
     if want_state:
@@ -150,14 +155,22 @@ def run(mesh, prob, member: int = 0, alias=None, want_du: bool = False, want_sta
         out["h"] = np.zeros(mesh.n_tets)
         out["theta"] = np.zeros((mesh.n_tets, 4, prob.n_springs, 6))
     r = _Result(_p(out["vel"]), _p(out["iters"], _ip), _p(out.get("du")), _p(out.get("u")),
-                _p(out.get("v")), _p(out.get("D")), _p(out.get("h")), _p(out.get("theta")), 0)
+                _p(out.get("v")), _p(out.get("D")), _p(out.get("h")), _p(out.get("theta")), _p(out["vmax"]),
+                (C.c_long * 3)(), 0.0, 0)
     t0 = time.perf_counter()
     code = L.or_run(C.byref(m), C.byref(p), C.byref(r))
     out["seconds"] = time.perf_counter() - t0
     out["steps_done"] = r.steps_done
+    out["setup_seconds"] = r.setup_seconds
+    out["law_events"] = tuple(int(x) for x in r.law_events)
     if code != 0:
         raise OracleError(code, L.or_last_error().decode(), out)
     return out
+
+
+def set_threads(n: int):
+    """Threads of the oracle's OpenMP loops (for timing on a stated core count)."""
+    lib().or_set_threads(int(n))
 
 
 def apply_operator(mesh, prob, which, D_ip, h, x, member: int = 0):
@@ -183,7 +196,7 @@ def apply_operator(mesh, prob, which, D_ip, h, x, member: int = 0):
     p = _Problem(prob.n_layers, _p(rho), _p(vs), _p(nu), _p(gr), _p(hm), _p(nl, _ip), prob.n_springs,
                  _p(dirs), _p(w), int(prob.damping_mode), float(prob.h0), float(prob.f_lo), float(prob.f_hi),
                  float(prob.dt), 0, None, 1e-8, 1, None, int(which), _p(D), _p(hh), _p(xx), _p(y))
-    out = _Result(_p(np.zeros(1)), None, None, None, None, None, None, None, 0)
+    out = _Result(_p(np.zeros(1)), None, None, None, None, None, None, None, None, (C.c_long * 3)(), 0.0, 0)
     code = L.or_run(C.byref(m), C.byref(p), C.byref(out))
     if code != 0:
         raise OracleError(code, L.or_last_error().decode())

@@ -34,6 +34,24 @@
 #include <omp.h>
 #endif
 
+static double wall_seconds(void)
+{
+#ifdef _OPENMP
+    return omp_get_wtime();
+#else
+    return 0.0;
+#endif
+}
+
+void or_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 static char g_err[512];
 const char* or_last_error(void) { return g_err; }
 static int fail(int code, const char* msg, long idx)
@@ -297,19 +315,26 @@ static double stress_on_curve(double g, const double* st, const spring_par* p)
 }
 
 /* state: gp (current strain), gr (reversal strain), tr (reversal stress),
- * gm (largest |strain| on the skeleton), dir (last loading sign), skel (on skeleton). */
-static void spring_update(double* st, double dg, const spring_par* p, double* Gt, double* hk)
+ * gm (largest |strain| on the skeleton), dir (last loading sign), skel (on skeleton).
+ * cnt (optional) counts the events of the step for the tests: [0] reversals
+ * taken on the skeleton, [1] reversals taken on a Masing branch, [2] rejoins
+ * of the skeleton. */
+static void spring_update(double* st, double dg, const spring_par* p, double* Gt, double* hk, long* cnt)
 {
     if (dg != 0.0) {
         double d = dg > 0.0 ? 1.0 : -1.0;
         if (st[4] != 0.0 && d != st[4]) { /* reversal: branch starts at the current point */
+            if (cnt) cnt[st[5] != 0.0 ? 0 : 1]++;
             st[2] = stress_on_curve(st[0], st, p);
             st[1] = st[0];
             st[5] = 0.0;
         }
         st[4] = d;
         double g = st[0] + dg;
-        if (st[5] == 0.0 && d * g >= st[3]) st[5] = 1.0; /* back on the skeleton */
+        if (st[5] == 0.0 && d * g >= st[3]) { /* back on the skeleton */
+            st[5] = 1.0;
+            if (cnt) cnt[2]++;
+        }
         if (st[5] != 0.0) st[3] = fmax(st[3], fabs(g));
         st[0] = g;
     }
@@ -328,13 +353,14 @@ double or_spring_step(double* st, double dg, double G0, double gref, double h_ma
                       double* hk)
 {
     spring_par p = {G0, gref, h_max, or_ro_beta(h_max)};
-    spring_update(st, dg, &p, Gt, hk);
+    spring_update(st, dg, &p, Gt, hk, NULL);
     return stress_on_curve(st[0], st, &p);
 }
 
-/* Multi-spring point: D = Kb m m^T + sum_k c_k G_t,k n_k n_k^T, h = mean h_k. */
-void or_ip_law(const double* deps, double* state, int ns, const double* dirs, const double* w,
-               double G0, double Kb, double gref, double hmax, double* D, double* hmean)
+/* Multi-spring point: D = Kb m m^T + sum_k c_k G_t,k n_k n_k^T, h = mean h_k.
+ * cnt (optional): law events, as for spring_update. */
+static void ip_law(const double* deps, double* state, int ns, const double* dirs, const double* w,
+                   double G0, double Kb, double gref, double hmax, double* D, double* hmean, long* cnt)
 {
     spring_par p = {G0, gref, hmax, or_ro_beta(hmax)};
     for (int i = 0; i < 36; ++i) D[i] = 0.0;
@@ -347,13 +373,19 @@ void or_ip_law(const double* deps, double* state, int ns, const double* dirs, co
         if (deps) { /* deps == NULL: the initial (virgin) tangent G0 */
             double dg = 0.0;
             for (int i = 0; i < 6; ++i) dg += n[i] * deps[i];
-            spring_update(state + 6 * k, dg, &p, &Gt, &hk);
+            spring_update(state + 6 * k, dg, &p, &Gt, &hk, cnt);
         }
         for (int r = 0; r < 6; ++r)
             for (int c = 0; c < 6; ++c) D[6 * r + c] += w[k] * Gt * n[r] * n[c];
         hs += hk;
     }
     *hmean = hs / ns;
+}
+
+void or_ip_law(const double* deps, double* state, int ns, const double* dirs, const double* w,
+               double G0, double Kb, double gref, double hmax, double* D, double* hmean)
+{
+    ip_law(deps, state, ns, dirs, w, G0, Kb, gref, hmax, D, hmean, NULL);
 }
 
 /* ------------------------------------------------------------------ */
@@ -580,7 +612,12 @@ int or_run(const or_mesh* m, const or_problem* pr, or_result* res)
     const int nn = m->n_nodes, ne = m->n_tets, ns = pr->n_springs;
     const long ndof = 3L * nn;
     const double dt = pr->dt;
+    const double t_start = wall_seconds();
     res->steps_done = 0;
+    res->setup_seconds = 0.0;
+    res->law_events[0] = res->law_events[1] = res->law_events[2] = 0;
+    if (res->vmax)
+        for (int r = 0; r < m->n_recv; ++r) res->vmax[r] = 0.0;
 
     /* --- validate the mesh --- */
     for (long i = 0; i < 10L * ne; ++i)
@@ -761,6 +798,7 @@ int or_run(const or_mesh* m, const or_problem* pr, or_result* res)
     double* KeB = malloc(sizeof(double) * 900 * BATCH);
     double* MeB = malloc(sizeof(double) * 900 * BATCH);
 
+    res->setup_seconds = wall_seconds() - t_start;
     for (int n = 1; n <= pr->n_steps; ++n) {
         /* incident velocity by the trapezoid rule */
         const double* an = pr->input_acc + 3L * (n - 1);
@@ -819,7 +857,8 @@ int or_run(const or_mesh* m, const or_problem* pr, or_result* res)
         }
 
         /* Multispring: D^n, theta^n, h^n from du^n (Alg. 1) */
-#pragma omp parallel for schedule(dynamic, 64)
+        long c_rs = 0, c_rb = 0, c_rj = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : c_rs, c_rb, c_rj)
         for (long e = 0; e < ne; ++e) {
             int l = m->layer[e];
             if (!pr->nonlinear[l]) {
@@ -841,16 +880,28 @@ int or_run(const or_mesh* m, const or_problem* pr, or_result* res)
                     de[r] = s;
                 }
                 double hm;
-                or_ip_law(de, th + 6L * ns * (4 * e + j), ns, pr->dirs, pr->weights, G0[l], Kb[l],
-                          pr->gamma_ref[l], pr->h_max[l], D + 36 * (4 * e + j), &hm);
+                long cnt[3] = {0, 0, 0};
+                ip_law(de, th + 6L * ns * (4 * e + j), ns, pr->dirs, pr->weights, G0[l], Kb[l],
+                       pr->gamma_ref[l], pr->h_max[l], D + 36 * (4 * e + j), &hm, cnt);
+                c_rs += cnt[0];
+                c_rb += cnt[1];
+                c_rj += cnt[2];
                 hsum += hm;
             }
             he[e] = 0.25 * hsum;
         }
+        res->law_events[0] += c_rs;
+        res->law_events[1] += c_rb;
+        res->law_events[2] += c_rj;
 
         for (int r = 0; r < m->n_recv; ++r) {
             int nd = m->alias ? m->alias[m->recv[r]] : m->recv[r];
             for (int c = 0; c < 3; ++c) res->vel[3L * (m->n_recv * (long)(n - 1) + r) + c] = v[3L * nd + c];
+            if (res->vmax) { /* largest velocity norm over the run (surface maps of Section 3) */
+                const double* vr = v + 3L * nd;
+                double nv = sqrt(vr[0] * vr[0] + vr[1] * vr[1] + vr[2] * vr[2]);
+                if (nv > res->vmax[r]) res->vmax[r] = nv;
+            }
         }
         if (res->du_hist) memcpy(res->du_hist + ndof * (n - 1), du, sizeof(double) * ndof);
         res->steps_done = n;

@@ -74,6 +74,10 @@ typedef struct {
     double* D_final;   /* [n_tets*4*21] upper-triangle row-major D per IP (optional) */
     double* h_final;   /* [n_tets] element damping (optional) */
     double* theta_final; /* [n_tets*4*n_springs*6] gp,gr,tr,gm,dir,skel (optional) */
+    double* vmax;      /* [n_recv] largest velocity norm over the run (optional) */
+    long law_events[3]; /* over the run: reversals on the skeleton, reversals on a
+                           Masing branch, rejoins of the skeleton */
+    double setup_seconds; /* wall time before the first step (pattern, mass, faces) */
     int steps_done;
 } or_result;
 
@@ -93,6 +97,8 @@ void or_element_matrices(const double* X4x3, const double* D4x36, double rho,
 void or_face_matrix(const double* X3x3, double* M36, double* normal3, double* area);
 void or_rayleigh(double f_lo, double f_hi, double* a_hat, double* b_hat);
 double or_ro_inverse(double e, double beta);
+/* threads of the OpenMP loops (timing of the oracle on a given core count) */
+void or_set_threads(int n);
 double or_ro_beta(double h_max);
 /* single-spring update; state = {gp, gr, tr, gm, dir, skel}; returns tau after
  * the update, writes the tangent and the spring's equivalent damping */

@@ -136,6 +136,62 @@ def test_element_energy_of_linear_field_is_exact(oracle_lib):
     assert abs(u @ Ke @ u - V * eps @ D @ eps) < 1e-12 * abs(V * eps @ D @ eps)
 
 
+def _conical_rule(X, n=4):
+    """Points and weights of a conical product Gauss rule on the tet X (4x3):
+    the unit cube (a, b, c) maps onto the simplex by xi1 = a, xi2 = b (1 - a),
+    xi3 = c (1 - a)(1 - b), with Jacobian 6V (1 - a)^2 (1 - b); Gauss-Legendre
+    in each direction (exact here for polynomials of degree 2 n - 3 in x)."""
+    g, w = np.polynomial.legendre.leggauss(n)
+    g, w = (g + 1) / 2, w / 2
+    E = np.array([X[1] - X[0], X[2] - X[0], X[3] - X[0]])
+    V6 = abs(np.linalg.det(E))
+    pts, wts = [], []
+    for a, wa in zip(g, w):
+        for b, wb in zip(g, w):
+            for c, wc in zip(g, w):
+                xi = np.array([a, b * (1 - a), c * (1 - a) * (1 - b)])
+                pts.append(X[0] + xi @ E)
+                wts.append(wa * wb * wc * V6 * (1 - a) ** 2 * (1 - b))
+    return np.array(pts), np.array(wts)
+
+
+def test_element_energy_of_quadratic_field_is_exact(oracle_lib):
+    """Eq. 2 with the 4-point rule on a quadratic displacement field: the strain
+    is linear in x, so eps^T D eps is a quadratic that a rule of degree 2
+    integrates exactly.  u^T K_e u must equal the integral taken by an
+    independent conical product Gauss rule.  Linear fields cannot tell where the
+    four points lie (any points with barycentrics summing to one integrate a
+    constant); a quadratic field pins their location (a, b, b, b)."""
+    rng = np.random.default_rng(31)
+    X = _rand_tet(rng)
+    Xn = np.vstack([X, [(X[a] + X[b]) / 2 for a, b in I.EDGES]])
+    F = rng.normal(size=(3, 3))
+    H = rng.normal(size=(3, 3, 3))
+    H = H + H.transpose(0, 2, 1)  # u_c = F[c] . x + x^T H[c] x / 2
+
+    def grad_u(x):  # G[c, d] = d u_c / d x_d
+        return F + np.einsum("cde,e->cd", H, x)
+
+    u = np.array([F @ x + 0.5 * np.einsum("cde,d,e->c", H, x, x) for x in Xn]).ravel()
+    L = rng.normal(size=(6, 6))
+    D = L @ L.T + 2 * np.eye(6)
+    Ke, _ = oracle_lib.element_matrices(X, D, 1.0)
+    pts, wts = _conical_rule(X)
+    energy = 0.0
+    for x, wq in zip(pts, wts):
+        G = grad_u(x)
+        eps = np.array([G[0, 0], G[1, 1], G[2, 2], G[0, 1] + G[1, 0], G[1, 2] + G[2, 1], G[2, 0] + G[0, 2]])
+        energy += wq * eps @ D @ eps
+    V = oracle_lib.tet_geometry(X)[1]
+    assert abs(wts.sum() - V) < 1e-14 * V  # the check rule itself
+    assert abs(u @ Ke @ u - energy) < 1e-12 * abs(energy)
+    # the field is genuinely quadratic: the centroid strain alone misses the energy
+    xc = X.mean(axis=0)
+    Gc = grad_u(xc)
+    ec = np.array([Gc[0, 0], Gc[1, 1], Gc[2, 2], Gc[0, 1] + Gc[1, 0], Gc[1, 2] + Gc[2, 1], Gc[2, 0] + Gc[0, 2]])
+    assert abs(V * ec @ D @ ec - energy) > 1e-3 * abs(energy)
+
+
 def test_patch_test_on_distorted_mesh(oracle_lib):
     """A linear displacement field on an assembled (distorted) mesh gives zero
     residual at interior nodes."""
@@ -172,17 +228,6 @@ def test_spring_table_isotropic(oracle_lib, ns):
     D, h = oracle_lib.ip_law(None, None, dirs, w, G0, Kb, 1e-3, 0.2)
     assert np.abs(D - _iso(lam, G0)).max() < 1e-14 * (lam + 2 * G0)
     assert h == 0.0
-
-
-def test_state_bytes_per_element_match_paper():
-    """Section 2.1: four doubles and two flags per spring; the flags (direction
-    in -1..1, skeleton 0/1) fit in 3 bits, so one int32 holds both: 36 B per
-    spring, 150 springs per point, four points per tet -> 21.6 kB per element."""
-    per_spring = 4 * 8 + 4
-    assert all(0 <= (d + 1) | (k << 2) < 8 and ((((d + 1) | (k << 2)) & 3) - 1, ((d + 1) | (k << 2)) >> 2) == (d, k)
-               for d in (-1, 0, 1) for k in (0, 1))
-    assert per_spring == 36
-    assert per_spring * 150 * 4 == 21600
 
 
 def test_skeleton_closed_forms(oracle_lib):
@@ -264,6 +309,63 @@ def test_masing_branch_residual_and_tangent(oracle_lib):
     # the secant slope between two branch points lies between their tangents
     slope = (taus[-1][1] - taus[-2][1]) / (taus[-1][0] - taus[-2][0])
     assert taus[-1][2] < slope < taus[-2][2] or taus[-2][2] < slope < taus[-1][2]
+
+
+def _skeleton_indep(g, G0, gref, beta):
+    """S(gamma) from the skeleton's definition e = s (1 + |2 s|^beta) by
+    bracketing root search (no Newton): an independent check of the oracle's
+    inversion."""
+    from scipy.optimize import brentq
+    e = g / gref
+    if e == 0.0:
+        return 0.0
+    a = abs(e)
+    s = brentq(lambda x: x * (1 + (2 * x) ** beta) - a, 0.0, a, xtol=1e-300, rtol=1e-15, maxiter=500)
+    return math.copysign(G0 * gref * s, e)
+
+
+def test_masing_reversal_on_a_branch_closed_form(oracle_lib):
+    """Masing rule (Section 2.1): load on the skeleton to A, unload to A/2 (a
+    branch from (A, S(A))), then reload, which reverses while on that branch.
+    In closed form tau(A/2) = S(A) - 2 S(A/4); the reload branch starts there,
+    tau = tau(A/2) + 2 S((gamma - A/2)/2), so tau(3A/4) = S(A) - 2 S(A/4) +
+    2 S(A/8), and at gamma = A it meets the skeleton again, tau = S(A), where
+    the spring rejoins it (S(5A/4) beyond).  Taking the reversal stress from
+    the skeleton instead of the branch would give S(A/2) at the second
+    reversal and fail.  The tangent on the reload branch is the slope of that
+    closed form."""
+    G0, gref, hmax = 3.0e7, 2.0 ** -10, 0.2
+    b = oracle_lib.ro_beta(hmax)
+    A = 2.0 ** -10 * 1.5  # binary fractions: every increment below is exact
+
+    def S(x):
+        return _skeleton_indep(x, G0, gref, b)
+
+    st = oracle_lib.new_spring()
+    n = 64
+    seen = {}
+    for target, label in ((A, "A"), (A / 2, "A/2"), (3 * A / 4, "3A/4"), (A, "A again"), (5 * A / 4, "5A/4")):
+        d = (target - st[0]) / n
+        for _ in range(n):
+            tau, Gt, _ = oracle_lib.spring_step(st, d, G0, gref, hmax)
+        assert st[0] == target
+        seen[label] = (tau, Gt, st.copy())
+    SA = S(A)
+    tol = 1e-13 * SA
+    assert abs(seen["A"][0] - SA) < tol
+    t_half = SA - 2 * S(A / 4)
+    assert abs(seen["A/2"][0] - t_half) < tol
+    assert seen["A/2"][2][5] == 0.0  # on a branch
+    t_34 = t_half + 2 * S(A / 8)
+    assert abs(seen["3A/4"][0] - t_34) < tol
+    st34 = seen["3A/4"][2]
+    assert st34[1] == A / 2 and abs(st34[2] - t_half) < tol and st34[5] == 0.0
+    # tangent: d/dgamma of t_half + 2 S((gamma - A/2)/2) at 3A/4, i.e. S'(A/8)
+    hd = A * 1e-5
+    slope = (S(A / 8 + hd) - S(A / 8 - hd)) / (2 * hd)
+    assert abs(seen["3A/4"][1] - slope) < 1e-7 * slope
+    assert abs(seen["A again"][0] - SA) < tol and seen["A again"][2][5] == 1.0
+    assert abs(seen["5A/4"][0] - S(5 * A / 4)) < tol and seen["5A/4"][2][3] == 5 * A / 4
 
 
 def test_single_spring_ip_equals_spring(oracle_lib):
@@ -387,6 +489,21 @@ def test_layer_over_halfspace_resonance(oracle_lib):
     H1d = 1 / np.sqrt(np.cos(k * 4) ** 2 + alpha ** 2 * np.sin(k * 4) ** 2)
     sel = (f > 1) & (f < 14)
     assert np.max(np.abs(H[sel] - H1d[sel]) / H1d[sel]) < 0.05
+
+
+def test_vmax_is_the_largest_velocity_norm(oracle_lib):
+    """Maximum velocity-norm maps (Section 3, Figs. 3-4): at each receiver the
+    largest |v| over the run, here against the receiver histories the oracle
+    records; a nonlinear run reaches every law event (reversals on the
+    skeleton and on Masing branches, rejoins), which the GPU parity runs of
+    the same setup inherit."""
+    mesh, prob = I.config(0, n_steps=30, mesh_dims=(4, 3, 2), cg_tol=1e-12, n_springs=12)
+    prob.input_acc *= 5.0
+    r = oracle_lib.run(mesh, prob)
+    ref = np.sqrt((r["vel"] ** 2).sum(axis=2)).max(axis=0)
+    assert ref.max() > 0 and np.allclose(r["vmax"], ref, rtol=1e-15, atol=0)
+    assert all(c > 0 for c in r["law_events"]), r["law_events"]
+    assert 0 <= r["setup_seconds"] <= r["seconds"]
 
 
 def test_cg_nonconvergence_is_reported(oracle_lib):
