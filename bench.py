@@ -63,6 +63,26 @@ EBE32_FLOPS_ELEMENT_D = 3 * 110 + 522 + 336 + 4 * 30 + 6 * 54
 FP32_PEAK_TFLOPS = 157.3
 
 
+# Algorithmic HBM bytes per DOF-step of the whole step, charging every array
+# once per pass the method needs (the measurement plan of the hot path): an
+# FP64 PCG iteration (operator pass with FP64 D per point, vectors) 279 B, an
+# FP32 inner iteration 139 B, and per step the right-hand side 223, the
+# block-Jacobi diagonal 183, the q pass 199, the Newmark update 56 and the law
+# 80 N_s r + 21 r 12 + 8 (state read and written, D written in FP64 and FP32;
+# r = integration points per DOF, 0.969 on the 64x64x32-cube box).
+def step_bytes_per_dof(n_outer: float, n_inner: float, n_springs: int, ip_per_dof: float) -> float:
+    law = 80.0 * n_springs * ip_per_dof + 21.0 * ip_per_dof * 12 + 8.0
+    return 279.0 * n_outer + 139.0 * n_inner + 223.0 + 183.0 + 199.0 + 56.0 + law
+
+
+def step_roofline(value: float, n_outer: float, n_inner: float, n_springs: int, ip_per_dof: float) -> dict:
+    b = step_bytes_per_dof(n_outer, n_inner, n_springs, ip_per_dof)
+    roof = HBM_PEAK_GBS * 1e9 / b
+    return {"bound": "hbm", "bytes_per_dof_step": round(b, 1), "peak_gbs": HBM_PEAK_GBS,
+            "roofline_dof_steps_per_s": roof, "frac": round(value / roof, 4),
+            "iterations_per_member_step": {"outer": round(n_outer, 3), "inner": round(n_inner, 3)}}
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for f in ("kernels.hip", "vec.hip"):
@@ -86,10 +106,15 @@ def traffic_from_profile(src_hash: str, element_members_per_launch: float):
     return round(d["element"]["bytes_per_element_member"] * element_members_per_launch, 0)
 
 
-def run_gpu(mesh, prob, warmup, steps, profile, tune_steps=0, tuned=None, ctx_kw=None, fixed=None, tuning_kw=None):
+def run_gpu(mesh, prob, warmup, steps, profile, tune_steps=0, tuned=None, ctx_kw=None, fixed=None, tuning_kw=None,
+            pre_steps=0, profile_steps=0):
     """Create the ensemble, step ``warmup`` steps, autotune it over the next
     ``tune_steps`` steps (or apply the launch shapes of ``tuned`` and step as
-    many), then time ``steps`` steps."""
+    many), step ``pre_steps`` more untimed, then time ``steps`` steps one by
+    one (hipGraph replay on; per-kernel event timing only if ``profile``).
+    With ``profile_steps`` > 0 a separate window of that many steps follows
+    with per-kernel event timing on (which replaces graph replay by direct
+    launches of the same kernels); its stats are returned as ``st["prof"]``."""
     from paper_2604_02755_amd import autotune, nlth
     import torch
     ctx = nlth.Context(0, use_torch_stream=True, **(ctx_kw or {}))
@@ -114,15 +139,28 @@ def run_gpu(mesh, prob, warmup, steps, profile, tune_steps=0, tuned=None, ctx_kw
             choice = autotune.tune(ens, mesh, prob, steps_per_trial=1, log=log)
             used = ens.stats()["steps_done"] - done0
             ens.step(max(0, tune_steps - used))
+        if pre_steps > 0:
+            ens.step(pre_steps)
         ens.reset_stats()
         ens.set_profile(profile)
         st0 = ens.stats()
         torch.cuda.synchronize()
+        step_ms = []
         t0 = time.perf_counter()
-        ens.step(steps)
+        for _ in range(steps):  # each step is synchronous; the timer reads add nothing on the device
+            ts = time.perf_counter()
+            ens.step(1)
+            step_ms.append((time.perf_counter() - ts) * 1e3)
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
         st = ens.stats()
+        st["step_ms"] = step_ms
+        if profile_steps > 0:
+            ens.reset_stats()
+            ens.set_profile(True)
+            ens.step(profile_steps)
+            st["prof"] = ens.stats()
+            ens.set_profile(False)
         out = ens.read()
         ens.close()
     finally:
@@ -144,6 +182,7 @@ def serve_run(rate, window_s, steps_range, sizes=(32, 48, 64), max_batch=16, n_c
         mh = {n: ctx.mesh(meshes[n]) for n in sizes}
         pending = {}
         i = 0
+        max_in_flight = 0
         t0 = time.perf_counter()
         last_log = t0
         while i < len(reqs) or pending:
@@ -153,6 +192,7 @@ def serve_run(rate, window_s, steps_range, sizes=(32, 48, 64), max_batch=16, n_c
                 pending[tk] = i
                 outs[i] = out
                 i += 1
+            max_in_flight = max(max_in_flight, len(pending))
             for tk in list(pending):
                 d, _ = ctx.poll(tk)
                 if d:
@@ -175,7 +215,10 @@ def serve_run(rate, window_s, steps_range, sizes=(32, 48, 64), max_batch=16, n_c
     finally:
         ctx.close()
     L = np.array([lat[j] for j in range(len(reqs))])
+    offered = sum(meshes[r["n"]].n_dof * r["steps"] for r in reqs) / window_s
     return {"requests": len(reqs), "rate_per_s": rate, "window_s": window_s,
+            "offered_dof_steps_per_s": offered, "max_in_flight": max_in_flight,
+            "drain_after_last_arrival_s": wall - reqs[-1]["t"],
             "steps_range": list(steps_range), "mesh_sizes": [f"{n}x{n}x16" for n in sizes],
             "max_batch": max_batch, "p50_s": float(np.percentile(L, 50)), "p99_s": float(np.percentile(L, 99)),
             "mean_s": float(L.mean()), "failed": int(sum(1 for v in rcs.values() if v != 0)),
@@ -292,6 +335,79 @@ def bench_serve(args):
     print(json.dumps(line), flush=True)
 
 
+def host_cpu_info() -> dict:
+    """Model, threads per core and the CPUs this process may run on."""
+    model, tpc = "unknown", None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for ln in out.splitlines():
+            if ln.startswith("Thread(s) per core"):
+                tpc = int(ln.split(":", 1)[1])
+    except Exception:
+        pass
+    return {"model": model, "threads_per_core": tpc, "affinity": len(os.sched_getaffinity(0))}
+
+
+def calibrate(kind: str):
+    """hbm: a plain copy of 1 GiB (6 dispatches), the reference for scaling
+    rocprofv3's FETCH_SIZE / WRITE_SIZE counters; link: pinned host memory to
+    and from the device, 2 GiB per copy, each direction alone and both at once
+    on two streams (the ceiling of the law-state paging)."""
+    import torch
+    if kind == "hbm":
+        n_bytes, reps = 1 << 30, 5
+        x = torch.ones(n_bytes // 4, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        torch.mul(x, 1.0, out=y)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            torch.mul(x, 1.0, out=y)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        print(json.dumps({"calibration": "hbm copy", "bytes_read": n_bytes, "bytes_written": n_bytes,
+                          "dispatches": reps + 1, "gbs_read_plus_write": 2 * n_bytes / dt / 1e9}), flush=True)
+        return
+    n_bytes, reps = 2 << 30, 4
+    h_src = torch.empty(n_bytes, dtype=torch.uint8, pin_memory=True)
+    h_dst = torch.empty(n_bytes, dtype=torch.uint8, pin_memory=True)
+    d_a = torch.empty(n_bytes, dtype=torch.uint8, device="cuda")
+    d_b = torch.empty(n_bytes, dtype=torch.uint8, device="cuda")
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    res = {"calibration": "pinned host link", "bytes_per_copy": n_bytes, "copies": reps}
+
+    def timed(h2d: bool, d2h: bool) -> float:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            if h2d:
+                with torch.cuda.stream(s1):
+                    d_a.copy_(h_src, non_blocking=True)
+            if d2h:
+                with torch.cuda.stream(s2):
+                    h_dst.copy_(d_b, non_blocking=True)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    timed(True, True)  # warm
+    t = timed(True, False)
+    res["h2d_alone_gbs"] = reps * n_bytes / t / 1e9
+    t = timed(False, True)
+    res["d2h_alone_gbs"] = reps * n_bytes / t / 1e9
+    t = timed(True, True)
+    res["both_directions_gbs_each"] = reps * n_bytes / t / 1e9
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -301,10 +417,17 @@ def main():
     ap.add_argument("--mesh", type=str, default="64x64x32")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-steps", type=int, default=3)
-    ap.add_argument("--acc-members", type=int, default=4)
-    ap.add_argument("--acc-steps", type=int, default=150)
-    ap.add_argument("--no-profile", action="store_true", help="no per-launch event timing")
+    ap.add_argument("--cpu-steps", type=int, default=10, help="steps of the CPU oracle sample (all host threads)")
+    ap.add_argument("--cpu-single-steps", type=int, default=1, help="steps of the one-thread oracle sample")
+    ap.add_argument("--acc-steps", type=int, default=150, help="--config 1: steps of the accuracy comparison")
+    ap.add_argument("--pre-steps", type=int, default=0,
+                    help="untimed steps between tuning and the timed window (a window later in the record)")
+    ap.add_argument("--profile-steps", type=int, default=3,
+                    help="steps of the profiled window after the timed steps (per-kernel event timing)")
+    ap.add_argument("--no-profile", action="store_true", help="--config 1: no per-launch event timing")
+    ap.add_argument("--calibrate", choices=("hbm", "link"), default=None,
+                    help="hbm: a plain device copy of known size (for the rocprofv3 counter scale); link: pinned "
+                         "host <-> device copy rates, each direction alone and both at once")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (defaults)")
     ap.add_argument("--inner-dtype", type=int, default=2,
                     help="storage of the inner operator's D: 0 bfloat16 per point, 1 FP32, 2 bfloat16 element mean")
@@ -325,6 +448,8 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); members shard across GPUs "
               "with no exchange, so the one-GPU rate is the per-GPU figure", file=sys.stderr)
         sys.exit(2)
+    if args.calibrate:
+        return calibrate(args.calibrate)
     if args.config == 1:
         return bench_single(args)
     if args.config == 3:
@@ -340,35 +465,46 @@ def main():
     prob.inner_dtype = args.inner_dtype
     fixed = json.loads(args.set_tuning) if args.set_tuning else None
     n_tune = 0 if (args.no_tune or fixed) else autotune.trial_steps(prob)
-    pre = n_tune + args.warmup
+    pre = n_tune + args.warmup + args.pre_steps
     n_total = pre + args.steps
-    # the first n_total samples of the 1500-step records (scaled on the full records)
-    prob.input_acc = np.ascontiguousarray(prob.input_acc[:, :n_total])
-    prob.n_steps = n_total
+    # the first samples of the 1500-step records (scaled on the full records)
+    n_rec = n_total + args.profile_steps
+    prob.input_acc = np.ascontiguousarray(prob.input_acc[:, :n_rec])
+    prob.n_steps = n_rec
     log(f"inputs: {mesh.n_tets} tets, {mesh.n_dof} DOF/member, {args.members} members ({time.perf_counter()-t0:.1f}s)")
     ndof = mesh.n_dof
     sl = slice(pre, n_total)
 
-    # batched mixed precision (the headline), autotuned over the first steps
-    el, st0, st, out_mixed, tuned = run_gpu(mesh, prob, args.warmup, args.steps, not args.no_profile, n_tune,
-                                            fixed=fixed)
+    # batched mixed precision (the headline), autotuned over the first steps;
+    # the timed steps replay hipGraphs with no per-kernel timing; a separate
+    # profiled window of the same ensemble follows for the kernel times
+    el, st0, st, out_mixed, tuned = run_gpu(mesh, prob, args.warmup, args.steps, False, n_tune, fixed=fixed,
+                                            pre_steps=args.pre_steps, profile_steps=args.profile_steps)
     value = args.members * ndof * args.steps / el
     log(f"mixed: {el/args.steps*1e3:.1f} ms/step, {value:.3e} DOF-steps/s, tuning {tuned and {k: tuned.get(k) for k in ('inner_method', 'inner_tol', 'inner_maxit', 'ebe_block', 'check_every', 'cluster_blocks', 'tail_members')}}")
+    log("mixed step ms: " + " ".join(f"{x:.0f}" for x in st["step_ms"]))
+    sp = st.get("prof")
+    psl = slice(n_total, n_total + args.profile_steps)
+    ip_per_dof = 4.0 * mesh.n_tets / ndof
+    n_out = float(out_mixed["iters"][:, sl, 0].mean())
+    n_in = float(out_mixed["iters"][:, sl, 1].mean())
+    step_roof = step_roofline(value, n_out, n_in, prob.n_springs, ip_per_dof)
 
-    # roofline of the dominant kernel, the inner operator's element kernel, over
-    # the timed region (the node gather that completes each application is a
-    # separate, HBM-bound kernel, reported beside it).  The bound follows from
-    # the arithmetic intensity: FP32 ALU when flops per algorithmic byte exceed
-    # the ridge point (157.3 TFLOP/s / 8 TB/s), HBM else.
-    inner = out_mixed["iters"][:, sl, 1].astype(np.int64).sum()
+    # roofline of the dominant kernel, the inner operator's element kernel,
+    # from the profiled window (per-launch HIP events on the library's compute
+    # stream; the node gather that completes each application is a separate,
+    # HBM-bound kernel, reported beside it).  The bound follows from the
+    # arithmetic intensity: FP32 ALU when flops per algorithmic byte exceed the
+    # ridge point (157.3 TFLOP/s / 8 TB/s), HBM else.
     roofline = None
-    if st["n_ebe32"] > 0 and st["ms_ebe32"] > 0:
-        per_unit = ebe32_algorithmic_bytes(mesh.n_tets, mesh.n_nodes, st["members_padded"], prob.inner_dtype)
+    if sp and sp["n_ebe32"] > 0 and sp["ms_ebe32"] > 0:
+        inner = out_mixed["iters"][:, psl, 1].astype(np.int64).sum()
+        per_unit = ebe32_algorithmic_bytes(mesh.n_tets, mesh.n_nodes, sp["members_padded"], prob.inner_dtype)
         # active element-members over all applications, less those of the
         # launches on the list of the last active members
-        units = int(inner) * mesh.n_tets - int(st["elems_tail32"])
-        n_app = st["n_ebe32"]
-        ms = st["ms_ebe32"]
+        units = int(inner) * mesh.n_tets - int(sp["elems_tail32"])
+        n_app = sp["n_ebe32"]
+        ms = sp["ms_ebe32"]
         flops = EBE32_FLOPS_ELEMENT_D if prob.inner_dtype == 2 else EBE32_FLOPS_PER_POINT_D
         alu = flops / per_unit > FP32_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
         gbs = per_unit * units / (ms * 1e-3) / 1e9
@@ -382,73 +518,88 @@ def main():
                     "traffic": tb,
                     "kernel": ("nlth::k_ebe_cluster<float, %d, 0, %d> (inner operator: element forces summed per "
                                "cluster in LDS)" % ({0: 1, 1: 0, 2: 4}[prob.inner_dtype], cb))
-                              if st["members_padded"] >= 64 else
+                              if sp["members_padded"] >= 64 else
                               "nlth::k_ebe<float, 1, 0, false, 1> (inner operator: element forces)",
+                    "timing": f"HIP events around each launch on the compute stream, profiled window of "
+                              f"{args.profile_steps} steps after the timed steps (steps {n_total + 1}-"
+                              f"{n_total + args.profile_steps})",
                     "launches": int(n_app), "avg_launch_us": round(ms / n_app * 1e3, 2),
                     "algorithmic_bytes_per_launch": round(per_unit * units / n_app, 0),
                     "algorithmic_flops_per_launch": round(flops * units / n_app, 0),
                     "bytes_per_element_member": round(per_unit, 1),
                     "flops_per_element_member": flops,
                     "hbm_gbs_algorithmic": round(gbs, 1), "fp32_tflops": round(tfl, 2),
+                    "fp32_nonpacked_peak": FP32_PEAK_TFLOPS / 2,
                     "fp32_nonpacked_frac": round(tfl / (FP32_PEAK_TFLOPS / 2), 4),
                     "gather_kernel": "nlth::k_gather<float, true, true> (node sums of the cluster rows, dot fused)",
-                    "gather_avg_launch_us": round(st["ms_gather32"] / max(1, st["n_gather32"]) * 1e3, 2),
-                    "operator_avg_us": round((st["ms_ebe32"] + st["ms_gather32"]) / n_app * 1e3, 2)}
+                    "gather_avg_launch_us": round(sp["ms_gather32"] / max(1, sp["n_gather32"]) * 1e3, 2),
+                    "operator_avg_us": round((sp["ms_ebe32"] + sp["ms_gather32"]) / n_app * 1e3, 2)}
 
-    # plain FP64 on the same GPU, same members, same timed steps
+    # plain FP64 on the same GPU, same members, same timed steps (graph replay
+    # on, no per-kernel timing, as for the headline)
     fp64 = None
     if not args.no_fp64:
         prob64 = I.config(2, n_members=args.members, mesh_dims=dims, precision=I.PRECISION_FP64)[1]
         prob64.input_acc = np.ascontiguousarray(prob64.input_acc[:, :n_total])
         prob64.n_steps = n_total
         el64, _, st64, out64, _ = run_gpu(mesh, prob64, args.warmup, args.steps, False, n_tune,
-                                          tuned=tuned or {"ebe_block": 256, "check_every": 8})
+                                          tuned=tuned or {"ebe_block": 256, "check_every": 8},
+                                          pre_steps=args.pre_steps)
         v64 = args.members * ndof * args.steps / el64
+        it64 = float(out64["iters"][:, sl, 0].mean())
         fp64 = {"value": v64, "ms_per_step": el64 / args.steps * 1e3, "speedup": value / v64,
-                "iters_per_member_step": float(out64["iters"][:, sl, 0].mean())}
+                "iters_per_member_step": it64,
+                "step_roofline": step_roofline(v64, it64, 0.0, prob.n_springs, ip_per_dof),
+                "step_ms": [round(x, 1) for x in st64["step_ms"]]}
         log(f"fp64: {el64/args.steps*1e3:.1f} ms/step, {v64:.3e} DOF-steps/s")
-        # accuracy of the mixed path (with the tuned inner policy) against FP64:
-        # the first members over a record long enough for the incident wave to
-        # reach the surface
-        na, ns_acc = min(args.members, args.acc_members), args.acc_steps
+        # accuracy of the timed path (64 member slots: cluster operator, compact
+        # tail, the tuned inner policy) against plain FP64: every member over
+        # every step both runs made
         errs = []
-        outs = []
-        for prec in (I.PRECISION_MIXED, I.PRECISION_FP64):
-            pa = I.config(2, n_members=args.members, mesh_dims=dims, precision=prec)[1]
-            for f in ("rho", "vs", "nu", "gamma_ref", "input_acc"):
-                setattr(pa, f, np.ascontiguousarray(getattr(pa, f)[:na]))
-            pa.input_acc = np.ascontiguousarray(pa.input_acc[:, :ns_acc])
-            pa.n_members, pa.n_steps = na, ns_acc
-            if prec == I.PRECISION_MIXED:
-                pa.inner_dtype = prob.inner_dtype
-                if tuned:
-                    pa.inner_tol, pa.inner_maxit = tuned["inner_tol"], tuned["inner_maxit"]
-            outs.append(run_gpu(mesh, pa, 0, ns_acc, False)[3])
-        for m in range(na):
-            a, b = outs[0]["vel"][m], outs[1]["vel"][m]
+        for m in range(args.members):
+            a, b = out_mixed["vel"][m, :n_total], out64["vel"][m, :n_total]
             errs.append(float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)))
         fp64["rel_err_max"] = max(errs)
-        fp64["rel_err_sample"] = f"members 0-{na - 1}, steps 1-{ns_acc}, receiver velocity, relative L2"
-        log(f"mixed vs fp64 over {ns_acc} steps, {na} members: max rel err {max(errs):.2e}")
+        fp64["rel_err_median"] = float(np.median(errs))
+        fp64["rel_err_sample"] = (f"all {args.members} members of the headline run, steps 1-{n_total}, receiver "
+                                  f"velocity, relative L2 per member")
+        log(f"mixed vs fp64 over {n_total} steps, {args.members} members: max rel err {max(errs):.2e}")
 
-    # CPU oracle on a bounded sample of the same workload
+    # CPU oracle on a bounded sample of the same workload: steps of member 0,
+    # setup (CRS pattern, mass, faces) excluded, on the host cores the box
+    # gives this job, and on one thread
     cpu = None
     if not args.no_cpu:
         import oracle
         oracle.build()
+        info = host_cpu_info()
+        cores = int(os.environ.get("OMP_NUM_THREADS", 0) or info["affinity"])
+        oracle.set_threads(cores)
         r = oracle.run(mesh, prob, member=0, n_steps=args.cpu_steps)
-        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        cpu = {"value": ndof * args.cpu_steps / r["seconds"], "unit": "DOF-steps/s", "cores": cores,
+        t_steps = r["seconds"] - r["setup_seconds"]
+        cpu = {"value": ndof * args.cpu_steps / t_steps, "unit": "DOF-steps/s", "cores": cores,
                "kind": "oracle",
-               "sample": f"member 0, steps 1-{args.cpu_steps} of the same record on the same mesh "
-                         f"(FP64 CRS-PCG, tol 1e-8, setup included), {r['seconds']:.1f} s"}
-        log(f"cpu oracle: {cpu['value']:.3e} DOF-steps/s on {cores} threads")
+               "sample": f"member 0, steps 1-{args.cpu_steps} of the same record on the same mesh (FP64 CRS "
+                         f"assembly + block-Jacobi PCG + law per step, tol 1e-8), {t_steps:.1f} s of steps, "
+                         f"setup {r['setup_seconds']:.1f} s excluded",
+               "cpu_model": info["model"], "threads_per_core": info["threads_per_core"],
+               "cpus_in_affinity": info["affinity"]}
+        log(f"cpu oracle: {cpu['value']:.3e} DOF-steps/s on {cores} threads ({info['model']})")
+        if args.cpu_single_steps > 0:
+            oracle.set_threads(1)
+            r1 = oracle.run(mesh, prob, member=0, n_steps=args.cpu_single_steps)
+            t1 = r1["seconds"] - r1["setup_seconds"]
+            cpu["single_thread"] = {"value": ndof * args.cpu_single_steps / t1, "steps": args.cpu_single_steps,
+                                    "seconds": round(t1, 2)}
+            oracle.set_threads(cores)
+            log(f"cpu oracle, one thread: {cpu['single_thread']['value']:.3e} DOF-steps/s")
 
-    # latency: a short request stream at a rate the GPU sustains (0.4/s of
-    # requests of about 1M DOF), with records one tenth of the specified length
+    # latency: a request stream at a rate the GPU sustains, with records
+    # shorter than the specified 500-2000 steps, long enough for p99 to be an
+    # interpolated percentile and not the maximum
     serving = None
     if not args.no_serve:
-        serving = serve_run(0.4, 30.0, (50, 200), max_batch=args.max_batch)
+        serving = serve_run(1.0, 50.0, (20, 60), max_batch=args.max_batch)
         log(f"serving: p50 {serving['p50_s']:.2f} s, p99 {serving['p99_s']:.2f} s over {serving['requests']} requests")
 
     line = {
@@ -468,9 +619,12 @@ def main():
                                                  "cluster_blocks", "tail_members")
                     if k in tuned} if tuned else None),
         "timed_steps": f"steps {pre + 1}-{n_total} of the record",
-        "phase_ms": {"ebe64": st["ms_ebe64"], "ebe32": st["ms_ebe32"], "gather32": st["ms_gather32"],
-                     "tail32": st["ms_tail32"], "law": st["ms_law"], "rhs_diag_q": st["ms_other"]}
-        if not args.no_profile else None,
+        "step_ms": [round(x, 1) for x in st["step_ms"]],
+        "phase_ms_per_step": ({k: round(sp[f] / args.profile_steps, 2) for k, f in
+                               (("ebe64", "ms_ebe64"), ("ebe32", "ms_ebe32"), ("gather32", "ms_gather32"),
+                                ("tail32", "ms_tail32"), ("law", "ms_law"), ("rhs_diag_q", "ms_other"))}
+                              if sp else None),
+        "step_roofline": step_roof,
         "fp64_plain": fp64,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -76,7 +76,9 @@ typedef struct nlth_ens nlth_ens;
 
 typedef struct {
     int64_t hbm_budget;   /* device bytes the library may allocate; 0 = 90 % of free */
-    int64_t host_budget;  /* pinned host bytes for paged law state; 0 = 64 GiB */
+    int64_t host_budget;  /* host bytes the library may hold: pinned law state of paged
+                             ensembles, and the serving loop's input copies of queued
+                             requests and of its batches; 0 = 64 GiB */
     void* stream;         /* optional hipStream_t for compute (e.g. torch's); NULL = own */
     int32_t log_level;    /* 0 silent, 1 per solve, 2 per step */
     int32_t max_batch;    /* serving: most members per batch (0 = 64); a batch is sized,
@@ -286,7 +288,12 @@ int nlth_ens_reset_stats(nlth_ens* ens);
 
 /* Continuous-batching request loop.  submit admits the request (queued until
  * slots and HBM free up); the result buffers must stay valid until poll/wait
- * reports completion.  NLTH_EBUSY if the request can never fit the budgets. */
+ * reports completion.  The request's input copy is charged to the host budget
+ * from submission until its members take slots, and each batch's copy of its
+ * members' inputs while the batch lives.  NLTH_EBUSY if the request can never
+ * fit the budgets, or if the host budget cannot hold its input copy now
+ * (submit again later).  A request whose batch cannot be made while nothing
+ * else runs ends with NLTH_ENOMEM_DEVICE or NLTH_ENOMEM_HOST. */
 int nlth_submit(nlth_ctx* ctx, const nlth_mesh* mesh, const nlth_problem* prob, nlth_result* res,
                 uint64_t* ticket);
 int nlth_poll(nlth_ctx* ctx, uint64_t ticket, int32_t* done);

@@ -231,7 +231,7 @@ struct Request {
     std::atomic<int> cancel{0};
     int status = 0;
     int members_left = 0;  // guarded by the context's request lock
-    int64_t need_bytes = 0;
+    int64_t host_bytes = 0;  // input copy charged to the host budget while queued
 };
 
 void serve_shutdown(Ctx* c);

@@ -26,12 +26,45 @@ struct Slot {
     int n_steps = 0;
 };
 
+// Host memory of the serving loop, charged against the context's host budget
+// beside the pinned law state of paged ensembles: the input copy of every
+// queued request (from submission until its members take slots) and each
+// batch's own copy of its members' inputs.
+static int64_t problem_host_bytes(const Problem& p)
+{
+    return (int64_t)(p.rho.size() + p.vs.size() + p.nu.size() + p.gref.size() + p.hmax.size() + p.dirs.size() +
+                     p.w.size() + p.acc.size()) * 8 + (int64_t)p.nonlinear.size() * 4;
+}
+
+static bool host_charge(Budget& b, int64_t n, int64_t* used = nullptr)
+{
+    std::lock_guard<std::mutex> g(b.mu);
+    if (used) *used = b.host_used;
+    if (b.host_limit > 0 && b.host_used + n > b.host_limit) return false;
+    b.host_used += n;
+    return true;
+}
+
+static void host_uncharge(Budget& b, int64_t& n)
+{
+    if (n == 0) return;
+    std::lock_guard<std::mutex> g(b.mu);
+    b.host_used -= n;
+    n = 0;
+}
+
 struct Batch {
     const Mesh* mesh = nullptr;
     Problem key;  // shared parameters (per-member arrays unused)
     std::unique_ptr<Ens> ens;
     std::vector<Slot> slots;
     int cap_steps = 0;
+    Budget* budget = nullptr;  // host bytes of the batch's input copy, charged while it lives
+    int64_t host_bytes = 0;
+    ~Batch()
+    {
+        if (budget) host_uncharge(*budget, host_bytes);
+    }
     int busy() const
     {
         int n = 0;
@@ -148,6 +181,7 @@ void Ctx::worker_loop()
                 auto r = queue.front();
                 queue.pop_front();
                 if (r->cancel.load()) {
+                    host_uncharge(budget, r->host_bytes);
                     r->status = NLTH_ECANCELED;
                     r->state = 3;
                     r->mesh->refs--;
@@ -178,6 +212,7 @@ void Ctx::worker_loop()
                     slots = std::max(slots, need);
                     bool made = false;
                     std::string why;
+                    int why_code = NLTH_ENOMEM_DEVICE;
                     while (!made && slots >= need) {
                         Problem tp = r->P;
                         tp.nm = slots;
@@ -194,15 +229,29 @@ void Ctx::worker_loop()
                                 tp.gref[(size_t)k * tp.nl + l] = r->P.gref[l];
                             }
                         tp.acc.assign((size_t)slots * tp.n_steps * 3, 0.0);
+                        int64_t hb = problem_host_bytes(tp);
+                        if (!host_charge(budget, hb)) {
+                            char buf[160];
+                            snprintf(buf, sizeof buf, "host budget: a batch of %d slots needs %.3f MB of inputs",
+                                     slots, hb / 1e6);
+                            why = buf;
+                            why_code = NLTH_ENOMEM_HOST;
+                            slots /= 2;
+                            continue;
+                        }
                         try {
                             std::lock_guard<std::mutex> g(mu);
                             std::unique_ptr<Ens> e(new Ens());
                             e->create(this, r->mesh, tp, pad_members(slots));
                             if (e->paged) throw Error{NLTH_ENOMEM_DEVICE, "serving batches keep their state resident"};
                             nb->ens = std::move(e);
+                            nb->budget = &budget;
+                            nb->host_bytes = hb;
                             made = true;
                         } catch (const Error& err) {
+                            host_uncharge(budget, hb);
                             why = err.msg;
+                            why_code = err.code == NLTH_ENOMEM_HOST ? NLTH_ENOMEM_HOST : NLTH_ENOMEM_DEVICE;
                             slots /= 2;
                         }
                     }
@@ -212,10 +261,11 @@ void Ctx::worker_loop()
                         if (busy) {  // wait for running batches to free memory
                             keep.push_back(r);
                         } else {     // nothing else holds memory: it cannot run
-                            r->status = NLTH_ENOMEM_DEVICE;
+                            host_uncharge(budget, r->host_bytes);
+                            r->status = why_code;
                             r->state = 2;
                             r->mesh->refs--;
-                            set_error(this, Error{NLTH_ENOMEM_DEVICE, why});
+                            set_error(this, Error{why_code, why});
                             scv.notify_all();
                         }
                         continue;
@@ -254,6 +304,7 @@ void Ctx::worker_loop()
                 }
                 r->state = 1;
                 std::vector<double>().swap(r->P.acc);  // the batch holds its own copy
+                host_uncharge(budget, r->host_bytes);
             }
             for (auto& r : keep) queue.push_back(r);
         }
@@ -356,6 +407,25 @@ int nlth_submit(nlth_ctx* ctx, const nlth_mesh* mesh, const nlth_problem* prob, 
                      ctx->budget.limit / 1e9);
             throw Error{NLTH_EBUSY, buf};
         }
+        // the host budget must hold the request's input copy until its members
+        // take slots (and can it ever hold it?)
+        const int64_t hb = problem_host_bytes(r->P);
+        if (ctx->budget.host_limit > 0 && hb > ctx->budget.host_limit) {
+            char buf[160];
+            snprintf(buf, sizeof buf, "request inputs need %.3f MB of host memory, host budget is %.3f MB", hb / 1e6,
+                     ctx->budget.host_limit / 1e6);
+            throw Error{NLTH_EBUSY, buf};
+        }
+        int64_t held = 0;
+        if (!host_charge(ctx->budget, hb, &held)) {
+            char buf[200];
+            snprintf(buf, sizeof buf,
+                     "host budget: queued requests, batches and paged state hold %.3f of %.3f MB; "
+                     "this request needs %.3f MB (submit again when requests finish)",
+                     held / 1e6, ctx->budget.host_limit / 1e6, hb / 1e6);
+            throw Error{NLTH_EBUSY, buf};
+        }
+        r->host_bytes = hb;
         r->mesh = mesh;
         r->res = *res;
         r->members_left = r->P.nm;

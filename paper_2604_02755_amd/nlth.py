@@ -218,6 +218,8 @@ def nlth_mesh_query(ctx, mesh_h, n_tets: int, n_colors_max: int = 256):
 
 
 def _problem_struct(prob, keep, members=None, n_steps=None):
+    """nlth_problem from the problem's arrays; the shapes the library reads
+    are checked here (a short array would otherwise be read past its end)."""
     sel = slice(None) if members is None else members
     rho = _f64(np.asarray(prob.rho)[sel])
     vs = _f64(np.asarray(prob.vs)[sel])
@@ -228,7 +230,20 @@ def _problem_struct(prob, keep, members=None, n_steps=None):
     dirs = _f64(prob.dirs)
     w = _f64(prob.weights)
     ns = int(prob.n_steps if n_steps is None else n_steps)
-    acc = _f64(np.asarray(prob.input_acc)[sel][:, :ns])
+    acc_all = np.asarray(prob.input_acc)[sel]
+    if rho.ndim != 2:
+        raise ValueError(f"rho must be [n_members, n_layers], got shape {rho.shape}")
+    nm, nly = rho.shape
+    for name, a in (("vs", vs), ("nu", nu), ("gamma_ref", gr)):
+        if a.shape != (nm, nly):
+            raise ValueError(f"{name} must have shape {(nm, nly)} like rho, got {a.shape}")
+    if hm.shape != (nly,) or nl.shape != (nly,):
+        raise ValueError(f"h_max and nonlinear must have {nly} entries (one per layer), got {hm.shape}, {nl.shape}")
+    if dirs.ndim != 2 or dirs.shape[1] != 6 or w.shape != (dirs.shape[0],):
+        raise ValueError(f"dirs must be [n_springs, 6] and weights [n_springs], got {dirs.shape}, {w.shape}")
+    if ns < 0 or acc_all.ndim != 3 or acc_all.shape[0] != nm or acc_all.shape[1] < ns or acc_all.shape[2] != 3:
+        raise ValueError(f"input_acc must be [n_members={nm}, >= n_steps={ns}, 3], got {acc_all.shape}")
+    acc = _f64(acc_all[:, :ns])
     keep += [rho, vs, nu, gr, hm, nl, dirs, w, acc]
     return nlth_problem(int(rho.shape[0]), int(rho.shape[1]), _ptr(rho), _ptr(vs), _ptr(nu), _ptr(gr),
                         _ptr(hm), _ptr(nl, _ip), int(dirs.shape[0]), _ptr(dirs), _ptr(w),

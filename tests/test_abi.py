@@ -145,3 +145,30 @@ def test_struct_layouts_match_header(nlth_mod, tmp_path):
     got = {k: int(v) for k, v in (ln.split() for ln in out.splitlines())}
     diff = {k: (got[k], want[k]) for k in want if got[k] != want[k]}
     assert not diff, diff
+
+
+def test_binding_rejects_short_problem_arrays(nlth_mod):
+    """The binding checks the shapes the library reads before any call: a
+    record shorter than n_steps or per-layer arrays of the wrong length raise
+    ValueError instead of becoming a read past the end of an array."""
+    mesh, prob = I.config(0, n_steps=10, mesh_dims=(3, 3, 2), n_members=2)
+    keep = []
+    p = nlth_mod._problem_struct(prob, keep)
+    assert p.n_members == 2 and p.n_steps == 10 and p.n_layers == 2
+    bad = []
+    for field, val in (("input_acc", prob.input_acc[:, :9]), ("input_acc", prob.input_acc[:1]),
+                       ("h_max", np.asarray(prob.h_max)[:1]), ("nonlinear", np.ones(3, np.int32)),
+                       ("dirs", np.asarray(prob.dirs)[:, :5]), ("weights", np.asarray(prob.weights)[:-1]),
+                       ("vs", np.asarray(prob.vs)[:, :1])):
+        old = getattr(prob, field)
+        setattr(prob, field, val)
+        try:
+            nlth_mod._problem_struct(prob, [])
+        except ValueError as e:
+            bad.append((field, str(e)))
+        finally:
+            setattr(prob, field, old)
+    assert len(bad) == 7, bad
+    # selecting members or fewer steps than the record holds is fine
+    p = nlth_mod._problem_struct(prob, [], members=[1], n_steps=4)
+    assert p.n_members == 1 and p.n_steps == 4

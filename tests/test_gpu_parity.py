@@ -103,7 +103,11 @@ def test_fp64_path_parity_small(gpu_ctx, oracle_lib):
     say("  rel L2", err, "iters gpu", out["iters"][0, :8, 0], "oracle", itref[:8])
     assert err < 1e-9
     assert np.max(np.abs(out["iters"][0, :, 0] - itref)) <= 1
-    assert np.isfinite(out["vmax"]).all() and out["vmax"].max() > 0
+    # maximum velocity-norm map (Section 3, Figs. 3-4) against the oracle's
+    ref = oracle_lib.run(mesh, prob)
+    verr = float(np.max(np.abs(out["vmax"][0] - ref["vmax"])) / np.max(ref["vmax"]))
+    say("  vmax max rel err", verr)
+    assert ref["vmax"].max() > 0 and verr < 1e-9
 
 
 def test_mixed_path_parity_small(gpu_ctx, oracle_lib):
@@ -437,3 +441,94 @@ def test_response_spectra_matches_oracle(gpu_ctx, oracle_lib, nlth_mod):
     with pytest.raises(nlth_mod.NlthError) as ei:
         gpu_ctx.response_spectra(recs[0], dt, [0.1, -1.0])
     assert ei.value.code == nlth_mod.NLTH_EINVAL
+
+
+def _three_layer(n_members, n_steps, precision, tol, dims=(8, 8, 8), ns=150, seed=5):
+    """Config-1 geometry at test size: three layers whose interfaces follow
+    seeded smooth random surfaces (nodes moved to fit), 150 springs."""
+    mesh = I.perturbed_three_layer_mesh(*dims, seed=seed, amp=0.8, corr=4.0, recv_stride=2)
+    acc = 8.0 * I.member_waves(1, range(n_members), n_steps, 1e-3)
+    prob = I.make_problem(n_members, (150.0, 250.0, 400.0), (1700.0, 1800.0, 1900.0), n_springs=ns,
+                          n_steps=n_steps, input_acc=acc, cg_tol=tol, precision=precision)
+    if n_members > 1:
+        vs, gr = I.ensemble_members(2100, n_members, (150.0, 250.0, 400.0))
+        prob.vs = np.ascontiguousarray(vs)
+        prob.gamma_ref = np.ascontiguousarray(np.tile(gr[:, None], (1, 3)))
+    return mesh, prob
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_perturbed_three_layer_mesh_matches_oracle(gpu_ctx, oracle_lib, precision):
+    """Distorted, non-box geometry (three layers with perturbed interfaces,
+    150 springs per point): one member, and 64 members on the cluster path
+    (members 0 and 63 checked), against the oracle at tolerance 1e-12."""
+    for nm in (1, 64):
+        mesh, prob = _three_layer(nm, 30, precision, 1e-12)
+        if precision == 1:
+            prob.inner_dtype = 2 if nm == 64 else 0
+        say("three-layer mesh", mesh.n_tets, "tets, members", nm, "precision", precision)
+        mh = gpu_ctx.mesh(mesh)
+        out = gpu_ctx.solve(mh, mesh, prob)
+        assert out["rc"] == 0
+        for m in ((0,) if nm == 1 else (0, 63)):
+            ref = oracle_lib.run(mesh, prob, member=m)
+            err = oracle_lib.rel_l2(out["vel"][m], ref["vel"])
+            say("  member", m, "rel L2 vs oracle", err, "law events", ref["law_events"])
+            assert np.abs(ref["vel"]).max() > 0 and err < 1e-9
+            assert ref["law_events"][0] > 0  # the springs yield and reverse
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_long_run_reaches_every_law_event(gpu_ctx, oracle_lib, precision):
+    """A long nonlinear run (400 steps) on a tiny mesh: the oracle counts
+    reversals taken on the skeleton, reversals taken on a Masing branch and
+    rejoins of the skeleton, all of which occur; the GPU run matches the
+    oracle's receiver velocity through all of them."""
+    mesh, prob = _small_problem(n_steps=400, precision=precision, tol=1e-12, dims=(4, 3, 2), ns=12, scale=6.0)
+    say("long law run, precision", precision, prob.n_steps, "steps")
+    ref = oracle_lib.run(mesh, prob)
+    ev = ref["law_events"]
+    say("  oracle law events (skeleton reversals, branch reversals, rejoins)", ev)
+    assert ev[0] > 0 and ev[1] > 0 and ev[2] > 0
+    out = gpu_ctx.solve(gpu_ctx.mesh(mesh), mesh, prob)
+    err = oracle_lib.rel_l2(out["vel"][0], ref["vel"])
+    verr = float(np.max(np.abs(out["vmax"][0] - ref["vmax"])) / np.max(ref["vmax"]))
+    say("  rel L2 vs oracle", err, "vmax rel err", verr)
+    assert out["rc"] == 0 and err < 1e-9 and verr < 1e-9
+
+
+def test_benchmark_path_at_throughput_tolerance(gpu_ctx, oracle_lib):
+    """The benchmark's launch configuration at its operating point: 64 member
+    slots (cluster operator, element-mean bfloat16 inner D, compact rows for
+    the convergence tail), a fixed 20 inner iterations per outer iteration,
+    CG tolerance 1e-8.  Every member stays within 1e-6 of the plain FP64 path
+    at 1e-8, and members 0 and 63 within 1e-6 of the oracle."""
+    mesh, pm = _small_problem(precision=1, n_members=64, n_steps=60, dims=(6, 5, 3), ns=12, tol=1e-8)
+    _, p64 = _small_problem(precision=0, n_members=64, n_steps=60, dims=(6, 5, 3), ns=12, tol=1e-8)
+    vs, gr = I.ensemble_members(91, 64, I.CFG0_LAYERS["vs"])
+    acc = 5.0 * I.member_waves(2, range(64), pm.n_steps, pm.dt)
+    for p in (pm, p64):
+        p.vs = vs
+        p.gamma_ref = np.tile(gr[:, None], (1, 2))
+        p.input_acc = acc
+    pm.inner_dtype = 2
+    mh = gpu_ctx.mesh(mesh)
+    ens = gpu_ctx.ensemble(mh, mesh, pm)
+    try:
+        ens.set_tuning(128, 16, 1, 20, 1e-12, cluster_blocks=3, tail_members=32)
+        ens.set_profile(True)
+        ens.step(pm.n_steps)
+        om, st = ens.read(), ens.stats()
+    finally:
+        ens.close()
+    o64 = gpu_ctx.solve(mh, mesh, p64)
+    say("benchmark path at 1e-8: cluster launches", st["n_ebe32"], "compact-row launches", st["n_tail32"])
+    assert st["n_ebe32"] > 0 and st["n_tail32"] > 0
+    errs = [oracle_lib.rel_l2(om["vel"][m], o64["vel"][m]) for m in range(64)]
+    say("  mixed vs fp64, max over 64 members", max(errs))
+    assert max(errs) < 1e-6
+    for m in (0, 63):
+        ref = oracle_lib.run(mesh, pm, member=m, cg_tol=1e-12)
+        err = oracle_lib.rel_l2(om["vel"][m], ref["vel"])
+        say("  member", m, "vs oracle", err)
+        assert err < 1e-6

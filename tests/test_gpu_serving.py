@@ -1,8 +1,9 @@
 """Continuous-batching request loop: requests of mixed mesh sizes admitted into
 member slots while others run; each result must equal the same problem solved
 alone (FP64 path: 1e-12 relative, i.e. reduction-order level; mixed path:
-1e-6, the mixed-precision bar).  Cancellation and budget refusal are checked
-from the host."""
+1e-6, the mixed-precision bar) and the oracle (1e-9 for FP64, 1e-6 for mixed;
+tolerance 1e-12 on both sides).  Cancellation and refusals by the device and
+host budgets are checked from the host."""
 import time
 
 import numpy as np
@@ -14,7 +15,7 @@ pytestmark = pytest.mark.gpu
 
 
 def _request(dims, seed, steps, precision):
-    mesh, prob = I.config(0, n_steps=steps, mesh_dims=dims, cg_tol=1e-10, precision=precision,
+    mesh, prob = I.config(0, n_steps=steps, mesh_dims=dims, cg_tol=1e-12, precision=precision,
                           n_springs=12)
     rng = np.random.default_rng(seed)
     prob.vs = prob.vs * np.exp(0.2 * rng.standard_normal(prob.vs.shape))
@@ -22,8 +23,8 @@ def _request(dims, seed, steps, precision):
     return mesh, prob
 
 
-@pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 1e-6)])
-def test_results_alone_and_in_the_mix(nlth_mod, precision, tol):
+@pytest.mark.parametrize("precision,tol,tol_oracle", [(0, 1e-12, 1e-9), (1, 1e-6, 1e-6)])
+def test_results_alone_in_the_mix_and_oracle(nlth_mod, oracle_lib, precision, tol, tol_oracle):
     ctx = nlth_mod.Context(0, max_batch=4, use_torch_stream=False)
     try:
         meshes = {}
@@ -44,8 +45,11 @@ def test_results_alone_and_in_the_mix(nlth_mod, precision, tol):
             assert rc == 0, rc
             alone = ctx.solve(meshes[dims][0], mesh, prob)
             err = np.linalg.norm(out["vel"] - alone["vel"]) / np.linalg.norm(alone["vel"])
-            print("  ticket", t, dims, "in the mix vs alone", err, flush=True)
+            ref = oracle_lib.run(mesh, prob)
+            err_or = oracle_lib.rel_l2(out["vel"][0], ref["vel"])
+            print("  ticket", t, dims, "in the mix vs alone", err, "vs oracle", err_or, flush=True)
             assert err < tol
+            assert np.abs(ref["vel"]).max() > 0 and err_or < tol_oracle
             assert np.array_equal(out["iters"][0, :, 0] > 0, alone["iters"][0, :, 0] > 0)
             assert ctx.release(t) == 0
             assert ctx.poll(t)[1] == nlth_mod.NLTH_ENOTFOUND
@@ -76,3 +80,33 @@ def test_cancel_and_budget_refusal(nlth_mod):
         assert ei.value.code == nlth_mod.NLTH_EBUSY
     finally:
         small.close()
+
+
+def test_host_budget_admission(nlth_mod):
+    """Admission by host memory: a request whose input copy can never fit the
+    host budget is refused at submission (NLTH_EBUSY); one that fits but whose
+    batch (its own copy of the members' inputs, 2048 steps per slot) cannot be
+    held beside it while nothing else runs ends with NLTH_ENOMEM_HOST; with
+    room for both it runs."""
+    mesh, prob = _request((4, 4, 2), 11, 1500, 0)  # input copy 1500 x 3 x 8 B = 36 kB
+    for budget, expect in ((16_000, "refused"), (60_000, "no batch"), (1 << 30, "runs")):
+        ctx = nlth_mod.Context(0, max_batch=1, host_budget=budget, use_torch_stream=False)
+        try:
+            mh = ctx.mesh(mesh)
+            if expect == "refused":
+                with pytest.raises(nlth_mod.NlthError) as ei:
+                    ctx.submit(mh, mesh, prob)
+                print("host budget", budget, "refused:", str(ei.value), flush=True)
+                assert ei.value.code == nlth_mod.NLTH_EBUSY
+                continue
+            prob.n_steps = 40 if expect == "runs" else 1500
+            t, out = ctx.submit(mh, mesh, prob)
+            rc = ctx.wait(t, 120.0)
+            print("host budget", budget, expect, "rc", rc, flush=True)
+            if expect == "no batch":
+                assert rc == nlth_mod.NLTH_ENOMEM_HOST
+            else:
+                assert rc == 0 and np.abs(out["vel"]).max() > 0
+            ctx.release(t)
+        finally:
+            ctx.close()
