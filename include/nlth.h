@@ -333,6 +333,23 @@ int nlth_apply_operator(nlth_ctx* ctx, const nlth_mesh* mesh, const nlth_problem
                         int32_t precision, const double* D_ip, const double* h, const double* x,
                         double* y);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * nlth_apply_operator's FP64 application y = Op x for member 0 of `prob`, on
+ * caller-owned DEVICE buffers, with no allocation.  D_ip [n_tets*4*21] (input
+ * tet order, upper triangle of D row by row per point), h [n_tets] (NULL =
+ * 0), x and y [3*n_nodes] (input node order).  Every intermediate lives in a
+ * library-held device array of 64 MiB per device (reserved for the life of
+ * the process), enough for meshes up to about 67,000 tets; larger meshes give
+ * NLTH_EINVAL, as do more than 32 layers.  The work is queued on the
+ * context's compute stream and the call returns without waiting: y is ready
+ * when that stream has drained.  Calls on one context are ordered by its
+ * stream; calls through different contexts (streams) of one device share the
+ * array and race when they overlap.  Same kernels, same results as
+ * nlth_apply_operator with precision NLTH_FP64. */
+int nlth_apply_operator_noalloc(nlth_ctx* ctx, const nlth_mesh* mesh, const nlth_problem* prob, int32_t which,
+                                const double* D_ip, const double* h, const double* x, double* y);
+
 #ifdef __cplusplus
 }
 #endif

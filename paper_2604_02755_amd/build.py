@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libnlth.so")
-SOURCES = ["kernels.hip", "vec.hip", "api.hip", "serve.hip", "spectra.hip"]
+SOURCES = ["kernels.hip", "vec.hip", "api.hip", "serve.hip", "spectra.hip", "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("NLTH_ARCH", "gfx950")
 FLAGS = ["-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC",

@@ -549,6 +549,8 @@ static void build_mesh_internal(Ctx* ctx, const nlth_mesh_desc* d, Mesh& M)
     upload(b, M.cl_lconn_d, cl_lconn);
     upload(b, M.cn_ptr_d, cn_ptr);
     upload(b, M.cn_row_d, cn_row);
+    upload(b, M.order_d, M.order);
+    upload(b, M.node_new_d, M.node_new);
 }
 
 DevMesh Mesh::dev() const
@@ -655,6 +657,8 @@ static void rayleigh_fit(double fl, double fh, double* a, double* b)
     *a = (t1 * s22 - s12 * t2) / det;
     *b = (s11 * t2 - s12 * t1) / det;
 }
+
+void rayleigh_coefficients(double f_lo, double f_hi, double* a, double* b) { rayleigh_fit(f_lo, f_hi, a, b); }
 
 int64_t ensemble_bytes(const Mesh& m, const Problem& p, int MB, bool paged)
 {
@@ -1652,6 +1656,7 @@ int nlth_ctx_create(int device, const nlth_ctx_opts* opts, nlth_ctx** out)
         if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n)
             throw Error{NLTH_EDEVICE, "no such HIP device"};
         NLTH_HIP(hipSetDevice(device));
+        scratch_setup(device);
         size_t fr = 0, tot = 0;
         NLTH_HIP(hipMemGetInfo(&fr, &tot));
         c->budget.limit = (opts && opts->hbm_budget > 0) ? opts->hbm_budget : (int64_t)(0.9 * fr);

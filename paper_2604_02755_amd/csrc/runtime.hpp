@@ -69,6 +69,7 @@ struct Mesh {
     DevBuf conn, geo64, geo32, layer, bn_node, bn_ptr, bn_face, bn_loc, f_node, f_M, f_n, f_layer, f_kind, recv_d;
     DevBuf inc_ptr, inc, celem, bn_of;
     DevBuf cl_off_d, cl_noff_d, cl_lconn_d, cn_ptr_d, cn_row_d;
+    DevBuf order_d, node_new_d;    // storage position -> input tet; input node -> storage node
     int ncl = 0;
     long cl_rows = 0;  // total rows of the clusters' node lists
     int nbn = 0;
@@ -235,6 +236,11 @@ struct Request {
 };
 
 void serve_shutdown(Ctx* c);
+// device address of the allocation-free entry point's scratch array on
+// `device` (current), taken once per device
+void scratch_setup(int device);
+// least-squares Rayleigh fit of alpha/(4 pi f) + pi beta f to 1 over [f_lo, f_hi]
+void rayleigh_coefficients(double f_lo, double f_hi, double* a, double* b);
 
 void set_error(Ctx* c, const Error& e);
 int64_t ensemble_bytes(const Mesh& m, const Problem& p, int MB, bool paged);

@@ -119,17 +119,28 @@ EXPORTS = {
                                       C.c_int32, _dp, _dp, _dp, _dp]),
     "nlth_response_spectra": (C.c_int, [C.c_void_p, _dp, C.c_int32, C.c_int32, C.c_double, _dp, C.c_int32,
                                         C.c_double, C.c_int32, _dp]),
+    "nlth_apply_operator_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(nlth_problem), C.c_int32,
+                                              C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
 }
 
 _lib = None
 
 
 def lib():
-    """Load libnlth.so (raises if it is missing: no CPU fallback exists)."""
+    """Load libnlth.so (raises if it is missing: no CPU fallback exists).
+
+    PyTorch, when installed, is imported first: its wheel carries its own HIP
+    runtime, and a process must hold only one.  Loaded after torch, the
+    library binds to torch's runtime (same soname); loaded before it, torch
+    would bring a second HIP/HSA runtime that cannot open the device again."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2604_02755_amd.build`")
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in EXPORTS.items():
             f = getattr(L, name)
@@ -294,6 +305,16 @@ def nlth_apply_operator(ctx, mesh_h, prob, which, precision, D_ip, h, x):
     _check(lib().nlth_apply_operator(ctx, mesh_h, C.byref(p), int(which), int(precision), _ptr(D),
                                      _ptr(hh), _ptr(xx), _ptr(y)), ctx)
     return y
+
+
+def nlth_apply_operator_noalloc(ctx, mesh_h, prob, which, D_ptr, h_ptr, x_ptr, y_ptr):
+    """FP64 y = Op x on device buffers (addresses as integers; h_ptr may be 0),
+    queued on the context's stream with no allocation; returns once queued."""
+    keep = []
+    p = _problem_struct(prob, keep, [0], 0)
+    _check(lib().nlth_apply_operator_noalloc(ctx, mesh_h, C.byref(p), int(which), C.c_void_p(int(D_ptr)),
+                                             C.c_void_p(int(h_ptr)) if h_ptr else None, C.c_void_p(int(x_ptr)),
+                                             C.c_void_p(int(y_ptr))), ctx)
 
 
 # ---------------------------------------------------------------------------
