@@ -108,10 +108,10 @@ def traffic_from_profile(src_hash: str, element_members_per_launch: float):
 
 def run_gpu(mesh, prob, warmup, steps, profile, tune_steps=0, tuned=None, ctx_kw=None, fixed=None, tuning_kw=None,
             pre_steps=0, profile_steps=0):
-    """Create the ensemble, step ``warmup`` steps, autotune it over the next
-    ``tune_steps`` steps (or apply the launch shapes of ``tuned`` and step as
-    many), step ``pre_steps`` more untimed, then time ``steps`` steps one by
-    one (hipGraph replay on; per-kernel event timing only if ``profile``).
+    """Create the ensemble, step ``warmup`` and then ``pre_steps`` steps,
+    autotune it over the next ``tune_steps`` steps (or apply the launch shapes
+    of ``tuned`` and step as many), then time ``steps`` steps one by one
+    (hipGraph replay on; per-kernel event timing only if ``profile``).
     With ``profile_steps`` > 0 a separate window of that many steps follows
     with per-kernel event timing on (which replaces graph replay by direct
     launches of the same kernels); its stats are returned as ``st["prof"]``."""
@@ -125,13 +125,16 @@ def run_gpu(mesh, prob, warmup, steps, profile, tune_steps=0, tuned=None, ctx_kw
         if fixed is not None:
             ens.set_tuning(fixed["ebe_block"], fixed["check_every"], 1, fixed["inner_maxit"], fixed["inner_tol"],
                            cluster_blocks=fixed.get("cluster_blocks", 0), inner_method=fixed.get("inner_method", 0),
-                           tail_members=fixed.get("tail_members", -1))
+                           tail_members=fixed.get("tail_members", -1), predictor=fixed.get("predictor", 0))
             choice = dict(fixed)
-        if tuned is not None:
-            ens.set_tuning(tuned["ebe_block"], tuned["check_every"], 1, cluster_blocks=tuned.get("cluster_blocks", 0))
+        if tuned is not None:  # the launch shapes and the initial-guess policy of the tuned mixed run
+            ens.set_tuning(tuned["ebe_block"], tuned["check_every"], 1, cluster_blocks=tuned.get("cluster_blocks", 0),
+                           predictor=tuned.get("predictor", 0))
         if tuning_kw:
             ens.set_tuning(**tuning_kw)
         ens.step(warmup)  # the first steps carry no wave yet: warm up before tuning
+        if pre_steps > 0:  # into the regime of the timed window, so the tuning sees it too
+            ens.step(pre_steps)
         if tuned is not None:
             ens.step(tune_steps)
         elif tune_steps > 0:
@@ -139,8 +142,6 @@ def run_gpu(mesh, prob, warmup, steps, profile, tune_steps=0, tuned=None, ctx_kw
             choice = autotune.tune(ens, mesh, prob, steps_per_trial=1, log=log)
             used = ens.stats()["steps_done"] - done0
             ens.step(max(0, tune_steps - used))
-        if pre_steps > 0:
-            ens.step(pre_steps)
         ens.reset_stats()
         ens.set_profile(profile)
         st0 = ens.stats()
@@ -420,8 +421,10 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=10, help="steps of the CPU oracle sample (all host threads)")
     ap.add_argument("--cpu-single-steps", type=int, default=1, help="steps of the one-thread oracle sample")
     ap.add_argument("--acc-steps", type=int, default=150, help="--config 1: steps of the accuracy comparison")
-    ap.add_argument("--pre-steps", type=int, default=0,
-                    help="untimed steps between tuning and the timed window (a window later in the record)")
+    ap.add_argument("--window-start", type=int, default=130,
+                    help="steps before the timed window (warmup and autotuning included, untimed steps added): "
+                         "the incident wave needs about 100 steps to fill the 32 m of soil, so the window and the "
+                         "accuracy comparison cover the developed response")
     ap.add_argument("--profile-steps", type=int, default=3,
                     help="steps of the profiled window after the timed steps (per-kernel event timing)")
     ap.add_argument("--no-profile", action="store_true", help="--config 1: no per-launch event timing")
@@ -465,6 +468,7 @@ def main():
     prob.inner_dtype = args.inner_dtype
     fixed = json.loads(args.set_tuning) if args.set_tuning else None
     n_tune = 0 if (args.no_tune or fixed) else autotune.trial_steps(prob)
+    args.pre_steps = max(0, args.window_start - n_tune - args.warmup)
     pre = n_tune + args.warmup + args.pre_steps
     n_total = pre + args.steps
     # the first samples of the 1500-step records (scaled on the full records)
@@ -481,7 +485,7 @@ def main():
     el, st0, st, out_mixed, tuned = run_gpu(mesh, prob, args.warmup, args.steps, False, n_tune, fixed=fixed,
                                             pre_steps=args.pre_steps, profile_steps=args.profile_steps)
     value = args.members * ndof * args.steps / el
-    log(f"mixed: {el/args.steps*1e3:.1f} ms/step, {value:.3e} DOF-steps/s, tuning {tuned and {k: tuned.get(k) for k in ('inner_method', 'inner_tol', 'inner_maxit', 'ebe_block', 'check_every', 'cluster_blocks', 'tail_members')}}")
+    log(f"mixed: {el/args.steps*1e3:.1f} ms/step, {value:.3e} DOF-steps/s, tuning {tuned and {k: tuned.get(k) for k in ('predictor', 'inner_method', 'inner_tol', 'inner_maxit', 'ebe_block', 'check_every', 'cluster_blocks', 'tail_members')}}")
     log("mixed step ms: " + " ".join(f"{x:.0f}" for x in st["step_ms"]))
     sp = st.get("prof")
     psl = slice(n_total, n_total + args.profile_steps)
@@ -615,8 +619,8 @@ def main():
                    "parallelism": "members batched in one launch"},
         "iterations": {"outer_per_member_step": float(out_mixed["iters"][:, sl, 0].mean()),
                        "inner_per_member_step": float(out_mixed["iters"][:, sl, 1].mean())},
-        "tuning": ({k: tuned.get(k, 0) for k in ("inner_method", "inner_tol", "inner_maxit", "ebe_block", "check_every",
-                                                 "cluster_blocks", "tail_members")
+        "tuning": ({k: tuned.get(k, 0) for k in ("predictor", "inner_method", "inner_tol", "inner_maxit", "ebe_block",
+                                                 "check_every", "cluster_blocks", "tail_members")
                     if k in tuned} if tuned else None),
         "timed_steps": f"steps {pre + 1}-{n_total} of the record",
         "step_ms": [round(x, 1) for x in st["step_ms"]],

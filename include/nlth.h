@@ -67,6 +67,7 @@ extern "C" {
 #define NLTH_OP_A 0 /* 4/dt^2 M + 2/dt C + K (Eq. 1 left-hand side) */
 #define NLTH_OP_K 1 /* K */
 #define NLTH_OP_M 2 /* M */
+#define NLTH_OP_DIAG 3 /* the 3x3 diagonal blocks of A (the block-Jacobi preconditioner's) */
 
 #define NLTH_DEVICE_NONE (-1) /* host-only context: validation and mesh analysis */
 
@@ -252,7 +253,8 @@ int nlth_ens_stats(const nlth_ens* ens, nlth_stats* st);
  * not 0/2/3/4, scatter outside -1..2 or not available for this ensemble,
  * inner_method outside -1..1, Chebyshev with a degree above 64, zero_copy outside
  * -1..1 or 1 for an ensemble whose state is resident, tail_members not -1/0/16/32
- * or above 0 for an FP64 ensemble or one outside 64..256 slots) give NLTH_EINVAL and
+ * or above 0 for an FP64 ensemble or one outside 64..256 slots, predictor outside -1..2)
+ * give NLTH_EINVAL and
  * change nothing.  Not to be called while the ensemble
  * is stepping on another thread. */
 typedef struct {
@@ -281,6 +283,11 @@ typedef struct {
                                   (default 32 there, 0 elsewhere).  The copies take 32 lanes of
                                   172 B per element and 84 B per node, allocated at first use; if
                                   that fails the path stays off for the ensemble */
+    int32_t predictor;         /* -1 keep; CG initial guess of a step from the increments of the
+                                  previous steps (their history from rest is zero): 0 the last
+                                  increment (default), 1 its linear extrapolation 2 du^{n-1} -
+                                  du^{n-2}, 2 the quadratic one 3 du^{n-1} - 3 du^{n-2} + du^{n-3}.
+                                  Changes the iteration path only, within the CG tolerance */
 } nlth_tuning;
 int nlth_ens_set_tuning(nlth_ens* ens, const nlth_tuning* t);
 int nlth_ens_set_profile(nlth_ens* ens, int32_t profile);
@@ -326,7 +333,10 @@ int nlth_response_spectra(nlth_ctx* ctx, const double* vel, int32_t n_series, in
 /* Diagnostic: one element-by-element operator application y = Op x for
  * member 0 of `prob` (Eq. 1 left-hand side with K from the given D and C from
  * the given h), on the device, in FP64 or (precision = NLTH_MIXED) the inner
- * FP32 operator with D stored as prob->inner_dtype says.  D_ip:
+ * FP32 operator with D stored as prob->inner_dtype says.  NLTH_OP_DIAG applies
+ * the 3x3 diagonal blocks of A that the block-Jacobi preconditioner inverts:
+ * from D per point in FP64, or, for NLTH_MIXED with NLTH_INNER_BF16_MEAN, those
+ * of the inner operator (one bfloat16 D per element).  D_ip:
  * [n_tets*4*21] upper triangle of D row by row per integration point (input
  * tet order); h: [n_tets] element damping (NULL = 0); x, y: [3*n_nodes]. */
 int nlth_apply_operator(nlth_ctx* ctx, const nlth_mesh* mesh, const nlth_problem* prob, int32_t which,

@@ -2,12 +2,14 @@
 
 It times candidate settings on the live ensemble, a step or two each, by
 coordinate descent:
-1. the inner iteration policy of the mixed path (tolerance-driven CG, a fixed
+1. the CG initial guess: the previous increment, or its linear or quadratic
+   extrapolation from the increments of the last steps;
+2. the inner iteration policy of the mixed path (tolerance-driven CG, a fixed
    CG count that keeps every member's lanes busy, or a fixed-degree Chebyshev
    iteration after the step's first CG solve);
-2. threads per block of the element-by-element launches;
-3. CG iterations per host convergence check (the hipGraph chunk length);
-4. co-resident blocks per CU of the cluster launches (64 and more member slots).
+3. threads per block of the element-by-element launches;
+4. CG iterations per host convergence check (the hipGraph chunk length);
+5. co-resident blocks per CU of the cluster launches (64 and more member slots).
 
 Every trial step is a complete, converged step of the simulation.  Only the
 iteration path inside the outer FP64 tolerance depends on the choice.  The
@@ -22,6 +24,7 @@ import time
 # (inner_tol, inner_maxit, inner_method): method 0 CG, 1 Chebyshev of degree inner_maxit
 INNER_POLICIES = [(0.1, 50, 0), (0.01, 60, 0), (1e-12, 12, 0), (1e-12, 16, 0), (1e-12, 20, 0),
                   (1e-12, 24, 0), (1e-12, 16, 1), (1e-12, 20, 1)]
+PREDICTORS = [0, 1, 2]  # degree of the extrapolation of the previous increments
 EBE_BLOCKS = [256, 128]
 CHECK_EVERY = [8, 16, 4]
 CLUSTER_BLOCKS = [3, 2, 4]
@@ -53,21 +56,23 @@ def trial_steps(prob, steps_per_trial: int = 1) -> int:
     one untimed step that makes the Chebyshev spectrum estimate."""
     n_pol = len(INNER_POLICIES) if prob.precision == 1 else 1
     n_cl = len(CLUSTER_BLOCKS) if 64 <= members_padded(prob.n_members) <= 256 else 1
-    stages = [n_pol, len(EBE_BLOCKS), len(CHECK_EVERY), n_cl]
+    stages = [len(PREDICTORS), n_pol, len(EBE_BLOCKS), len(CHECK_EVERY), n_cl]
     return 2 * steps_per_trial * sum(n for n in stages if n > 1) + (1 if prob.precision == 1 else 0)
 
 
 def _apply(ens, c):
     ens.set_tuning(c["ebe_block"], c["check_every"], 1, c["inner_maxit"], c["inner_tol"],
-                   cluster_blocks=c["cluster_blocks"], inner_method=c.get("inner_method", 0))
+                   cluster_blocks=c["cluster_blocks"], inner_method=c.get("inner_method", 0),
+                   predictor=c.get("predictor", 0))
 
 
 def tune(ens, mesh, prob, steps_per_trial: int = 1, cache_file: str | None = None, log=None) -> dict:
     """Tune ``ens`` in place; returns the chosen settings and the trial times.
 
     The cost of a step drifts as the wave evolves, so each stage times its
-    candidates in the order A B C ... C B A and sums the two visits: a drift
-    that is linear over the stage cancels exactly."""
+    candidates in the order A B C ... C B A and scores each by its faster
+    visit: a slow drift moves both visits of neighbours alike, and a single
+    step made slow by one member's hard convergence does not decide."""
     st = ens.stats()
     key = shape_key(mesh, prob, st["members_padded"])
     if cache_file and os.path.exists(cache_file):
@@ -85,13 +90,13 @@ def tune(ens, mesh, prob, steps_per_trial: int = 1, cache_file: str | None = Non
     def stage(cands):
         if len(cands) < 2:
             return cands[0], None
-        ms = [0.0] * len(cands)
+        ms = [float("inf")] * len(cands)
         for i in list(range(len(cands))) + list(reversed(range(len(cands)))):
             _apply(ens, cands[i])
             t0 = time.perf_counter()
             ens.step(steps_per_trial)
             dt = (time.perf_counter() - t0) / steps_per_trial * 1e3
-            ms[i] += dt / 2
+            ms[i] = min(ms[i], dt)
             trials.append(dict(cands[i], ms=dt))
             if log:
                 log(f"autotune {cands[i]} -> {dt:.1f} ms/step")
@@ -99,8 +104,8 @@ def tune(ens, mesh, prob, steps_per_trial: int = 1, cache_file: str | None = Non
         return cands[i], ms[i]
 
     cur = dict(ebe_block=EBE_BLOCKS[0], check_every=CHECK_EVERY[0], cluster_blocks=CLUSTER_BLOCKS[0],
-               inner_tol=prob.inner_tol, inner_maxit=prob.inner_maxit, inner_method=0)
-    best_ms = None
+               inner_tol=prob.inner_tol, inner_maxit=prob.inner_maxit, inner_method=0, predictor=PREDICTORS[0])
+    cur, best_ms = stage([dict(cur, predictor=k) for k in PREDICTORS])
     if prob.precision == 1:
         # the first Chebyshev step also estimates the top of the spectrum (a
         # cost shared by the next 32 steps): make it here, untimed

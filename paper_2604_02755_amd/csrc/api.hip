@@ -664,7 +664,7 @@ int64_t ensemble_bytes(const Mesh& m, const Problem& p, int MB, bool paged)
 {
     const int64_t ndof = 3L * m.nn;
     int64_t v = ndof * MB * 8;
-    int64_t bytes = 10 * v;                                  // u v a q du b r z p Ap
+    int64_t bytes = 12 * v;                                  // u v a q du du2 du3 b r z p Ap
     bytes += 2 * (int64_t)m.nn * 6 * MB * 8 + (int64_t)m.nn * 6 * MB * 4;  // diag, pinv, pinv32
     if (p.precision == NLTH_MIXED) {
         bytes += 5 * ndof * MB * 4;
@@ -787,7 +787,7 @@ void Ens::create(Ctx* c, const Mesh* m, const Problem& prob, int member_pad)
     vI_cur.alloc(bg, 3L * MB * 8);
 
     const size_t vb = (size_t)ndof * MB * 8;
-    for (DevBuf* bb : {&u, &v, &a, &q, &du, &b, &r, &z, &p, &Ap}) {
+    for (DevBuf* bb : {&u, &v, &a, &q, &du, &du2, &du3, &b, &r, &z, &p, &Ap}) {
         bb->alloc(bg, vb);
         launch_fill(s, bb->as<double>(), 0.0, (long)ndof * MB);
     }
@@ -1050,13 +1050,23 @@ void Ens::build_rhs()
         vI_cur.as<double>(), nullptr);
 }
 
+// Block-Jacobi diagonal: from D per point (FP64), or, for the mixed path with
+// one D per element in the inner operator, the diagonal blocks of that inner
+// operator itself (closed-form integrals, a fraction of the bytes); the outer
+// FP64 iteration of the mixed path does not use the diagonal.
 void Ens::build_diag()
 {
     const DevMesh dm = mesh->dev();
+    const bool mean = P.precision == NLTH_MIXED && d16_mean;
     launch_fill(s, diag.as<double>(), 0.0, (long)mesh->nn * 6 * MB);
-    for (int c = 0; c < mesh->ncolor; ++c)
-        launch_diag(s, dm, MB, nm, mesh->color_off[c], mesh->color_off[c + 1], D64.as<double>(), h.as<double>(),
-                    mat.as<double>(), P.nl, sc, diag.as<double>());
+    for (int c = 0; c < mesh->ncolor; ++c) {
+        if (mean)
+            launch_diag_mean(s, dm, MB, nm, mesh->color_off[c], mesh->color_off[c + 1], D16.as<uint32_t>(),
+                             h.as<double>(), mat.as<double>(), sc, diag.as<double>());
+        else
+            launch_diag(s, dm, MB, nm, mesh->color_off[c], mesh->color_off[c + 1], D64.as<double>(), h.as<double>(),
+                        mat.as<double>(), P.nl, sc, diag.as<double>());
+    }
     launch_diag_dashpot(s, dm, MB, nm, mat.as<double>(), P.nl, 2.0 / P.dt, diag.as<double>());
     launch_invert_diag(s, mesh->nn, MB, nm, diag.as<double>(), pinv.as<double>(),
                        P.precision == NLTH_MIXED ? pinv32.as<float>() : nullptr);
@@ -1536,6 +1546,9 @@ void Ens::one_step()
         cheb_est_age = 0;
     }
     if (cheb_est_age >= 0) ++cheb_est_age;
+    // CG initial guess: the last increment, or its extrapolation in time
+    launch_predict(s, ndof, MB, nm, predictor, du.as<double>(), du2.as<double>(), du3.as<double>(),
+                   stepping.as<int>());
     if (P.precision == NLTH_FP64) solve_pcg();
     else solve_fcg();
     tstart(t0);
@@ -1822,6 +1835,7 @@ int nlth_ens_set_tuning(nlth_ens* ens, const nlth_tuning* t)
         throw Error{NLTH_EINVAL, "tail_members needs a mixed-precision ensemble of 64..256 member slots with the "
                                  "element-mean inner D"};
     if (t->zero_copy == 1 && !ens->paged) throw Error{NLTH_EINVAL, "zero_copy needs an ensemble whose law state is paged"};
+    if (t->predictor < -1 || t->predictor > 2) throw Error{NLTH_EINVAL, "predictor must be -1, 0, 1 or 2"};
     if ((t->inner_method == 1 || (t->inner_method == -1 && ens->inner_method == 1)) &&
         (t->inner_maxit ? t->inner_maxit : ens->P.inner_maxit) > kChebMax)
         throw Error{NLTH_EINVAL, "the Chebyshev degree (inner_maxit) must be at most 64"};
@@ -1836,6 +1850,7 @@ int nlth_ens_set_tuning(nlth_ens* ens, const nlth_tuning* t)
     if (t->inner_method >= 0) ens->inner_method = t->inner_method;
     if (t->zero_copy >= 0) ens->zero_copy = t->zero_copy != 0;
     if (t->tail_members >= 0) ens->tail_max = t->tail_members;
+    if (t->predictor >= 0) ens->predictor = t->predictor;
     ens->tail_g = 0;
     // captured chunks hold the old launch shapes
     if (ens->g_inner) (void)hipGraphExecDestroy(ens->g_inner);
@@ -1963,8 +1978,9 @@ int nlth_apply_operator(nlth_ctx* ctx, const nlth_mesh* mesh, const nlth_problem
     API_BEGIN(ctx)
     if (!ctx || !mesh || !prob || !D_ip || !x || !y) throw Error{NLTH_EINVAL, "NULL argument"};
     if (ctx->host_only) throw Error{NLTH_EDEVICE, "host-only context"};
-    if (which < NLTH_OP_A || which > NLTH_OP_M) throw Error{NLTH_EINVAL, "which must be NLTH_OP_A/K/M"};
-    if (precision == NLTH_MIXED && which != NLTH_OP_A) throw Error{NLTH_EINVAL, "FP32 apply supports NLTH_OP_A"};
+    if (which < NLTH_OP_A || which > NLTH_OP_DIAG) throw Error{NLTH_EINVAL, "which must be NLTH_OP_A/K/M/DIAG"};
+    if (precision == NLTH_MIXED && which != NLTH_OP_A && which != NLTH_OP_DIAG)
+        throw Error{NLTH_EINVAL, "FP32 apply supports NLTH_OP_A and NLTH_OP_DIAG"};
     std::lock_guard<std::mutex> g(ctx->mu);
     NLTH_HIP(hipSetDevice(ctx->device));
     Problem P;
@@ -2041,7 +2057,20 @@ int nlth_apply_operator(nlth_ctx* ctx, const nlth_mesh* mesh, const nlth_problem
     x = xs.data();
     double* y_user = y;
     y = ys.data();
-    if (precision == NLTH_FP64) {
+    if (which == NLTH_OP_DIAG) {
+        // the block-Jacobi preconditioner's 3x3 diagonal blocks applied to x
+        e->build_diag();
+        std::vector<double> dg((size_t)nn * 6);
+        NLTH_HIP(hipStreamSynchronize(s));
+        NLTH_HIP(hipMemcpy(dg.data(), e->diag.p, dg.size() * 8, hipMemcpyDeviceToHost));
+        for (int i = 0; i < nn; ++i) {
+            const double* b = &dg[(size_t)i * 6];  // 00 01 02 11 12 22
+            const double* xv = x + 3L * i;
+            y[3L * i] = b[0] * xv[0] + b[1] * xv[1] + b[2] * xv[2];
+            y[3L * i + 1] = b[1] * xv[0] + b[3] * xv[1] + b[4] * xv[2];
+            y[3L * i + 2] = b[2] * xv[0] + b[4] * xv[1] + b[5] * xv[2];
+        }
+    } else if (precision == NLTH_FP64) {
         NLTH_HIP(hipMemcpy(e->p.p, x, n * 8, hipMemcpyHostToDevice));
         launch_fill(s, e->Ap.as<double>(), 0.0, n);
         e->ebe((OpMode)which, e->p.as<double>(), nullptr, e->Ap.as<double>(), e->stepping.as<int>(), nullptr, 0.0,

@@ -1309,6 +1309,97 @@ __global__ __launch_bounds__(256) void k_diag(DevMesh M, int MB, int nm, int e0,
     }
 }
 
+// Diagonal blocks of the inner operator (one D per element, the bfloat16
+// element mean): with D constant over the element the stiffness block of
+// node n is C : int grad N_n grad N_n^T dV, and that integral has a closed
+// form in the barycentric gradients g (int L_a^2 = V/10, int L_a L_b = V/20,
+// int L_a = V/4): corner a 0.6 V g_a g_a^T; edge (a, b)
+// 1.6 V (g_a g_a^T + g_b g_b^T) + 0.8 V (g_a g_b^T + g_b g_a^T).  One lane
+// per element-member of a colour (the colour's elements share no node).
+__global__ __launch_bounds__(256) void k_diag_mean(DevMesh M, int MB, int nm, int e0, int e1,
+                                                  const uint32_t* __restrict__ D16, const double* __restrict__ h,
+                                                  const double* __restrict__ mat, StepConst sc,
+                                                  double* __restrict__ diag)
+{
+    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const int m = (int)(t % MB);
+    long r = t / MB;
+    if (MB >= 64) r = __builtin_amdgcn_readfirstlane((int)r);
+    const long pos = e0 + r;
+    if (pos >= e1 || m >= nm) return;
+    const long e = MB >= 64 ? (long)__builtin_amdgcn_readfirstlane(M.celem[pos]) : (long)M.celem[pos];
+    const long ne = M.ne;
+    double gL[4][3];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) gL[k / 3][k % 3] = M.geo64[k * ne + e];
+    const double vol = M.geo64[12 * ne + e];
+    const int l = M.layer[e];
+    const double rho = matv(mat, l, MAT_RHO, MB, m);
+    double he = 0.0;
+    if (sc.damping_mode == 0 && h) he = h[e * MB + m];
+    else if (sc.damping_mode == 1) he = sc.h0;
+    const double dt = sc.dt;
+    const double sm = rho * vol * (4.0 / (dt * dt) + 2.0 * sc.ahat * he / dt);
+    const double sk = (1.0 + 2.0 * sc.bhat * he / dt) * vol;
+    constexpr int PQ[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {1, 2}, {2, 0}};
+    constexpr int CD[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
+    constexpr int E[6][2] = {{0, 1}, {1, 2}, {2, 0}, {0, 3}, {1, 3}, {2, 3}};
+    const int EB = MB >= 64 ? 1 : 64 / MB;
+    double C[6][6];
+    {
+        double d[22];
+#pragma unroll
+        for (int q = 0; q < 11; ++q) {
+            const uint32_t wv = D16[d16m_index(e, q, MB, EB, m)];
+            d[2 * q] = (double)bf2f(wv & 0xFFFFu);
+            d[2 * q + 1] = (double)bf2f(wv >> 16);
+        }
+#pragma unroll
+        for (int cd = 0; cd < 6; ++cd)
+#pragma unroll
+            for (int pq = 0; pq < 6; ++pq) {
+                const int c = CD[cd][0], dd = CD[cd][1], p = PQ[pq][0], q = PQ[pq][1];
+                double v = d[sym6(voigt_of(c, p), voigt_of(dd, q))];
+                if (p != q) v += d[sym6(voigt_of(c, q), voigt_of(dd, p))];
+                C[cd][pq] = v;
+            }
+    }
+#pragma unroll
+    for (int n = 0; n < 10; ++n) {
+        double G[6];  // int d_p N_n d_q N_n dV / V in the PQ order
+        if (n < 4) {
+#pragma unroll
+            for (int pq = 0; pq < 6; ++pq) G[pq] = 0.6 * gL[n][PQ[pq][0]] * gL[n][PQ[pq][1]];
+        } else {
+            const int a = E[n - 4][0], b = E[n - 4][1];
+#pragma unroll
+            for (int pq = 0; pq < 6; ++pq) {
+                const int p = PQ[pq][0], q = PQ[pq][1];
+                G[pq] = 1.6 * (gL[a][p] * gL[a][q] + gL[b][p] * gL[b][q]) +
+                        0.8 * (gL[a][p] * gL[b][q] + gL[b][p] * gL[a][q]);
+            }
+        }
+        const long node = M.conn[n * ne + e];
+        const double md = sm * mass_ref(n, n);
+        double* dg = diag + node * 6 * MB;
+#pragma unroll
+        for (int cd = 0; cd < 6; ++cd) {
+            double a = 0.0;
+#pragma unroll
+            for (int pq = 0; pq < 6; ++pq) a += G[pq] * C[cd][pq];
+            double& o = *reinterpret_cast<double*>(reinterpret_cast<char*>(dg) + (uint32_t)(cd * MB + m) * 8u);
+            o += sk * a + ((cd == 0 || cd == 3 || cd == 5) ? md : 0.0);
+        }
+    }
+}
+
+void launch_diag_mean(hipStream_t s, const DevMesh& M, int MB, int nm, int e0, int e1, const uint32_t* D16,
+                      const double* h, const double* mat, StepConst sc, double* diag)
+{
+    const long n = (long)(e1 - e0) * MB;
+    if (n > 0) hipLaunchKernelGGL(k_diag_mean, dim3(nblocks(n)), dim3(256), 0, s, M, MB, nm, e0, e1, D16, h, mat, sc, diag);
+}
+
 void launch_diag(hipStream_t s, const DevMesh& M, int MB, int nm, int e0, int e1, const double* D, const double* h,
                  const double* mat, int, StepConst sc, double* diag)
 {
@@ -1760,6 +1851,32 @@ void launch_newmark(hipStream_t s, long n, int MB, int nm, const double* du, dou
 {
     long N = n * MB;
     hipLaunchKernelGGL(k_newmark, dim3(nblocks(N)), dim3(256), 0, s, N, MB, nm, du, u, v, a, dt, stepping);
+}
+
+// Initial guess of the step's CG from the increments of the previous steps
+// (du holds du^{n-1}, d2 du^{n-2}, d3 du^{n-3}; zero before a member's first
+// steps, which is its true history from rest), extrapolated by a polynomial
+// of degree `order` in time: 0 keeps du^{n-1}, 1 gives 2 du^{n-1} - du^{n-2},
+// 2 gives 3 du^{n-1} - 3 du^{n-2} + du^{n-3}.  The history shifts every step
+// whatever the order.
+__global__ void k_predict(long n, int MB, int nm, int order, double* __restrict__ du, double* __restrict__ d2,
+                          double* __restrict__ d3, const int* __restrict__ stepping)
+{
+    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const int m = (int)(i % MB);
+    if (i >= n || m >= nm || !stepping[m]) return;
+    const double a = du[i], b = d2[i], c = d3[i];
+    d3[i] = b;
+    d2[i] = a;
+    if (order == 1) du[i] = 2.0 * a - b;
+    else if (order == 2) du[i] = 3.0 * (a - b) + c;
+}
+
+void launch_predict(hipStream_t s, long n, int MB, int nm, int order, double* du, double* d2, double* d3,
+                    const int* stepping)
+{
+    const long N = n * MB;
+    hipLaunchKernelGGL(k_predict, dim3(nblocks(N)), dim3(256), 0, s, N, MB, nm, order, du, d2, d3, stepping);
 }
 
 __global__ void k_receivers(int nrecv, const int* __restrict__ recv, int MB, int nm, const double* __restrict__ v,

@@ -106,6 +106,9 @@ void launch_dashpot(hipStream_t s, const DevMesh& M, int MB, int nm, const doubl
 // diagonal 3x3 blocks of A (sym, 6 entries per node) over elements [e0, e1)
 void launch_diag(hipStream_t s, const DevMesh& M, int MB, int nm, int e0, int e1, const double* D,
                  const double* h, const double* mat, int n_layers, StepConst sc, double* diag);
+// the same from the bfloat16 element-mean D of the inner operator (closed-form integrals)
+void launch_diag_mean(hipStream_t s, const DevMesh& M, int MB, int nm, int e0, int e1, const uint32_t* D16,
+                      const double* h, const double* mat, StepConst sc, double* diag);
 void launch_diag_dashpot(hipStream_t s, const DevMesh& M, int MB, int nm, const double* mat, int n_layers,
                          double coef, double* diag);
 void launch_invert_diag(hipStream_t s, int nn, int MB, int nm, const double* diag, double* pinv,
@@ -262,6 +265,9 @@ void launch_gather_cheb(hipStream_t s, const DevMesh& M, int MB, int nm, int k, 
 // Newmark state updates (Section 2.1) and receivers
 void launch_newmark(hipStream_t s, long n, int MB, int nm, const double* du, double* u, double* v,
                     double* a, double dt, const int* stepping);
+// CG initial guess extrapolated from the previous increments (order 0..2), history shifted
+void launch_predict(hipStream_t s, long n, int MB, int nm, int order, double* du, double* d2, double* d3,
+                    const int* stepping);
 void launch_receivers(hipStream_t s, int nrecv, const int* recv, int MB, int nm, const double* v,
                       double* vel_hist, const int* member_step, int n_steps_max, double* vmax,
                       const int* stepping);

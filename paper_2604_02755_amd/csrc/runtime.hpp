@@ -99,6 +99,8 @@ struct Ens {
     // device state
     DevBuf mat, dirs, w, nonlinear, acc, vI_all, vI_cur;
     DevBuf u, v, a, q, du, b, r, z, p, Ap, diag, pinv, pinv32;
+    DevBuf du2, du3;                    // increments of the two steps before the last (CG initial guess)
+    int predictor = 0;                  // degree of the extrapolation of the increments giving x0 (0..2)
     DevBuf ir, iz, ip, iw, iAp;
     DevBuf lz, chebc, cheb_bounds, qb;  // inner CG coefficients, Chebyshev table and bounds, dashpot rows
     int inner_method = 0;               // 0: inner CG; 1: Chebyshev after one inner CG per step

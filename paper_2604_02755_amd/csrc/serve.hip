@@ -125,7 +125,7 @@ void Ens::reset_member(int m)
                             (size_t)ns_steps * 3 * 8, hipMemcpyHostToDevice, s));
     launch_incident_velocity(s, MB, 1, ns_steps, acc.as<double>() + (size_t)m * ns_steps * 3,
                              vI_all.as<double>() + (size_t)m * ns_steps * 3, P.dt);
-    for (DevBuf* bb : {&u, &v, &a, &q, &du}) launch_zero_member(s, bb->as<double>(), ndof, MB, m);
+    for (DevBuf* bb : {&u, &v, &a, &q, &du, &du2, &du3}) launch_zero_member(s, bb->as<double>(), ndof, MB, m);
     launch_fill(s, vmax.as<double>() + (size_t)m * std::max(1, mesh->nrecv), 0.0, std::max(1, mesh->nrecv));
     launch_theta_reset_member(s, theta.p, ne_pad, P.ns, MB, m);
     launch_law_init(s, dm, MB, nm, mat.as<double>(), P.nl, P.ns, dirs.as<double>(), w.as<double>(), D64.as<double>(),

@@ -33,7 +33,7 @@ NLTH_FP64, NLTH_MIXED = 0, 1
 NLTH_INNER_BF16, NLTH_INNER_FP32, NLTH_INNER_BF16_MEAN = 0, 1, 2
 INNER_CG, INNER_CHEBYSHEV = 0, 1  # nlth_tuning.inner_method
 NLTH_SPEC_VELOCITY, NLTH_SPEC_PSEUDO_VELOCITY = 0, 1
-NLTH_OP_A, NLTH_OP_K, NLTH_OP_M = 0, 1, 2
+NLTH_OP_A, NLTH_OP_K, NLTH_OP_M, NLTH_OP_DIAG = 0, 1, 2, 3
 NLTH_DEVICE_NONE = -1
 
 _dp = C.POINTER(C.c_double)
@@ -72,7 +72,7 @@ class nlth_tuning(C.Structure):
     _fields_ = [("ebe_block", C.c_int32), ("check_every", C.c_int32), ("use_graph", C.c_int32),
                 ("inner_maxit", C.c_int32), ("inner_tol", C.c_double), ("scatter", C.c_int32),
                 ("cluster_blocks", C.c_int32), ("inner_method", C.c_int32), ("zero_copy", C.c_int32),
-                ("tail_members", C.c_int32)]
+                ("tail_members", C.c_int32), ("predictor", C.c_int32)]
 
 
 class nlth_result(C.Structure):
@@ -363,11 +363,12 @@ class Ensemble:
         lib().nlth_ens_reset_stats(self.h)
 
     def set_tuning(self, ebe_block=0, check_every=0, use_graph=-1, inner_maxit=0, inner_tol=0.0, scatter=-1,
-                   cluster_blocks=0, inner_method=-1, zero_copy=-1, tail_members=-1):
+                   cluster_blocks=0, inner_method=-1, zero_copy=-1, tail_members=-1, predictor=-1):
         """nlth_ens_set_tuning: the defaults (0, or -1 where 0 is a setting) keep
         the current value; include/nlth.h documents each field."""
         t = nlth_tuning(int(ebe_block), int(check_every), int(use_graph), int(inner_maxit), float(inner_tol),
-                        int(scatter), int(cluster_blocks), int(inner_method), int(zero_copy), int(tail_members))
+                        int(scatter), int(cluster_blocks), int(inner_method), int(zero_copy), int(tail_members),
+                        int(predictor))
         return _check(lib().nlth_ens_set_tuning(self.h, C.byref(t)), self.ctx)
 
     def close(self):

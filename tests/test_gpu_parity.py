@@ -532,3 +532,81 @@ def test_benchmark_path_at_throughput_tolerance(gpu_ctx, oracle_lib):
         err = oracle_lib.rel_l2(om["vel"][m], ref["vel"])
         say("  member", m, "vs oracle", err)
         assert err < 1e-6
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_extrapolated_initial_guess_matches_oracle(gpu_ctx, oracle_lib, precision):
+    """The CG initial guess extrapolated from the previous increments (linear,
+    quadratic) changes the iteration path only: at tolerance 1e-12 the run
+    matches the oracle (whose initial guess is the last increment), and at
+    1e-8 it needs fewer iterations than the last increment alone."""
+    mesh, prob = _small_problem(precision=precision, n_members=2, n_steps=60, dims=(6, 5, 3), ns=12, tol=1e-12)
+    mh = gpu_ctx.mesh(mesh)
+
+    def run(p, order):
+        ens = gpu_ctx.ensemble(mh, mesh, p)
+        try:
+            ens.set_tuning(predictor=order)
+            ens.step(p.n_steps)
+            return ens.read()
+        finally:
+            ens.close()
+
+    refs = [oracle_lib.run(mesh, prob, member=m) for m in range(2)]
+    for order in (1, 2):
+        out = run(prob, order)
+        for m in range(2):
+            err = oracle_lib.rel_l2(out["vel"][m], refs[m]["vel"])
+            say("predictor", order, "precision", precision, "member", m, "rel L2 vs oracle", err)
+            assert out["status"][m] == 0 and err < 1e-9
+    mesh, p8 = _small_problem(precision=precision, n_members=2, n_steps=60, dims=(6, 5, 3), ns=12, tol=1e-8)
+    its = {k: run(p8, k)["iters"][:, 10:, 0].sum() for k in (0, 1, 2)}
+    say("  outer iterations at tol 1e-8 over steps 11-60 by predictor order", its)
+    assert its[1] < its[0] and its[2] < its[0]
+    with pytest.raises(Exception):
+        ens = gpu_ctx.ensemble(mh, mesh, p8)
+        try:
+            ens.set_tuning(predictor=3)
+        finally:
+            ens.close()
+
+
+def test_block_jacobi_diagonal_matches_oracle(gpu_ctx, oracle_lib):
+    """The 3x3 diagonal blocks that the block-Jacobi preconditioner inverts
+    (step a2): from D per point in FP64, and, for the mixed path with one
+    bfloat16 D per element, the inner operator's blocks from closed-form
+    integrals, against the diagonal blocks of the oracle's assembled A (its
+    CRS operator applied to unit vectors).  With D constant per element and
+    exact in bfloat16 the two forms agree to FP64 rounding."""
+    mesh, prob = I.config(0, n_steps=1, mesh_dims=(3, 2, 2))
+    rng = np.random.default_rng(21)
+    D = _rand_D(rng, mesh.n_tets)
+    h = rng.uniform(0, 0.2, mesh.n_tets)
+    x = rng.normal(size=mesh.n_dof)
+    mh = gpu_ctx.mesh(mesh)
+
+    def oracle_blocks_times_x(Dx):
+        B = np.zeros((mesh.n_nodes, 3, 3))
+        e = np.zeros(mesh.n_dof)
+        for i in range(mesh.n_dof):
+            e[i] = 1.0
+            col = oracle_lib.apply_operator(mesh, prob, 0, Dx, h, e)
+            e[i] = 0.0
+            node, c = divmod(i, 3)
+            B[node, :, c] = col[3 * node:3 * node + 3]
+        return np.einsum("nij,nj->ni", B, x.reshape(-1, 3)).ravel()
+
+    y_ref = oracle_blocks_times_x(D)
+    y = gpu_ctx.apply_operator(mh, prob, 3, 0, D, h, x)
+    err = np.linalg.norm(y - y_ref) / np.linalg.norm(y_ref)
+    say("block diagonal, FP64 per-point D, rel err vs oracle", err)
+    assert err < 1e-13
+    Dc = D.mean(axis=1, keepdims=True).astype(np.float32).view(np.uint32) & np.uint32(0xFFFF0000)
+    Dc = np.repeat(Dc.view(np.float32).astype(np.float64), 4, axis=1)
+    prob.inner_dtype = 2
+    y_ref = oracle_blocks_times_x(Dc)
+    y = gpu_ctx.apply_operator(mh, prob, 3, 1, Dc, h, x)
+    err = np.linalg.norm(y - y_ref) / np.linalg.norm(y_ref)
+    say("block diagonal, inner operator (bfloat16 element-mean D, closed form), rel err vs oracle", err)
+    assert err < 1e-13
+    prob.inner_dtype = 0

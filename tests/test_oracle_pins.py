@@ -559,3 +559,21 @@ def test_response_spectra_closed_forms(oracle_lib):
     assert abs(stiff / np.abs(a).max() - 1) < 2e-2
     assert abs(soft / np.abs(v).max() - 1) < 1e-3
     assert np.all(oracle_lib.response_spectra(np.zeros((2, 50)), 1e-3, [0.1, 1.0], h) == 0.0)
+
+
+def test_extrapolated_initial_guess_is_closer(oracle_lib):
+    """The study behind the library's initial-guess option (the paper does not
+    fix the CG initial guess): on the oracle's increments of a benchmark-like
+    member (config-2 layers and wave, 8x8x8 cubes, 1 ms steps), once the wave
+    is in, the linear extrapolation 2 du^{n-1} - du^{n-2} is an order of
+    magnitude closer to du^n than du^{n-1}, and the quadratic one
+    3 du^{n-1} - 3 du^{n-2} + du^{n-3} another order closer."""
+    mesh, prob = I.config(2, n_members=1, mesh_dims=(8, 8, 8), n_steps=120, cg_tol=1e-12)
+    du = oracle_lib.run(mesh, prob, want_du=True)["du"]
+    err = []
+    for n in range(60, 120):
+        nd = np.linalg.norm(du[n])
+        err.append([np.linalg.norm(du[n] - g) / nd for g in
+                    (du[n - 1], 2 * du[n - 1] - du[n - 2], 3 * du[n - 1] - 3 * du[n - 2] + du[n - 3])])
+    e0, e1, e2 = np.median(np.array(err), axis=0)
+    assert e1 < e0 / 10 and e2 < e1 / 5, (e0, e1, e2)
