@@ -421,6 +421,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=10, help="steps of the CPU oracle sample (all host threads)")
     ap.add_argument("--cpu-single-steps", type=int, default=1, help="steps of the one-thread oracle sample")
     ap.add_argument("--acc-steps", type=int, default=150, help="--config 1: steps of the accuracy comparison")
+    ap.add_argument("--accuracy-ref-tol", type=float, default=0.0,
+                    help="also run plain FP64 at this CG tolerance and report both paths' error against it")
     ap.add_argument("--window-start", type=int, default=130,
                     help="steps before the timed window (warmup and autotuning included, untimed steps added): "
                          "the incident wave needs about 100 steps to fill the 32 m of soil, so the window and the "
@@ -568,6 +570,24 @@ def main():
         fp64["rel_err_sample"] = (f"all {args.members} members of the headline run, steps 1-{n_total}, receiver "
                                   f"velocity, relative L2 per member")
         log(f"mixed vs fp64 over {n_total} steps, {args.members} members: max rel err {max(errs):.2e}")
+        if args.accuracy_ref_tol > 0:
+            # both paths against a plain FP64 run at a much tighter tolerance
+            pref = I.config(2, n_members=args.members, mesh_dims=dims, precision=I.PRECISION_FP64,
+                            cg_tol=args.accuracy_ref_tol)[1]
+            pref.input_acc = np.ascontiguousarray(pref.input_acc[:, :n_total])
+            pref.n_steps = n_total
+            outr = run_gpu(mesh, pref, args.warmup, args.steps, False, n_tune,
+                           tuned=tuned or {"ebe_block": 256, "check_every": 8}, pre_steps=args.pre_steps)[3]
+
+            def rel(o):
+                return [float(np.linalg.norm(o["vel"][m, :n_total] - outr["vel"][m, :n_total]) /
+                              max(np.linalg.norm(outr["vel"][m, :n_total]), 1e-300)) for m in range(args.members)]
+            em, ef = rel(out_mixed), rel(out64)
+            fp64["vs_reference"] = {"reference": f"plain FP64 at CG tolerance {args.accuracy_ref_tol:g}, same steps",
+                                    "mixed_max": max(em), "mixed_median": float(np.median(em)),
+                                    "fp64_max": max(ef), "fp64_median": float(np.median(ef))}
+            log(f"against FP64 at tol {args.accuracy_ref_tol:g}: mixed max {max(em):.2e} median "
+                f"{np.median(em):.2e}; FP64 at 1e-8 max {max(ef):.2e} median {np.median(ef):.2e}")
 
     # CPU oracle on a bounded sample of the same workload: steps of member 0,
     # setup (CRS pattern, mass, faces) excluded, on the host cores the box

@@ -1685,7 +1685,17 @@ void launch_zero_member(hipStream_t s, double* p, long rows, int MB, int m)
 // from du, then every spring's Masing/RO update and tangent,
 // D = Kb m m^T + sum c_k G_t n n^T at the point, and the element damping h
 // (the mean over the four points, summed across the four lanes).
-__global__ __launch_bounds__(256) void k_law(DevMesh M, int MB, int nm, int e0, int ec, long ecp,
+// WAVE_ELEM: a wavefront covers one element (MB >= 16): its geometry and
+// connectivity are then wave-uniform and live in scalar registers.
+// LDS_NS > 0 (at most that many springs): each lane parks its springs' c_k G_k
+// in LDS during the spring loop and forms D after it, so the 21 FP64
+// accumulators of D are not live across the skeleton inversions: 139
+// registers instead of 178 (3 wavefronts per SIMD instead of 2), and with the
+// launch bound of 4 wavefronts per SIMD 128 registers and 36 B of spills
+// (4 % faster again); 0: D accumulated in registers.
+constexpr int kLawLdsSprings = 16;
+template <bool WAVE_ELEM, int LDS_NS>
+__global__ __launch_bounds__(256, LDS_NS > 0 ? 4 : 1) void k_law(DevMesh M, int MB, int nm, int e0, int ec, long ecp,
                                             const double* __restrict__ mat, const int* __restrict__ nonlinear,
                                             int ns, const double* __restrict__ dirs,
                                             const double* __restrict__ w, const double* __restrict__ du,
@@ -1697,7 +1707,8 @@ __global__ __launch_bounds__(256) void k_law(DevMesh M, int MB, int nm, int e0, 
     const int j = (int)(t & 3);
     const long q = t >> 2;
     const int m = (int)(q % MB);
-    const long el = q / MB;
+    long el = q / MB;
+    if (WAVE_ELEM) el = __builtin_amdgcn_readfirstlane((int)el);
     if (el >= ec || m >= nm) return;
     if (stepping && !stepping[m]) return;
     const long e = e0 + el;
@@ -1711,22 +1722,38 @@ __global__ __launch_bounds__(256) void k_law(DevMesh M, int MB, int nm, int e0, 
     P.hmax = matv(mat, l, MAT_HMAX, MB, m);
     P.beta = matv(mat, l, MAT_BETA, MB, m);
     const double Kb = matv(mat, l, MAT_KB, MB, m);
-    // strain increment at point j
-    double ej[6];
+    // strain increment at point j, node by node (gradient of N_n at the point
+    // times the node's increment)
+    double ej[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     {
         double gL[4][3];
+#pragma unroll
         for (int k = 0; k < 12; ++k) gL[k / 3][k % 3] = M.geo64[k * ne + e];
-        double u[10][3];
+        double L[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) L[i] = (i == j) ? QA_ : QB_;
+        constexpr int E[6][2] = {{0, 1}, {1, 2}, {2, 0}, {0, 3}, {1, 3}, {2, 3}};
+#pragma unroll
         for (int n = 0; n < 10; ++n) {
             const long node = M.conn[n * ne + e];
-            for (int c = 0; c < 3; ++c) u[n][c] = du[(node * 3 + c) * MB + m];
+            const double* un = du + node * 3 * MB + m;
+            const double u0 = un[0], u1 = un[MB], u2 = un[2 * MB];
+            double g[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                g[a] = n < 4 ? (4.0 * L[n] - 1.0) * gL[n][a]
+                             : 4.0 * (L[E[n - 4][0]] * gL[E[n - 4][1]][a] + L[E[n - 4][1]] * gL[E[n - 4][0]][a]);
+            ej[0] += g[0] * u0;
+            ej[1] += g[1] * u1;
+            ej[2] += g[2] * u2;
+            ej[3] += g[1] * u0 + g[0] * u1;
+            ej[4] += g[2] * u1 + g[1] * u2;
+            ej[5] += g[0] * u2 + g[2] * u0;
         }
-        double G[10][3];
-        shape_grads<double>(j, gL, G);
-        strain<double>(G, u, ej);
     }
     ThetaView th = theta_view(theta, ecp, ns, MB);
     const long fn = th.field_n;
+    __shared__ double cgs[LDS_NS > 0 ? LDS_NS * 256 : 1];
     double d[21];
 #pragma unroll
     for (int k = 0; k < 21; ++k) d[k] = 0;
@@ -1791,10 +1818,25 @@ __global__ __launch_bounds__(256) void k_law(DevMesh M, int MB, int nm, int e0, 
         }
         hs += hk;
         const double c = w[sp] * Gt;
+        if (LDS_NS > 0) {
+            cgs[sp * 256 + threadIdx.x] = c;
+        } else {
 #pragma unroll
-        for (int r = 0; r < 6; ++r)
+            for (int r = 0; r < 6; ++r)
 #pragma unroll
-            for (int qq = r; qq < 6; ++qq) d[sym6(r, qq)] += c * n[r] * n[qq];
+                for (int qq = r; qq < 6; ++qq) d[sym6(r, qq)] += c * n[r] * n[qq];
+        }
+    }
+    if (LDS_NS > 0) {
+#pragma unroll 1
+        for (int sp = 0; sp < ns; ++sp) {
+            const double* n = dirs + 6 * sp;
+            const double c = cgs[sp * 256 + threadIdx.x];
+#pragma unroll
+            for (int r = 0; r < 6; ++r)
+#pragma unroll
+                for (int qq = r; qq < 6; ++qq) d[sym6(r, qq)] += c * n[r] * n[qq];
+        }
     }
 #pragma unroll
     for (int r = 0; r < 3; ++r)
@@ -1825,9 +1867,23 @@ void launch_law(hipStream_t s, const DevMesh& M, int MB, int nm, int e0, int ec,
                 void* theta, double* D, float* D32, uint32_t* D16, double* h, const int* stepping, bool d16_mean)
 {
     long n = (long)ec * MB * 4;
-    if (n > 0)
-        hipLaunchKernelGGL(k_law, dim3(nblocks(n)), dim3(256), 0, s, M, MB, nm, e0, ec, ecp, mat, nonlinear, ns, dirs,
-                           w, du, theta, D, D32, D16, h, stepping, d16_mean);
+    if (n <= 0) return;
+    const dim3 g(nblocks(n)), b(256);
+    if (ns <= kLawLdsSprings) {
+        if (MB >= 16)
+            hipLaunchKernelGGL((k_law<true, kLawLdsSprings>), g, b, 0, s, M, MB, nm, e0, ec, ecp, mat, nonlinear, ns,
+                               dirs, w, du, theta, D, D32, D16, h, stepping, d16_mean);
+        else
+            hipLaunchKernelGGL((k_law<false, kLawLdsSprings>), g, b, 0, s, M, MB, nm, e0, ec, ecp, mat, nonlinear, ns,
+                               dirs, w, du, theta, D, D32, D16, h, stepping, d16_mean);
+    } else {
+        if (MB >= 16)
+            hipLaunchKernelGGL((k_law<true, 0>), g, b, 0, s, M, MB, nm, e0, ec, ecp, mat, nonlinear, ns, dirs, w, du,
+                               theta, D, D32, D16, h, stepping, d16_mean);
+        else
+            hipLaunchKernelGGL((k_law<false, 0>), g, b, 0, s, M, MB, nm, e0, ec, ecp, mat, nonlinear, ns, dirs, w, du,
+                               theta, D, D32, D16, h, stepping, d16_mean);
+    }
 }
 
 // ---------------------------------------------------------------------------
