@@ -54,13 +54,13 @@ class _Problem(C.Structure):
                 ("f_lo", C.c_double), ("f_hi", C.c_double), ("dt", C.c_double),
                 ("n_steps", C.c_int), ("input_acc", _dp), ("cg_tol", C.c_double),
                 ("cg_maxit", C.c_int), ("v0", _dp), ("apply_which", C.c_int), ("apply_D", _dp),
-                ("apply_h", _dp), ("apply_x", _dp), ("apply_y", _dp)]
+                ("apply_h", _dp), ("apply_x", _dp), ("apply_y", _dp), ("masing_depth", C.c_int)]
 
 
 class _Result(C.Structure):
     _fields_ = [("vel", _dp), ("iters", _ip), ("du_hist", _dp), ("u_final", _dp),
                 ("v_final", _dp), ("D_final", _dp), ("h_final", _dp), ("theta_final", _dp), ("vmax", _dp),
-                ("law_events", C.c_long * 3), ("setup_seconds", C.c_double), ("steps_done", C.c_int)]
+                ("law_events", C.c_long * 4), ("setup_seconds", C.c_double), ("steps_done", C.c_int)]
 
 
 def lib():
@@ -83,6 +83,11 @@ def lib():
         _lib.or_ip_law.argtypes = [_dp, _dp, C.c_int, _dp, _dp, C.c_double, C.c_double,
                                    C.c_double, C.c_double, _dp, _dp]
         _lib.or_set_threads.argtypes = [C.c_int]
+        _lib.or_spring_step_mem.restype = C.c_double
+        _lib.or_spring_step_mem.argtypes = [_dp, C.c_int, C.c_double, C.c_double, C.c_double, C.c_double, _dp,
+                                            _dp, C.POINTER(C.c_long)]
+        _lib.or_spring_words.restype = C.c_int
+        _lib.or_spring_words.argtypes = [C.c_int]
     return _lib
 
 
@@ -112,8 +117,9 @@ def run(mesh, prob, member: int = 0, alias=None, want_du: bool = False, want_sta
     ``vel``: [n_steps, n_recv, 3]; ``vmax``: [n_recv], the largest velocity
     norm over the run at each receiver; ``iters``: [n_steps]; ``law_events``:
     counts over the run of (reversals on the skeleton, reversals on a Masing
-    branch, rejoins of the skeleton); optional ``du`` [n_steps, n_dof]; ``u``,
-    ``D`` [n_tets, 4, 21], ``h`` [n_tets], ``theta`` [n_tets, 4, n_springs, 6];
+    branch, rejoins of the skeleton, inner loops closed); optional ``du``
+    [n_steps, n_dof]; ``u``, ``D`` [n_tets, 4, 21], ``h`` [n_tets], ``theta``
+    [n_tets, 4, n_springs, W] (W = 6 for the three-rule law);
     ``seconds`` wall time, of which ``setup_seconds`` before the first step.
     """
     L = lib()
@@ -144,7 +150,8 @@ def run(mesh, prob, member: int = 0, alias=None, want_du: bool = False, want_sta
                  prob.n_springs, _p(dirs), _p(w), int(prob.damping_mode), float(prob.h0),
                  float(prob.f_lo), float(prob.f_hi), float(prob.dt), ns, _p(acc),
                  float(cg_tol if cg_tol is not None else prob.cg_tol), int(prob.cg_maxit),
-                 _p(k(_f64(v0))) if v0 is not None else None, -1, None, None, None, None)
+                 _p(k(_f64(v0))) if v0 is not None else None, -1, None, None, None, None,
+                 int(getattr(prob, "masing_depth", 1) or 1))
     out = dict(vel=np.zeros((ns, rc.size, 3)), iters=np.zeros(ns, np.int32), vmax=np.zeros(rc.size))
     if want_du:
         out["du"] = np.zeros((ns, 3 * mesh.n_nodes))
@@ -153,10 +160,11 @@ def run(mesh, prob, member: int = 0, alias=None, want_du: bool = False, want_sta
         out["v"] = np.zeros(3 * mesh.n_nodes)
         out["D"] = np.zeros((mesh.n_tets, 4, 21))
         out["h"] = np.zeros(mesh.n_tets)
-        out["theta"] = np.zeros((mesh.n_tets, 4, prob.n_springs, 6))
+        out["theta"] = np.zeros((mesh.n_tets, 4, prob.n_springs,
+                                 L.or_spring_words(int(getattr(prob, "masing_depth", 1) or 1))))
     r = _Result(_p(out["vel"]), _p(out["iters"], _ip), _p(out.get("du")), _p(out.get("u")),
                 _p(out.get("v")), _p(out.get("D")), _p(out.get("h")), _p(out.get("theta")), _p(out["vmax"]),
-                (C.c_long * 3)(), 0.0, 0)
+                (C.c_long * 4)(), 0.0, 0)
     t0 = time.perf_counter()
     code = L.or_run(C.byref(m), C.byref(p), C.byref(r))
     out["seconds"] = time.perf_counter() - t0
@@ -195,8 +203,8 @@ def apply_operator(mesh, prob, which, D_ip, h, x, member: int = 0):
     y = np.zeros_like(xx)
     p = _Problem(prob.n_layers, _p(rho), _p(vs), _p(nu), _p(gr), _p(hm), _p(nl, _ip), prob.n_springs,
                  _p(dirs), _p(w), int(prob.damping_mode), float(prob.h0), float(prob.f_lo), float(prob.f_hi),
-                 float(prob.dt), 0, None, 1e-8, 1, None, int(which), _p(D), _p(hh), _p(xx), _p(y))
-    out = _Result(_p(np.zeros(1)), None, None, None, None, None, None, None, None, (C.c_long * 3)(), 0.0, 0)
+                 float(prob.dt), 0, None, 1e-8, 1, None, int(which), _p(D), _p(hh), _p(xx), _p(y), 1)
+    out = _Result(_p(np.zeros(1)), None, None, None, None, None, None, None, None, (C.c_long * 4)(), 0.0, 0)
     code = L.or_run(C.byref(m), C.byref(p), C.byref(out))
     if code != 0:
         raise OracleError(code, L.or_last_error().decode())
@@ -258,6 +266,23 @@ def spring_step(state, dgamma, G0, gref, h_max):
     Gt, hk = C.c_double(), C.c_double()
     tau = lib().or_spring_step(_p(state), float(dgamma), float(G0), float(gref), float(h_max),
                                C.byref(Gt), C.byref(hk))
+    return tau, Gt.value, hk.value
+
+
+def new_spring_mem(depth):
+    """Virgin spring state with a reversal memory of ``depth`` points."""
+    st = np.zeros(lib().or_spring_words(int(depth)))
+    st[5] = 1.0
+    return st
+
+
+def spring_step_mem(state, depth, dgamma, G0, gref, h_max, events=None):
+    """Advance one spring with a reversal memory of ``depth``; returns
+    (tau, G_t, h_k); ``events`` (4 longs) accumulates the law events."""
+    Gt, hk = C.c_double(), C.c_double()
+    ev = events if events is not None else (C.c_long * 4)()
+    tau = lib().or_spring_step_mem(_p(state), int(depth), float(dgamma), float(G0), float(gref), float(h_max),
+                                   C.byref(Gt), C.byref(hk), ev)
     return tau, Gt.value, hk.value
 
 

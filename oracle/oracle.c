@@ -316,24 +316,58 @@ static double stress_on_curve(double g, const double* st, const spring_par* p)
 
 /* state: gp (current strain), gr (reversal strain), tr (reversal stress),
  * gm (largest |strain| on the skeleton), dir (last loading sign), skel (on skeleton).
+ * With a memory of depth K > 1 (the last K reversal points: the current
+ * branch's origin and K - 1 older ones) the record goes on with the count of
+ * older points and up to K - 1 of them as (gr, tr) pairs, the most recent
+ * last: st[6] = count, st[7 + 2i], st[8 + 2i].  Depth 1 is the three-rule law
+ * (skeleton, Masing branch from the last reversal, rejoin beyond the largest
+ * strain reached).  Depth K adds the rule that closes inner loops: a branch
+ * that reaches the reversal point where the previous branch began continues
+ * on the branch before that one (the two reversal points are forgotten), so
+ * loops nested up to K - 2 deep close (depth 2 behaves as depth 1); when
+ * K - 1 older points are held the oldest is dropped, and a loop that lost
+ * its outer point ends only by the rejoin.
  * cnt (optional) counts the events of the step for the tests: [0] reversals
  * taken on the skeleton, [1] reversals taken on a Masing branch, [2] rejoins
- * of the skeleton. */
-static void spring_update(double* st, double dg, const spring_par* p, double* Gt, double* hk, long* cnt)
+ * of the skeleton, [3] inner loops closed. */
+static void spring_update(double* st, double dg, const spring_par* p, int depth, double* Gt, double* hk, long* cnt)
 {
     if (dg != 0.0) {
         double d = dg > 0.0 ? 1.0 : -1.0;
         if (st[4] != 0.0 && d != st[4]) { /* reversal: branch starts at the current point */
             if (cnt) cnt[st[5] != 0.0 ? 0 : 1]++;
-            st[2] = stress_on_curve(st[0], st, p);
+            const double trev = stress_on_curve(st[0], st, p);
+            if (depth > 1 && st[5] == 0.0) { /* keep the origin of the branch being left */
+                int k = (int)st[6];
+                if (k == depth - 1) { /* full: drop the oldest point */
+                    for (int i = 0; i + 1 < k; ++i) {
+                        st[7 + 2 * i] = st[9 + 2 * i];
+                        st[8 + 2 * i] = st[10 + 2 * i];
+                    }
+                    --k;
+                }
+                st[7 + 2 * k] = st[1];
+                st[8 + 2 * k] = st[2];
+                st[6] = k + 1;
+            }
+            st[2] = trev;
             st[1] = st[0];
             st[5] = 0.0;
         }
         st[4] = d;
         double g = st[0] + dg;
-        if (st[5] == 0.0 && d * g >= st[3]) { /* back on the skeleton */
+        if (st[5] == 0.0 && d * g >= st[3]) { /* back on the skeleton beyond every loop */
             st[5] = 1.0;
+            if (depth > 1) st[6] = 0.0;
             if (cnt) cnt[2]++;
+        }
+        /* a closed inner loop: on to the branch before the previous one */
+        while (depth > 1 && st[5] == 0.0 && st[6] >= 2.0 && d * g >= d * st[7 + 2 * ((int)st[6] - 1)]) {
+            const int k = (int)st[6];
+            st[1] = st[7 + 2 * (k - 2)];
+            st[2] = st[8 + 2 * (k - 2)];
+            st[6] = k - 2;
+            if (cnt) cnt[3]++;
         }
         if (st[5] != 0.0) st[3] = fmax(st[3], fabs(g));
         st[0] = g;
@@ -353,15 +387,26 @@ double or_spring_step(double* st, double dg, double G0, double gref, double h_ma
                       double* hk)
 {
     spring_par p = {G0, gref, h_max, or_ro_beta(h_max)};
-    spring_update(st, dg, &p, Gt, hk, NULL);
+    spring_update(st, dg, &p, 1, Gt, hk, NULL);
     return stress_on_curve(st[0], st, &p);
 }
 
+double or_spring_step_mem(double* st, int depth, double dg, double G0, double gref, double h_max, double* Gt,
+                          double* hk, long* events)
+{
+    spring_par p = {G0, gref, h_max, or_ro_beta(h_max)};
+    spring_update(st, dg, &p, depth, Gt, hk, events);
+    return stress_on_curve(st[0], st, &p);
+}
+
+int or_spring_words(int depth) { return depth > 1 ? 5 + 2 * depth : 6; }
+
 /* Multi-spring point: D = Kb m m^T + sum_k c_k G_t,k n_k n_k^T, h = mean h_k.
  * cnt (optional): law events, as for spring_update. */
-static void ip_law(const double* deps, double* state, int ns, const double* dirs, const double* w,
+static void ip_law(const double* deps, double* state, int ns, int depth, const double* dirs, const double* w,
                    double G0, double Kb, double gref, double hmax, double* D, double* hmean, long* cnt)
 {
+    const int sw = or_spring_words(depth);
     spring_par p = {G0, gref, hmax, or_ro_beta(hmax)};
     for (int i = 0; i < 36; ++i) D[i] = 0.0;
     for (int r = 0; r < 3; ++r)
@@ -373,7 +418,7 @@ static void ip_law(const double* deps, double* state, int ns, const double* dirs
         if (deps) { /* deps == NULL: the initial (virgin) tangent G0 */
             double dg = 0.0;
             for (int i = 0; i < 6; ++i) dg += n[i] * deps[i];
-            spring_update(state + 6 * k, dg, &p, &Gt, &hk, cnt);
+            spring_update(state + (long)sw * k, dg, &p, depth, &Gt, &hk, cnt);
         }
         for (int r = 0; r < 6; ++r)
             for (int c = 0; c < 6; ++c) D[6 * r + c] += w[k] * Gt * n[r] * n[c];
@@ -385,7 +430,7 @@ static void ip_law(const double* deps, double* state, int ns, const double* dirs
 void or_ip_law(const double* deps, double* state, int ns, const double* dirs, const double* w,
                double G0, double Kb, double gref, double hmax, double* D, double* hmean)
 {
-    ip_law(deps, state, ns, dirs, w, G0, Kb, gref, hmax, D, hmean, NULL);
+    ip_law(deps, state, ns, 1, dirs, w, G0, Kb, gref, hmax, D, hmean, NULL);
 }
 
 /* ------------------------------------------------------------------ */
@@ -615,7 +660,7 @@ int or_run(const or_mesh* m, const or_problem* pr, or_result* res)
     const double t_start = wall_seconds();
     res->steps_done = 0;
     res->setup_seconds = 0.0;
-    res->law_events[0] = res->law_events[1] = res->law_events[2] = 0;
+    res->law_events[0] = res->law_events[1] = res->law_events[2] = res->law_events[3] = 0;
     if (res->vmax)
         for (int r = 0; r < m->n_recv; ++r) res->vmax[r] = 0.0;
 
@@ -738,9 +783,11 @@ int or_run(const or_mesh* m, const or_problem* pr, or_result* res)
 
     /* --- state --- */
     double* D = malloc(sizeof(double) * 36 * 4 * (size_t)ne);
-    double* th = calloc((size_t)ne * 4 * ns * 6, sizeof(double));
+    const int depth = pr->masing_depth > 1 ? pr->masing_depth : 1;
+    const int sw = or_spring_words(depth);
+    double* th = calloc((size_t)ne * 4 * ns * sw, sizeof(double));
     double* he = calloc((size_t)ne, sizeof(double));
-    for (long i = 0; i < (long)ne * 4 * ns; ++i) th[6 * i + 5] = 1.0; /* start on the skeleton */
+    for (long i = 0; i < (long)ne * 4 * ns; ++i) th[sw * i + 5] = 1.0; /* start on the skeleton */
     for (long e = 0; e < ne; ++e) {
         int l = m->layer[e];
         for (int j = 0; j < 4; ++j) {
@@ -857,8 +904,8 @@ int or_run(const or_mesh* m, const or_problem* pr, or_result* res)
         }
 
         /* Multispring: D^n, theta^n, h^n from du^n (Alg. 1) */
-        long c_rs = 0, c_rb = 0, c_rj = 0;
-#pragma omp parallel for schedule(dynamic, 64) reduction(+ : c_rs, c_rb, c_rj)
+        long c_rs = 0, c_rb = 0, c_rj = 0, c_cl = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : c_rs, c_rb, c_rj, c_cl)
         for (long e = 0; e < ne; ++e) {
             int l = m->layer[e];
             if (!pr->nonlinear[l]) {
@@ -880,12 +927,13 @@ int or_run(const or_mesh* m, const or_problem* pr, or_result* res)
                     de[r] = s;
                 }
                 double hm;
-                long cnt[3] = {0, 0, 0};
-                ip_law(de, th + 6L * ns * (4 * e + j), ns, pr->dirs, pr->weights, G0[l], Kb[l],
+                long cnt[4] = {0, 0, 0, 0};
+                ip_law(de, th + (long)sw * ns * (4 * e + j), ns, depth, pr->dirs, pr->weights, G0[l], Kb[l],
                        pr->gamma_ref[l], pr->h_max[l], D + 36 * (4 * e + j), &hm, cnt);
                 c_rs += cnt[0];
                 c_rb += cnt[1];
                 c_rj += cnt[2];
+                c_cl += cnt[3];
                 hsum += hm;
             }
             he[e] = 0.25 * hsum;
@@ -893,6 +941,7 @@ int or_run(const or_mesh* m, const or_problem* pr, or_result* res)
         res->law_events[0] += c_rs;
         res->law_events[1] += c_rb;
         res->law_events[2] += c_rj;
+        res->law_events[3] += c_cl;
 
         for (int r = 0; r < m->n_recv; ++r) {
             int nd = m->alias ? m->alias[m->recv[r]] : m->recv[r];
@@ -916,7 +965,7 @@ int or_run(const or_mesh* m, const or_problem* pr, or_result* res)
                 for (int c = r; c < 6; ++c) res->D_final[21 * i + k++] = D[36 * i + 6 * r + c];
         }
     if (res->h_final) memcpy(res->h_final, he, sizeof(double) * ne);
-    if (res->theta_final) memcpy(res->theta_final, th, sizeof(double) * 6 * (size_t)ne * 4 * ns);
+    if (res->theta_final) memcpy(res->theta_final, th, sizeof(double) * sw * (size_t)ne * 4 * ns);
 
     free(KeB); free(MeB);
     free(u); free(v); free(acc); free(q); free(du); free(b); free(t1); free(t2);

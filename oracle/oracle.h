@@ -63,6 +63,8 @@ typedef struct {
     const double* apply_h;   /* [n_tets] element damping (NULL = 0) */
     const double* apply_x;   /* [3*n_nodes] */
     double* apply_y;         /* [3*n_nodes] */
+    int masing_depth;        /* reversal points a spring remembers: 0 or 1 the three-rule law,
+                                K > 1 also closes inner loops up to K - 1 deep */
 } or_problem;
 
 typedef struct {
@@ -73,10 +75,11 @@ typedef struct {
     double* v_final;   /* [3*n_nodes] (optional) */
     double* D_final;   /* [n_tets*4*21] upper-triangle row-major D per IP (optional) */
     double* h_final;   /* [n_tets] element damping (optional) */
-    double* theta_final; /* [n_tets*4*n_springs*6] gp,gr,tr,gm,dir,skel (optional) */
+    double* theta_final; /* [n_tets*4*n_springs*W] gp,gr,tr,gm,dir,skel, then for depth K > 1
+                            the count and K - 1 older (gr, tr); W = or_spring_words(K) (optional) */
     double* vmax;      /* [n_recv] largest velocity norm over the run (optional) */
-    long law_events[3]; /* over the run: reversals on the skeleton, reversals on a
-                           Masing branch, rejoins of the skeleton */
+    long law_events[4]; /* over the run: reversals on the skeleton, reversals on a
+                           Masing branch, rejoins of the skeleton, inner loops closed */
     double setup_seconds; /* wall time before the first step (pattern, mass, faces) */
     int steps_done;
 } or_result;
@@ -97,6 +100,11 @@ void or_element_matrices(const double* X4x3, const double* D4x36, double rho,
 void or_face_matrix(const double* X3x3, double* M36, double* normal3, double* area);
 void or_rayleigh(double f_lo, double f_hi, double* a_hat, double* b_hat);
 double or_ro_inverse(double e, double beta);
+/* one spring with a reversal memory of `depth` (state of or_spring_words(depth)
+ * doubles, see or_run's theta_final); events[4] accumulates as law_events */
+double or_spring_step_mem(double* state, int depth, double dgamma, double G0, double gref, double h_max,
+                          double* Gt, double* hk, long* events);
+int or_spring_words(int depth);
 /* threads of the OpenMP loops (timing of the oracle on a given core count) */
 void or_set_threads(int n);
 double or_ro_beta(double h_max);

@@ -502,7 +502,7 @@ def test_vmax_is_the_largest_velocity_norm(oracle_lib):
     r = oracle_lib.run(mesh, prob)
     ref = np.sqrt((r["vel"] ** 2).sum(axis=2)).max(axis=0)
     assert ref.max() > 0 and np.allclose(r["vmax"], ref, rtol=1e-15, atol=0)
-    assert all(c > 0 for c in r["law_events"]), r["law_events"]
+    assert all(c > 0 for c in r["law_events"][:3]) and r["law_events"][3] == 0, r["law_events"]
     assert 0 <= r["setup_seconds"] <= r["seconds"]
 
 
@@ -577,3 +577,103 @@ def test_extrapolated_initial_guess_is_closer(oracle_lib):
                     (du[n - 1], 2 * du[n - 1] - du[n - 2], 3 * du[n - 1] - 3 * du[n - 2] + du[n - 3])])
     e0, e1, e2 = np.median(np.array(err), axis=0)
     assert e1 < e0 / 10 and e2 < e1 / 5, (e0, e1, e2)
+
+
+def _mem_path(oracle_lib, depth, targets, G0, gref, hmax, n=64):
+    st = oracle_lib.new_spring_mem(depth)
+    ev = (__import__("ctypes").c_long * 4)()
+    seen = []
+    for target in targets:
+        d = (target - st[0]) / n
+        for _ in range(n):
+            tau, Gt, _ = oracle_lib.spring_step_mem(st, depth, d, G0, gref, hmax, ev)
+        assert st[0] == target
+        seen.append((tau, Gt, st.copy()))
+    return seen, tuple(ev)
+
+
+def test_masing_memory_closes_inner_loops(oracle_lib):
+    """Masing's rule for inner loops (the law-fidelity extension): with the
+    last three reversal points remembered, the path 0 -> A -> -A/2 -> A/4 ->
+    -3A/4 -> -A -> -5A/4 closes the inner loop (-A/2 -> A/4 -> -A/2) and goes
+    on along the branch from A: in closed form tau(-A/2) = S(A) - 2S(3A/4),
+    tau(A/4) = tau(-A/2) + 2S(3A/8), tau(-3A/4) = S(A) - 2S(7A/8), then the
+    skeleton at -A and -5A/4.  With the three-rule law (one point) the branch
+    from A/4 goes on instead: tau(-3A/4) = tau(A/4) - 2S(A/2).  Depth 1 is
+    the oracle's default spring law step for step, and depth 2 behaves as
+    depth 1 (an inner loop needs three points)."""
+    G0, gref, hmax = 3.0e7, 2.0 ** -10, 0.2
+    b = oracle_lib.ro_beta(hmax)
+    A = 2.0 ** -10 * 1.5
+
+    def S(x):
+        return _skeleton_indep(x, G0, gref, b)
+
+    path = (A, -A / 2, A / 4, -3 * A / 4, -A, -5 * A / 4)
+    seen, ev = _mem_path(oracle_lib, 3, path, G0, gref, hmax)
+    tol = 1e-13 * S(A)
+    t1 = S(A) - 2 * S(3 * A / 4)
+    t2 = t1 + 2 * S(3 * A / 8)
+    assert abs(seen[0][0] - S(A)) < tol
+    assert abs(seen[1][0] - t1) < tol
+    assert abs(seen[2][0] - t2) < tol and seen[2][2][6] == 1  # one older point held
+    assert abs(seen[3][0] - (S(A) - 2 * S(7 * A / 8))) < tol
+    assert seen[3][2][6] == 0 and seen[3][2][1] == A  # back on the branch from A
+    assert abs(seen[4][0] + S(A)) < tol and seen[4][2][5] == 1.0  # rejoin at -A
+    assert abs(seen[5][0] - S(-5 * A / 4)) < tol
+    assert ev[3] == 1 and ev[2] == 1, ev
+    # tangent just after the closure: the slope of the branch from A
+    hd = A * 1e-5
+    slope = (S(7 * A / 8 + hd) - S(7 * A / 8 - hd)) / (2 * hd)
+    assert abs(seen[3][1] - slope) < 1e-7 * slope
+    # depth 1 (and 2): the three-rule law, equal to or_spring_step throughout
+    for depth in (1, 2):
+        s1, e1 = _mem_path(oracle_lib, depth, path, G0, gref, hmax)
+        assert abs(s1[3][0] - (t2 - 2 * S(A / 2))) < tol and e1[3] == 0
+    ref = oracle_lib.new_spring()
+    st = oracle_lib.new_spring_mem(1)
+    for target in path:
+        for _ in range(64):
+            d = (target - ref[0]) / 64
+            t_ref = oracle_lib.spring_step(ref, d, G0, gref, hmax)
+            t_mem = oracle_lib.spring_step_mem(st, 1, d, G0, gref, hmax)
+            assert t_ref == t_mem and np.array_equal(ref, st[:6])
+
+
+def test_masing_memory_stress_stays_continuous(oracle_lib):
+    """With enough memory (64 points, more than the reversals of the path) the
+    stress never jumps on a random strain path with many nested reversals:
+    |tau(g + dg) - tau(g)| <= G0 |dg| (the tangent lies in (0, G0]), through
+    every closed inner loop and rejoin.  The three-rule law (depth 1) jumps
+    where a branch started inside an earlier loop reaches the largest strain
+    and rejoins the skeleton (here 0 -> A -> -A/2 -> A/4 -> -5A/4), which is
+    what the memory removes."""
+    G0, gref, hmax = 3.0e7, 1e-3, 0.2
+    rng = np.random.default_rng(9)
+    depth = 64
+    st = oracle_lib.new_spring_mem(depth)
+    ev = (__import__("ctypes").c_long * 4)()
+    tau_prev, g, amp = 0.0, 0.0, 3e-3
+    for _ in range(60):
+        target = float(np.clip(g + rng.normal(0, 1.5e-3), -amp, amp))
+        n = max(1, int(abs(target - g) / 1e-5))
+        for _ in range(n):
+            dg = (target - g) / n
+            tau, Gt, _ = oracle_lib.spring_step_mem(st, depth, dg, G0, gref, hmax, ev)
+            assert abs(tau - tau_prev) <= G0 * abs(dg) * (1 + 1e-9) + 1e-6
+            assert 0 < Gt <= G0
+            tau_prev, g = tau, st[0]
+    assert ev[3] >= 5 and ev[2] >= 1, tuple(ev)
+    A = 1.5e-3
+    jumps = {}
+    for depth in (1, 3):
+        st = oracle_lib.new_spring_mem(depth)
+        tau_prev, big = 0.0, 0.0
+        for target in (A, -A / 2, A / 4, -5 * A / 4):
+            for _ in range(200):
+                dg = (target - st[0]) / 200
+                tau, _, _ = oracle_lib.spring_step_mem(st, depth, dg, G0, gref, hmax)
+                big = max(big, abs(tau - tau_prev) / (G0 * abs(dg)))
+                tau_prev = tau
+        jumps[depth] = big
+    assert jumps[3] <= 1.0 + 1e-9 and jumps[1] > 1.5, jumps
