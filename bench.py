@@ -279,7 +279,7 @@ def bench_paged(args):
     dims = tuple(int(v) for v in args.mesh.split("x"))
     n_total = args.warmup + args.steps
     mesh, prob = I.config(3, n_members=args.members, mesh_dims=dims, n_steps=n_total)
-    theta_gb = mesh.n_tets * 4 * prob.n_springs * args.members * 36 / 1e9
+    theta_gb = mesh.n_tets * 4 * prob.n_springs * args.members * (36 + 16 * (max(prob.masing_depth, 1) - 1)) / 1e9
     log(f"paged ensemble: {args.members} members, law state {theta_gb:.1f} GB, device budget {args.hbm_budget_gb} GB")
     t0 = time.perf_counter()
     el, _, st, out, _ = run_gpu(mesh, prob, args.warmup, args.steps, False,

@@ -180,6 +180,16 @@ typedef struct {
                                   the mean over its four points; the preconditioner then
                                   applies a slightly different operator, which the FP64 outer
                                   iteration corrects) */
+    int32_t masing_depth;      /* 0 or 1: the law's three Masing rules (each spring keeps its
+                                  last reversal point; a branch runs until it meets the
+                                  skeleton, Section 2.1 with the extended Masing rules of its
+                                  cited law).  K in 2..8: each spring also keeps the origins of
+                                  up to K-1 earlier branches, so an inner loop closes when the
+                                  strain passes the last reversal point and the path goes on
+                                  along the branch it left (the fourth rule; with the memory
+                                  full the oldest point is dropped).  Law state per spring and
+                                  point: 36 B, plus 16 B per remembered point beyond the
+                                  first.  Other values: NLTH_EINVAL. */
 } nlth_problem;
 
 /* Result buffers (caller-owned host memory; NULL fields are skipped).

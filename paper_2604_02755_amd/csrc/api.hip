@@ -638,6 +638,9 @@ void copy_problem(const nlth_problem* in, Problem& P)
     P.precision = in->precision;
     P.inner_tol = in->inner_tol;
     P.inner_maxit = in->inner_maxit;
+    if (in->masing_depth < 0 || in->masing_depth > kMaxMasingDepth)
+        throw Error{NLTH_EINVAL, "problem: masing_depth must be in 0..8"};
+    P.depth = std::max(1, (int)in->masing_depth);
     if (in->inner_dtype != NLTH_INNER_BF16 && in->inner_dtype != NLTH_INNER_FP32 &&
         in->inner_dtype != NLTH_INNER_BF16_MEAN)
         throw Error{NLTH_EINVAL, "problem: inner_dtype must be NLTH_INNER_BF16, NLTH_INNER_FP32 or NLTH_INNER_BF16_MEAN"};
@@ -680,7 +683,7 @@ int64_t ensemble_bytes(const Mesh& m, const Problem& p, int MB, bool paged)
     else if (MB < 64) bytes += (int64_t)m.ne * 30 * MB * 8;             // element outputs
     bytes += (int64_t)p.n_steps * std::max(1, m.nrecv) * 3 * MB * 8;  // receiver history
     bytes += (int64_t)p.n_steps * 3 * MB * 8 * 2;           // acc, vI
-    if (!paged) bytes += (int64_t)m.ne * 4 * p.ns * MB * kThetaBytes;
+    if (!paged) bytes += (int64_t)m.ne * 4 * p.ns * MB * theta_bytes(p.depth);
     return bytes;
 }
 
@@ -834,17 +837,17 @@ void Ens::create(Ctx* c, const Mesh* m, const Problem& prob, int member_pad)
                     D64.as<double>(), D32.as<float>(), D16.as<uint32_t>(), h.as<double>(), -1, d16_mean);
 
     // law state: resident if it fits the remaining budget, else paged
-    const size_t per_elem = (size_t)4 * P.ns * MB * kThetaBytes;
-    const size_t theta_bytes = per_elem * ne_pad;
+    const size_t per_elem = (size_t)4 * P.ns * MB * theta_bytes(P.depth);
+    const size_t state_bytes = per_elem * ne_pad;
     int64_t avail;
     {
         std::lock_guard<std::mutex> g(bg->mu);
         avail = bg->limit > 0 ? bg->limit - bg->used : INT64_MAX;
     }
     const int64_t reserve = (int64_t)P.n_steps * std::max(1, m->nrecv) * 3 * MB * 8 * 2 + (64 << 20);
-    paged = (int64_t)theta_bytes + reserve > avail;
+    paged = (int64_t)state_bytes + reserve > avail;
     if (!paged) {
-        theta.alloc(bg, theta_bytes);
+        theta.alloc(bg, state_bytes);
         launch_theta_init(s, theta.p, ne_pad, P.ns, MB);
     } else {
         // chunk ring: the largest chunk with 3 slots fitting a quarter of what is left
@@ -854,7 +857,7 @@ void Ens::create(Ctx* c, const Mesh* m, const Problem& prob, int member_pad)
         chunk_elems = std::max(EB, chunk_elems / EB * EB);
         nchunks = (m->ne + chunk_elems - 1) / chunk_elems;
         if (nchunks < ring) ring = std::max(1, nchunks);
-        theta_host.alloc(bg, theta_bytes, true);
+        theta_host.alloc(bg, state_bytes, true);
         theta.alloc(bg, (size_t)chunk_elems * per_elem * ring);
         long off = 0;
         for (int cix = 0; cix < nchunks; ++cix) {
@@ -1449,11 +1452,11 @@ void Ens::solve_fcg()
 void Ens::law_phase()
 {
     const DevMesh dm = mesh->dev();
-    const size_t per_elem = (size_t)4 * P.ns * MB * kThetaBytes;
+    const size_t per_elem = (size_t)4 * P.ns * MB * theta_bytes(P.depth);
     if (!paged) {
         hipEvent_t t0;
         tstart(t0);
-        launch_law(s, dm, MB, nm, 0, mesh->ne, ne_pad, mat.as<double>(), P.nl, nonlinear.as<int>(), P.ns, dirs.as<double>(),
+        launch_law(s, dm, MB, nm, 0, mesh->ne, ne_pad, mat.as<double>(), P.nl, nonlinear.as<int>(), P.ns, P.depth, dirs.as<double>(),
                    w.as<double>(), du.as<double>(), theta.p, D64.as<double>(), D32.as<float>(), D16.as<uint32_t>(), h.as<double>(),
                    stepping.as<int>(), d16_mean);
         tstop(t0, &pc_law, (int64_t)mesh->ne * nm);
@@ -1469,7 +1472,7 @@ void Ens::law_phase()
             hipEvent_t t0;
             tstart(t0);
             launch_law(s, dm, MB, nm, chunk_e0[cix], chunk_ec[cix], chunk_ecp[cix], mat.as<double>(), P.nl,
-                       nonlinear.as<int>(), P.ns, dirs.as<double>(), w.as<double>(), du.as<double>(),
+                       nonlinear.as<int>(), P.ns, P.depth, dirs.as<double>(), w.as<double>(), du.as<double>(),
                        (char*)theta_host.p + chunk_off[cix], D64.as<double>(), D32.as<float>(), D16.as<uint32_t>(),
                        h.as<double>(), stepping.as<int>(), d16_mean);
             tstop(t0, &pc_law, (int64_t)chunk_ec[cix] * nm);
@@ -1496,7 +1499,7 @@ void Ens::law_phase()
         NLTH_HIP(hipStreamWaitEvent(s, ev_h2d[slot], 0));
         hipEvent_t t0;
         tstart(t0);
-        launch_law(s, dm, MB, nm, chunk_e0[cix], chunk_ec[cix], chunk_ecp[cix], mat.as<double>(), P.nl, nonlinear.as<int>(), P.ns,
+        launch_law(s, dm, MB, nm, chunk_e0[cix], chunk_ec[cix], chunk_ecp[cix], mat.as<double>(), P.nl, nonlinear.as<int>(), P.ns, P.depth,
                    dirs.as<double>(), w.as<double>(), du.as<double>(), dslot, D64.as<double>(), D32.as<float>(), D16.as<uint32_t>(),
                    h.as<double>(), stepping.as<int>(), d16_mean);
         tstop(t0, &pc_law, (int64_t)chunk_ec[cix] * nm);
@@ -1513,7 +1516,7 @@ void Ens::law_phase()
 
 void Ens::prefetch_next()
 {
-    const size_t per_elem = (size_t)4 * P.ns * MB * kThetaBytes;
+    const size_t per_elem = (size_t)4 * P.ns * MB * theta_bytes(P.depth);
     for (int cix = 0; cix < std::min(ring - 1, nchunks); ++cix) {
         const int slot = cix % ring;
         char* dslot = (char*)theta.p + (size_t)slot * chunk_elems * per_elem;

@@ -1543,15 +1543,19 @@ __device__ __forceinline__ double skeleton_tau(double g, const SpringPar& p)
 }
 
 // Law state of a chunk of ecp elements (ecp a multiple of EB): four FP64
-// fields (gp, gr, tr, gm) then one int32 field packing the loading direction
-// and the skeleton flag, (dir + 1) | skel << 2 (36 B per spring and point);
-// within a field, element blocks of EB, then spring, point, element-in-block,
-// member.
+// fields (gp, gr, tr, gm) then one int32 field packing the loading direction,
+// the skeleton flag and the count of older reversal points kept,
+// (dir + 1) | skel << 2 | count << 3 (36 B per spring and point); with a
+// reversal memory of depth K > 1 the int32 field is followed by 2 (K - 1)
+// FP64 fields, the older points' (gr, tr) pairs, oldest first (36 + 16 (K - 1)
+// B).  Within a field: element blocks of EB, then spring, point,
+// element-in-block, member.
 __device__ __forceinline__ int theta_flags(int dir, int skel) { return (dir + 1) | (skel << 2); }
 
 struct ThetaView {
     double* d;
     int* i;
+    double* od;    // older reversal points: gr of point k at od[2k * field_n], tr at od[(2k + 1) * field_n]
     long field_n;  // entries per field = ecp * 4 * ns * MB
     int ns, MB, EB;
     __device__ __forceinline__ long at(long el, int s, int j, int m) const
@@ -1566,6 +1570,7 @@ __device__ __forceinline__ ThetaView theta_view(void* base, long ecp, int ns, in
     v.field_n = ecp * 4 * (long)ns * MB;
     v.d = (double*)base;
     v.i = (int*)(v.d + 4 * v.field_n);
+    v.od = (double*)(v.i + v.field_n);  // field_n is a multiple of 4: 8-byte aligned
     v.ns = ns;
     v.MB = MB;
     v.EB = MB >= 64 ? 1 : 64 / MB;
@@ -1693,11 +1698,13 @@ void launch_zero_member(hipStream_t s, double* p, long rows, int MB, int m)
 // registers instead of 178 (3 wavefronts per SIMD instead of 2), and with the
 // launch bound of 4 wavefronts per SIMD 128 registers and 36 B of spills
 // (4 % faster again); 0: D accumulated in registers.
+// MEM: a reversal memory of `depth` > 1 points (inner loops close, as the
+// oracle's law with that depth); false: the three-rule law.
 constexpr int kLawLdsSprings = 16;
-template <bool WAVE_ELEM, int LDS_NS>
+template <bool WAVE_ELEM, int LDS_NS, bool MEM>
 __global__ __launch_bounds__(256, LDS_NS > 0 ? 4 : 1) void k_law(DevMesh M, int MB, int nm, int e0, int ec, long ecp,
                                             const double* __restrict__ mat, const int* __restrict__ nonlinear,
-                                            int ns, const double* __restrict__ dirs,
+                                            int ns, int depth, const double* __restrict__ dirs,
                                             const double* __restrict__ w, const double* __restrict__ du,
                                             void* theta, double* __restrict__ D, float* __restrict__ D32,
                                             uint32_t* __restrict__ D16, double* __restrict__ h,
@@ -1768,7 +1775,8 @@ __global__ __launch_bounds__(256, LDS_NS > 0 ? 4 : 1) void k_law(DevMesh M, int 
         const double dg = n[0] * ej[0] + n[1] * ej[1] + n[2] * ej[2] + n[3] * ej[3] + n[4] * ej[4] + n[5] * ej[5];
         const long idx = nidx;
         double gp = ngp, gr = ngr, tr = ntr, gm = ngm;
-        int dir = (nfl & 3) - 1, skel = nfl >> 2;
+        int dir = (nfl & 3) - 1, skel = (nfl >> 2) & 1;
+        int cnt = MEM ? nfl >> 3 : 0;  // older reversal points kept
         if (sp + 1 < ns) {
             nidx = th.at(el, sp + 1, j, m);
             ngp = th.d[nidx]; ngr = th.d[fn + nidx]; ntr = th.d[2 * fn + nidx]; ngm = th.d[3 * fn + nidx];
@@ -1781,12 +1789,43 @@ __global__ __launch_bounds__(256, LDS_NS > 0 ? 4 : 1) void k_law(DevMesh M, int 
             if (dir != 0 && dsg != dir) {  // reversal: a Masing branch starts here
                 rev = skel ? 1 : 2;
                 rev_arg = skel ? gp : 0.5 * (gp - gr);
+                if (MEM) {
+                    // the reversal stress now (a closed loop below may replace the branch), and the
+                    // origin of the branch being left kept (the oldest dropped when full)
+                    double pk;
+                    const double sv = ro_inverse_pw(rev_arg / P.gref, P.beta, &pk);
+                    const double trev = rev == 1 ? P.G0 * P.gref * sv : tr + 2.0 * P.G0 * P.gref * sv;
+                    if (!skel) {
+                        if (cnt == depth - 1) {
+                            for (int k = 0; k + 1 < cnt; ++k) {
+                                th.od[(2 * k) * fn + idx] = th.od[(2 * k + 2) * fn + idx];
+                                th.od[(2 * k + 1) * fn + idx] = th.od[(2 * k + 3) * fn + idx];
+                            }
+                            --cnt;
+                        }
+                        th.od[(2 * cnt) * fn + idx] = gr;
+                        th.od[(2 * cnt + 1) * fn + idx] = tr;
+                        ++cnt;
+                    }
+                    tr = trev;
+                    rev = 0;
+                }
                 gr = gp;
                 skel = 0;
             }
             dir = dsg;
             const double g = gp + dg;
-            if (!skel && (double)dsg * g >= gm) skel = 1;  // rejoin the skeleton
+            if (!skel && (double)dsg * g >= gm) {  // rejoin the skeleton
+                skel = 1;
+                cnt = 0;
+            }
+            if (MEM) {  // closed inner loops: on along the branch before the previous one
+                while (!skel && cnt >= 2 && (double)dsg * g >= (double)dsg * th.od[(2 * cnt - 2) * fn + idx]) {
+                    gr = th.od[(2 * cnt - 4) * fn + idx];
+                    tr = th.od[(2 * cnt - 3) * fn + idx];
+                    cnt -= 2;
+                }
+            }
             if (skel) gm = fmax(gm, fabs(g));
             gp = g;
         }
@@ -1808,7 +1847,7 @@ __global__ __launch_bounds__(256, LDS_NS > 0 ? 4 : 1) void k_law(DevMesh M, int 
         if (rev) tr = rev == 1 ? P.G0 * P.gref * s_rev : tr + 2.0 * P.G0 * P.gref * s_rev;
         if (dg != 0.0) {
             th.d[idx] = gp; th.d[fn + idx] = gr; th.d[2 * fn + idx] = tr; th.d[3 * fn + idx] = gm;
-            th.i[idx] = theta_flags(dir, skel);
+            th.i[idx] = theta_flags(dir, skel) | (cnt << 3);
         }
         const double Gt = P.G0 / (1.0 + (1.0 + P.beta) * pw);
         double hk = 0.0;
@@ -1862,28 +1901,40 @@ __global__ __launch_bounds__(256, LDS_NS > 0 ? 4 : 1) void k_law(DevMesh M, int 
     if (j == 0) h[e * MB + m] = 0.25 * hsum;
 }
 
+template <int LDS_NS, bool MEM>
+static void law_dispatch(hipStream_t s, dim3 g, const DevMesh& M, int MB, int nm, int e0, int ec, long ecp,
+                         const double* mat, const int* nonlinear, int ns, int depth, const double* dirs,
+                         const double* w, const double* du, void* theta, double* D, float* D32, uint32_t* D16,
+                         double* h, const int* stepping, bool d16_mean)
+{
+    if (MB >= 16)
+        hipLaunchKernelGGL((k_law<true, LDS_NS, MEM>), g, dim3(256), 0, s, M, MB, nm, e0, ec, ecp, mat, nonlinear, ns,
+                           depth, dirs, w, du, theta, D, D32, D16, h, stepping, d16_mean);
+    else
+        hipLaunchKernelGGL((k_law<false, LDS_NS, MEM>), g, dim3(256), 0, s, M, MB, nm, e0, ec, ecp, mat, nonlinear, ns,
+                           depth, dirs, w, du, theta, D, D32, D16, h, stepping, d16_mean);
+}
+
 void launch_law(hipStream_t s, const DevMesh& M, int MB, int nm, int e0, int ec, long ecp, const double* mat, int,
-                const int* nonlinear, int ns, const double* dirs, const double* w, const double* du,
+                const int* nonlinear, int ns, int depth, const double* dirs, const double* w, const double* du,
                 void* theta, double* D, float* D32, uint32_t* D16, double* h, const int* stepping, bool d16_mean)
 {
     long n = (long)ec * MB * 4;
     if (n <= 0) return;
-    const dim3 g(nblocks(n)), b(256);
-    if (ns <= kLawLdsSprings) {
-        if (MB >= 16)
-            hipLaunchKernelGGL((k_law<true, kLawLdsSprings>), g, b, 0, s, M, MB, nm, e0, ec, ecp, mat, nonlinear, ns,
-                               dirs, w, du, theta, D, D32, D16, h, stepping, d16_mean);
-        else
-            hipLaunchKernelGGL((k_law<false, kLawLdsSprings>), g, b, 0, s, M, MB, nm, e0, ec, ecp, mat, nonlinear, ns,
-                               dirs, w, du, theta, D, D32, D16, h, stepping, d16_mean);
-    } else {
-        if (MB >= 16)
-            hipLaunchKernelGGL((k_law<true, 0>), g, b, 0, s, M, MB, nm, e0, ec, ecp, mat, nonlinear, ns, dirs, w, du,
-                               theta, D, D32, D16, h, stepping, d16_mean);
-        else
-            hipLaunchKernelGGL((k_law<false, 0>), g, b, 0, s, M, MB, nm, e0, ec, ecp, mat, nonlinear, ns, dirs, w, du,
-                               theta, D, D32, D16, h, stepping, d16_mean);
-    }
+    const dim3 g(nblocks(n));
+    const bool small = ns <= kLawLdsSprings, mem = depth > 1;
+    if (small && !mem)
+        law_dispatch<kLawLdsSprings, false>(s, g, M, MB, nm, e0, ec, ecp, mat, nonlinear, ns, depth, dirs, w, du,
+                                            theta, D, D32, D16, h, stepping, d16_mean);
+    else if (small)
+        law_dispatch<kLawLdsSprings, true>(s, g, M, MB, nm, e0, ec, ecp, mat, nonlinear, ns, depth, dirs, w, du,
+                                           theta, D, D32, D16, h, stepping, d16_mean);
+    else if (!mem)
+        law_dispatch<0, false>(s, g, M, MB, nm, e0, ec, ecp, mat, nonlinear, ns, depth, dirs, w, du, theta, D, D32,
+                               D16, h, stepping, d16_mean);
+    else
+        law_dispatch<0, true>(s, g, M, MB, nm, e0, ec, ecp, mat, nonlinear, ns, depth, dirs, w, du, theta, D, D32,
+                              D16, h, stepping, d16_mean);
 }
 
 // ---------------------------------------------------------------------------

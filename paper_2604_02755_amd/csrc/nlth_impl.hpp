@@ -151,7 +151,7 @@ void launch_ebe32(hipStream_t s, const DevMesh& M, int MB, int nm, int e0, int e
                   const int* active, bool out, bool d16_mean);
 void launch_theta_init(hipStream_t s, void* theta_chunk, long ecp, int ns, int MB);
 void launch_law(hipStream_t s, const DevMesh& M, int MB, int nm, int e0, int ec, long ecp, const double* mat,
-                int n_layers, const int* nonlinear, int ns, const double* dirs, const double* w,
+                int n_layers, const int* nonlinear, int ns, int depth, const double* dirs, const double* w,
                 const double* du, void* theta_chunk, double* D, float* D32, uint32_t* D16, double* h,
                 const int* stepping, bool d16_mean);
 
@@ -171,8 +171,11 @@ struct CgScalars {  // per member [MB] device arrays
 
 // inner CG iterations whose coefficients are kept for the spectrum estimate
 constexpr int kLanczosMax = 64;
-// law state per spring and integration point: 4 FP64 + one int32 of flags
+// law state per spring and integration point: 4 FP64 + one int32 of flags,
+// plus two FP64 per older reversal point kept with a memory of depth > 1
 constexpr int kThetaBytes = 36;
+constexpr int kMaxMasingDepth = 8;  // the count of older points fits 3 bits of the flags
+inline int theta_bytes(int depth) { return kThetaBytes + 16 * ((depth > 1 ? depth : 1) - 1); }
 // Chebyshev degree limit; coefficient table cheb[(2 k + 0/1) * MB + m] =
 // (c1_k, c2_k), k < kChebMax, and cheb[2 kChebMax * MB + m] = c0
 constexpr int kChebMax = 64;

@@ -84,6 +84,7 @@ struct Problem {  // host copy of an nlth_problem
     int damping_mode = 0;
     double h0 = 0, f_lo = 0.1, f_hi = 10, dt = 1e-3, cg_tol = 1e-8, inner_tol = 0.1;
     int cg_maxit = 1000, precision = 0, inner_maxit = 50, inner_dtype = 0;
+    int depth = 1;  // reversal points the law remembers (1: the three-rule law)
 };
 
 struct ProfCat { double ms = 0; int64_t n = 0; int64_t elems = 0; };

@@ -80,7 +80,7 @@ static bool same_shared(const Problem& a, const Problem& b)
            a.nonlinear == b.nonlinear && a.damping_mode == b.damping_mode && a.h0 == b.h0 && a.f_lo == b.f_lo &&
            a.f_hi == b.f_hi && a.dt == b.dt && a.cg_tol == b.cg_tol && a.cg_maxit == b.cg_maxit &&
            a.precision == b.precision && a.inner_tol == b.inner_tol && a.inner_maxit == b.inner_maxit &&
-           a.inner_dtype == b.inner_dtype;
+           a.inner_dtype == b.inner_dtype && a.depth == b.depth;
 }
 
 struct ServeState {

@@ -355,6 +355,7 @@ class Problem:
     inner_tol: float = 0.1
     inner_maxit: int = 50
     inner_dtype: int = 0   # 0: bfloat16 D for the inner operator, 1: FP32
+    masing_depth: int = 1  # reversal points the law remembers (1: three rules; K > 1: inner loops close)
 
     @property
     def n_springs(self) -> int:

@@ -65,7 +65,7 @@ class nlth_problem(C.Structure):
                 ("f_hi", C.c_double), ("dt", C.c_double), ("n_steps", C.c_int32),
                 ("input_acc", _dp), ("cg_tol", C.c_double), ("cg_maxit", C.c_int32),
                 ("precision", C.c_int32), ("inner_tol", C.c_double), ("inner_maxit", C.c_int32),
-                ("inner_dtype", C.c_int32)]
+                ("inner_dtype", C.c_int32), ("masing_depth", C.c_int32)]
 
 
 class nlth_tuning(C.Structure):
@@ -261,7 +261,7 @@ def _problem_struct(prob, keep, members=None, n_steps=None):
                         int(prob.damping_mode), float(prob.h0), float(prob.f_lo), float(prob.f_hi),
                         float(prob.dt), ns, _ptr(acc), float(prob.cg_tol), int(prob.cg_maxit),
                         int(prob.precision), float(prob.inner_tol), int(prob.inner_maxit),
-                        int(getattr(prob, "inner_dtype", 0)))
+                        int(getattr(prob, "inner_dtype", 0)), int(getattr(prob, "masing_depth", 1)))
 
 
 def _result_buffers(nm, ns, nrecv):

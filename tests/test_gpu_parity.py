@@ -497,6 +497,38 @@ def test_long_run_reaches_every_law_event(gpu_ctx, oracle_lib, precision):
     assert out["rc"] == 0 and err < 1e-9 and verr < 1e-9
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_reversal_memory_matches_oracle(gpu_ctx, oracle_lib, precision):
+    """The law with a reversal memory of depth 3 (inner loops close and the
+    path goes on along the branch it left): the oracle closes loops in this
+    run and its result differs from the three-rule law's; the GPU matches it
+    with one member slot and with 64 (members 0 and 63 checked)."""
+    mesh, prob = _small_problem(n_steps=400, precision=precision, tol=1e-12, dims=(4, 3, 2), ns=12, scale=6.0)
+    prob.masing_depth = 3
+    ref = oracle_lib.run(mesh, prob)
+    ev = ref["law_events"]
+    say("reversal memory depth 3, precision", precision, "oracle law events", ev)
+    assert ev[3] > 0
+    prob.masing_depth = 1
+    assert oracle_lib.rel_l2(oracle_lib.run(mesh, prob)["vel"], ref["vel"]) > 1e-4
+    prob.masing_depth = 3
+    mh = gpu_ctx.mesh(mesh)
+    out = gpu_ctx.solve(mh, mesh, prob)
+    err = oracle_lib.rel_l2(out["vel"][0], ref["vel"])
+    say("  one member: rel L2 vs oracle", err)
+    assert out["rc"] == 0 and err < 1e-9
+    mesh, prob = _small_problem(n_steps=150, precision=precision, tol=1e-12, dims=(4, 3, 2), ns=12, scale=6.0,
+                                n_members=64)
+    prob.masing_depth = 3
+    out = gpu_ctx.solve(mh, mesh, prob)
+    assert out["rc"] == 0
+    for m in (0, 63):
+        ref = oracle_lib.run(mesh, prob, member=m)
+        err = oracle_lib.rel_l2(out["vel"][m], ref["vel"])
+        say("  64 members, member", m, "rel L2 vs oracle", err, "law events", ref["law_events"])
+        assert ref["law_events"][3] > 0 and err < 1e-9
+
+
 def test_benchmark_path_at_throughput_tolerance(gpu_ctx, oracle_lib):
     """The benchmark's launch configuration at its operating point: 64 member
     slots (cluster operator, element-mean bfloat16 inner D, compact rows for
