@@ -169,7 +169,7 @@ def run_gpu(mesh, prob, warmup, steps, profile, tune_steps=0, tuned=None, ctx_kw
     return elapsed, st0, st, out, choice
 
 
-def serve_run(rate, window_s, steps_range, sizes=(32, 48, 64), max_batch=16, n_check=3, seed=4000):
+def serve_run(rate, window_s, steps_range, sizes=(32, 48, 64), max_batch=64, n_check=3, seed=4000):
     """Serving stream of single-member requests (Poisson arrivals, mixed mesh
     sizes) through the library's request loop; latency = completion - arrival.
     A few requests are re-run alone afterwards (batch invariance)."""
@@ -210,7 +210,7 @@ def serve_run(rate, window_s, steps_range, sizes=(32, 48, 64), max_batch=16, n_c
         # batch invariance: re-run a few requests alone
         inv = []
         for j in np.linspace(0, len(reqs) - 1, min(n_check, len(reqs))).astype(int):
-            alone = ctx.solve(mh[reqs[j]["n"]], meshes[reqs[j]["n"]], probs[j])
+            alone = ctx.solve_as_served(mh[reqs[j]["n"]], meshes[reqs[j]["n"]], probs[j])
             b = alone["vel"]
             inv.append(float(np.linalg.norm(outs[j]["vel"] - b) / max(np.linalg.norm(b), 1e-300)))
     finally:
@@ -282,10 +282,11 @@ def bench_paged(args):
     theta_gb = mesh.n_tets * 4 * prob.n_springs * args.members * (36 + 16 * (max(prob.masing_depth, 1) - 1)) / 1e9
     log(f"paged ensemble: {args.members} members, law state {theta_gb:.1f} GB, device budget {args.hbm_budget_gb} GB")
     t0 = time.perf_counter()
-    el, _, st, out, _ = run_gpu(mesh, prob, args.warmup, args.steps, False,
-                                ctx_kw=dict(hbm_budget=int(args.hbm_budget_gb * 2**30),
-                                            host_budget=int((theta_gb * 1.05 + 8) * 1e9)))
-    log(f"paged: {el / args.steps * 1e3:.0f} ms/step, paged={st['paged']}, total {time.perf_counter() - t0:.0f} s")
+    ctx_kw = dict(hbm_budget=int(args.hbm_budget_gb * 2**30), host_budget=int((theta_gb * 1.05 + 8) * 1e9),
+                  paging_sets=args.paging_sets)
+    el, _, st, out, _ = run_gpu(mesh, prob, args.warmup, args.steps, False, ctx_kw=ctx_kw)
+    log(f"paged: {el / args.steps * 1e3:.0f} ms/step, paged={st['paged']}, member sets {st['member_sets']}, "
+        f"total {time.perf_counter() - t0:.0f} s")
     value = args.members * mesh.n_dof * args.steps / el
     line = {
         "metric": METRIC, "value": value, "unit": "DOF-steps/s", "n_gpus": 1, "steps": args.steps,
@@ -296,6 +297,7 @@ def bench_paged(args):
                                f"springs/point, mixed, law state {theta_gb:.1f} GB in pinned host memory",
                    "members": args.members, "hbm_budget_gb": args.hbm_budget_gb},
         "paged": bool(st["paged"]),
+        "member_sets": st["member_sets"],
         "host_link": {"h2d_gb_per_step": st["h2d_bytes"] / args.steps / 1e9,
                       "d2h_gb_per_step": st["d2h_bytes"] / args.steps / 1e9,
                       "h2d_gbps": st["h2d_bytes"] / el / 1e9, "d2h_gbps": st["d2h_bytes"] / el / 1e9},
@@ -306,9 +308,7 @@ def bench_paged(args):
     elif args.zero_copy_steps > 0:
         # ablation of the pipeline: the law kernel works on the pinned host
         # state over the host link (the form the footnote of Section 2.3 times)
-        el_zc, _, st_zc, out_zc, _ = run_gpu(mesh, prob, args.warmup, args.zero_copy_steps, False,
-                                             ctx_kw=dict(hbm_budget=int(args.hbm_budget_gb * 2**30),
-                                                         host_budget=int((theta_gb * 1.05 + 8) * 1e9)),
+        el_zc, _, st_zc, out_zc, _ = run_gpu(mesh, prob, args.warmup, args.zero_copy_steps, False, ctx_kw=ctx_kw,
                                              tuning_kw={"zero_copy": 1})
         ms_zc = el_zc / args.zero_copy_steps * 1e3
         k = min(args.steps, args.zero_copy_steps)
@@ -441,13 +441,15 @@ def main():
     ap.add_argument("--config", type=int, default=2, choices=(1, 2, 3, 4),
                     help="2: batched ensemble (default); 1: one large member; 3: paged ensemble; 4: serving")
     ap.add_argument("--hbm-budget-gb", type=float, default=0.0, help="device budget of --config 3 (0: 90%% of free)")
+    ap.add_argument("--paging-sets", type=int, default=0, choices=(0, 1, 2),
+                    help="--config 3: member sets of the paged ensemble (0: the library's default, two)")
     ap.add_argument("--zero-copy-steps", type=int, default=0,
                     help="--config 3: also time this many steps with the law on the host state directly (ablation)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving sub-run of --config 2")
     ap.add_argument("--serve-rate", type=float, default=4.0)
     ap.add_argument("--serve-window", type=float, default=60.0)
     ap.add_argument("--serve-scale", type=float, default=0.1, help="record-length factor of --config 4")
-    ap.add_argument("--max-batch", type=int, default=16)
+    ap.add_argument("--max-batch", type=int, default=64, help="serving: most members per batch")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); members shard across GPUs "
@@ -548,13 +550,27 @@ def main():
         prob64 = I.config(2, n_members=args.members, mesh_dims=dims, precision=I.PRECISION_FP64)[1]
         prob64.input_acc = np.ascontiguousarray(prob64.input_acc[:, :n_total])
         prob64.n_steps = n_total
-        el64, _, st64, out64, _ = run_gpu(mesh, prob64, args.warmup, args.steps, False, n_tune,
-                                          tuned=tuned or {"ebe_block": 256, "check_every": 8},
-                                          pre_steps=args.pre_steps)
+        # the comparator is tuned on its own ensemble (initial guess, launch
+        # shapes, convergence-check interval), over the steps before the same
+        # timed window
+        n_tune64 = 0 if (args.no_tune or fixed) else autotune.trial_steps(prob64)
+        el64, _, st64, out64, tuned64 = run_gpu(mesh, prob64, args.warmup, args.steps, False, n_tune64,
+                                                tuned=None if n_tune64 else (tuned or {"ebe_block": 256,
+                                                                                       "check_every": 8}),
+                                                pre_steps=args.pre_steps + n_tune - n_tune64)
         v64 = args.members * ndof * args.steps / el64
         it64 = float(out64["iters"][:, sl, 0].mean())
+        # lanes the lockstep batch keeps busy: member iterations over the
+        # iterations the batch runs (whole chunks of check_every up to the
+        # slowest member of each step) times the members
+        it_t = out64["iters"][:, sl, 0].astype(np.int64)
+        ce = (tuned64 or tuned or {}).get("check_every", 8) or 8
+        lane_use = float(it_t.sum() / (args.members * (ce * np.ceil(it_t.max(axis=0) / ce)).sum()))
         fp64 = {"value": v64, "ms_per_step": el64 / args.steps * 1e3, "speedup": value / v64,
                 "iters_per_member_step": it64,
+                "tuning": ({k: tuned64.get(k) for k in ("predictor", "ebe_block", "check_every", "cluster_blocks")
+                            if k in tuned64} if tuned64 else None),
+                "iters_min_max": [int(it_t.min()), int(it_t.max())], "lane_use": round(lane_use, 4),
                 "step_roofline": step_roofline(v64, it64, 0.0, prob.n_springs, ip_per_dof),
                 "step_ms": [round(x, 1) for x in st64["step_ms"]]}
         log(f"fp64: {el64/args.steps*1e3:.1f} ms/step, {v64:.3e} DOF-steps/s")

@@ -84,6 +84,13 @@ typedef struct {
     int32_t log_level;    /* 0 silent, 1 per solve, 2 per step */
     int32_t max_batch;    /* serving: most members per batch (0 = 64); a batch is sized,
                              in powers of two, for the members waiting when it forms */
+    int32_t paging_sets;  /* an ensemble whose law state does not fit the device budget:
+                             0 or 2 = two member sets, the solve of one running while the
+                             other's law state streams over the host link (the chunk
+                             pipeline of Section 2.2, Alg. 3, hides the transfers behind
+                             the law kernels only); 1 = one set (its law phase waits for
+                             the link);
+                             other values: NLTH_EINVAL */
 } nlth_ctx_opts;
 
 /* Create a context on HIP device `device` (or NLTH_DEVICE_NONE).  `opts` may
@@ -211,7 +218,12 @@ int nlth_solve(nlth_ctx* ctx, const nlth_mesh* mesh, const nlth_problem* prob, n
 /* Staged form of nlth_solve: create uploads the problem and allocates all
  * device state (and pinned host state when paging); step advances every
  * member by n_steps (synchronous); read copies the results recorded so far;
- * stats reports phase timers.  The problem's arrays are copied by create. */
+ * stats reports phase timers.  The problem's arrays are copied by create.
+ * When the whole ensemble does not fit the device budget and the context
+ * allows two member sets, create splits the members in two halves (the first
+ * ceil(n/2), then the rest), each paging its law state; step alternates them
+ * (results, numbering and iteration counts are those of the members run
+ * alone: the sets share no arithmetic). */
 int nlth_ens_create(nlth_ctx* ctx, const nlth_mesh* mesh, const nlth_problem* prob, nlth_ens** out);
 int nlth_ens_step(nlth_ens* ens, int32_t n_steps);
 int nlth_ens_read(nlth_ens* ens, nlth_result* res);
@@ -240,6 +252,7 @@ typedef struct {
                                   kernel and node gather) */
     int64_t n_tail32;
     int64_t elems_tail32;      /* element-member pairs of those launches (listed members only) */
+    int32_t member_sets;       /* 2: a paged ensemble run as two member sets; 1 otherwise */
 } nlth_stats;
 int nlth_ens_stats(const nlth_ens* ens, nlth_stats* st);
 
@@ -305,7 +318,9 @@ int nlth_ens_reset_stats(nlth_ens* ens);
 
 /* Continuous-batching request loop.  submit admits the request (queued until
  * slots and HBM free up); the result buffers must stay valid until poll/wait
- * reports completion.  The request's input copy is charged to the host budget
+ * reports completion.  Batches take the CG initial guess from the quadratic
+ * extrapolation of the increments (tuning predictor 2), which changes a
+ * member's iteration path only, within its CG tolerance.  The request's input copy is charged to the host budget
  * from submission until its members take slots, and each batch's copy of its
  * members' inputs while the batch lives.  NLTH_EBUSY if the request can never
  * fit the budgets, or if the host budget cannot hold its input copy now

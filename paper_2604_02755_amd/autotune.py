@@ -27,6 +27,7 @@ INNER_POLICIES = [(0.1, 50, 0), (0.01, 60, 0), (1e-12, 12, 0), (1e-12, 16, 0), (
 PREDICTORS = [0, 1, 2]  # degree of the extrapolation of the previous increments
 EBE_BLOCKS = [256, 128]
 CHECK_EVERY = [8, 16, 4]
+CHECK_EVERY_FP64 = [8, 4, 2]  # a plain FP64 PCG iteration is long: checking often costs little
 CLUSTER_BLOCKS = [3, 2, 4]
 
 _cache: dict = {}
@@ -56,7 +57,8 @@ def trial_steps(prob, steps_per_trial: int = 1) -> int:
     one untimed step that makes the Chebyshev spectrum estimate."""
     n_pol = len(INNER_POLICIES) if prob.precision == 1 else 1
     n_cl = len(CLUSTER_BLOCKS) if 64 <= members_padded(prob.n_members) <= 256 else 1
-    stages = [len(PREDICTORS), n_pol, len(EBE_BLOCKS), len(CHECK_EVERY), n_cl]
+    n_ce = len(CHECK_EVERY if prob.precision == 1 else CHECK_EVERY_FP64)
+    stages = [len(PREDICTORS), n_pol, len(EBE_BLOCKS), n_ce, n_cl]
     return 2 * steps_per_trial * sum(n for n in stages if n > 1) + (1 if prob.precision == 1 else 0)
 
 
@@ -116,7 +118,7 @@ def tune(ens, mesh, prob, steps_per_trial: int = 1, cache_file: str | None = Non
         cur, best_ms = stage([dict(cur, inner_tol=t, inner_maxit=m, inner_method=k) for t, m, k in INNER_POLICIES])
     cur, ms = stage([dict(cur, ebe_block=b) for b in EBE_BLOCKS])
     best_ms = ms if ms is not None else best_ms
-    cur, ms = stage([dict(cur, check_every=c) for c in CHECK_EVERY])
+    cur, ms = stage([dict(cur, check_every=c) for c in (CHECK_EVERY if prob.precision == 1 else CHECK_EVERY_FP64)])
     best_ms = ms if ms is not None else best_ms
     if 64 <= st["members_padded"] <= 256:  # the cluster path
         cur, ms = stage([dict(cur, cluster_blocks=b) for b in CLUSTER_BLOCKS])

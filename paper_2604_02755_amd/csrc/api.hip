@@ -589,6 +589,20 @@ DevMesh Mesh::dev() const
 // problem
 // ---------------------------------------------------------------------------
 
+// members m0 .. m0+n-1 of a problem (the per-member arrays sliced)
+Problem member_slice(const Problem& P, int m0, int n)
+{
+    Problem q = P;
+    q.nm = n;
+    const long nl = P.nl, ns3 = (long)P.n_steps * 3;
+    q.rho.assign(P.rho.begin() + m0 * nl, P.rho.begin() + (m0 + n) * nl);
+    q.vs.assign(P.vs.begin() + m0 * nl, P.vs.begin() + (m0 + n) * nl);
+    q.nu.assign(P.nu.begin() + m0 * nl, P.nu.begin() + (m0 + n) * nl);
+    q.gref.assign(P.gref.begin() + m0 * nl, P.gref.begin() + (m0 + n) * nl);
+    if (!P.acc.empty()) q.acc.assign(P.acc.begin() + m0 * ns3, P.acc.begin() + (m0 + n) * ns3);
+    return q;
+}
+
 void copy_problem(const nlth_problem* in, Problem& P)
 {
     if (!in) throw Error{NLTH_EINVAL, "problem is NULL"};
@@ -748,7 +762,7 @@ void Ens::create(Ctx* c, const Mesh* m, const Problem& prob, int member_pad)
     nm = P.nm;
     MB = member_pad > 0 ? member_pad : pad_members(nm);
     ndof = 3L * m->nn;
-    s = c->stream;
+    s = own_s ? own_s : c->stream;
     Budget* bg = &c->budget;
     sc.dt = P.dt;
     sc.damping_mode = P.damping_mode;
@@ -844,8 +858,8 @@ void Ens::create(Ctx* c, const Mesh* m, const Problem& prob, int member_pad)
         std::lock_guard<std::mutex> g(bg->mu);
         avail = bg->limit > 0 ? bg->limit - bg->used : INT64_MAX;
     }
-    const int64_t reserve = (int64_t)P.n_steps * std::max(1, m->nrecv) * 3 * MB * 8 * 2 + (64 << 20);
-    paged = (int64_t)state_bytes + reserve > avail;
+    const int64_t reserve = (int64_t)P.n_steps * std::max(1, m->nrecv) * 3 * MB * 8 * 2 + (64 << 20) + reserve_extra;
+    paged = force_paged || (int64_t)state_bytes + reserve > avail;
     if (!paged) {
         theta.alloc(bg, state_bytes);
         launch_theta_init(s, theta.p, ne_pad, P.ns, MB);
@@ -874,16 +888,13 @@ void Ens::create(Ctx* c, const Mesh* m, const Problem& prob, int member_pad)
             NLTH_HIP(hipMemcpyAsync((char*)theta_host.p + chunk_off[cix], theta.p, (size_t)chunk_ecp[cix] * per_elem,
                                     hipMemcpyDeviceToHost, s));
         }
-        NLTH_HIP(hipStreamCreateWithFlags(&s_h2d, hipStreamNonBlocking));
-        NLTH_HIP(hipStreamCreateWithFlags(&s_d2h, hipStreamNonBlocking));
+        if (!shared_copy_streams) NLTH_HIP(hipStreamCreateWithFlags(&s_h2d, hipStreamNonBlocking));
         for (int k = 0; k < ring; ++k) {
-            hipEvent_t e1, e2, e3;
+            hipEvent_t e1, e2;
             NLTH_HIP(hipEventCreateWithFlags(&e1, hipEventDisableTiming));
             NLTH_HIP(hipEventCreateWithFlags(&e2, hipEventDisableTiming));
-            NLTH_HIP(hipEventCreateWithFlags(&e3, hipEventDisableTiming));
             ev_h2d.push_back(e1);
-            ev_law.push_back(e2);
-            ev_d2h.push_back(e3);
+            ev_d2h.push_back(e2);
         }
         slot_chunk.assign(ring, -1);
         prefetched.assign(nchunks, false);
@@ -910,7 +921,11 @@ void Ens::create(Ctx* c, const Mesh* m, const Problem& prob, int member_pad)
     cs.active = iptr; cs.iters = iptr + MB; cs.status = iptr + 2 * MB; cs.inner_active = iptr + 3 * MB;
     cs.inner_iters = iptr + 4 * MB; cs.inner_total = iptr + 5 * MB; cs.inner_upd = iptr + 6 * MB;
     cs.lz = lz.as<double>();
-    NLTH_HIP(hipHostMalloc((void**)&h_flags, sizeof(int) * MB, hipHostMallocDefault));
+    NLTH_HIP(hipHostMalloc((void**)&h_mail, sizeof(int) * (5 * (size_t)MB + 1),
+                           hipHostMallocMapped | hipHostMallocCoherent));
+    NLTH_HIP(hipHostGetDevicePointer((void**)&d_mail, h_mail, 0));
+    h_flags = h_mail;
+    h_tlist = h_mail + 4 * MB;
     member_step.alloc(bg, (size_t)MB * 4);
     stepping.alloc(bg, (size_t)MB * 4);
     cs.stepping = stepping.as<int>();
@@ -927,14 +942,23 @@ void Ens::create(Ctx* c, const Mesh* m, const Problem& prob, int member_pad)
 
 void Ens::destroy()
 {
-    if (!ctx) return;
+    twin.reset();  // the second set uses this set's transfer-in stream
+    if (!ctx) {
+        if (own_s) (void)hipStreamDestroy(own_s);
+        own_s = nullptr;
+        return;
+    }
     if (s) (void)hipStreamSynchronize(s);
-    if (s_h2d) { (void)hipStreamSynchronize(s_h2d); (void)hipStreamDestroy(s_h2d); s_h2d = nullptr; }
-    if (s_d2h) { (void)hipStreamSynchronize(s_d2h); (void)hipStreamDestroy(s_d2h); s_d2h = nullptr; }
+    if (shared_copy_streams) {
+        s_h2d = nullptr;
+    } else if (s_h2d) {
+        (void)hipStreamSynchronize(s_h2d);
+        (void)hipStreamDestroy(s_h2d);
+        s_h2d = nullptr;
+    }
     for (auto e : ev_h2d) (void)hipEventDestroy(e);
-    for (auto e : ev_law) (void)hipEventDestroy(e);
     for (auto e : ev_d2h) (void)hipEventDestroy(e);
-    ev_h2d.clear(); ev_law.clear(); ev_d2h.clear();
+    ev_h2d.clear(); ev_d2h.clear();
     if (ev_zc) (void)hipEventDestroy(ev_zc);
     ev_zc = nullptr;
     for (auto& pe : pending) { (void)hipEventDestroy(pe.first.first); (void)hipEventDestroy(pe.first.second); }
@@ -949,14 +973,15 @@ void Ens::destroy()
         gt = nullptr;
     }
     g_inner = g_pcg = g_cheb = nullptr;
-    if (h_tlist) (void)hipHostFree(h_tlist);
-    h_tlist = nullptr;
-    if (h_flags) (void)hipHostFree(h_flags);
-    h_flags = nullptr;
+    if (h_mail) (void)hipHostFree(h_mail);
+    h_mail = d_mail = h_flags = h_tlist = nullptr;
     if (ev_copy0) (void)hipEventDestroy(ev_copy0);
     if (ev_copy1) (void)hipEventDestroy(ev_copy1);
     ev_copy0 = ev_copy1 = nullptr;
     ctx = nullptr;
+    // device buffers go with the object; the stream after the work on it
+    if (own_s) (void)hipStreamDestroy(own_s);
+    own_s = nullptr;
 }
 
 // y = operator of `mode` applied to x1 (and x2 for the right-hand side)
@@ -1081,10 +1106,10 @@ void Ens::dots(int nd, const double* a0, const double* b0, const double* a1, con
     launch_dotsv<double>(s, nd, a0, b0, a1, b1, a2, b2, ndof, MB, nm, nullptr, partial.as<double>(), &nblk);
 }
 
-// any member still iterating?  (one small device-to-host copy of the flags)
+// any member still iterating?  (the flags copied to the host mailbox)
 int Ens::read_any_active(const int* flags)
 {
-    NLTH_HIP(hipMemcpyAsync(h_flags, flags, sizeof(int) * nm, hipMemcpyDeviceToHost, s));
+    launch_copy_i32(s, flags, d_mail, nm);
     NLTH_HIP(hipStreamSynchronize(s));
     for (int m = 0; m < nm; ++m)
         if (h_flags[m]) return 1;
@@ -1177,11 +1202,9 @@ void Ens::update_tail()
         try {
             tail_mem.alloc(&ctx->budget, tot);
             tlist.alloc(&ctx->budget, (size_t)(1 + MB) * 4);
-            NLTH_HIP(hipHostMalloc((void**)&h_tlist, sizeof(int) * (1 + MB), hipHostMallocDefault));
         } catch (const Error&) {  // no room: keep the full operator
             tail_mem.release();
             tlist.release();
-            h_tlist = nullptr;
             tail_max = 0;
             return;
         }
@@ -1202,7 +1225,7 @@ void Ens::update_tail()
     for (int m = 0; m < nm; ++m)
         if (h_flags[m]) h_tlist[k++] = m;
     // the previous list copy has completed: the caller synchronised to read h_flags
-    NLTH_HIP(hipMemcpyAsync(tlist.p, h_tlist, sizeof(int) * (1 + na), hipMemcpyHostToDevice, s));
+    launch_copy_i32(s, d_mail + 4 * MB, tlist.as<int>(), 1 + na);
     tail_g = na <= 16 ? 16 : 32;
     launch_tail_pack(s, mesh->dev(), MB, tail_g, P.nl, tlist.as<int>(), D16.as<uint32_t>(), h.as<double>(),
                      mat.as<double>(), pinv32.as<float>(), tb.D, tb.h, tb.mat, tb.pinv);
@@ -1481,8 +1504,9 @@ void Ens::law_phase()
         NLTH_HIP(hipEventRecord(ev_zc, s));
         return;
     }
-    // Algorithm 3 pipeline: chunk c computes while c-1 goes to the host and
-    // c+1 comes to the device, on two copy streams and a ring of slots
+    // Algorithm 3 pipeline over a ring of device slots: chunk c goes back to
+    // the host (after its law kernel, on the compute stream) while chunk c+1
+    // comes in on the copy stream
     for (int cix = 0; cix < nchunks; ++cix) {
         const int slot = cix % ring;
         char* dslot = (char*)theta.p + (size_t)slot * chunk_elems * per_elem;
@@ -1503,10 +1527,13 @@ void Ens::law_phase()
                    dirs.as<double>(), w.as<double>(), du.as<double>(), dslot, D64.as<double>(), D32.as<float>(), D16.as<uint32_t>(),
                    h.as<double>(), stepping.as<int>(), d16_mean);
         tstop(t0, &pc_law, (int64_t)chunk_ec[cix] * nm);
-        NLTH_HIP(hipEventRecord(ev_law[slot], s));
-        NLTH_HIP(hipStreamWaitEvent(s_d2h, ev_law[slot], 0));
-        NLTH_HIP(hipMemcpyAsync((char*)theta_host.p + chunk_off[cix], dslot, bytes, hipMemcpyDeviceToHost, s_d2h));
-        NLTH_HIP(hipEventRecord(ev_d2h[slot], s_d2h));
+        // the write-back follows the law kernel on the compute stream (the
+        // runtime copies to pinned host memory with a blit kernel, which on a
+        // stream of its own could share a hardware queue with the other member
+        // set's solve and hold it back); the next chunk's transfer in runs
+        // meanwhile on the copy stream
+        NLTH_HIP(hipMemcpyAsync((char*)theta_host.p + chunk_off[cix], dslot, bytes, hipMemcpyDeviceToHost, s));
+        NLTH_HIP(hipEventRecord(ev_d2h[slot], s));
         d2h_bytes += bytes;
     }
     // the next step's first chunks are prefetched now so their transfer
@@ -1533,9 +1560,26 @@ void Ens::prefetch_next()
 
 void Ens::one_step()
 {
+    enqueue_step();
+    read_status();
+}
+
+// wait for the stream, then the member status from the mailbox
+void Ens::read_status()
+{
+    launch_copy_i32(s, cs.status, d_mail + MB, MB);
+    sync();
+    std::copy(h_mail + MB, h_mail + 2 * MB, h_status.begin());
+}
+
+void Ens::enqueue_step()
+{
     const DevMesh dm = mesh->dev();
-    NLTH_HIP(hipMemcpyAsync(member_step.p, h_member_step.data(), MB * 4, hipMemcpyHostToDevice, s));
-    NLTH_HIP(hipMemcpyAsync(stepping.p, h_stepping.data(), MB * 4, hipMemcpyHostToDevice, s));
+    // the previous step has completed (its status was read), so the mailbox is free
+    std::copy(h_member_step.begin(), h_member_step.end(), h_mail + 2 * MB);
+    std::copy(h_stepping.begin(), h_stepping.end(), h_mail + 3 * MB);
+    launch_copy_i32(s, d_mail + 2 * MB, member_step.as<int>(), MB);
+    launch_copy_i32(s, d_mail + 3 * MB, stepping.as<int>(), MB);
     const int ns_steps = std::max(1, P.n_steps);
     launch_pick_vI(s, MB, nm, ns_steps, vI_all.as<double>(), member_step.as<int>(), vI_cur.as<double>());
     hipEvent_t t0;
@@ -1565,8 +1609,44 @@ void Ens::one_step()
                      member_step.as<int>(), ns_steps, vmax.as<double>(), stepping.as<int>());
     launch_record_iters(s, MB, nm, ns_steps, member_step.as<int>(), stepping.as<int>(), cs.iters, cs.inner_total,
                         iters_dev.as<int>());
-    NLTH_HIP(hipMemcpyAsync(h_status.data(), cs.status, MB * 4, hipMemcpyDeviceToHost, s));
-    sync();
+}
+
+void Ens::step_begin()
+{
+    for (int m = 0; m < MB; ++m) {
+        h_member_step[m] = steps_done;
+        h_stepping[m] = (m < nm && h_status[m] == 0) ? 1 : 0;
+    }
+    enqueue_step();
+}
+
+void Ens::step_end()
+{
+    read_status();  // after the step's law phase
+    ++steps_done;
+}
+
+// Two member sets A (this) and B (twin): A's solve of step k runs while B's
+// law state of step k-1 streams, then B's solve of step k while A's law state
+// of step k streams.  Each set's solve waits on its own stream only.  (The
+// chunk pipeline of Alg. 3 overlaps the transfers with the law kernels alone,
+// which take a tenth of the link time here; Alg. 4 runs its two sets' solves
+// together and then their law updates.)
+void Ens::step_pair(int n_steps)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    Ens& A = *this;
+    Ens& B = *twin;
+    const int n = std::min(n_steps, P.n_steps - steps_done);
+    if (n > 0) A.step_begin();
+    for (int k = 0; k < n; ++k) {
+        B.step_begin();
+        A.step_end();
+        if (k + 1 < n) A.step_begin();
+        B.step_end();
+    }
+    NLTH_HIP(hipStreamSynchronize(s_h2d));
+    ms_total += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
 void Ens::step_all(int n_steps)
@@ -1582,7 +1662,6 @@ void Ens::step_all(int n_steps)
     }
     if (paged) {
         NLTH_HIP(hipStreamSynchronize(s_h2d));
-        NLTH_HIP(hipStreamSynchronize(s_d2h));
     }
     ms_total += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
@@ -1665,6 +1744,8 @@ int nlth_ctx_create(int device, const nlth_ctx_opts* opts, nlth_ctx** out)
     if (opts) {
         c->log_level = opts->log_level;
         if (opts->max_batch > 0) c->max_batch = opts->max_batch;
+        if (opts->paging_sets < 0 || opts->paging_sets > 2) throw Error{NLTH_EINVAL, "paging_sets must be 0, 1 or 2"};
+        c->paging_sets = opts->paging_sets == 1 ? 1 : 2;
     }
     c->budget.host_limit = (opts && opts->host_budget > 0) ? opts->host_budget : (int64_t)64 << 30;
     if (!c->host_only) {
@@ -1768,7 +1849,30 @@ int nlth_ens_create(nlth_ctx* ctx, const nlth_mesh* mesh, const nlth_problem* pr
     std::lock_guard<std::mutex> g(ctx->mu);
     NLTH_HIP(hipSetDevice(ctx->device));
     std::unique_ptr<nlth_ens> e(new nlth_ens());
-    e->create(ctx, mesh, P);
+    int64_t avail;
+    {
+        std::lock_guard<std::mutex> gb(ctx->budget.mu);
+        avail = ctx->budget.limit > 0 ? ctx->budget.limit - ctx->budget.used : INT64_MAX;
+    }
+    if (ctx->paging_sets == 2 && P.nm >= 2 && ensemble_bytes(*mesh, P, pad_members(P.nm), false) > avail) {
+        // the law state will not stay resident: two member sets, so that the
+        // transfers of one overlap the solve of the other
+        const int nA = (P.nm + 1) / 2;
+        const Problem PA = member_slice(P, 0, nA), PB = member_slice(P, nA, P.nm - nA);
+        e->force_paged = true;
+        e->reserve_extra = ensemble_bytes(*mesh, PB, pad_members(PB.nm), true);
+        e->create(ctx, mesh, PA);
+        std::unique_ptr<Ens> b(new Ens());
+        b->force_paged = true;
+        b->member_base = nA;
+        b->shared_copy_streams = true;
+        b->s_h2d = e->s_h2d;
+        NLTH_HIP(hipStreamCreateWithFlags(&b->own_s, hipStreamNonBlocking));
+        b->create(ctx, mesh, PB);
+        e->twin = std::move(b);
+    } else {
+        e->create(ctx, mesh, P);
+    }
     *out = e.release();
     API_END
 }
@@ -1779,13 +1883,15 @@ int nlth_ens_step(nlth_ens* ens, int32_t n_steps)
     if (!ens || n_steps < 0) throw Error{NLTH_EINVAL, "ens is NULL or n_steps < 0"};
     std::lock_guard<std::mutex> g(ens->ctx->mu);
     NLTH_HIP(hipSetDevice(ens->ctx->device));
-    ens->step_all(n_steps);
-    for (int m = 0; m < ens->nm; ++m)
-        if (ens->h_status[m] != 0) {
-            char buf[128];
-            snprintf(buf, sizeof buf, "member %d: CG did not converge within cg_maxit", m);
-            throw Error{NLTH_ENOCONV, buf};
-        }
+    if (ens->twin) ens->step_pair(n_steps);
+    else ens->step_all(n_steps);
+    for (const Ens* e = ens; e; e = e->twin.get())
+        for (int m = 0; m < e->nm; ++m)
+            if (e->h_status[m] != 0) {
+                char buf[128];
+                snprintf(buf, sizeof buf, "member %d: CG did not converge within cg_maxit", e->member_base + m);
+                throw Error{NLTH_ENOCONV, buf};
+            }
     API_END
 }
 
@@ -1796,6 +1902,15 @@ int nlth_ens_read(nlth_ens* ens, nlth_result* res)
     std::lock_guard<std::mutex> g(ens->ctx->mu);
     NLTH_HIP(hipSetDevice(ens->ctx->device));
     ens->read(res);
+    if (const Ens* b = ens->twin.get()) {  // the second set's members follow the first's
+        const long ns_steps = std::max(1, ens->P.n_steps), nr = std::max(1, ens->mesh->nrecv), m0 = b->member_base;
+        nlth_result rb{};
+        rb.vel = res->vel ? res->vel + m0 * ns_steps * nr * 3 : nullptr;
+        rb.iters = res->iters ? res->iters + m0 * ns_steps * 2 : nullptr;
+        rb.member_status = res->member_status ? res->member_status + m0 : nullptr;
+        rb.vmax = res->vmax ? res->vmax + m0 * nr : nullptr;
+        b->read(&rb);
+    }
     API_END
 }
 
@@ -1812,9 +1927,11 @@ int nlth_ens_destroy(nlth_ens* ens)
 int nlth_ens_set_profile(nlth_ens* ens, int32_t profile)
 {
     if (!ens) return NLTH_EINVAL;
-    ens->profile = profile != 0;
+    for (Ens* e = ens; e; e = e->twin.get()) e->profile = profile != 0;
     return NLTH_OK;
 }
+
+static void apply_tuning(Ens* ens, const nlth_tuning* t);
 
 int nlth_ens_set_tuning(nlth_ens* ens, const nlth_tuning* t)
 {
@@ -1843,6 +1960,13 @@ int nlth_ens_set_tuning(nlth_ens* ens, const nlth_tuning* t)
         (t->inner_maxit ? t->inner_maxit : ens->P.inner_maxit) > kChebMax)
         throw Error{NLTH_EINVAL, "the Chebyshev degree (inner_maxit) must be at most 64"};
     std::lock_guard<std::mutex> g(ens->ctx->mu);
+    for (Ens* e = ens; e; e = e->twin.get()) apply_tuning(e, t);
+    return NLTH_OK;
+    API_END
+}
+
+static void apply_tuning(Ens* ens, const nlth_tuning* t)
+{
     if (t->ebe_block) ens->ebe_block = t->ebe_block;
     if (t->check_every) ens->check_every = t->check_every;
     if (t->use_graph >= 0) ens->use_graph = t->use_graph != 0;
@@ -1864,17 +1988,16 @@ int nlth_ens_set_tuning(nlth_ens* ens, const nlth_tuning* t)
         if (gt) (void)hipGraphExecDestroy(gt);
         gt = nullptr;
     }
-    return NLTH_OK;
-    API_END
 }
 
 int nlth_ens_reset_stats(nlth_ens* ens)
 {
     if (!ens) return NLTH_EINVAL;
-    ens->pc_ebe64 = ens->pc_ebe32 = ens->pc_gather32 = ens->pc_vec = ens->pc_law = ens->pc_other = ens->pc_tail32 =
-        ProfCat{};
-    ens->ms_total = ens->ms_copy = 0;
-    ens->h2d_bytes = ens->d2h_bytes = 0;
+    for (Ens* e = ens; e; e = e->twin.get()) {
+        e->pc_ebe64 = e->pc_ebe32 = e->pc_gather32 = e->pc_vec = e->pc_law = e->pc_other = e->pc_tail32 = ProfCat{};
+        e->ms_total = e->ms_copy = 0;
+        e->h2d_bytes = e->d2h_bytes = 0;
+    }
     return NLTH_OK;
 }
 
@@ -1885,37 +2008,42 @@ int nlth_ens_stats(const nlth_ens* ens, nlth_stats* st)
     memset(st, 0, sizeof *st);
     st->steps_done = ens->steps_done;
     st->paged = ens->paged;
-    const int ns_steps = std::max(1, ens->P.n_steps);
-    std::vector<int> it((size_t)ens->nm * ns_steps * 2);
-    NLTH_HIP(hipMemcpy(it.data(), ens->iters_dev.p, it.size() * 4, hipMemcpyDeviceToHost));
-    for (size_t i = 0; i < it.size(); i += 2) {
-        st->outer_iters += it[i];
-        st->inner_iters += it[i + 1];
-    }
     st->ms_total = ens->ms_total;
-    st->ms_ebe64 = ens->pc_ebe64.ms;
-    st->ms_ebe32 = ens->pc_ebe32.ms;
-    st->ms_vec = ens->pc_vec.ms;
-    st->ms_law = ens->pc_law.ms;
-    st->ms_other = ens->pc_other.ms;
-    st->n_ebe64 = ens->pc_ebe64.n;
-    st->n_ebe32 = ens->pc_ebe32.n;
-    st->n_law = ens->pc_law.n;
-    st->elems_ebe64 = ens->pc_ebe64.elems;
-    st->elems_ebe32 = ens->pc_ebe32.elems;
-    st->h2d_bytes = ens->h2d_bytes;
-    st->d2h_bytes = ens->d2h_bytes;
-    st->ms_copy = ens->ms_copy;
-    st->n_members = ens->nm;
-    st->members_padded = ens->MB;
     st->n_colors = ens->mesh->ncolor;
-    st->device_bytes = ens->dev_bytes;
-    st->host_bytes = ens->host_bytes;
-    st->ms_gather32 = ens->pc_gather32.ms;
-    st->n_gather32 = ens->pc_gather32.n;
-    st->ms_tail32 = ens->pc_tail32.ms;
-    st->n_tail32 = ens->pc_tail32.n;
-    st->elems_tail32 = ens->pc_tail32.elems;
+    // counters and timers summed over the member sets; the budget figures are
+    // those after the last set was created
+    for (const Ens* e = ens; e; e = e->twin.get()) {
+        const int ns_steps = std::max(1, e->P.n_steps);
+        std::vector<int> it((size_t)e->nm * ns_steps * 2);
+        NLTH_HIP(hipMemcpy(it.data(), e->iters_dev.p, it.size() * 4, hipMemcpyDeviceToHost));
+        for (size_t i = 0; i < it.size(); i += 2) {
+            st->outer_iters += it[i];
+            st->inner_iters += it[i + 1];
+        }
+        st->ms_ebe64 += e->pc_ebe64.ms;
+        st->ms_ebe32 += e->pc_ebe32.ms;
+        st->ms_vec += e->pc_vec.ms;
+        st->ms_law += e->pc_law.ms;
+        st->ms_other += e->pc_other.ms;
+        st->n_ebe64 += e->pc_ebe64.n;
+        st->n_ebe32 += e->pc_ebe32.n;
+        st->n_law += e->pc_law.n;
+        st->elems_ebe64 += e->pc_ebe64.elems;
+        st->elems_ebe32 += e->pc_ebe32.elems;
+        st->h2d_bytes += e->h2d_bytes;
+        st->d2h_bytes += e->d2h_bytes;
+        st->ms_copy += e->ms_copy;
+        st->n_members += e->nm;
+        st->members_padded += e->MB;
+        st->device_bytes = e->dev_bytes;
+        st->host_bytes = e->host_bytes;
+        st->ms_gather32 += e->pc_gather32.ms;
+        st->n_gather32 += e->pc_gather32.n;
+        st->ms_tail32 += e->pc_tail32.ms;
+        st->n_tail32 += e->pc_tail32.n;
+        st->elems_tail32 += e->pc_tail32.elems;
+    }
+    st->member_sets = ens->twin ? 2 : 1;
     if (ens->cheb_bounds.p && ens->inner_method == 1) {
         std::vector<double> bd((size_t)2 * ens->MB);
         NLTH_HIP(hipMemcpy(bd.data(), ens->cheb_bounds.p, bd.size() * 8, hipMemcpyDeviceToHost));

@@ -123,9 +123,18 @@ __global__ void k_cast32(const double* a, float* b, long n)
     long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (i < n) b[i] = (float)a[i];
 }
+__global__ void k_copy_i32(const int* a, int* b, int n)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = a[i];
+}
 
 static inline unsigned nblocks(long n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
 
+void launch_copy_i32(hipStream_t s, const int* src, int* dst, int n)
+{
+    if (n > 0) hipLaunchKernelGGL(k_copy_i32, dim3(nblocks(n)), dim3(256), 0, s, src, dst, n);
+}
 void launch_fill(hipStream_t s, double* p, double v, long n)
 {
     if (n > 0) hipLaunchKernelGGL(k_fill, dim3(nblocks(n)), dim3(256), 0, s, p, v, n);

@@ -75,6 +75,8 @@ struct StepConst {
 
 // ---- kernel launchers (kernels.hip) ----
 void launch_fill(hipStream_t s, double* p, double v, long n);
+// n int32 from src to dst (either may be device-mapped host memory)
+void launch_copy_i32(hipStream_t s, const int* src, int* dst, int n);
 void launch_fill32(hipStream_t s, float* p, float v, long n);
 void launch_neg_copy(hipStream_t s, const double* a, double* b, long n);
 

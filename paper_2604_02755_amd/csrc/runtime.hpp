@@ -114,7 +114,7 @@ struct Ens {
         double *h, *mat;
         float *pinv, *ir, *iz, *ip, *w, *Ap, *f;
     } tb{};
-    int* h_tlist = nullptr;             // pinned staging of the list
+    int* h_tlist = nullptr;             // the list in the host mailbox
     void update_tail();                 // from h_flags (the outer-active members just read)
     void tail_iter();                   // one inner CG iteration on the compact rows
     double cheb_lo = 1.0, cheb_hi = 1.05;  // scales of the Lanczos extreme eigenvalues of a step's first inner CG
@@ -138,8 +138,8 @@ struct Ens {
     int chunk_elems = 0, nchunks = 0, ring = 3;
     std::vector<long> chunk_off;        // byte offset of each chunk in theta_host
     std::vector<int> chunk_e0, chunk_ec, chunk_ecp;
-    hipStream_t s_h2d = nullptr, s_d2h = nullptr;
-    std::vector<hipEvent_t> ev_h2d, ev_law, ev_d2h;
+    hipStream_t s_h2d = nullptr;        // transfers in; the write-backs run on the compute stream
+    std::vector<hipEvent_t> ev_h2d, ev_d2h;
     hipEvent_t ev_zc = nullptr;         // end of the last zero-copy law pass (the copies wait for it)
     std::vector<int> slot_chunk;        // chunk currently held by each slot (-1 none)
     std::vector<bool> prefetched;
@@ -157,11 +157,27 @@ struct Ens {
     int64_t dev_bytes = 0, host_bytes = 0;
     hipEvent_t ev_copy0 = nullptr, ev_copy1 = nullptr;
 
+    // A paged ensemble runs as two member sets, each with its own compute
+    // stream; the solve of one set runs while the law state of the other
+    // streams over the host link.  `twin` is the second set (members
+    // member_base.. of the caller's numbering); the transfer-in stream is shared.
+    std::unique_ptr<Ens> twin;
+    int member_base = 0;
+    bool force_paged = false;           // page the law state even if it fits (a set of a pair)
+    int64_t reserve_extra = 0;          // device bytes left for the second set when sizing the ring
+    hipStream_t own_s = nullptr;        // compute stream of a second set (else the context's)
+    bool shared_copy_streams = false;   // s_h2d belongs to the first set
+
     void create(Ctx* c, const Mesh* m, const Problem& p, int member_pad = 0);
     void destroy();
     ~Ens() { destroy(); }
     void step_all(int n_steps);        // lockstep members
+    void step_pair(int n_steps);       // two member sets, alternating solves and law phases
+    void step_begin();                  // member flags, then one step enqueued up to its receivers
+    void step_end();                    // wait for the step, read the member status
     void one_step();                    // uses h_member_step / h_stepping
+    void enqueue_step();                // one_step without the final wait
+    void read_status();                 // wait for the stream; h_status from the device
     void read(nlth_result* res) const;
     // pieces
     void ebe(OpMode mode, const double* x1, const double* x2, double* y, const int* active, const double* base,
@@ -190,7 +206,13 @@ struct Ens {
     int cluster_blocks = 3;             // co-resident cluster blocks per CU
     void fin(FinalizeStage st, int nd, int nblk, double tol2, int maxit);
     void apply_A64(const double* x, double* y, const int* act, int* nblk = nullptr);
-    int* h_flags = nullptr;             // pinned copy of per-member flags
+    // Host mailbox: pinned, device-mapped and coherent, written and read by
+    // small copy kernels on the compute stream (not by the copy engines, which
+    // a paged member set keeps busy with large transfers): per-member flags,
+    // status, step index and stepping flag, then the tail list [1 + MB].
+    int* h_mail = nullptr;
+    int* d_mail = nullptr;              // device address of h_mail
+    int* h_flags = nullptr;             // = h_mail: per-member flags just read
     hipEvent_t ev();
     void tstart(hipEvent_t& e0);
     void tstop(hipEvent_t e0, ProfCat* cat, int64_t elems);
@@ -209,6 +231,7 @@ struct Ctx {
     bool own_stream = false;
     Budget budget;
     std::mutex mu;  // serialises API calls on the context
+    int paging_sets = 2;  // member sets of a paged ensemble (1 or 2)
     std::string last_error;
     int log_level = 0;
     int max_batch = 64;

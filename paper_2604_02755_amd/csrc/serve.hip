@@ -244,6 +244,7 @@ void Ctx::worker_loop()
                             std::unique_ptr<Ens> e(new Ens());
                             e->create(this, r->mesh, tp, pad_members(slots));
                             if (e->paged) throw Error{NLTH_ENOMEM_DEVICE, "serving batches keep their state resident"};
+                            e->predictor = 2;  // fewer iterations per step; same results within tol
                             nb->ens = std::move(e);
                             nb->budget = &budget;
                             nb->host_bytes = hb;

@@ -42,7 +42,7 @@ _ip = C.POINTER(C.c_int32)
 
 class nlth_ctx_opts(C.Structure):
     _fields_ = [("hbm_budget", C.c_int64), ("host_budget", C.c_int64), ("stream", C.c_void_p),
-                ("log_level", C.c_int32), ("max_batch", C.c_int32)]
+                ("log_level", C.c_int32), ("max_batch", C.c_int32), ("paging_sets", C.c_int32)]
 
 
 class nlth_mesh_desc(C.Structure):
@@ -89,7 +89,8 @@ class nlth_stats(C.Structure):
                 ("n_members", C.c_int32), ("members_padded", C.c_int32), ("n_colors", C.c_int32),
                 ("device_bytes", C.c_int64), ("host_bytes", C.c_int64), ("ms_gather32", C.c_double),
                 ("n_gather32", C.c_int64), ("cheb_lo_min", C.c_double), ("cheb_hi_max", C.c_double),
-                ("ms_tail32", C.c_double), ("n_tail32", C.c_int64), ("elems_tail32", C.c_int64)]
+                ("ms_tail32", C.c_double), ("n_tail32", C.c_int64), ("elems_tail32", C.c_int64),
+                ("member_sets", C.c_int32)]
 
 
 EXPORTS = {
@@ -184,8 +185,9 @@ def nlth_version() -> int:
 
 
 def nlth_ctx_create(device: int = 0, hbm_budget: int = 0, host_budget: int = 0, stream=None,
-                    log_level: int = 0, max_batch: int = 0):
-    opts = nlth_ctx_opts(int(hbm_budget), int(host_budget), stream, int(log_level), int(max_batch))
+                    log_level: int = 0, max_batch: int = 0, paging_sets: int = 0):
+    opts = nlth_ctx_opts(int(hbm_budget), int(host_budget), stream, int(log_level), int(max_batch),
+                         int(paging_sets))
     h = C.c_void_p()
     _check(lib().nlth_ctx_create(int(device), C.byref(opts), C.byref(h)))
     return h
@@ -384,10 +386,10 @@ class Ensemble:
 
 
 class Context:
-    def __init__(self, device=0, hbm_budget=0, host_budget=0, use_torch_stream=True, max_batch=0):
+    def __init__(self, device=0, hbm_budget=0, host_budget=0, use_torch_stream=True, max_batch=0, paging_sets=0):
         stream = torch_stream() if (use_torch_stream and device != NLTH_DEVICE_NONE) else None
         self._stream = stream
-        self.h = nlth_ctx_create(device, hbm_budget, host_budget, stream, 0, max_batch)
+        self.h = nlth_ctx_create(device, hbm_budget, host_budget, stream, 0, max_batch, paging_sets)
         self._meshes = []
 
     def mesh(self, mesh):
@@ -397,6 +399,18 @@ class Context:
 
     def solve(self, mesh_h, mesh, prob, **kw):
         return nlth_solve(self.h, mesh_h, mesh, prob, **kw)
+
+    def solve_as_served(self, mesh_h, mesh, prob):
+        """The problem solved alone with the policy of the serving batches (the
+        quadratic-extrapolation initial guess): a served request's results
+        equal these up to the order of reductions."""
+        ens = self.ensemble(mesh_h, mesh, prob)
+        try:
+            ens.set_tuning(predictor=2)
+            ens.step(prob.n_steps)
+            return ens.read()
+        finally:
+            ens.close()
 
     def ensemble(self, mesh_h, mesh, prob, **kw):
         return Ensemble(self.h, mesh_h, mesh, prob, **kw)

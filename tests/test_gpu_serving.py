@@ -1,6 +1,6 @@
 """Continuous-batching request loop: requests of mixed mesh sizes admitted into
 member slots while others run; each result must equal the same problem solved
-alone (FP64 path: 1e-12 relative, i.e. reduction-order level; mixed path:
+alone with the batches' policy (FP64 path: 1e-12 relative, i.e. reduction-order level; mixed path:
 1e-6, the mixed-precision bar) and the oracle (1e-9 for FP64, 1e-6 for mixed;
 tolerance 1e-12 on both sides).  Cancellation and refusals by the device and
 host budgets are checked from the host."""
@@ -43,7 +43,7 @@ def test_results_alone_in_the_mix_and_oracle(nlth_mod, oracle_lib, precision, to
         for t, out, mesh, prob, dims in reqs:
             rc = ctx.wait(t, 120.0)
             assert rc == 0, rc
-            alone = ctx.solve(meshes[dims][0], mesh, prob)
+            alone = ctx.solve_as_served(meshes[dims][0], mesh, prob)
             err = np.linalg.norm(out["vel"] - alone["vel"]) / np.linalg.norm(alone["vel"])
             ref = oracle_lib.run(mesh, prob)
             err_or = oracle_lib.rel_l2(out["vel"][0], ref["vel"])
