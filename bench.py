@@ -560,9 +560,10 @@ def main():
                                                 pre_steps=args.pre_steps + n_tune - n_tune64)
         v64 = args.members * ndof * args.steps / el64
         it64 = float(out64["iters"][:, sl, 0].mean())
-        # lanes the lockstep batch keeps busy: member iterations over the
-        # iterations the batch runs (whole chunks of check_every up to the
-        # slowest member of each step) times the members
+        # spread of the members' iteration counts: member iterations over the
+        # members times the iterations of each step's slowest member (whole
+        # chunks of check_every), the share of lanes a lockstep batch without
+        # the compact convergence tail keeps busy
         it_t = out64["iters"][:, sl, 0].astype(np.int64)
         ce = (tuned64 or tuned or {}).get("check_every", 8) or 8
         lane_use = float(it_t.sum() / (args.members * (ce * np.ceil(it_t.max(axis=0) / ce)).sum()))
@@ -570,7 +571,7 @@ def main():
                 "iters_per_member_step": it64,
                 "tuning": ({k: tuned64.get(k) for k in ("predictor", "ebe_block", "check_every", "cluster_blocks")
                             if k in tuned64} if tuned64 else None),
-                "iters_min_max": [int(it_t.min()), int(it_t.max())], "lane_use": round(lane_use, 4),
+                "iters_min_max": [int(it_t.min()), int(it_t.max())], "lockstep_lane_use": round(lane_use, 4),
                 "step_roofline": step_roofline(v64, it64, 0.0, prob.n_springs, ip_per_dof),
                 "step_ms": [round(x, 1) for x in st64["step_ms"]]}
         log(f"fp64: {el64/args.steps*1e3:.1f} ms/step, {v64:.3e} DOF-steps/s")

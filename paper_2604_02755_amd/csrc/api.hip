@@ -832,7 +832,7 @@ void Ens::create(Ctx* c, const Mesh* m, const Problem& prob, int member_pad)
     if (P.precision == NLTH_MIXED && P.inner_dtype == NLTH_INNER_BF16) D16.alloc(bg, (size_t)ne_pad * 4 * 11 * MB * 4);
     if (P.precision == NLTH_MIXED && P.inner_dtype == NLTH_INNER_BF16_MEAN) D16.alloc(bg, (size_t)ne_pad * 11 * MB * 4);
     d16_mean = P.inner_dtype == NLTH_INNER_BF16_MEAN;
-    tail_max = P.precision == NLTH_MIXED && MB >= 64 && MB <= 256 && d16_mean ? 32 : 0;
+    tail_max = MB >= 64 && MB <= 256 && (P.precision == NLTH_FP64 || d16_mean) ? 32 : 0;
     h.alloc(bg, (size_t)m->ne * MB * 8);
     // operator path: element clusters (64-member groups) when MB is a multiple
     // of 64, element outputs below that, colours above 256 member slots (the
@@ -969,6 +969,10 @@ void Ens::destroy()
     if (g_pcg) (void)hipGraphExecDestroy(g_pcg);
     if (g_cheb) (void)hipGraphExecDestroy(g_cheb);
     for (auto& gt : g_inner_tail) {
+        if (gt) (void)hipGraphExecDestroy(gt);
+        gt = nullptr;
+    }
+    for (auto& gt : g_pcg_tail) {
         if (gt) (void)hipGraphExecDestroy(gt);
         gt = nullptr;
     }
@@ -1144,9 +1148,89 @@ void Ens::solve_pcg()
     launch_p_update<double>(s, n, MB, nm, z.as<double>(), p.as<double>(), nullptr, nullptr, nullptr);
     if (!read_any_active(act)) return;
     for (;;) {
+        if (!tail64_g) enter_tail64();  // with few members left: compact rows
         run_iters(1, check_every);
         if (!read_any_active(act)) break;
     }
+    if (tail64_g) leave_tail64();
+}
+
+// With at most tail_max of the members just read (h_flags) still iterating,
+// their PCG state and operator data go to compact rows of 16 or 32 lanes for
+// the rest of the step's solve.
+bool Ens::enter_tail64()
+{
+    if (tail_max <= 0 || P.precision != NLTH_FP64 || MB < 64 || MB > 256) return false;
+    int na = 0;
+    for (int m = 0; m < nm; ++m) na += h_flags[m] != 0;
+    if (na == 0 || na > tail_max) return false;
+    if (!tail64_mem.p) {
+        // 32 lanes: D per point (elements padded to blocks of 4), h, material,
+        // inverse blocks, five PCG vectors, element outputs
+        const size_t ne4 = ((size_t)mesh->ne + 3) / 4 * 4, nn = mesh->nn, L = 32;
+        const size_t nv = 3 * nn * L * 8;
+        const size_t sz[10] = {ne4 * 84 * L * 8, (size_t)mesh->ne * L * 8, (size_t)P.nl * MAT_N * L * 8,
+                               nn * 6 * L * 8, nv, nv, nv, nv, nv, (size_t)mesh->ne * 30 * L * 8};
+        size_t off[10], tot = 0;
+        for (int i = 0; i < 10; ++i) {
+            off[i] = tot;
+            tot += (sz[i] + 255) / 256 * 256;
+        }
+        try {
+            tail64_mem.alloc(&ctx->budget, tot);
+            if (!tlist.p) tlist.alloc(&ctx->budget, (size_t)(1 + MB) * 4);
+        } catch (const Error&) {  // no room: keep the full operator
+            tail64_mem.release();
+            tail_max = 0;
+            return false;
+        }
+        char* b = (char*)tail64_mem.p;
+        double** dst[10] = {&tc.D, &tc.h, &tc.mat, &tc.pinv, &tc.x, &tc.r, &tc.z, &tc.p, &tc.Ap, &tc.f};
+        for (int i = 0; i < 10; ++i) *dst[i] = (double*)(b + off[i]);
+    }
+    h_tlist[0] = na;
+    int k = 1;
+    for (int m = 0; m < nm; ++m)
+        if (h_flags[m]) h_tlist[k++] = m;
+    launch_copy_i32(s, d_mail + 4 * MB, tlist.as<int>(), 1 + na);
+    tail64_g = na <= 16 ? 16 : 32;
+    const int* tl = tlist.as<int>();
+    launch_tail_pack64(s, mesh->dev(), MB, tail64_g, P.nl, tl, D64.as<double>(), h.as<double>(), mat.as<double>(),
+                       pinv.as<double>(), tc.D, tc.h, tc.mat, tc.pinv);
+    launch_tail_rows64(s, ndof, MB, tail64_g, tl, du.as<double>(), tc.x, false);
+    launch_tail_rows64(s, ndof, MB, tail64_g, tl, r.as<double>(), tc.r, false);
+    launch_tail_rows64(s, ndof, MB, tail64_g, tl, z.as<double>(), tc.z, false);
+    launch_tail_rows64(s, ndof, MB, tail64_g, tl, p.as<double>(), tc.p, false);
+    return true;
+}
+
+void Ens::leave_tail64()
+{
+    launch_tail_rows64(s, ndof, MB, tail64_g, tlist.as<int>(), tc.x, du.as<double>(), true);
+    tail64_g = 0;
+}
+
+// one FP64 PCG iteration of the listed members on the compact rows, with the
+// stage logic of the full path
+void Ens::tail64_iter()
+{
+    const DevMesh dm = mesh->dev();
+    const int* tl = tlist.as<int>();
+    const int* act = cs.active;
+    const double tol2 = P.cg_tol * P.cg_tol;
+    double* pd = partial.as<double>();
+    int nblk;
+    hipEvent_t t0;
+    tstart(t0);
+    launch_ebe64_tail(s, dm, tail64_g, tl, tc.D, tc.h, tc.mat, sc, tc.p, tc.f);
+    launch_gather_tail<double>(s, dm, MB, nm, tail64_g, tl, tc.f, tc.Ap, act, tc.p, pd, &nblk);
+    launch_dashpot_tail<double>(s, dm, MB, nm, tail64_g, tl, tc.mat, 2.0 / P.dt, tc.p, tc.Ap, act, pd, &nblk);
+    tstop(t0, &pc_tail32, (int64_t)mesh->ne * h_tlist[0]);
+    fin(FIN_ALPHA, 1, nblk, tol2, P.cg_maxit);
+    launch_tail_pcg_update(s, mesh->nn, MB, nm, tail64_g, tl, tc.x, tc.r, tc.z, tc.p, tc.Ap, tc.pinv, cs.alpha, act,
+                           pd, &nblk);
+    fin(FIN_BETA, 2, nblk, tol2, P.cg_maxit);
+    launch_tail_p_update(s, ndof, nm, tail64_g, tl, tc.z, tc.p, cs.beta, act);
 }
 
 // inner FP32 block-Jacobi PCG: z ~ A^-1 r to inner_tol relative (preconditioner)
@@ -1376,6 +1460,10 @@ void Ens::inner_iter()
 // one FP64 block-Jacobi PCG iteration
 void Ens::pcg_iter()
 {
+    if (tail64_g) {
+        tail64_iter();
+        return;
+    }
     const long n = ndof;
     int nblk;
     double* x = du.as<double>();
@@ -1399,7 +1487,8 @@ void Ens::run_iters(int kind, int k)
         for (int i = 0; i < k; ++i) kind == 0 ? inner_iter() : pcg_iter();
         return;
     }
-    hipGraphExec_t& ge = kind == 1 ? g_pcg : (tail_g ? g_inner_tail[tail_g == 16 ? 0 : 1] : g_inner);
+    hipGraphExec_t& ge = kind == 1 ? (tail64_g ? g_pcg_tail[tail64_g == 16 ? 0 : 1] : g_pcg)
+                                   : (tail_g ? g_inner_tail[tail_g == 16 ? 0 : 1] : g_inner);
     if (!ge) {
         hipGraph_t g = nullptr;
         NLTH_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -1951,9 +2040,10 @@ int nlth_ens_set_tuning(nlth_ens* ens, const nlth_tuning* t)
     if (t->zero_copy < -1 || t->zero_copy > 1) throw Error{NLTH_EINVAL, "zero_copy must be -1, 0 or 1"};
     if (t->tail_members != -1 && t->tail_members != 0 && t->tail_members != 16 && t->tail_members != 32)
         throw Error{NLTH_EINVAL, "tail_members must be -1, 0, 16 or 32"};
-    if (t->tail_members > 0 && (ens->MB < 64 || ens->MB > 256 || ens->P.precision != NLTH_MIXED || !ens->d16_mean))
-        throw Error{NLTH_EINVAL, "tail_members needs a mixed-precision ensemble of 64..256 member slots with the "
-                                 "element-mean inner D"};
+    if (t->tail_members > 0 &&
+        (ens->MB < 64 || ens->MB > 256 || (ens->P.precision == NLTH_MIXED && !ens->d16_mean)))
+        throw Error{NLTH_EINVAL, "tail_members needs an ensemble of 64..256 member slots (FP64, or mixed with the "
+                                 "element-mean inner D)"};
     if (t->zero_copy == 1 && !ens->paged) throw Error{NLTH_EINVAL, "zero_copy needs an ensemble whose law state is paged"};
     if (t->predictor < -1 || t->predictor > 2) throw Error{NLTH_EINVAL, "predictor must be -1, 0, 1 or 2"};
     if ((t->inner_method == 1 || (t->inner_method == -1 && ens->inner_method == 1)) &&
@@ -1985,6 +2075,10 @@ static void apply_tuning(Ens* ens, const nlth_tuning* t)
     if (ens->g_cheb) (void)hipGraphExecDestroy(ens->g_cheb);
     ens->g_inner = ens->g_pcg = ens->g_cheb = nullptr;
     for (auto& gt : ens->g_inner_tail) {
+        if (gt) (void)hipGraphExecDestroy(gt);
+        gt = nullptr;
+    }
+    for (auto& gt : ens->g_pcg_tail) {
         if (gt) (void)hipGraphExecDestroy(gt);
         gt = nullptr;
     }

@@ -771,14 +771,16 @@ void launch_ebe32(hipStream_t s, const DevMesh& M, int MB, int nm, int e0, int e
 }
 
 // ---------------------------------------------------------------------------
-// convergence tail: once at most G (16 or 32) members are still iterating in
-// the outer CG, their inner solve runs on compact copies, lane k of a row being
-// member tl[1 + k] (tl[0] = the count): the member-innermost rows of the full
-// arrays would otherwise be fetched whole for a few members each.  D, h, the
-// material rows and the block-Jacobi inverse are packed once per outer
-// iteration; the operator writes compact element outputs, summed per node into
-// a compact result.  Partial sums keep the full [block][MB] layout (zero for
-// members not listed), so the per-member stage logic is the same.
+// convergence tail: once at most G (16 or 32) members are still iterating,
+// their CG runs on compact copies, lane k of a row being member tl[1 + k]
+// (tl[0] = the count): the member-innermost rows of the full arrays would
+// otherwise be fetched whole for a few members each.  The mixed path packs the
+// element-mean D, h, the material rows and the FP32 block-Jacobi inverse once
+// per outer iteration for its inner CG; the FP64 PCG packs the FP64 D per
+// point, h, the material rows, its inverse and the CG vectors once per step.
+// The operator writes compact element outputs, summed per node into a compact
+// result.  Partial sums keep the full [block][MB] layout (zero for members not
+// listed), so the per-member stage logic is the same.
 // ---------------------------------------------------------------------------
 
 // rows of a member-innermost array, listed members only: compact row rc of G
@@ -830,22 +832,38 @@ void launch_tail_unpack(hipStream_t s, long nrows, int MB, int G, const int* tl,
     tail_rows<float>(s, nrows, MB, G, 1, 1, tl, c, full, true);
 }
 
-// inner operator A on the compact rows: lane (element, k), element-mean D;
-// outputs f[(e * 30 + 3n + c) * G + k]
-template <int G>
-__global__ __launch_bounds__(256) void k_ebe_tail(DevMesh M, const int* __restrict__ tl,
-                                                 const uint32_t* __restrict__ cD, const double* __restrict__ ch,
-                                                 const double* __restrict__ cmat, StepConst sc,
-                                                 const float* __restrict__ x, float* __restrict__ f)
+void launch_tail_pack64(hipStream_t s, const DevMesh& M, int MB, int G, int n_layers, const int* tl,
+                        const double* D64, const double* h, const double* mat, const double* pinv, double* cD,
+                        double* ch, double* cmat, double* cpinv)
+{
+    tail_rows<double>(s, (long)M.ne * 84, MB, G, 84, 64 / G, tl, D64, cD, false);
+    if (h) tail_rows<double>(s, M.ne, MB, G, 1, 1, tl, h, ch, false);
+    tail_rows<double>(s, (long)n_layers * MAT_N, MB, G, 1, 1, tl, mat, cmat, false);
+    tail_rows<double>(s, (long)M.nn * 6, MB, G, 1, 1, tl, pinv, cpinv, false);
+}
+
+void launch_tail_rows64(hipStream_t s, long nrows, int MB, int G, const int* tl, const double* src, double* dst,
+                        bool unpack)
+{
+    tail_rows<double>(s, nrows, MB, G, 1, 1, tl, src, dst, unpack);
+}
+
+// operator A on the compact rows: lane (element, k); the mixed path's inner
+// operator (FP32, element-mean bfloat16 D) or the FP64 operator (D per
+// point); outputs f[(e * 30 + 3n + c) * G + k]
+template <typename T, int DK, int G>
+__global__ __launch_bounds__(256) void k_ebe_tail(DevMesh M, const int* __restrict__ tl, const void* __restrict__ cD,
+                                                 const double* __restrict__ ch, const double* __restrict__ cmat,
+                                                 StepConst sc, const T* __restrict__ x, T* __restrict__ f)
 {
     const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
     const int k = (int)(t % G);
     const long e = t / G;
     if (e >= M.ne || k >= min(tl[0], G)) return;
-    float fe[10][3];
+    T fe[10][3];
     size_t nbase[10];
-    ebe_element<float, 4, OP_A>(M, G, k, e, cD, ch, cmat, sc, x, nullptr, fe, nbase);
-    float* fb = f + (size_t)e * 30 * G + k;
+    ebe_element<T, DK, OP_A>(M, G, k, e, cD, ch, cmat, sc, x, nullptr, fe, nbase);
+    T* fb = f + (size_t)e * 30 * G + k;
 #pragma unroll
     for (int n = 0; n < 10; ++n)
 #pragma unroll
@@ -857,17 +875,32 @@ void launch_ebe32_tail(hipStream_t s, const DevMesh& M, int G, const int* tl, co
 {
     const long n = (long)M.ne * G;
     if (n <= 0) return;
-    if (G == 16) hipLaunchKernelGGL((k_ebe_tail<16>), dim3(nblocks(n)), dim3(256), 0, s, M, tl, cD, ch, cmat, sc, x, f);
-    else hipLaunchKernelGGL((k_ebe_tail<32>), dim3(nblocks(n)), dim3(256), 0, s, M, tl, cD, ch, cmat, sc, x, f);
+    if (G == 16)
+        hipLaunchKernelGGL((k_ebe_tail<float, 4, 16>), dim3(nblocks(n)), dim3(256), 0, s, M, tl, cD, ch, cmat, sc, x, f);
+    else
+        hipLaunchKernelGGL((k_ebe_tail<float, 4, 32>), dim3(nblocks(n)), dim3(256), 0, s, M, tl, cD, ch, cmat, sc, x, f);
+}
+
+void launch_ebe64_tail(hipStream_t s, const DevMesh& M, int G, const int* tl, const double* cD, const double* ch,
+                       const double* cmat, StepConst sc, const double* x, double* f)
+{
+    const long n = (long)M.ne * G;
+    if (n <= 0) return;
+    if (G == 16)
+        hipLaunchKernelGGL((k_ebe_tail<double, 0, 16>), dim3(nblocks(n)), dim3(256), 0, s, M, tl, cD, ch, cmat, sc, x,
+                           f);
+    else
+        hipLaunchKernelGGL((k_ebe_tail<double, 0, 32>), dim3(nblocks(n)), dim3(256), 0, s, M, tl, cD, ch, cmat, sc, x,
+                           f);
 }
 
 // node sums of the compact element outputs (incidences in ascending order)
 // into the compact y of the listed, active members; with partial, the x . y
 // partials of the block's nodes
-template <int G>
+template <typename T, int G>
 __global__ __launch_bounds__(256) void k_gather_tail(DevMesh M, int MB, int nm, const int* __restrict__ tl,
-                                                    const float* __restrict__ fc, float* __restrict__ y,
-                                                    const int* __restrict__ active, const float* __restrict__ x,
+                                                    const T* __restrict__ fc, T* __restrict__ y,
+                                                    const int* __restrict__ active, const T* __restrict__ x,
                                                     double* __restrict__ partial)
 {
     constexpr int NPB = 256 / G;  // nodes per block pass
@@ -879,12 +912,12 @@ __global__ __launch_bounds__(256) void k_gather_tail(DevMesh M, int MB, int nm, 
     const long n0 = (long)blockIdx.x * per, n1 = n0 + per < M.nn ? n0 + per : M.nn;
     if (act) {
         for (long nd = n0 + slot; nd < n1; nd += NPB) {
-            float a0 = 0, a1 = 0, a2 = 0;
+            T a0 = 0, a1 = 0, a2 = 0;
             const int q1 = M.inc_ptr[nd + 1];
 #pragma unroll 4
             for (int q = M.inc_ptr[nd]; q < q1; ++q) {
                 // incidence e * 10 + local node: its output rows start at 3 * incidence
-                const float* fb = fc + (size_t)3 * M.inc[q] * G + k;
+                const T* fb = fc + (size_t)3 * M.inc[q] * G + k;
                 a0 += fb[0];
                 a1 += fb[G];
                 a2 += fb[2 * G];
@@ -903,16 +936,21 @@ __global__ __launch_bounds__(256) void k_gather_tail(DevMesh M, int MB, int nm, 
     }
 }
 
-void launch_gather_tail(hipStream_t s, const DevMesh& M, int MB, int nm, int G, const int* tl, const float* fc,
-                        float* y, const int* active, const float* x, double* partial, int* nblk)
+template <typename T>
+void launch_gather_tail(hipStream_t s, const DevMesh& M, int MB, int nm, int G, const int* tl, const T* fc, T* y,
+                        const int* active, const T* x, double* partial, int* nblk)
 {
     const int g = gather_blocks(M.nn, G, partial ? kGatherBlocks : (1 << 24));
     if (partial) *nblk = g;
     if (G == 16)
-        hipLaunchKernelGGL((k_gather_tail<16>), dim3(g), dim3(256), 0, s, M, MB, nm, tl, fc, y, active, x, partial);
+        hipLaunchKernelGGL((k_gather_tail<T, 16>), dim3(g), dim3(256), 0, s, M, MB, nm, tl, fc, y, active, x, partial);
     else
-        hipLaunchKernelGGL((k_gather_tail<32>), dim3(g), dim3(256), 0, s, M, MB, nm, tl, fc, y, active, x, partial);
+        hipLaunchKernelGGL((k_gather_tail<T, 32>), dim3(g), dim3(256), 0, s, M, MB, nm, tl, fc, y, active, x, partial);
 }
+template void launch_gather_tail<float>(hipStream_t, const DevMesh&, int, int, int, const int*, const float*, float*,
+                                        const int*, const float*, double*, int*);
+template void launch_gather_tail<double>(hipStream_t, const DevMesh&, int, int, int, const int*, const double*,
+                                         double*, const int*, const double*, double*, int*);
 
 template <typename T>
 void launch_ebe(hipStream_t s, OpMode mode, const DevMesh& M, int MB, int nm, int e0, int e1, const T* D,
@@ -1045,10 +1083,10 @@ template void launch_dashpot<float>(hipStream_t, const DevMesh&, int, int, const
 // dashpot of the compact rows (material rows packed, lane k = member tl[1 + k]):
 // y += coef C x at the boundary nodes for the listed, active members; partials
 // of x . (C x) appended after the boff blocks already written
-template <int G>
+template <typename T, int G>
 __global__ __launch_bounds__(256) void k_dashpot_tail(DevMesh M, int MB, int nm, const int* __restrict__ tl,
                                                      const double* __restrict__ cmat, double coef,
-                                                     const float* __restrict__ x, float* __restrict__ y,
+                                                     const T* __restrict__ x, T* __restrict__ y,
                                                      const int* __restrict__ active, double* __restrict__ partial,
                                                      int boff, int nblk)
 {
@@ -1061,11 +1099,11 @@ __global__ __launch_bounds__(256) void k_dashpot_tail(DevMesh M, int MB, int nm,
         for (long i = (long)blockIdx.x * NPB + t / G; i < M.nbn; i += (long)gridDim.x * NPB) {
             const int node = M.bn_node[i];
             double acc[3] = {0, 0, 0};
-            dashpot_at<float>(M, G, k, (int)i, cmat, coef, x, nullptr, acc);
+            dashpot_at<T>(M, G, k, (int)i, cmat, coef, x, nullptr, acc);
             for (int c = 0; c < 3; ++c) {
                 const size_t yi = ((size_t)node * 3 + c) * G + k;
-                y[yi] += (float)acc[c];
-                if (partial) dot += (double)x[yi] * (double)(float)acc[c];
+                y[yi] += (T)acc[c];
+                if (partial) dot += (double)x[yi] * (double)(T)acc[c];
             }
         }
     }
@@ -1075,8 +1113,9 @@ __global__ __launch_bounds__(256) void k_dashpot_tail(DevMesh M, int MB, int nm,
     }
 }
 
+template <typename T>
 void launch_dashpot_tail(hipStream_t s, const DevMesh& M, int MB, int nm, int G, const int* tl, const double* cmat,
-                         float coef, const float* x, float* y, const int* active, double* partial, int* nblk)
+                         T coef, const T* x, T* y, const int* active, double* partial, int* nblk)
 {
     if (M.nbn <= 0) return;
     const long rpb = 256 / G;
@@ -1086,13 +1125,17 @@ void launch_dashpot_tail(hipStream_t s, const DevMesh& M, int MB, int nm, int G,
     // the partials of one part: rows boff .. boff + g of the gather's layout,
     // so the row count passed as nblk is irrelevant for part 0
     if (G == 16)
-        hipLaunchKernelGGL((k_dashpot_tail<16>), dim3(g), dim3(256), 0, s, M, MB, nm, tl, cmat, (double)coef, x, y,
+        hipLaunchKernelGGL((k_dashpot_tail<T, 16>), dim3(g), dim3(256), 0, s, M, MB, nm, tl, cmat, (double)coef, x, y,
                            active, partial, boff, 0);
     else
-        hipLaunchKernelGGL((k_dashpot_tail<32>), dim3(g), dim3(256), 0, s, M, MB, nm, tl, cmat, (double)coef, x, y,
+        hipLaunchKernelGGL((k_dashpot_tail<T, 32>), dim3(g), dim3(256), 0, s, M, MB, nm, tl, cmat, (double)coef, x, y,
                            active, partial, boff, 0);
     if (partial) *nblk += (int)g;
 }
+template void launch_dashpot_tail<float>(hipStream_t, const DevMesh&, int, int, int, const int*, const double*, float,
+                                         const float*, float*, const int*, double*, int*);
+template void launch_dashpot_tail<double>(hipStream_t, const DevMesh&, int, int, int, const int*, const double*,
+                                          double, const double*, double*, const int*, double*, int*);
 
 // dashpot rows of the boundary nodes for the fused Chebyshev gather:
 // qb[(i * 3 + c) * MB + m] = (dashpot x)(boundary node i), active members only

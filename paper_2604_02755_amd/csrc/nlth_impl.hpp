@@ -126,19 +126,36 @@ void launch_zero_member(hipStream_t s, double* p, long rows, int MB, int m);
 void set_ebe_block(int bs);
 // blocks per CU of the cluster launches on this host thread
 void set_cluster_blocks(int b);
-// convergence tail: the inner solve of at most G (16 or 32) listed members on
-// compact rows (lane k = member tl[1 + k], tl[0] = the count); partial sums in
-// the full [block][MB] layout
+// convergence tail: the CG of at most G (16 or 32) listed members on compact
+// rows (lane k = member tl[1 + k], tl[0] = the count); partial sums in the
+// full [block][MB] layout.  Mixed path: its inner FP32 solve; FP64 path: PCG.
 void launch_tail_pack(hipStream_t s, const DevMesh& M, int MB, int G, int n_layers, const int* tl,
                       const uint32_t* D16, const double* h, const double* mat, const float* pinv32, uint32_t* cD,
                       double* ch, double* cmat, float* cpinv);
 void launch_tail_unpack(hipStream_t s, long nrows, int MB, int G, const int* tl, const float* c, float* full);
+void launch_tail_pack64(hipStream_t s, const DevMesh& M, int MB, int G, int n_layers, const int* tl,
+                        const double* D64, const double* h, const double* mat, const double* pinv, double* cD,
+                        double* ch, double* cmat, double* cpinv);
+// nrows member-innermost FP64 rows, full <-> compact
+void launch_tail_rows64(hipStream_t s, long nrows, int MB, int G, const int* tl, const double* src, double* dst,
+                        bool unpack);
 void launch_ebe32_tail(hipStream_t s, const DevMesh& M, int G, const int* tl, const uint32_t* cD, const double* ch,
                        const double* cmat, StepConst sc, const float* x, float* f);
-void launch_gather_tail(hipStream_t s, const DevMesh& M, int MB, int nm, int G, const int* tl, const float* fc,
-                        float* y, const int* active, const float* x, double* partial, int* nblk);
+void launch_ebe64_tail(hipStream_t s, const DevMesh& M, int G, const int* tl, const double* cD, const double* ch,
+                       const double* cmat, StepConst sc, const double* x, double* f);
+template <typename T>
+void launch_gather_tail(hipStream_t s, const DevMesh& M, int MB, int nm, int G, const int* tl, const T* fc, T* y,
+                        const int* active, const T* x, double* partial, int* nblk);
+template <typename T>
 void launch_dashpot_tail(hipStream_t s, const DevMesh& M, int MB, int nm, int G, const int* tl, const double* cmat,
-                         float coef, const float* x, float* y, const int* active, double* partial, int* nblk);
+                         T coef, const T* x, T* y, const int* active, double* partial, int* nblk);
+// FP64 PCG on the compact rows: x += a p, r -= a Ap, z = P r with partials
+// (r.r, r.z); then p = z + beta p
+void launch_tail_pcg_update(hipStream_t s, int nn, int MB, int nm, int G, const int* tl, double* cx, double* cr,
+                            double* cz, const double* cp, const double* cAp, const double* cpinv,
+                            const double* alpha, const int* active, double* partial, int* nblk);
+void launch_tail_p_update(hipStream_t s, long nrows, int nm, int G, const int* tl, const double* cz, double* cp,
+                          const double* beta, const int* active);
 void launch_tail_start(hipStream_t s, int nn, int MB, int nm, int G, const int* tl, const double* r,
                        const float* cpinv, float* cir, float* ciz, float* cip, const int* active, double* partial,
                        int* nblk);

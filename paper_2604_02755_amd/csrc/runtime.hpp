@@ -115,6 +115,16 @@ struct Ens {
         float *pinv, *ir, *iz, *ip, *w, *Ap, *f;
     } tb{};
     int* h_tlist = nullptr;             // the list in the host mailbox
+    // the same for the plain FP64 PCG: once at most tail_max members are still
+    // iterating, their PCG moves to compact rows for the rest of the step
+    int tail64_g = 0;
+    DevBuf tail64_mem;
+    struct {
+        double *D, *h, *mat, *pinv, *x, *r, *z, *p, *Ap, *f;
+    } tc{};
+    bool enter_tail64();                // from h_flags: pack the listed members' rows
+    void leave_tail64();                // their increment back to the full rows
+    void tail64_iter();                 // one PCG iteration on the compact rows
     void update_tail();                 // from h_flags (the outer-active members just read)
     void tail_iter();                   // one inner CG iteration on the compact rows
     double cheb_lo = 1.0, cheb_hi = 1.05;  // scales of the Lanczos extreme eigenvalues of a step's first inner CG
@@ -202,6 +212,7 @@ struct Ens {
     void run_iters(int kind, int k);
     bool use_graph = true;
     hipGraphExec_t g_inner = nullptr, g_pcg = nullptr, g_cheb = nullptr, g_inner_tail[2] = {nullptr, nullptr};
+    hipGraphExec_t g_pcg_tail[2] = {nullptr, nullptr};
     int ebe_block = 256;
     int cluster_blocks = 3;             // co-resident cluster blocks per CU
     void fin(FinalizeStage st, int nd, int nblk, double tol2, int maxit);

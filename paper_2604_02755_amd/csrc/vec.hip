@@ -682,6 +682,83 @@ __global__ __launch_bounds__(256) void k_tail_pz(long nrows, int nm, const int* 
     }
 }
 
+// FP64 PCG on the compact rows (the tail of the plain FP64 path): the update
+// of k_pcg_update and the p step of k_p_update for the listed members
+template <int G>
+__global__ __launch_bounds__(256) void k_tail_pcg_update(int nn, int MB, int nm, const int* __restrict__ tl,
+                                                        double* __restrict__ cx, double* __restrict__ cr,
+                                                        double* __restrict__ cz, const double* __restrict__ cp,
+                                                        const double* __restrict__ cAp,
+                                                        const double* __restrict__ cpinv,
+                                                        const double* __restrict__ alpha,
+                                                        const int* __restrict__ active, double* __restrict__ partial)
+{
+    constexpr int NPB = 256 / G;
+    const int t = threadIdx.x, k = t % G;
+    const int m = tail_member(tl, k, G);
+    double acc[2] = {0.0, 0.0};
+    if (m >= 0 && m < nm && active[m]) {
+        const double al = alpha[m];
+        for (long node = (long)blockIdx.x * NPB + t / G; node < nn; node += (long)gridDim.x * NPB) {
+            Pk<double, 1> R[3], Z[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const long i = (node * 3 + c) * G + k;
+                cx[i] += al * cp[i];
+                R[c].a[0] = cr[i] - al * cAp[i];
+                cr[i] = R[c].a[0];
+            }
+            pinv_apply<double, 1>(cpinv, node, G, k, R, Z);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                cz[(node * 3 + c) * G + k] = Z[c].a[0];
+                acc[0] += R[c].a[0] * R[c].a[0];
+                acc[1] += R[c].a[0] * Z[c].a[0];
+            }
+        }
+    }
+    tail_partials<2, G>(acc, MB, m, partial, 0, gridDim.x);
+}
+
+template <int G>
+__global__ __launch_bounds__(256) void k_tail_p_update(long nrows, int nm, const int* __restrict__ tl,
+                                                      const double* __restrict__ cz, double* __restrict__ cp,
+                                                      const double* __restrict__ beta,
+                                                      const int* __restrict__ active)
+{
+    constexpr int NPB = 256 / G;
+    const int t = threadIdx.x, k = t % G;
+    const int m = tail_member(tl, k, G);
+    if (m < 0 || m >= nm || !active[m]) return;
+    const double be = beta[m];
+    for (long row = (long)blockIdx.x * NPB + t / G; row < nrows; row += (long)gridDim.x * NPB) {
+        const long i = row * G + k;
+        cp[i] = cz[i] + be * cp[i];
+    }
+}
+
+void launch_tail_pcg_update(hipStream_t s, int nn, int MB, int nm, int G, const int* tl, double* cx, double* cr,
+                            double* cz, const double* cp, const double* cAp, const double* cpinv,
+                            const double* alpha, const int* active, double* partial, int* nblk)
+{
+    const int g = grid_for(nn, 256 / G);
+    *nblk = g;
+    if (G == 16)
+        hipLaunchKernelGGL((k_tail_pcg_update<16>), dim3(g), dim3(256), 0, s, nn, MB, nm, tl, cx, cr, cz, cp, cAp, cpinv,
+                           alpha, active, partial);
+    else
+        hipLaunchKernelGGL((k_tail_pcg_update<32>), dim3(g), dim3(256), 0, s, nn, MB, nm, tl, cx, cr, cz, cp, cAp, cpinv,
+                           alpha, active, partial);
+}
+
+void launch_tail_p_update(hipStream_t s, long nrows, int nm, int G, const int* tl, const double* cz, double* cp,
+                          const double* beta, const int* active)
+{
+    const int g = grid_for(nrows, 256 / G);
+    if (G == 16) hipLaunchKernelGGL((k_tail_p_update<16>), dim3(g), dim3(256), 0, s, nrows, nm, tl, cz, cp, beta, active);
+    else hipLaunchKernelGGL((k_tail_p_update<32>), dim3(g), dim3(256), 0, s, nrows, nm, tl, cz, cp, beta, active);
+}
+
 void launch_tail_start(hipStream_t s, int nn, int MB, int nm, int G, const int* tl, const double* r,
                        const float* cpinv, float* cir, float* ciz, float* cip, const int* active, double* partial,
                        int* nblk)

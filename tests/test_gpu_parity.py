@@ -354,6 +354,59 @@ def test_tail_operator_matches_full_and_oracle(gpu_ctx, oracle_lib, n_members, n
         assert err < 1e-9
 
 
+@pytest.mark.parametrize("n_members,n_live", [(64, 20), (64, 10), (128, 24)])
+def test_fp64_tail_matches_full_and_oracle(gpu_ctx, oracle_lib, n_members, n_live):
+    """Plain FP64 PCG: once at most 32 members are still iterating, their PCG
+    moves to compact rows of 16 or 32 lanes (D per point, the PCG vectors)
+    for the rest of the step.  Members without input converge at once, so the
+    compact path runs from the first check: results match the full path and
+    the oracle, silent members stay at rest, iteration counts match the full
+    path's, and graph replay equals direct launches bitwise."""
+    nmb = n_members
+    mesh, prob = _small_problem(precision=0, n_members=nmb, n_steps=16, dims=(6, 5, 3), ns=12, tol=1e-12)
+    vs, gr = I.ensemble_members(93, nmb, I.CFG0_LAYERS["vs"])
+    prob.vs = vs
+    prob.gamma_ref = np.tile(gr[:, None], (1, 2))
+    live = np.arange(5, nmb, nmb // n_live)[:n_live]
+    acc = 5.0 * I.member_waves(3, range(nmb), prob.n_steps, prob.dt)
+    mask = np.zeros(nmb, dtype=bool)
+    mask[live] = True
+    acc[~mask] = 0.0
+    prob.input_acc = acc
+    mh = gpu_ctx.mesh(mesh)
+
+    def run(profile=False, **kw):
+        ens = gpu_ctx.ensemble(mh, mesh, prob)
+        try:
+            ens.set_tuning(**kw)
+            if profile:
+                ens.set_profile(True)
+            ens.step(prob.n_steps)
+            return ens.read(), ens.stats()
+        finally:
+            ens.close()
+
+    say("fp64 tail:", n_live, "of", nmb, "members live")
+    full, _ = run(tail_members=0)
+    lst, _ = run(tail_members=32)
+    prof, st = run(profile=True, tail_members=32)
+    say("  tail launches", st["n_tail32"], "element-member pairs", st["elems_tail32"])
+    assert st["n_tail32"] > 0 and st["elems_tail32"] <= st["n_tail32"] * mesh.n_tets * n_live
+    assert st["elems_tail32"] % mesh.n_tets == 0
+    assert np.all(lst["vel"][~mask] == 0.0)
+    scale = np.max(np.abs(full["vel"]))
+    d = float(np.max(np.abs(lst["vel"] - full["vel"])) / scale)
+    dp = float(np.max(np.abs(prof["vel"] - lst["vel"])) / scale)
+    say("  list vs full max rel diff", d, "profiled vs graph-replayed", dp)
+    assert d < 1e-10 and dp == 0.0
+    assert np.max(np.abs(lst["iters"][:, :, 0] - full["iters"][:, :, 0])) <= 1
+    for m in (live[0], live[-1]):
+        vref, itref = _oracle_vel(oracle_lib, mesh, prob, int(m))
+        err = oracle_lib.rel_l2(lst["vel"][m], vref)
+        say("  member", int(m), "vs oracle", err)
+        assert err < 1e-9 and np.max(np.abs(lst["iters"][m, :, 0] - itref)) <= 1
+
+
 def test_chebyshev_inner_matches_oracle(gpu_ctx, oracle_lib, nlth_mod):
     """Inner Chebyshev iteration (bounds from the step's first inner CG): the
     outer FP64 flexible CG still converges to its tolerance, so members match
