@@ -640,7 +640,7 @@ def main():
     # interpolated percentile and not the maximum
     serving = None
     if not args.no_serve:
-        serving = serve_run(1.0, 50.0, (20, 60), max_batch=args.max_batch)
+        serving = serve_run(1.0, 65.0, (20, 60), max_batch=args.max_batch)
         log(f"serving: p50 {serving['p50_s']:.2f} s, p99 {serving['p99_s']:.2f} s over {serving['requests']} requests")
 
     line = {

@@ -1090,12 +1090,13 @@ void Ens::build_diag()
 {
     const DevMesh dm = mesh->dev();
     const bool mean = P.precision == NLTH_MIXED && d16_mean;
-    launch_fill(s, diag.as<double>(), 0.0, (long)mesh->nn * 6 * MB);
-    for (int c = 0; c < mesh->ncolor; ++c) {
-        if (mean)
-            launch_diag_mean(s, dm, MB, nm, mesh->color_off[c], mesh->color_off[c + 1], D16.as<uint32_t>(),
-                             h.as<double>(), mat.as<double>(), sc, diag.as<double>());
-        else
+    if (mean) {
+        // every block written once (members beyond nm are never read)
+        launch_diag_mean_node(s, dm, MB, nm, D16.as<uint32_t>(), h.as<double>(), mat.as<double>(), sc,
+                              diag.as<double>());
+    } else {
+        launch_fill(s, diag.as<double>(), 0.0, (long)mesh->nn * 6 * MB);
+        for (int c = 0; c < mesh->ncolor; ++c)
             launch_diag(s, dm, MB, nm, mesh->color_off[c], mesh->color_off[c + 1], D64.as<double>(), h.as<double>(),
                         mat.as<double>(), P.nl, sc, diag.as<double>());
     }
