@@ -176,7 +176,9 @@ def serve_run(rate, window_s, steps_range, sizes=(32, 48, 64), max_batch=64, n_c
     from paper_2604_02755_amd import inputs as I, nlth
     reqs = I.serving_requests(rate=rate, window_s=window_s, seed=seed, sizes=sizes, steps_range=steps_range)
     meshes = {n: I.serving_mesh(n) for n in sizes}
-    probs = [I.serving_problem(r) for r in reqs]
+    # the solver settings of the batched benchmark: element-mean bfloat16 D in
+    # the inner operator, 12 inner CG iterations per outer iteration
+    probs = [I.serving_problem(r, inner_dtype=2, inner_tol=1e-12, inner_maxit=12) for r in reqs]
     ctx = nlth.Context(0, max_batch=max_batch, use_torch_stream=False)
     lat, rcs, outs = {}, {}, {}
     try:

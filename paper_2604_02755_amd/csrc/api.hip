@@ -965,18 +965,7 @@ void Ens::destroy()
     pending.clear();
     for (auto e : ev_pool) (void)hipEventDestroy(e);
     ev_pool.clear();
-    if (g_inner) (void)hipGraphExecDestroy(g_inner);
-    if (g_pcg) (void)hipGraphExecDestroy(g_pcg);
-    if (g_cheb) (void)hipGraphExecDestroy(g_cheb);
-    for (auto& gt : g_inner_tail) {
-        if (gt) (void)hipGraphExecDestroy(gt);
-        gt = nullptr;
-    }
-    for (auto& gt : g_pcg_tail) {
-        if (gt) (void)hipGraphExecDestroy(gt);
-        gt = nullptr;
-    }
-    g_inner = g_pcg = g_cheb = nullptr;
+    clear_graphs();
     if (h_mail) (void)hipHostFree(h_mail);
     h_mail = d_mail = h_flags = h_tlist = nullptr;
     if (ev_copy0) (void)hipEventDestroy(ev_copy0);
@@ -1090,13 +1079,12 @@ void Ens::build_diag()
 {
     const DevMesh dm = mesh->dev();
     const bool mean = P.precision == NLTH_MIXED && d16_mean;
-    if (mean) {
-        // every block written once (members beyond nm are never read)
-        launch_diag_mean_node(s, dm, MB, nm, D16.as<uint32_t>(), h.as<double>(), mat.as<double>(), sc,
-                              diag.as<double>());
-    } else {
-        launch_fill(s, diag.as<double>(), 0.0, (long)mesh->nn * 6 * MB);
-        for (int c = 0; c < mesh->ncolor; ++c)
+    launch_fill(s, diag.as<double>(), 0.0, (long)mesh->nn * 6 * MB);
+    for (int c = 0; c < mesh->ncolor; ++c) {
+        if (mean)
+            launch_diag_mean(s, dm, MB, nm, mesh->color_off[c], mesh->color_off[c + 1], D16.as<uint32_t>(),
+                             h.as<double>(), mat.as<double>(), sc, diag.as<double>());
+        else
             launch_diag(s, dm, MB, nm, mesh->color_off[c], mesh->color_off[c + 1], D64.as<double>(), h.as<double>(),
                         mat.as<double>(), P.nl, sc, diag.as<double>());
     }
@@ -1479,17 +1467,27 @@ void Ens::pcg_iter()
     launch_p_update<double>(s, n, MB, nm, z.as<double>(), p.as<double>(), cs.beta, act, nullptr);
 }
 
-// k iterations of kind 0 (inner) or 1 (FP64 PCG); a full chunk is captured
-// once into a hipGraph and replayed (the launches and their arguments are the
-// same every chunk), which removes per-launch host overhead
+void Ens::clear_graphs()
+{
+    for (auto& kv : g_chunks)
+        if (kv.second) (void)hipGraphExecDestroy(kv.second);
+    g_chunks.clear();
+    if (g_cheb) (void)hipGraphExecDestroy(g_cheb);
+    g_cheb = nullptr;
+}
+
+// k iterations of kind 0 (inner) or 1 (FP64 PCG); a chunk of k iterations is
+// captured once into a hipGraph per (kind, compact-row width, k) and replayed
+// (the launches and their arguments are the same every chunk: scalars are
+// read on the device), which removes per-launch host overhead
 void Ens::run_iters(int kind, int k)
 {
-    if (!use_graph || profile || k != check_every) {
+    if (!use_graph || profile || k <= 0 || k > 64) {
         for (int i = 0; i < k; ++i) kind == 0 ? inner_iter() : pcg_iter();
         return;
     }
-    hipGraphExec_t& ge = kind == 1 ? (tail64_g ? g_pcg_tail[tail64_g == 16 ? 0 : 1] : g_pcg)
-                                   : (tail_g ? g_inner_tail[tail_g == 16 ? 0 : 1] : g_inner);
+    const int g = kind == 1 ? tail64_g : tail_g;
+    hipGraphExec_t& ge = g_chunks[(kind * 64 + g) * 128 + k];
     if (!ge) {
         hipGraph_t g = nullptr;
         NLTH_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -2070,19 +2068,7 @@ static void apply_tuning(Ens* ens, const nlth_tuning* t)
     if (t->tail_members >= 0) ens->tail_max = t->tail_members;
     if (t->predictor >= 0) ens->predictor = t->predictor;
     ens->tail_g = 0;
-    // captured chunks hold the old launch shapes
-    if (ens->g_inner) (void)hipGraphExecDestroy(ens->g_inner);
-    if (ens->g_pcg) (void)hipGraphExecDestroy(ens->g_pcg);
-    if (ens->g_cheb) (void)hipGraphExecDestroy(ens->g_cheb);
-    ens->g_inner = ens->g_pcg = ens->g_cheb = nullptr;
-    for (auto& gt : ens->g_inner_tail) {
-        if (gt) (void)hipGraphExecDestroy(gt);
-        gt = nullptr;
-    }
-    for (auto& gt : ens->g_pcg_tail) {
-        if (gt) (void)hipGraphExecDestroy(gt);
-        gt = nullptr;
-    }
+    ens->clear_graphs();  // captured chunks hold the old launch shapes
 }
 
 int nlth_ens_reset_stats(nlth_ens* ens)

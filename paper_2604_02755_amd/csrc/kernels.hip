@@ -1452,100 +1452,6 @@ void launch_diag_mean(hipStream_t s, const DevMesh& M, int MB, int nm, int e0, i
     if (n > 0) hipLaunchKernelGGL(k_diag_mean, dim3(nblocks(n)), dim3(256), 0, s, M, MB, nm, e0, e1, D16, h, mat, sc, diag);
 }
 
-// The same blocks gathered per node: a lane takes (node, member) and sums the
-// closed-form blocks of the node's incident elements in ascending storage
-// order, writing each block once (no colour launches, no read-modify-write).
-// With 64 or more member slots a wavefront is one node and the element data
-// it reads are wave-uniform.
-__global__ __launch_bounds__(256) void k_diag_mean_node(DevMesh M, int MB, int nm, const uint32_t* __restrict__ D16,
-                                                       const double* __restrict__ h,
-                                                       const double* __restrict__ mat, StepConst sc,
-                                                       double* __restrict__ diag)
-{
-    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    const int m = (int)(t % MB);
-    long node = t / MB;
-    if (MB >= 64) node = __builtin_amdgcn_readfirstlane((int)node);
-    if (node >= M.nn || m >= nm) return;
-    const long ne = M.ne;
-    const int EB = MB >= 64 ? 1 : 64 / MB;
-    constexpr int PQ[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {1, 2}, {2, 0}};
-    constexpr int CD[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
-    constexpr int E[6][2] = {{0, 1}, {1, 2}, {2, 0}, {0, 3}, {1, 3}, {2, 3}};
-    const double dt = sc.dt;
-    double acc[6] = {0, 0, 0, 0, 0, 0};
-    const int q1 = M.inc_ptr[node + 1];
-    for (int q = M.inc_ptr[node]; q < q1; ++q) {
-        const int ie = MB >= 64 ? __builtin_amdgcn_readfirstlane(M.inc[q]) : M.inc[q];
-        const long e = ie / 10;
-        const int n = ie % 10;
-        double gL[4][3];
-#pragma unroll
-        for (int k = 0; k < 12; ++k) gL[k / 3][k % 3] = M.geo64[k * ne + e];
-        const double vol = M.geo64[12 * ne + e];
-        const int l = M.layer[e];
-        const double rho = matv(mat, l, MAT_RHO, MB, m);
-        double he = 0.0;
-        if (sc.damping_mode == 0 && h) he = h[e * MB + m];
-        else if (sc.damping_mode == 1) he = sc.h0;
-        const double sm = rho * vol * (4.0 / (dt * dt) + 2.0 * sc.ahat * he / dt);
-        const double sk = (1.0 + 2.0 * sc.bhat * he / dt) * vol;
-        double d[22];
-#pragma unroll
-        for (int k = 0; k < 11; ++k) {
-            const uint32_t wv = D16[d16m_index(e, k, MB, EB, m)];
-            d[2 * k] = (double)bf2f(wv & 0xFFFFu);
-            d[2 * k + 1] = (double)bf2f(wv >> 16);
-        }
-        double G[6];  // int d_p N_n d_q N_n dV / V in the PQ order
-        if (n < 4) {
-#pragma unroll
-            for (int pq = 0; pq < 6; ++pq) G[pq] = 0.6 * gL[n][PQ[pq][0]] * gL[n][PQ[pq][1]];
-        } else {
-            int a = 0, b = 0;
-#pragma unroll
-            for (int k = 0; k < 6; ++k)
-                if (n - 4 == k) {
-                    a = E[k][0];
-                    b = E[k][1];
-                }
-            double ga[3], gb[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                ga[c] = a == 0 ? gL[0][c] : (a == 1 ? gL[1][c] : (a == 2 ? gL[2][c] : gL[3][c]));
-                gb[c] = b == 0 ? gL[0][c] : (b == 1 ? gL[1][c] : (b == 2 ? gL[2][c] : gL[3][c]));
-            }
-#pragma unroll
-            for (int pq = 0; pq < 6; ++pq) {
-                const int p = PQ[pq][0], qq = PQ[pq][1];
-                G[pq] = 1.6 * (ga[p] * ga[qq] + gb[p] * gb[qq]) + 0.8 * (ga[p] * gb[qq] + gb[p] * ga[qq]);
-            }
-        }
-        const double md = sm * mass_ref(n, n);
-#pragma unroll
-        for (int cd = 0; cd < 6; ++cd) {
-            double a = 0.0;
-#pragma unroll
-            for (int pq = 0; pq < 6; ++pq) {
-                const int c = CD[cd][0], dd = CD[cd][1], p = PQ[pq][0], qq = PQ[pq][1];
-                double v = d[sym6(voigt_of(c, p), voigt_of(dd, qq))];
-                if (p != qq) v += d[sym6(voigt_of(c, qq), voigt_of(dd, p))];
-                a += G[pq] * v;
-            }
-            acc[cd] += sk * a + ((cd == 0 || cd == 3 || cd == 5) ? md : 0.0);
-        }
-    }
-#pragma unroll
-    for (int cd = 0; cd < 6; ++cd) diag[(node * 6 + cd) * MB + m] = acc[cd];
-}
-
-void launch_diag_mean_node(hipStream_t s, const DevMesh& M, int MB, int nm, const uint32_t* D16, const double* h,
-                           const double* mat, StepConst sc, double* diag)
-{
-    const long n = (long)M.nn * MB;
-    if (n > 0) hipLaunchKernelGGL(k_diag_mean_node, dim3(nblocks(n)), dim3(256), 0, s, M, MB, nm, D16, h, mat, sc, diag);
-}
-
 void launch_diag(hipStream_t s, const DevMesh& M, int MB, int nm, int e0, int e1, const double* D, const double* h,
                  const double* mat, int, StepConst sc, double* diag)
 {

@@ -111,9 +111,6 @@ void launch_diag(hipStream_t s, const DevMesh& M, int MB, int nm, int e0, int e1
 // the same from the bfloat16 element-mean D of the inner operator (closed-form integrals)
 void launch_diag_mean(hipStream_t s, const DevMesh& M, int MB, int nm, int e0, int e1, const uint32_t* D16,
                       const double* h, const double* mat, StepConst sc, double* diag);
-// the same blocks summed per node over its incident elements (written once)
-void launch_diag_mean_node(hipStream_t s, const DevMesh& M, int MB, int nm, const uint32_t* D16, const double* h,
-                           const double* mat, StepConst sc, double* diag);
 void launch_diag_dashpot(hipStream_t s, const DevMesh& M, int MB, int nm, const double* mat, int n_layers,
                          double coef, double* diag);
 void launch_invert_diag(hipStream_t s, int nn, int MB, int nm, const double* diag, double* pinv,

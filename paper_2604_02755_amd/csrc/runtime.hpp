@@ -211,8 +211,10 @@ struct Ens {
     void pcg_iter();
     void run_iters(int kind, int k);
     bool use_graph = true;
-    hipGraphExec_t g_inner = nullptr, g_pcg = nullptr, g_cheb = nullptr, g_inner_tail[2] = {nullptr, nullptr};
-    hipGraphExec_t g_pcg_tail[2] = {nullptr, nullptr};
+    // captured CG chunks, by (kind, compact-row width, iterations); the Chebyshev solve
+    std::map<int, hipGraphExec_t> g_chunks;
+    hipGraphExec_t g_cheb = nullptr;
+    void clear_graphs();
     int ebe_block = 256;
     int cluster_blocks = 3;             // co-resident cluster blocks per CU
     void fin(FinalizeStage st, int nd, int nblk, double tol2, int maxit);
