@@ -1153,29 +1153,9 @@ bool Ens::enter_tail64()
     int na = 0;
     for (int m = 0; m < nm; ++m) na += h_flags[m] != 0;
     if (na == 0 || na > tail_max) return false;
-    if (!tail64_mem.p) {
-        // 32 lanes: D per point (elements padded to blocks of 4), h, material,
-        // inverse blocks, five PCG vectors, element outputs
-        const size_t ne4 = ((size_t)mesh->ne + 3) / 4 * 4, nn = mesh->nn, L = 32;
-        const size_t nv = 3 * nn * L * 8;
-        const size_t sz[10] = {ne4 * 84 * L * 8, (size_t)mesh->ne * L * 8, (size_t)P.nl * MAT_N * L * 8,
-                               nn * 6 * L * 8, nv, nv, nv, nv, nv, (size_t)mesh->ne * 30 * L * 8};
-        size_t off[10], tot = 0;
-        for (int i = 0; i < 10; ++i) {
-            off[i] = tot;
-            tot += (sz[i] + 255) / 256 * 256;
-        }
-        try {
-            tail64_mem.alloc(&ctx->budget, tot);
-            if (!tlist.p) tlist.alloc(&ctx->budget, (size_t)(1 + MB) * 4);
-        } catch (const Error&) {  // no room: keep the full operator
-            tail64_mem.release();
-            tail_max = 0;
-            return false;
-        }
-        char* b = (char*)tail64_mem.p;
-        double** dst[10] = {&tc.D, &tc.h, &tc.mat, &tc.pinv, &tc.x, &tc.r, &tc.z, &tc.p, &tc.Ap, &tc.f};
-        for (int i = 0; i < 10; ++i) *dst[i] = (double*)(b + off[i]);
+    if (!alloc_tail64()) {  // no room: keep the full operator
+        tail_max = 0;
+        return false;
     }
     h_tlist[0] = na;
     int k = 1;
@@ -1190,6 +1170,56 @@ bool Ens::enter_tail64()
     launch_tail_rows64(s, ndof, MB, tail64_g, tl, r.as<double>(), tc.r, false);
     launch_tail_rows64(s, ndof, MB, tail64_g, tl, z.as<double>(), tc.z, false);
     launch_tail_rows64(s, ndof, MB, tail64_g, tl, p.as<double>(), tc.p, false);
+    return true;
+}
+
+// FP64 compact rows of 32 lanes: D per point (elements padded to blocks of
+// 4), h, material, inverse blocks, five CG vectors, element outputs
+bool Ens::alloc_tail64()
+{
+    if (tail64_mem.p) return true;
+    const size_t ne4 = ((size_t)mesh->ne + 3) / 4 * 4, nn = mesh->nn, L = 32;
+    const size_t nv = 3 * nn * L * 8;
+    const size_t sz[10] = {ne4 * 84 * L * 8, (size_t)mesh->ne * L * 8, (size_t)P.nl * MAT_N * L * 8,
+                           nn * 6 * L * 8, nv, nv, nv, nv, nv, (size_t)mesh->ne * 30 * L * 8};
+    size_t off[10], tot = 0;
+    for (int i = 0; i < 10; ++i) {
+        off[i] = tot;
+        tot += (sz[i] + 255) / 256 * 256;
+    }
+    try {
+        tail64_mem.alloc(&ctx->budget, tot);
+        if (!tlist.p) tlist.alloc(&ctx->budget, (size_t)(1 + MB) * 4);
+    } catch (const Error&) {
+        tail64_mem.release();
+        return false;
+    }
+    char* b = (char*)tail64_mem.p;
+    double** dst[10] = {&tc.D, &tc.h, &tc.mat, &tc.pinv, &tc.x, &tc.r, &tc.z, &tc.p, &tc.Ap, &tc.f};
+    for (int i = 0; i < 10; ++i) *dst[i] = (double*)(b + off[i]);
+    return true;
+}
+
+// Mixed path, once the inner solve runs on the compact rows of a list (just
+// packed by update_tail): the outer iteration of the listed members moves to
+// the FP64 compact rows too, its operator data and the increment, residual,
+// direction and last operator result packed once; the list stays fixed for
+// the rest of the step.
+bool Ens::enter_outer_tail()
+{
+    if (!outer_tail_ok || P.precision != NLTH_MIXED || !tail_g || MB < 64 || MB > 256) return false;
+    if (!alloc_tail64()) {
+        outer_tail_ok = false;
+        return false;
+    }
+    const int* tl = tlist.as<int>();
+    launch_tail_pack64(s, mesh->dev(), MB, tail_g, P.nl, tl, D64.as<double>(), h.as<double>(), mat.as<double>(),
+                       pinv.as<double>(), tc.D, tc.h, tc.mat, tc.pinv);
+    launch_tail_rows64(s, ndof, MB, tail_g, tl, du.as<double>(), tc.x, false);
+    launch_tail_rows64(s, ndof, MB, tail_g, tl, r.as<double>(), tc.r, false);
+    launch_tail_rows64(s, ndof, MB, tail_g, tl, p.as<double>(), tc.p, false);
+    launch_tail_rows64(s, ndof, MB, tail_g, tl, Ap.as<double>(), tc.Ap, false);  // the flexible beta reads it
+    outer_compact = true;
     return true;
 }
 
@@ -1232,8 +1262,8 @@ void Ens::inner_solve()
     const double tol2 = P.inner_tol * P.inner_tol;
     double* pd = partial.as<double>();
     if (tail_g)
-        launch_tail_start(s, mesh->nn, MB, nm, tail_g, tlist.as<int>(), r.as<double>(), tb.pinv, tb.ir, tb.iz, tb.ip,
-                          act, pd, &nblk);
+        launch_tail_start(s, mesh->nn, MB, nm, tail_g, tlist.as<int>(), outer_compact ? tc.r : r.as<double>(),
+                          outer_compact, tb.pinv, tb.ir, tb.iz, tb.ip, act, pd, &nblk);
     else
         launch_inner_start(s, mesh->nn, MB, nm, r.as<double>(), pinv32.as<float>(), ir.as<float>(), iz.as<float>(),
                            ip.as<float>(), iw.as<float>(), iAp.as<float>(), act, pd, &nblk);
@@ -1246,8 +1276,9 @@ void Ens::inner_solve()
         if (!read_any_active(iact)) break;
     }
     // the listed members' result back to the full rows (the others are not
-    // outer-active: the output step writes zero for them)
-    if (tail_g) launch_tail_unpack(s, n, MB, tail_g, tlist.as<int>(), tb.iz, iz.as<float>());
+    // outer-active: the output step writes zero for them); with the outer
+    // iteration on the compact rows it stays there
+    if (tail_g && !outer_compact) launch_tail_unpack(s, n, MB, tail_g, tlist.as<int>(), tb.iz, iz.as<float>());
 }
 
 // Choose the inner operator for the next preconditioner calls from the
@@ -1543,20 +1574,47 @@ void Ens::solve_fcg()
     launch_inner_out(s, n, MB, nm, iz.as<float>(), z.as<double>(), Ap.as<double>(), r.as<double>(), act, pd, &nblk);
     fin(FIN_FCG_RZ, 2, nblk, tol2, P.cg_maxit);
     launch_p_update<double>(s, n, MB, nm, z.as<double>(), p.as<double>(), nullptr, act, nullptr);
+    outer_compact = false;
+    const DevMesh dm = mesh->dev();
     for (;;) {
-        apply_A64(p.as<double>(), Ap.as<double>(), act, &nblk);
-        fin(FIN_ALPHA, 1, nblk, tol2, P.cg_maxit);
-        launch_xr_update(s, n, MB, nm, x, r.as<double>(), p.as<double>(), Ap.as<double>(), cs.alpha, act, pd, &nblk);
+        if (outer_compact) {
+            const int* tl = tlist.as<int>();
+            hipEvent_t t0;
+            tstart(t0);
+            launch_ebe64_tail(s, dm, tail_g, tl, tc.D, tc.h, tc.mat, sc, tc.p, tc.f);
+            launch_gather_tail<double>(s, dm, MB, nm, tail_g, tl, tc.f, tc.Ap, act, tc.p, pd, &nblk);
+            launch_dashpot_tail<double>(s, dm, MB, nm, tail_g, tl, tc.mat, 2.0 / P.dt, tc.p, tc.Ap, act, pd, &nblk);
+            tstop(t0, &pc_tail32, (int64_t)mesh->ne * h_tlist[0]);
+            fin(FIN_ALPHA, 1, nblk, tol2, P.cg_maxit);
+            launch_tail_xr_update(s, n, MB, nm, tail_g, tl, tc.x, tc.r, tc.p, tc.Ap, cs.alpha, act, pd, &nblk);
+        } else {
+            apply_A64(p.as<double>(), Ap.as<double>(), act, &nblk);
+            fin(FIN_ALPHA, 1, nblk, tol2, P.cg_maxit);
+            launch_xr_update(s, n, MB, nm, x, r.as<double>(), p.as<double>(), Ap.as<double>(), cs.alpha, act, pd,
+                             &nblk);
+        }
         fin(FIN_FCG_RR, 1, nblk, tol2, P.cg_maxit);
         if (!read_any_active(act)) break;
-        update_tail();
+        if (!outer_compact) {
+            update_tail();
+            enter_outer_tail();
+        }
         if (cheb) cheb_solve();
         else inner_solve();
-        launch_inner_out(s, n, MB, nm, iz.as<float>(), z.as<double>(), Ap.as<double>(), r.as<double>(), act, pd,
-                         &nblk);
-        fin(FIN_FCG_BETA, 2, nblk, tol2, P.cg_maxit);
-        launch_p_update<double>(s, n, MB, nm, z.as<double>(), p.as<double>(), cs.beta, act, nullptr);
+        if (outer_compact) {
+            const int* tl = tlist.as<int>();
+            launch_tail_inner_out(s, n, MB, nm, tail_g, tl, tb.iz, tc.z, tc.Ap, tc.r, act, pd, &nblk);
+            fin(FIN_FCG_BETA, 2, nblk, tol2, P.cg_maxit);
+            launch_tail_p_update(s, n, nm, tail_g, tl, tc.z, tc.p, cs.beta, act);
+        } else {
+            launch_inner_out(s, n, MB, nm, iz.as<float>(), z.as<double>(), Ap.as<double>(), r.as<double>(), act, pd,
+                             &nblk);
+            fin(FIN_FCG_BETA, 2, nblk, tol2, P.cg_maxit);
+            launch_p_update<double>(s, n, MB, nm, z.as<double>(), p.as<double>(), cs.beta, act, nullptr);
+        }
     }
+    if (outer_compact) launch_tail_rows64(s, n, MB, tail_g, tlist.as<int>(), tc.x, x, true);
+    outer_compact = false;
     tail_g = 0;
 }
 

@@ -156,9 +156,17 @@ void launch_tail_pcg_update(hipStream_t s, int nn, int MB, int nm, int G, const 
                             const double* alpha, const int* active, double* partial, int* nblk);
 void launch_tail_p_update(hipStream_t s, long nrows, int nm, int G, const int* tl, const double* cz, double* cp,
                           const double* beta, const int* active);
-void launch_tail_start(hipStream_t s, int nn, int MB, int nm, int G, const int* tl, const double* r,
+// r_compact: r in the compact rows (the outer CG on compact rows), else full
+void launch_tail_start(hipStream_t s, int nn, int MB, int nm, int G, const int* tl, const double* r, bool r_compact,
                        const float* cpinv, float* cir, float* ciz, float* cip, const int* active, double* partial,
                        int* nblk);
+// the mixed path's outer flexible CG on the compact rows
+void launch_tail_xr_update(hipStream_t s, long nrows, int MB, int nm, int G, const int* tl, double* cx, double* cr,
+                           const double* cp, const double* cAp, const double* alpha, const int* active,
+                           double* partial, int* nblk);
+void launch_tail_inner_out(hipStream_t s, long nrows, int MB, int nm, int G, const int* tl, const float* ciz,
+                           double* cz, const double* cAp, const double* cr, const int* active, double* partial,
+                           int* nblk);
 void launch_tail_update(hipStream_t s, int nn, int MB, int nm, int G, const int* tl, float* cir, float* cw,
                         const float* ciAp, const float* cpinv, const double* ialpha, const int* iactive,
                         double* partial, int* nblk);

@@ -125,6 +125,12 @@ struct Ens {
     bool enter_tail64();                // from h_flags: pack the listed members' rows
     void leave_tail64();                // their increment back to the full rows
     void tail64_iter();                 // one PCG iteration on the compact rows
+    bool alloc_tail64();                // the FP64 compact rows (32 lanes), at first use
+    // the mixed path's outer flexible CG moves to the same compact rows (the
+    // inner tail's list) for the rest of the step
+    bool outer_tail_ok = true;          // false once the compact rows could not be allocated
+    bool outer_compact = false;
+    bool enter_outer_tail();
     void update_tail();                 // from h_flags (the outer-active members just read)
     void tail_iter();                   // one inner CG iteration on the compact rows
     double cheb_lo = 1.0, cheb_hi = 1.05;  // scales of the Lanczos extreme eigenvalues of a step's first inner CG
@@ -197,7 +203,7 @@ struct Ens {
     void build_diag();
     void solve_pcg();
     void solve_fcg();
-    void inner_solve();
+    void inner_solve();                 // the preconditioner: z ~ A^-1 r
     void cheb_solve();
     void cheb_estimate();
     void cheb_body();

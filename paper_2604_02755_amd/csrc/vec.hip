@@ -599,7 +599,7 @@ __device__ __forceinline__ int tail_member(const int* __restrict__ tl, int k, in
     return k < min(tl[0], G) ? tl[1 + k] : -1;
 }
 
-template <int G>
+template <int G, bool CR>
 __global__ __launch_bounds__(256) void k_tail_start(int nn, int MB, int nm, const int* __restrict__ tl,
                                                    const double* __restrict__ r, const float* __restrict__ cpinv,
                                                    float* __restrict__ cir, float* __restrict__ ciz,
@@ -614,7 +614,7 @@ __global__ __launch_bounds__(256) void k_tail_start(int nn, int MB, int nm, cons
         for (long node = (long)blockIdx.x * NPB + t / G; node < nn; node += (long)gridDim.x * NPB) {
             Pk<float, 1> R[3], W[3];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) R[c].a[0] = (float)r[(node * 3 + c) * MB + m];
+            for (int c = 0; c < 3; ++c) R[c].a[0] = (float)(CR ? r[(node * 3 + c) * G + k] : r[(node * 3 + c) * MB + m]);
             pinv_apply<float, 1>(cpinv, node, G, k, R, W);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
@@ -759,14 +759,94 @@ void launch_tail_p_update(hipStream_t s, long nrows, int nm, int G, const int* t
     else hipLaunchKernelGGL((k_tail_p_update<32>), dim3(g), dim3(256), 0, s, nrows, nm, tl, cz, cp, beta, active);
 }
 
-void launch_tail_start(hipStream_t s, int nn, int MB, int nm, int G, const int* tl, const double* r,
+void launch_tail_start(hipStream_t s, int nn, int MB, int nm, int G, const int* tl, const double* r, bool r_compact,
                        const float* cpinv, float* cir, float* ciz, float* cip, const int* active, double* partial,
                        int* nblk)
 {
     const int g = grid_for(nn, 256 / G);
     *nblk = g;
-    if (G == 16) hipLaunchKernelGGL((k_tail_start<16>), dim3(g), dim3(256), 0, s, nn, MB, nm, tl, r, cpinv, cir, ciz, cip, active, partial);
-    else hipLaunchKernelGGL((k_tail_start<32>), dim3(g), dim3(256), 0, s, nn, MB, nm, tl, r, cpinv, cir, ciz, cip, active, partial);
+    if (G == 16 && r_compact)
+        hipLaunchKernelGGL((k_tail_start<16, true>), dim3(g), dim3(256), 0, s, nn, MB, nm, tl, r, cpinv, cir, ciz, cip, active, partial);
+    else if (G == 16)
+        hipLaunchKernelGGL((k_tail_start<16, false>), dim3(g), dim3(256), 0, s, nn, MB, nm, tl, r, cpinv, cir, ciz, cip, active, partial);
+    else if (r_compact)
+        hipLaunchKernelGGL((k_tail_start<32, true>), dim3(g), dim3(256), 0, s, nn, MB, nm, tl, r, cpinv, cir, ciz, cip, active, partial);
+    else
+        hipLaunchKernelGGL((k_tail_start<32, false>), dim3(g), dim3(256), 0, s, nn, MB, nm, tl, r, cpinv, cir, ciz, cip, active, partial);
+}
+
+// outer flexible CG of the mixed path on the compact rows: x += a p, r -= a Ap
+// with the partial r.r (k_xr_update), and z = iz for the outer-active members
+// with the partials (z.Ap, z.r) (k_inner_out)
+template <int G>
+__global__ __launch_bounds__(256) void k_tail_xr_update(long nrows, int MB, int nm, const int* __restrict__ tl,
+                                                       double* __restrict__ cx, double* __restrict__ cr,
+                                                       const double* __restrict__ cp, const double* __restrict__ cAp,
+                                                       const double* __restrict__ alpha,
+                                                       const int* __restrict__ active, double* __restrict__ partial)
+{
+    constexpr int NPB = 256 / G;
+    const int t = threadIdx.x, k = t % G;
+    const int m = tail_member(tl, k, G);
+    double acc[1] = {0.0};
+    if (m >= 0 && m < nm && active[m]) {
+        const double al = alpha[m];
+        for (long row = (long)blockIdx.x * NPB + t / G; row < nrows; row += (long)gridDim.x * NPB) {
+            const long i = row * G + k;
+            cx[i] += al * cp[i];
+            const double R = cr[i] - al * cAp[i];
+            cr[i] = R;
+            acc[0] += R * R;
+        }
+    }
+    tail_partials<1, G>(acc, MB, m, partial, 0, gridDim.x);
+}
+
+template <int G>
+__global__ __launch_bounds__(256) void k_tail_inner_out(long nrows, int MB, int nm, const int* __restrict__ tl,
+                                                       const float* __restrict__ ciz, double* __restrict__ cz,
+                                                       const double* __restrict__ cAp, const double* __restrict__ cr,
+                                                       const int* __restrict__ active, double* __restrict__ partial)
+{
+    constexpr int NPB = 256 / G;
+    const int t = threadIdx.x, k = t % G;
+    const int m = tail_member(tl, k, G);
+    double acc[2] = {0.0, 0.0};
+    if (m >= 0 && m < nm) {
+        const bool act = active[m] != 0;
+        for (long row = (long)blockIdx.x * NPB + t / G; row < nrows; row += (long)gridDim.x * NPB) {
+            const long i = row * G + k;
+            const double Z = act ? (double)ciz[i] : 0.0;
+            acc[0] += Z * cAp[i];
+            acc[1] += Z * cr[i];
+            cz[i] = Z;
+        }
+    }
+    tail_partials<2, G>(acc, MB, m, partial, 0, gridDim.x);
+}
+
+void launch_tail_xr_update(hipStream_t s, long nrows, int MB, int nm, int G, const int* tl, double* cx, double* cr,
+                           const double* cp, const double* cAp, const double* alpha, const int* active,
+                           double* partial, int* nblk)
+{
+    const int g = grid_for(nrows, 256 / G);
+    *nblk = g;
+    if (G == 16)
+        hipLaunchKernelGGL((k_tail_xr_update<16>), dim3(g), dim3(256), 0, s, nrows, MB, nm, tl, cx, cr, cp, cAp, alpha, active, partial);
+    else
+        hipLaunchKernelGGL((k_tail_xr_update<32>), dim3(g), dim3(256), 0, s, nrows, MB, nm, tl, cx, cr, cp, cAp, alpha, active, partial);
+}
+
+void launch_tail_inner_out(hipStream_t s, long nrows, int MB, int nm, int G, const int* tl, const float* ciz,
+                           double* cz, const double* cAp, const double* cr, const int* active, double* partial,
+                           int* nblk)
+{
+    const int g = grid_for(nrows, 256 / G);
+    *nblk = g;
+    if (G == 16)
+        hipLaunchKernelGGL((k_tail_inner_out<16>), dim3(g), dim3(256), 0, s, nrows, MB, nm, tl, ciz, cz, cAp, cr, active, partial);
+    else
+        hipLaunchKernelGGL((k_tail_inner_out<32>), dim3(g), dim3(256), 0, s, nrows, MB, nm, tl, ciz, cz, cAp, cr, active, partial);
 }
 
 void launch_tail_update(hipStream_t s, int nn, int MB, int nm, int G, const int* tl, float* cir, float* cw,

@@ -695,3 +695,58 @@ def test_block_jacobi_diagonal_matches_oracle(gpu_ctx, oracle_lib):
     say("block diagonal, inner operator (bfloat16 element-mean D, closed form), rel err vs oracle", err)
     assert err < 1e-13
     prob.inner_dtype = 0
+
+
+@pytest.mark.parametrize("n_members", [65, 100, 257])
+def test_ragged_member_counts(gpu_ctx, oracle_lib, n_members):
+    """Member counts that are not a power of two: 65 and 100 pad to 128 slots
+    (cluster path, a second group of 64 lanes mostly padding), 257 pads to 512
+    (the colour path above 256 slots).  The first, a middle and the last
+    member match the oracle and the same member solved alone."""
+    mesh, prob = _small_problem(precision=0, n_members=n_members, n_steps=6, dims=(4, 3, 2), ns=12, tol=1e-12)
+    vs, gr = I.ensemble_members(95, n_members, I.CFG0_LAYERS["vs"])
+    prob.vs = vs
+    prob.gamma_ref = np.tile(gr[:, None], (1, 2))
+    mh = gpu_ctx.mesh(mesh)
+    out = gpu_ctx.solve(mh, mesh, prob)
+    assert out["rc"] == 0 and out["vel"].shape[0] == n_members
+    for m in (0, n_members // 2, n_members - 1):
+        vref, _ = _oracle_vel(oracle_lib, mesh, prob, m)
+        alone = gpu_ctx.solve(mh, mesh, prob, members=[m])
+        e_or = oracle_lib.rel_l2(out["vel"][m], vref)
+        e_al = oracle_lib.rel_l2(out["vel"][m], alone["vel"][0])
+        say(n_members, "members: member", m, "vs oracle", e_or, "vs alone", e_al)
+        assert np.abs(vref).max() > 0 and e_or < 1e-9 and e_al < 1e-12
+
+
+def test_degenerate_inputs(gpu_ctx, oracle_lib, nlth_mod):
+    """A one-cube mesh (6 tets, fewer than one cluster), FP64 and mixed, against
+    the oracle; a record of zero input stays exactly at rest with no CG
+    iterations; a problem of zero steps solves to empty results; stepping an
+    ensemble past its record end does nothing."""
+    for precision in (0, 1):
+        mesh, prob = I.config(0, n_steps=8, mesh_dims=(1, 1, 1), n_members=2, cg_tol=1e-12, precision=precision,
+                              n_springs=12)
+        prob.input_acc = np.ascontiguousarray(prob.input_acc * 5.0)
+        prob.input_acc[1] = 0.0  # member 1: no input
+        mh = gpu_ctx.mesh(mesh)
+        out = gpu_ctx.solve(mh, mesh, prob)
+        assert out["rc"] == 0
+        vref, _ = _oracle_vel(oracle_lib, mesh, prob, 0)
+        err = oracle_lib.rel_l2(out["vel"][0], vref)
+        say("one cube, precision", precision, "member 0 vs oracle", err)
+        assert np.abs(vref).max() > 0 and err < 1e-9
+        assert np.all(out["vel"][1] == 0.0) and np.all(out["iters"][1] == 0)
+    mesh, prob = I.config(0, n_steps=4, mesh_dims=(2, 2, 1), n_members=1, cg_tol=1e-12, n_springs=12)
+    out = gpu_ctx.solve(gpu_ctx.mesh(mesh), mesh, prob, n_steps=0)
+    assert out["rc"] == 0 and out["vel"].size == 0
+    mesh, prob = _small_problem(precision=0, n_steps=4, dims=(2, 2, 1), ns=12)
+    mh = gpu_ctx.mesh(mesh)
+    ens = gpu_ctx.ensemble(mh, mesh, prob)
+    try:
+        ens.step(4)
+        first = ens.read()["vel"].copy()
+        ens.step(3)  # past the end of the record
+        assert ens.stats()["steps_done"] == 4 and np.array_equal(ens.read()["vel"], first)
+    finally:
+        ens.close()
