@@ -1584,7 +1584,7 @@ void Ens::solve_fcg()
             launch_ebe64_tail(s, dm, tail_g, tl, tc.D, tc.h, tc.mat, sc, tc.p, tc.f);
             launch_gather_tail<double>(s, dm, MB, nm, tail_g, tl, tc.f, tc.Ap, act, tc.p, pd, &nblk);
             launch_dashpot_tail<double>(s, dm, MB, nm, tail_g, tl, tc.mat, 2.0 / P.dt, tc.p, tc.Ap, act, pd, &nblk);
-            tstop(t0, &pc_tail32, (int64_t)mesh->ne * h_tlist[0]);
+            tstop(t0, &pc_ebe64, (int64_t)mesh->ne * h_tlist[0]);  // an FP64 operator application
             fin(FIN_ALPHA, 1, nblk, tol2, P.cg_maxit);
             launch_tail_xr_update(s, n, MB, nm, tail_g, tl, tc.x, tc.r, tc.p, tc.Ap, cs.alpha, act, pd, &nblk);
         } else {
