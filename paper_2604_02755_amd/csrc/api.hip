@@ -1099,6 +1099,14 @@ void Ens::dots(int nd, const double* a0, const double* b0, const double* a1, con
     launch_dotsv<double>(s, nd, a0, b0, a1, b1, a2, b2, ndof, MB, nm, nullptr, partial.as<double>(), &nblk);
 }
 
+// members whose flag was set at the last read
+int Ens::count_flags() const
+{
+    int n = 0;
+    for (int m = 0; m < nm; ++m) n += h_flags[m] != 0;
+    return n;
+}
+
 // any member still iterating?  (the flags copied to the host mailbox)
 int Ens::read_any_active(const int* flags)
 {
@@ -1140,6 +1148,7 @@ void Ens::solve_pcg()
         if (!tail64_g) enter_tail64();  // with few members left: compact rows
         run_iters(1, check_every);
         if (!read_any_active(act)) break;
+        if (tail64_g) tail_count = count_flags();
     }
     if (tail64_g) leave_tail64();
 }
@@ -1158,6 +1167,7 @@ bool Ens::enter_tail64()
         return false;
     }
     h_tlist[0] = na;
+    tail_count = na;
     int k = 1;
     for (int m = 0; m < nm; ++m)
         if (h_flags[m]) h_tlist[k++] = m;
@@ -1244,7 +1254,7 @@ void Ens::tail64_iter()
     launch_ebe64_tail(s, dm, tail64_g, tl, tc.D, tc.h, tc.mat, sc, tc.p, tc.f);
     launch_gather_tail<double>(s, dm, MB, nm, tail64_g, tl, tc.f, tc.Ap, act, tc.p, pd, &nblk);
     launch_dashpot_tail<double>(s, dm, MB, nm, tail64_g, tl, tc.mat, 2.0 / P.dt, tc.p, tc.Ap, act, pd, &nblk);
-    tstop(t0, &pc_tail32, (int64_t)mesh->ne * h_tlist[0]);
+    tstop(t0, &pc_tail32, (int64_t)mesh->ne * tail_count);
     fin(FIN_ALPHA, 1, nblk, tol2, P.cg_maxit);
     launch_tail_pcg_update(s, mesh->nn, MB, nm, tail64_g, tl, tc.x, tc.r, tc.z, tc.p, tc.Ap, tc.pinv, cs.alpha, act,
                            pd, &nblk);
@@ -1325,6 +1335,7 @@ void Ens::update_tail()
         tb.f = (float*)(b + off[9]);
     }
     h_tlist[0] = na;
+    tail_count = na;
     int k = 1;
     for (int m = 0; m < nm; ++m)
         if (h_flags[m]) h_tlist[k++] = m;
@@ -1351,7 +1362,7 @@ void Ens::tail_iter()
     launch_ebe32_tail(s, dm, tail_g, tl, tb.D, tb.h, tb.mat, sc, tb.ip, tb.f);
     launch_gather_tail(s, dm, MB, nm, tail_g, tl, tb.f, tb.Ap, iact, tb.ip, pd, &nblk);
     launch_dashpot_tail(s, dm, MB, nm, tail_g, tl, tb.mat, (float)(2.0 / P.dt), tb.ip, tb.Ap, iact, pd, &nblk);
-    tstop(t0, &pc_tail32, (int64_t)mesh->ne * h_tlist[0]);
+    tstop(t0, &pc_tail32, (int64_t)mesh->ne * tail_count);
     fin(FIN_IN_ALPHA, 1, nblk, tol2, P.inner_maxit);
     launch_tail_update(s, mesh->nn, MB, nm, tail_g, tl, tb.ir, tb.w, tb.Ap, tb.pinv, cs.ialpha, iact, pd, &nblk);
     fin(FIN_IN_BETA, 2, nblk, tol2, P.inner_maxit);
@@ -1584,7 +1595,7 @@ void Ens::solve_fcg()
             launch_ebe64_tail(s, dm, tail_g, tl, tc.D, tc.h, tc.mat, sc, tc.p, tc.f);
             launch_gather_tail<double>(s, dm, MB, nm, tail_g, tl, tc.f, tc.Ap, act, tc.p, pd, &nblk);
             launch_dashpot_tail<double>(s, dm, MB, nm, tail_g, tl, tc.mat, 2.0 / P.dt, tc.p, tc.Ap, act, pd, &nblk);
-            tstop(t0, &pc_ebe64, (int64_t)mesh->ne * h_tlist[0]);  // an FP64 operator application
+            tstop(t0, &pc_ebe64, (int64_t)mesh->ne * tail_count);  // an FP64 operator application
             fin(FIN_ALPHA, 1, nblk, tol2, P.cg_maxit);
             launch_tail_xr_update(s, n, MB, nm, tail_g, tl, tc.x, tc.r, tc.p, tc.Ap, cs.alpha, act, pd, &nblk);
         } else {
@@ -1598,6 +1609,8 @@ void Ens::solve_fcg()
         if (!outer_compact) {
             update_tail();
             enter_outer_tail();
+        } else {
+            tail_count = count_flags();  // the listed members still iterating
         }
         if (cheb) cheb_solve();
         else inner_solve();

@@ -115,6 +115,8 @@ struct Ens {
         float *pinv, *ir, *iz, *ip, *w, *Ap, *f;
     } tb{};
     int* h_tlist = nullptr;             // the list in the host mailbox
+    int tail_count = 0;                 // listed members still iterating (profile counts)
+    int count_flags() const;            // flags set at the last read_any_active
     // the same for the plain FP64 PCG: once at most tail_max members are still
     // iterating, their PCG moves to compact rows for the rest of the step
     int tail64_g = 0;
