@@ -165,14 +165,15 @@ void launch_cast32(hipStream_t s, const double* a, float* b, long n)
 
 // Voigt symmetric part of u (x) g  (F_cd = u_c g_d, engineering shear)
 template <typename T>
-__device__ __forceinline__ void vsym_acc(const T u[3], const T g[3], T s, T o[6])
+__device__ __forceinline__ void vsym_acc(const T u[3], const T g[3], T o[6])
 {
-    o[0] += s * u[0] * g[0];
-    o[1] += s * u[1] * g[1];
-    o[2] += s * u[2] * g[2];
-    o[3] += s * (u[0] * g[1] + u[1] * g[0]);
-    o[4] += s * (u[1] * g[2] + u[2] * g[1]);
-    o[5] += s * (u[2] * g[0] + u[0] * g[2]);
+    // each component a chain of fused multiply-adds into the accumulator
+    o[0] = fma(u[0], g[0], o[0]);
+    o[1] = fma(u[1], g[1], o[1]);
+    o[2] = fma(u[2], g[2], o[2]);
+    o[3] = fma(u[0], g[1], fma(u[1], g[0], o[3]));
+    o[4] = fma(u[1], g[2], fma(u[2], g[1], o[4]));
+    o[5] = fma(u[2], g[0], fma(u[0], g[2], o[5]));
 }
 
 // f += s * sigma . g  (sigma in Voigt order xx, yy, zz, xy, yz, zx)
@@ -182,6 +183,15 @@ __device__ __forceinline__ void tdot_acc(const T sg[6], const T g[3], T s, T f[3
     f[0] += s * (sg[0] * g[0] + sg[3] * g[1] + sg[5] * g[2]);
     f[1] += s * (sg[3] * g[0] + sg[1] * g[1] + sg[4] * g[2]);
     f[2] += s * (sg[5] * g[0] + sg[4] * g[1] + sg[2] * g[2]);
+}
+
+// f += sigma . g as chains of fused multiply-adds into f
+template <typename T>
+__device__ __forceinline__ void tdot_add(const T sg[6], const T g[3], T f[3])
+{
+    f[0] = fma(sg[0], g[0], fma(sg[3], g[1], fma(sg[5], g[2], f[0])));
+    f[1] = fma(sg[3], g[0], fma(sg[1], g[1], fma(sg[4], g[2], f[1])));
+    f[2] = fma(sg[5], g[0], fma(sg[4], g[1], fma(sg[2], g[2], f[2])));
 }
 
 // index of D(e, j, k) for member m: elements in blocks of EB so that a
@@ -267,8 +277,11 @@ __device__ __forceinline__ void ebe_element(const DevMesh& M, int MB, int m, lon
     const double dt = sc.dt;
     T sm, sk, cv = 0;
     if (MODE == OP_A) {
-        sm = (T)(rho * (double)vol * (4.0 / (dt * dt) + 2.0 * sc.ahat * he / dt));
-        sk = (T)(1.0 + 2.0 * sc.bhat * he / dt);
+        // the quotients by dt involve kernel arguments only (computed once per
+        // thread), so no FP64 division is left per element
+        const double m4 = 4.0 / (dt * dt), a2 = 2.0 * sc.ahat / dt, b2 = 2.0 * sc.bhat / dt;
+        sm = (T)(rho * (double)vol * (m4 + a2 * he));
+        sk = (T)(1.0 + b2 * he);
     } else if (MODE == OP_K) {
         sm = 0; sk = 1;
     } else if (MODE == OP_M) {
@@ -283,16 +296,23 @@ __device__ __forceinline__ void ebe_element(const DevMesh& M, int MB, int m, lon
 #pragma unroll
     for (int n = 0; n < 10; ++n) nbase[n] = (size_t)nodes[n] * 3 * MB;
     T xk[10][3];
-    // ---- mass: consistent P2 mass applied through corner/edge sums
+    // ---- mass: consistent P2 mass applied through corner/edge sums; with
+    // the scale folded into the coefficients each node's force is a short
+    // chain of fused multiply-adds on the corner and edge sums
+    const T s420 = sm * (T)(1.0 / 420.0);
+    const T c2 = s420 * (T)2, c5 = s420 * (T)5, c6 = s420 * (T)6, c8 = s420 * (T)8, c16 = s420 * (T)16;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         T xm[10];
-        const uint32_t off = (uint32_t)(c * MB + m);
+        // the component's offset joins the uniform base, so every load is a
+        // scalar base plus the member lane
+        const T* x1c = x1 + (size_t)c * MB;
+        const T* x2c = (MODE == OP_RHS) ? x2 + (size_t)c * MB : x2;
 #pragma unroll
         for (int n = 0; n < 10; ++n) {
-            const T v1 = ld_u(x1 + nbase[n], off);
+            const T v1 = ld_u(x1c + nbase[n], (uint32_t)m);
             xk[n][c] = v1;
-            xm[n] = (MODE == OP_RHS) ? ld_u(x2 + nbase[n], off) + cv * v1 : v1;
+            xm[n] = (MODE == OP_RHS) ? ld_u(x2c + nbase[n], (uint32_t)m) + cv * v1 : v1;
         }
         if (MODE == OP_K) {
 #pragma unroll
@@ -301,19 +321,22 @@ __device__ __forceinline__ void ebe_element(const DevMesh& M, int MB, int m, lon
             constexpr int E[6][2] = {{0, 1}, {1, 2}, {2, 0}, {0, 3}, {1, 3}, {2, 3}};
             const T Sc = xm[0] + xm[1] + xm[2] + xm[3];
             const T Se = xm[4] + xm[5] + xm[6] + xm[7] + xm[8] + xm[9];
-            const T s420 = sm * (T)(1.0 / 420.0);
+            // corner i: (5 x_i + Sc + 2 A_i - 6 Se) / 420, A_i = the edges at i;
+            // edge q (a, b): (2 (x_a + x_b) - 6 Sc + 16 x_q + 16 Se - 8 x_opp) / 420
+            const T bc = fma(-c6, Se, s420 * Sc);
+            const T be = fma(c16, Se, -c6 * Sc);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 T A = 0;
 #pragma unroll
                 for (int q = 0; q < 6; ++q)
                     if (E[q][0] == i || E[q][1] == i) A += xm[4 + q];
-                f[i][c] = s420 * ((T)5 * xm[i] + Sc + (T)2 * A - (T)6 * Se);
+                f[i][c] = fma(c5, xm[i], fma(c2, A, bc));
             }
 #pragma unroll
             for (int q = 0; q < 6; ++q)
-                f[4 + q][c] = s420 * ((T)2 * (xm[E[q][0]] + xm[E[q][1]]) - (T)6 * Sc + (T)16 * xm[4 + q] +
-                                      (T)16 * Se - (T)8 * xm[4 + kEdgeOpp[q]]);
+                f[4 + q][c] = fma(c2, xm[E[q][0]] + xm[E[q][1]],
+                                  fma(c16, xm[4 + q], fma(-c8, xm[4 + kEdgeOpp[q]], be)));
         }
     }
     // ---- stiffness (Eq. 2)
@@ -326,7 +349,7 @@ __device__ __forceinline__ void ebe_element(const DevMesh& M, int MB, int m, lon
         for (int k = 0; k < 4; ++k) {
 #pragma unroll
             for (int q = 0; q < 6; ++q) Ek[k][q] = 0;
-            vsym_acc<T>(xk[k], gL[k], (T)1, Ek[k]);
+            vsym_acc<T>(xk[k], gL[k], Ek[k]);
         }
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
@@ -337,8 +360,8 @@ __device__ __forceinline__ void ebe_element(const DevMesh& M, int MB, int m, lon
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
             const T u4[3] = {(T)4 * xk[4 + q][0], (T)4 * xk[4 + q][1], (T)4 * xk[4 + q][2]};
-            vsym_acc<T>(u4, gL[E[q][1]], (T)1, Ek[E[q][0]]);
-            vsym_acc<T>(u4, gL[E[q][0]], (T)1, Ek[E[q][1]]);
+            vsym_acc<T>(u4, gL[E[q][1]], Ek[E[q][0]]);
+            vsym_acc<T>(u4, gL[E[q][0]], Ek[E[q][1]]);
         }
         T S[6];
 #pragma unroll
@@ -382,19 +405,22 @@ __device__ __forceinline__ void ebe_element(const DevMesh& M, int MB, int m, lon
                 T v[6];
 #pragma unroll
                 for (int r = 0; r < 6; ++r) v[r] = (T)4 * sgk[i][r] - T6[r];
-                tdot_acc<T>(v, gL[i], (T)1, f[i]);
+                tdot_add<T>(v, gL[i], f[i]);
             }
+            T T4[6];  // the edges' factor 4 folded into their stress sums
+#pragma unroll
+            for (int r = 0; r < 6; ++r) T4[r] = (T)4 * T6[r];
 #pragma unroll
             for (int q = 0; q < 6; ++q) {
                 const int a = E[q][0], b = E[q][1];
                 T va[6], vb[6];
 #pragma unroll
                 for (int r = 0; r < 6; ++r) {
-                    va[r] = T6[r] + sgk[a][r];
-                    vb[r] = T6[r] + sgk[b][r];
+                    va[r] = fma((T)4, sgk[a][r], T4[r]);
+                    vb[r] = fma((T)4, sgk[b][r], T4[r]);
                 }
-                tdot_acc<T>(va, gL[b], (T)4, f[4 + q]);
-                tdot_acc<T>(vb, gL[a], (T)4, f[4 + q]);
+                tdot_add<T>(va, gL[b], f[4 + q]);
+                tdot_add<T>(vb, gL[a], f[4 + q]);
             }
             return;
         }
