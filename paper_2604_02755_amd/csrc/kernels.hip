@@ -1559,20 +1559,84 @@ void launch_invert_diag(hipStream_t s, int nn, int MB, int nm, const double* dia
 // ---------------------------------------------------------------------------
 
 // normalised skeleton inverse: s with s (1 + |2s|^beta) = e.  Newton in FP32
-// (hardware log2/exp2) from the upper bound min(|e|, (|e| / 2^beta)^(1/(1+beta))),
-// on which the iteration decreases monotonically, then Newton in FP64 until the
-// step is below 2^-44 |s| (quadratic convergence: the error left is ~ step^2,
-// so the root is exact to rounding; two FP64 steps in the usual case).  The
-// FP64 power is evaluated once, p0 = (2 s0)^beta at the FP32 root s0, and at
-// the later iterates s = s0 (1 + d) as p0 (1 + d)^beta from its series, which
-// is exact to rounding for |d| < 1e-4 (the FP32 root is good to ~1e-7).
-// *pw receives |2s|^beta at the last FP64 iterate.
+// (hardware log2/exp2 and reciprocal) from the upper bound
+// min(|e|, (|e| / 2^beta)^(1/(1+beta))), on which the iteration decreases
+// monotonically, then in FP64 until the step is below 2^-44 |s|.  The FP64
+// power is evaluated once, p0 = (2 s0)^beta at the FP32 root s0, and at the
+// later iterates s = s0 (1 + d) as p0 (1 + d)^beta from its series, which is
+// exact to rounding for |d| < 1e-4 (the FP32 root is good to ~1e-7).  The FP64
+// steps divide by the derivative at s0 (a chord step: it differs from the
+// derivative at s by ~1e-7 relative, so each step still squares the error to
+// rounding; two steps in the usual case).  *pw receives |2s|^beta at the last
+// FP64 iterate.
 __device__ __forceinline__ float pow2s_f32(float s, float beta)
 {
     return __builtin_amdgcn_exp2f(beta * __builtin_amdgcn_logf(2.0f * s));
 }
 
 __device__ __forceinline__ double pow2s_f64(double s, double beta) { return exp2(beta * log2(2.0 * s)); }
+
+// 1/x in FP64 from the FP32 hardware reciprocal (1 ulp) and one Newton step:
+// relative error ~1e-14 for x within the FP32 normal range
+__device__ __forceinline__ double rcp_refined(double x)
+{
+    const double r = (double)__builtin_amdgcn_rcpf((float)x);
+    return r * fma(-x, r, 2.0);
+}
+
+// (2 s)^beta for 2 s > 0 in the FP64 normal range, without the library's
+// special-case handling and extra-precise argument: log2 of the mantissa
+// reduced to [sqrt(1/2), sqrt(2)) from the series
+// ln m = 2 (f + f^3/3 + f^5/5 + ...), f = (m - 1)/(m + 1), |f| < 0.172,
+// to f^21; 2^y as 2^n e^t, n = rint(y), |t| <= ln2/2, from the Taylor series
+// of e^t to t^12.  Relative error below 1e-14 while |beta log2(2 s)| < 60.
+// a constant materialised in scalar registers where it is used: keeps the
+// compiler from hoisting the series coefficients below out of the spring loop
+// into vector registers (38 of them, which then spill)
+__device__ __forceinline__ double sconst(double c)
+{
+    asm volatile("" : "+s"(c));
+    return c;
+}
+
+__device__ __forceinline__ double pow2s_fast(double s, double beta)
+{
+    const double x = 2.0 * s;
+    double m = __builtin_amdgcn_frexp_mant(x);  // [0.5, 1)
+    int ex = __builtin_amdgcn_frexp_exp(x);
+    if (m < sconst(0.70710678118654752)) {
+        m *= 2.0;
+        --ex;
+    }
+    const double f = (m - 1.0) * rcp_refined(m + 1.0), f2 = f * f;
+    double q = sconst(1.0 / 21);
+    q = fma(q, f2, sconst(1.0 / 19));
+    q = fma(q, f2, sconst(1.0 / 17));
+    q = fma(q, f2, sconst(1.0 / 15));
+    q = fma(q, f2, sconst(1.0 / 13));
+    q = fma(q, f2, sconst(1.0 / 11));
+    q = fma(q, f2, sconst(1.0 / 9));
+    q = fma(q, f2, sconst(1.0 / 7));
+    q = fma(q, f2, sconst(1.0 / 5));
+    q = fma(q, f2, sconst(1.0 / 3));
+    const double lnm = 2.0 * f * fma(q, f2, 1.0);
+    const double y = beta * fma(lnm, sconst(1.4426950408889634), (double)ex);
+    const double n = __builtin_rint(y), t = (y - n) * sconst(0.69314718055994531);
+    double r = sconst(1.0 / 479001600.0);  // 1/12!
+    r = fma(r, t, sconst(1.0 / 39916800.0));
+    r = fma(r, t, sconst(1.0 / 3628800.0));
+    r = fma(r, t, sconst(1.0 / 362880.0));
+    r = fma(r, t, sconst(1.0 / 40320.0));
+    r = fma(r, t, sconst(1.0 / 5040.0));
+    r = fma(r, t, sconst(1.0 / 720.0));
+    r = fma(r, t, sconst(1.0 / 120.0));
+    r = fma(r, t, sconst(1.0 / 24.0));
+    r = fma(r, t, sconst(1.0 / 6.0));
+    r = fma(r, t, sconst(0.5));
+    r = fma(r, t, 1.0);
+    r = fma(r, t, 1.0);
+    return __builtin_amdgcn_ldexp(r, (int)n);
+}
 
 __device__ __forceinline__ double ro_inverse_pw(double e, double beta, double* pw)
 {
@@ -1581,44 +1645,42 @@ __device__ __forceinline__ double ro_inverse_pw(double e, double beta, double* p
         *pw = a == 0.0 ? 0.0 : pow2s_f64(a, beta);
         return e;
     }
-    const float af = (float)a, bf = (float)beta;
-    float sf = fminf(af, __builtin_amdgcn_exp2f((__builtin_amdgcn_logf(af) - bf) / (1.0f + bf)));
+    const float af = (float)a, bf = (float)beta, bp1f = 1.0f + bf;
+    float sf = fminf(af, __builtin_amdgcn_exp2f((__builtin_amdgcn_logf(af) - bf) * __builtin_amdgcn_rcpf(bp1f)));
 #pragma unroll 1
     for (int it = 0; it < 12; ++it) {
         const float p = pow2s_f32(sf, bf);
         const float f = sf * (1.0f + p) - af;
         if (f <= 0.0f) break;
-        const float ds = f / (1.0f + (1.0f + bf) * p);
+        const float ds = f * __builtin_amdgcn_rcpf(fmaf(bp1f, p, 1.0f));
         sf -= ds;
         if (ds <= 1e-7f * sf) break;
     }
-    const double s0 = (double)sf, p0 = pow2s_f64(s0, beta);
-    const double c1 = beta, c2 = 0.5 * beta * (beta - 1.0), c3 = c2 * (beta - 2.0) / 3.0;
-    double s = s0, p = p0;
+    const double c1 = beta, c2 = 0.5 * beta * (beta - 1.0), c3 = c2 * (beta - 2.0) * (1.0 / 3.0);
+    double s = (double)sf, s0 = 0.0, p0 = 0.0, r0 = 0.0, rd = 0.0, p = 0.0;
+    bool fresh = true;  // take the power afresh at the current iterate
 #pragma unroll 1
     for (int it = 0; it < 60; ++it) {
-        const double ds = (s * (1.0 + p) - a) / (1.0 + (1.0 + beta) * p);
+        if (fresh) {
+            s0 = s;
+            p0 = p = pow2s_fast(s0, beta);
+            r0 = rcp_refined(s0);
+            rd = rcp_refined(fma(1.0 + beta, p0, 1.0));
+        }
+        const double ds = fma(s, 1.0 + p, -a) * rd;
         s -= ds;
-        const double d = (s - s0) / s0;
-        p = fabs(d) < 1e-4 ? p0 * (1.0 + d * (c1 + d * (c2 + d * c3))) : pow2s_f64(s, beta);
-        if (fabs(ds) <= 0x1p-44 * s) break;
+        const double d = (s - s0) * r0;
+        fresh = !(fabs(d) < 1e-4);  // far from the FP32 root (its iteration cap)
+        if (!fresh) {
+            p = p0 * fma(d, fma(d, fma(d, c3, c2), c1), 1.0);
+            if (fabs(ds) <= 0x1p-44 * s) break;
+        }
     }
     *pw = p;
     return e < 0 ? -s : s;
 }
 
-__device__ __forceinline__ double ro_inverse(double e, double beta)
-{
-    double pw;
-    return ro_inverse_pw(e, beta, &pw);
-}
-
 struct SpringPar { double G0, gref, hmax, beta; };
-
-__device__ __forceinline__ double skeleton_tau(double g, const SpringPar& p)
-{
-    return p.G0 * p.gref * ro_inverse(g / p.gref, p.beta);
-}
 
 // Law state of a chunk of ecp elements (ecp a multiple of EB): four FP64
 // fields (gp, gr, tr, gm) then one int32 field packing the loading direction,
@@ -1807,6 +1869,7 @@ __global__ __launch_bounds__(256, LDS_NS > 0 ? 4 : 1) void k_law(DevMesh M, int 
     P.hmax = matv(mat, l, MAT_HMAX, MB, m);
     P.beta = matv(mat, l, MAT_BETA, MB, m);
     const double Kb = matv(mat, l, MAT_KB, MB, m);
+    const double rgref = 1.0 / P.gref;
     // strain increment at point j, node by node (gradient of N_n at the point
     // times the node's increment)
     double ej[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -1839,6 +1902,16 @@ __global__ __launch_bounds__(256, LDS_NS > 0 ? 4 : 1) void k_law(DevMesh M, int 
     ThetaView th = theta_view(theta, ecp, ns, MB);
     const long fn = th.field_n;
     __shared__ double cgs[LDS_NS > 0 ? LDS_NS * 256 : 1];
+    if (LDS_NS > 0) {
+        // each spring's strain increment waits in its LDS slot (the slot takes
+        // c_k G_k after the update), so the strain is not live across the loop
+#pragma unroll 1
+        for (int sp = 0; sp < ns; ++sp) {
+            const double* n = dirs + 6 * sp;
+            cgs[sp * 256 + threadIdx.x] =
+                n[0] * ej[0] + n[1] * ej[1] + n[2] * ej[2] + n[3] * ej[3] + n[4] * ej[4] + n[5] * ej[5];
+        }
+    }
     double d[21];
 #pragma unroll
     for (int k = 0; k < 21; ++k) d[k] = 0;
@@ -1850,7 +1923,9 @@ __global__ __launch_bounds__(256, LDS_NS > 0 ? 4 : 1) void k_law(DevMesh M, int 
 #pragma unroll 1
     for (int sp = 0; sp < ns; ++sp) {
         const double* n = dirs + 6 * sp;
-        const double dg = n[0] * ej[0] + n[1] * ej[1] + n[2] * ej[2] + n[3] * ej[3] + n[4] * ej[4] + n[5] * ej[5];
+        const double dg = LDS_NS > 0 ? cgs[sp * 256 + threadIdx.x]
+                                     : n[0] * ej[0] + n[1] * ej[1] + n[2] * ej[2] + n[3] * ej[3] + n[4] * ej[4] +
+                                           n[5] * ej[5];
         const long idx = nidx;
         double gp = ngp, gr = ngr, tr = ntr, gm = ngm;
         int dir = (nfl & 3) - 1, skel = (nfl >> 2) & 1;
@@ -1871,7 +1946,7 @@ __global__ __launch_bounds__(256, LDS_NS > 0 ? 4 : 1) void k_law(DevMesh M, int 
                     // the reversal stress now (a closed loop below may replace the branch), and the
                     // origin of the branch being left kept (the oldest dropped when full)
                     double pk;
-                    const double sv = ro_inverse_pw(rev_arg / P.gref, P.beta, &pk);
+                    const double sv = ro_inverse_pw(rev_arg * rgref, P.beta, &pk);
                     const double trev = rev == 1 ? P.G0 * P.gref * sv : tr + 2.0 * P.G0 * P.gref * sv;
                     if (!skel) {
                         if (cnt == depth - 1) {
@@ -1917,7 +1992,7 @@ __global__ __launch_bounds__(256, LDS_NS > 0 ? 4 : 1) void k_law(DevMesh M, int 
             if (k == 0 ? rev == 0 : (k == 2 && !em_own)) continue;
             const double arg = k == 0 ? rev_arg : (k == 1 ? xi : gm);
             double pk;
-            const double sv = ro_inverse_pw(arg / P.gref, P.beta, &pk);
+            const double sv = ro_inverse_pw(arg * rgref, P.beta, &pk);
             if (k == 0) s_rev = sv;
             else if (k == 1) { s_xi = sv; pw = pk; }
             else s_em = sv;
@@ -1929,10 +2004,7 @@ __global__ __launch_bounds__(256, LDS_NS > 0 ? 4 : 1) void k_law(DevMesh M, int 
         }
         const double Gt = P.G0 / (1.0 + (1.0 + P.beta) * pw);
         double hk = 0.0;
-        if (gm > 0.0) {
-            const double em = gm / P.gref;
-            hk = P.hmax * (1.0 - (em_own ? s_em : fabs(s_xi)) / em);
-        }
+        if (gm > 0.0) hk = P.hmax * (1.0 - (em_own ? s_em : fabs(s_xi)) * P.gref / gm);
         hs += hk;
         const double c = w[sp] * Gt;
         if (LDS_NS > 0) {
