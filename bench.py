@@ -91,17 +91,18 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(src_hash: str, element_members_per_launch: float):
+def traffic_from_profile(src_hash: str, element_members_per_launch: float, cluster_blocks: int):
     """HBM bytes per launch of the inner operator's element kernel from the
     committed rocprofv3 --pmc summary (FETCH_SIZE and WRITE_SIZE scaled by
     the copy calibration), taken per element-member and applied to this run's
-    launches; None if the summary was taken on other kernel sources."""
+    launches; None if the summary was taken on other kernel sources or with
+    another number of cluster blocks per CU (which changes the L2 reuse)."""
     p = os.path.join(ROOT, "profiles", "inner_operator_traffic_64x64x32.json")
     if not os.path.exists(p):
         return None
     with open(p) as fh:
         d = json.load(fh)
-    if d.get("kernel_source_hash") != src_hash:
+    if d.get("kernel_source_hash") != src_hash or d.get("cluster_blocks") != cluster_blocks:
         return None
     return round(d["element"]["bytes_per_element_member"] * element_members_per_launch, 0)
 
@@ -520,9 +521,9 @@ def main():
         gbs = per_unit * units / (ms * 1e-3) / 1e9
         tfl = flops * units / (ms * 1e-3) / 1e12
         src = kernel_source_hash()
-        tb = traffic_from_profile(src, units / n_app)
-        achieved, peak = (tfl, FP32_PEAK_TFLOPS) if alu else (gbs, HBM_PEAK_GBS)
         cb = (tuned or {}).get("cluster_blocks", 3)
+        tb = traffic_from_profile(src, units / n_app, cb)
+        achieved, peak = (tfl, FP32_PEAK_TFLOPS) if alu else (gbs, HBM_PEAK_GBS)
         roofline = {"bound": "alu" if alu else "hbm", "achieved": round(achieved, 2), "peak": peak,
                     "unit": "TFLOP/s" if alu else "GB/s", "frac": round(achieved / peak, 4),
                     "traffic": tb,

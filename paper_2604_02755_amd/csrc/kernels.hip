@@ -1927,7 +1927,7 @@ __global__ __launch_bounds__(256, LDS_NS > 0 ? 4 : 1) void k_law(DevMesh M, int 
                                      : n[0] * ej[0] + n[1] * ej[1] + n[2] * ej[2] + n[3] * ej[3] + n[4] * ej[4] +
                                            n[5] * ej[5];
         const long idx = nidx;
-        double gp = ngp, gr = ngr, tr = ntr, gm = ngm;
+        double gp = ngp, gr = ngr, tr = ntr, sm = ngm;
         int dir = (nfl & 3) - 1, skel = (nfl >> 2) & 1;
         int cnt = MEM ? nfl >> 3 : 0;  // older reversal points kept
         if (sp + 1 < ns) {
@@ -1935,19 +1935,37 @@ __global__ __launch_bounds__(256, LDS_NS > 0 ? 4 : 1) void k_law(DevMesh M, int 
             ngp = th.d[nidx]; ngr = th.d[fn + nidx]; ntr = th.d[2 * fn + nidx]; ngm = th.d[3 * fn + nidx];
             nfl = th.i[nidx];
         }
-        int rev = 0;           // 1: reversal on the skeleton, 2: reversal on a branch
-        double rev_arg = 0.0;  // strain whose skeleton stress the reversal needs
-        if (dg != 0.0) {
-            const int dsg = dg > 0.0 ? 1 : -1;
-            if (dir != 0 && dsg != dir) {  // reversal: a Masing branch starts here
-                rev = skel ? 1 : 2;
-                rev_arg = skel ? gp : 0.5 * (gp - gr);
+        const int dsg = dg > 0.0 ? 1 : (dg < 0.0 ? -1 : 0);
+        const bool reverse = dsg != 0 && dir != 0 && dsg != dir;
+        // largest strain reached on the skeleton: |gp| while on it; off it, from
+        // the stored normalised skeleton stress sm through the explicit forward
+        // relation gm = gref sm (1 + pm), pm = (2 sm)^beta, whose power also
+        // gives the damping of an off-skeleton spring
+        double pm = 0.0, gm = fabs(gp);
+        if ((!skel || reverse) && sm > 0.0) {
+            pm = pow2s_fast(sm, P.beta);
+            if (!skel) gm = P.gref * sm * (1.0 + pm);
+        }
+        bool rev2 = false;     // reversal on a branch: the skeleton inverted at rev_arg
+        double rev_arg = 0.0;
+        if (dsg != 0) {
+            if (reverse) {  // a Masing branch starts here
+                double trev = 0.0;
+                if (skel) {
+                    // the skeleton stress at gp = +-gm is +-sm (stored by the last update on the skeleton)
+                    trev = P.G0 * P.gref * copysign(sm, gp);
+                } else {
+                    rev_arg = 0.5 * (gp - gr);
+                    if (MEM) {
+                        double pk;
+                        trev = tr + 2.0 * P.G0 * P.gref * ro_inverse_pw(rev_arg * rgref, P.beta, &pk);
+                    } else {
+                        rev2 = true;
+                    }
+                }
                 if (MEM) {
-                    // the reversal stress now (a closed loop below may replace the branch), and the
-                    // origin of the branch being left kept (the oldest dropped when full)
-                    double pk;
-                    const double sv = ro_inverse_pw(rev_arg * rgref, P.beta, &pk);
-                    const double trev = rev == 1 ? P.G0 * P.gref * sv : tr + 2.0 * P.G0 * P.gref * sv;
+                    // the origin of the branch being left is kept (the oldest dropped when
+                    // full); a closed loop below may replace the new branch
                     if (!skel) {
                         if (cnt == depth - 1) {
                             for (int k = 0; k + 1 < cnt; ++k) {
@@ -1960,9 +1978,8 @@ __global__ __launch_bounds__(256, LDS_NS > 0 ? 4 : 1) void k_law(DevMesh M, int 
                         th.od[(2 * cnt + 1) * fn + idx] = tr;
                         ++cnt;
                     }
-                    tr = trev;
-                    rev = 0;
                 }
+                if (!rev2) tr = trev;
                 gr = gp;
                 skel = 0;
             }
@@ -1979,32 +1996,30 @@ __global__ __launch_bounds__(256, LDS_NS > 0 ? 4 : 1) void k_law(DevMesh M, int 
                     cnt -= 2;
                 }
             }
-            if (skel) gm = fmax(gm, fabs(g));
             gp = g;
         }
         const double xi = skel ? gp : 0.5 * (gp - gr);
-        // on the skeleton gm == |gp| reuses the inverse at xi for the damping
-        const bool em_own = gm > 0.0 && !(skel && fabs(gp) == gm);
-        // up to three skeleton inversions through one copy of the solver
-        double s_rev = 0.0, s_xi = 0.0, s_em = 0.0, pw = 0.0;
+        // the inversions through one copy of the solver: a branch reversal's, then xi's
+        double s_rev = 0.0, s_xi = 0.0, pw = 0.0;
 #pragma unroll 1
-        for (int k = 0; k < 3; ++k) {
-            if (k == 0 ? rev == 0 : (k == 2 && !em_own)) continue;
-            const double arg = k == 0 ? rev_arg : (k == 1 ? xi : gm);
+        for (int k = 0; k < 2; ++k) {
+            if (k == 0 && !rev2) continue;
             double pk;
-            const double sv = ro_inverse_pw(arg * rgref, P.beta, &pk);
+            const double sv = ro_inverse_pw((k == 0 ? rev_arg : xi) * rgref, P.beta, &pk);
             if (k == 0) s_rev = sv;
-            else if (k == 1) { s_xi = sv; pw = pk; }
-            else s_em = sv;
+            else { s_xi = sv; pw = pk; }
         }
-        if (rev) tr = rev == 1 ? P.G0 * P.gref * s_rev : tr + 2.0 * P.G0 * P.gref * s_rev;
-        if (dg != 0.0) {
-            th.d[idx] = gp; th.d[fn + idx] = gr; th.d[2 * fn + idx] = tr; th.d[3 * fn + idx] = gm;
+        if (rev2) tr += 2.0 * P.G0 * P.gref * s_rev;
+        if (skel) sm = fabs(s_xi);  // on the skeleton gm = |gp|
+        if (dsg != 0) {
+            th.d[idx] = gp; th.d[fn + idx] = gr; th.d[2 * fn + idx] = tr; th.d[3 * fn + idx] = sm;
             th.i[idx] = theta_flags(dir, skel) | (cnt << 3);
         }
         const double Gt = P.G0 / (1.0 + (1.0 + P.beta) * pw);
-        double hk = 0.0;
-        if (gm > 0.0) hk = P.hmax * (1.0 - (em_own ? s_em : fabs(s_xi)) * P.gref / gm);
+        // damping 1 - S(em)/em at em = gm/gref: with em = s (1 + (2s)^beta) at s = S(em)
+        // it is p/(1 + p), p the power at the skeleton stress of the largest strain
+        const double ph = skel ? pw : pm;
+        const double hk = P.hmax * ph / (1.0 + ph);
         hs += hk;
         const double c = w[sp] * Gt;
         if (LDS_NS > 0) {
