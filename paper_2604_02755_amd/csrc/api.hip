@@ -1303,7 +1303,8 @@ void Ens::update_tail()
     if (na == 0 || na > tail_max) return;
     if (!tail_mem.p) {
         // compact rows of 32 lanes: D (elements padded to blocks of 4), h,
-        // material, inverse blocks, five CG vectors, element outputs
+        // material, inverse blocks, five CG vectors, the operator's cluster
+        // rows (at most 10 per element: sized as element outputs)
         const size_t ne4 = ((size_t)mesh->ne + 3) / 4 * 4, nn = mesh->nn, L = 32;
         const size_t sz[10] = {ne4 * 11 * L * 4, (size_t)mesh->ne * L * 8, (size_t)P.nl * MAT_N * L * 8,
                                nn * 6 * L * 4, nn * 3 * L * 4, nn * 3 * L * 4, nn * 3 * L * 4, nn * 3 * L * 4,
@@ -1347,7 +1348,7 @@ void Ens::update_tail()
 }
 
 // one inner CG iteration of the listed members on the compact rows: the
-// operator (element outputs, node sums, dashpot), then the updates of the
+// operator (cluster rows, node sums, dashpot), then the updates of the
 // full path with the same per-member stage logic
 void Ens::tail_iter()
 {
@@ -1359,8 +1360,8 @@ void Ens::tail_iter()
     int nblk;
     hipEvent_t t0;
     tstart(t0);
-    launch_ebe32_tail(s, dm, tail_g, tl, tb.D, tb.h, tb.mat, sc, tb.ip, tb.f);
-    launch_gather_tail(s, dm, MB, nm, tail_g, tl, tb.f, tb.Ap, iact, tb.ip, pd, &nblk);
+    launch_ebe32_ctail(s, dm, tail_g, tl, tb.D, tb.h, tb.mat, sc, tb.ip, tb.f);
+    launch_gather_tail(s, dm, MB, nm, tail_g, tl, tb.f, tb.Ap, iact, tb.ip, pd, &nblk, true);
     launch_dashpot_tail(s, dm, MB, nm, tail_g, tl, tb.mat, (float)(2.0 / P.dt), tb.ip, tb.Ap, iact, pd, &nblk);
     tstop(t0, &pc_tail32, (int64_t)mesh->ne * tail_count);
     fin(FIN_IN_ALPHA, 1, nblk, tol2, P.inner_maxit);

@@ -907,6 +907,84 @@ void launch_ebe32_tail(hipStream_t s, const DevMesh& M, int G, const int* tl, co
         hipLaunchKernelGGL((k_ebe_tail<float, 4, 32>), dim3(nblocks(n)), dim3(256), 0, s, M, tl, cD, ch, cmat, sc, x, f);
 }
 
+// operator A on the compact rows summed per element cluster (the compact form
+// of k_ebe_cluster): one block per cluster; a wavefront holds 64/G element
+// slots of G lanes, and each slot adds its element's forces into its own copy
+// of the cluster's node rows in LDS (the slots of a wavefront run in
+// lockstep), the wavefronts one after another; on the way out the copies are
+// summed in slot order and written as G-wide cluster rows
+// co[(row * 3 + c) * G + k], which the cluster-row gather completes.  The
+// order of every sum is fixed.  The cluster rows take about a third of the
+// element outputs' bytes, written once and read once.
+template <typename T, int DK, int G>
+__global__ __launch_bounds__(256) void k_ebe_ctail(DevMesh M, const int* __restrict__ tl, const void* __restrict__ cD,
+                                                  const double* __restrict__ ch, const double* __restrict__ cmat,
+                                                  StepConst sc, const T* __restrict__ x, T* __restrict__ co)
+{
+    constexpr int S = 64 / G, SLOTS = 4 * S, ROWS = kClusterNodes * 3 * G;
+    __shared__ T ys[S * ROWS];
+    const int c = (int)((blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8);  // XCD-contiguous clusters
+    if (c >= M.ncl) return;  // whole block: padding of the grid to a multiple of 8
+    const int t = threadIdx.x, k = t % G, slot = t / G, sw = (t & 63) / G;
+    const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int e0 = M.cl_off[c], nec = M.cl_off[c + 1] - e0;
+    const int r0 = M.cl_noff[c], n3 = (M.cl_noff[c + 1] - r0) * 3 * G;
+    for (int i = t; i < S * n3; i += 256) ys[(i / n3) * ROWS + i % n3] = (T)0;
+    const bool act = k < min(tl[0], G);
+    T* yc = ys + sw * ROWS;
+    __syncthreads();
+    for (int r = 0; r < nec; r += SLOTS) {
+        const int le = r + slot;
+        T f[10][3];
+        if (le < nec && act) {
+            size_t nbase[10];
+            ebe_element<T, DK, OP_A>(M, G, k, e0 + le, cD, ch, cmat, sc, x, nullptr, f, nbase);
+        } else {
+#pragma unroll
+            for (int n = 0; n < 10; ++n) f[n][0] = f[n][1] = f[n][2] = (T)0;
+        }
+        uint32_t lw[3] = {0u, 0u, 0u};
+        if (le < nec) {
+            const uint32_t* lp = M.cl_lconn + (size_t)(e0 + le) * 4;
+            lw[0] = lp[0];
+            lw[1] = lp[1];
+            lw[2] = lp[2];
+        }
+        for (int ww = 0; ww < 4; ++ww) {
+            __syncthreads();
+            if (w == ww && le < nec) {
+#pragma unroll
+                for (int n = 0; n < 10; ++n) {
+                    T* yr = yc + (int)((lw[n / 4] >> (8 * (n % 4))) & 0xFFu) * 3 * G + k;
+                    yr[0] += f[n][0];
+                    yr[G] += f[n][1];
+                    yr[2 * G] += f[n][2];
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = t; i < n3; i += 256) {
+        T v = ys[i];
+#pragma unroll
+        for (int q = 1; q < S; ++q) v += ys[q * ROWS + i];
+        co[(size_t)r0 * 3 * G + i] = v;
+    }
+}
+
+void launch_ebe32_ctail(hipStream_t s, const DevMesh& M, int G, const int* tl, const uint32_t* cD, const double* ch,
+                        const double* cmat, StepConst sc, const float* x, float* co)
+{
+    long g = (M.ncl + 7) / 8 * 8;
+    if (M.ncl <= 0) return;
+    if (G == 16)
+        hipLaunchKernelGGL((k_ebe_ctail<float, 4, 16>), dim3((unsigned)g), dim3(256), 0, s, M, tl, cD, ch, cmat, sc, x,
+                           co);
+    else
+        hipLaunchKernelGGL((k_ebe_ctail<float, 4, 32>), dim3((unsigned)g), dim3(256), 0, s, M, tl, cD, ch, cmat, sc, x,
+                           co);
+}
+
 void launch_ebe64_tail(hipStream_t s, const DevMesh& M, int G, const int* tl, const double* cD, const double* ch,
                        const double* cmat, StepConst sc, const double* x, double* f)
 {
@@ -921,9 +999,10 @@ void launch_ebe64_tail(hipStream_t s, const DevMesh& M, int G, const int* tl, co
 }
 
 // node sums of the compact element outputs (incidences in ascending order)
-// into the compact y of the listed, active members; with partial, the x . y
-// partials of the block's nodes
-template <typename T, int G>
+// or, with CL, of the compact cluster rows (the node's rows in ascending
+// order) into the compact y of the listed, active members; with partial, the
+// x . y partials of the block's nodes
+template <typename T, int G, bool CL>
 __global__ __launch_bounds__(256) void k_gather_tail(DevMesh M, int MB, int nm, const int* __restrict__ tl,
                                                     const T* __restrict__ fc, T* __restrict__ y,
                                                     const int* __restrict__ active, const T* __restrict__ x,
@@ -939,14 +1018,25 @@ __global__ __launch_bounds__(256) void k_gather_tail(DevMesh M, int MB, int nm, 
     if (act) {
         for (long nd = n0 + slot; nd < n1; nd += NPB) {
             T a0 = 0, a1 = 0, a2 = 0;
-            const int q1 = M.inc_ptr[nd + 1];
+            if (CL) {
+                const int q1 = M.cn_ptr[nd + 1];
 #pragma unroll 4
-            for (int q = M.inc_ptr[nd]; q < q1; ++q) {
-                // incidence e * 10 + local node: its output rows start at 3 * incidence
-                const T* fb = fc + (size_t)3 * M.inc[q] * G + k;
-                a0 += fb[0];
-                a1 += fb[G];
-                a2 += fb[2 * G];
+                for (int q = M.cn_ptr[nd]; q < q1; ++q) {
+                    const T* fb = fc + (size_t)3 * M.cn_row[q] * G + k;
+                    a0 += fb[0];
+                    a1 += fb[G];
+                    a2 += fb[2 * G];
+                }
+            } else {
+                const int q1 = M.inc_ptr[nd + 1];
+#pragma unroll 4
+                for (int q = M.inc_ptr[nd]; q < q1; ++q) {
+                    // incidence e * 10 + local node: its output rows start at 3 * incidence
+                    const T* fb = fc + (size_t)3 * M.inc[q] * G + k;
+                    a0 += fb[0];
+                    a1 += fb[G];
+                    a2 += fb[2 * G];
+                }
             }
             const size_t yi = (size_t)nd * 3 * G + k;
             y[yi] = a0;
@@ -964,19 +1054,30 @@ __global__ __launch_bounds__(256) void k_gather_tail(DevMesh M, int MB, int nm, 
 
 template <typename T>
 void launch_gather_tail(hipStream_t s, const DevMesh& M, int MB, int nm, int G, const int* tl, const T* fc, T* y,
-                        const int* active, const T* x, double* partial, int* nblk)
+                        const int* active, const T* x, double* partial, int* nblk, bool clusters)
 {
     const int g = gather_blocks(M.nn, G, partial ? kGatherBlocks : (1 << 24));
     if (partial) *nblk = g;
-    if (G == 16)
-        hipLaunchKernelGGL((k_gather_tail<T, 16>), dim3(g), dim3(256), 0, s, M, MB, nm, tl, fc, y, active, x, partial);
-    else
-        hipLaunchKernelGGL((k_gather_tail<T, 32>), dim3(g), dim3(256), 0, s, M, MB, nm, tl, fc, y, active, x, partial);
+    if (clusters) {
+        if (G == 16)
+            hipLaunchKernelGGL((k_gather_tail<T, 16, true>), dim3(g), dim3(256), 0, s, M, MB, nm, tl, fc, y, active, x,
+                               partial);
+        else
+            hipLaunchKernelGGL((k_gather_tail<T, 32, true>), dim3(g), dim3(256), 0, s, M, MB, nm, tl, fc, y, active, x,
+                               partial);
+    } else {
+        if (G == 16)
+            hipLaunchKernelGGL((k_gather_tail<T, 16, false>), dim3(g), dim3(256), 0, s, M, MB, nm, tl, fc, y, active, x,
+                               partial);
+        else
+            hipLaunchKernelGGL((k_gather_tail<T, 32, false>), dim3(g), dim3(256), 0, s, M, MB, nm, tl, fc, y, active, x,
+                               partial);
+    }
 }
 template void launch_gather_tail<float>(hipStream_t, const DevMesh&, int, int, int, const int*, const float*, float*,
-                                        const int*, const float*, double*, int*);
+                                        const int*, const float*, double*, int*, bool);
 template void launch_gather_tail<double>(hipStream_t, const DevMesh&, int, int, int, const int*, const double*,
-                                         double*, const int*, const double*, double*, int*);
+                                         double*, const int*, const double*, double*, int*, bool);
 
 template <typename T>
 void launch_ebe(hipStream_t s, OpMode mode, const DevMesh& M, int MB, int nm, int e0, int e1, const T* D,

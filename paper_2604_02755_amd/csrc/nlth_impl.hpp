@@ -143,9 +143,14 @@ void launch_ebe32_tail(hipStream_t s, const DevMesh& M, int G, const int* tl, co
                        const double* cmat, StepConst sc, const float* x, float* f);
 void launch_ebe64_tail(hipStream_t s, const DevMesh& M, int G, const int* tl, const double* cD, const double* ch,
                        const double* cmat, StepConst sc, const double* x, double* f);
+// the mixed path's inner operator on the compact rows summed per element
+// cluster: G-wide cluster rows co[(row * 3 + c) * G + k] for the gather with
+// clusters = true
+void launch_ebe32_ctail(hipStream_t s, const DevMesh& M, int G, const int* tl, const uint32_t* cD, const double* ch,
+                        const double* cmat, StepConst sc, const float* x, float* co);
 template <typename T>
 void launch_gather_tail(hipStream_t s, const DevMesh& M, int MB, int nm, int G, const int* tl, const T* fc, T* y,
-                        const int* active, const T* x, double* partial, int* nblk);
+                        const int* active, const T* x, double* partial, int* nblk, bool clusters = false);
 template <typename T>
 void launch_dashpot_tail(hipStream_t s, const DevMesh& M, int MB, int nm, int G, const int* tl, const double* cmat,
                          T coef, const T* x, T* y, const int* active, double* partial, int* nblk);
