@@ -1184,7 +1184,8 @@ bool Ens::enter_tail64()
 }
 
 // FP64 compact rows of 32 lanes: D per point (elements padded to blocks of
-// 4), h, material, inverse blocks, five CG vectors, element outputs
+// 4), h, material, inverse blocks, five CG vectors, the operator's cluster
+// rows (at most 10 per element: sized as element outputs)
 bool Ens::alloc_tail64()
 {
     if (tail64_mem.p) return true;
@@ -1251,8 +1252,8 @@ void Ens::tail64_iter()
     int nblk;
     hipEvent_t t0;
     tstart(t0);
-    launch_ebe64_tail(s, dm, tail64_g, tl, tc.D, tc.h, tc.mat, sc, tc.p, tc.f);
-    launch_gather_tail<double>(s, dm, MB, nm, tail64_g, tl, tc.f, tc.Ap, act, tc.p, pd, &nblk);
+    launch_ebe64_ctail(s, dm, tail64_g, tl, tc.D, tc.h, tc.mat, sc, tc.p, tc.f);
+    launch_gather_tail<double>(s, dm, MB, nm, tail64_g, tl, tc.f, tc.Ap, act, tc.p, pd, &nblk, true);
     launch_dashpot_tail<double>(s, dm, MB, nm, tail64_g, tl, tc.mat, 2.0 / P.dt, tc.p, tc.Ap, act, pd, &nblk);
     tstop(t0, &pc_tail32, (int64_t)mesh->ne * tail_count);
     fin(FIN_ALPHA, 1, nblk, tol2, P.cg_maxit);
@@ -1593,8 +1594,8 @@ void Ens::solve_fcg()
             const int* tl = tlist.as<int>();
             hipEvent_t t0;
             tstart(t0);
-            launch_ebe64_tail(s, dm, tail_g, tl, tc.D, tc.h, tc.mat, sc, tc.p, tc.f);
-            launch_gather_tail<double>(s, dm, MB, nm, tail_g, tl, tc.f, tc.Ap, act, tc.p, pd, &nblk);
+            launch_ebe64_ctail(s, dm, tail_g, tl, tc.D, tc.h, tc.mat, sc, tc.p, tc.f);
+            launch_gather_tail<double>(s, dm, MB, nm, tail_g, tl, tc.f, tc.Ap, act, tc.p, pd, &nblk, true);
             launch_dashpot_tail<double>(s, dm, MB, nm, tail_g, tl, tc.mat, 2.0 / P.dt, tc.p, tc.Ap, act, pd, &nblk);
             tstop(t0, &pc_ebe64, (int64_t)mesh->ne * tail_count);  // an FP64 operator application
             fin(FIN_ALPHA, 1, nblk, tol2, P.cg_maxit);

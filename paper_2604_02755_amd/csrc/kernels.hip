@@ -524,9 +524,10 @@ __global__ __launch_bounds__(256) void k_ebe(DevMesh M, int MB, int nm, int e0, 
 // co[(row * 3 + c) * MB + m] (row = the cluster's first row + local node) and
 // a gather over the node -> rows lists finishes the sum.
 // LDS of a cluster block: the node rows, padded so that NB blocks share a CU
-// (160 KB of LDS per CU, allocated in 8 KB steps).  Three FP32 blocks per CU
-// measured fastest: four thrash the L2 that holds the nodal rows shared by
-// neighbouring clusters, two leave too few wavefronts to cover latency.
+// (160 KB of LDS per CU, allocated in 8 KB steps).  With one bfloat16 D per
+// element four FP32 blocks per CU run fastest; with D per point four thrash
+// the L2 that holds the nodal rows shared by neighbouring clusters and three
+// are faster; two leave too few wavefronts to cover latency.
 template <typename T, int NB>
 constexpr int cluster_lds_elems()
 {
@@ -804,8 +805,8 @@ void launch_ebe32(hipStream_t s, const DevMesh& M, int MB, int nm, int e0, int e
 // element-mean D, h, the material rows and the FP32 block-Jacobi inverse once
 // per outer iteration for its inner CG; the FP64 PCG packs the FP64 D per
 // point, h, the material rows, its inverse and the CG vectors once per step.
-// The operator writes compact element outputs, summed per node into a compact
-// result.  Partial sums keep the full [block][MB] layout (zero for members not
+// The operator sums its element forces per element cluster into compact
+// cluster rows, which a gather sums per node into a compact result.  Partial sums keep the full [block][MB] layout (zero for members not
 // listed), so the per-member stage logic is the same.
 // ---------------------------------------------------------------------------
 
@@ -874,39 +875,6 @@ void launch_tail_rows64(hipStream_t s, long nrows, int MB, int G, const int* tl,
     tail_rows<double>(s, nrows, MB, G, 1, 1, tl, src, dst, unpack);
 }
 
-// operator A on the compact rows: lane (element, k); the mixed path's inner
-// operator (FP32, element-mean bfloat16 D) or the FP64 operator (D per
-// point); outputs f[(e * 30 + 3n + c) * G + k]
-template <typename T, int DK, int G>
-__global__ __launch_bounds__(256) void k_ebe_tail(DevMesh M, const int* __restrict__ tl, const void* __restrict__ cD,
-                                                 const double* __restrict__ ch, const double* __restrict__ cmat,
-                                                 StepConst sc, const T* __restrict__ x, T* __restrict__ f)
-{
-    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    const int k = (int)(t % G);
-    const long e = t / G;
-    if (e >= M.ne || k >= min(tl[0], G)) return;
-    T fe[10][3];
-    size_t nbase[10];
-    ebe_element<T, DK, OP_A>(M, G, k, e, cD, ch, cmat, sc, x, nullptr, fe, nbase);
-    T* fb = f + (size_t)e * 30 * G + k;
-#pragma unroll
-    for (int n = 0; n < 10; ++n)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) fb[(3 * n + c) * G] = fe[n][c];
-}
-
-void launch_ebe32_tail(hipStream_t s, const DevMesh& M, int G, const int* tl, const uint32_t* cD, const double* ch,
-                       const double* cmat, StepConst sc, const float* x, float* f)
-{
-    const long n = (long)M.ne * G;
-    if (n <= 0) return;
-    if (G == 16)
-        hipLaunchKernelGGL((k_ebe_tail<float, 4, 16>), dim3(nblocks(n)), dim3(256), 0, s, M, tl, cD, ch, cmat, sc, x, f);
-    else
-        hipLaunchKernelGGL((k_ebe_tail<float, 4, 32>), dim3(nblocks(n)), dim3(256), 0, s, M, tl, cD, ch, cmat, sc, x, f);
-}
-
 // operator A on the compact rows summed per element cluster (the compact form
 // of k_ebe_cluster): one block per cluster; a wavefront holds 64/G element
 // slots of G lanes, and each slot adds its element's forces into its own copy
@@ -972,6 +940,19 @@ __global__ __launch_bounds__(256) void k_ebe_ctail(DevMesh M, const int* __restr
     }
 }
 
+void launch_ebe64_ctail(hipStream_t s, const DevMesh& M, int G, const int* tl, const double* cD, const double* ch,
+                        const double* cmat, StepConst sc, const double* x, double* co)
+{
+    long g = (M.ncl + 7) / 8 * 8;
+    if (M.ncl <= 0) return;
+    if (G == 16)
+        hipLaunchKernelGGL((k_ebe_ctail<double, 0, 16>), dim3((unsigned)g), dim3(256), 0, s, M, tl, cD, ch, cmat, sc, x,
+                           co);
+    else
+        hipLaunchKernelGGL((k_ebe_ctail<double, 0, 32>), dim3((unsigned)g), dim3(256), 0, s, M, tl, cD, ch, cmat, sc, x,
+                           co);
+}
+
 void launch_ebe32_ctail(hipStream_t s, const DevMesh& M, int G, const int* tl, const uint32_t* cD, const double* ch,
                         const double* cmat, StepConst sc, const float* x, float* co)
 {
@@ -985,23 +966,10 @@ void launch_ebe32_ctail(hipStream_t s, const DevMesh& M, int G, const int* tl, c
                            co);
 }
 
-void launch_ebe64_tail(hipStream_t s, const DevMesh& M, int G, const int* tl, const double* cD, const double* ch,
-                       const double* cmat, StepConst sc, const double* x, double* f)
-{
-    const long n = (long)M.ne * G;
-    if (n <= 0) return;
-    if (G == 16)
-        hipLaunchKernelGGL((k_ebe_tail<double, 0, 16>), dim3(nblocks(n)), dim3(256), 0, s, M, tl, cD, ch, cmat, sc, x,
-                           f);
-    else
-        hipLaunchKernelGGL((k_ebe_tail<double, 0, 32>), dim3(nblocks(n)), dim3(256), 0, s, M, tl, cD, ch, cmat, sc, x,
-                           f);
-}
-
-// node sums of the compact element outputs (incidences in ascending order)
-// or, with CL, of the compact cluster rows (the node's rows in ascending
-// order) into the compact y of the listed, active members; with partial, the
-// x . y partials of the block's nodes
+// node sums of compact element outputs (incidences in ascending order) or,
+// with CL, of the compact cluster rows (the node's rows in ascending order;
+// the form the operators write) into the compact y of the listed, active
+// members; with partial, the x . y partials of the block's nodes
 template <typename T, int G, bool CL>
 __global__ __launch_bounds__(256) void k_gather_tail(DevMesh M, int MB, int nm, const int* __restrict__ tl,
                                                     const T* __restrict__ fc, T* __restrict__ y,

@@ -139,15 +139,13 @@ void launch_tail_pack64(hipStream_t s, const DevMesh& M, int MB, int G, int n_la
 // nrows member-innermost FP64 rows, full <-> compact
 void launch_tail_rows64(hipStream_t s, long nrows, int MB, int G, const int* tl, const double* src, double* dst,
                         bool unpack);
-void launch_ebe32_tail(hipStream_t s, const DevMesh& M, int G, const int* tl, const uint32_t* cD, const double* ch,
-                       const double* cmat, StepConst sc, const float* x, float* f);
-void launch_ebe64_tail(hipStream_t s, const DevMesh& M, int G, const int* tl, const double* cD, const double* ch,
-                       const double* cmat, StepConst sc, const double* x, double* f);
-// the mixed path's inner operator on the compact rows summed per element
-// cluster: G-wide cluster rows co[(row * 3 + c) * G + k] for the gather with
-// clusters = true
+// operator A on the compact rows summed per element cluster (the mixed path's
+// inner operator, or the FP64 one with D per point): G-wide cluster rows
+// co[(row * 3 + c) * G + k] for the gather with clusters = true
 void launch_ebe32_ctail(hipStream_t s, const DevMesh& M, int G, const int* tl, const uint32_t* cD, const double* ch,
                         const double* cmat, StepConst sc, const float* x, float* co);
+void launch_ebe64_ctail(hipStream_t s, const DevMesh& M, int G, const int* tl, const double* cD, const double* ch,
+                        const double* cmat, StepConst sc, const double* x, double* co);
 template <typename T>
 void launch_gather_tail(hipStream_t s, const DevMesh& M, int MB, int nm, int G, const int* tl, const T* fc, T* y,
                         const int* active, const T* x, double* partial, int* nblk, bool clusters = false);
