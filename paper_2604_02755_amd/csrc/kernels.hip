@@ -1752,7 +1752,9 @@ __device__ __forceinline__ double ro_inverse_pw(double e, double beta, double* p
 struct SpringPar { double G0, gref, hmax, beta; };
 
 // Law state of a chunk of ecp elements (ecp a multiple of EB): four FP64
-// fields (gp, gr, tr, gm) then one int32 field packing the loading direction,
+// fields (gp, gr, tr, sm: the strain, the reversal strain and stress, and the
+// normalised skeleton stress at the largest strain reached on the skeleton)
+// then one int32 field packing the loading direction,
 // the skeleton flag and the count of older reversal points kept,
 // (dir + 1) | skel << 2 | count << 3 (36 B per spring and point); with a
 // reversal memory of depth K > 1 the int32 field is followed by 2 (K - 1)
@@ -1987,7 +1989,7 @@ __global__ __launch_bounds__(256, LDS_NS > 0 ? 4 : 1) void k_law(DevMesh M, int 
     double hs = 0.0;
     // the next spring's state is loaded while this one is updated
     long nidx = th.at(el, 0, j, m);
-    double ngp = th.d[nidx], ngr = th.d[fn + nidx], ntr = th.d[2 * fn + nidx], ngm = th.d[3 * fn + nidx];
+    double ngp = th.d[nidx], ngr = th.d[fn + nidx], ntr = th.d[2 * fn + nidx], nsm = th.d[3 * fn + nidx];
     int nfl = th.i[nidx];
 #pragma unroll 1
     for (int sp = 0; sp < ns; ++sp) {
@@ -1996,12 +1998,12 @@ __global__ __launch_bounds__(256, LDS_NS > 0 ? 4 : 1) void k_law(DevMesh M, int 
                                      : n[0] * ej[0] + n[1] * ej[1] + n[2] * ej[2] + n[3] * ej[3] + n[4] * ej[4] +
                                            n[5] * ej[5];
         const long idx = nidx;
-        double gp = ngp, gr = ngr, tr = ntr, sm = ngm;
+        double gp = ngp, gr = ngr, tr = ntr, sm = nsm;
         int dir = (nfl & 3) - 1, skel = (nfl >> 2) & 1;
         int cnt = MEM ? nfl >> 3 : 0;  // older reversal points kept
         if (sp + 1 < ns) {
             nidx = th.at(el, sp + 1, j, m);
-            ngp = th.d[nidx]; ngr = th.d[fn + nidx]; ntr = th.d[2 * fn + nidx]; ngm = th.d[3 * fn + nidx];
+            ngp = th.d[nidx]; ngr = th.d[fn + nidx]; ntr = th.d[2 * fn + nidx]; nsm = th.d[3 * fn + nidx];
             nfl = th.i[nidx];
         }
         const int dsg = dg > 0.0 ? 1 : (dg < 0.0 ? -1 : 0);
