@@ -7,7 +7,9 @@
 // and queued requests take the free slots, so requests that arrive while
 // others run overlap with them in the same launches.  Members of a batch run
 // at their own step index (their own input wave position); all per-member
-// arithmetic is independent of the other slots.
+// arithmetic is independent of the other slots' values, except that when few
+// members of a batch of 64 or more slots are still iterating, they finish on
+// compact rows (the same arithmetic, its sums in another order).
 #include <math.h>
 #include <string.h>
 
