@@ -578,14 +578,24 @@ __global__ __launch_bounds__(256) void k_ebe_cluster(DevMesh M, int MB, int nm, 
         for (int ww = 0; ww < 4; ++ww) {
             __syncthreads();
             if (w == ww && le < nec) {
+                // LDS read-add-write (the no-return LDS atomic add measured 3.5x
+                // slower for the whole kernel).  An element's ten nodes are
+                // distinct rows: all thirty values are read before any is
+                // written back, one LDS round trip instead of ten.
+                T* yr[10];
+                T v[10][3];
 #pragma unroll
                 for (int n = 0; n < 10; ++n) {
-                    // (LDS read-add-write: the no-return LDS atomic add measured
-                    // 3.5x slower for the whole kernel)
-                    T* yr = ys + (int)((lw[n / 4] >> (8 * (n % 4))) & 0xFFu) * 3 * 64 + lane;
-                    yr[0] += f[n][0];
-                    yr[64] += f[n][1];
-                    yr[128] += f[n][2];
+                    yr[n] = ys + (int)((lw[n / 4] >> (8 * (n % 4))) & 0xFFu) * 3 * 64 + lane;
+                    v[n][0] = yr[n][0];
+                    v[n][1] = yr[n][64];
+                    v[n][2] = yr[n][128];
+                }
+#pragma unroll
+                for (int n = 0; n < 10; ++n) {
+                    yr[n][0] = v[n][0] + f[n][0];
+                    yr[n][64] = v[n][1] + f[n][1];
+                    yr[n][128] = v[n][2] + f[n][2];
                 }
             }
         }
@@ -921,12 +931,21 @@ __global__ __launch_bounds__(256) void k_ebe_ctail(DevMesh M, const int* __restr
         for (int ww = 0; ww < 4; ++ww) {
             __syncthreads();
             if (w == ww && le < nec) {
+                // the element's ten distinct node rows: all reads before the writes
+                T* yr[10];
+                T v[10][3];
 #pragma unroll
                 for (int n = 0; n < 10; ++n) {
-                    T* yr = yc + (int)((lw[n / 4] >> (8 * (n % 4))) & 0xFFu) * 3 * G + k;
-                    yr[0] += f[n][0];
-                    yr[G] += f[n][1];
-                    yr[2 * G] += f[n][2];
+                    yr[n] = yc + (int)((lw[n / 4] >> (8 * (n % 4))) & 0xFFu) * 3 * G + k;
+                    v[n][0] = yr[n][0];
+                    v[n][1] = yr[n][G];
+                    v[n][2] = yr[n][2 * G];
+                }
+#pragma unroll
+                for (int n = 0; n < 10; ++n) {
+                    yr[n][0] = v[n][0] + f[n][0];
+                    yr[n][G] = v[n][1] + f[n][1];
+                    yr[n][2 * G] = v[n][2] + f[n][2];
                 }
             }
         }
