@@ -244,12 +244,14 @@ typedef struct {
     double ms_copy;            /* copy-stream busy time while paging */
     int32_t n_members, members_padded, n_colors;
     int64_t device_bytes, host_bytes;
-    double ms_gather32;        /* node gather of the inner operator's element outputs */
+    double ms_gather32;        /* node gather of the inner operator's element outputs or cluster rows */
     int64_t n_gather32;
     double cheb_lo_min;        /* Chebyshev inner bounds of the last step: smallest lower bound and */
     double cheb_hi_max;        /* largest upper bound over the members (0 without Chebyshev) */
-    double ms_tail32;          /* inner operator on the list of the last active members (element
-                                  kernel and node gather) */
+    double ms_tail32;          /* operator on the compact rows of the last active members
+                                  (element kernel, node gather and dashpot): the inner FP32 one,
+                                  or with NLTH_FP64 the PCG's; the mixed path's outer FP64
+                                  operator on those rows counts in ms_ebe64 */
     int64_t n_tail32;
     int64_t elems_tail32;      /* element-member pairs of those launches (listed members only) */
     int32_t member_sets;       /* 2: a paged ensemble run as two member sets; 1 otherwise */
@@ -276,7 +278,8 @@ int nlth_ens_stats(const nlth_ens* ens, nlth_stats* st);
  * not 0/2/3/4, scatter outside -1..2 or not available for this ensemble,
  * inner_method outside -1..1, Chebyshev with a degree above 64, zero_copy outside
  * -1..1 or 1 for an ensemble whose state is resident, tail_members not -1/0/16/32
- * or above 0 for an FP64 ensemble or one outside 64..256 slots, predictor outside -1..2)
+ * or above 0 for an ensemble outside 64..256 slots or a mixed one without the
+ * element-mean inner D, predictor outside -1..2)
  * give NLTH_EINVAL and
  * change nothing.  Not to be called while the ensemble
  * is stepping on another thread. */
@@ -299,13 +302,15 @@ typedef struct {
                                   over the host link itself (an ablation of the pipeline; only for an
                                   ensemble whose state is paged) */
     int32_t tail_members;      /* -1 keep; 0 off; 16 or 32: once at most this many members are
-                                  still iterating in the outer CG, their inner CG runs on compact
-                                  copies of their rows (16 or 32 lanes instead of all member slots);
-                                  results equal the full path's to rounding order.  Mixed precision
-                                  with the element-mean inner D, 64..256 slots, inner CG only
-                                  (default 32 there, 0 elsewhere).  The copies take 32 lanes of
-                                  172 B per element and 84 B per node, allocated at first use; if
-                                  that fails the path stays off for the ensemble */
+                                  still iterating, their solve moves to compact copies of their
+                                  rows (16 or 32 lanes instead of all member slots): the plain PCG
+                                  of NLTH_FP64, or with NLTH_MIXED (element-mean inner D, inner CG)
+                                  the inner CG and then the outer iteration.  Results equal the
+                                  full path's to rounding order.  64..256 slots (default 32 there,
+                                  0 elsewhere).  The copies take 32 lanes of 172 B per element and
+                                  84 B per node for the inner solve, and of 920 B per element and
+                                  168 B per node for the FP64 rows, allocated at first use; if that
+                                  fails the path stays off for the ensemble */
     int32_t predictor;         /* -1 keep; CG initial guess of a step from the increments of the
                                   previous steps (their history from rest is zero): 0 the last
                                   increment (default), 1 its linear extrapolation 2 du^{n-1} -
